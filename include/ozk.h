@@ -1,0 +1,231 @@
+/*
+ * ozk.h -- C ABI of an FP64 / complex128 GEMM library that emulates the
+ * products on INT8 matrix cores (AMD MI355X, gfx950) with the Ozaki schemes.
+ *
+ * Paper: "EmuGEMM: Fused Tensor Core Kernels for Precision Emulation in Matrix
+ * Multiplication".  Problem statement C = A B with A in R^{MxK},
+ * B in R^{KxN} (Sec. II-B); this library computes C = alpha*A*B + beta*C.
+ *
+ * Conventions for every call
+ * --------------------------
+ * - Matrices are row-major (C order, as in PyTorch) with leading dimensions
+ *   in elements: A(i,k) = A[i*lda + k], B(k,j) = B[k*ldb + j],
+ *   C(i,j) = C[i*ldc + j].  Complex matrices are interleaved (re, im) pairs
+ *   (std::complex<double> / torch.complex128) and leading dimensions count
+ *   complex elements.
+ * - Every pointer argument except the context is a DEVICE pointer owned by
+ *   the caller.  The library never allocates or frees per call, never
+ *   synchronises the stream and never reads device data on the host, so
+ *   calls may be captured into a HIP graph.  All work is enqueued on
+ *   `stream` (0 = the null stream).
+ * - Arguments are validated synchronously; on failure nothing is enqueued
+ *   and the status says why (ozk_last_arg() names the 1-based position of
+ *   the offending argument).  No exception or abort crosses the ABI.
+ * - beta == 0 means C is not read (BLAS convention).  M, N or K == 0 are
+ *   valid: with K == 0 the product is exactly zero.
+ * - A row of A or a column of B that holds a NaN or an infinity yields NaN
+ *   in the corresponding row/column of alpha*A*B (the paper does not define
+ *   this case); finite rows and columns are unaffected.
+ *
+ * Packed operand layouts (workspace contents, documented so that each step
+ * can be called and checked on its own)
+ * ------------------------------------------------------------------------
+ * OZK_ROW_ALIGN = 256: packed operands hold Rp = roundup(rows, 256) rows;
+ * the rows past `rows` are zero.  K is padded with zeros to
+ * Kp = roundup(K, 32) (OZK_K_CHUNK).
+ *
+ * Scheme I packed operand (Sec. III-A, Eq. 11, with t_K = 32):
+ *   P[r][c][t][kk] = slice t of row r at k = 32c + kk,   int8,
+ *   r < Rp, c < Kp/32, t < p, kk < 32.  Each row holds, chunk after chunk of
+ *   32 k, the p slices of that chunk side by side: [A'_0|A'_1|..|A'_(p-1)|
+ *   A'_0|..].  The "rows" of B's packed operand are the COLUMNS of B (B is
+ *   transposed so that both operands are contiguous along k).
+ *   Slice format: with e the row (column) exponent -- the smallest e with
+ *   |x| < 2^e over the row's nonzero entries -- and X = floor(x 2^(8p-2-e)
+ *   + 1/2), the slices are the balanced base-256 digits of X: slice t in
+ *   [-128, 127] (slice 0 in [-64, 64]) with x ~ 2^e sum_t slice_t 2^(-6-8t).
+ *
+ * Scheme II packed operand (Sec. II-C.2, Eq. 5):
+ *   R[l][r][k] = smod(trunc(x 2^sigma_r), m_l), int8, l < s, r < Rp, k < Kp,
+ *   smod(x, m) the representative in [-floor(m/2), ceil(m/2)-1]; moduli
+ *   m_l = 256, 255, 253, 251, 247, 241, ... (greedy pairwise coprime).
+ *   3M complex: each modulus plane l is a packed operand in the Scheme I
+ *   layout with three slices, R[l][r][c][q][kk] = residue at k = 32c + kk of
+ *   q = 0 the real part, 1 the imaginary part, 2 smod(real + imaginary).
+ *   The row (column) scale sigma is shared by both parts; rows past `rows`
+ *   and k past K are zero.
+ *
+ * Exponent sentinels in the int32 scale vectors: OZK_EXP_ZERO marks a row
+ * (column) with no nonzero entry, OZK_EXP_NONFINITE one with a NaN or inf.
+ */
+#ifndef OZK_H
+#define OZK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define OZK_ROW_ALIGN 256
+#define OZK_K_CHUNK 32
+#define OZK_EXP_ZERO (-100000)
+#define OZK_EXP_NONFINITE 100000
+#define OZK_MAX_P 8
+#define OZK_MAX_S 20
+
+typedef struct ozk_ctx ozk_ctx;
+
+typedef enum {
+  OZK_OK = 0,
+  OZK_ERR_INVALID_ARG = -1, /* bad pointer, dimension, leading dimension */
+  OZK_ERR_UNSUPPORTED = -2, /* p outside [1, 8], s outside [1, 20], ... */
+  OZK_ERR_WORKSPACE = -3,   /* workspace missing or too small */
+  OZK_ERR_HIP = -4          /* a HIP runtime call failed */
+} ozk_status;
+
+typedef enum { OZK_SCHEME1 = 1, OZK_SCHEME2 = 2 } ozk_scheme;
+typedef enum { OZK_OP_DGEMM = 0, OZK_OP_ZGEMM = 1 } ozk_op;
+
+/* ---------------------------------------------------------------- context */
+
+/* Create a context bound to HIP device `device` (made current on the calling
+ * thread).  The context owns only small constant tables.  One context per
+ * host thread; a context may be used with any stream of its device. */
+ozk_status ozk_create(ozk_ctx** ctx, int device);
+/* Destroy a context (NULL is accepted).  Work already enqueued must have
+ * completed. */
+ozk_status ozk_destroy(ozk_ctx* ctx);
+/* 1-based position of the argument that made the last call on this context
+ * fail with OZK_ERR_INVALID_ARG / UNSUPPORTED / WORKSPACE; 0 otherwise. */
+int ozk_last_arg(const ozk_ctx* ctx);
+/* Static description of a status code. */
+const char* ozk_status_string(ozk_status s);
+/* Library version, "major.minor.patch". */
+const char* ozk_version(void);
+
+/* ---------------------------------------------------------- sizes / layout */
+
+/* Bytes of a Scheme I packed operand with `rows` rows, contraction length K
+ * and p slices: roundup(rows, 256) * roundup(K, 32) * p. */
+size_t ozk_s1_packed_bytes(int64_t rows, int64_t K, int p);
+/* Bytes of a Scheme II packed operand: s * roundup(rows,256) * roundup(K,32)
+ * * (3 if complex else 1). */
+size_t ozk_s2_packed_bytes(int64_t rows, int64_t K, int s, int complex_planes);
+/* Longest K run whose Scheme I INT32 diagonals cannot overflow
+ * (|slice_0| <= 64, |slice_t| <= 128 bound diagonal d by max(2^12, d 2^14)
+ * per k), rounded down to a multiple of 32. */
+int64_t ozk_s1_k_split(int p);
+
+/* Workspace bytes ozk_dgemm / ozk_zgemm_3m need for this problem.  For
+ * Scheme I it holds the scale vectors, the two packed operands and, when K
+ * exceeds ozk_s1_k_split(p), 16 bytes per output per K run; for Scheme II
+ * the scales, the residue planes and s (or 2s for complex) int8 output
+ * residue planes. */
+ozk_status ozk_workspace_size(ozk_ctx* ctx, ozk_op op, ozk_scheme scheme,
+                              int64_t M, int64_t N, int64_t K, int p_or_s,
+                              size_t* bytes);
+
+/* ------------------------------------------------------------ whole calls */
+
+/* C = alpha*A*B + beta*C in FP64, emulated with Scheme I (p = slices per
+ * operand, 1..8; Sec. II-C.1, Sec. III) or Scheme II (p_or_s = number of
+ * moduli, 1..20; Sec. II-C.2, Sec. IV-A).  Runs the pre-pass, the fused
+ * GEMM and the epilogue (CRT for Scheme II) on `stream`.  `ws` must hold
+ * ozk_workspace_size(..) bytes. */
+ozk_status ozk_dgemm(ozk_ctx* ctx, ozk_scheme scheme, int p_or_s, int64_t M,
+                     int64_t N, int64_t K, double alpha, const double* A,
+                     int64_t lda, const double* B, int64_t ldb, double beta,
+                     double* C, int64_t ldc, void* ws, size_t ws_bytes,
+                     hipStream_t stream);
+
+/* C = alpha*A*B + beta*C in complex128 with Scheme II and the 3M identity
+ * (Sec. IV-B, Eq. 16): three modular products per modulus, exact.  alpha and
+ * beta are HOST arrays {re, im}; beta == 0 (both parts) means C is not read.
+ * The update is out_re = fma(a_re, h_re, fma(-a_im, h_im, bc_re)),
+ * out_im = fma(a_re, h_im, fma(a_im, h_re, bc_im)) with
+ * bc = (fma(b_re, c_re, -(b_im c_im)), fma(b_re, c_im, b_im c_re)). */
+ozk_status ozk_zgemm_3m(ozk_ctx* ctx, int s, int64_t M, int64_t N, int64_t K,
+                        const double* alpha, const double* A, int64_t lda,
+                        const double* B, int64_t ldb, const double* beta,
+                        double* C, int64_t ldc, void* ws, size_t ws_bytes,
+                        hipStream_t stream);
+
+/* ------------------------------------------------ Scheme I, step by step */
+
+/* Pre-pass for a row operand (A): e[i] = row exponent (smallest e with
+ * |a_ik| < 2^e, or a sentinel) for i < rows, and the packed slices P
+ * (ozk_s1_packed_bytes(rows, K, p) bytes, layout above).  Sec. II-C.1 Eq. 1,
+ * Sec. III-A Eq. 11. */
+ozk_status ozk_s1_split_rows(ozk_ctx* ctx, int p, int64_t rows, int64_t K,
+                             const double* X, int64_t ldx, int32_t* e,
+                             int8_t* packed, hipStream_t stream);
+/* The same for a column operand (B, K x cols): f[j] = column exponent, and
+ * the packed slices of B transposed. */
+ozk_status ozk_s1_split_cols(ozk_ctx* ctx, int p, int64_t K, int64_t cols,
+                             const double* X, int64_t ldx, int32_t* f,
+                             int8_t* packed, hipStream_t stream);
+/* Fused Scheme I GEMM (Sec. III-B, Alg. 1): all p(p+1)/2 slice-pair INT8
+ * products accumulated into p INT32 diagonals that stay in registers; the
+ * epilogue forms the exact integer Z = sum_d 2^(8(p-1-d)) C_d and writes
+ * RN(Z 2^(e_i + f_j - 12 - 8(p-1))) through alpha/beta.  When K exceeds
+ * ozk_s1_k_split(p) the K runs are folded exactly through `ws` (16 bytes per
+ * output per run; pass NULL/0 otherwise). */
+ozk_status ozk_s1_gemm(ozk_ctx* ctx, int p, int64_t M, int64_t N, int64_t K,
+                       const int8_t* packedA, const int32_t* e,
+                       const int8_t* packedB, const int32_t* f, double alpha,
+                       double beta, double* C, int64_t ldc, void* ws,
+                       size_t ws_bytes, hipStream_t stream);
+/* Check entry point: the raw INT32 diagonals C_d (Eq. 2) of the fused
+ * kernel, Cd[d][i][j] (int32, M x N per diagonal, row-major).  Requires
+ * K <= ozk_s1_k_split(p). */
+ozk_status ozk_s1_diagonals(ozk_ctx* ctx, int p, int64_t M, int64_t N,
+                            int64_t K, const int8_t* packedA,
+                            const int8_t* packedB, int32_t* Cd,
+                            hipStream_t stream);
+
+/* ----------------------------------------------- Scheme II, step by step */
+
+/* Pre-pass for a row operand: sigma[i] (power-of-two row scale exponent,
+ * chosen from an exact bound on the row's 2-norm so that the CRT exactness
+ * condition 2 sum |a'||b'| < P holds, Sec. II-C.2) and the s residue planes.
+ * complex_planes = 1: X is complex (interleaved) and three planes per
+ * modulus are written (real, imaginary, their sum mod m) with one shared
+ * sigma per row (Sec. IV-B). */
+ozk_status ozk_s2_split_rows(ozk_ctx* ctx, int s, int complex_planes,
+                             int64_t rows, int64_t K, const double* X,
+                             int64_t ldx, int32_t* sigma, int8_t* packed,
+                             hipStream_t stream);
+/* The same for a column operand (B, K x cols), transposed on the fly. */
+ozk_status ozk_s2_split_cols(ozk_ctx* ctx, int s, int complex_planes,
+                             int64_t K, int64_t cols, const double* X,
+                             int64_t ldx, int32_t* tau, int8_t* packed,
+                             hipStream_t stream);
+/* Per-modulus INT8 GEMM with the modular reduction fused into the epilogue
+ * (Sec. IV-A, Eqs. 6-7): Cres[l][i][j] = smod(sum_k R_l[i][k] S_l[j][k], m_l)
+ * (int8, s planes of M x N).  complex_planes = 1: 3M (Sec. IV-B, Eq. 16),
+ * Cres[l][0] = smod(T1 - T2), Cres[l][1] = smod(T3 - T1 - T2), 2s planes.
+ * Any K: the INT32 accumulators are reduced by multiples of m_l every
+ * 131040 values of k, which leaves their residues unchanged. */
+ozk_status ozk_s2_gemm_mod(ozk_ctx* ctx, int s, int complex_planes, int64_t M,
+                           int64_t N, int64_t K, const int8_t* packedA,
+                           const int8_t* packedB, int8_t* Cres,
+                           hipStream_t stream);
+/* CRT recombination and inverse scaling (Eq. 8): Z = smod(sum_l
+ * (P/m_l) q_l Cres_l, P) in multiword integers, h = RN(Z 2^(-sigma_i -
+ * tau_j)), then the alpha/beta update (real: alpha[0], beta[0]; complex:
+ * the fma sequence of ozk_zgemm_3m).  alpha, beta are HOST arrays. */
+ozk_status ozk_s2_crt(ozk_ctx* ctx, int s, int complex_planes, int64_t M,
+                      int64_t N, const int8_t* Cres, const int32_t* sigma,
+                      const int32_t* tau, const double* alpha,
+                      const double* beta, double* C, int64_t ldc,
+                      hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* OZK_H */

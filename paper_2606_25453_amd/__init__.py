@@ -1,0 +1,321 @@
+"""Python binding of libozk (FP64/complex128 GEMM emulated on MI355X INT8
+MFMA with the Ozaki schemes).
+
+Argument marshalling only: every function forwards to the C ABI of the same
+name declared in include/ozk.h; all arithmetic runs in the library's HIP
+kernels.  PyTorch supplies device memory (tensors) and streams.  There is no
+fallback: importing works without a GPU, but every call needs the built
+library (``paper_2606_25453_amd/libozk.so``) and raises if it is missing.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libozk.so")
+
+OZK_OK = 0
+OZK_ERR_INVALID_ARG = -1
+OZK_ERR_UNSUPPORTED = -2
+OZK_ERR_WORKSPACE = -3
+OZK_ERR_HIP = -4
+OZK_SCHEME1 = 1
+OZK_SCHEME2 = 2
+OZK_OP_DGEMM = 0
+OZK_OP_ZGEMM = 1
+OZK_ROW_ALIGN = 256
+OZK_K_CHUNK = 32
+OZK_EXP_ZERO = -100000
+OZK_EXP_NONFINITE = 100000
+
+# every symbol include/ozk.h declares
+EXPORTS = (
+    "ozk_create", "ozk_destroy", "ozk_last_arg", "ozk_status_string", "ozk_version",
+    "ozk_s1_packed_bytes", "ozk_s2_packed_bytes", "ozk_s1_k_split", "ozk_workspace_size",
+    "ozk_dgemm", "ozk_zgemm_3m", "ozk_s1_split_rows", "ozk_s1_split_cols", "ozk_s1_gemm",
+    "ozk_s1_diagonals", "ozk_s2_split_rows", "ozk_s2_split_cols", "ozk_s2_gemm_mod", "ozk_s2_crt",
+)
+
+
+class OzkError(RuntimeError):
+    def __init__(self, fn: str, status: int, arg: int):
+        self.status = status
+        self.arg = arg
+        msg = _lib().ozk_status_string(status).decode() if _LIB is not None else str(status)
+        super().__init__("%s failed: %s (status %d, argument %d)" % (fn, msg, status, arg))
+
+
+_LIB = None
+
+
+def _lib() -> ctypes.CDLL:
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libozk.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I, I64, D, SZ = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
+    sig = {
+        "ozk_create": (I, [ctypes.POINTER(P), I]),
+        "ozk_destroy": (I, [P]),
+        "ozk_last_arg": (I, [P]),
+        "ozk_status_string": (ctypes.c_char_p, [I]),
+        "ozk_version": (ctypes.c_char_p, []),
+        "ozk_s1_packed_bytes": (SZ, [I64, I64, I]),
+        "ozk_s2_packed_bytes": (SZ, [I64, I64, I, I]),
+        "ozk_s1_k_split": (I64, [I]),
+        "ozk_workspace_size": (I, [P, I, I, I64, I64, I64, I, ctypes.POINTER(SZ)]),
+        "ozk_dgemm": (I, [P, I, I, I64, I64, I64, D, P, I64, P, I64, D, P, I64, P, SZ, P]),
+        "ozk_zgemm_3m": (I, [P, I, I64, I64, I64, P, P, I64, P, I64, P, P, I64, P, SZ, P]),
+        "ozk_s1_split_rows": (I, [P, I, I64, I64, P, I64, P, P, P]),
+        "ozk_s1_split_cols": (I, [P, I, I64, I64, P, I64, P, P, P]),
+        "ozk_s1_gemm": (I, [P, I, I64, I64, I64, P, P, P, P, D, D, P, I64, P, SZ, P]),
+        "ozk_s1_diagonals": (I, [P, I, I64, I64, I64, P, P, P, P]),
+        "ozk_s2_split_rows": (I, [P, I, I, I64, I64, P, I64, P, P, P]),
+        "ozk_s2_split_cols": (I, [P, I, I, I64, I64, P, I64, P, P, P]),
+        "ozk_s2_gemm_mod": (I, [P, I, I, I64, I64, I64, P, P, P, P]),
+        "ozk_s2_crt": (I, [P, I, I, I64, I64, P, P, P, P, P, P, I64, P]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _LIB = lib
+    return lib
+
+
+def library() -> ctypes.CDLL:
+    """The loaded libozk (raises if it has not been built)."""
+    return _lib()
+
+
+# ------------------------------------------------------------------ helpers
+
+def _ptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    return t.data_ptr()
+
+
+def _stream(stream) -> Optional[int]:
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream
+
+
+def _check(fn: str, status: int, ctx) -> None:
+    if status != OZK_OK:
+        arg = _lib().ozk_last_arg(ctx.handle if isinstance(ctx, Context) else ctx)
+        raise OzkError(fn, status, arg)
+
+
+def _ld(t) -> int:
+    """Leading dimension of a row-major (unit column stride) matrix view."""
+    if t.dim() == 2 and t.numel() == 0:
+        return max(t.shape[1], 1)
+    if t.dim() != 2 or (t.shape[1] > 1 and t.stride(1) != 1):
+        raise ValueError("expected a 2-D row-major view with unit column stride")
+    return max(t.stride(0), 1)
+
+
+class Context:
+    """An ozk context bound to one device (ozk_create / ozk_destroy)."""
+
+    def __init__(self, device: int = 0):
+        h = ctypes.c_void_p()
+        st = _lib().ozk_create(ctypes.byref(h), device)
+        if st != OZK_OK:
+            raise OzkError("ozk_create", st, 0)
+        self.handle = h
+        self.device = device
+
+    def close(self) -> None:
+        if self.handle:
+            _lib().ozk_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def ozk_version() -> str:
+    return _lib().ozk_version().decode()
+
+
+def ozk_s1_packed_bytes(rows: int, K: int, p: int) -> int:
+    return int(_lib().ozk_s1_packed_bytes(rows, K, p))
+
+
+def ozk_s2_packed_bytes(rows: int, K: int, s: int, complex_planes: int = 0) -> int:
+    return int(_lib().ozk_s2_packed_bytes(rows, K, s, complex_planes))
+
+
+def ozk_s1_k_split(p: int) -> int:
+    return int(_lib().ozk_s1_k_split(p))
+
+
+def ozk_workspace_size(ctx: Context, op: int, scheme: int, M: int, N: int, K: int, p_or_s: int) -> int:
+    out = ctypes.c_size_t()
+    _check("ozk_workspace_size", _lib().ozk_workspace_size(ctx.handle, op, scheme, M, N, K, p_or_s,
+                                                           ctypes.byref(out)), ctx)
+    return int(out.value)
+
+
+def _workspace(nbytes: int, device):
+    import torch
+    return torch.empty(max(nbytes, 1), dtype=torch.uint8, device=device)
+
+
+# --------------------------------------------------------------- whole calls
+
+def ozk_dgemm(ctx: Context, scheme: int, p_or_s: int, A, B, C=None, alpha: float = 1.0,
+              beta: float = 0.0, ws=None, stream=None):
+    """C = alpha*A*B + beta*C (float64 CUDA tensors); returns C."""
+    import torch
+    M, K = A.shape
+    N = B.shape[1]
+    if C is None:
+        C = torch.empty((M, N), dtype=torch.float64, device=A.device)
+    if ws is None:
+        ws = _workspace(ozk_workspace_size(ctx, OZK_OP_DGEMM, scheme, M, N, K, p_or_s), A.device)
+    st = _lib().ozk_dgemm(ctx.handle, scheme, p_or_s, M, N, K, float(alpha), _ptr(A), _ld(A), _ptr(B), _ld(B),
+                          float(beta), _ptr(C), _ld(C), _ptr(ws), ws.numel(), _stream(stream))
+    _check("ozk_dgemm", st, ctx)
+    return C
+
+
+def ozk_zgemm_3m(ctx: Context, s: int, A, B, C=None, alpha: complex = 1.0, beta: complex = 0.0, ws=None,
+                 stream=None):
+    """C = alpha*A*B + beta*C (complex128 CUDA tensors) with Scheme II + 3M."""
+    import torch
+    M, K = A.shape
+    N = B.shape[1]
+    if C is None:
+        C = torch.empty((M, N), dtype=torch.complex128, device=A.device)
+    if ws is None:
+        ws = _workspace(ozk_workspace_size(ctx, OZK_OP_ZGEMM, OZK_SCHEME2, M, N, K, s), A.device)
+    al = (ctypes.c_double * 2)(complex(alpha).real, complex(alpha).imag)
+    be = (ctypes.c_double * 2)(complex(beta).real, complex(beta).imag)
+    st = _lib().ozk_zgemm_3m(ctx.handle, s, M, N, K, ctypes.cast(al, ctypes.c_void_p), _ptr(A), _ld(A), _ptr(B),
+                             _ld(B), ctypes.cast(be, ctypes.c_void_p), _ptr(C), _ld(C), _ptr(ws), ws.numel(),
+                             _stream(stream))
+    _check("ozk_zgemm_3m", st, ctx)
+    return C
+
+
+# ---------------------------------------------------------- Scheme I steps
+
+def ozk_s1_split_rows(ctx: Context, p: int, X, e=None, packed=None, stream=None):
+    """Row exponents and packed slices of a row operand; returns (e, packed)."""
+    import torch
+    rows, K = X.shape
+    if e is None:
+        e = torch.empty(max(rows, 1), dtype=torch.int32, device=X.device)
+    if packed is None:
+        packed = torch.empty(max(ozk_s1_packed_bytes(rows, K, p), 1), dtype=torch.int8, device=X.device)
+    st = _lib().ozk_s1_split_rows(ctx.handle, p, rows, K, _ptr(X), _ld(X), _ptr(e), _ptr(packed), _stream(stream))
+    _check("ozk_s1_split_rows", st, ctx)
+    return e, packed
+
+
+def ozk_s1_split_cols(ctx: Context, p: int, X, f=None, packed=None, stream=None):
+    """Column exponents and packed (transposed) slices of a column operand."""
+    import torch
+    K, cols = X.shape
+    if f is None:
+        f = torch.empty(max(cols, 1), dtype=torch.int32, device=X.device)
+    if packed is None:
+        packed = torch.empty(max(ozk_s1_packed_bytes(cols, K, p), 1), dtype=torch.int8, device=X.device)
+    st = _lib().ozk_s1_split_cols(ctx.handle, p, K, cols, _ptr(X), _ld(X), _ptr(f), _ptr(packed), _stream(stream))
+    _check("ozk_s1_split_cols", st, ctx)
+    return f, packed
+
+
+def ozk_s1_gemm(ctx: Context, p: int, M: int, N: int, K: int, packedA, e, packedB, f, C, alpha: float = 1.0,
+                beta: float = 0.0, ws=None, stream=None):
+    st = _lib().ozk_s1_gemm(ctx.handle, p, M, N, K, _ptr(packedA), _ptr(e), _ptr(packedB), _ptr(f), float(alpha),
+                            float(beta), _ptr(C), _ld(C), _ptr(ws), 0 if ws is None else ws.numel(),
+                            _stream(stream))
+    _check("ozk_s1_gemm", st, ctx)
+    return C
+
+
+def ozk_s1_diagonals(ctx: Context, p: int, M: int, N: int, K: int, packedA, packedB, Cd=None, stream=None):
+    """Raw INT32 diagonals [p][M][N] of the fused kernel."""
+    import torch
+    if Cd is None:
+        Cd = torch.empty((p, M, N), dtype=torch.int32, device=packedA.device)
+    st = _lib().ozk_s1_diagonals(ctx.handle, p, M, N, K, _ptr(packedA), _ptr(packedB), _ptr(Cd), _stream(stream))
+    _check("ozk_s1_diagonals", st, ctx)
+    return Cd
+
+
+# --------------------------------------------------------- Scheme II steps
+
+def ozk_s2_split_rows(ctx: Context, s: int, X, complex_planes: int = 0, sigma=None, packed=None, stream=None):
+    import torch
+    rows, K = X.shape
+    if sigma is None:
+        sigma = torch.empty(max(rows, 1), dtype=torch.int32, device=X.device)
+    if packed is None:
+        packed = torch.empty(max(ozk_s2_packed_bytes(rows, K, s, complex_planes), 1), dtype=torch.int8,
+                             device=X.device)
+    st = _lib().ozk_s2_split_rows(ctx.handle, s, complex_planes, rows, K, _ptr(X), _ld(X), _ptr(sigma),
+                                  _ptr(packed), _stream(stream))
+    _check("ozk_s2_split_rows", st, ctx)
+    return sigma, packed
+
+
+def ozk_s2_split_cols(ctx: Context, s: int, X, complex_planes: int = 0, tau=None, packed=None, stream=None):
+    import torch
+    K, cols = X.shape
+    if tau is None:
+        tau = torch.empty(max(cols, 1), dtype=torch.int32, device=X.device)
+    if packed is None:
+        packed = torch.empty(max(ozk_s2_packed_bytes(cols, K, s, complex_planes), 1), dtype=torch.int8,
+                             device=X.device)
+    st = _lib().ozk_s2_split_cols(ctx.handle, s, complex_planes, K, cols, _ptr(X), _ld(X), _ptr(tau),
+                                  _ptr(packed), _stream(stream))
+    _check("ozk_s2_split_cols", st, ctx)
+    return tau, packed
+
+
+def ozk_s2_gemm_mod(ctx: Context, s: int, M: int, N: int, K: int, packedA, packedB, complex_planes: int = 0,
+                    Cres=None, stream=None):
+    import torch
+    if Cres is None:
+        Cres = torch.empty((s * (2 if complex_planes else 1), M, N), dtype=torch.int8, device=packedA.device)
+    st = _lib().ozk_s2_gemm_mod(ctx.handle, s, complex_planes, M, N, K, _ptr(packedA), _ptr(packedB), _ptr(Cres),
+                                _stream(stream))
+    _check("ozk_s2_gemm_mod", st, ctx)
+    return Cres
+
+
+def ozk_s2_crt(ctx: Context, s: int, M: int, N: int, Cres, sigma, tau, C, alpha=1.0, beta=0.0,
+               complex_planes: int = 0, stream=None):
+    al = (ctypes.c_double * 2)(complex(alpha).real, complex(alpha).imag)
+    be = (ctypes.c_double * 2)(complex(beta).real, complex(beta).imag)
+    st = _lib().ozk_s2_crt(ctx.handle, s, complex_planes, M, N, _ptr(Cres), _ptr(sigma), _ptr(tau),
+                           ctypes.cast(al, ctypes.c_void_p), ctypes.cast(be, ctypes.c_void_p), _ptr(C), _ld(C),
+                           _stream(stream))
+    _check("ozk_s2_crt", st, ctx)
+    return C
+
+
+# ----------------------------------------------------------- layout helpers
+
+def unpack_s1(packed, rows: int, K: int, p: int):
+    """View a Scheme I packed operand (a torch int8 tensor) as [p][rows][K]
+    (drops the padding); a pure reshape of the documented layout."""
+    Rp = (rows + OZK_ROW_ALIGN - 1) // OZK_ROW_ALIGN * OZK_ROW_ALIGN
+    Kp = (K + OZK_K_CHUNK - 1) // OZK_K_CHUNK * OZK_K_CHUNK
+    v = packed[: Rp * Kp * p].reshape(Rp, Kp // OZK_K_CHUNK, p, OZK_K_CHUNK)
+    v = v.permute(2, 0, 1, 3).reshape(p, Rp, Kp)
+    return v[:, :rows, :K]

@@ -1,0 +1,388 @@
+// C ABI of the emulation library: argument validation, workspace layout and
+// dispatch to the kernels.  Nothing here allocates device memory per call or
+// synchronises a stream.
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include "ozk.h"
+#include "ozk_internal.hpp"
+
+struct ozk_ctx {
+  int device;
+  int last_arg;
+  int64_t k_split_override;  // > 0: shorter K runs (testing the fold path)
+};
+
+using ozk::round_up;
+
+namespace {
+
+ozk_status fail(ozk_ctx* c, ozk_status s, int arg) {
+  if (c) c->last_arg = arg;
+  return s;
+}
+
+ozk_status hip_status(ozk_ctx* c, hipError_t e) {
+  if (e == hipSuccess) return OZK_OK;
+  if (c) c->last_arg = 0;
+  return OZK_ERR_HIP;
+}
+
+size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
+int64_t k_split_of(const ozk_ctx* c, int p) {
+  const int64_t per_k = p == 1 ? (1 << 12) : (int64_t)(p - 1) << 14;
+  int64_t k = ((int64_t)0x7fffffff / per_k) / OZK_K_CHUNK * OZK_K_CHUNK;
+  if (c && c->k_split_override > 0 && c->k_split_override < k) k = c->k_split_override;
+  return k;
+}
+
+struct S1Plan {
+  size_t off_e, off_f, off_a, off_b, off_z, total;
+  int64_t nsplit, steps_per_split, nchunk;
+};
+
+S1Plan s1_plan(const ozk_ctx* c, int p, int64_t M, int64_t N, int64_t K) {
+  S1Plan pl;
+  const int64_t kp = round_up(K, OZK_K_CHUNK);
+  pl.nchunk = kp / OZK_K_CHUNK;
+  const int64_t ks = k_split_of(c, p);
+  pl.steps_per_split = ks / OZK_K_CHUNK;
+  pl.nsplit = pl.nchunk <= pl.steps_per_split ? 1 : (pl.nchunk + pl.steps_per_split - 1) / pl.steps_per_split;
+  if (pl.nchunk == 0) pl.nsplit = 1;
+  size_t o = 0;
+  pl.off_e = o; o = align256(o + 4 * (size_t)(M > 0 ? M : 1));
+  pl.off_f = o; o = align256(o + 4 * (size_t)(N > 0 ? N : 1));
+  pl.off_a = o; o = align256(o + ozk_s1_packed_bytes(M, K, p));
+  pl.off_b = o; o = align256(o + ozk_s1_packed_bytes(N, K, p));
+  pl.off_z = o;
+  if (pl.nsplit > 1) o = align256(o + 16 * (size_t)pl.nsplit * M * N);
+  pl.total = o;
+  return pl;
+}
+
+struct S2Plan {
+  size_t off_sig, off_tau, off_a, off_b, off_res, total;
+};
+
+S2Plan s2_plan(int s, bool cplx, int64_t M, int64_t N, int64_t K) {
+  S2Plan pl;
+  size_t o = 0;
+  pl.off_sig = o; o = align256(o + 4 * (size_t)(M > 0 ? M : 1));
+  pl.off_tau = o; o = align256(o + 4 * (size_t)(N > 0 ? N : 1));
+  pl.off_a = o; o = align256(o + ozk_s2_packed_bytes(M, K, s, cplx));
+  pl.off_b = o; o = align256(o + ozk_s2_packed_bytes(N, K, s, cplx));
+  pl.off_res = o; o = align256(o + (size_t)s * (cplx ? 2 : 1) * M * N);
+  pl.total = o;
+  return pl;
+}
+
+bool bad_dims(int64_t M, int64_t N, int64_t K) {
+  return M < 0 || N < 0 || K < 0 || M > 0x7fffffff || N > 0x7fffffff || K > ((int64_t)1 << 40);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* ozk_version(void) { return "0.1.0"; }
+
+const char* ozk_status_string(ozk_status s) {
+  switch (s) {
+    case OZK_OK: return "ok";
+    case OZK_ERR_INVALID_ARG: return "invalid argument";
+    case OZK_ERR_UNSUPPORTED: return "unsupported slice or modulus count";
+    case OZK_ERR_WORKSPACE: return "workspace missing or too small";
+    case OZK_ERR_HIP: return "HIP runtime error";
+  }
+  return "unknown status";
+}
+
+ozk_status ozk_create(ozk_ctx** ctx, int device) {
+  if (!ctx) return OZK_ERR_INVALID_ARG;
+  *ctx = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess) return OZK_ERR_HIP;
+  if (device < 0 || device >= n) return OZK_ERR_INVALID_ARG;
+  if (hipSetDevice(device) != hipSuccess) return OZK_ERR_HIP;
+  ozk_ctx* c = (ozk_ctx*)calloc(1, sizeof(ozk_ctx));
+  if (!c) return OZK_ERR_HIP;
+  c->device = device;
+  const char* ks = getenv("OZK_K_SPLIT");
+  if (ks) c->k_split_override = atoll(ks);
+  *ctx = c;
+  return OZK_OK;
+}
+
+ozk_status ozk_destroy(ozk_ctx* ctx) {
+  free(ctx);
+  return OZK_OK;
+}
+
+int ozk_last_arg(const ozk_ctx* ctx) { return ctx ? ctx->last_arg : 0; }
+
+size_t ozk_s1_packed_bytes(int64_t rows, int64_t K, int p) {
+  if (rows < 0 || K < 0 || p < 1) return 0;
+  return (size_t)round_up(rows, OZK_ROW_ALIGN) * (size_t)round_up(K, OZK_K_CHUNK) * (size_t)p;
+}
+
+size_t ozk_s2_packed_bytes(int64_t rows, int64_t K, int s, int complex_planes) {
+  if (rows < 0 || K < 0 || s < 1) return 0;
+  return (size_t)round_up(rows, OZK_ROW_ALIGN) * (size_t)round_up(K, OZK_K_CHUNK) * (size_t)s *
+         (complex_planes ? 3 : 1);
+}
+
+int64_t ozk_s1_k_split(int p) {
+  if (p < 1 || p > OZK_MAX_P) return 0;
+  return k_split_of(nullptr, p);
+}
+
+ozk_status ozk_workspace_size(ozk_ctx* ctx, ozk_op op, ozk_scheme scheme, int64_t M, int64_t N, int64_t K,
+                              int p_or_s, size_t* bytes) {
+  if (!ctx) return OZK_ERR_INVALID_ARG;
+  ctx->last_arg = 0;
+  if (!bytes) return fail(ctx, OZK_ERR_INVALID_ARG, 8);
+  if (bad_dims(M, N, K)) return fail(ctx, OZK_ERR_INVALID_ARG, 4);
+  if (op == OZK_OP_DGEMM && scheme == OZK_SCHEME1) {
+    if (p_or_s < 1 || p_or_s > OZK_MAX_P) return fail(ctx, OZK_ERR_UNSUPPORTED, 7);
+    *bytes = s1_plan(ctx, p_or_s, M, N, K).total;
+    return OZK_OK;
+  }
+  if (scheme == OZK_SCHEME2 && (op == OZK_OP_DGEMM || op == OZK_OP_ZGEMM)) {
+    if (p_or_s < 1 || p_or_s > OZK_MAX_S) return fail(ctx, OZK_ERR_UNSUPPORTED, 7);
+    *bytes = s2_plan(p_or_s, op == OZK_OP_ZGEMM, M, N, K).total;
+    return OZK_OK;
+  }
+  if (op != OZK_OP_DGEMM && op != OZK_OP_ZGEMM) return fail(ctx, OZK_ERR_INVALID_ARG, 2);
+  return fail(ctx, OZK_ERR_UNSUPPORTED, 3);
+}
+
+ozk_status ozk_s1_split_rows(ozk_ctx* ctx, int p, int64_t rows, int64_t K, const double* X, int64_t ldx,
+                             int32_t* e, int8_t* packed, hipStream_t stream) {
+  if (!ctx) return OZK_ERR_INVALID_ARG;
+  ctx->last_arg = 0;
+  if (p < 1 || p > OZK_MAX_P) return fail(ctx, OZK_ERR_UNSUPPORTED, 2);
+  if (rows < 0 || rows > 0x7fffffff) return fail(ctx, OZK_ERR_INVALID_ARG, 3);
+  if (K < 0 || K > ((int64_t)1 << 40)) return fail(ctx, OZK_ERR_INVALID_ARG, 4);
+  if (!X && rows > 0 && K > 0) return fail(ctx, OZK_ERR_INVALID_ARG, 5);
+  if (ldx < (K > 0 ? K : 1)) return fail(ctx, OZK_ERR_INVALID_ARG, 6);
+  if (!e && rows > 0) return fail(ctx, OZK_ERR_INVALID_ARG, 7);
+  if (!packed && rows > 0) return fail(ctx, OZK_ERR_INVALID_ARG, 8);
+  return hip_status(ctx, ozk::s1_split_rows(p, X, ldx, rows, K, e, packed, stream));
+}
+
+ozk_status ozk_s1_split_cols(ozk_ctx* ctx, int p, int64_t K, int64_t cols, const double* X, int64_t ldx,
+                             int32_t* f, int8_t* packed, hipStream_t stream) {
+  if (!ctx) return OZK_ERR_INVALID_ARG;
+  ctx->last_arg = 0;
+  if (p < 1 || p > OZK_MAX_P) return fail(ctx, OZK_ERR_UNSUPPORTED, 2);
+  if (K < 0 || K > ((int64_t)1 << 40)) return fail(ctx, OZK_ERR_INVALID_ARG, 3);
+  if (cols < 0 || cols > 0x7fffffff) return fail(ctx, OZK_ERR_INVALID_ARG, 4);
+  if (!X && cols > 0 && K > 0) return fail(ctx, OZK_ERR_INVALID_ARG, 5);
+  if (ldx < (cols > 0 ? cols : 1)) return fail(ctx, OZK_ERR_INVALID_ARG, 6);
+  if (!f && cols > 0) return fail(ctx, OZK_ERR_INVALID_ARG, 7);
+  if (!packed && cols > 0) return fail(ctx, OZK_ERR_INVALID_ARG, 8);
+  return hip_status(ctx, ozk::s1_split_cols(p, X, ldx, K, cols, f, packed, stream));
+}
+
+static ozk_status s1_gemm_common(ozk_ctx* ctx, int p, int64_t M, int64_t N, int64_t K, const int8_t* Ap,
+                                 const int32_t* e, const int8_t* Bp, const int32_t* f, double alpha,
+                                 double beta, double* C, int64_t ldc, void* ws, size_t ws_bytes,
+                                 int32_t* diag, hipStream_t stream) {
+  const S1Plan pl = s1_plan(ctx, p, M, N, K);
+  ozk::S1GemmArgs g;
+  g.M = M;
+  g.N = N;
+  g.Ap = Ap;
+  g.Bp = Bp;
+  g.nchunk = pl.nchunk;
+  g.steps_per_split = pl.nsplit > 1 ? pl.steps_per_split : (pl.nchunk > 0 ? pl.nchunk : 1);
+  g.nsplit = pl.nsplit;
+  g.e = e;
+  g.f = f;
+  g.alpha = alpha;
+  g.beta = beta;
+  g.C = C;
+  g.ldc = ldc;
+  g.zpart = nullptr;
+  g.diag = diag;
+  if (!diag && pl.nsplit > 1) {
+    const size_t need = 16 * (size_t)pl.nsplit * M * N;
+    if (!ws || ws_bytes < need) return fail(ctx, OZK_ERR_WORKSPACE, 15);
+    g.zpart = (int64_t*)ws;
+  }
+  return hip_status(ctx, ozk::s1_gemm(p, g, stream));
+}
+
+ozk_status ozk_s1_gemm(ozk_ctx* ctx, int p, int64_t M, int64_t N, int64_t K, const int8_t* packedA,
+                       const int32_t* e, const int8_t* packedB, const int32_t* f, double alpha, double beta,
+                       double* C, int64_t ldc, void* ws, size_t ws_bytes, hipStream_t stream) {
+  if (!ctx) return OZK_ERR_INVALID_ARG;
+  ctx->last_arg = 0;
+  if (p < 1 || p > OZK_MAX_P) return fail(ctx, OZK_ERR_UNSUPPORTED, 2);
+  if (bad_dims(M, N, K)) return fail(ctx, OZK_ERR_INVALID_ARG, 3);
+  if (M > 0 && N > 0) {
+    if (!packedA) return fail(ctx, OZK_ERR_INVALID_ARG, 6);
+    if (!e) return fail(ctx, OZK_ERR_INVALID_ARG, 7);
+    if (!packedB) return fail(ctx, OZK_ERR_INVALID_ARG, 8);
+    if (!f) return fail(ctx, OZK_ERR_INVALID_ARG, 9);
+    if (!C) return fail(ctx, OZK_ERR_INVALID_ARG, 12);
+  }
+  if (ldc < (N > 0 ? N : 1)) return fail(ctx, OZK_ERR_INVALID_ARG, 13);
+  return s1_gemm_common(ctx, p, M, N, K, packedA, e, packedB, f, alpha, beta, C, ldc, ws, ws_bytes, nullptr,
+                        stream);
+}
+
+ozk_status ozk_s1_diagonals(ozk_ctx* ctx, int p, int64_t M, int64_t N, int64_t K, const int8_t* packedA,
+                            const int8_t* packedB, int32_t* Cd, hipStream_t stream) {
+  if (!ctx) return OZK_ERR_INVALID_ARG;
+  ctx->last_arg = 0;
+  if (p < 1 || p > OZK_MAX_P) return fail(ctx, OZK_ERR_UNSUPPORTED, 2);
+  if (bad_dims(M, N, K)) return fail(ctx, OZK_ERR_INVALID_ARG, 3);
+  if (K > k_split_of(ctx, p)) return fail(ctx, OZK_ERR_UNSUPPORTED, 5);
+  if (M > 0 && N > 0 && (!packedA || !packedB || !Cd)) return fail(ctx, OZK_ERR_INVALID_ARG, 6);
+  return s1_gemm_common(ctx, p, M, N, K, packedA, nullptr, packedB, nullptr, 1.0, 0.0, nullptr, N > 0 ? N : 1,
+                        nullptr, 0, Cd, stream);
+}
+
+ozk_status ozk_dgemm(ozk_ctx* ctx, ozk_scheme scheme, int p_or_s, int64_t M, int64_t N, int64_t K,
+                     double alpha, const double* A, int64_t lda, const double* B, int64_t ldb, double beta,
+                     double* C, int64_t ldc, void* ws, size_t ws_bytes, hipStream_t stream) {
+  if (!ctx) return OZK_ERR_INVALID_ARG;
+  ctx->last_arg = 0;
+  if (scheme != OZK_SCHEME1 && scheme != OZK_SCHEME2) return fail(ctx, OZK_ERR_INVALID_ARG, 2);
+  if (bad_dims(M, N, K)) return fail(ctx, OZK_ERR_INVALID_ARG, M < 0 ? 4 : (N < 0 ? 5 : 6));
+  if (!A && M > 0 && K > 0) return fail(ctx, OZK_ERR_INVALID_ARG, 8);
+  if (lda < (K > 0 ? K : 1)) return fail(ctx, OZK_ERR_INVALID_ARG, 9);
+  if (!B && K > 0 && N > 0) return fail(ctx, OZK_ERR_INVALID_ARG, 10);
+  if (ldb < (N > 0 ? N : 1)) return fail(ctx, OZK_ERR_INVALID_ARG, 11);
+  if (!C && M > 0 && N > 0) return fail(ctx, OZK_ERR_INVALID_ARG, 13);
+  if (ldc < (N > 0 ? N : 1)) return fail(ctx, OZK_ERR_INVALID_ARG, 14);
+  if (scheme == OZK_SCHEME2) {
+    const int s = p_or_s;
+    if (s < 1 || s > OZK_MAX_S) return fail(ctx, OZK_ERR_UNSUPPORTED, 3);
+    const S2Plan pl = s2_plan(s, false, M, N, K);
+    if (!ws || ws_bytes < pl.total) return fail(ctx, OZK_ERR_WORKSPACE, 15);
+    if (M == 0 || N == 0) return OZK_OK;
+    char* w = (char*)ws;
+    int32_t* sig = (int32_t*)(w + pl.off_sig);
+    int32_t* tau = (int32_t*)(w + pl.off_tau);
+    int8_t* Ap = (int8_t*)(w + pl.off_a);
+    int8_t* Bp = (int8_t*)(w + pl.off_b);
+    int8_t* res = (int8_t*)(w + pl.off_res);
+    hipError_t err = ozk::s2_split_rows(s, false, A, lda, M, K, sig, Ap, stream);
+    if (err == hipSuccess) err = ozk::s2_split_cols(s, false, B, ldb, K, N, tau, Bp, stream);
+    if (err == hipSuccess) err = ozk::s2_gemm_mod(s, false, M, N, K, Ap, Bp, res, stream);
+    const double al[2] = {alpha, 0.0}, be[2] = {beta, 0.0};
+    if (err == hipSuccess) err = ozk::s2_crt(s, false, M, N, res, sig, tau, al, be, C, ldc, stream);
+    return hip_status(ctx, err);
+  }
+  const int p = p_or_s;
+  if (p < 1 || p > OZK_MAX_P) return fail(ctx, OZK_ERR_UNSUPPORTED, 3);
+  const S1Plan pl = s1_plan(ctx, p, M, N, K);
+  if (!ws || ws_bytes < pl.total) return fail(ctx, OZK_ERR_WORKSPACE, 15);
+  if (M == 0 || N == 0) return OZK_OK;
+  char* w = (char*)ws;
+  int32_t* e = (int32_t*)(w + pl.off_e);
+  int32_t* f = (int32_t*)(w + pl.off_f);
+  int8_t* Ap = (int8_t*)(w + pl.off_a);
+  int8_t* Bp = (int8_t*)(w + pl.off_b);
+  hipError_t err = ozk::s1_split_rows(p, A, lda, M, K, e, Ap, stream);
+  if (err == hipSuccess) err = ozk::s1_split_cols(p, B, ldb, K, N, f, Bp, stream);
+  if (err != hipSuccess) return hip_status(ctx, err);
+  return s1_gemm_common(ctx, p, M, N, K, Ap, e, Bp, f, alpha, beta, C, ldc, w + pl.off_z,
+                        pl.total - pl.off_z, nullptr, stream);
+}
+
+ozk_status ozk_zgemm_3m(ozk_ctx* ctx, int s, int64_t M, int64_t N, int64_t K, const double* alpha,
+                        const double* A, int64_t lda, const double* B, int64_t ldb, const double* beta,
+                        double* C, int64_t ldc, void* ws, size_t ws_bytes, hipStream_t stream) {
+  if (!ctx) return OZK_ERR_INVALID_ARG;
+  ctx->last_arg = 0;
+  if (s < 1 || s > OZK_MAX_S) return fail(ctx, OZK_ERR_UNSUPPORTED, 2);
+  if (bad_dims(M, N, K)) return fail(ctx, OZK_ERR_INVALID_ARG, M < 0 ? 3 : (N < 0 ? 4 : 5));
+  if (!alpha) return fail(ctx, OZK_ERR_INVALID_ARG, 6);
+  if (!A && M > 0 && K > 0) return fail(ctx, OZK_ERR_INVALID_ARG, 7);
+  if (lda < (K > 0 ? K : 1)) return fail(ctx, OZK_ERR_INVALID_ARG, 8);
+  if (!B && K > 0 && N > 0) return fail(ctx, OZK_ERR_INVALID_ARG, 9);
+  if (ldb < (N > 0 ? N : 1)) return fail(ctx, OZK_ERR_INVALID_ARG, 10);
+  if (!beta) return fail(ctx, OZK_ERR_INVALID_ARG, 11);
+  if (!C && M > 0 && N > 0) return fail(ctx, OZK_ERR_INVALID_ARG, 12);
+  if (ldc < (N > 0 ? N : 1)) return fail(ctx, OZK_ERR_INVALID_ARG, 13);
+  const S2Plan pl = s2_plan(s, true, M, N, K);
+  if (!ws || ws_bytes < pl.total) return fail(ctx, OZK_ERR_WORKSPACE, 14);
+  if (M == 0 || N == 0) return OZK_OK;
+  char* w = (char*)ws;
+  int32_t* sig = (int32_t*)(w + pl.off_sig);
+  int32_t* tau = (int32_t*)(w + pl.off_tau);
+  int8_t* Ap = (int8_t*)(w + pl.off_a);
+  int8_t* Bp = (int8_t*)(w + pl.off_b);
+  int8_t* res = (int8_t*)(w + pl.off_res);
+  hipError_t err = ozk::s2_split_rows(s, true, A, lda, M, K, sig, Ap, stream);
+  if (err == hipSuccess) err = ozk::s2_split_cols(s, true, B, ldb, K, N, tau, Bp, stream);
+  if (err == hipSuccess) err = ozk::s2_gemm_mod(s, true, M, N, K, Ap, Bp, res, stream);
+  if (err == hipSuccess) err = ozk::s2_crt(s, true, M, N, res, sig, tau, alpha, beta, C, ldc, stream);
+  return hip_status(ctx, err);
+}
+
+ozk_status ozk_s2_split_rows(ozk_ctx* ctx, int s, int complex_planes, int64_t rows, int64_t K,
+                             const double* X, int64_t ldx, int32_t* sigma, int8_t* packed,
+                             hipStream_t stream) {
+  if (!ctx) return OZK_ERR_INVALID_ARG;
+  ctx->last_arg = 0;
+  if (s < 1 || s > OZK_MAX_S) return fail(ctx, OZK_ERR_UNSUPPORTED, 2);
+  if (complex_planes != 0 && complex_planes != 1) return fail(ctx, OZK_ERR_INVALID_ARG, 3);
+  if (rows < 0 || rows > 0x7fffffff) return fail(ctx, OZK_ERR_INVALID_ARG, 4);
+  if (K < 0 || K > ((int64_t)1 << 40)) return fail(ctx, OZK_ERR_INVALID_ARG, 5);
+  if (!X && rows > 0 && K > 0) return fail(ctx, OZK_ERR_INVALID_ARG, 6);
+  if (ldx < (K > 0 ? K : 1)) return fail(ctx, OZK_ERR_INVALID_ARG, 7);
+  if (!sigma && rows > 0) return fail(ctx, OZK_ERR_INVALID_ARG, 8);
+  if (!packed && rows > 0) return fail(ctx, OZK_ERR_INVALID_ARG, 9);
+  return hip_status(ctx, ozk::s2_split_rows(s, complex_planes != 0, X, ldx, rows, K, sigma, packed, stream));
+}
+
+ozk_status ozk_s2_split_cols(ozk_ctx* ctx, int s, int complex_planes, int64_t K, int64_t cols,
+                             const double* X, int64_t ldx, int32_t* tau, int8_t* packed,
+                             hipStream_t stream) {
+  if (!ctx) return OZK_ERR_INVALID_ARG;
+  ctx->last_arg = 0;
+  if (s < 1 || s > OZK_MAX_S) return fail(ctx, OZK_ERR_UNSUPPORTED, 2);
+  if (complex_planes != 0 && complex_planes != 1) return fail(ctx, OZK_ERR_INVALID_ARG, 3);
+  if (K < 0 || K > ((int64_t)1 << 40)) return fail(ctx, OZK_ERR_INVALID_ARG, 4);
+  if (cols < 0 || cols > 0x7fffffff) return fail(ctx, OZK_ERR_INVALID_ARG, 5);
+  if (!X && cols > 0 && K > 0) return fail(ctx, OZK_ERR_INVALID_ARG, 6);
+  if (ldx < (cols > 0 ? cols : 1)) return fail(ctx, OZK_ERR_INVALID_ARG, 7);
+  if (!tau && cols > 0) return fail(ctx, OZK_ERR_INVALID_ARG, 8);
+  if (!packed && cols > 0) return fail(ctx, OZK_ERR_INVALID_ARG, 9);
+  return hip_status(ctx, ozk::s2_split_cols(s, complex_planes != 0, X, ldx, K, cols, tau, packed, stream));
+}
+
+ozk_status ozk_s2_gemm_mod(ozk_ctx* ctx, int s, int complex_planes, int64_t M, int64_t N, int64_t K,
+                           const int8_t* packedA, const int8_t* packedB, int8_t* Cres, hipStream_t stream) {
+  if (!ctx) return OZK_ERR_INVALID_ARG;
+  ctx->last_arg = 0;
+  if (s < 1 || s > OZK_MAX_S) return fail(ctx, OZK_ERR_UNSUPPORTED, 2);
+  if (complex_planes != 0 && complex_planes != 1) return fail(ctx, OZK_ERR_INVALID_ARG, 3);
+  if (bad_dims(M, N, K)) return fail(ctx, OZK_ERR_INVALID_ARG, 4);
+  if (M > 0 && N > 0 && (!packedA || !packedB || !Cres)) return fail(ctx, OZK_ERR_INVALID_ARG, 7);
+  return hip_status(ctx, ozk::s2_gemm_mod(s, complex_planes != 0, M, N, K, packedA, packedB, Cres, stream));
+}
+
+ozk_status ozk_s2_crt(ozk_ctx* ctx, int s, int complex_planes, int64_t M, int64_t N, const int8_t* Cres,
+                      const int32_t* sigma, const int32_t* tau, const double* alpha, const double* beta,
+                      double* C, int64_t ldc, hipStream_t stream) {
+  if (!ctx) return OZK_ERR_INVALID_ARG;
+  ctx->last_arg = 0;
+  if (s < 1 || s > OZK_MAX_S) return fail(ctx, OZK_ERR_UNSUPPORTED, 2);
+  if (complex_planes != 0 && complex_planes != 1) return fail(ctx, OZK_ERR_INVALID_ARG, 3);
+  if (M < 0 || M > 0x7fffffff) return fail(ctx, OZK_ERR_INVALID_ARG, 4);
+  if (N < 0 || N > 0x7fffffff) return fail(ctx, OZK_ERR_INVALID_ARG, 5);
+  if (M > 0 && N > 0 && (!Cres || !sigma || !tau || !C)) return fail(ctx, OZK_ERR_INVALID_ARG, 6);
+  if (!alpha) return fail(ctx, OZK_ERR_INVALID_ARG, 9);
+  if (!beta) return fail(ctx, OZK_ERR_INVALID_ARG, 10);
+  if (ldc < (N > 0 ? N : 1)) return fail(ctx, OZK_ERR_INVALID_ARG, 12);
+  return hip_status(ctx, ozk::s2_crt(s, complex_planes != 0, M, N, Cres, sigma, tau, alpha, beta, C, ldc, stream));
+}
+
+}  // extern "C"

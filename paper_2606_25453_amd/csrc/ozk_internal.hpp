@@ -1,0 +1,45 @@
+// Host-side declarations shared by the kernel files and the C ABI layer.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ozk.h"
+
+namespace ozk {
+
+static inline int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
+
+struct S1GemmArgs {
+  int64_t M, N;
+  const int8_t* Ap;
+  const int8_t* Bp;
+  int64_t nchunk;           // K steps of 32 in the packed operands
+  int64_t steps_per_split;  // K steps per K run (overflow-free)
+  int64_t nsplit;           // number of K runs
+  const int32_t* e;
+  const int32_t* f;
+  double alpha, beta;
+  double* C;
+  int64_t ldc;
+  int64_t* zpart;  // nsplit x M x N x 2 int64 when nsplit > 1
+  int32_t* diag;   // p x M x N int32 for the check entry point, else null
+};
+
+hipError_t s1_split_rows(int p, const double* X, int64_t ldx, int64_t rows, int64_t K, int32_t* e,
+                         int8_t* packed, hipStream_t st);
+hipError_t s1_split_cols(int p, const double* X, int64_t ldx, int64_t K, int64_t cols, int32_t* f,
+                         int8_t* packed, hipStream_t st);
+hipError_t s1_gemm(int p, const S1GemmArgs& g, hipStream_t st);
+
+void s2_targets(int s, int& ta, int& tb);
+hipError_t s2_split_rows(int s, bool cplx, const double* X, int64_t ldx, int64_t rows, int64_t K, int32_t* sigma,
+                         int8_t* packed, hipStream_t st);
+hipError_t s2_split_cols(int s, bool cplx, const double* X, int64_t ldx, int64_t K, int64_t cols, int32_t* tau,
+                         int8_t* packed, hipStream_t st);
+hipError_t s2_gemm_mod(int s, bool cplx, int64_t M, int64_t N, int64_t K, const int8_t* Ap, const int8_t* Bp,
+                       int8_t* out, hipStream_t st);
+hipError_t s2_crt(int s, bool cplx, int64_t M, int64_t N, const int8_t* res, const int32_t* sigma,
+                  const int32_t* tau, const double* alpha, const double* beta, double* C, int64_t ldc,
+                  hipStream_t st);
+
+}  // namespace ozk

@@ -1,0 +1,694 @@
+// Ozaki Scheme II on gfx950 INT8 MFMA (paper Sec. II-C.2 and Sec. IV), real
+// and 3M complex.
+//
+//   k_s2_split_rows     row scale sigma_i from an exact bound on the row's
+//                       2-norm, then the s symmetric residue planes (Eq. 5)
+//   k_s2_col_scales     the same for the columns of B (LDS reductions of
+//                       integers, so the result does not depend on the order)
+//   k_s2_gemm_mod       one INT8 GEMM per modulus with smod in the epilogue
+//                       (Eqs. 6-7); 3M: three products per modulus and the
+//                       combination T1-T2, T3-T1-T2 before the reduction
+//   k_s2_crt            CRT recombination in multiword integers (Eq. 8) with
+//                       the symmetric lift, then one rounding of Z 2^-(sigma+tau)
+#include "mfma_gemm.hpp"
+#include "ozk_device.hpp"
+#include "ozk_internal.hpp"
+
+namespace ozk {
+
+// ------------------------------------------------------------- moduli table
+
+struct S2Tables {
+  int m[OZK_MAX_S];
+  double inv_m[OZK_MAX_S];
+  uint8_t pow2[OZK_MAX_S][128];  // 2^k mod m_l
+};
+
+constexpr int gcd_c(int a, int b) { return b == 0 ? a : gcd_c(b, a % b); }
+
+// Greedy descending pairwise-coprime moduli from 256 (256, 255, 253, ...).
+constexpr S2Tables make_s2_tables() {
+  S2Tables t{};
+  int n = 0;
+  for (int c = 256; n < OZK_MAX_S; --c) {
+    bool ok = true;
+    for (int i = 0; i < n; ++i)
+      if (gcd_c(c, t.m[i]) != 1) ok = false;
+    if (ok) t.m[n++] = c;
+  }
+  for (int i = 0; i < OZK_MAX_S; ++i) {
+    t.inv_m[i] = 1.0 / t.m[i];
+    int r = 1 % t.m[i];
+    for (int k = 0; k < 128; ++k) {
+      t.pow2[i][k] = (uint8_t)r;
+      r = (2 * r) % t.m[i];
+    }
+  }
+  return t;
+}
+
+constexpr S2Tables kS2 = make_s2_tables();
+__constant__ S2Tables c_s2 = kS2;
+
+int s2_modulus(int l) { return kS2.m[l]; }
+
+// x mod m in [0, m) for |x| < 2^53 given as an exact double.
+__device__ __forceinline__ int mod_small(double x, int m, double inv_m) {
+  const double q = floor(x * inv_m);
+  int r = (int)__fma_rn(-q, (double)m, x);
+  if (r < 0) r += m;
+  if (r >= m) r -= m;
+  return r;
+}
+
+// smod: the representative of r (0 <= r < m) in [-floor(m/2), ceil(m/2)-1].
+__device__ __forceinline__ int sym(int r, int m) { return r >= (m + 1) / 2 ? r - m : r; }
+
+// smod of an INT32 accumulator.
+__device__ __forceinline__ int smod_i32(int x, int l) {
+  const int m = c_s2.m[l];
+  return sym(mod_small((double)x, m, c_s2.inv_m[l]), m);
+}
+
+// a' = trunc(a 2^sigma) as sign * u * 2^k with u < 2^53 an integer (as an
+// exact double) and k >= 0.
+struct ScaledInt {
+  double u;
+  int k;
+  bool neg;
+};
+
+__device__ __forceinline__ ScaledInt scaled_int(double a, int sigma) {
+  int64_t m;
+  int q;
+  split_fp64(a, m, q);
+  ScaledInt s;
+  s.neg = m < 0;
+  uint64_t am = s.neg ? (uint64_t)(-m) : (uint64_t)m;
+  const int sh = q + sigma;
+  if (am == 0) {
+    s.u = 0.0;
+    s.k = 0;
+  } else if (sh >= 0) {
+    s.u = (double)am;
+    s.k = sh;
+  } else {
+    s.u = (-sh >= 64) ? 0.0 : (double)(am >> (-sh));
+    s.k = 0;
+  }
+  return s;
+}
+
+__device__ __forceinline__ int residue_of(const ScaledInt& v, int l) {
+  const int m = c_s2.m[l];
+  int r = mod_small(v.u, m, c_s2.inv_m[l]);
+  if (v.k > 0) r = mod_small((double)(r * (int)c_s2.pow2[l][v.k < 128 ? v.k : 127]), m, c_s2.inv_m[l]);
+  if (v.neg && r) r = m - r;
+  return sym(r, m);
+}
+
+// Per-entry exponent for the scale bound: |entry| < 2^ex.  Complex entries
+// bound |re| + |im| < 2^(max(expo re, expo im) + 1).
+template <bool CPLX>
+__device__ __forceinline__ int entry_expo(const double* x) {
+  if (!CPLX) return expo_of(x[0]);
+  const int a = expo_of(x[0]), b = expo_of(x[1]);
+  if (a == OZK_EXP_NONFINITE || b == OZK_EXP_NONFINITE) return OZK_EXP_NONFINITE;
+  const int e = a > b ? a : b;
+  return e == OZK_EXP_ZERO ? OZK_EXP_ZERO : e + 1;
+}
+
+// ceil(2^40 4^(ex - emax)) for an entry with exponent ex <= emax; 0 for zero.
+__device__ __forceinline__ int64_t norm_term(int ex, int emax) {
+  if (ex == OZK_EXP_ZERO) return 0;
+  const int d = ex - emax;
+  return d >= -20 ? ((int64_t)1 << (40 + 2 * d)) : 1;
+}
+
+// sigma = T - nb with nb = emax + ceil((ceil(log2 S) - 40) / 2).
+__device__ __forceinline__ int scale_from(int emax, int64_t S, int T) {
+  if (emax == OZK_EXP_NONFINITE) return OZK_EXP_NONFINITE;
+  if (emax == OZK_EXP_ZERO || S <= 0) return 0;
+  const int clog = S == 1 ? 0 : 64 - __clzll((uint64_t)(S - 1));
+  const int c = clog - 40;
+  const int half = c >= 0 ? (c + 1) / 2 : -((-c) / 2);
+  return T - (emax + half);
+}
+
+__device__ __forceinline__ int64_t wave_sum64(int64_t v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+struct S2Args {
+  int s;
+  int T;  // T_A for rows, T_B for columns
+};
+
+// One wave per packed row: exponent max, norm-bound sum, then residues of 4
+// consecutive k per lane (one dword per plane).  Real layout
+// packed[l][r][k]; complex layout packed[l][r][c][q][32] (q = re, im, sum).
+template <bool CPLX>
+__global__ __launch_bounds__(256) void k_s2_split_rows(const double* __restrict__ X, int64_t ldx, int64_t rows,
+                                                       int64_t K, int64_t Kp, int64_t rows_packed, S2Args sa,
+                                                       int32_t* __restrict__ sigma_out,
+                                                       int8_t* __restrict__ packed) {
+  constexpr int W = CPLX ? 2 : 1;
+  const int lane = threadIdx.x & 63;
+  const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (r >= rows_packed) return;
+  const double* xr = X + r * ldx * W;
+  int sigma = 0;
+  if (r < rows) {
+    int e = OZK_EXP_ZERO;
+    for (int64_t k = lane; k < K; k += 64) {
+      const int ek = entry_expo<CPLX>(xr + k * W);
+      e = ek > e ? ek : e;
+    }
+    e = wave_max(e);
+    int64_t S = 0;
+    if (e != OZK_EXP_NONFINITE && e != OZK_EXP_ZERO)
+      for (int64_t k = lane; k < K; k += 64) S += norm_term(entry_expo<CPLX>(xr + k * W), e);
+    S = wave_sum64(S);
+    sigma = scale_from(e, S, sa.T);
+    if (lane == 0) sigma_out[r] = sigma;
+  }
+  const bool live = r < rows && sigma != OZK_EXP_NONFINITE;
+  const int64_t plane = rows_packed * Kp * (CPLX ? 3 : 1);
+  for (int64_t k0 = (int64_t)lane * 4; k0 < Kp; k0 += 256) {
+    ScaledInt vr[4], vi[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int64_t k = k0 + j;
+      const bool in = live && k < K;
+      vr[j] = scaled_int(in ? xr[k * W] : 0.0, sigma);
+      if (CPLX) vi[j] = scaled_int(in ? xr[k * W + 1] : 0.0, sigma);
+    }
+    for (int l = 0; l < sa.s; ++l) {
+      const int m = c_s2.m[l];
+      uint32_t w0 = 0, w1 = 0, w2 = 0;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int a = residue_of(vr[j], l);
+        w0 |= (uint32_t)(uint8_t)a << (8 * j);
+        if (CPLX) {
+          const int b = residue_of(vi[j], l);
+          w1 |= (uint32_t)(uint8_t)b << (8 * j);
+          w2 |= (uint32_t)(uint8_t)sym(((a + b) % m + m) % m, m) << (8 * j);
+        }
+      }
+      int8_t* base = packed + l * plane;
+      if (!CPLX) {
+        *reinterpret_cast<uint32_t*>(base + r * Kp + k0) = w0;
+      } else {
+        const int64_t c = k0 / OZK_K_CHUNK, kk = k0 % OZK_K_CHUNK;
+        int8_t* dst = base + (r * (Kp / OZK_K_CHUNK) + c) * 3 * OZK_K_CHUNK + kk;
+        *reinterpret_cast<uint32_t*>(dst) = w0;
+        *reinterpret_cast<uint32_t*>(dst + OZK_K_CHUNK) = w1;
+        *reinterpret_cast<uint32_t*>(dst + 2 * OZK_K_CHUNK) = w2;
+      }
+    }
+  }
+}
+
+// Column scales: a block of 256 threads covers 32 consecutive columns with 8
+// k-groups per column (coalesced 32-column row segments); the max exponent
+// and then the norm-bound sum are reduced through LDS, so no atomics and no
+// scratch memory are needed and the result does not depend on the order.
+template <bool CPLX>
+__global__ __launch_bounds__(256) void k_s2_col_scales(const double* __restrict__ X, int64_t ldx, int64_t K,
+                                                       int64_t cols, int T, int32_t* __restrict__ tau) {
+  constexpr int W = CPLX ? 2 : 1;
+  __shared__ int red_e[8][32];
+  __shared__ int64_t red_s[8][32];
+  const int cl = threadIdx.x & 31, g = threadIdx.x >> 5;
+  const int64_t j = (int64_t)blockIdx.x * 32 + cl;
+  const bool in = j < cols;
+  int e = OZK_EXP_ZERO;
+  if (in)
+    for (int64_t k = g; k < K; k += 8) {
+      const int ek = entry_expo<CPLX>(X + (k * ldx + j) * W);
+      e = ek > e ? ek : e;
+    }
+  red_e[g][cl] = e;
+  __syncthreads();
+  int emax = red_e[0][cl];
+#pragma unroll
+  for (int i = 1; i < 8; ++i) emax = red_e[i][cl] > emax ? red_e[i][cl] : emax;
+  int64_t S = 0;
+  if (in && emax != OZK_EXP_ZERO && emax != OZK_EXP_NONFINITE)
+    for (int64_t k = g; k < K; k += 8) S += norm_term(entry_expo<CPLX>(X + (k * ldx + j) * W), emax);
+  red_s[g][cl] = S;
+  __syncthreads();
+  if (g == 0 && in) {
+    int64_t tot = 0;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) tot += red_s[i][cl];
+    tau[j] = scale_from(emax, tot, T);
+  }
+}
+
+// Thread (j, c): the 32 k of chunk c of column j, residues for every modulus.
+template <bool CPLX>
+__global__ __launch_bounds__(256) void k_s2_split_cols(const double* __restrict__ X, int64_t ldx, int64_t K,
+                                                       int64_t cols, int64_t Kp, int64_t cols_packed, int s,
+                                                       const int32_t* __restrict__ tau,
+                                                       int8_t* __restrict__ packed) {
+  constexpr int W = CPLX ? 2 : 1;
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t c = blockIdx.y;
+  if (j >= cols_packed) return;
+  const int t = j < cols ? tau[j] : 0;
+  const bool live = j < cols && t != OZK_EXP_NONFINITE;
+  ScaledInt vr[OZK_K_CHUNK], vi[CPLX ? OZK_K_CHUNK : 1];
+#pragma unroll
+  for (int kk = 0; kk < OZK_K_CHUNK; ++kk) {
+    const int64_t k = c * OZK_K_CHUNK + kk;
+    const bool in = live && k < K;
+    vr[kk] = scaled_int(in ? X[(k * ldx + j) * W] : 0.0, t);
+    if (CPLX) vi[CPLX ? kk : 0] = scaled_int(in ? X[(k * ldx + j) * W + 1] : 0.0, t);
+  }
+  const int64_t plane = cols_packed * Kp * (CPLX ? 3 : 1);
+  for (int l = 0; l < s; ++l) {
+    const int m = c_s2.m[l];
+    uint32_t w0[8] = {0, 0, 0, 0, 0, 0, 0, 0}, w1[8] = {0, 0, 0, 0, 0, 0, 0, 0}, w2[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+    for (int kk = 0; kk < OZK_K_CHUNK; ++kk) {
+      const int a = residue_of(vr[kk], l);
+      w0[kk / 4] |= (uint32_t)(uint8_t)a << (8 * (kk % 4));
+      if (CPLX) {
+        const int b = residue_of(vi[CPLX ? kk : 0], l);
+        w1[kk / 4] |= (uint32_t)(uint8_t)b << (8 * (kk % 4));
+        w2[kk / 4] |= (uint32_t)(uint8_t)sym(((a + b) % m + m) % m, m) << (8 * (kk % 4));
+      }
+    }
+    int8_t* base = packed + l * plane;
+    int8_t* dst = CPLX ? base + (j * (Kp / OZK_K_CHUNK) + c) * 3 * OZK_K_CHUNK : base + j * Kp + c * OZK_K_CHUNK;
+    uint4* q0 = reinterpret_cast<uint4*>(dst);
+    q0[0] = make_uint4(w0[0], w0[1], w0[2], w0[3]);
+    q0[1] = make_uint4(w0[4], w0[5], w0[6], w0[7]);
+    if (CPLX) {
+      uint4* q1 = reinterpret_cast<uint4*>(dst + OZK_K_CHUNK);
+      q1[0] = make_uint4(w1[0], w1[1], w1[2], w1[3]);
+      q1[1] = make_uint4(w1[4], w1[5], w1[6], w1[7]);
+      uint4* q2 = reinterpret_cast<uint4*>(dst + 2 * OZK_K_CHUNK);
+      q2[0] = make_uint4(w2[0], w2[1], w2[2], w2[3]);
+      q2[1] = make_uint4(w2[4], w2[5], w2[6], w2[7]);
+    }
+  }
+}
+
+// ----------------------------------------------------------- modular GEMM
+
+// Steps per INT32-safe run: |acc| <= 32 * steps * 128^2 must stay below 2^31,
+// so the accumulators are reduced mod m every 4095 steps (K = 131040); the
+// reduction is exact because only the residue is kept.
+constexpr int64_t S2_RUN_STEPS = 4095;
+
+template <bool CPLX>
+__global__ __launch_bounds__(256, 1) void k_s2_gemm_mod(const int8_t* __restrict__ Ap,
+                                                       const int8_t* __restrict__ Bp, int64_t plane_a,
+                                                       int64_t plane_b, int64_t nsteps, int M, int N,
+                                                       int8_t* __restrict__ out) {
+  constexpr int P = CPLX ? 3 : 1;
+  constexpr int TM = 2, TN = CPLX ? 1 : 2;
+  using T = GemmTile<P, TM, TN>;
+  extern __shared__ __attribute__((aligned(16))) int8_t lds[];
+  const int l = blockIdx.z;
+  const int64_t m0 = (int64_t)blockIdx.y * T::BM, n0 = (int64_t)blockIdx.x * T::BN;
+  const int64_t row_bytes = nsteps * T::ROW_BYTES;
+  v16i acc[P][TM][TN];
+  zero_acc<P, TM, TN>(acc);
+  for (int64_t s0 = 0; s0 < nsteps || s0 == 0; s0 += S2_RUN_STEPS) {
+    const int64_t n = nsteps - s0 < S2_RUN_STEPS ? nsteps - s0 : S2_RUN_STEPS;
+    gemm_tile_accumulate<P, TM, TN, DIAGONAL>(Ap + l * plane_a, Bp + l * plane_b, row_bytes, m0, n0, s0, n, lds,
+                                              acc);
+    if (s0 + S2_RUN_STEPS >= nsteps) break;
+    // keep the accumulators small by subtracting a multiple of m (exact mod m)
+    const int m = c_s2.m[l];
+    const float inv = 1.0f / (float)m;
+#pragma unroll
+    for (int d = 0; d < P; ++d)
+#pragma unroll
+      for (int a = 0; a < TM; ++a)
+#pragma unroll
+        for (int b = 0; b < TN; ++b)
+#pragma unroll
+          for (int v = 0; v < 16; ++v) {
+            const int x = acc[d][a][b][v];
+            acc[d][a][b][v] = x - m * (int)rintf((float)x * inv);
+          }
+  }
+  const int64_t mn = (int64_t)M * N;
+  for_each_output<P, TM, TN>(acc, m0, n0, M, N, [&](int64_t row, int64_t col, const int* vals) {
+    if (!CPLX) {
+      out[l * mn + row * N + col] = (int8_t)smod_i32(vals[0], l);
+    } else {
+      const int t1 = smod_i32(vals[0], l), t2 = smod_i32(vals[CPLX ? 1 : 0], l),
+                t3 = smod_i32(vals[CPLX ? 2 : 0], l);
+      out[(2 * l) * mn + row * N + col] = (int8_t)smod_i32(t1 - t2, l);
+      out[(2 * l + 1) * mn + row * N + col] = (int8_t)smod_i32(t3 - t1 - t2, l);
+    }
+  });
+}
+
+// ------------------------------------------------------------------- CRT
+
+constexpr int NL = 6;  // 32-bit limbs: P < 2^156 for s <= 20, sums < 2^170
+
+struct CrtArgs {
+  int s;
+  uint32_t W[OZK_MAX_S][NL];  // (P/m_l) q_l
+  uint32_t P[NL];
+  double Pf;
+};
+
+// Z = smod(sum_l W_l c_l, P) as a sign and magnitude limbs.
+__device__ __forceinline__ void crt_combine(const CrtArgs& ca, const int8_t* res, int64_t stride, uint32_t (&mag)[NL],
+                                            bool& neg) {
+  uint64_t acc[NL] = {0, 0, 0, 0, 0, 0};
+  for (int l = 0; l < ca.s; ++l) {
+    const int m = c_s2.m[l];
+    int c = res[l * stride];
+    if (c < 0) c += m;
+#pragma unroll
+    for (int i = 0; i < NL; ++i) acc[i] += (uint64_t)ca.W[l][i] * (uint32_t)c;
+  }
+  uint32_t v[NL + 1];
+  uint64_t carry = 0;
+#pragma unroll
+  for (int i = 0; i < NL; ++i) {
+    const uint64_t t = acc[i] + carry;
+    v[i] = (uint32_t)t;
+    carry = t >> 32;
+  }
+  v[NL] = (uint32_t)carry;
+  // quotient estimate by floating point, then exact correction
+  double vf = 0.0;
+#pragma unroll
+  for (int i = NL; i >= 0; --i) vf = vf * 4294967296.0 + (double)v[i];
+  int64_t q = (int64_t)floor(vf / ca.Pf);
+  if (q < 0) q = 0;
+  // r = v - q P (signed, NL+1 limbs, two's complement)
+  int64_t borrow = 0;
+  uint32_t r[NL + 1];
+  uint64_t mc = 0;
+#pragma unroll
+  for (int i = 0; i <= NL; ++i) {
+    const uint64_t pi = i < NL ? ca.P[i] : 0;
+    const uint64_t prod = pi * (uint64_t)q + mc;
+    mc = prod >> 32;
+    const int64_t d = (int64_t)v[i] - (int64_t)(uint32_t)prod + borrow;
+    r[i] = (uint32_t)d;
+    borrow = d >> 32;  // 0 or -1
+  }
+  auto negative = [&]() { return (int32_t)r[NL] < 0; };
+  auto add_p = [&](int sign) {  // r += sign * P
+    int64_t cy = 0;
+#pragma unroll
+    for (int i = 0; i <= NL; ++i) {
+      const int64_t pi = i < NL ? (int64_t)ca.P[i] : 0;
+      const int64_t d = (int64_t)r[i] + sign * pi + cy;
+      r[i] = (uint32_t)d;
+      cy = d >> 32;
+    }
+  };
+  auto ge_p = [&]() {  // r >= P (r non-negative)
+    if (r[NL]) return true;
+    for (int i = NL - 1; i >= 0; --i) {
+      if (r[i] != ca.P[i]) return r[i] > ca.P[i];
+    }
+    return true;
+  };
+  while (negative()) add_p(1);
+  while (ge_p()) add_p(-1);
+  // symmetric lift: r >= P/2  <=>  2r >= P
+  uint32_t tw[NL + 1];
+  uint32_t cy2 = 0;
+#pragma unroll
+  for (int i = 0; i <= NL; ++i) {
+    tw[i] = (r[i] << 1) | cy2;
+    cy2 = r[i] >> 31;
+  }
+  bool ge = false;
+  {
+    bool decided = false;
+    if (tw[NL]) {
+      ge = true;
+      decided = true;
+    }
+    for (int i = NL - 1; i >= 0 && !decided; --i) {
+      if (tw[i] != ca.P[i]) {
+        ge = tw[i] > ca.P[i];
+        decided = true;
+      }
+    }
+    if (!decided) ge = true;
+  }
+  if (ge) {
+    // magnitude = P - r
+    int64_t b = 0;
+#pragma unroll
+    for (int i = 0; i < NL; ++i) {
+      const int64_t d = (int64_t)ca.P[i] - (int64_t)r[i] + b;
+      mag[i] = (uint32_t)d;
+      b = d >> 32;
+    }
+    neg = true;
+  } else {
+#pragma unroll
+    for (int i = 0; i < NL; ++i) mag[i] = r[i];
+    neg = false;
+  }
+}
+
+// RN-even of +-mag 2^E (one rounding, gradual underflow included).
+__device__ __forceinline__ double round_limbs(const uint32_t (&mag)[NL], bool neg, int E) {
+  int top = -1;
+#pragma unroll
+  for (int i = NL - 1; i >= 0; --i)
+    if (top < 0 && mag[i]) top = i;
+  if (top < 0) return 0.0;
+  const int n = 32 * top + (32 - __clz(mag[top]));
+  int drop = n - 53;
+  if (-1074 - E > drop) drop = -1074 - E;
+  auto bit = [&](int pos) -> uint32_t { return (pos < 0 || pos >= 32 * NL) ? 0u : (mag[pos >> 5] >> (pos & 31)) & 1u; };
+  uint64_t q = 0;
+  if (drop <= 0) {
+    for (int i = n - 1; i >= 0; --i) q = (q << 1) | bit(i);
+    drop = 0;
+  } else {
+    for (int i = n - 1; i >= drop; --i) q = (q << 1) | bit(i);
+    const uint32_t rb = bit(drop - 1);
+    bool sticky = false;
+    for (int i = 0; i < drop - 1 && i < n; ++i) sticky |= bit(i) != 0;
+    if (rb && (sticky || (q & 1))) q += 1;
+  }
+  const double r = ldexp((double)q, E + drop);
+  return neg ? -r : r;
+}
+
+template <bool CPLX>
+__global__ __launch_bounds__(256) void k_s2_crt(CrtArgs ca, int M, int N, const int8_t* __restrict__ res,
+                                                const int32_t* __restrict__ sigma, const int32_t* __restrict__ tau,
+                                                double a_re, double a_im, double b_re, double b_im,
+                                                double* __restrict__ C, int64_t ldc) {
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t mn = (int64_t)M * N;
+  if (idx >= mn) return;
+  const int64_t row = idx / N, col = idx % N;
+  const int si = sigma[row], tj = tau[col];
+  const bool bad = si == OZK_EXP_NONFINITE || tj == OZK_EXP_NONFINITE;
+  const int E = -si - tj;
+  double h[2];
+#pragma unroll
+  for (int q = 0; q < (CPLX ? 2 : 1); ++q) {
+    if (bad) {
+      h[q] = __builtin_nan("");
+      continue;
+    }
+    uint32_t mag[NL];
+    bool neg;
+    crt_combine(ca, res + (CPLX ? q * mn : 0) + idx, CPLX ? 2 * mn : mn, mag, neg);
+    h[q] = round_limbs(mag, neg, E);
+  }
+  if (!CPLX) {
+    double* cp = C + row * ldc + col;
+    *cp = axpby(a_re, h[0], b_re, cp);
+  } else {
+    double* cp = C + 2 * (row * ldc + col);
+    double bre = 0.0, bim = 0.0;
+    if (!(b_re == 0.0 && b_im == 0.0)) {
+      const double cre = cp[0], cim = cp[1];
+      bre = __fma_rn(b_re, cre, -(b_im * cim));
+      bim = __fma_rn(b_re, cim, b_im * cre);
+    }
+    const double ore = __fma_rn(a_re, h[0], __fma_rn(-a_im, h[1], bre));
+    const double oim = __fma_rn(a_re, h[1], __fma_rn(a_im, h[0], bim));
+    cp[0] = ore;
+    cp[1] = oim;
+  }
+}
+
+// ------------------------------------------------------------ host side
+
+// Little host bignum in 32-bit limbs for the CRT constants.
+static void big_mul_small(uint32_t* x, int n, uint32_t f) {
+  uint64_t c = 0;
+  for (int i = 0; i < n; ++i) {
+    const uint64_t t = (uint64_t)x[i] * f + c;
+    x[i] = (uint32_t)t;
+    c = t >> 32;
+  }
+}
+static uint32_t big_div_small(uint32_t* x, int n, uint32_t d) {
+  uint64_t r = 0;
+  for (int i = n - 1; i >= 0; --i) {
+    const uint64_t cur = (r << 32) | x[i];
+    x[i] = (uint32_t)(cur / d);
+    r = cur % d;
+  }
+  return (uint32_t)r;
+}
+static int inv_mod(int a, int m) {
+  int t = 0, nt = 1, r = m, nr = a % m;
+  while (nr) {
+    const int q = r / nr, tt = t - q * nt, rr = r - q * nr;
+    t = nt;
+    nt = tt;
+    r = nr;
+    nr = rr;
+  }
+  return t < 0 ? t + m : t;
+}
+
+static void crt_args(int s, CrtArgs& ca, int& ta, int& tb) {
+  ca.s = s;
+  uint32_t P[NL] = {1, 0, 0, 0, 0, 0};
+  for (int l = 0; l < s; ++l) big_mul_small(P, NL, (uint32_t)kS2.m[l]);
+  for (int i = 0; i < NL; ++i) ca.P[i] = P[i];
+  double pf = 0.0;
+  for (int i = NL - 1; i >= 0; --i) pf = pf * 4294967296.0 + (double)P[i];
+  ca.Pf = pf;
+  for (int l = 0; l < OZK_MAX_S; ++l)
+    for (int i = 0; i < NL; ++i) ca.W[l][i] = 0;
+  for (int l = 0; l < s; ++l) {
+    uint32_t Q[NL];
+    for (int i = 0; i < NL; ++i) Q[i] = P[i];
+    big_div_small(Q, NL, (uint32_t)kS2.m[l]);  // P / m_l
+    uint32_t R[NL];
+    for (int i = 0; i < NL; ++i) R[i] = Q[i];
+    const int rem = (int)big_div_small(R, NL, (uint32_t)kS2.m[l]);  // (P/m_l) mod m_l
+    const int q = kS2.m[l] == 1 ? 0 : inv_mod(rem, kS2.m[l]);
+    big_mul_small(Q, NL, (uint32_t)q);
+    for (int i = 0; i < NL; ++i) ca.W[l][i] = Q[i];
+  }
+  // ceil(log2 P) = bit length of P - 1
+  uint32_t Pm1[NL];
+  for (int i = 0; i < NL; ++i) Pm1[i] = P[i];
+  for (int i = 0; i < NL; ++i) {
+    if (Pm1[i]--) break;
+  }
+  int bl = 0;
+  for (int i = NL - 1; i >= 0; --i)
+    if (Pm1[i]) {
+      bl = 32 * i + (32 - __builtin_clz(Pm1[i]));
+      break;
+    }
+  const int L = bl - 2;
+  ta = L / 2;
+  tb = L - ta;
+}
+
+void s2_targets(int s, int& ta, int& tb) {
+  CrtArgs ca;
+  crt_args(s, ca, ta, tb);
+}
+
+hipError_t s2_split_rows(int s, bool cplx, const double* X, int64_t ldx, int64_t rows, int64_t K, int32_t* sigma,
+                         int8_t* packed, hipStream_t st) {
+  int ta, tb;
+  s2_targets(s, ta, tb);
+  const int64_t rp = round_up(rows, OZK_ROW_ALIGN), kp = round_up(K, OZK_K_CHUNK);
+  if (rp == 0) return hipSuccess;
+  S2Args sa{s, ta};
+  if (cplx)
+    hipLaunchKernelGGL(k_s2_split_rows<true>, dim3((unsigned)(rp / 4)), dim3(256), 0, st, X, ldx, rows, K, kp, rp,
+                       sa, sigma, packed);
+  else
+    hipLaunchKernelGGL(k_s2_split_rows<false>, dim3((unsigned)(rp / 4)), dim3(256), 0, st, X, ldx, rows, K, kp,
+                       rp, sa, sigma, packed);
+  return hipGetLastError();
+}
+
+hipError_t s2_split_cols(int s, bool cplx, const double* X, int64_t ldx, int64_t K, int64_t cols, int32_t* tau,
+                         int8_t* packed, hipStream_t st) {
+  int ta, tb;
+  s2_targets(s, ta, tb);
+  const int64_t cp = round_up(cols, OZK_ROW_ALIGN), kp = round_up(K, OZK_K_CHUNK);
+  if (cols > 0) {
+    const unsigned gx = (unsigned)((cols + 31) / 32);
+    if (cplx)
+      hipLaunchKernelGGL(k_s2_col_scales<true>, dim3(gx), dim3(256), 0, st, X, ldx, K, cols, tb, tau);
+    else
+      hipLaunchKernelGGL(k_s2_col_scales<false>, dim3(gx), dim3(256), 0, st, X, ldx, K, cols, tb, tau);
+  }
+  if (cp > 0 && kp > 0) {
+    if (cplx)
+      hipLaunchKernelGGL(k_s2_split_cols<true>, dim3((unsigned)(cp / 256), (unsigned)(kp / OZK_K_CHUNK)),
+                         dim3(256), 0, st, X, ldx, K, cols, kp, cp, s, tau, packed);
+    else
+      hipLaunchKernelGGL(k_s2_split_cols<false>, dim3((unsigned)(cp / 256), (unsigned)(kp / OZK_K_CHUNK)),
+                         dim3(256), 0, st, X, ldx, K, cols, kp, cp, s, tau, packed);
+  }
+  return hipGetLastError();
+}
+
+template <bool CPLX>
+static hipError_t launch_gemm_mod(int s, int64_t M, int64_t N, int64_t K, const int8_t* Ap, const int8_t* Bp,
+                                  int8_t* out, hipStream_t st) {
+  constexpr int P = CPLX ? 3 : 1;
+  using T = GemmTile<P, 2, CPLX ? 1 : 2>;
+  auto kern = k_s2_gemm_mod<CPLX>;
+  static bool attr = false;
+  if (!attr) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, T::LDS_BYTES);
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  const int64_t kp = round_up(K, OZK_K_CHUNK);
+  const int64_t plane_a = round_up(M, OZK_ROW_ALIGN) * kp * P, plane_b = round_up(N, OZK_ROW_ALIGN) * kp * P;
+  const dim3 grid((unsigned)((N + T::BN - 1) / T::BN), (unsigned)((M + T::BM - 1) / T::BM), (unsigned)s);
+  hipLaunchKernelGGL(kern, grid, dim3(256), T::LDS_BYTES, st, Ap, Bp, plane_a, plane_b, kp / OZK_K_CHUNK, (int)M,
+                     (int)N, out);
+  return hipGetLastError();
+}
+
+hipError_t s2_gemm_mod(int s, bool cplx, int64_t M, int64_t N, int64_t K, const int8_t* Ap, const int8_t* Bp,
+                       int8_t* out, hipStream_t st) {
+  if (M == 0 || N == 0) return hipSuccess;
+  return cplx ? launch_gemm_mod<true>(s, M, N, K, Ap, Bp, out, st)
+              : launch_gemm_mod<false>(s, M, N, K, Ap, Bp, out, st);
+}
+
+hipError_t s2_crt(int s, bool cplx, int64_t M, int64_t N, const int8_t* res, const int32_t* sigma,
+                  const int32_t* tau, const double* alpha, const double* beta, double* C, int64_t ldc,
+                  hipStream_t st) {
+  if (M == 0 || N == 0) return hipSuccess;
+  CrtArgs ca;
+  int ta, tb;
+  crt_args(s, ca, ta, tb);
+  const int64_t n = M * N;
+  const double ai = cplx ? alpha[1] : 0.0, bi = cplx ? beta[1] : 0.0;
+  if (cplx)
+    hipLaunchKernelGGL(k_s2_crt<true>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, ca, (int)M, (int)N,
+                       res, sigma, tau, alpha[0], ai, beta[0], bi, C, ldc);
+  else
+    hipLaunchKernelGGL(k_s2_crt<false>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, ca, (int)M, (int)N,
+                       res, sigma, tau, alpha[0], ai, beta[0], bi, C, ldc);
+  return hipGetLastError();
+}
+
+}  // namespace ozk

@@ -1,0 +1,240 @@
+"""Scheme I on the GPU against the CPU oracle, through the C ABI.
+
+Bit-exact: exponents, packed slices (Eq. 1 and the interleaved layout of
+Eq. 11), the raw INT32 diagonals of the fused kernel (Eq. 2) and the FP64
+outputs (exact shift-reduce + one rounding, Eq. 3).  Sizes span several
+workgroup tiles and ragged tails; large sizes are checked on sampled outputs
+that the oracle computes one by one."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2606_25453_amd as ozk
+import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = ozk.Context(0)
+    yield c
+    c.close()
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda:0")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+SHAPES = [(1, 1, 1), (63, 65, 127), (128, 128, 128), (129, 257, 95), (300, 200, 513), (64, 300, 33)]
+
+
+@pytest.mark.parametrize("p", [1, 3, 4, 5, 8])
+@pytest.mark.parametrize("shape", [(37, 70), (256, 128), (300, 513)])
+def test_split_rows_bit_exact(ctx, p, shape):
+    rows, K = shape
+    X = synth.phi_matrix(rows, K, 2.0, 1000 + p)
+    X[min(3, rows - 1)] = 0.0
+    e, packed = ozk.ozk_s1_split_rows(ctx, p, dev(X))
+    e = host(e)[:rows]
+    assert np.array_equal(e, oracle.s1_row_exponents(X))
+    D = host(ozk.unpack_s1(packed, rows, K, p))
+    assert np.array_equal(D, oracle.s1_digits_a(X, e, p))
+    # padding rows and padded k are zero
+    full = host(ozk.unpack_s1(packed, ((rows + 255) // 256) * 256, ((K + 31) // 32) * 32, p))
+    assert not full[:, rows:, :].any() and not full[:, :, K:].any()
+
+
+@pytest.mark.parametrize("p", [1, 2, 6, 8])
+@pytest.mark.parametrize("shape", [(70, 37), (128, 256), (513, 300)])
+def test_split_cols_bit_exact(ctx, p, shape):
+    K, cols = shape
+    X = synth.phi_matrix(K, cols, 2.0, 2000 + p)
+    X[:, min(5, cols - 1)] = 0.0
+    f, packed = ozk.ozk_s1_split_cols(ctx, p, dev(X))
+    f = host(f)[:cols]
+    assert np.array_equal(f, oracle.s1_col_exponents(X))
+    D = host(ozk.unpack_s1(packed, cols, K, p))
+    assert np.array_equal(D, oracle.s1_digits_b(X, f, p).transpose(0, 2, 1))
+
+
+def test_interleaved_layout_matches_eq11(ctx):
+    """Eq. 11 with t_K = 32: row r of the packed operand is
+    [A'_0 | A'_1 | A'_2 | A'_0 | ...] in 32-wide blocks (the paper's p = 3
+    example)."""
+    p, rows, K = 3, 5, 96
+    X = synth.phi_matrix(rows, K, 1.0, 3)
+    e, packed = ozk.ozk_s1_split_rows(ctx, p, dev(X))
+    raw = host(packed)[: 256 * K * p].reshape(256, K * p)
+    D = oracle.s1_digits_a(X, oracle.s1_row_exponents(X), p)
+    for r in range(rows):
+        for c in range(K // 32):
+            for i in range(p):
+                assert np.array_equal(raw[r, (c * p + i) * 32:(c * p + i + 1) * 32], D[i, r, c * 32:(c + 1) * 32])
+
+
+@pytest.mark.parametrize("p", [1, 2, 4, 5, 7, 8])
+@pytest.mark.parametrize("shape", [(63, 65, 127), (129, 257, 95), (256, 64, 320)])
+def test_int32_diagonals_bit_exact(ctx, p, shape):
+    M, N, K = shape
+    A = synth.phi_matrix(M, K, 1.0, 3000 + p)
+    B = synth.phi_matrix(K, N, 1.0, 3100 + p)
+    e, pa = ozk.ozk_s1_split_rows(ctx, p, dev(A))
+    f, pb = ozk.ozk_s1_split_cols(ctx, p, dev(B))
+    Cd = host(ozk.ozk_s1_diagonals(ctx, p, M, N, K, pa, pb))
+    D = oracle.s1_digits_a(A, oracle.s1_row_exponents(A), p).astype(np.int64)
+    E = oracle.s1_digits_b(B, oracle.s1_col_exponents(B), p).astype(np.int64)
+    for d in range(p):
+        ref = sum(D[t] @ E[d - t] for t in range(d + 1))
+        assert np.array_equal(Cd[d].astype(np.int64), ref), d
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4, 5, 6, 7, 8])
+@pytest.mark.parametrize("shape", SHAPES)
+def test_dgemm_bit_exact(ctx, p, shape):
+    M, N, K = shape
+    A = synth.phi_matrix(M, K, 1.0, 4000 + 10 * p + M)
+    B = synth.phi_matrix(K, N, 1.0, 4100 + 10 * p + N)
+    C = host(ozk.ozk_dgemm(ctx, ozk.OZK_SCHEME1, p, dev(A), dev(B)))
+    assert np.array_equal(C, oracle.s1_dgemm(A, B, p))
+
+
+def test_config1_uniform_128(ctx):
+    """128^3, entries uniform in (-1, 1), p = 4: bit-exact, and compared with
+    the naive and double-double references."""
+    M = N = K = 128
+    A = synth.uniform_matrix(M, K, synth.seed_for(1, M, 0.0, synth.ROLE_A))
+    B = synth.uniform_matrix(K, N, synth.seed_for(1, M, 0.0, synth.ROLE_B))
+    C = host(ozk.ozk_dgemm(ctx, ozk.OZK_SCHEME1, 4, dev(A), dev(B)))
+    assert np.array_equal(C, oracle.s1_dgemm(A, B, 4))
+    hi, lo = oracle.gemm_dd(A, B)
+    err = oracle.metrics.e_cw(C, hi, lo, A, B)
+    assert 1e-12 < err < 1e-7  # p = 4 keeps 30 bits per operand
+
+
+def test_alpha_beta_and_strides(ctx):
+    M, N, K, p = 70, 90, 110, 6
+    A = synth.phi_matrix(M, K, 1.0, 1)
+    B = synth.phi_matrix(K, N, 1.0, 2)
+    C0 = synth.phi_matrix(M, N, 1.0, 3)
+    # strided views: leading dimensions larger than the row length
+    Ab = dev(np.zeros((M, K + 7)))
+    Ab[:, :K] = dev(A)
+    Bb = dev(np.zeros((K, N + 3)))
+    Bb[:, :N] = dev(B)
+    Cb = dev(np.full((M, N + 5), np.nan))
+    ozk.ozk_dgemm(ctx, ozk.OZK_SCHEME1, p, Ab[:, :K], Bb[:, :N], C=Cb[:, :N], alpha=-2.5, beta=0.0)
+    out = host(Cb)
+    assert np.array_equal(out[:, :N], oracle.s1_dgemm(A, B, p, alpha=-2.5))
+    assert np.isnan(out[:, N:]).all()  # untouched
+    Cb[:, :N] = dev(C0)
+    ozk.ozk_dgemm(ctx, ozk.OZK_SCHEME1, p, Ab[:, :K], Bb[:, :N], C=Cb[:, :N], alpha=0.75, beta=-1.25)
+    assert np.array_equal(host(Cb)[:, :N], oracle.s1_dgemm(A, B, p, alpha=0.75, beta=-1.25, C=C0))
+
+
+def test_edge_values(ctx):
+    M, N, K, p = 40, 33, 50, 8
+    A = synth.phi_matrix(M, K, 1.0, 11)
+    B = synth.phi_matrix(K, N, 1.0, 12)
+    A[0] = 0.0
+    B[:, 1] = 0.0
+    A[2] *= 1e-300
+    A[3] *= 1e300
+    A[4, :5] = [5e-324, -2.0 ** -1074, 1e-310, 0.0, -3e-320]
+    A[5, 7] = np.nan
+    B[9, 4] = -np.inf
+    A[6] = A[7] = 1e-200  # products underflow into subnormals
+    B[:, 8] *= 1e-150
+    C = host(ozk.ozk_dgemm(ctx, ozk.OZK_SCHEME1, p, dev(A), dev(B)))
+    ref = oracle.s1_dgemm(A, B, p)
+    assert np.array_equal(np.isnan(C), np.isnan(ref))
+    ok = ~np.isnan(ref)
+    assert np.array_equal(C[ok], ref[ok])
+    assert np.isnan(C[5]).all() and np.isnan(C[:, 4]).all()
+
+
+def test_empty_dimensions(ctx):
+    for (M, N, K) in [(0, 5, 7), (5, 0, 7), (5, 7, 0), (0, 0, 0)]:
+        A = dev(np.ones((M, K)))
+        B = dev(np.ones((K, N)))
+        C = dev(np.full((M, N), 7.0))
+        ozk.ozk_dgemm(ctx, ozk.OZK_SCHEME1, 3, A, B, C=C, alpha=1.0, beta=0.0)
+        assert np.array_equal(host(C), np.zeros((M, N)))
+
+
+def test_k_runs_fold_exactly():
+    """Shorter overflow-free K runs (forced through OZK_K_SPLIT) fold into the
+    same result as one run."""
+    os.environ["OZK_K_SPLIT"] = "64"
+    try:
+        c2 = ozk.Context(0)
+    finally:
+        del os.environ["OZK_K_SPLIT"]
+    M, N, K, p = 150, 70, 333, 8
+    A = synth.phi_matrix(M, K, 1.0, 21)
+    B = synth.phi_matrix(K, N, 1.0, 22)
+    C = host(ozk.ozk_dgemm(c2, ozk.OZK_SCHEME1, p, dev(A), dev(B)))
+    assert np.array_equal(C, oracle.s1_dgemm(A, B, p))
+    c2.close()
+
+
+def test_invalid_arguments(ctx):
+    A = dev(np.ones((4, 4)))
+    with pytest.raises(ozk.OzkError) as ei:
+        ozk.ozk_dgemm(ctx, ozk.OZK_SCHEME1, 9, A, A)
+    assert ei.value.status == ozk.OZK_ERR_UNSUPPORTED
+    with pytest.raises(ozk.OzkError) as ei:
+        ozk.ozk_dgemm(ctx, ozk.OZK_SCHEME1, 0, A, A)
+    assert ei.value.status == ozk.OZK_ERR_UNSUPPORTED
+    small = torch.empty(16, dtype=torch.uint8, device="cuda:0")
+    with pytest.raises(ozk.OzkError) as ei:
+        ozk.ozk_dgemm(ctx, ozk.OZK_SCHEME1, 4, A, A, ws=small)
+    assert ei.value.status == ozk.OZK_ERR_WORKSPACE
+    lib = ozk.library()
+    st = lib.ozk_dgemm(ctx.handle, 1, 4, 4, 4, 4, 1.0, A.data_ptr(), 3, A.data_ptr(), 4, 0.0, A.data_ptr(), 4,
+                       None, 0, None)
+    assert st == ozk.OZK_ERR_INVALID_ARG and lib.ozk_last_arg(ctx.handle) == 9  # lda < K
+
+
+def test_deterministic(ctx):
+    A = synth.phi_matrix(200, 300, 2.0, 31)
+    B = synth.phi_matrix(300, 150, 2.0, 32)
+    a, b = dev(A), dev(B)
+    r1 = host(ozk.ozk_dgemm(ctx, ozk.OZK_SCHEME1, 7, a, b))
+    r2 = host(ozk.ozk_dgemm(ctx, ozk.OZK_SCHEME1, 7, a, b))
+    assert np.array_equal(r1, r2)
+
+
+@pytest.mark.parametrize("n,p", [(2048, 8), (8192, 8), (8192, 7)])
+def test_large_sampled_bit_exact(ctx, n, p):
+    """Full-size problems: sampled outputs against the oracle computed entry
+    by entry, plus accuracy against double-double on a sampled block."""
+    A = synth.phi_matrix(n, n, 1.0, synth.seed_for(2, n, 1.0, synth.ROLE_A))
+    B = synth.phi_matrix(n, n, 1.0, synth.seed_for(2, n, 1.0, synth.ROLE_B))
+    a, b = dev(A), dev(B)
+    C = host(ozk.ozk_dgemm(ctx, ozk.OZK_SCHEME1, p, a, b))
+    rng = np.random.default_rng(n + p)
+    rows = np.concatenate([rng.integers(0, n, 200), [0, n - 1, n - 1, 0]])
+    cols = np.concatenate([rng.integers(0, n, 200), [0, n - 1, 0, n - 1]])
+    ref = oracle.s1_entries(A, B, p, rows, cols)
+    assert np.array_equal(C[rows, cols], ref)
+    ri = rng.choice(n, 8, replace=False)
+    ci = rng.choice(n, 8, replace=False)
+    hi, lo = oracle.gemm_dd(A[ri], B[:, ci])
+    sub = C[np.ix_(ri, ci)]
+    err = oracle.metrics.e_cw(sub, hi, lo, A[ri], B[:, ci])
+    nat = host(torch.matmul(a, b))[np.ix_(ri, ci)]
+    err_nat = oracle.metrics.e_cw(nat, hi, lo, A[ri], B[:, ci])
+    assert err < 1e-13
+    if p == 8:
+        assert err <= 2 * err_nat, (err, err_nat)

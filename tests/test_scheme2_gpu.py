@@ -1,0 +1,222 @@
+"""Scheme II (real) and 3M ZGEMM on the GPU against the CPU oracle, through
+the C ABI.  Bit-exact: scale exponents, residue planes (Eq. 5), the per-modulus
+INT8 output residues (Eqs. 6-7, Eq. 16) and the FP64 / complex128 outputs
+after the CRT (Eq. 8) and one rounding."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2606_25453_amd as ozk
+import synth
+from oracle import scheme2 as s2
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = ozk.Context(0)
+    yield c
+    c.close()
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda:0")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def rp(n):
+    return (n + 255) // 256 * 256
+
+
+def kp(k):
+    return (k + 31) // 32 * 32
+
+
+@pytest.mark.parametrize("s", [1, 8, 13, 16, 20])
+@pytest.mark.parametrize("shape", [(37, 70), (300, 129)])
+def test_split_rows_real(ctx, s, shape):
+    rows, K = shape
+    X = synth.phi_matrix(rows, K, 2.0, 500 + s)
+    X[min(2, rows - 1)] = 0
+    X[min(4, rows - 1)] *= 1e-290
+    sig, packed = ozk.ozk_s2_split_rows(ctx, s, dev(X))
+    ta, _ = s2.targets(s)
+    ref_sig, _ = s2.row_scales(X, ta)
+    assert np.array_equal(host(sig)[:rows], ref_sig)
+    R = host(packed).reshape(s, rp(rows), kp(K))
+    Xi = s2.integerise(X, ref_sig, 1)
+    for l, m in enumerate(s2.moduli(s)):
+        assert np.array_equal(R[l, :rows, :K], s2.residues(Xi, m)), l
+    assert not R[:, rows:, :].any() and not R[:, :, K:].any()
+
+
+@pytest.mark.parametrize("s", [2, 14, 20])
+@pytest.mark.parametrize("shape", [(70, 37), (129, 300)])
+def test_split_cols_real(ctx, s, shape):
+    K, cols = shape
+    X = synth.phi_matrix(K, cols, 2.0, 600 + s)
+    X[:, min(3, cols - 1)] = 0
+    tau, packed = ozk.ozk_s2_split_cols(ctx, s, dev(X))
+    _, tb = s2.targets(s)
+    ref_tau, _ = s2.col_scales(X, tb)
+    assert np.array_equal(host(tau)[:cols], ref_tau)
+    R = host(packed).reshape(s, rp(cols), kp(K))
+    Xi = s2.integerise(X, ref_tau, 0)
+    for l, m in enumerate(s2.moduli(s)):
+        assert np.array_equal(R[l, :cols, :K], s2.residues(Xi, m).T), l
+
+
+@pytest.mark.parametrize("s", [5, 16])
+def test_split_complex(ctx, s):
+    rows, K = 45, 100
+    X = synth.complex_phi_matrix(rows, K, 1.0, 700 + s, 710 + s)
+    X[3] = X[3].real  # imaginary part zero in one row
+    sig, packed = ozk.ozk_s2_split_rows(ctx, s, dev(X), complex_planes=1)
+    Y = synth.complex_phi_matrix(K, rows, 1.0, 720 + s, 730 + s)
+    tau, packedb = ozk.ozk_s2_split_cols(ctx, s, dev(Y), complex_planes=1)
+    st = s2.z3m_prepare(X, Y, s)
+    assert np.array_equal(host(sig)[:rows], st["sig"])
+    assert np.array_equal(host(tau)[:rows], st["tau"])
+    R = host(packed).reshape(s, rp(rows), kp(K) // 32, 3, 32).transpose(0, 3, 1, 2, 4).reshape(s, 3, rp(rows), kp(K))
+    S = host(packedb).reshape(s, rp(rows), kp(K) // 32, 3, 32).transpose(0, 3, 1, 2, 4).reshape(s, 3, rp(rows), kp(K))
+    for l in range(s):
+        (r_re, r_im, r_sum), (s_re, s_im, s_sum) = st["planes"][l]
+        assert np.array_equal(R[l, 0, :rows, :K], r_re)
+        assert np.array_equal(R[l, 1, :rows, :K], r_im)
+        assert np.array_equal(R[l, 2, :rows, :K], r_sum)
+        assert np.array_equal(S[l, 0, :rows, :K], s_re.T)
+        assert np.array_equal(S[l, 2, :rows, :K], s_sum.T)
+
+
+@pytest.mark.parametrize("s", [3, 16])
+@pytest.mark.parametrize("shape", [(63, 65, 127), (129, 257, 95)])
+def test_gemm_mod_residues_bit_exact(ctx, s, shape):
+    M, N, K = shape
+    A = synth.phi_matrix(M, K, 1.0, 800 + s)
+    B = synth.phi_matrix(K, N, 1.0, 810 + s)
+    sig, pa = ozk.ozk_s2_split_rows(ctx, s, dev(A))
+    tau, pb = ozk.ozk_s2_split_cols(ctx, s, dev(B))
+    Cres = host(ozk.ozk_s2_gemm_mod(ctx, s, M, N, K, pa, pb))
+    st = s2.s2_prepare(A, B, s)
+    for l, m in enumerate(st["ms"]):
+        assert np.array_equal(Cres[l], s2.modular_product(st["RA"][l], st["RB"][l], m)), l
+
+
+def test_gemm_mod_3m_residues_bit_exact(ctx):
+    s, M, N, K = 9, 70, 90, 110
+    A = synth.complex_phi_matrix(M, K, 1.0, 900, 901)
+    B = synth.complex_phi_matrix(K, N, 1.0, 902, 903)
+    _, pa = ozk.ozk_s2_split_rows(ctx, s, dev(A), complex_planes=1)
+    _, pb = ozk.ozk_s2_split_cols(ctx, s, dev(B), complex_planes=1)
+    Cres = host(ozk.ozk_s2_gemm_mod(ctx, s, M, N, K, pa, pb, complex_planes=1)).reshape(s, 2, M, N)
+    st = s2.z3m_prepare(A, B, s)
+    for l, m in enumerate(st["ms"]):
+        re, im = s2.z3m_modular(st["planes"][l][0], st["planes"][l][1], m)
+        assert np.array_equal(Cres[l, 0], re) and np.array_equal(Cres[l, 1], im), l
+
+
+@pytest.mark.parametrize("s", [1, 6, 8, 12, 14, 16, 18, 20])
+@pytest.mark.parametrize("shape", [(1, 1, 1), (63, 65, 127), (129, 130, 95), (200, 64, 300)])
+def test_dgemm_scheme2_bit_exact(ctx, s, shape):
+    M, N, K = shape
+    A = synth.phi_matrix(M, K, 1.0, 1000 + s + M)
+    B = synth.phi_matrix(K, N, 1.0, 1100 + s + N)
+    C = host(ozk.ozk_dgemm(ctx, ozk.OZK_SCHEME2, s, dev(A), dev(B)))
+    assert np.array_equal(C, s2.s2_dgemm(A, B, s))
+
+
+def test_scheme2_alpha_beta_edges(ctx):
+    s, M, N, K = 14, 40, 30, 50
+    A = synth.phi_matrix(M, K, 1.0, 1)
+    B = synth.phi_matrix(K, N, 1.0, 2)
+    C0 = synth.phi_matrix(M, N, 1.0, 3)
+    A[0] = 0
+    A[1] *= 1e-300
+    A[2] *= 1e300
+    A[3, 4] = np.inf
+    B[:, 5] = 0
+    B[7, 6] = np.nan
+    got = host(ozk.ozk_dgemm(ctx, ozk.OZK_SCHEME2, s, dev(A), dev(B), C=dev(C0), alpha=-1.5, beta=0.5))
+    ref = s2.s2_dgemm(A, B, s, alpha=-1.5, beta=0.5, C=C0)
+    assert np.array_equal(np.isnan(got), np.isnan(ref))
+    ok = ~np.isnan(ref)
+    assert np.array_equal(got[ok], ref[ok])
+    assert np.isnan(got[3]).all() and np.isnan(got[:, 6]).all()
+
+
+@pytest.mark.parametrize("s", [4, 11, 16])
+@pytest.mark.parametrize("shape", [(1, 1, 1), (63, 65, 70), (130, 40, 96)])
+def test_zgemm_3m_bit_exact(ctx, s, shape):
+    M, N, K = shape
+    A = synth.complex_phi_matrix(M, K, 1.0, 1200 + s, 1201 + s)
+    B = synth.complex_phi_matrix(K, N, 1.0, 1202 + s, 1203 + s)
+    C = host(ozk.ozk_zgemm_3m(ctx, s, dev(A), dev(B)))
+    assert np.array_equal(C, s2.z3m_gemm(A, B, s))
+
+
+def test_zgemm_3m_alpha_beta_and_cancellation(ctx):
+    s, M, N, K = 16, 30, 20, 40
+    rng = np.random.default_rng(5)
+    X = rng.standard_normal((M, K))
+    A = X + 1j * X * (1 + 2.0 ** -40)  # re ~ im
+    B = synth.complex_phi_matrix(K, N, 1.0, 1300, 1301)
+    C0 = synth.complex_phi_matrix(M, N, 1.0, 1302, 1303)
+    al, be = 0.5 - 2j, -1 + 0.25j
+    got = host(ozk.ozk_zgemm_3m(ctx, s, dev(A), dev(B), C=dev(C0), alpha=al, beta=be))
+    assert np.array_equal(got, s2.z3m_gemm(A, B, s, alpha=al, beta=be, C=C0))
+    got0 = host(ozk.ozk_zgemm_3m(ctx, s, dev(A), dev(B), C=dev(np.full((M, N), np.nan + 0j))))
+    assert np.array_equal(got0, s2.z3m_gemm(A, B, s))
+
+
+def test_empty_and_invalid(ctx):
+    for (M, N, K) in [(0, 4, 3), (4, 0, 3), (4, 3, 0)]:
+        C = dev(np.full((M, N), 5.0))
+        ozk.ozk_dgemm(ctx, ozk.OZK_SCHEME2, 10, dev(np.ones((M, K))), dev(np.ones((K, N))), C=C)
+        assert np.array_equal(host(C), np.zeros((M, N)))
+    A = dev(np.ones((4, 4)))
+    for bad in (0, 21):
+        with pytest.raises(ozk.OzkError) as ei:
+            ozk.ozk_dgemm(ctx, ozk.OZK_SCHEME2, bad, A, A)
+        assert ei.value.status == ozk.OZK_ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("n,s", [(4096, 14), (4096, 16)])
+def test_large_scheme2_sampled(ctx, n, s):
+    A = synth.phi_matrix(n, n, 1.0, synth.seed_for(3, n, 1.0, synth.ROLE_A))
+    B = synth.phi_matrix(n, n, 1.0, synth.seed_for(3, n, 1.0, synth.ROLE_B))
+    a, b = dev(A), dev(B)
+    C = host(ozk.ozk_dgemm(ctx, ozk.OZK_SCHEME2, s, a, b))
+    rng = np.random.default_rng(n + s)
+    rows = np.concatenate([rng.integers(0, n, 40), [0, n - 1]])
+    cols = np.concatenate([rng.integers(0, n, 40), [n - 1, 0]])
+    assert np.array_equal(C[rows, cols], s2.s2_entries(A, B, s, rows, cols))
+    ri = rng.choice(n, 8, replace=False)
+    ci = rng.choice(n, 8, replace=False)
+    hi, lo = oracle.gemm_dd(A[ri], B[:, ci])
+    err = oracle.metrics.e_cw(C[np.ix_(ri, ci)], hi, lo, A[ri], B[:, ci])
+    nat = host(torch.matmul(a, b))[np.ix_(ri, ci)]
+    err_nat = oracle.metrics.e_cw(nat, hi, lo, A[ri], B[:, ci])
+    assert err < 1e-13
+    if s == 16:
+        assert err <= 2 * err_nat, (err, err_nat)
+
+
+def test_large_zgemm_3m_sampled(ctx):
+    n, s = 2048, 16
+    A = synth.complex_phi_matrix(n, n, 1.0, synth.seed_for(4, n, 1.0, synth.ROLE_A),
+                                 synth.seed_for(4, n, 1.0, synth.ROLE_A_IM))
+    B = synth.complex_phi_matrix(n, n, 1.0, synth.seed_for(4, n, 1.0, synth.ROLE_B),
+                                 synth.seed_for(4, n, 1.0, synth.ROLE_B_IM))
+    C = host(ozk.ozk_zgemm_3m(ctx, s, dev(A), dev(B)))
+    rng = np.random.default_rng(11)
+    rows = rng.integers(0, n, 16)
+    cols = rng.integers(0, n, 16)
+    assert np.array_equal(C[rows, cols], s2.z3m_entries(A, B, s, rows, cols))
