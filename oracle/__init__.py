@@ -252,11 +252,11 @@ def s1_scale_exponent(e: int, f: int, p: int) -> int:
 
 
 def k_split_s1(p: int) -> int:
-    """Longest K run (a multiple of 64) over which no INT32 diagonal can
+    """Longest K run (a multiple of 32) over which no INT32 diagonal can
     overflow: |d_0| <= 64 and |d_t| <= 128 bound diagonal d by
     max(2^12, d 2^14) per k."""
     per_k = max(2 ** 12, (p - 1) * 2 ** 14)
-    return ((2 ** 31 - 1) // per_k) // 64 * 64
+    return ((2 ** 31 - 1) // per_k) // 32 * 32
 
 
 from . import scheme2, metrics  # noqa: E402,F401

@@ -225,7 +225,11 @@ def _round_all(Z: np.ndarray, sig: np.ndarray, tau: np.ndarray) -> np.ndarray:
 
 
 def _fma(a, b, c):
-    """Correctly rounded fused multiply-add through exact rationals."""
+    """Correctly rounded fused multiply-add through exact rationals; a NaN or
+    infinite operand propagates as in IEEE 754 (the product and sum are then
+    not finite and no rounding question arises)."""
+    if not (math.isfinite(a) and math.isfinite(b) and math.isfinite(c)):
+        return a * b + c
     return float(Fraction(a) * Fraction(b) + Fraction(c))
 
 
@@ -371,3 +375,66 @@ def z3m_exact_definition(A, B, s: int) -> np.ndarray:
     Zre = ar @ br - ai @ bi
     Zim = ar @ bi + ai @ br
     return _round_all(Zre, st["sig"], st["tau"]) + 1j * _round_all(Zim, st["sig"], st["tau"])
+
+
+# ------------------------------------------------------ sampled outputs only
+
+def s2_entries(A, B, s: int, rows, cols, alpha=1.0, beta=0.0, cin=None) -> np.ndarray:
+    """Scheme II outputs (rows[n], cols[n]) computed one by one with the same
+    steps: full-row/column scales, integerise the needed row and column,
+    residues, one modular dot product per modulus, CRT, one rounding."""
+    A = np.asarray(A, np.float64)
+    B = np.asarray(B, np.float64)
+    ta, tb = targets(s)
+    sig, bad_r = row_scales(A, ta)
+    tau, bad_c = col_scales(B, tb)
+    ms = moduli(s)
+    out = np.empty(len(rows), np.float64)
+    for n, (i, j) in enumerate(zip(rows, cols)):
+        i, j = int(i), int(j)
+        if bad_r[i] or bad_c[j]:
+            h = math.nan
+        else:
+            a = integerise(A[i:i + 1], sig[i:i + 1], 1)
+            b = integerise(B[:, j:j + 1], tau[j:j + 1], 0)
+            Cl = [modular_product(residues(a, m), residues(b, m), m) for m in ms]
+            z = int(crt(Cl, s)[0, 0])
+            h = scaled_round(z, -int(sig[i]) - int(tau[j]))
+        if beta == 0.0:
+            out[n] = alpha * h
+        else:
+            out[n] = _fma(alpha, h, beta * float(cin[n]))
+    return out
+
+
+def z3m_entries(A, B, s: int, rows, cols) -> np.ndarray:
+    """3M ZGEMM outputs (rows[n], cols[n]) one by one (alpha = 1, beta = 0)."""
+    A = np.asarray(A, np.complex128)
+    B = np.asarray(B, np.complex128)
+    ta, tb = targets(s)
+    sig, bad_r = row_scales_complex(A, ta)
+    tau, bad_c = col_scales_complex(B, tb)
+    ms = moduli(s)
+    out = np.empty(len(rows), np.complex128)
+    for n, (i, j) in enumerate(zip(rows, cols)):
+        i, j = int(i), int(j)
+        if bad_r[i] or bad_c[j]:
+            out[n] = complex(math.nan, math.nan)
+            continue
+        ar = integerise(A[i:i + 1].real, sig[i:i + 1], 1)
+        ai = integerise(A[i:i + 1].imag, sig[i:i + 1], 1)
+        br = integerise(B[:, j:j + 1].real, tau[j:j + 1], 0)
+        bi = integerise(B[:, j:j + 1].imag, tau[j:j + 1], 0)
+        cre, cim = [], []
+        for m in ms:
+            r_re, r_im = residues(ar, m), residues(ai, m)
+            s_re, s_im = residues(br, m), residues(bi, m)
+            r_sum = smod(r_re.astype(np.int64) + r_im, m).astype(np.int8)
+            s_sum = smod(s_re.astype(np.int64) + s_im, m).astype(np.int8)
+            x, y = z3m_modular((r_re, r_im, r_sum), (s_re, s_im, s_sum), m)
+            cre.append(x)
+            cim.append(y)
+        E = -int(sig[i]) - int(tau[j])
+        h = complex(scaled_round(int(crt(cre, s)[0, 0]), E), scaled_round(int(crt(cim, s)[0, 0]), E))
+        out[n] = zaxpby(1.0, np.array([h]), 0.0, None)[0]
+    return out

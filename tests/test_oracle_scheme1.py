@@ -137,9 +137,9 @@ def test_k_split_bound():
     stays below 2^31."""
     for p in range(1, 9):
         k = oracle.k_split_s1(p)
-        assert k % 64 == 0
+        assert k % 32 == 0
         per_k = max(2 ** 12, (p - 1) * 2 ** 14)
-        assert per_k * k < 2 ** 31 <= per_k * (k + 64) or per_k * (k + 64) >= 2 ** 31
+        assert per_k * k < 2 ** 31 <= per_k * (k + 32)
     # every diagonal at the worst-case digits reaches the stated per-k bound
     p = 8
     D = np.full((p, 1, 1), -128, np.int8)

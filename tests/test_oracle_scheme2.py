@@ -226,3 +226,21 @@ def test_zaxpby_sequence():
     ref = (2 - 1j) * H + (0.5 + 0.5j) * C
     assert np.allclose(out, ref, rtol=1e-15, atol=0)
     assert np.array_equal(s2.zaxpby(1.0, H, 0.0, np.full((1, 2), np.nan)), H)
+
+
+def test_entries_match_full_results():
+    A = synth.phi_matrix(12, 40, 1.0, 90)
+    B = synth.phi_matrix(40, 9, 1.0, 91)
+    A[3, 2] = np.nan
+    rows = np.array([0, 3, 11, 5, 7])
+    cols = np.array([0, 4, 8, 2, 7])
+    full = s2.s2_dgemm(A, B, 13)
+    got = s2.s2_entries(A, B, 13, rows, cols)
+    assert np.array_equal(np.isnan(got), np.isnan(full[rows, cols]))
+    ok = ~np.isnan(got)
+    assert np.array_equal(got[ok], full[rows, cols][ok])
+    Z = synth.complex_phi_matrix(10, 30, 1.0, 92, 93)
+    W = synth.complex_phi_matrix(30, 8, 1.0, 94, 95)
+    fz = s2.z3m_gemm(Z, W, 11)
+    assert np.array_equal(s2.z3m_entries(Z, W, 11, rows[[0, 2, 3, 4]] % 10, cols[[0, 2, 3, 4]] % 8),
+                          fz[rows[[0, 2, 3, 4]] % 10, cols[[0, 2, 3, 4]] % 8])
