@@ -34,24 +34,27 @@
  * the rows past `rows` are zero.  K is padded with zeros to
  * Kp = roundup(K, 32) (OZK_K_CHUNK).
  *
- * Scheme I packed operand (Sec. III-A, Eq. 11, with t_K = 32):
- *   P[r][c][t][kk] = slice t of row r at k = 32c + kk,   int8,
- *   r < Rp, c < Kp/32, t < p, kk < 32.  Each row holds, chunk after chunk of
- *   32 k, the p slices of that chunk side by side: [A'_0|A'_1|..|A'_(p-1)|
- *   A'_0|..].  The "rows" of B's packed operand are the COLUMNS of B (B is
- *   transposed so that both operands are contiguous along k).
+ * Scheme I packed operand (Sec. III-A, Eq. 11, with t_K = 32): the
+ *   interleaved matrix A^ (rows x p K, 32-wide column blocks cycling through
+ *   the slices: block j = c p + t holds slice t of k = 32c .. 32c+31) stored
+ *   block-column by block-column, each block a contiguous Rp x 32 slab:
+ *   P[c][t][r][kk] = slice t of row r at k = 32c + kk,   int8,
+ *   byte offset ((c p + t) Rp + r) 32 + kk,  c < Kp/32, t < p, r < Rp.
+ *   The "rows" of B's packed operand are the COLUMNS of B (B is transposed
+ *   so that both operands are contiguous along k).
  *   Slice format: with e the row (column) exponent -- the smallest e with
  *   |x| < 2^e over the row's nonzero entries -- and X = floor(x 2^(8p-2-e)
  *   + 1/2), the slices are the balanced base-256 digits of X: slice t in
  *   [-128, 127] (slice 0 in [-64, 64]) with x ~ 2^e sum_t slice_t 2^(-6-8t).
  *
- * Scheme II packed operand (Sec. II-C.2, Eq. 5):
- *   R[l][r][k] = smod(trunc(x 2^sigma_r), m_l), int8, l < s, r < Rp, k < Kp,
+ * Scheme II packed operand (Sec. II-C.2, Eq. 5): per modulus l one packed
+ *   operand in the Scheme I layout with a single slice,
+ *   R[l][c][r][kk] = smod(trunc(x 2^sigma_r), m_l) at k = 32c + kk, int8,
  *   smod(x, m) the representative in [-floor(m/2), ceil(m/2)-1]; moduli
  *   m_l = 256, 255, 253, 251, 247, 241, ... (greedy pairwise coprime).
- *   3M complex: each modulus plane l is a packed operand in the Scheme I
- *   layout with three slices, R[l][r][c][q][kk] = residue at k = 32c + kk of
- *   q = 0 the real part, 1 the imaginary part, 2 smod(real + imaginary).
+ *   3M complex: per modulus a packed operand with three slices,
+ *   R[l][c][q][r][kk], q = 0 the real part, 1 the imaginary part,
+ *   2 smod(real + imaginary).
  *   The row (column) scale sigma is shared by both parts; rows past `rows`
  *   and k past K are zero.
  *
@@ -223,6 +226,49 @@ ozk_status ozk_s2_crt(ozk_ctx* ctx, int s, int complex_planes, int64_t M,
                       const int32_t* tau, const double* alpha,
                       const double* beta, double* C, int64_t ldc,
                       hipStream_t stream);
+
+/* ------------------------------------------------- batches of problems */
+
+/* One problem of a batch: C = alpha*A*B + beta*C with the same conventions
+ * as the single calls (device pointers, row-major, leading dimensions in
+ * elements; complex data interleaved).  alpha/beta are {re, im}; DGEMM uses
+ * the real parts. */
+typedef struct ozk_gemm_desc {
+  int64_t M, N, K;
+  const double* A;
+  int64_t lda;
+  const double* B;
+  int64_t ldb;
+  double* C;
+  int64_t ldc;
+  double alpha[2];
+  double beta[2];
+} ozk_gemm_desc;
+
+typedef struct ozk_batch_plan ozk_batch_plan;
+
+/* Plan a batch of `count` uneven problems (descs is a HOST array; the
+ * pointers inside are kept and used by every ozk_gemm_batched call).  This
+ * is the only step that allocates: a small device table with the problem
+ * list, per-step prefix sums of the work units and the order of the GEMM
+ * work items (problems by decreasing K, so the longest items start first).
+ * *ws_bytes receives the workspace every call needs.  Supported: Scheme II
+ * real DGEMM (op OZK_OP_DGEMM) and 3M ZGEMM (op OZK_OP_ZGEMM), 1 <= s <= 20;
+ * other combinations return OZK_ERR_UNSUPPORTED.  Not in the paper: its
+ * problems are single square GEMMs (Sec. V-B). */
+ozk_status ozk_batch_plan_create(ozk_ctx* ctx, ozk_op op, ozk_scheme scheme,
+                                 int p_or_s, int count,
+                                 const ozk_gemm_desc* descs,
+                                 ozk_batch_plan** plan, size_t* ws_bytes);
+/* Run a planned batch on `stream`: one launch per step for all problems
+ * (pre-pass of the rows, column scales, column residues, a persistent
+ * INT8 GEMM over every (problem, modulus, tile) item, CRT).  No allocation,
+ * no host synchronisation, no memset: the sequence can be captured into a
+ * HIP graph and replayed. */
+ozk_status ozk_gemm_batched(ozk_ctx* ctx, const ozk_batch_plan* plan, void* ws,
+                            size_t ws_bytes, hipStream_t stream);
+/* Free a plan (NULL accepted); work using it must have completed. */
+ozk_status ozk_batch_plan_destroy(ozk_batch_plan* plan);
 
 #ifdef __cplusplus
 }

@@ -259,4 +259,4 @@ def k_split_s1(p: int) -> int:
     return ((2 ** 31 - 1) // per_k) // 32 * 32
 
 
-from . import scheme2, metrics  # noqa: E402,F401
+from . import scheme2, metrics, selector  # noqa: E402,F401

@@ -36,6 +36,7 @@ EXPORTS = (
     "ozk_s1_packed_bytes", "ozk_s2_packed_bytes", "ozk_s1_k_split", "ozk_workspace_size",
     "ozk_dgemm", "ozk_zgemm_3m", "ozk_s1_split_rows", "ozk_s1_split_cols", "ozk_s1_gemm",
     "ozk_s1_diagonals", "ozk_s2_split_rows", "ozk_s2_split_cols", "ozk_s2_gemm_mod", "ozk_s2_crt",
+    "ozk_batch_plan_create", "ozk_gemm_batched", "ozk_batch_plan_destroy",
 )
 
 
@@ -78,6 +79,9 @@ def _lib() -> ctypes.CDLL:
         "ozk_s2_split_cols": (I, [P, I, I, I64, I64, P, I64, P, P, P]),
         "ozk_s2_gemm_mod": (I, [P, I, I, I64, I64, I64, P, P, P, P]),
         "ozk_s2_crt": (I, [P, I, I, I64, I64, P, P, P, P, P, P, I64, P]),
+        "ozk_batch_plan_create": (I, [P, I, I, I, I, P, ctypes.POINTER(P), ctypes.POINTER(SZ)]),
+        "ozk_gemm_batched": (I, [P, P, P, SZ, P]),
+        "ozk_batch_plan_destroy": (I, [P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -316,6 +320,77 @@ def unpack_s1(packed, rows: int, K: int, p: int):
     (drops the padding); a pure reshape of the documented layout."""
     Rp = (rows + OZK_ROW_ALIGN - 1) // OZK_ROW_ALIGN * OZK_ROW_ALIGN
     Kp = (K + OZK_K_CHUNK - 1) // OZK_K_CHUNK * OZK_K_CHUNK
-    v = packed[: Rp * Kp * p].reshape(Rp, Kp // OZK_K_CHUNK, p, OZK_K_CHUNK)
-    v = v.permute(2, 0, 1, 3).reshape(p, Rp, Kp)
+    v = packed[: Rp * Kp * p].reshape(Kp // OZK_K_CHUNK, p, Rp, OZK_K_CHUNK)
+    v = v.permute(1, 2, 0, 3).reshape(p, Rp, Kp)
     return v[:, :rows, :K]
+
+
+# ------------------------------------------------------------------ batches
+
+class OzkGemmDesc(ctypes.Structure):
+    """ozk_gemm_desc of include/ozk.h."""
+    _fields_ = [("M", ctypes.c_int64), ("N", ctypes.c_int64), ("K", ctypes.c_int64),
+                ("A", ctypes.c_void_p), ("lda", ctypes.c_int64),
+                ("B", ctypes.c_void_p), ("ldb", ctypes.c_int64),
+                ("C", ctypes.c_void_p), ("ldc", ctypes.c_int64),
+                ("alpha", ctypes.c_double * 2), ("beta", ctypes.c_double * 2)]
+
+
+def ozk_batch_plan_create(ctx: Context, op: int, scheme: int, p_or_s: int, descs):
+    """Plan a batch from a sequence of OzkGemmDesc; returns (plan, ws_bytes)."""
+    arr = (OzkGemmDesc * max(len(descs), 1))(*descs)
+    plan = ctypes.c_void_p()
+    ws = ctypes.c_size_t()
+    st = _lib().ozk_batch_plan_create(ctx.handle, op, scheme, p_or_s, len(descs), ctypes.cast(arr, ctypes.c_void_p),
+                                      ctypes.byref(plan), ctypes.byref(ws))
+    _check("ozk_batch_plan_create", st, ctx)
+    return plan, int(ws.value)
+
+
+def ozk_gemm_batched(ctx: Context, plan, ws, stream=None) -> None:
+    st = _lib().ozk_gemm_batched(ctx.handle, plan, _ptr(ws), ws.numel(), _stream(stream))
+    _check("ozk_gemm_batched", st, ctx)
+
+
+def ozk_batch_plan_destroy(plan) -> None:
+    _lib().ozk_batch_plan_destroy(plan)
+
+
+class BatchPlan:
+    """A planned batch over (A, B, C) CUDA tensors (float64 for DGEMM,
+    complex128 for ZGEMM) that owns its workspace; run() enqueues the whole
+    batch on a stream (graph-capturable)."""
+
+    def __init__(self, ctx: Context, op: int, scheme: int, p_or_s: int, problems, alpha=1.0, beta=0.0):
+        import torch
+        self.ctx = ctx
+        self.keep = list(problems)  # the plan keeps raw pointers to these tensors
+        al, be = complex(alpha), complex(beta)
+        descs = []
+        for A, B, C in self.keep:
+            d = OzkGemmDesc()
+            d.M, d.K = A.shape
+            d.N = B.shape[1]
+            d.A, d.lda = _ptr(A), _ld(A)
+            d.B, d.ldb = _ptr(B), _ld(B)
+            d.C, d.ldc = _ptr(C), _ld(C)
+            d.alpha[0], d.alpha[1] = al.real, al.imag
+            d.beta[0], d.beta[1] = be.real, be.imag
+            descs.append(d)
+        self.plan, nbytes = ozk_batch_plan_create(ctx, op, scheme, p_or_s, descs)
+        dev = self.keep[0][0].device if self.keep else torch.device("cuda:0")
+        self.ws = _workspace(nbytes, dev)
+
+    def run(self, stream=None) -> None:
+        ozk_gemm_batched(self.ctx, self.plan, self.ws, stream)
+
+    def close(self) -> None:
+        if self.plan:
+            ozk_batch_plan_destroy(self.plan)
+            self.plan = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

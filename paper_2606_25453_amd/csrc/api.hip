@@ -5,6 +5,10 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
+#include <numeric>
+#include <vector>
+
 #include "ozk.h"
 #include "ozk_internal.hpp"
 
@@ -383,6 +387,157 @@ ozk_status ozk_s2_crt(ozk_ctx* ctx, int s, int complex_planes, int64_t M, int64_
   if (!beta) return fail(ctx, OZK_ERR_INVALID_ARG, 10);
   if (ldc < (N > 0 ? N : 1)) return fail(ctx, OZK_ERR_INVALID_ARG, 12);
   return hip_status(ctx, ozk::s2_crt(s, complex_planes != 0, M, N, Cres, sigma, tau, alpha, beta, C, ldc, stream));
+}
+
+struct ozk_batch_plan {
+  int device;
+  ozk_op op;
+  ozk_scheme scheme;
+  int s;
+  int count;
+  void* dev;  // device tables
+  ozk::BatchDev bd;
+  ozk::BatchTotals tot;
+  size_t ws_bytes;
+  int gemm_grid;
+};
+
+ozk_status ozk_batch_plan_create(ozk_ctx* ctx, ozk_op op, ozk_scheme scheme, int p_or_s, int count,
+                                 const ozk_gemm_desc* descs, ozk_batch_plan** plan, size_t* ws_bytes) {
+  if (!ctx) return OZK_ERR_INVALID_ARG;
+  ctx->last_arg = 0;
+  if (!plan) return fail(ctx, OZK_ERR_INVALID_ARG, 7);
+  *plan = nullptr;
+  if (op != OZK_OP_DGEMM && op != OZK_OP_ZGEMM) return fail(ctx, OZK_ERR_INVALID_ARG, 2);
+  if (scheme != OZK_SCHEME2) return fail(ctx, OZK_ERR_UNSUPPORTED, 3);
+  if (p_or_s < 1 || p_or_s > OZK_MAX_S) return fail(ctx, OZK_ERR_UNSUPPORTED, 4);
+  if (count < 0) return fail(ctx, OZK_ERR_INVALID_ARG, 5);
+  if (count > 0 && !descs) return fail(ctx, OZK_ERR_INVALID_ARG, 6);
+  const bool cplx = op == OZK_OP_ZGEMM;
+  const int s = p_or_s;
+  for (int i = 0; i < count; ++i) {
+    const ozk_gemm_desc& d = descs[i];
+    if (bad_dims(d.M, d.N, d.K) || d.lda < (d.K > 0 ? d.K : 1) || d.ldb < (d.N > 0 ? d.N : 1) ||
+        d.ldc < (d.N > 0 ? d.N : 1) || (!d.A && d.M > 0 && d.K > 0) || (!d.B && d.K > 0 && d.N > 0) ||
+        (!d.C && d.M > 0 && d.N > 0))
+      return fail(ctx, OZK_ERR_INVALID_ARG, 6);
+  }
+  std::vector<ozk::BatchProb> prob(count);
+  size_t o = 0;
+  for (int i = 0; i < count; ++i) {
+    const ozk_gemm_desc& d = descs[i];
+    ozk::BatchProb& q = prob[i];
+    q.M = d.M;
+    q.N = d.N;
+    q.K = d.K;
+    q.Kp = round_up(d.K, OZK_K_CHUNK);
+    q.ra = round_up(d.M, OZK_ROW_ALIGN);
+    q.rb = round_up(d.N, OZK_ROW_ALIGN);
+    q.tiles = (d.M > 0 && d.N > 0) ? ozk::s2_tile_count(cplx, d.M, d.N) : 0;
+    q.A = d.A;
+    q.lda = d.lda;
+    q.B = d.B;
+    q.ldb = d.ldb;
+    q.C = d.C;
+    q.ldc = d.ldc;
+    q.a_re = d.alpha[0];
+    q.a_im = cplx ? d.alpha[1] : 0.0;
+    q.b_re = d.beta[0];
+    q.b_im = cplx ? d.beta[1] : 0.0;
+    q.off_sig = o; o = align256(o + 4 * (size_t)(d.M > 0 ? d.M : 1));
+    q.off_tau = o; o = align256(o + 4 * (size_t)(d.N > 0 ? d.N : 1));
+    q.off_a = o; o = align256(o + ozk_s2_packed_bytes(d.M, d.K, s, cplx));
+    q.off_b = o; o = align256(o + ozk_s2_packed_bytes(d.N, d.K, s, cplx));
+    q.off_res = o; o = align256(o + (size_t)s * (cplx ? 2 : 1) * d.M * d.N);
+  }
+  // GEMM item order: problems by decreasing K (stable), so the longest items go first
+  std::vector<int32_t> order(count);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return prob[a].Kp > prob[b].Kp; });
+  std::vector<int64_t> rows(count + 1, 0), cols(count + 1, 0), split(count + 1, 0), items(count + 1, 0),
+      crt(count + 1, 0);
+  for (int i = 0; i < count; ++i) {
+    const ozk::BatchProb& q = prob[i];
+    const bool live = q.M > 0 && q.N > 0;
+    rows[i + 1] = rows[i] + (live ? q.ra / 4 : 0);
+    cols[i + 1] = cols[i] + (live ? (q.N + 31) / 32 : 0);
+    split[i + 1] = split[i] + (live ? (q.rb / 256) * (q.Kp / OZK_K_CHUNK) : 0);
+    crt[i + 1] = crt[i] + (live ? (q.M * q.N + 255) / 256 : 0);
+  }
+  for (int i = 0; i < count; ++i) items[i + 1] = items[i] + prob[order[i]].tiles * s;
+  ozk_batch_plan* pl = (ozk_batch_plan*)calloc(1, sizeof(ozk_batch_plan));
+  if (!pl) return fail(ctx, OZK_ERR_HIP, 0);
+  pl->device = ctx->device;
+  pl->op = op;
+  pl->scheme = scheme;
+  pl->s = s;
+  pl->count = count;
+  pl->ws_bytes = o > 0 ? o : 256;
+  pl->tot = {rows[count], cols[count], split[count], items[count], crt[count]};
+  // device tables: problems, then six int64 prefix arrays, then the order
+  const size_t nprob = sizeof(ozk::BatchProb) * (count > 0 ? count : 1);
+  const size_t npre = sizeof(int64_t) * (count + 1);
+  const size_t total = align256(nprob) + 6 * align256(npre) + align256(sizeof(int32_t) * (count > 0 ? count : 1));
+  if (hipMalloc(&pl->dev, total) != hipSuccess) {
+    free(pl);
+    return fail(ctx, OZK_ERR_HIP, 0);
+  }
+  char* base = (char*)pl->dev;
+  size_t off = 0;
+  auto put = [&](const void* src, size_t bytes) -> void* {
+    void* dst = base + off;
+    if (bytes && hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice) != hipSuccess) return nullptr;
+    off += align256(bytes > 0 ? bytes : 1);
+    return dst;
+  };
+  void* pp = put(prob.data(), sizeof(ozk::BatchProb) * count);
+  if (count == 0) off = align256(nprob);
+  void* r1 = put(rows.data(), npre);
+  void* r2 = put(cols.data(), npre);
+  void* r3 = put(split.data(), npre);
+  void* r4 = put(items.data(), npre);
+  void* r5 = put(crt.data(), npre);
+  off += align256(npre);  // spare
+  void* r6 = put(order.data(), sizeof(int32_t) * count);
+  if ((count > 0 && (!pp || !r6)) || !r1 || !r2 || !r3 || !r4 || !r5) {
+    hipFree(pl->dev);
+    free(pl);
+    return fail(ctx, OZK_ERR_HIP, 0);
+  }
+  pl->bd.prob = (const ozk::BatchProb*)pp;
+  pl->bd.rows_start = (const int64_t*)r1;
+  pl->bd.cols_start = (const int64_t*)r2;
+  pl->bd.split_start = (const int64_t*)r3;
+  pl->bd.item_start = (const int64_t*)r4;
+  pl->bd.crt_start = (const int64_t*)r5;
+  pl->bd.order = (const int32_t*)r6;
+  pl->bd.count = count;
+  hipDeviceProp_t prop;
+  int ncu = 256;
+  if (hipGetDeviceProperties(&prop, ctx->device) == hipSuccess) ncu = prop.multiProcessorCount;
+  const int64_t slots = (int64_t)ncu * ozk::s2_batch_gemm_blocks_per_cu(cplx);
+  pl->gemm_grid = (int)(pl->tot.items < slots ? (pl->tot.items > 0 ? pl->tot.items : 1) : slots);
+  *plan = pl;
+  if (ws_bytes) *ws_bytes = pl->ws_bytes;
+  return OZK_OK;
+}
+
+ozk_status ozk_gemm_batched(ozk_ctx* ctx, const ozk_batch_plan* plan, void* ws, size_t ws_bytes,
+                            hipStream_t stream) {
+  if (!ctx) return OZK_ERR_INVALID_ARG;
+  ctx->last_arg = 0;
+  if (!plan) return fail(ctx, OZK_ERR_INVALID_ARG, 2);
+  if (!ws || ws_bytes < plan->ws_bytes) return fail(ctx, OZK_ERR_WORKSPACE, 3);
+  if (plan->count == 0) return OZK_OK;
+  return hip_status(ctx, ozk::s2_batched(plan->s, plan->op == OZK_OP_ZGEMM, plan->bd, plan->tot, (int8_t*)ws,
+                                         plan->gemm_grid, stream));
+}
+
+ozk_status ozk_batch_plan_destroy(ozk_batch_plan* plan) {
+  if (!plan) return OZK_OK;
+  if (plan->dev) hipFree(plan->dev);
+  free(plan);
+  return OZK_OK;
 }
 
 }  // extern "C"

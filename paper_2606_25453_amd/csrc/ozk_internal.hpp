@@ -31,6 +31,42 @@ hipError_t s1_split_cols(int p, const double* X, int64_t ldx, int64_t K, int64_t
                          int8_t* packed, hipStream_t st);
 hipError_t s1_gemm(int p, const S1GemmArgs& g, hipStream_t st);
 
+// One problem of a batch; workspace parts are byte offsets from the
+// workspace base passed to each launch.
+struct BatchProb {
+  int64_t M, N, K, Kp, ra, rb, tiles;
+  const double* A;
+  int64_t lda;
+  const double* B;
+  int64_t ldb;
+  double* C;
+  int64_t ldc;
+  double a_re, a_im, b_re, b_im;
+  int64_t off_sig, off_tau, off_a, off_b, off_res;
+};
+
+// Device view of a batch plan: the problem table and per-step prefix sums of
+// work units (count + 1 entries each, starting at 0).
+struct BatchDev {
+  const BatchProb* prob;
+  const int64_t* rows_start;   // row blocks of 4 rows (pre-pass of A)
+  const int64_t* cols_start;   // column blocks of 32 (column scales of B)
+  const int64_t* split_start;  // (256-column block, K chunk) pairs (residues of B)
+  const int64_t* item_start;   // GEMM items in the order below
+  const int32_t* order;        // GEMM item order -> problem index
+  const int64_t* crt_start;    // output blocks of 256 (CRT)
+  int count;
+};
+
+struct BatchTotals {
+  int64_t rows, cols, split, items, crt;
+};
+
+hipError_t s2_batched(int s, bool cplx, const BatchDev& bd, const BatchTotals& tot, int8_t* ws, int gemm_grid,
+                      hipStream_t st);
+int s2_batch_gemm_blocks_per_cu(bool cplx);
+int64_t s2_tile_count(bool cplx, int64_t M, int64_t N);
+
 void s2_targets(int s, int& ta, int& tb);
 hipError_t s2_split_rows(int s, bool cplx, const double* X, int64_t ldx, int64_t rows, int64_t K, int32_t* sigma,
                          int8_t* packed, hipStream_t st);

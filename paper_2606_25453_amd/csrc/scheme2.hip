@@ -147,16 +147,17 @@ struct S2Args {
 };
 
 // One wave per packed row: exponent max, norm-bound sum, then residues of 4
-// consecutive k per lane (one dword per plane).  Real layout
-// packed[l][r][k]; complex layout packed[l][r][c][q][32] (q = re, im, sum).
+// consecutive k per lane (one dword per plane).  Every modulus plane is a
+// packed operand of the shared GEMM core: real packed[l][c][r][32], complex
+// packed[l][c][q][r][32] (q = re, im, sum).
 template <bool CPLX>
-__global__ __launch_bounds__(256) void k_s2_split_rows(const double* __restrict__ X, int64_t ldx, int64_t rows,
-                                                       int64_t K, int64_t Kp, int64_t rows_packed, S2Args sa,
-                                                       int32_t* __restrict__ sigma_out,
-                                                       int8_t* __restrict__ packed) {
+__device__ __forceinline__ void s2_split_rows_block(const double* __restrict__ X, int64_t ldx, int64_t rows,
+                                                    int64_t K, int64_t Kp, int64_t rows_packed, S2Args sa,
+                                                    int32_t* __restrict__ sigma_out, int8_t* __restrict__ packed,
+                                                    int64_t blk) {
   constexpr int W = CPLX ? 2 : 1;
   const int lane = threadIdx.x & 63;
-  const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int64_t r = blk * 4 + (threadIdx.x >> 6);
   if (r >= rows_packed) return;
   const double* xr = X + r * ldx * W;
   int sigma = 0;
@@ -199,17 +200,25 @@ __global__ __launch_bounds__(256) void k_s2_split_rows(const double* __restrict_
         }
       }
       int8_t* base = packed + l * plane;
-      if (!CPLX) {
-        *reinterpret_cast<uint32_t*>(base + r * Kp + k0) = w0;
-      } else {
-        const int64_t c = k0 / OZK_K_CHUNK, kk = k0 % OZK_K_CHUNK;
-        int8_t* dst = base + (r * (Kp / OZK_K_CHUNK) + c) * 3 * OZK_K_CHUNK + kk;
-        *reinterpret_cast<uint32_t*>(dst) = w0;
-        *reinterpret_cast<uint32_t*>(dst + OZK_K_CHUNK) = w1;
-        *reinterpret_cast<uint32_t*>(dst + 2 * OZK_K_CHUNK) = w2;
+      const int64_t c = k0 / OZK_K_CHUNK, kk = k0 % OZK_K_CHUNK;
+      constexpr int NP = CPLX ? 3 : 1;
+      const int64_t slab = rows_packed * OZK_K_CHUNK;
+      int8_t* dst = base + c * NP * slab + r * OZK_K_CHUNK + kk;
+      *reinterpret_cast<uint32_t*>(dst) = w0;
+      if (CPLX) {
+        *reinterpret_cast<uint32_t*>(dst + slab) = w1;
+        *reinterpret_cast<uint32_t*>(dst + 2 * slab) = w2;
       }
     }
   }
+}
+
+template <bool CPLX>
+__global__ __launch_bounds__(256) void k_s2_split_rows(const double* __restrict__ X, int64_t ldx, int64_t rows,
+                                                       int64_t K, int64_t Kp, int64_t rows_packed, S2Args sa,
+                                                       int32_t* __restrict__ sigma_out,
+                                                       int8_t* __restrict__ packed) {
+  s2_split_rows_block<CPLX>(X, ldx, rows, K, Kp, rows_packed, sa, sigma_out, packed, blockIdx.x);
 }
 
 // Column scales: a block of 256 threads covers 32 consecutive columns with 8
@@ -217,13 +226,13 @@ __global__ __launch_bounds__(256) void k_s2_split_rows(const double* __restrict_
 // and then the norm-bound sum are reduced through LDS, so no atomics and no
 // scratch memory are needed and the result does not depend on the order.
 template <bool CPLX>
-__global__ __launch_bounds__(256) void k_s2_col_scales(const double* __restrict__ X, int64_t ldx, int64_t K,
-                                                       int64_t cols, int T, int32_t* __restrict__ tau) {
+__device__ __forceinline__ void s2_col_scales_block(const double* __restrict__ X, int64_t ldx, int64_t K,
+                                                    int64_t cols, int T, int32_t* __restrict__ tau, int64_t blk) {
   constexpr int W = CPLX ? 2 : 1;
   __shared__ int red_e[8][32];
   __shared__ int64_t red_s[8][32];
   const int cl = threadIdx.x & 31, g = threadIdx.x >> 5;
-  const int64_t j = (int64_t)blockIdx.x * 32 + cl;
+  const int64_t j = blk * 32 + cl;
   const bool in = j < cols;
   int e = OZK_EXP_ZERO;
   if (in)
@@ -249,15 +258,20 @@ __global__ __launch_bounds__(256) void k_s2_col_scales(const double* __restrict_
   }
 }
 
+template <bool CPLX>
+__global__ __launch_bounds__(256) void k_s2_col_scales(const double* __restrict__ X, int64_t ldx, int64_t K,
+                                                       int64_t cols, int T, int32_t* __restrict__ tau) {
+  s2_col_scales_block<CPLX>(X, ldx, K, cols, T, tau, blockIdx.x);
+}
+
 // Thread (j, c): the 32 k of chunk c of column j, residues for every modulus.
 template <bool CPLX>
-__global__ __launch_bounds__(256) void k_s2_split_cols(const double* __restrict__ X, int64_t ldx, int64_t K,
-                                                       int64_t cols, int64_t Kp, int64_t cols_packed, int s,
-                                                       const int32_t* __restrict__ tau,
-                                                       int8_t* __restrict__ packed) {
+__device__ __forceinline__ void s2_split_cols_block(const double* __restrict__ X, int64_t ldx, int64_t K,
+                                                    int64_t cols, int64_t Kp, int64_t cols_packed, int s,
+                                                    const int32_t* __restrict__ tau, int8_t* __restrict__ packed,
+                                                    int64_t jb, int64_t c) {
   constexpr int W = CPLX ? 2 : 1;
-  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  const int64_t c = blockIdx.y;
+  const int64_t j = jb * 256 + threadIdx.x;
   if (j >= cols_packed) return;
   const int t = j < cols ? tau[j] : 0;
   const bool live = j < cols && t != OZK_EXP_NONFINITE;
@@ -283,20 +297,29 @@ __global__ __launch_bounds__(256) void k_s2_split_cols(const double* __restrict_
         w2[kk / 4] |= (uint32_t)(uint8_t)sym(((a + b) % m + m) % m, m) << (8 * (kk % 4));
       }
     }
-    int8_t* base = packed + l * plane;
-    int8_t* dst = CPLX ? base + (j * (Kp / OZK_K_CHUNK) + c) * 3 * OZK_K_CHUNK : base + j * Kp + c * OZK_K_CHUNK;
+    constexpr int NP = CPLX ? 3 : 1;
+    const int64_t slab = cols_packed * OZK_K_CHUNK;
+    int8_t* dst = packed + l * plane + c * NP * slab + j * OZK_K_CHUNK;
     uint4* q0 = reinterpret_cast<uint4*>(dst);
     q0[0] = make_uint4(w0[0], w0[1], w0[2], w0[3]);
     q0[1] = make_uint4(w0[4], w0[5], w0[6], w0[7]);
     if (CPLX) {
-      uint4* q1 = reinterpret_cast<uint4*>(dst + OZK_K_CHUNK);
+      uint4* q1 = reinterpret_cast<uint4*>(dst + slab);
       q1[0] = make_uint4(w1[0], w1[1], w1[2], w1[3]);
       q1[1] = make_uint4(w1[4], w1[5], w1[6], w1[7]);
-      uint4* q2 = reinterpret_cast<uint4*>(dst + 2 * OZK_K_CHUNK);
+      uint4* q2 = reinterpret_cast<uint4*>(dst + 2 * slab);
       q2[0] = make_uint4(w2[0], w2[1], w2[2], w2[3]);
       q2[1] = make_uint4(w2[4], w2[5], w2[6], w2[7]);
     }
   }
+}
+
+template <bool CPLX>
+__global__ __launch_bounds__(256) void k_s2_split_cols(const double* __restrict__ X, int64_t ldx, int64_t K,
+                                                       int64_t cols, int64_t Kp, int64_t cols_packed, int s,
+                                                       const int32_t* __restrict__ tau,
+                                                       int8_t* __restrict__ packed) {
+  s2_split_cols_block<CPLX>(X, ldx, K, cols, Kp, cols_packed, s, tau, packed, blockIdx.x, blockIdx.y);
 }
 
 // ----------------------------------------------------------- modular GEMM
@@ -307,23 +330,32 @@ __global__ __launch_bounds__(256) void k_s2_split_cols(const double* __restrict_
 constexpr int64_t S2_RUN_STEPS = 4095;
 
 template <bool CPLX>
-__global__ __launch_bounds__(256, 1) void k_s2_gemm_mod(const int8_t* __restrict__ Ap,
-                                                       const int8_t* __restrict__ Bp, int64_t plane_a,
-                                                       int64_t plane_b, int64_t nsteps, int M, int N,
-                                                       int8_t* __restrict__ out) {
-  constexpr int P = CPLX ? 3 : 1;
-  constexpr int TM = 2, TN = CPLX ? 1 : 2;
-  using T = GemmTile<P, TM, TN>;
-  extern __shared__ __attribute__((aligned(16))) int8_t lds[];
-  const int l = blockIdx.z;
-  const int64_t m0 = (int64_t)blockIdx.y * T::BM, n0 = (int64_t)blockIdx.x * T::BN;
-  const int64_t row_bytes = nsteps * T::ROW_BYTES;
+struct S2Cfg {
+  static constexpr int P = CPLX ? 3 : 1;
+  static constexpr int TM = 2, TN = CPLX ? 1 : 2;
+  static constexpr int NS = 4;
+};
+
+// One output tile of one modulus: the per-modulus products, then smod (3M:
+// the combination first) and the int8 output residues.
+template <bool CPLX>
+__device__ __forceinline__ void s2_gemm_tile(const int8_t* __restrict__ Ap, const int8_t* __restrict__ Bp,
+                                             int64_t plane_a, int64_t plane_b, int64_t rows_a, int64_t rows_b,
+                                             int64_t nsteps, int64_t M, int64_t N, int8_t* __restrict__ out,
+                                             int64_t tile, int l, int8_t* lds) {
+  using Cfg = S2Cfg<CPLX>;
+  constexpr int P = Cfg::P, TM = Cfg::TM, TN = Cfg::TN, NS = Cfg::NS;
+  using T = GemmTile<P, TM, TN, NS>;
+  const int64_t tiles_m = (M + T::BM - 1) / T::BM, tiles_n = (N + T::BN - 1) / T::BN;
+  int64_t tm, tn;
+  tile_of(tile, tiles_m, tiles_n, tm, tn);
+  const int64_t m0 = tm * T::BM, n0 = tn * T::BN;
   v16i acc[P][TM][TN];
   zero_acc<P, TM, TN>(acc);
   for (int64_t s0 = 0; s0 < nsteps || s0 == 0; s0 += S2_RUN_STEPS) {
     const int64_t n = nsteps - s0 < S2_RUN_STEPS ? nsteps - s0 : S2_RUN_STEPS;
-    gemm_tile_accumulate<P, TM, TN, DIAGONAL>(Ap + l * plane_a, Bp + l * plane_b, row_bytes, m0, n0, s0, n, lds,
-                                              acc);
+    gemm_tile_accumulate<P, TM, TN, NS, DIAGONAL>(Ap + l * plane_a, Bp + l * plane_b, rows_a, rows_b, m0, n0, s0,
+                                                  n, lds, acc);
     if (s0 + S2_RUN_STEPS >= nsteps) break;
     // keep the accumulators small by subtracting a multiple of m (exact mod m)
     const int m = c_s2.m[l];
@@ -351,6 +383,16 @@ __global__ __launch_bounds__(256, 1) void k_s2_gemm_mod(const int8_t* __restrict
       out[(2 * l + 1) * mn + row * N + col] = (int8_t)smod_i32(t3 - t1 - t2, l);
     }
   });
+}
+
+template <bool CPLX>
+__global__ __launch_bounds__(256, 1) void k_s2_gemm_mod(const int8_t* __restrict__ Ap,
+                                                       const int8_t* __restrict__ Bp, int64_t plane_a,
+                                                       int64_t plane_b, int64_t rows_a, int64_t rows_b,
+                                                       int64_t nsteps, int M, int N, int8_t* __restrict__ out) {
+  extern __shared__ __attribute__((aligned(1024))) int8_t lds[];
+  s2_gemm_tile<CPLX>(Ap, Bp, plane_a, plane_b, rows_a, rows_b, nsteps, M, N, out, blockIdx.x, (int)blockIdx.z,
+                     lds);
 }
 
 // ------------------------------------------------------------------- CRT
@@ -490,11 +532,11 @@ __device__ __forceinline__ double round_limbs(const uint32_t (&mag)[NL], bool ne
 }
 
 template <bool CPLX>
-__global__ __launch_bounds__(256) void k_s2_crt(CrtArgs ca, int M, int N, const int8_t* __restrict__ res,
-                                                const int32_t* __restrict__ sigma, const int32_t* __restrict__ tau,
-                                                double a_re, double a_im, double b_re, double b_im,
-                                                double* __restrict__ C, int64_t ldc) {
-  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+__device__ __forceinline__ void s2_crt_block(const CrtArgs& ca, int64_t M, int64_t N, const int8_t* __restrict__ res,
+                                             const int32_t* __restrict__ sigma, const int32_t* __restrict__ tau,
+                                             double a_re, double a_im, double b_re, double b_im,
+                                             double* __restrict__ C, int64_t ldc, int64_t blk) {
+  const int64_t idx = blk * 256 + threadIdx.x;
   const int64_t mn = (int64_t)M * N;
   if (idx >= mn) return;
   const int64_t row = idx / N, col = idx % N;
@@ -529,6 +571,14 @@ __global__ __launch_bounds__(256) void k_s2_crt(CrtArgs ca, int M, int N, const 
     cp[0] = ore;
     cp[1] = oim;
   }
+}
+
+template <bool CPLX>
+__global__ __launch_bounds__(256) void k_s2_crt(CrtArgs ca, int M, int N, const int8_t* __restrict__ res,
+                                                const int32_t* __restrict__ sigma, const int32_t* __restrict__ tau,
+                                                double a_re, double a_im, double b_re, double b_im,
+                                                double* __restrict__ C, int64_t ldc) {
+  s2_crt_block<CPLX>(ca, M, N, res, sigma, tau, a_re, a_im, b_re, b_im, C, ldc, blockIdx.x);
 }
 
 // ------------------------------------------------------------ host side
@@ -648,8 +698,9 @@ hipError_t s2_split_cols(int s, bool cplx, const double* X, int64_t ldx, int64_t
 template <bool CPLX>
 static hipError_t launch_gemm_mod(int s, int64_t M, int64_t N, int64_t K, const int8_t* Ap, const int8_t* Bp,
                                   int8_t* out, hipStream_t st) {
-  constexpr int P = CPLX ? 3 : 1;
-  using T = GemmTile<P, 2, CPLX ? 1 : 2>;
+  using Cfg = S2Cfg<CPLX>;
+  constexpr int P = Cfg::P;
+  using T = GemmTile<P, Cfg::TM, Cfg::TN, Cfg::NS>;
   auto kern = k_s2_gemm_mod<CPLX>;
   static bool attr = false;
   if (!attr) {
@@ -659,10 +710,12 @@ static hipError_t launch_gemm_mod(int s, int64_t M, int64_t N, int64_t K, const 
     attr = true;
   }
   const int64_t kp = round_up(K, OZK_K_CHUNK);
-  const int64_t plane_a = round_up(M, OZK_ROW_ALIGN) * kp * P, plane_b = round_up(N, OZK_ROW_ALIGN) * kp * P;
-  const dim3 grid((unsigned)((N + T::BN - 1) / T::BN), (unsigned)((M + T::BM - 1) / T::BM), (unsigned)s);
-  hipLaunchKernelGGL(kern, grid, dim3(256), T::LDS_BYTES, st, Ap, Bp, plane_a, plane_b, kp / OZK_K_CHUNK, (int)M,
-                     (int)N, out);
+  const int64_t ra = round_up(M, OZK_ROW_ALIGN), rb = round_up(N, OZK_ROW_ALIGN);
+  const int64_t plane_a = ra * kp * P, plane_b = rb * kp * P;
+  const int64_t tiles = ((M + T::BM - 1) / T::BM) * ((N + T::BN - 1) / T::BN);
+  const dim3 grid((unsigned)tiles, 1, (unsigned)s);
+  hipLaunchKernelGGL(kern, grid, dim3(256), T::LDS_BYTES, st, Ap, Bp, plane_a, plane_b, ra, rb, kp / OZK_K_CHUNK,
+                     (int)M, (int)N, out);
   return hipGetLastError();
 }
 
@@ -688,6 +741,129 @@ hipError_t s2_crt(int s, bool cplx, int64_t M, int64_t N, const int8_t* res, con
   else
     hipLaunchKernelGGL(k_s2_crt<false>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, ca, (int)M, (int)N,
                        res, sigma, tau, alpha[0], ai, beta[0], bi, C, ldc);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------- batched problems
+//
+// Many uneven problems in one launch per step.  The plan uploads a problem
+// table and, per step, the prefix sums of the work units of each problem;
+// a workgroup finds its problem by binary search.  The GEMM step is one
+// persistent launch: the (problem, modulus, tile) items are enumerated with
+// the problems in decreasing K (longest items first) and workgroup w takes
+// items w, w + G, w + 2G, ... so that the load is balanced without atomics.
+
+namespace {
+
+__device__ __forceinline__ int find_problem(const int64_t* __restrict__ start, int count, int64_t x) {
+  int lo = 0, hi = count - 1;  // largest i with start[i] <= x
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (start[mid] <= x) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+}  // namespace
+
+template <bool CPLX>
+__global__ __launch_bounds__(256) void k_b_split_rows(BatchDev bd, int8_t* __restrict__ ws, S2Args sa) {
+  const int p = find_problem(bd.rows_start, bd.count, blockIdx.x);
+  const BatchProb& q = bd.prob[p];
+  s2_split_rows_block<CPLX>(q.A, q.lda, q.M, q.K, q.Kp, q.ra, sa, reinterpret_cast<int32_t*>(ws + q.off_sig),
+                            ws + q.off_a, blockIdx.x - bd.rows_start[p]);
+}
+
+template <bool CPLX>
+__global__ __launch_bounds__(256) void k_b_col_scales(BatchDev bd, int8_t* __restrict__ ws, int T) {
+  const int p = find_problem(bd.cols_start, bd.count, blockIdx.x);
+  const BatchProb& q = bd.prob[p];
+  s2_col_scales_block<CPLX>(q.B, q.ldb, q.K, q.N, T, reinterpret_cast<int32_t*>(ws + q.off_tau),
+                            blockIdx.x - bd.cols_start[p]);
+}
+
+template <bool CPLX>
+__global__ __launch_bounds__(256) void k_b_split_cols(BatchDev bd, int8_t* __restrict__ ws, int s) {
+  const int p = find_problem(bd.split_start, bd.count, blockIdx.x);
+  const BatchProb& q = bd.prob[p];
+  const int64_t local = blockIdx.x - bd.split_start[p];
+  const int64_t jblocks = q.rb / 256;
+  s2_split_cols_block<CPLX>(q.B, q.ldb, q.K, q.N, q.Kp, q.rb, s, reinterpret_cast<const int32_t*>(ws + q.off_tau),
+                            ws + q.off_b, local % jblocks, local / jblocks);
+}
+
+template <bool CPLX>
+__global__ __launch_bounds__(256, 1) void k_b_gemm_mod(BatchDev bd, int8_t* __restrict__ ws, int s) {
+  extern __shared__ __attribute__((aligned(1024))) int8_t lds[];
+  constexpr int NP = CPLX ? 3 : 1;
+  const int64_t total = bd.item_start[bd.count];
+  for (int64_t it = blockIdx.x; it < total; it += gridDim.x) {
+    const int i = find_problem(bd.item_start, bd.count, it);
+    const BatchProb& q = bd.prob[bd.order[i]];
+    const int64_t local = it - bd.item_start[i];
+    const int l = (int)(local / q.tiles);
+    const int64_t tile = local % q.tiles;
+    s2_gemm_tile<CPLX>(ws + q.off_a, ws + q.off_b, q.ra * q.Kp * NP, q.rb * q.Kp * NP, q.ra, q.rb,
+                       q.Kp / OZK_K_CHUNK, q.M, q.N, ws + q.off_res, tile, l, lds);
+  }
+  (void)s;
+}
+
+template <bool CPLX>
+__global__ __launch_bounds__(256) void k_b_crt(CrtArgs ca, BatchDev bd, int8_t* __restrict__ ws) {
+  const int p = find_problem(bd.crt_start, bd.count, blockIdx.x);
+  const BatchProb& q = bd.prob[p];
+  s2_crt_block<CPLX>(ca, q.M, q.N, ws + q.off_res, reinterpret_cast<const int32_t*>(ws + q.off_sig),
+                     reinterpret_cast<const int32_t*>(ws + q.off_tau), q.a_re, q.a_im, q.b_re, q.b_im, q.C, q.ldc,
+                     blockIdx.x - bd.crt_start[p]);
+}
+
+int64_t s2_tile_count(bool cplx, int64_t M, int64_t N) {
+  const int bm = cplx ? GemmTile<3, 2, 1, 4>::BM : GemmTile<1, 2, 2, 4>::BM;
+  const int bn = cplx ? GemmTile<3, 2, 1, 4>::BN : GemmTile<1, 2, 2, 4>::BN;
+  return ((M + bm - 1) / bm) * ((N + bn - 1) / bn);
+}
+
+int s2_batch_gemm_blocks_per_cu(bool cplx) {
+  int n = 0;
+  const int lds = cplx ? GemmTile<3, 2, 1, 4>::LDS_BYTES : GemmTile<1, 2, 2, 4>::LDS_BYTES;
+  hipError_t e = cplx ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_b_gemm_mod<true>, 256, lds)
+                      : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_b_gemm_mod<false>, 256, lds);
+  return (e == hipSuccess && n > 0) ? n : 1;
+}
+
+hipError_t s2_batched(int s, bool cplx, const BatchDev& bd, const BatchTotals& tot, int8_t* ws, int gemm_grid,
+                      hipStream_t st) {
+  int ta, tb;
+  CrtArgs ca;
+  crt_args(s, ca, ta, tb);
+  if (tot.rows == 0 || tot.crt == 0) return hipSuccess;
+  S2Args sa{s, ta};
+  const int lds = cplx ? GemmTile<3, 2, 1, 4>::LDS_BYTES : GemmTile<1, 2, 2, 4>::LDS_BYTES;
+  static bool attr[2] = {false, false};
+  if (!attr[cplx]) {
+    hipError_t e = cplx ? hipFuncSetAttribute(reinterpret_cast<const void*>(k_b_gemm_mod<true>),
+                                              hipFuncAttributeMaxDynamicSharedMemorySize, lds)
+                        : hipFuncSetAttribute(reinterpret_cast<const void*>(k_b_gemm_mod<false>),
+                                              hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (e != hipSuccess) return e;
+    attr[cplx] = true;
+  }
+  if (cplx) {
+    hipLaunchKernelGGL(k_b_split_rows<true>, dim3((unsigned)tot.rows), dim3(256), 0, st, bd, ws, sa);
+    hipLaunchKernelGGL(k_b_col_scales<true>, dim3((unsigned)tot.cols), dim3(256), 0, st, bd, ws, tb);
+    if (tot.split) hipLaunchKernelGGL(k_b_split_cols<true>, dim3((unsigned)tot.split), dim3(256), 0, st, bd, ws, s);
+    if (tot.items) hipLaunchKernelGGL(k_b_gemm_mod<true>, dim3((unsigned)gemm_grid), dim3(256), lds, st, bd, ws, s);
+    hipLaunchKernelGGL(k_b_crt<true>, dim3((unsigned)tot.crt), dim3(256), 0, st, ca, bd, ws);
+  } else {
+    hipLaunchKernelGGL(k_b_split_rows<false>, dim3((unsigned)tot.rows), dim3(256), 0, st, bd, ws, sa);
+    hipLaunchKernelGGL(k_b_col_scales<false>, dim3((unsigned)tot.cols), dim3(256), 0, st, bd, ws, tb);
+    if (tot.split) hipLaunchKernelGGL(k_b_split_cols<false>, dim3((unsigned)tot.split), dim3(256), 0, st, bd, ws, s);
+    if (tot.items)
+      hipLaunchKernelGGL(k_b_gemm_mod<false>, dim3((unsigned)gemm_grid), dim3(256), lds, st, bd, ws, s);
+    hipLaunchKernelGGL(k_b_crt<false>, dim3((unsigned)tot.crt), dim3(256), 0, st, ca, bd, ws);
+  }
   return hipGetLastError();
 }
 

@@ -1,0 +1,142 @@
+"""Batched uneven problems in one launch per step (persistent GEMM), through
+the C ABI: every problem of a batch equals its single-call result and the
+CPU oracle bit for bit, and graph replays are bit-identical to the eager
+run, also with eager work in between."""
+import numpy as np
+import pytest
+
+import paper_2606_25453_amd as ozk
+import synth
+from oracle import scheme2 as s2
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = ozk.Context(0)
+    yield c
+    c.close()
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda:0")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def make_batch(count, lo, hi, seed, cplx):
+    dims = synth.log_uniform_ints(3 * count, lo, hi, seed).reshape(count, 3)
+    probs = []
+    for i, (M, N, K) in enumerate(dims):
+        M, N, K = int(M), int(N), int(K)
+        if cplx:
+            A = synth.complex_phi_matrix(M, K, 1.0, seed + 10 * i, seed + 10 * i + 1)
+            B = synth.complex_phi_matrix(K, N, 1.0, seed + 10 * i + 2, seed + 10 * i + 3)
+        else:
+            A = synth.phi_matrix(M, K, 1.0, seed + 10 * i)
+            B = synth.phi_matrix(K, N, 1.0, seed + 10 * i + 2)
+        probs.append((A, B))
+    return probs
+
+
+@pytest.mark.parametrize("cplx,s", [(True, 16), (True, 7), (False, 14)])
+def test_batch_matches_single_calls_and_oracle(ctx, cplx, s):
+    probs = make_batch(12, 1, 300, 77 + s, cplx)
+    probs.append((np.zeros((0, 5), probs[0][0].dtype), np.zeros((5, 3), probs[0][0].dtype)))  # empty M
+    dA = [dev(A) for A, _ in probs]
+    dB = [dev(B) for _, B in probs]
+    dtype = torch.complex128 if cplx else torch.float64
+    dC = [torch.full((A.shape[0], B.shape[1]), float("nan"), dtype=dtype, device="cuda:0") for A, B in probs]
+    op = ozk.OZK_OP_ZGEMM if cplx else ozk.OZK_OP_DGEMM
+    plan = ozk.BatchPlan(ctx, op, ozk.OZK_SCHEME2, s, list(zip(dA, dB, dC)))
+    plan.run()
+    for i, (A, B) in enumerate(probs):
+        got = host(dC[i])
+        if cplx:
+            single = host(ozk.ozk_zgemm_3m(ctx, s, dA[i], dB[i]))
+        else:
+            single = host(ozk.ozk_dgemm(ctx, ozk.OZK_SCHEME2, s, dA[i], dB[i]))
+        assert np.array_equal(got, single), i
+        if i < 5 and A.size and B.size:
+            ref = s2.z3m_gemm(A, B, s) if cplx else s2.s2_dgemm(A, B, s)
+            assert np.array_equal(got, ref), i
+    plan.close()
+
+
+def test_batch_alpha_beta(ctx):
+    s = 12
+    probs = make_batch(5, 10, 90, 5, True)
+    dA = [dev(A) for A, _ in probs]
+    dB = [dev(B) for _, B in probs]
+    C0 = [synth.complex_phi_matrix(A.shape[0], B.shape[1], 1.0, 300 + i, 400 + i) for i, (A, B) in enumerate(probs)]
+    dC = [dev(c) for c in C0]
+    al, be = 0.25 + 1j, -0.5 + 0.125j
+    plan = ozk.BatchPlan(ctx, ozk.OZK_OP_ZGEMM, ozk.OZK_SCHEME2, s, list(zip(dA, dB, dC)), alpha=al, beta=be)
+    plan.run()
+    for i, (A, B) in enumerate(probs):
+        assert np.array_equal(host(dC[i]), s2.z3m_gemm(A, B, s, alpha=al, beta=be, C=C0[i])), i
+    plan.close()
+
+
+def test_batch_graph_replay_is_bit_identical(ctx):
+    s = 16
+    probs = make_batch(40, 16, 256, 123, True)
+    dA = [dev(A) for A, _ in probs]
+    dB = [dev(B) for _, B in probs]
+    dC = [torch.zeros((A.shape[0], B.shape[1]), dtype=torch.complex128, device="cuda:0") for A, B in probs]
+    plan = ozk.BatchPlan(ctx, ozk.OZK_OP_ZGEMM, ozk.OZK_SCHEME2, s, list(zip(dA, dB, dC)))
+    plan.run()
+    eager = [host(c).copy() for c in dC]
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(side):
+        plan.run(stream=side)  # warm up on the capture stream
+        torch.cuda.synchronize()
+        for c in dC:
+            c.zero_()
+        torch.cuda.synchronize()
+        with torch.cuda.graph(g, stream=side):
+            plan.run(stream=side)
+    torch.cuda.current_stream().wait_stream(side)
+    for rep in range(3):
+        for c in dC:
+            c.fill_(complex(rep + 7.0, -1.0))  # eager work between replays
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for i, c in enumerate(dC):
+            assert np.array_equal(host(c), eager[i]), (rep, i)
+    plan.close()
+
+
+def test_batch_config_256_uneven_zgemm(ctx):
+    """The batch workload: 256 ZGEMMs with M, N, K log-uniform in [64, 1024],
+    one launch per step; sampled problems against single calls."""
+    s = 16
+    count = 256
+    dims = synth.log_uniform_ints(3 * count, 64, 1024, synth.seed_for(4, 256, 1.0, 0)).reshape(count, 3)
+    dA, dB, dC = [], [], []
+    g = torch.Generator(device="cpu").manual_seed(9)
+    for (M, N, K) in dims:
+        M, N, K = int(M), int(N), int(K)
+        a = (torch.rand((M, K), generator=g, dtype=torch.float64) - 0.5) + 1j * (
+            torch.rand((M, K), generator=g, dtype=torch.float64) - 0.5)
+        b = (torch.rand((K, N), generator=g, dtype=torch.float64) - 0.5) + 1j * (
+            torch.rand((K, N), generator=g, dtype=torch.float64) - 0.5)
+        dA.append(a.to("cuda:0"))
+        dB.append(b.to("cuda:0"))
+        dC.append(torch.empty((M, N), dtype=torch.complex128, device="cuda:0"))
+    plan = ozk.BatchPlan(ctx, ozk.OZK_OP_ZGEMM, ozk.OZK_SCHEME2, s, list(zip(dA, dB, dC)))
+    plan.run()
+    torch.cuda.synchronize()
+    for i in (0, 17, 101, 255):
+        assert torch.equal(dC[i], ozk.ozk_zgemm_3m(ctx, s, dA[i], dB[i])), i
+    plan.close()

@@ -1,0 +1,93 @@
+"""Pins of the selector reference: analytic gradients against central finite
+differences, Adam's first step against its closed form, the histogram
+against a brute-force count, and the a-priori bound against the measured
+error of the Scheme I oracle."""
+import math
+
+import numpy as np
+
+import oracle
+import synth
+from oracle import selector as sel
+
+
+def _params(seed):
+    r = np.random.default_rng(seed)
+    return (r.standard_normal((sel.N_FEAT, sel.HIDDEN)) * 0.3, r.standard_normal(sel.HIDDEN) * 0.1,
+            r.standard_normal((sel.HIDDEN, sel.HIDDEN)) * 0.2, r.standard_normal(sel.HIDDEN) * 0.1,
+            r.standard_normal((sel.HIDDEN, sel.N_OUT)) * 0.2, r.standard_normal(sel.N_OUT) * 0.1)
+
+
+def test_backward_matches_finite_differences():
+    r = np.random.default_rng(1)
+    params = _params(2)
+    X = r.random((7, sel.N_FEAT))
+    y = sel.ordinal_targets(r.integers(1, 10, 7))
+    logits, cache = sel.mlp_forward(params, X)
+    grads = sel.mlp_backward(params, cache, logits, y)
+    h = 1e-6
+    for pi in range(6):
+        P = params[pi]
+        flat = P.reshape(-1)
+        for idx in r.choice(flat.size, min(12, flat.size), replace=False):
+            plus = [q.copy() for q in params]
+            minus = [q.copy() for q in params]
+            plus[pi].reshape(-1)[idx] += h
+            minus[pi].reshape(-1)[idx] -= h
+            lp = sel.bce_loss(sel.mlp_forward(tuple(plus), X)[0], y)
+            lm = sel.bce_loss(sel.mlp_forward(tuple(minus), X)[0], y)
+            fd = (lp - lm) / (2 * h)
+            an = grads[pi].reshape(-1)[idx]
+            assert abs(fd - an) <= 1e-6 + 1e-5 * abs(fd), (pi, idx, fd, an)
+
+
+def test_adam_first_step_closed_form():
+    """With zero moments, the first bias-corrected step moves every
+    parameter by lr * g / (|g| + eps)."""
+    params = _params(3)
+    r = np.random.default_rng(4)
+    grads = tuple(r.standard_normal(p.shape) for p in params)
+    zeros = tuple(np.zeros_like(p) for p in params)
+    new, m, v = sel.adam_step(params, grads, zeros, zeros, 1, lr=0.01)
+    for p0, p1, g in zip(params, new, grads):
+        assert np.allclose(p0 - p1, 0.01 * g / (np.abs(g) + 1e-8), rtol=1e-12, atol=1e-15)
+
+
+def test_histogram_brute_force():
+    A = synth.phi_matrix(13, 40, 3.0, 5)
+    A[2] = 0
+    A[4, :7] = 0
+    h = sel._hist(A, 1)
+    counts = np.zeros(sel.N_BINS)
+    for i in range(13):
+        nz = [x for x in A[i] if x != 0]
+        if not nz:
+            continue
+        e = max(math.frexp(x)[1] for x in nz)
+        for x in nz:
+            d = e - math.frexp(x)[1]
+            b = max(k for k, edge in enumerate(sel.BIN_EDGES) if d >= edge)
+            counts[b] += 1
+    assert np.allclose(h, counts / counts.sum(), rtol=0, atol=1e-15)
+    f = sel.features(A, A.T.copy(), 1e-13)
+    assert f.shape == (34,) and abs(f[32] - math.log2(40) / 14) < 1e-15 and abs(f[33] - 13 / 16) < 1e-15
+
+
+def test_bound_holds_on_oracle_errors():
+    """The a-priori bound is never below the measured error."""
+    for phi, seed in ((0.5, 1), (1.0, 2), (2.0, 3)):
+        A = synth.phi_matrix(20, 64, phi, 10 + seed)
+        B = synth.phi_matrix(64, 18, phi, 20 + seed)
+        hi, lo = oracle.gemm_dd(A, B)
+        ra, rb = sel.max_deficit(A, 1), sel.max_deficit(B, 0)
+        for p in range(1, 9):
+            err = oracle.metrics.e_cw(oracle.s1_dgemm(A, B, p), hi, lo, A, B)
+            assert err <= sel.bound(p, ra, rb), (phi, p, err, sel.bound(p, ra, rb))
+
+
+def test_predict_and_targets():
+    y = sel.ordinal_targets(np.array([1, 3, 9]))
+    assert y.tolist()[0] == [0] * 8 and y.tolist()[1] == [1, 1, 0, 0, 0, 0, 0, 0] and y.tolist()[2] == [1] * 8
+    logits = np.where(y > 0, 5.0, -5.0)
+    assert sel.predict_p(logits).tolist() == [1, 3, 9]
+    assert sel.predict_p(logits, margin=1).tolist() == [2, 4, 9]

@@ -69,18 +69,20 @@ def test_split_cols_bit_exact(ctx, p, shape):
 
 
 def test_interleaved_layout_matches_eq11(ctx):
-    """Eq. 11 with t_K = 32: row r of the packed operand is
-    [A'_0 | A'_1 | A'_2 | A'_0 | ...] in 32-wide blocks (the paper's p = 3
-    example)."""
+    """Eq. 11 with t_K = 32: column block (c p + i) of the interleaved matrix
+    holds slice i of K chunk c, so a row reads [A'_0 | A'_1 | A'_2 | A'_0 |
+    ...] (the paper's p = 3 example); the blocks are stored one after the
+    other, each as a contiguous 256-row slab."""
     p, rows, K = 3, 5, 96
     X = synth.phi_matrix(rows, K, 1.0, 3)
     e, packed = ozk.ozk_s1_split_rows(ctx, p, dev(X))
-    raw = host(packed)[: 256 * K * p].reshape(256, K * p)
+    blocks = host(packed)[: 256 * K * p].reshape(K * p // 32, 256, 32)
+    Ahat = np.concatenate(list(blocks), axis=1)  # rows x pK, Eq. 11's matrix
     D = oracle.s1_digits_a(X, oracle.s1_row_exponents(X), p)
     for r in range(rows):
         for c in range(K // 32):
             for i in range(p):
-                assert np.array_equal(raw[r, (c * p + i) * 32:(c * p + i + 1) * 32], D[i, r, c * 32:(c + 1) * 32])
+                assert np.array_equal(Ahat[r, (c * p + i) * 32:(c * p + i + 1) * 32], D[i, r, c * 32:(c + 1) * 32])
 
 
 @pytest.mark.parametrize("p", [1, 2, 4, 5, 7, 8])

@@ -40,6 +40,18 @@ def kp(k):
     return (k + 31) // 32 * 32
 
 
+def planes_real(packed, s, rows, K):
+    """[s][c][r][32] -> [s][Rp][Kp]"""
+    return host(packed)[: s * rp(rows) * kp(K)].reshape(s, kp(K) // 32, rp(rows), 32).transpose(0, 2, 1, 3).reshape(
+        s, rp(rows), kp(K))
+
+
+def planes_cplx(packed, s, rows, K):
+    """[s][c][q][r][32] -> [s][q][Rp][Kp]"""
+    return host(packed)[: 3 * s * rp(rows) * kp(K)].reshape(s, kp(K) // 32, 3, rp(rows), 32).transpose(
+        0, 2, 3, 1, 4).reshape(s, 3, rp(rows), kp(K))
+
+
 @pytest.mark.parametrize("s", [1, 8, 13, 16, 20])
 @pytest.mark.parametrize("shape", [(37, 70), (300, 129)])
 def test_split_rows_real(ctx, s, shape):
@@ -51,7 +63,7 @@ def test_split_rows_real(ctx, s, shape):
     ta, _ = s2.targets(s)
     ref_sig, _ = s2.row_scales(X, ta)
     assert np.array_equal(host(sig)[:rows], ref_sig)
-    R = host(packed).reshape(s, rp(rows), kp(K))
+    R = planes_real(packed, s, rows, K)
     Xi = s2.integerise(X, ref_sig, 1)
     for l, m in enumerate(s2.moduli(s)):
         assert np.array_equal(R[l, :rows, :K], s2.residues(Xi, m)), l
@@ -68,7 +80,7 @@ def test_split_cols_real(ctx, s, shape):
     _, tb = s2.targets(s)
     ref_tau, _ = s2.col_scales(X, tb)
     assert np.array_equal(host(tau)[:cols], ref_tau)
-    R = host(packed).reshape(s, rp(cols), kp(K))
+    R = planes_real(packed, s, cols, K)
     Xi = s2.integerise(X, ref_tau, 0)
     for l, m in enumerate(s2.moduli(s)):
         assert np.array_equal(R[l, :cols, :K], s2.residues(Xi, m).T), l
@@ -85,8 +97,8 @@ def test_split_complex(ctx, s):
     st = s2.z3m_prepare(X, Y, s)
     assert np.array_equal(host(sig)[:rows], st["sig"])
     assert np.array_equal(host(tau)[:rows], st["tau"])
-    R = host(packed).reshape(s, rp(rows), kp(K) // 32, 3, 32).transpose(0, 3, 1, 2, 4).reshape(s, 3, rp(rows), kp(K))
-    S = host(packedb).reshape(s, rp(rows), kp(K) // 32, 3, 32).transpose(0, 3, 1, 2, 4).reshape(s, 3, rp(rows), kp(K))
+    R = planes_cplx(packed, s, rows, K)
+    S = planes_cplx(packedb, s, rows, K)
     for l in range(s):
         (r_re, r_im, r_sum), (s_re, s_im, s_sum) = st["planes"][l]
         assert np.array_equal(R[l, 0, :rows, :K], r_re)
