@@ -79,6 +79,8 @@ extern "C" {
 #define OZK_EXP_NONFINITE 100000
 #define OZK_MAX_P 8
 #define OZK_MAX_S 20
+#define OZK_SELECTOR_PARAMS 6920   /* float32 parameters of the selector MLP */
+#define OZK_SELECTOR_COUNTERS 34   /* int32 feature counters */
 
 typedef struct ozk_ctx ozk_ctx;
 
@@ -127,7 +129,8 @@ int64_t ozk_s1_k_split(int p);
  * Scheme I it holds the scale vectors, the two packed operands and, when K
  * exceeds ozk_s1_k_split(p), 16 bytes per output per K run; for Scheme II
  * the scales, the residue planes and s (or 2s for complex) int8 output
- * residue planes. */
+ * residue planes.  Scheme I with p_or_s = 0: the size ozk_dgemm_auto needs
+ * (room for p = 8 plus the selector counters). */
 ozk_status ozk_workspace_size(ozk_ctx* ctx, ozk_op op, ozk_scheme scheme,
                               int64_t M, int64_t N, int64_t K, int p_or_s,
                               size_t* bytes);
@@ -226,6 +229,72 @@ ozk_status ozk_s2_crt(ozk_ctx* ctx, int s, int complex_planes, int64_t M,
                       const int32_t* tau, const double* alpha,
                       const double* beta, double* C, int64_t ldc,
                       hipStream_t stream);
+
+/* ------------------------------------------ learned slice-count selector */
+/* The paper's implementation has no automatic precision selection (it is
+ * named as missing, Sec. VI); this library predicts the smallest Scheme I
+ * slice count p meeting a componentwise tolerance with a small MLP
+ * (34 -> 64 -> 64 -> 8, ReLU, 8 ordinal heads "p > t") from exponent
+ * statistics gathered on the device, bounded by an a-priori error bound.
+ *
+ * Parameter layout (float32, OZK_SELECTOR_PARAMS values, weights [in][out]):
+ * W1[34][64], b1[64], W2[64][64], b2[64], W3[64][8], b3[8].
+ * Features: for A's rows and B's columns, the fractions of nonzero entries
+ * whose exponent deficit e_i - expo(a_ik) falls in the bins [0] [1] [2] [3]
+ * [4,6) [6,8) [8,12) [12,16) [16,24) [24,32) [32,48) [48,64) [64,96)
+ * [96,128) [128,256) [256,inf); then log2(K)/14 and -log10(tol)/16.
+ * Counters (int32, OZK_SELECTOR_COUNTERS): 16 + 16 bin counts, the largest
+ * deficit of A, of B.  Decision: p_net = 1 + #{t : sigmoid(z_t) > threshold}
+ * + margin; p_bound = smallest p whose a-priori bound is <= tol (9 if none);
+ * p = min(p_net, p_bound), or p_bound when no network is loaded or the
+ * features are outside the training range (K > 16384, tol outside
+ * [1e-16, 1e-5], any entry in the last deficit bin); clamped to [1, 8].
+ * info (device int32[4]): p, p_net (0 without network), p_bound, 1 if out
+ * of range. */
+
+/* Load selector parameters (HOST float array of OZK_SELECTOR_PARAMS) into
+ * the context (copied to device memory owned by the context). */
+ozk_status ozk_selector_load(ozk_ctx* ctx, const float* params, size_t n,
+                             float threshold, int margin);
+/* Exponent statistics and the selector decision for C = A B, all on the
+ * device: e[M], f[N] (the Scheme I row/column exponents), counters,
+ * info[4] and, if features is not NULL, the 34 features (float32). */
+ozk_status ozk_select(ozk_ctx* ctx, double tol, int64_t M, int64_t N,
+                      int64_t K, const double* A, int64_t lda, const double* B,
+                      int64_t ldb, int32_t* e, int32_t* f, int32_t* counters,
+                      int32_t* info, float* features, hipStream_t stream);
+/* Scheme I DGEMM with the slice count chosen on the device for tolerance
+ * `tol` (no host round trip; graph-capturable).  ws must hold
+ * ozk_workspace_size(ctx, OZK_OP_DGEMM, OZK_SCHEME1, M, N, K, 0) bytes;
+ * info (device int32[4], may be NULL) receives the decision. */
+ozk_status ozk_dgemm_auto(ozk_ctx* ctx, double tol, int64_t M, int64_t N,
+                          int64_t K, double alpha, const double* A,
+                          int64_t lda, const double* B, int64_t ldb,
+                          double beta, double* C, int64_t ldc, void* ws,
+                          size_t ws_bytes, int32_t* info, hipStream_t stream);
+
+/* Training kernels of the selector network (device float32 arrays; X is
+ * n x 34, Y n x 8 ordinal targets, logits n x 8).  ozk_mlp_grad writes the
+ * gradient of the mean binary cross-entropy into grad (OZK_SELECTOR_PARAMS)
+ * and the loss into *loss; ozk_mlp_adam applies one bias-corrected Adam
+ * step (beta1 0.9, beta2 0.999, eps 1e-8; step counts from 1). */
+ozk_status ozk_mlp_forward(ozk_ctx* ctx, const float* params, const float* X,
+                           int n, float* logits, hipStream_t stream);
+ozk_status ozk_mlp_grad(ozk_ctx* ctx, const float* params, const float* X,
+                        const float* Y, int n, float* grad, float* loss,
+                        hipStream_t stream);
+ozk_status ozk_mlp_adam(ozk_ctx* ctx, float* params, const float* grad,
+                        float* m, float* v, int step, float lr,
+                        hipStream_t stream);
+/* Check tool: double-double dot products of the n outputs (rows[i],
+ * cols[i]) of A B (device index arrays): hi + lo to about 2^-104 relative
+ * per term, absab = sum_k |a||b| (for componentwise errors).  An index
+ * outside [0, M) x [0, N) yields NaN in all three outputs. */
+ozk_status ozk_ref_dd(ozk_ctx* ctx, int64_t M, int64_t N, int64_t K,
+                      const double* A, int64_t lda, const double* B,
+                      int64_t ldb, int64_t n, const int64_t* rows,
+                      const int64_t* cols, double* hi, double* lo,
+                      double* absab, hipStream_t stream);
 
 /* ------------------------------------------------- batches of problems */
 

@@ -36,31 +36,36 @@ def deficit_bin(d: int) -> int:
     return b
 
 
-def _hist(X: np.ndarray, axis: int) -> np.ndarray:
-    """Fractions of the nonzero finite entries per deficit bin, deficits taken
-    against the max exponent of each row (axis=1) or column (axis=0)."""
+def deficit_counts(X, axis: int):
+    """Integer counts of the exponent deficits per bin and the largest
+    deficit.  Deficits are taken against the largest exponent of each row
+    (axis=1) or column (axis=0) over its nonzero entries; zero entries are
+    not counted, and a row (column) holding a non-finite entry contributes
+    nothing (its outputs are not finite whatever p is)."""
     X = np.asarray(X, np.float64)
-    fin = np.isfinite(X) & (X != 0)
-    _, ex = np.frexp(np.where(fin, X, 1.0))
-    ex = np.where(fin, ex, np.iinfo(np.int32).min)
+    if X.size == 0:
+        return np.zeros(N_BINS, np.int64), 0
+    fin = np.isfinite(X)
+    ok_line = fin.all(axis=axis, keepdims=True)
+    nz = fin & (X != 0) & ok_line
+    _, ex = np.frexp(np.where(nz, X, 1.0))
+    ex = np.where(nz, ex, np.iinfo(np.int32).min).astype(np.int64)
     emax = ex.max(axis=axis, keepdims=True)
-    d = (emax - ex)[fin]
-    counts = np.zeros(N_BINS)
-    for v in d.ravel():
-        counts[deficit_bin(int(v))] += 1
+    d = (emax - ex)[nz]
+    bins = np.searchsorted(np.asarray(BIN_EDGES), d, side="right") - 1
+    counts = np.bincount(bins, minlength=N_BINS).astype(np.int64)
+    return counts, int(d.max()) if d.size else 0
+
+
+def _hist(X, axis: int) -> np.ndarray:
+    """Fractions of the counted entries per deficit bin."""
+    counts, _ = deficit_counts(X, axis)
     n = counts.sum()
-    return counts / n if n else counts
+    return counts / n if n else counts.astype(np.float64)
 
 
-def max_deficit(X: np.ndarray, axis: int) -> int:
-    X = np.asarray(X, np.float64)
-    fin = np.isfinite(X) & (X != 0)
-    if not fin.any():
-        return 0
-    _, ex = np.frexp(np.where(fin, X, 1.0))
-    ex = np.where(fin, ex, np.iinfo(np.int32).min)
-    emax = ex.max(axis=axis, keepdims=True)
-    return int((emax - ex)[fin].max())
+def max_deficit(X, axis: int) -> int:
+    return deficit_counts(X, axis)[1]
 
 
 def features(A, B, tol: float) -> np.ndarray:
@@ -78,6 +83,8 @@ def bound(p: int, ra: int, rb: int) -> float:
       + dropped slice pairs (at most p-1 pairs per diagonal d >= p, each
         below 128^2 2^(-12-8d)): (p-1) 1.01 2^(2-8p) 2^(ra+rb+2),
     plus the final rounding 2^-53."""
+    if ra + rb + 2 > 1000:  # beyond any tolerance <= 1
+        return math.inf
     a = 2.0 ** (-(8 * p - 1)) * (2.0 ** (ra + 1) + 2.0 ** (rb + 1))
     a += 2.0 ** (-2 * (8 * p - 1)) * 2.0 ** (ra + rb + 2)
     a += (p - 1) * 1.01 * 2.0 ** (2 - 8 * p) * 2.0 ** (ra + rb + 2)

@@ -29,6 +29,8 @@ OZK_ROW_ALIGN = 256
 OZK_K_CHUNK = 32
 OZK_EXP_ZERO = -100000
 OZK_EXP_NONFINITE = 100000
+OZK_SELECTOR_PARAMS = 6920
+OZK_SELECTOR_COUNTERS = 34
 
 # every symbol include/ozk.h declares
 EXPORTS = (
@@ -36,7 +38,8 @@ EXPORTS = (
     "ozk_s1_packed_bytes", "ozk_s2_packed_bytes", "ozk_s1_k_split", "ozk_workspace_size",
     "ozk_dgemm", "ozk_zgemm_3m", "ozk_s1_split_rows", "ozk_s1_split_cols", "ozk_s1_gemm",
     "ozk_s1_diagonals", "ozk_s2_split_rows", "ozk_s2_split_cols", "ozk_s2_gemm_mod", "ozk_s2_crt",
-    "ozk_batch_plan_create", "ozk_gemm_batched", "ozk_batch_plan_destroy",
+    "ozk_selector_load", "ozk_select", "ozk_dgemm_auto", "ozk_mlp_forward", "ozk_mlp_grad", "ozk_mlp_adam",
+    "ozk_ref_dd", "ozk_batch_plan_create", "ozk_gemm_batched", "ozk_batch_plan_destroy",
 )
 
 
@@ -79,6 +82,13 @@ def _lib() -> ctypes.CDLL:
         "ozk_s2_split_cols": (I, [P, I, I, I64, I64, P, I64, P, P, P]),
         "ozk_s2_gemm_mod": (I, [P, I, I, I64, I64, I64, P, P, P, P]),
         "ozk_s2_crt": (I, [P, I, I, I64, I64, P, P, P, P, P, P, I64, P]),
+        "ozk_selector_load": (I, [P, P, SZ, ctypes.c_float, I]),
+        "ozk_select": (I, [P, D, I64, I64, I64, P, I64, P, I64, P, P, P, P, P, P]),
+        "ozk_dgemm_auto": (I, [P, D, I64, I64, I64, D, P, I64, P, I64, D, P, I64, P, SZ, P, P]),
+        "ozk_mlp_forward": (I, [P, P, P, I, P, P]),
+        "ozk_mlp_grad": (I, [P, P, P, P, I, P, P, P]),
+        "ozk_mlp_adam": (I, [P, P, P, P, P, I, ctypes.c_float, P]),
+        "ozk_ref_dd": (I, [P, I64, I64, I64, P, I64, P, I64, I64, P, P, P, P, P, P]),
         "ozk_batch_plan_create": (I, [P, I, I, I, I, P, ctypes.POINTER(P), ctypes.POINTER(SZ)]),
         "ozk_gemm_batched": (I, [P, P, P, SZ, P]),
         "ozk_batch_plan_destroy": (I, [P]),

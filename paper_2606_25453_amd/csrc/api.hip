@@ -16,6 +16,9 @@ struct ozk_ctx {
   int device;
   int last_arg;
   int64_t k_split_override;  // > 0: shorter K runs (testing the fold path)
+  float* sel_w;              // selector parameters on the device (or null)
+  float sel_threshold;
+  int sel_margin;
 };
 
 using ozk::round_up;
@@ -120,6 +123,7 @@ ozk_status ozk_create(ozk_ctx** ctx, int device) {
 }
 
 ozk_status ozk_destroy(ozk_ctx* ctx) {
+  if (ctx && ctx->sel_w) (void)hipFree(ctx->sel_w);
   free(ctx);
   return OZK_OK;
 }
@@ -149,6 +153,10 @@ ozk_status ozk_workspace_size(ozk_ctx* ctx, ozk_op op, ozk_scheme scheme, int64_
   if (!bytes) return fail(ctx, OZK_ERR_INVALID_ARG, 8);
   if (bad_dims(M, N, K)) return fail(ctx, OZK_ERR_INVALID_ARG, 4);
   if (op == OZK_OP_DGEMM && scheme == OZK_SCHEME1) {
+    if (p_or_s == 0) {
+      *bytes = s1_plan(ctx, OZK_MAX_P, M, N, K).total + 512;
+      return OZK_OK;
+    }
     if (p_or_s < 1 || p_or_s > OZK_MAX_P) return fail(ctx, OZK_ERR_UNSUPPORTED, 7);
     *bytes = s1_plan(ctx, p_or_s, M, N, K).total;
     return OZK_OK;
@@ -389,6 +397,136 @@ ozk_status ozk_s2_crt(ozk_ctx* ctx, int s, int complex_planes, int64_t M, int64_
   return hip_status(ctx, ozk::s2_crt(s, complex_planes != 0, M, N, Cres, sigma, tau, alpha, beta, C, ldc, stream));
 }
 
+ozk_status ozk_selector_load(ozk_ctx* ctx, const float* params, size_t n, float threshold, int margin) {
+  if (!ctx) return OZK_ERR_INVALID_ARG;
+  ctx->last_arg = 0;
+  if (!params || n != OZK_SELECTOR_PARAMS) return fail(ctx, OZK_ERR_INVALID_ARG, 2);
+  if (!(threshold > 0.f && threshold < 1.f)) return fail(ctx, OZK_ERR_INVALID_ARG, 4);
+  if (margin < 0 || margin > 8) return fail(ctx, OZK_ERR_INVALID_ARG, 5);
+  if (!ctx->sel_w && hipMalloc(&ctx->sel_w, sizeof(float) * OZK_SELECTOR_PARAMS) != hipSuccess) {
+    ctx->sel_w = nullptr;
+    return fail(ctx, OZK_ERR_HIP, 0);
+  }
+  if (hipMemcpy(ctx->sel_w, params, sizeof(float) * OZK_SELECTOR_PARAMS, hipMemcpyHostToDevice) != hipSuccess)
+    return fail(ctx, OZK_ERR_HIP, 0);
+  ctx->sel_threshold = threshold;
+  ctx->sel_margin = margin;
+  return OZK_OK;
+}
+
+static bool bad_tol(double tol) { return !(tol > 0.0 && tol < 1.0); }
+
+ozk_status ozk_select(ozk_ctx* ctx, double tol, int64_t M, int64_t N, int64_t K, const double* A, int64_t lda,
+                      const double* B, int64_t ldb, int32_t* e, int32_t* f, int32_t* counters, int32_t* info,
+                      float* features, hipStream_t stream) {
+  if (!ctx) return OZK_ERR_INVALID_ARG;
+  ctx->last_arg = 0;
+  if (bad_tol(tol)) return fail(ctx, OZK_ERR_INVALID_ARG, 2);
+  if (bad_dims(M, N, K)) return fail(ctx, OZK_ERR_INVALID_ARG, 3);
+  if (!A && M > 0 && K > 0) return fail(ctx, OZK_ERR_INVALID_ARG, 6);
+  if (lda < (K > 0 ? K : 1)) return fail(ctx, OZK_ERR_INVALID_ARG, 7);
+  if (!B && K > 0 && N > 0) return fail(ctx, OZK_ERR_INVALID_ARG, 8);
+  if (ldb < (N > 0 ? N : 1)) return fail(ctx, OZK_ERR_INVALID_ARG, 9);
+  if ((!e && M > 0) || (!f && N > 0)) return fail(ctx, OZK_ERR_INVALID_ARG, 10);
+  if (!counters) return fail(ctx, OZK_ERR_INVALID_ARG, 12);
+  if (!info) return fail(ctx, OZK_ERR_INVALID_ARG, 13);
+  hipError_t err = ozk::sel_features(A, lda, M, B, ldb, N, K, e, f, counters, stream);
+  if (err == hipSuccess)
+    err = ozk::sel_infer(counters, ctx->sel_w, ctx->sel_threshold, ctx->sel_margin, tol, K, info, features, stream);
+  return hip_status(ctx, err);
+}
+
+ozk_status ozk_dgemm_auto(ozk_ctx* ctx, double tol, int64_t M, int64_t N, int64_t K, double alpha, const double* A,
+                          int64_t lda, const double* B, int64_t ldb, double beta, double* C, int64_t ldc, void* ws,
+                          size_t ws_bytes, int32_t* info, hipStream_t stream) {
+  if (!ctx) return OZK_ERR_INVALID_ARG;
+  ctx->last_arg = 0;
+  if (bad_tol(tol)) return fail(ctx, OZK_ERR_INVALID_ARG, 2);
+  if (bad_dims(M, N, K)) return fail(ctx, OZK_ERR_INVALID_ARG, M < 0 ? 3 : (N < 0 ? 4 : 5));
+  if (!A && M > 0 && K > 0) return fail(ctx, OZK_ERR_INVALID_ARG, 7);
+  if (lda < (K > 0 ? K : 1)) return fail(ctx, OZK_ERR_INVALID_ARG, 8);
+  if (!B && K > 0 && N > 0) return fail(ctx, OZK_ERR_INVALID_ARG, 9);
+  if (ldb < (N > 0 ? N : 1)) return fail(ctx, OZK_ERR_INVALID_ARG, 10);
+  if (!C && M > 0 && N > 0) return fail(ctx, OZK_ERR_INVALID_ARG, 12);
+  if (ldc < (N > 0 ? N : 1)) return fail(ctx, OZK_ERR_INVALID_ARG, 13);
+  const S1Plan pl = s1_plan(ctx, OZK_MAX_P, M, N, K);
+  if (!ws || ws_bytes < pl.total + 512) return fail(ctx, OZK_ERR_WORKSPACE, 14);
+  if (M == 0 || N == 0) return OZK_OK;
+  char* w = (char*)ws;
+  int32_t* e = (int32_t*)(w + pl.off_e);
+  int32_t* f = (int32_t*)(w + pl.off_f);
+  int8_t* Ap = (int8_t*)(w + pl.off_a);
+  int8_t* Bp = (int8_t*)(w + pl.off_b);
+  int32_t* cnt = (int32_t*)(w + pl.total);
+  int32_t* inf = info ? info : (int32_t*)(w + pl.total + 256);
+  hipError_t err = ozk::sel_features(A, lda, M, B, ldb, N, K, e, f, cnt, stream);
+  if (err == hipSuccess)
+    err = ozk::sel_infer(cnt, ctx->sel_w, ctx->sel_threshold, ctx->sel_margin, tol, K, inf, nullptr, stream);
+  if (err == hipSuccess) err = ozk::s1_slice_auto(inf, A, lda, M, B, ldb, N, K, e, f, Ap, Bp, stream);
+  if (err != hipSuccess) return hip_status(ctx, err);
+  ozk::S1GemmArgs g;
+  g.M = M;
+  g.N = N;
+  g.Ap = Ap;
+  g.Bp = Bp;
+  g.nchunk = pl.nchunk;
+  g.steps_per_split = pl.nsplit > 1 ? pl.steps_per_split : (pl.nchunk > 0 ? pl.nchunk : 1);
+  g.nsplit = pl.nsplit;
+  g.e = e;
+  g.f = f;
+  g.alpha = alpha;
+  g.beta = beta;
+  g.C = C;
+  g.ldc = ldc;
+  g.zpart = pl.nsplit > 1 ? (int64_t*)(w + pl.off_z) : nullptr;
+  g.diag = nullptr;
+  return hip_status(ctx, ozk::s1_gemm_auto(inf, g, stream));
+}
+
+ozk_status ozk_mlp_forward(ozk_ctx* ctx, const float* params, const float* X, int n, float* logits,
+                           hipStream_t stream) {
+  if (!ctx) return OZK_ERR_INVALID_ARG;
+  ctx->last_arg = 0;
+  if (!params) return fail(ctx, OZK_ERR_INVALID_ARG, 2);
+  if (n < 0) return fail(ctx, OZK_ERR_INVALID_ARG, 4);
+  if (n > 0 && (!X || !logits)) return fail(ctx, OZK_ERR_INVALID_ARG, 3);
+  return hip_status(ctx, ozk::mlp_forward(params, X, n, logits, stream));
+}
+
+ozk_status ozk_mlp_grad(ozk_ctx* ctx, const float* params, const float* X, const float* Y, int n, float* grad,
+                        float* loss, hipStream_t stream) {
+  if (!ctx) return OZK_ERR_INVALID_ARG;
+  ctx->last_arg = 0;
+  if (!params) return fail(ctx, OZK_ERR_INVALID_ARG, 2);
+  if (n < 0) return fail(ctx, OZK_ERR_INVALID_ARG, 5);
+  if (n > 0 && (!X || !Y)) return fail(ctx, OZK_ERR_INVALID_ARG, 3);
+  if (!grad || !loss) return fail(ctx, OZK_ERR_INVALID_ARG, 6);
+  return hip_status(ctx, ozk::mlp_grad(params, X, Y, n, grad, loss, stream));
+}
+
+ozk_status ozk_mlp_adam(ozk_ctx* ctx, float* params, const float* grad, float* m, float* v, int step, float lr,
+                        hipStream_t stream) {
+  if (!ctx) return OZK_ERR_INVALID_ARG;
+  ctx->last_arg = 0;
+  if (!params || !grad || !m || !v) return fail(ctx, OZK_ERR_INVALID_ARG, 2);
+  if (step < 1) return fail(ctx, OZK_ERR_INVALID_ARG, 6);
+  if (!(lr > 0.f)) return fail(ctx, OZK_ERR_INVALID_ARG, 7);
+  return hip_status(ctx, ozk::mlp_adam(params, grad, m, v, step, lr, stream));
+}
+
+ozk_status ozk_ref_dd(ozk_ctx* ctx, int64_t M, int64_t N, int64_t K, const double* A, int64_t lda, const double* B,
+                      int64_t ldb, int64_t n, const int64_t* rows, const int64_t* cols, double* hi, double* lo,
+                      double* absab, hipStream_t stream) {
+  if (!ctx) return OZK_ERR_INVALID_ARG;
+  ctx->last_arg = 0;
+  if (bad_dims(M, N, K)) return fail(ctx, OZK_ERR_INVALID_ARG, 2);
+  if (lda < (K > 0 ? K : 1)) return fail(ctx, OZK_ERR_INVALID_ARG, 6);
+  if (ldb < (N > 0 ? N : 1)) return fail(ctx, OZK_ERR_INVALID_ARG, 8);
+  if (n < 0) return fail(ctx, OZK_ERR_INVALID_ARG, 9);
+  if (n > 0 && (!A || !B || !rows || !cols || !hi || !lo || !absab)) return fail(ctx, OZK_ERR_INVALID_ARG, 10);
+  return hip_status(ctx, ozk::ref_dd(M, N, K, A, lda, B, ldb, n, rows, cols, hi, lo, absab, stream));
+}
+
 struct ozk_batch_plan {
   int device;
   ozk_op op;
@@ -500,7 +638,7 @@ ozk_status ozk_batch_plan_create(ozk_ctx* ctx, ozk_op op, ozk_scheme scheme, int
   off += align256(npre);  // spare
   void* r6 = put(order.data(), sizeof(int32_t) * count);
   if ((count > 0 && (!pp || !r6)) || !r1 || !r2 || !r3 || !r4 || !r5) {
-    hipFree(pl->dev);
+    (void)hipFree(pl->dev);
     free(pl);
     return fail(ctx, OZK_ERR_HIP, 0);
   }
@@ -535,7 +673,7 @@ ozk_status ozk_gemm_batched(ozk_ctx* ctx, const ozk_batch_plan* plan, void* ws, 
 
 ozk_status ozk_batch_plan_destroy(ozk_batch_plan* plan) {
   if (!plan) return OZK_OK;
-  if (plan->dev) hipFree(plan->dev);
+  if (plan->dev) (void)hipFree(plan->dev);
   free(plan);
   return OZK_OK;
 }

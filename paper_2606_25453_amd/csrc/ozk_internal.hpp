@@ -30,6 +30,11 @@ hipError_t s1_split_rows(int p, const double* X, int64_t ldx, int64_t rows, int6
 hipError_t s1_split_cols(int p, const double* X, int64_t ldx, int64_t K, int64_t cols, int32_t* f,
                          int8_t* packed, hipStream_t st);
 hipError_t s1_gemm(int p, const S1GemmArgs& g, hipStream_t st);
+// slice count read from device memory (selector output)
+hipError_t s1_slice_auto(const int32_t* p_dev, const double* A, int64_t lda, int64_t M, const double* B, int64_t ldb,
+                         int64_t N, int64_t K, const int32_t* e, const int32_t* f, int8_t* Ap, int8_t* Bp,
+                         hipStream_t st);
+hipError_t s1_gemm_auto(const int32_t* p_dev, const S1GemmArgs& g, hipStream_t st);
 
 // One problem of a batch; workspace parts are byte offsets from the
 // workspace base passed to each launch.
@@ -68,6 +73,17 @@ int s2_batch_gemm_blocks_per_cu(bool cplx);
 int64_t s2_tile_count(bool cplx, int64_t M, int64_t N);
 
 void s2_targets(int s, int& ta, int& tb);
+
+hipError_t sel_features(const double* A, int64_t lda, int64_t M, const double* B, int64_t ldb, int64_t N, int64_t K,
+                        int32_t* e, int32_t* f, int32_t* cnt, hipStream_t st);
+hipError_t sel_infer(const int32_t* cnt, const float* w, float threshold, int margin, double tol, int64_t K,
+                     int32_t* info, float* feat, hipStream_t st);
+hipError_t mlp_forward(const float* w, const float* X, int n, float* logits, hipStream_t st);
+hipError_t mlp_grad(const float* w, const float* X, const float* Y, int n, float* grad, float* loss, hipStream_t st);
+hipError_t mlp_adam(float* w, const float* g, float* m, float* v, int step, float lr, hipStream_t st);
+hipError_t ref_dd(int64_t M, int64_t N, int64_t K, const double* A, int64_t lda, const double* B, int64_t ldb,
+                  int64_t n, const int64_t* rows, const int64_t* cols, double* hi, double* lo, double* absab,
+                  hipStream_t st);
 hipError_t s2_split_rows(int s, bool cplx, const double* X, int64_t ldx, int64_t rows, int64_t K, int32_t* sigma,
                          int8_t* packed, hipStream_t st);
 hipError_t s2_split_cols(int s, bool cplx, const double* X, int64_t ldx, int64_t K, int64_t cols, int32_t* tau,

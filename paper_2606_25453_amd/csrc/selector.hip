@@ -1,0 +1,391 @@
+// Learned slice-count selector for Scheme I and the tools it is trained with.
+//
+// The paper's implementation has no automatic precision selection (it names
+// the runtime estimate of the slice count as missing, Sec. VI).  Here a small
+// MLP predicts the smallest p meeting a tolerance from exponent statistics
+// gathered in the pre-pass, on the device, so that the emulated GEMM stays a
+// stream-ordered, graph-capturable sequence:
+//
+//   k_sel_rows / k_sel_cols  row / column exponents (also the Scheme I scales)
+//                            and histograms of the exponent deficits
+//                            e_i - expo(a_ik) over 16 bins, plus the largest
+//                            deficit (for the a-priori bound)
+//   k_sel_infer              features -> MLP 34 -> 64 -> 64 -> 8 (ReLU) ->
+//                            ordinal decision p = 1 + #{t : sigmoid(z_t) > thr}
+//                            + margin; the a-priori bound p_b; p = min(p, p_b),
+//                            or p_b when the features are outside the training
+//                            range; written to device memory
+//   k_mlp_forward / k_mlp_grad / k_mlp_adam   training kernels (FP32)
+//   k_ref_dd                 double-double dot products of chosen outputs
+//                            (labels and accuracy measurement)
+#include "ozk_device.hpp"
+#include "ozk_internal.hpp"
+
+namespace ozk {
+
+constexpr int SEL_BINS = 16, SEL_FEAT = 34, SEL_H = 64, SEL_OUT = 8;
+constexpr int OFF_W1 = 0, OFF_B1 = OFF_W1 + SEL_FEAT * SEL_H, OFF_W2 = OFF_B1 + SEL_H,
+              OFF_B2 = OFF_W2 + SEL_H * SEL_H, OFF_W3 = OFF_B2 + SEL_H, OFF_B3 = OFF_W3 + SEL_H * SEL_OUT,
+              SEL_NPARAM = OFF_B3 + SEL_OUT;  // 6920
+static_assert(SEL_NPARAM == OZK_SELECTOR_PARAMS, "parameter count");
+
+// bins: [0] [1] [2] [3] [4,6) [6,8) [8,12) [12,16) [16,24) [24,32) [32,48)
+// [48,64) [64,96) [96,128) [128,256) [256,inf)
+__device__ __forceinline__ int deficit_bin(int d) {
+  if (d < 4) return d;
+  if (d < 8) return d < 6 ? 4 : 5;
+  if (d < 16) return d < 12 ? 6 : 7;
+  if (d < 32) return d < 24 ? 8 : 9;
+  if (d < 64) return d < 48 ? 10 : 11;
+  if (d < 128) return d < 96 ? 12 : 13;
+  return d < 256 ? 14 : 15;
+}
+
+// counters: [0,16) A histogram, [16,32) B histogram, [32] max deficit of A,
+// [33] max deficit of B.
+__global__ void k_sel_zero(int32_t* __restrict__ cnt) {
+  if (threadIdx.x < OZK_SELECTOR_COUNTERS) cnt[threadIdx.x] = 0;
+}
+
+// One wave per row: the row exponent (written to e_out), then the deficit
+// histogram of the row's nonzero entries.
+__global__ __launch_bounds__(256) void k_sel_rows(const double* __restrict__ X, int64_t ldx, int64_t rows,
+                                                  int64_t K, int32_t* __restrict__ e_out,
+                                                  int32_t* __restrict__ cnt) {
+  __shared__ int h[SEL_BINS];
+  __shared__ int md;
+  if (threadIdx.x < SEL_BINS) h[threadIdx.x] = 0;
+  if (threadIdx.x == 0) md = 0;
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (r < rows) {
+    const double* xr = X + r * ldx;
+    int e = OZK_EXP_ZERO;
+    for (int64_t k = lane; k < K; k += 64) {
+      const int ek = expo_of(xr[k]);
+      e = ek > e ? ek : e;
+    }
+    e = wave_max(e);
+    if (lane == 0) e_out[r] = e;
+    int dmax = 0;
+    if (e != OZK_EXP_ZERO && e != OZK_EXP_NONFINITE) {
+      for (int64_t k = lane; k < K; k += 64) {
+        const int ek = expo_of(xr[k]);
+        if (ek == OZK_EXP_ZERO) continue;
+        const int d = e - ek;
+        atomicAdd(&h[deficit_bin(d)], 1);
+        dmax = d > dmax ? d : dmax;
+      }
+    }
+    dmax = wave_max(dmax);
+    if (lane == 0) atomicMax(&md, dmax);
+  }
+  __syncthreads();
+  if (threadIdx.x < SEL_BINS && h[threadIdx.x]) atomicAdd(&cnt[threadIdx.x], h[threadIdx.x]);
+  if (threadIdx.x == 0 && md) atomicMax(&cnt[32], md);
+}
+
+// 32 columns x 8 k-groups per block: column exponents (written to f_out),
+// then the deficit histogram.
+__global__ __launch_bounds__(256) void k_sel_cols(const double* __restrict__ X, int64_t ldx, int64_t K,
+                                                  int64_t cols, int32_t* __restrict__ f_out,
+                                                  int32_t* __restrict__ cnt) {
+  __shared__ int red[8][32];
+  __shared__ int h[SEL_BINS];
+  __shared__ int md;
+  const int cl = threadIdx.x & 31, g = threadIdx.x >> 5;
+  const int64_t j = (int64_t)blockIdx.x * 32 + cl;
+  const bool in = j < cols;
+  if (threadIdx.x < SEL_BINS) h[threadIdx.x] = 0;
+  if (threadIdx.x == 0) md = 0;
+  int e = OZK_EXP_ZERO;
+  if (in)
+    for (int64_t k = g; k < K; k += 8) {
+      const int ek = expo_of(X[k * ldx + j]);
+      e = ek > e ? ek : e;
+    }
+  red[g][cl] = e;
+  __syncthreads();
+  int emax = red[0][cl];
+#pragma unroll
+  for (int i = 1; i < 8; ++i) emax = red[i][cl] > emax ? red[i][cl] : emax;
+  if (in && g == 0) f_out[j] = emax;
+  int dmax = 0;
+  if (in && emax != OZK_EXP_ZERO && emax != OZK_EXP_NONFINITE)
+    for (int64_t k = g; k < K; k += 8) {
+      const int ek = expo_of(X[k * ldx + j]);
+      if (ek == OZK_EXP_ZERO) continue;
+      const int d = emax - ek;
+      atomicAdd(&h[deficit_bin(d)], 1);
+      dmax = d > dmax ? d : dmax;
+    }
+  dmax = wave_max(dmax);
+  if ((threadIdx.x & 63) == 0 && dmax) atomicMax(&md, dmax);
+  __syncthreads();
+  if (threadIdx.x < SEL_BINS && h[threadIdx.x]) atomicAdd(&cnt[SEL_BINS + threadIdx.x], h[threadIdx.x]);
+  if (threadIdx.x == 0 && md) atomicMax(&cnt[33], md);
+}
+
+// A-priori componentwise error bound of Scheme I with p balanced slices for
+// entries at most ra (rb) exponent steps below their row (column) maximum:
+// rounding to 8p-2 bits (<= 2^-(8p-1) of the scale) on both operands, the
+// dropped slice pairs (at most p-1 per diagonal d >= p, each below
+// 128^2 2^(-12-8d)) and the final rounding 2^-53.
+__device__ __forceinline__ double s1_bound(int p, int ra, int rb) {
+  if (ra + rb + 2 > 1000) return __builtin_inf();
+  double a = ldexp(1.0, -(8 * p - 1)) * (ldexp(1.0, ra + 1) + ldexp(1.0, rb + 1));
+  a += ldexp(1.0, -2 * (8 * p - 1)) * ldexp(1.0, ra + rb + 2);
+  a += (double)(p - 1) * 1.01 * ldexp(1.0, 2 - 8 * p) * ldexp(1.0, ra + rb + 2);
+  return a + ldexp(1.0, -53);
+}
+
+struct SelInfer {
+  const float* w;  // device parameters, null = no network (bound only)
+  float threshold;
+  int margin;
+  double tol;
+  int64_t K;
+};
+
+// out[0] p used, [1] p from the network (0 if none), [2] p from the bound
+// (9 = none up to 8), [3] 1 when the features were outside the training range.
+__global__ __launch_bounds__(64) void k_sel_infer(const int32_t* __restrict__ cnt, SelInfer si,
+                                                  int32_t* __restrict__ out, float* __restrict__ feat_out) {
+  __shared__ float x[SEL_FEAT], h1[SEL_H], h2[SEL_H], z[SEL_OUT];
+  __shared__ float tot[2];
+  const int t = threadIdx.x;
+  if (t < 2) {
+    long long n = 0;
+    for (int i = 0; i < SEL_BINS; ++i) n += cnt[t * SEL_BINS + i];
+    tot[t] = (float)n;
+  }
+  __syncthreads();
+  if (t < 2 * SEL_BINS) {
+    const float n = tot[t / SEL_BINS];
+    x[t] = n > 0.f ? (float)cnt[t] / n : 0.f;
+  }
+  if (t == 0) {
+    x[32] = (float)(log2((double)(si.K > 0 ? si.K : 1)) / 14.0);
+    x[33] = (float)(-log10(si.tol) / 16.0);
+  }
+  __syncthreads();
+  if (feat_out && t < SEL_FEAT) feat_out[t] = x[t];
+  int p_net = 0;
+  if (si.w) {
+    float a = si.w[OFF_B1 + t];
+    for (int i = 0; i < SEL_FEAT; ++i) a += si.w[OFF_W1 + i * SEL_H + t] * x[i];
+    h1[t] = a > 0.f ? a : 0.f;
+    __syncthreads();
+    a = si.w[OFF_B2 + t];
+    for (int i = 0; i < SEL_H; ++i) a += si.w[OFF_W2 + i * SEL_H + t] * h1[i];
+    h2[t] = a > 0.f ? a : 0.f;
+    __syncthreads();
+    if (t < SEL_OUT) {
+      a = si.w[OFF_B3 + t];
+      for (int i = 0; i < SEL_H; ++i) a += si.w[OFF_W3 + i * SEL_OUT + t] * h2[i];
+      z[t] = a;
+    }
+    __syncthreads();
+    int c = 0;
+    for (int i = 0; i < SEL_OUT; ++i) c += (1.f / (1.f + expf(-z[i]))) > si.threshold ? 1 : 0;
+    p_net = 1 + c + si.margin;
+    p_net = p_net > 9 ? 9 : p_net;
+  }
+  if (t == 0) {
+    int pb = 9;
+    for (int p = 1; p <= 8; ++p)
+      if (s1_bound(p, cnt[32], cnt[33]) <= si.tol) {
+        pb = p;
+        break;
+      }
+    // outside the training range: K beyond 2^14, tolerance outside
+    // [1e-16, 1e-5], or mass in the last deficit bin
+    const bool ood = si.K > 16384 || si.tol < 1e-16 || si.tol > 1e-5 || x[15] > 0.f || x[31] > 0.f;
+    int p = pb;
+    if (si.w && !ood) p = p_net < pb ? p_net : pb;
+    p = p < 1 ? 1 : (p > 8 ? 8 : p);
+    out[0] = p;
+    out[1] = p_net;
+    out[2] = pb;
+    out[3] = ood ? 1 : 0;
+  }
+}
+
+// ------------------------------------------------------------- training
+
+__device__ __forceinline__ void mlp_layers(const float* __restrict__ w, const float* __restrict__ xin, float* x,
+                                           float* z1, float* h1, float* z2, float* h2, float* out) {
+  const int t = threadIdx.x;
+  if (t < SEL_FEAT) x[t] = xin[t];
+  __syncthreads();
+  float a = w[OFF_B1 + t];
+  for (int i = 0; i < SEL_FEAT; ++i) a += w[OFF_W1 + i * SEL_H + t] * x[i];
+  z1[t] = a;
+  h1[t] = a > 0.f ? a : 0.f;
+  __syncthreads();
+  a = w[OFF_B2 + t];
+  for (int i = 0; i < SEL_H; ++i) a += w[OFF_W2 + i * SEL_H + t] * h1[i];
+  z2[t] = a;
+  h2[t] = a > 0.f ? a : 0.f;
+  __syncthreads();
+  if (t < SEL_OUT) {
+    a = w[OFF_B3 + t];
+    for (int i = 0; i < SEL_H; ++i) a += w[OFF_W3 + i * SEL_OUT + t] * h2[i];
+    out[t] = a;
+  }
+  __syncthreads();
+}
+
+// One block of 64 threads per sample.
+__global__ __launch_bounds__(64) void k_mlp_forward(const float* __restrict__ w, const float* __restrict__ X, int n,
+                                                    float* __restrict__ logits) {
+  __shared__ float x[SEL_FEAT], z1[SEL_H], h1[SEL_H], z2[SEL_H], h2[SEL_H], out[SEL_OUT];
+  const int s = blockIdx.x;
+  if (s >= n) return;
+  mlp_layers(w, X + (int64_t)s * SEL_FEAT, x, z1, h1, z2, h2, out);
+  if (threadIdx.x < SEL_OUT) logits[(int64_t)s * SEL_OUT + threadIdx.x] = out[threadIdx.x];
+}
+
+// Gradient of the mean binary cross-entropy over samples and the 8 ordinal
+// heads, accumulated into grad (zeroed beforehand); loss sum into *loss.
+__global__ __launch_bounds__(64) void k_mlp_grad(const float* __restrict__ w, const float* __restrict__ X,
+                                                 const float* __restrict__ Y, int n, float* __restrict__ grad,
+                                                 float* __restrict__ loss) {
+  __shared__ float x[SEL_FEAT], z1[SEL_H], h1[SEL_H], z2[SEL_H], h2[SEL_H], out[SEL_OUT];
+  __shared__ float go[SEL_OUT], gz2[SEL_H];
+  const int s = blockIdx.x, t = threadIdx.x;
+  if (s >= n) return;
+  mlp_layers(w, X + (int64_t)s * SEL_FEAT, x, z1, h1, z2, h2, out);
+  const float scale = 1.f / ((float)n * SEL_OUT);
+  if (t < SEL_OUT) {
+    const float y = Y[(int64_t)s * SEL_OUT + t], zz = out[t];
+    const float sg = 1.f / (1.f + expf(-zz));
+    go[t] = (sg - y) * scale;
+    const float l = fmaxf(zz, 0.f) - zz * y + log1pf(expf(-fabsf(zz)));
+    atomicAdd(loss, l * scale);
+    atomicAdd(&grad[OFF_B3 + t], go[t]);
+  }
+  __syncthreads();
+  // layer 3 weights and the gradient at z2 (thread t = hidden unit)
+  float gh2 = 0.f;
+  for (int o = 0; o < SEL_OUT; ++o) {
+    atomicAdd(&grad[OFF_W3 + t * SEL_OUT + o], h2[t] * go[o]);
+    gh2 += w[OFF_W3 + t * SEL_OUT + o] * go[o];
+  }
+  gz2[t] = z2[t] > 0.f ? gh2 : 0.f;
+  __syncthreads();
+  atomicAdd(&grad[OFF_B2 + t], gz2[t]);
+  for (int i = 0; i < SEL_H; ++i) atomicAdd(&grad[OFF_W2 + i * SEL_H + t], h1[i] * gz2[t]);
+  // gradient at z1 (thread t = layer-1 unit)
+  float gh1 = 0.f;
+  for (int j = 0; j < SEL_H; ++j) gh1 += w[OFF_W2 + t * SEL_H + j] * gz2[j];
+  const float gz1 = z1[t] > 0.f ? gh1 : 0.f;
+  atomicAdd(&grad[OFF_B1 + t], gz1);
+  for (int i = 0; i < SEL_FEAT; ++i) atomicAdd(&grad[OFF_W1 + i * SEL_H + t], x[i] * gz1);
+}
+
+__global__ void k_fill_f32(float* __restrict__ p, int64_t n, float v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// Adam with bias correction; c1 = 1 - beta1^t, c2 = 1 - beta2^t.
+__global__ void k_mlp_adam(float* __restrict__ w, const float* __restrict__ g, float* __restrict__ m,
+                           float* __restrict__ v, int n, float lr, float beta1, float beta2, float eps, float c1,
+                           float c2) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float mi = beta1 * m[i] + (1.f - beta1) * g[i];
+  const float vi = beta2 * v[i] + (1.f - beta2) * g[i] * g[i];
+  m[i] = mi;
+  v[i] = vi;
+  w[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// ------------------------------------------------- double-double reference
+
+__device__ __forceinline__ void dd_two_sum(double a, double b, double& s, double& e) {
+  s = a + b;
+  const double bb = s - a;
+  e = (a - (s - bb)) + (b - bb);
+}
+
+// Thread per chosen output (rows[i], cols[i]): hi + lo ~ sum_k a b with
+// error-free products and sums, absab = sum_k |a||b|.
+__global__ __launch_bounds__(256) void k_ref_dd(int64_t M, int64_t N, int64_t K, const double* __restrict__ A,
+                                                int64_t lda, const double* __restrict__ B, int64_t ldb, int64_t n,
+                                                const int64_t* __restrict__ rows, const int64_t* __restrict__ cols,
+                                                double* __restrict__ hi, double* __restrict__ lo,
+                                                double* __restrict__ absab) {
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= n) return;
+  const int64_t i = rows[idx], j = cols[idx];
+  if (i < 0 || i >= M || j < 0 || j >= N) {  // an index outside the matrix gives NaN
+    hi[idx] = lo[idx] = absab[idx] = __builtin_nan("");
+    return;
+  }
+  double h = 0.0, l = 0.0, ab = 0.0;
+  for (int64_t k = 0; k < K; ++k) {
+    const double a = A[i * lda + k], b = B[k * ldb + j];
+    const double p = a * b;
+    const double pe = __fma_rn(a, b, -p);
+    double s, e;
+    dd_two_sum(h, p, s, e);
+    e += l + pe;
+    h = s + e;
+    l = e - (h - s);
+    ab += fabs(a) * fabs(b);
+  }
+  hi[idx] = h;
+  lo[idx] = l;
+  absab[idx] = ab;
+}
+
+// ------------------------------------------------------------ launchers
+
+hipError_t sel_features(const double* A, int64_t lda, int64_t M, const double* B, int64_t ldb, int64_t N, int64_t K,
+                        int32_t* e, int32_t* f, int32_t* cnt, hipStream_t st) {
+  hipLaunchKernelGGL(k_sel_zero, dim3(1), dim3(64), 0, st, cnt);
+  if (M > 0) hipLaunchKernelGGL(k_sel_rows, dim3((unsigned)((M + 3) / 4)), dim3(256), 0, st, A, lda, M, K, e, cnt);
+  if (N > 0) hipLaunchKernelGGL(k_sel_cols, dim3((unsigned)((N + 31) / 32)), dim3(256), 0, st, B, ldb, K, N, f, cnt);
+  return hipGetLastError();
+}
+
+hipError_t sel_infer(const int32_t* cnt, const float* w, float threshold, int margin, double tol, int64_t K,
+                     int32_t* info, float* feat, hipStream_t st) {
+  SelInfer si{w, threshold, margin, tol, K};
+  hipLaunchKernelGGL(k_sel_infer, dim3(1), dim3(64), 0, st, cnt, si, info, feat);
+  return hipGetLastError();
+}
+
+hipError_t mlp_forward(const float* w, const float* X, int n, float* logits, hipStream_t st) {
+  if (n > 0) hipLaunchKernelGGL(k_mlp_forward, dim3((unsigned)n), dim3(64), 0, st, w, X, n, logits);
+  return hipGetLastError();
+}
+
+hipError_t mlp_grad(const float* w, const float* X, const float* Y, int n, float* grad, float* loss, hipStream_t st) {
+  hipLaunchKernelGGL(k_fill_f32, dim3((SEL_NPARAM + 255) / 256), dim3(256), 0, st, grad, (int64_t)SEL_NPARAM, 0.f);
+  hipLaunchKernelGGL(k_fill_f32, dim3(1), dim3(64), 0, st, loss, (int64_t)1, 0.f);
+  if (n > 0) hipLaunchKernelGGL(k_mlp_grad, dim3((unsigned)n), dim3(64), 0, st, w, X, Y, n, grad, loss);
+  return hipGetLastError();
+}
+
+hipError_t mlp_adam(float* w, const float* g, float* m, float* v, int step, float lr, hipStream_t st) {
+  const float b1 = 0.9f, b2 = 0.999f;
+  const float c1 = 1.f - powf(b1, (float)step), c2 = 1.f - powf(b2, (float)step);
+  hipLaunchKernelGGL(k_mlp_adam, dim3((SEL_NPARAM + 255) / 256), dim3(256), 0, st, w, g, m, v, SEL_NPARAM, lr, b1,
+                     b2, 1e-8f, c1, c2);
+  return hipGetLastError();
+}
+
+hipError_t ref_dd(int64_t M, int64_t N, int64_t K, const double* A, int64_t lda, const double* B, int64_t ldb,
+                  int64_t n, const int64_t* rows, const int64_t* cols, double* hi, double* lo, double* absab,
+                  hipStream_t st) {
+  if (n > 0)
+    hipLaunchKernelGGL(k_ref_dd, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, M, N, K, A, lda, B, ldb, n,
+                       rows, cols, hi, lo, absab);
+  return hipGetLastError();
+}
+
+}  // namespace ozk

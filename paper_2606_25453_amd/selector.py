@@ -1,0 +1,271 @@
+"""Training and loading of the learned slice-count selector (Scheme I).
+
+Everything numeric runs on the GPU through the library's C ABI:
+* problems: synthetic (u - 0.5) exp(phi g) matrices with phi ~ U(0, 4) for A
+  and B independently and M, N, K log-uniform (the paper's generator,
+  Sec. V-B, Eq. 19, with random conditioning);
+* labels: the componentwise error of the emulated product for p = 1..8
+  against the double-double reference kernel, E_cw(p) = max |C_p - C_dd| /
+  (|A||B|), and the smallest p with E_cw(p) <= tol (9 if none), for four
+  tolerances per problem drawn log-uniformly in [1e-16, 1e-5];
+* features: the selector's own exponent-statistics kernels;
+* training: the library's MLP forward / gradient / Adam kernels.
+PyTorch only allocates and fills device memory and does the small
+element-wise bookkeeping around those calls.
+
+The trained parameters ship as selector_weights.json next to this file.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+from typing import Dict, List, Tuple
+
+import paper_2606_25453_amd as ozk
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+WEIGHTS = os.path.join(HERE, "selector_weights.json")
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def random_problem(gen, M: int, N: int, K: int, phi_a: float, phi_b: float, device):
+    torch = _torch()
+    a = (torch.rand((M, K), generator=gen, device=device, dtype=torch.float64) - 0.5) * torch.exp(
+        phi_a * torch.randn((M, K), generator=gen, device=device, dtype=torch.float64))
+    b = (torch.rand((K, N), generator=gen, device=device, dtype=torch.float64) - 0.5) * torch.exp(
+        phi_b * torch.randn((K, N), generator=gen, device=device, dtype=torch.float64))
+    return a, b
+
+
+def dd_reference(ctx, A, B, rows=None, cols=None):
+    """(hi, lo, absab) for all outputs, or for the listed ones."""
+    torch = _torch()
+    M, K = A.shape
+    N = B.shape[1]
+    if rows is None:
+        ii, jj = torch.meshgrid(torch.arange(M, device=A.device), torch.arange(N, device=A.device), indexing="ij")
+        rows, cols = ii.reshape(-1).contiguous(), jj.reshape(-1).contiguous()
+    n = rows.numel()
+    hi = torch.empty(n, dtype=torch.float64, device=A.device)
+    lo = torch.empty_like(hi)
+    ab = torch.empty_like(hi)
+    st = ozk.library().ozk_ref_dd(ctx.handle, M, N, K, A.data_ptr(), ozk._ld(A), B.data_ptr(), ozk._ld(B), n,
+                                  rows.data_ptr(), cols.data_ptr(), hi.data_ptr(), lo.data_ptr(), ab.data_ptr(),
+                                  ozk._stream(None))
+    ozk._check("ozk_ref_dd", st, ctx)
+    return hi, lo, ab
+
+
+def e_cw(C, hi, lo, ab) -> float:
+    """max |C - hi - lo| / (|A||B|) over entries with a nonzero scale."""
+    torch = _torch()
+    err = ((C.reshape(-1) - hi) - lo).abs()
+    ok = (ab > 0) & torch.isfinite(err)
+    if not bool(ok.any()):
+        return 0.0
+    return float((err[ok] / ab[ok]).max())
+
+
+def error_curve(ctx, A, B) -> List[float]:
+    """E_cw of Scheme I for p = 1..8 on one problem."""
+    hi, lo, ab = dd_reference(ctx, A, B)
+    return [e_cw(ozk.ozk_dgemm(ctx, ozk.OZK_SCHEME1, p, A, B), hi, lo, ab) for p in range(1, 9)]
+
+
+def label_from_curve(curve: List[float], tol: float) -> int:
+    for p, err in enumerate(curve, start=1):
+        if err <= tol:
+            return p
+    return 9
+
+
+def features(ctx, A, B, tol: float):
+    """(34 features, info[4]) from the selector's own device kernels."""
+    torch = _torch()
+    M, K = A.shape
+    N = B.shape[1]
+    dev = A.device
+    e = torch.empty(max(M, 1), dtype=torch.int32, device=dev)
+    f = torch.empty(max(N, 1), dtype=torch.int32, device=dev)
+    cnt = torch.empty(34, dtype=torch.int32, device=dev)
+    info = torch.empty(4, dtype=torch.int32, device=dev)
+    feat = torch.empty(34, dtype=torch.float32, device=dev)
+    st = ozk.library().ozk_select(ctx.handle, float(tol), M, N, K, A.data_ptr(), ozk._ld(A), B.data_ptr(), ozk._ld(B),
+                                  e.data_ptr(), f.data_ptr(), cnt.data_ptr(), info.data_ptr(), feat.data_ptr(),
+                                  ozk._stream(None))
+    ozk._check("ozk_select", st, ctx)
+    return feat, info, cnt
+
+
+def build_dataset(ctx, count: int, seed: int, lo: int = 64, hi: int = 768, tols_per_problem: int = 4,
+                  device="cuda:0"):
+    """Features (n x 34), labels (n) and bound decisions for `count` random
+    problems, each used at `tols_per_problem` tolerances drawn log-uniformly
+    in [1e-16, 1e-5] (the range the selector is trusted in)."""
+    torch = _torch()
+    host_gen = torch.Generator().manual_seed(seed)
+    gen = torch.Generator(device=device).manual_seed(seed)
+    X, labels, bounds, curves = [], [], [], []
+    log_lo, log_hi = math.log(lo), math.log(hi + 1)
+    for i in range(count):
+        if i % 250 == 0:
+            print("dataset seed %d: problem %d of %d" % (seed, i, count), flush=True)
+        u = torch.rand(3 + 2 + tols_per_problem, generator=host_gen, dtype=torch.float64).tolist()
+        M, N, K = (int(math.exp(log_lo + (log_hi - log_lo) * v)) for v in u[:3])
+        phi_a, phi_b = 4.0 * u[3], 4.0 * u[4]
+        A, B = random_problem(gen, M, N, K, phi_a, phi_b, device)
+        curve = error_curve(ctx, A, B)
+        curves.append((M, N, K, phi_a, phi_b, curve))
+        for v in u[5:]:
+            tol = 10.0 ** (-16.0 + 11.0 * v)
+            feat, info, _ = features(ctx, A, B, tol)
+            X.append(feat.clone())
+            labels.append(label_from_curve(curve, tol))
+            bounds.append(int(info[2]))
+    return torch.stack(X), torch.tensor(labels, dtype=torch.int64), torch.tensor(bounds, dtype=torch.int64), curves
+
+
+def ordinal_targets(labels):
+    torch = _torch()
+    t = torch.arange(1, 9, device=labels.device).reshape(1, -1)
+    return (labels.reshape(-1, 1) > t).to(torch.float32)
+
+
+def init_params(seed: int, device):
+    torch = _torch()
+    g = torch.Generator(device="cpu").manual_seed(seed)
+    shapes = [(34, 64), (64,), (64, 64), (64,), (64, 8), (8,)]
+    parts = []
+    for sh in shapes:
+        if len(sh) == 2:
+            parts.append((torch.randn(sh, generator=g) * math.sqrt(2.0 / sh[0])).reshape(-1))
+        else:
+            parts.append(torch.zeros(sh))
+    return torch.cat(parts).to(torch.float32).to(device).contiguous()
+
+
+def train(ctx, X, labels, steps: int = 3000, batch: int = 256, lr: float = 3e-3, seed: int = 0):
+    """Mini-batch Adam on the ordinal cross-entropy with the library kernels."""
+    torch = _torch()
+    dev = X.device
+    Y = ordinal_targets(labels.to(dev))
+    w = init_params(seed, dev)
+    m = torch.zeros_like(w)
+    v = torch.zeros_like(w)
+    g = torch.empty_like(w)
+    loss = torch.empty(1, dtype=torch.float32, device=dev)
+    gen = torch.Generator(device=dev).manual_seed(seed + 1)
+    lib = ozk.library()
+    st_ = ozk._stream(None)
+    hist = []
+    n = X.shape[0]
+    for step in range(1, steps + 1):
+        idx = torch.randint(0, n, (min(batch, n),), generator=gen, device=dev)
+        xb = X[idx].contiguous()
+        yb = Y[idx].contiguous()
+        st = lib.ozk_mlp_grad(ctx.handle, w.data_ptr(), xb.data_ptr(), yb.data_ptr(), xb.shape[0], g.data_ptr(),
+                              loss.data_ptr(), st_)
+        ozk._check("ozk_mlp_grad", st, ctx)
+        st = lib.ozk_mlp_adam(ctx.handle, w.data_ptr(), g.data_ptr(), m.data_ptr(), v.data_ptr(), step, lr, st_)
+        ozk._check("ozk_mlp_adam", st, ctx)
+        if step % 100 == 0:
+            hist.append(float(loss))
+        if step % 1000 == 0:
+            print("training step %d: loss %.5f" % (step, hist[-1]), flush=True)
+    return w, hist
+
+
+def forward(ctx, w, X):
+    torch = _torch()
+    out = torch.empty((X.shape[0], 8), dtype=torch.float32, device=X.device)
+    st = ozk.library().ozk_mlp_forward(ctx.handle, w.data_ptr(), X.contiguous().data_ptr(), X.shape[0],
+                                       out.data_ptr(), ozk._stream(None))
+    ozk._check("ozk_mlp_forward", st, ctx)
+    return out
+
+
+def decide(logits, threshold: float, margin: int):
+    torch = _torch()
+    return torch.clamp(1 + (torch.sigmoid(logits) > threshold).sum(dim=1) + margin, max=9)
+
+
+def needed(labels):
+    """Slices a sample needs: its label, or 8 when no p up to 8 meets the
+    tolerance (then the most accurate choice is the right one)."""
+    torch = _torch()
+    return torch.clamp(labels, max=8)
+
+
+def calibrate(ctx, w, X, labels) -> Tuple[float, int]:
+    """The smallest margin, then the largest threshold, for which no sample
+    of the calibration set is given fewer slices than it needs."""
+    logits = forward(ctx, w, X)
+    need = needed(labels.to(X.device))
+    for margin in range(0, 5):
+        for thr in (0.5, 0.4, 0.3, 0.2, 0.1, 0.05, 0.02, 0.01):
+            p = decide(logits, thr, margin)
+            if bool((p >= need).all()):
+                return thr, margin
+    return 0.01, 8
+
+
+def save(path: str, w, threshold: float, margin: int, meta: Dict) -> None:
+    with open(path, "w") as fh:
+        json.dump({"params": [float(x) for x in w.cpu().tolist()], "threshold": threshold, "margin": margin,
+                   "meta": meta}, fh)
+
+
+def load(path: str = WEIGHTS):
+    with open(path) as fh:
+        return json.load(fh)
+
+
+def install(ctx, path: str = WEIGHTS) -> Dict:
+    """Load the shipped (or given) parameters into the context."""
+    import ctypes
+    d = load(path)
+    arr = (ctypes.c_float * len(d["params"]))(*d["params"])
+    st = ozk.library().ozk_selector_load(ctx.handle, ctypes.cast(arr, ctypes.c_void_p), len(d["params"]),
+                                         float(d["threshold"]), int(d["margin"]))
+    ozk._check("ozk_selector_load", st, ctx)
+    return d
+
+
+def main():
+    import argparse
+    import time
+    torch = _torch()
+    ap = argparse.ArgumentParser(description="train the slice-count selector on the GPU")
+    ap.add_argument("--train", type=int, default=1500)
+    ap.add_argument("--val", type=int, default=300)
+    ap.add_argument("--steps", type=int, default=4000)
+    ap.add_argument("--out", default=WEIGHTS)
+    a = ap.parse_args()
+    ctx = ozk.Context(0)
+    t0 = time.time()
+    Xtr, ytr, btr, _ = build_dataset(ctx, a.train, seed=1)
+    Xva, yva, bva, _ = build_dataset(ctx, a.val, seed=2)
+    print("datasets %.1fs: train %d val %d" % (time.time() - t0, len(ytr), len(yva)), flush=True)
+    w, hist = train(ctx, Xtr, ytr, steps=a.steps)
+    thr, margin = calibrate(ctx, w, Xva, yva)
+    pva = decide(forward(ctx, w, Xva), thr, margin).cpu()
+    pbound = torch.clamp(bva, max=8)
+    used = torch.clamp(torch.minimum(pva, bva), 1, 8)
+    meta = {"train_problems": a.train, "val_problems": a.val, "steps": a.steps, "loss": hist[-5:],
+            "tols": "4 per problem, log-uniform in [1e-16, 1e-5]", "sizes": "M,N,K log-uniform in [64, 768]",
+            "phi": "U(0,4) for A and for B", "threshold": thr, "margin": margin,
+            "val_mean_p_selector": float(used.double().mean()), "val_mean_p_bound": float(pbound.double().mean()),
+            "val_mean_p_needed": float(needed(yva).double().mean()),
+            "val_under": int((used < needed(yva)).sum())}
+    save(a.out, w, thr, margin, meta)
+    print(json.dumps(meta), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

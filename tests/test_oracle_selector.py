@@ -69,8 +69,34 @@ def test_histogram_brute_force():
             b = max(k for k, edge in enumerate(sel.BIN_EDGES) if d >= edge)
             counts[b] += 1
     assert np.allclose(h, counts / counts.sum(), rtol=0, atol=1e-15)
+    c, dmax = sel.deficit_counts(A, 1)
+    assert c.tolist() == counts.tolist()
+    assert dmax == max(max(math.frexp(x)[1] for x in A[i] if x != 0) - math.frexp(x)[1]
+                       for i in range(13) for x in A[i] if x != 0)
     f = sel.features(A, A.T.copy(), 1e-13)
     assert f.shape == (34,) and abs(f[32] - math.log2(40) / 14) < 1e-15 and abs(f[33] - 13 / 16) < 1e-15
+
+
+def test_deficit_bins_brute_force():
+    """Bin of every deficit 0..300 against the edge list read literally."""
+    for d in range(301):
+        b = max(k for k, edge in enumerate(sel.BIN_EDGES) if d >= edge)
+        assert sel.deficit_bin(d) == b
+        A = np.array([[1.0, math.ldexp(1.0, -d)]])
+        assert sel.deficit_counts(A, 1)[0].tolist() == [2 if (k == 0 and b == 0) else int(k == 0) + int(k == b)
+                                                        for k in range(sel.N_BINS)]
+
+
+def test_nonfinite_lines_and_columns_are_skipped():
+    A = synth.phi_matrix(6, 9, 2.0, 3)
+    A[1, 4] = np.inf
+    A[3, 0] = np.nan
+    c_rows, _ = sel.deficit_counts(A, 1)
+    keep = np.delete(A, [1, 3], axis=0)
+    assert c_rows.tolist() == sel.deficit_counts(keep, 1)[0].tolist() and c_rows.sum() == 4 * 9
+    c_cols, _ = sel.deficit_counts(A, 0)
+    keepc = np.delete(A, [0, 4], axis=1)
+    assert c_cols.tolist() == sel.deficit_counts(keepc, 0)[0].tolist() and c_cols.sum() == 6 * 7
 
 
 def test_bound_holds_on_oracle_errors():
