@@ -36,6 +36,10 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
     ap.add_argument("--no-native", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (default configurations)")
+    ap.add_argument("--save-config", default=None, help="write the tuned configuration table (JSON)")
+    ap.add_argument("--load-config", default=None, help="use a saved configuration table instead of tuning")
+    ap.add_argument("--err-samples", type=int, default=4096, help="outputs sampled for the accuracy check")
     return ap.parse_args()
 
 
@@ -137,8 +141,26 @@ def main():
                 ev[2].record(stream)
         return step
 
+    ps = sorted({p, 8} if p != 8 else {8})
+    tuned = {}
+    if args.load_config:
+        ozk.ozk_config_load(ctx, args.load_config)
+        for pp in ps:
+            cfg, found, tms = ozk.ozk_config_get(ctx, ozk.OZK_OP_DGEMM, ozk.OZK_SCHEME1, pp, M, N, K)
+            if found:
+                tuned[pp] = {"variant": cfg[0], "raster": cfg[1], "group": cfg[2], "split": cfg[3],
+                             "tuned_gemm_ms": round(tms, 4), "loaded": True}
+    elif not args.no_tune:  # untimed: pick the GEMM configuration of this size class
+        for pp in ps:
+            _, cfg, tms = ozk.ozk_tune(ctx, ozk.OZK_OP_DGEMM, ozk.OZK_SCHEME1, pp, a, b, C=c, reps=2)
+            tuned[pp] = {"variant": cfg[0], "raster": cfg[1], "group": cfg[2], "split": cfg[3],
+                         "tuned_gemm_ms": round(tms, 4)}
+        torch.cuda.synchronize()
+        if args.save_config:
+            ozk.ozk_config_save(ctx, args.save_config)
+
     results = {}
-    for pp in sorted({p, 8} if p != 8 else {8}):
+    for pp in ps:
         total_ms, marks = time_steps(make_step(pp), args.steps, args.warmup, torch)
         gemm_ms = sum(m[1].elapsed_time(m[2]) for m in marks) / len(marks)
         pre_ms = sum(m[0].elapsed_time(m[1]) for m in marks) / len(marks)
@@ -149,6 +171,28 @@ def main():
     torch.cuda.synchronize()
     same = bool(torch.equal(whole, c))
     del whole
+
+    # accuracy on sampled outputs: E_cw = max |C - C_dd| / (|A||B|) against the
+    # double-double reference kernel, for the emulation at p and native FP64
+    g = torch.Generator(device="cpu").manual_seed(12345)
+    ns = args.err_samples
+    rows = torch.randint(0, M, (ns,), generator=g).to(dev)
+    cols = torch.randint(0, N, (ns,), generator=g).to(dev)
+    hi = torch.empty(ns, dtype=torch.float64, device=dev)
+    lo = torch.empty_like(hi)
+    ab = torch.empty_like(hi)
+    st = ozk.library().ozk_ref_dd(ctx.handle, M, N, K, a.data_ptr(), K, b.data_ptr(), N, ns, rows.data_ptr(),
+                                  cols.data_ptr(), hi.data_ptr(), lo.data_ptr(), ab.data_ptr(), ozk._stream(None))
+    ozk._check("ozk_ref_dd", st, ctx)
+
+    def e_cw(Cm):
+        got = Cm[rows, cols]
+        return float((((got - hi) - lo).abs() / ab).max())
+
+    err_emul = e_cw(c)
+    nat_c = torch.matmul(a, b)
+    err_native = e_cw(nat_c)
+    del nat_c
 
     native = None
     if not args.no_native:
@@ -185,6 +229,9 @@ def main():
         "native_dgemm_tflops": None if native is None else round(native, 2),
         "speedup_vs_native": None if native is None else round(value / native, 3),
         "whole_call_matches_steps": same,
+        "err_cw_sampled": {"emulated_p%d" % p: err_emul, "native_fp64": err_native, "samples": ns,
+                           "meets_1e-13": err_emul <= 1e-13, "within_2x_native": err_emul <= 2 * err_native},
+        "gemm_config": tuned.get(p, "default"),
     }
     for pp, rr in results.items():
         line["p%d_tflops" % pp] = round(2.0 * M * N * K / (rr["ms"] * 1e-3) / 1e12, 3)

@@ -22,7 +22,9 @@
  *   and the status says why (ozk_last_arg() names the 1-based position of
  *   the offending argument).  No exception or abort crosses the ABI.
  * - beta == 0 means C is not read (BLAS convention).  M, N or K == 0 are
- *   valid: with K == 0 the product is exactly zero.
+ *   valid: with K == 0 the product is exactly zero.  M and N (rows and
+ *   columns of packed operands) are at most OZK_MAX_ROWS = 2^24, K at most
+ *   2^40; larger sizes return OZK_ERR_INVALID_ARG.
  * - A row of A or a column of B that holds a NaN or an infinity yields NaN
  *   in the corresponding row/column of alpha*A*B (the paper does not define
  *   this case); finite rows and columns are unaffected.
@@ -79,6 +81,9 @@ extern "C" {
 #define OZK_EXP_NONFINITE 100000
 #define OZK_MAX_P 8
 #define OZK_MAX_S 20
+#define OZK_MAX_ROWS 16777216       /* 2^24: largest M, N (32-bit packed offsets) */
+#define OZK_S1_VARIANTS 4           /* Scheme I GEMM tile variants */
+#define OZK_S2_VARIANTS 2           /* Scheme II GEMM tile variants */
 #define OZK_SELECTOR_PARAMS 6920   /* float32 parameters of the selector MLP */
 #define OZK_SELECTOR_COUNTERS 34   /* int32 feature counters */
 
@@ -338,6 +343,67 @@ ozk_status ozk_gemm_batched(ozk_ctx* ctx, const ozk_batch_plan* plan, void* ws,
                             size_t ws_bytes, hipStream_t stream);
 /* Free a plan (NULL accepted); work using it must have completed. */
 ozk_status ozk_batch_plan_destroy(ozk_batch_plan* plan);
+
+/* -------------------------------------------------------- autotuner */
+/* A GEMM configuration.  The paper picks its kernel parameters (M stacking,
+ * N tile, swizzle, buffering stages; Table I) with an autotuner (Sec. V-A);
+ * here the INT8 GEMM step of each
+ * call takes its configuration from a per-context table keyed by the size
+ * class (op, scheme, p or s, and ceil(log2) of M, N and K), filled by
+ * ozk_tune, ozk_config_set or ozk_config_load; classes without an entry use
+ * the default {0, 0, 4, 1}.  Every configuration computes the same integers,
+ * so results are bit-identical whichever is used; only the time differs.
+ *   variant: tile variant, Scheme I 0 .. OZK_S1_VARIANTS-1 (bit 1: the other
+ *            wave-tile orientation, 128x64 <-> 128x128 for p <= 4 and
+ *            128x64 <-> 64x128 for p >= 5; bit 0: one LDS stage fewer),
+ *            Scheme II 0 .. OZK_S2_VARIANTS-1 (1: one LDS stage fewer);
+ *   raster:  0 = tiles of one XCD form a compact block, 1 = dispatch order;
+ *   group:   tile rows per raster group, 1 .. 64;
+ *   split:   Scheme I only: at least this many K runs (their 128-bit partial
+ *            sums are folded exactly; the workspace grows by 16*split*M*N
+ *            bytes), 1 .. 64; Scheme II stores 1.
+ * The table is host state of the context (not thread-safe: one context per
+ * host thread).  ozk_workspace_size reflects the configuration of the size
+ * class, so query it after tuning or setting. */
+typedef struct ozk_gemm_config {
+  int variant;
+  int raster;
+  int group;
+  int split;
+} ozk_gemm_config;
+
+/* Store cfg for the size class of (M, N, K).  Scheme I needs op DGEMM. */
+ozk_status ozk_config_set(ozk_ctx* ctx, ozk_op op, ozk_scheme scheme,
+                          int p_or_s, int64_t M, int64_t N, int64_t K,
+                          const ozk_gemm_config* cfg);
+/* The configuration calls of this size class use (*found = 1 and *ms the
+ * tuned time if an entry exists, else the default and *found = 0); found
+ * and ms may be NULL. */
+ozk_status ozk_config_get(ozk_ctx* ctx, ozk_op op, ozk_scheme scheme,
+                          int p_or_s, int64_t M, int64_t N, int64_t K,
+                          ozk_gemm_config* cfg, int* found, float* ms);
+ozk_status ozk_config_clear(ozk_ctx* ctx);
+/* Write / merge the table as JSON (a host file path). */
+ozk_status ozk_config_save(ozk_ctx* ctx, const char* path);
+ozk_status ozk_config_load(ozk_ctx* ctx, const char* path);
+/* Workspace ozk_tune needs to try every candidate (smaller workspaces skip
+ * the K splits that do not fit). */
+ozk_status ozk_tune_workspace_size(ozk_ctx* ctx, ozk_op op, ozk_scheme scheme,
+                                   int p_or_s, int64_t M, int64_t N, int64_t K,
+                                   size_t* bytes);
+/* Tune the size class of (M, N, K) on these operands: run the pre-pass
+ * once, time the INT8 GEMM step (with the K-run fold) of every candidate
+ * configuration -- variants x rasters x groups {4, 8} x K splits 1, 2, 4, 8
+ * (Scheme I, while the partial sums fit 256 MiB) -- as the median of `reps`
+ * runs after one warm-up, store the fastest in the table, and leave
+ * C = A B (alpha 1, beta 0) computed with it.  Complex operands (ZGEMM,
+ * Scheme II) are interleaved.  Unlike the other calls this one synchronises
+ * the stream (HIP events) and must not be captured into a graph. */
+ozk_status ozk_tune(ozk_ctx* ctx, ozk_op op, ozk_scheme scheme, int p_or_s,
+                    int64_t M, int64_t N, int64_t K, const double* A,
+                    int64_t lda, const double* B, int64_t ldb, double* C,
+                    int64_t ldc, void* ws, size_t ws_bytes, int reps,
+                    ozk_gemm_config* best, float* best_ms, hipStream_t stream);
 
 #ifdef __cplusplus
 }

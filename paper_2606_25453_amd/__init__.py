@@ -31,6 +31,18 @@ OZK_EXP_ZERO = -100000
 OZK_EXP_NONFINITE = 100000
 OZK_SELECTOR_PARAMS = 6920
 OZK_SELECTOR_COUNTERS = 34
+OZK_MAX_ROWS = 1 << 24
+OZK_S1_VARIANTS = 4
+OZK_S2_VARIANTS = 2
+
+
+class OzkGemmConfig(ctypes.Structure):
+    """ozk_gemm_config: tile variant, raster order, raster group, K split."""
+    _fields_ = [("variant", ctypes.c_int), ("raster", ctypes.c_int), ("group", ctypes.c_int),
+                ("split", ctypes.c_int)]
+
+    def as_tuple(self):
+        return (self.variant, self.raster, self.group, self.split)
 
 # every symbol include/ozk.h declares
 EXPORTS = (
@@ -40,6 +52,8 @@ EXPORTS = (
     "ozk_s1_diagonals", "ozk_s2_split_rows", "ozk_s2_split_cols", "ozk_s2_gemm_mod", "ozk_s2_crt",
     "ozk_selector_load", "ozk_select", "ozk_dgemm_auto", "ozk_mlp_forward", "ozk_mlp_grad", "ozk_mlp_adam",
     "ozk_ref_dd", "ozk_batch_plan_create", "ozk_gemm_batched", "ozk_batch_plan_destroy",
+    "ozk_config_set", "ozk_config_get", "ozk_config_clear", "ozk_config_save", "ozk_config_load",
+    "ozk_tune_workspace_size", "ozk_tune",
 )
 
 
@@ -89,6 +103,15 @@ def _lib() -> ctypes.CDLL:
         "ozk_mlp_grad": (I, [P, P, P, P, I, P, P, P]),
         "ozk_mlp_adam": (I, [P, P, P, P, P, I, ctypes.c_float, P]),
         "ozk_ref_dd": (I, [P, I64, I64, I64, P, I64, P, I64, I64, P, P, P, P, P, P]),
+        "ozk_config_set": (I, [P, I, I, I, I64, I64, I64, ctypes.POINTER(OzkGemmConfig)]),
+        "ozk_config_get": (I, [P, I, I, I, I64, I64, I64, ctypes.POINTER(OzkGemmConfig), ctypes.POINTER(I),
+                               ctypes.POINTER(ctypes.c_float)]),
+        "ozk_config_clear": (I, [P]),
+        "ozk_config_save": (I, [P, ctypes.c_char_p]),
+        "ozk_config_load": (I, [P, ctypes.c_char_p]),
+        "ozk_tune_workspace_size": (I, [P, I, I, I, I64, I64, I64, ctypes.POINTER(SZ)]),
+        "ozk_tune": (I, [P, I, I, I, I64, I64, I64, P, I64, P, I64, P, I64, P, SZ, I, ctypes.POINTER(OzkGemmConfig),
+                         ctypes.POINTER(ctypes.c_float), P]),
         "ozk_batch_plan_create": (I, [P, I, I, I, I, P, ctypes.POINTER(P), ctypes.POINTER(SZ)]),
         "ozk_gemm_batched": (I, [P, P, P, SZ, P]),
         "ozk_batch_plan_destroy": (I, [P]),
@@ -404,3 +427,58 @@ class BatchPlan:
             self.close()
         except Exception:
             pass
+
+
+# ---------------------------------------------------------------- autotuner
+
+def ozk_config_set(ctx: Context, op: int, scheme: int, p_or_s: int, M: int, N: int, K: int, config) -> None:
+    """Store a configuration (OzkGemmConfig or a 4-tuple) for the size class of (M, N, K)."""
+    cfg = config if isinstance(config, OzkGemmConfig) else OzkGemmConfig(*config)
+    _check("ozk_config_set", _lib().ozk_config_set(ctx.handle, op, scheme, p_or_s, M, N, K, ctypes.byref(cfg)), ctx)
+
+
+def ozk_config_get(ctx: Context, op: int, scheme: int, p_or_s: int, M: int, N: int, K: int):
+    """(config tuple, found, tuned ms) for the size class of (M, N, K)."""
+    cfg = OzkGemmConfig()
+    found = ctypes.c_int()
+    ms = ctypes.c_float()
+    _check("ozk_config_get", _lib().ozk_config_get(ctx.handle, op, scheme, p_or_s, M, N, K, ctypes.byref(cfg),
+                                                   ctypes.byref(found), ctypes.byref(ms)), ctx)
+    return cfg.as_tuple(), bool(found.value), float(ms.value)
+
+
+def ozk_config_clear(ctx: Context) -> None:
+    _check("ozk_config_clear", _lib().ozk_config_clear(ctx.handle), ctx)
+
+
+def ozk_config_save(ctx: Context, path: str) -> None:
+    _check("ozk_config_save", _lib().ozk_config_save(ctx.handle, os.fsencode(path)), ctx)
+
+
+def ozk_config_load(ctx: Context, path: str) -> None:
+    _check("ozk_config_load", _lib().ozk_config_load(ctx.handle, os.fsencode(path)), ctx)
+
+
+def ozk_tune_workspace_size(ctx: Context, op: int, scheme: int, p_or_s: int, M: int, N: int, K: int) -> int:
+    out = ctypes.c_size_t()
+    _check("ozk_tune_workspace_size", _lib().ozk_tune_workspace_size(ctx.handle, op, scheme, p_or_s, M, N, K,
+                                                                     ctypes.byref(out)), ctx)
+    return int(out.value)
+
+
+def ozk_tune(ctx: Context, op: int, scheme: int, p_or_s: int, A, B, C=None, reps: int = 3, ws=None, stream=None):
+    """Tune the size class of A B (float64 or complex128 CUDA tensors); returns
+    (C = A B, best config tuple, best ms)."""
+    import torch
+    M, K = A.shape
+    N = B.shape[1]
+    if C is None:
+        C = torch.empty((M, N), dtype=A.dtype, device=A.device)
+    if ws is None:
+        ws = _workspace(ozk_tune_workspace_size(ctx, op, scheme, p_or_s, M, N, K), A.device)
+    best = OzkGemmConfig()
+    ms = ctypes.c_float()
+    st = _lib().ozk_tune(ctx.handle, op, scheme, p_or_s, M, N, K, _ptr(A), _ld(A), _ptr(B), _ld(B), _ptr(C), _ld(C),
+                         _ptr(ws), ws.numel(), reps, ctypes.byref(best), ctypes.byref(ms), _stream(stream))
+    _check("ozk_tune", st, ctx)
+    return C, best.as_tuple(), float(ms.value)

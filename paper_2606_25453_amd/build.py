@@ -22,22 +22,42 @@ FLAGS = [
 ]
 
 
+# compiled once per slice count (-DOZK_S1_P=p) so the kernels build in parallel
+PER_P = {"s1_gemm_inst.hip"}
+MAX_P = 8
+
+
 def sources():
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hip"))
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(OBJDIR, os.path.basename(src)[:-4] + ".o")
-    subprocess.check_call([HIPCC, *FLAGS, "-c", src, "-o", obj])
+def units():
+    """(source, object, extra flags) for every compilation."""
+    out = []
+    for src in sources():
+        base = os.path.basename(src)[:-4]
+        if os.path.basename(src) in PER_P:
+            for p in range(1, MAX_P + 1):
+                out.append((src, os.path.join(OBJDIR, "%s_p%d.o" % (base, p)), ["-DOZK_S1_P=%d" % p]))
+        else:
+            out.append((src, os.path.join(OBJDIR, base + ".o"), []))
+    return out
+
+
+def _compile(unit) -> str:
+    src, obj, extra = unit
+    subprocess.check_call([HIPCC, *FLAGS, *extra, "-c", src, "-o", obj])
     return obj
 
 
 def build(verbose: bool = False) -> str:
     """Compile every kernel source and link libozk.so (always rebuilds)."""
     os.makedirs(OBJDIR, exist_ok=True)
-    srcs = sources()
-    with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
-        objs = list(ex.map(_compile, srcs))
+    todo = units()
+    # the longest compilations first
+    todo.sort(key=lambda u: (os.path.basename(u[0]) not in PER_P, u[1]))
+    with cf.ThreadPoolExecutor(max_workers=min(os.cpu_count() or 8, 16, len(todo))) as ex:
+        objs = list(ex.map(_compile, todo))
     tmp = LIB + ".tmp%d" % os.getpid()
     subprocess.check_call([HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp, *objs])
     os.replace(tmp, LIB)

@@ -6,19 +6,38 @@
 #include <string.h>
 
 #include <algorithm>
+#include <map>
+#include <new>
 #include <numeric>
+#include <string>
+#include <tuple>
 #include <vector>
 
 #include "ozk.h"
 #include "ozk_internal.hpp"
 
+// Size class of a GEMM configuration: the operation, scheme and slice or
+// modulus count, and ceil(log2) of M, N and K.
+struct ozk_cfg_key {
+  int op, scheme, p_or_s, mb, nb, kb;
+  bool operator<(const ozk_cfg_key& o) const {
+    return std::tie(op, scheme, p_or_s, mb, nb, kb) < std::tie(o.op, o.scheme, o.p_or_s, o.mb, o.nb, o.kb);
+  }
+};
+
+struct ozk_cfg_entry {
+  ozk_gemm_config cfg;
+  float ms;  // tuned time of the GEMM kernel(s), 0 if set by hand
+};
+
 struct ozk_ctx {
-  int device;
-  int last_arg;
-  int64_t k_split_override;  // > 0: shorter K runs (testing the fold path)
-  float* sel_w;              // selector parameters on the device (or null)
-  float sel_threshold;
-  int sel_margin;
+  int device = 0;
+  int last_arg = 0;
+  int64_t k_split_override = 0;  // > 0: shorter K runs (testing the fold path)
+  float* sel_w = nullptr;        // selector parameters on the device (or null)
+  float sel_threshold = 0.5f;
+  int sel_margin = 0;
+  std::map<ozk_cfg_key, ozk_cfg_entry> configs;  // tuned or set GEMM configurations
 };
 
 using ozk::round_up;
@@ -50,12 +69,18 @@ struct S1Plan {
   int64_t nsplit, steps_per_split, nchunk;
 };
 
-S1Plan s1_plan(const ozk_ctx* c, int p, int64_t M, int64_t N, int64_t K) {
+// Workspace layout of Scheme I.  `split` asks for at least that many K runs
+// (a configuration's choice); INT32 exactness may need more.
+S1Plan s1_plan(const ozk_ctx* c, int p, int64_t M, int64_t N, int64_t K, int split = 1) {
   S1Plan pl;
   const int64_t kp = round_up(K, OZK_K_CHUNK);
   pl.nchunk = kp / OZK_K_CHUNK;
   const int64_t ks = k_split_of(c, p);
   pl.steps_per_split = ks / OZK_K_CHUNK;
+  if (split > 1 && pl.nchunk > 1) {
+    const int64_t want = (pl.nchunk + split - 1) / split;
+    if (want < pl.steps_per_split) pl.steps_per_split = want;
+  }
   pl.nsplit = pl.nchunk <= pl.steps_per_split ? 1 : (pl.nchunk + pl.steps_per_split - 1) / pl.steps_per_split;
   if (pl.nchunk == 0) pl.nsplit = 1;
   size_t o = 0;
@@ -85,8 +110,65 @@ S2Plan s2_plan(int s, bool cplx, int64_t M, int64_t N, int64_t K) {
   return pl;
 }
 
+// Median time (ms) of `reps` runs of fn on the stream, after one untimed run.
+template <class F>
+static hipError_t time_median(hipStream_t st, int reps, F&& fn, float* ms) {
+  hipEvent_t a, b;
+  if (hipEventCreate(&a) != hipSuccess) return hipErrorUnknown;
+  if (hipEventCreate(&b) != hipSuccess) {
+    (void)hipEventDestroy(a);
+    return hipErrorUnknown;
+  }
+  hipError_t err = fn();
+  std::vector<float> t;
+  for (int r = 0; r < reps && err == hipSuccess; ++r) {
+    err = hipEventRecord(a, st);
+    if (err == hipSuccess) err = fn();
+    if (err == hipSuccess) err = hipEventRecord(b, st);
+    if (err == hipSuccess) err = hipEventSynchronize(b);
+    float x = 0.f;
+    if (err == hipSuccess) err = hipEventElapsedTime(&x, a, b);
+    t.push_back(x);
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  if (err != hipSuccess) return err;
+  std::sort(t.begin(), t.end());
+  *ms = t[t.size() / 2];
+  return hipSuccess;
+}
+
+bool bad_rows(int64_t r) { return r < 0 || r > OZK_MAX_ROWS; }
+
 bool bad_dims(int64_t M, int64_t N, int64_t K) {
-  return M < 0 || N < 0 || K < 0 || M > 0x7fffffff || N > 0x7fffffff || K > ((int64_t)1 << 40);
+  return bad_rows(M) || bad_rows(N) || K < 0 || K > ((int64_t)1 << 40);
+}
+
+int log2_class(int64_t x) {
+  int b = 0;
+  while (b < 62 && ((int64_t)1 << b) < x) ++b;
+  return b;
+}
+
+ozk_cfg_key cfg_key(int op, int scheme, int p_or_s, int64_t M, int64_t N, int64_t K) {
+  return ozk_cfg_key{op, scheme, p_or_s, log2_class(M), log2_class(N), log2_class(K)};
+}
+
+ozk_gemm_config default_config() { return ozk_gemm_config{0, 0, 4, 1}; }
+
+// The configuration for this size class: the tuned or set one, else the default.
+ozk_gemm_config config_for(const ozk_ctx* c, int op, int scheme, int p_or_s, int64_t M, int64_t N, int64_t K) {
+  if (c) {
+    auto it = c->configs.find(cfg_key(op, scheme, p_or_s, M, N, K));
+    if (it != c->configs.end()) return it->second.cfg;
+  }
+  return default_config();
+}
+
+bool valid_config(int scheme, const ozk_gemm_config& g) {
+  const int nv = scheme == OZK_SCHEME1 ? OZK_S1_VARIANTS : OZK_S2_VARIANTS;
+  return g.variant >= 0 && g.variant < nv && (g.raster == 0 || g.raster == 1) && g.group >= 1 && g.group <= 64 &&
+         g.split >= 1 && g.split <= 64;
 }
 
 }  // namespace
@@ -113,7 +195,7 @@ ozk_status ozk_create(ozk_ctx** ctx, int device) {
   if (hipGetDeviceCount(&n) != hipSuccess) return OZK_ERR_HIP;
   if (device < 0 || device >= n) return OZK_ERR_INVALID_ARG;
   if (hipSetDevice(device) != hipSuccess) return OZK_ERR_HIP;
-  ozk_ctx* c = (ozk_ctx*)calloc(1, sizeof(ozk_ctx));
+  ozk_ctx* c = new (std::nothrow) ozk_ctx();
   if (!c) return OZK_ERR_HIP;
   c->device = device;
   const char* ks = getenv("OZK_K_SPLIT");
@@ -124,7 +206,7 @@ ozk_status ozk_create(ozk_ctx** ctx, int device) {
 
 ozk_status ozk_destroy(ozk_ctx* ctx) {
   if (ctx && ctx->sel_w) (void)hipFree(ctx->sel_w);
-  free(ctx);
+  delete ctx;
   return OZK_OK;
 }
 
@@ -158,7 +240,7 @@ ozk_status ozk_workspace_size(ozk_ctx* ctx, ozk_op op, ozk_scheme scheme, int64_
       return OZK_OK;
     }
     if (p_or_s < 1 || p_or_s > OZK_MAX_P) return fail(ctx, OZK_ERR_UNSUPPORTED, 7);
-    *bytes = s1_plan(ctx, p_or_s, M, N, K).total;
+    *bytes = s1_plan(ctx, p_or_s, M, N, K, config_for(ctx, op, scheme, p_or_s, M, N, K).split).total;
     return OZK_OK;
   }
   if (scheme == OZK_SCHEME2 && (op == OZK_OP_DGEMM || op == OZK_OP_ZGEMM)) {
@@ -175,7 +257,7 @@ ozk_status ozk_s1_split_rows(ozk_ctx* ctx, int p, int64_t rows, int64_t K, const
   if (!ctx) return OZK_ERR_INVALID_ARG;
   ctx->last_arg = 0;
   if (p < 1 || p > OZK_MAX_P) return fail(ctx, OZK_ERR_UNSUPPORTED, 2);
-  if (rows < 0 || rows > 0x7fffffff) return fail(ctx, OZK_ERR_INVALID_ARG, 3);
+  if (bad_rows(rows)) return fail(ctx, OZK_ERR_INVALID_ARG, 3);
   if (K < 0 || K > ((int64_t)1 << 40)) return fail(ctx, OZK_ERR_INVALID_ARG, 4);
   if (!X && rows > 0 && K > 0) return fail(ctx, OZK_ERR_INVALID_ARG, 5);
   if (ldx < (K > 0 ? K : 1)) return fail(ctx, OZK_ERR_INVALID_ARG, 6);
@@ -190,7 +272,7 @@ ozk_status ozk_s1_split_cols(ozk_ctx* ctx, int p, int64_t K, int64_t cols, const
   ctx->last_arg = 0;
   if (p < 1 || p > OZK_MAX_P) return fail(ctx, OZK_ERR_UNSUPPORTED, 2);
   if (K < 0 || K > ((int64_t)1 << 40)) return fail(ctx, OZK_ERR_INVALID_ARG, 3);
-  if (cols < 0 || cols > 0x7fffffff) return fail(ctx, OZK_ERR_INVALID_ARG, 4);
+  if (bad_rows(cols)) return fail(ctx, OZK_ERR_INVALID_ARG, 4);
   if (!X && cols > 0 && K > 0) return fail(ctx, OZK_ERR_INVALID_ARG, 5);
   if (ldx < (cols > 0 ? cols : 1)) return fail(ctx, OZK_ERR_INVALID_ARG, 6);
   if (!f && cols > 0) return fail(ctx, OZK_ERR_INVALID_ARG, 7);
@@ -198,12 +280,18 @@ ozk_status ozk_s1_split_cols(ozk_ctx* ctx, int p, int64_t K, int64_t cols, const
   return hip_status(ctx, ozk::s1_split_cols(p, X, ldx, K, cols, f, packed, stream));
 }
 
+// The Scheme I GEMM of packed operands with configuration cfg (the check
+// entry point writing diagonals always uses the default).
 static ozk_status s1_gemm_common(ozk_ctx* ctx, int p, int64_t M, int64_t N, int64_t K, const int8_t* Ap,
                                  const int32_t* e, const int8_t* Bp, const int32_t* f, double alpha,
                                  double beta, double* C, int64_t ldc, void* ws, size_t ws_bytes,
-                                 int32_t* diag, hipStream_t stream) {
-  const S1Plan pl = s1_plan(ctx, p, M, N, K);
+                                 int32_t* diag, hipStream_t stream, ozk_gemm_config cfg) {
+  if (diag) cfg = default_config();
+  const S1Plan pl = s1_plan(ctx, p, M, N, K, cfg.split);
   ozk::S1GemmArgs g;
+  g.variant = cfg.variant;
+  g.raster = cfg.raster;
+  g.group = cfg.group;
   g.M = M;
   g.N = N;
   g.Ap = Ap;
@@ -243,7 +331,7 @@ ozk_status ozk_s1_gemm(ozk_ctx* ctx, int p, int64_t M, int64_t N, int64_t K, con
   }
   if (ldc < (N > 0 ? N : 1)) return fail(ctx, OZK_ERR_INVALID_ARG, 13);
   return s1_gemm_common(ctx, p, M, N, K, packedA, e, packedB, f, alpha, beta, C, ldc, ws, ws_bytes, nullptr,
-                        stream);
+                        stream, config_for(ctx, OZK_OP_DGEMM, OZK_SCHEME1, p, M, N, K));
 }
 
 ozk_status ozk_s1_diagonals(ozk_ctx* ctx, int p, int64_t M, int64_t N, int64_t K, const int8_t* packedA,
@@ -255,7 +343,7 @@ ozk_status ozk_s1_diagonals(ozk_ctx* ctx, int p, int64_t M, int64_t N, int64_t K
   if (K > k_split_of(ctx, p)) return fail(ctx, OZK_ERR_UNSUPPORTED, 5);
   if (M > 0 && N > 0 && (!packedA || !packedB || !Cd)) return fail(ctx, OZK_ERR_INVALID_ARG, 6);
   return s1_gemm_common(ctx, p, M, N, K, packedA, nullptr, packedB, nullptr, 1.0, 0.0, nullptr, N > 0 ? N : 1,
-                        nullptr, 0, Cd, stream);
+                        nullptr, 0, Cd, stream, default_config());
 }
 
 ozk_status ozk_dgemm(ozk_ctx* ctx, ozk_scheme scheme, int p_or_s, int64_t M, int64_t N, int64_t K,
@@ -285,14 +373,17 @@ ozk_status ozk_dgemm(ozk_ctx* ctx, ozk_scheme scheme, int p_or_s, int64_t M, int
     int8_t* res = (int8_t*)(w + pl.off_res);
     hipError_t err = ozk::s2_split_rows(s, false, A, lda, M, K, sig, Ap, stream);
     if (err == hipSuccess) err = ozk::s2_split_cols(s, false, B, ldb, K, N, tau, Bp, stream);
-    if (err == hipSuccess) err = ozk::s2_gemm_mod(s, false, M, N, K, Ap, Bp, res, stream);
+    const ozk_gemm_config cfg = config_for(ctx, OZK_OP_DGEMM, OZK_SCHEME2, s, M, N, K);
+    if (err == hipSuccess)
+      err = ozk::s2_gemm_mod(s, false, M, N, K, Ap, Bp, res, stream, cfg.variant, cfg.raster, cfg.group);
     const double al[2] = {alpha, 0.0}, be[2] = {beta, 0.0};
     if (err == hipSuccess) err = ozk::s2_crt(s, false, M, N, res, sig, tau, al, be, C, ldc, stream);
     return hip_status(ctx, err);
   }
   const int p = p_or_s;
   if (p < 1 || p > OZK_MAX_P) return fail(ctx, OZK_ERR_UNSUPPORTED, 3);
-  const S1Plan pl = s1_plan(ctx, p, M, N, K);
+  const ozk_gemm_config cfg = config_for(ctx, OZK_OP_DGEMM, OZK_SCHEME1, p, M, N, K);
+  const S1Plan pl = s1_plan(ctx, p, M, N, K, cfg.split);
   if (!ws || ws_bytes < pl.total) return fail(ctx, OZK_ERR_WORKSPACE, 15);
   if (M == 0 || N == 0) return OZK_OK;
   char* w = (char*)ws;
@@ -304,7 +395,7 @@ ozk_status ozk_dgemm(ozk_ctx* ctx, ozk_scheme scheme, int p_or_s, int64_t M, int
   if (err == hipSuccess) err = ozk::s1_split_cols(p, B, ldb, K, N, f, Bp, stream);
   if (err != hipSuccess) return hip_status(ctx, err);
   return s1_gemm_common(ctx, p, M, N, K, Ap, e, Bp, f, alpha, beta, C, ldc, w + pl.off_z,
-                        pl.total - pl.off_z, nullptr, stream);
+                        pl.total - pl.off_z, nullptr, stream, cfg);
 }
 
 ozk_status ozk_zgemm_3m(ozk_ctx* ctx, int s, int64_t M, int64_t N, int64_t K, const double* alpha,
@@ -333,7 +424,9 @@ ozk_status ozk_zgemm_3m(ozk_ctx* ctx, int s, int64_t M, int64_t N, int64_t K, co
   int8_t* res = (int8_t*)(w + pl.off_res);
   hipError_t err = ozk::s2_split_rows(s, true, A, lda, M, K, sig, Ap, stream);
   if (err == hipSuccess) err = ozk::s2_split_cols(s, true, B, ldb, K, N, tau, Bp, stream);
-  if (err == hipSuccess) err = ozk::s2_gemm_mod(s, true, M, N, K, Ap, Bp, res, stream);
+  const ozk_gemm_config cfg = config_for(ctx, OZK_OP_ZGEMM, OZK_SCHEME2, s, M, N, K);
+  if (err == hipSuccess)
+    err = ozk::s2_gemm_mod(s, true, M, N, K, Ap, Bp, res, stream, cfg.variant, cfg.raster, cfg.group);
   if (err == hipSuccess) err = ozk::s2_crt(s, true, M, N, res, sig, tau, alpha, beta, C, ldc, stream);
   return hip_status(ctx, err);
 }
@@ -345,7 +438,7 @@ ozk_status ozk_s2_split_rows(ozk_ctx* ctx, int s, int complex_planes, int64_t ro
   ctx->last_arg = 0;
   if (s < 1 || s > OZK_MAX_S) return fail(ctx, OZK_ERR_UNSUPPORTED, 2);
   if (complex_planes != 0 && complex_planes != 1) return fail(ctx, OZK_ERR_INVALID_ARG, 3);
-  if (rows < 0 || rows > 0x7fffffff) return fail(ctx, OZK_ERR_INVALID_ARG, 4);
+  if (bad_rows(rows)) return fail(ctx, OZK_ERR_INVALID_ARG, 4);
   if (K < 0 || K > ((int64_t)1 << 40)) return fail(ctx, OZK_ERR_INVALID_ARG, 5);
   if (!X && rows > 0 && K > 0) return fail(ctx, OZK_ERR_INVALID_ARG, 6);
   if (ldx < (K > 0 ? K : 1)) return fail(ctx, OZK_ERR_INVALID_ARG, 7);
@@ -362,7 +455,7 @@ ozk_status ozk_s2_split_cols(ozk_ctx* ctx, int s, int complex_planes, int64_t K,
   if (s < 1 || s > OZK_MAX_S) return fail(ctx, OZK_ERR_UNSUPPORTED, 2);
   if (complex_planes != 0 && complex_planes != 1) return fail(ctx, OZK_ERR_INVALID_ARG, 3);
   if (K < 0 || K > ((int64_t)1 << 40)) return fail(ctx, OZK_ERR_INVALID_ARG, 4);
-  if (cols < 0 || cols > 0x7fffffff) return fail(ctx, OZK_ERR_INVALID_ARG, 5);
+  if (bad_rows(cols)) return fail(ctx, OZK_ERR_INVALID_ARG, 5);
   if (!X && cols > 0 && K > 0) return fail(ctx, OZK_ERR_INVALID_ARG, 6);
   if (ldx < (cols > 0 ? cols : 1)) return fail(ctx, OZK_ERR_INVALID_ARG, 7);
   if (!tau && cols > 0) return fail(ctx, OZK_ERR_INVALID_ARG, 8);
@@ -378,7 +471,10 @@ ozk_status ozk_s2_gemm_mod(ozk_ctx* ctx, int s, int complex_planes, int64_t M, i
   if (complex_planes != 0 && complex_planes != 1) return fail(ctx, OZK_ERR_INVALID_ARG, 3);
   if (bad_dims(M, N, K)) return fail(ctx, OZK_ERR_INVALID_ARG, 4);
   if (M > 0 && N > 0 && (!packedA || !packedB || !Cres)) return fail(ctx, OZK_ERR_INVALID_ARG, 7);
-  return hip_status(ctx, ozk::s2_gemm_mod(s, complex_planes != 0, M, N, K, packedA, packedB, Cres, stream));
+  const ozk_gemm_config cfg =
+      config_for(ctx, complex_planes ? OZK_OP_ZGEMM : OZK_OP_DGEMM, OZK_SCHEME2, s, M, N, K);
+  return hip_status(ctx, ozk::s2_gemm_mod(s, complex_planes != 0, M, N, K, packedA, packedB, Cres, stream,
+                                          cfg.variant, cfg.raster, cfg.group));
 }
 
 ozk_status ozk_s2_crt(ozk_ctx* ctx, int s, int complex_planes, int64_t M, int64_t N, const int8_t* Cres,
@@ -388,8 +484,8 @@ ozk_status ozk_s2_crt(ozk_ctx* ctx, int s, int complex_planes, int64_t M, int64_
   ctx->last_arg = 0;
   if (s < 1 || s > OZK_MAX_S) return fail(ctx, OZK_ERR_UNSUPPORTED, 2);
   if (complex_planes != 0 && complex_planes != 1) return fail(ctx, OZK_ERR_INVALID_ARG, 3);
-  if (M < 0 || M > 0x7fffffff) return fail(ctx, OZK_ERR_INVALID_ARG, 4);
-  if (N < 0 || N > 0x7fffffff) return fail(ctx, OZK_ERR_INVALID_ARG, 5);
+  if (bad_rows(M)) return fail(ctx, OZK_ERR_INVALID_ARG, 4);
+  if (bad_rows(N)) return fail(ctx, OZK_ERR_INVALID_ARG, 5);
   if (M > 0 && N > 0 && (!Cres || !sigma || !tau || !C)) return fail(ctx, OZK_ERR_INVALID_ARG, 6);
   if (!alpha) return fail(ctx, OZK_ERR_INVALID_ARG, 9);
   if (!beta) return fail(ctx, OZK_ERR_INVALID_ARG, 10);
@@ -675,6 +771,278 @@ ozk_status ozk_batch_plan_destroy(ozk_batch_plan* plan) {
   if (!plan) return OZK_OK;
   if (plan->dev) (void)hipFree(plan->dev);
   free(plan);
+  return OZK_OK;
+}
+
+// ------------------------------------------------------------- autotuner
+
+static ozk_status check_target(ozk_ctx* ctx, int op, int scheme, int p_or_s) {
+  if (op != OZK_OP_DGEMM && op != OZK_OP_ZGEMM) return fail(ctx, OZK_ERR_INVALID_ARG, 2);
+  if (scheme != OZK_SCHEME1 && scheme != OZK_SCHEME2) return fail(ctx, OZK_ERR_INVALID_ARG, 3);
+  if (scheme == OZK_SCHEME1 && op != OZK_OP_DGEMM) return fail(ctx, OZK_ERR_UNSUPPORTED, 3);
+  const int hi = scheme == OZK_SCHEME1 ? OZK_MAX_P : OZK_MAX_S;
+  if (p_or_s < 1 || p_or_s > hi) return fail(ctx, OZK_ERR_UNSUPPORTED, 4);
+  return OZK_OK;
+}
+
+// Largest K split the tuner tries: the 128-bit partials of all runs stay
+// within 256 MiB, at most 8 runs and at most one run per K step.
+static int tune_max_split(int64_t M, int64_t N, int64_t K) {
+  const int64_t nchunk = round_up(K, OZK_K_CHUNK) / OZK_K_CHUNK;
+  int s = 1;
+  while (s < 8 && 2 * s <= nchunk && 16 * (2 * s) * M * N <= ((int64_t)256 << 20)) s *= 2;
+  return s;
+}
+
+ozk_status ozk_config_set(ozk_ctx* ctx, ozk_op op, ozk_scheme scheme, int p_or_s, int64_t M, int64_t N, int64_t K,
+                          const ozk_gemm_config* cfg) {
+  if (!ctx) return OZK_ERR_INVALID_ARG;
+  ctx->last_arg = 0;
+  ozk_status st = check_target(ctx, op, scheme, p_or_s);
+  if (st != OZK_OK) return st;
+  if (bad_dims(M, N, K)) return fail(ctx, OZK_ERR_INVALID_ARG, 5);
+  if (!cfg || !valid_config(scheme, *cfg)) return fail(ctx, OZK_ERR_INVALID_ARG, 8);
+  ozk_gemm_config c = *cfg;
+  if (scheme == OZK_SCHEME2) c.split = 1;
+  ctx->configs[cfg_key(op, scheme, p_or_s, M, N, K)] = ozk_cfg_entry{c, 0.f};
+  return OZK_OK;
+}
+
+ozk_status ozk_config_get(ozk_ctx* ctx, ozk_op op, ozk_scheme scheme, int p_or_s, int64_t M, int64_t N, int64_t K,
+                          ozk_gemm_config* cfg, int* found, float* ms) {
+  if (!ctx) return OZK_ERR_INVALID_ARG;
+  ctx->last_arg = 0;
+  ozk_status st = check_target(ctx, op, scheme, p_or_s);
+  if (st != OZK_OK) return st;
+  if (bad_dims(M, N, K)) return fail(ctx, OZK_ERR_INVALID_ARG, 5);
+  if (!cfg) return fail(ctx, OZK_ERR_INVALID_ARG, 8);
+  auto it = ctx->configs.find(cfg_key(op, scheme, p_or_s, M, N, K));
+  const bool have = it != ctx->configs.end();
+  *cfg = have ? it->second.cfg : default_config();
+  if (found) *found = have ? 1 : 0;
+  if (ms) *ms = have ? it->second.ms : 0.f;
+  return OZK_OK;
+}
+
+ozk_status ozk_config_clear(ozk_ctx* ctx) {
+  if (!ctx) return OZK_ERR_INVALID_ARG;
+  ctx->last_arg = 0;
+  ctx->configs.clear();
+  return OZK_OK;
+}
+
+static const char* const CFG_FIELDS[] = {"op", "scheme", "p_or_s", "m_class", "n_class", "k_class",
+                                         "variant", "raster", "group", "split"};
+
+ozk_status ozk_config_save(ozk_ctx* ctx, const char* path) {
+  if (!ctx) return OZK_ERR_INVALID_ARG;
+  ctx->last_arg = 0;
+  if (!path) return fail(ctx, OZK_ERR_INVALID_ARG, 2);
+  FILE* fh = fopen(path, "w");
+  if (!fh) return fail(ctx, OZK_ERR_INVALID_ARG, 2);
+  fprintf(fh, "{\"format\": \"ozk-gemm-configs-1\", \"entries\": [");
+  bool first = true;
+  for (const auto& kv : ctx->configs) {
+    const ozk_cfg_key& k = kv.first;
+    const ozk_gemm_config& c = kv.second.cfg;
+    const int v[10] = {k.op, k.scheme, k.p_or_s, k.mb, k.nb, k.kb, c.variant, c.raster, c.group, c.split};
+    fprintf(fh, "%s\n  {", first ? "" : ",");
+    for (int i = 0; i < 10; ++i) fprintf(fh, "\"%s\": %d, ", CFG_FIELDS[i], v[i]);
+    fprintf(fh, "\"ms\": %.6g}", (double)kv.second.ms);
+    first = false;
+  }
+  fprintf(fh, "\n]}\n");
+  const bool ok = fclose(fh) == 0;
+  return ok ? OZK_OK : fail(ctx, OZK_ERR_INVALID_ARG, 2);
+}
+
+// Reads what ozk_config_save writes: every {...} inside the entries list
+// with the ten integer fields (and "ms"); entries are added to the table.
+ozk_status ozk_config_load(ozk_ctx* ctx, const char* path) {
+  if (!ctx) return OZK_ERR_INVALID_ARG;
+  ctx->last_arg = 0;
+  if (!path) return fail(ctx, OZK_ERR_INVALID_ARG, 2);
+  FILE* fh = fopen(path, "r");
+  if (!fh) return fail(ctx, OZK_ERR_INVALID_ARG, 2);
+  std::string text;
+  char buf[4096];
+  size_t n;
+  while ((n = fread(buf, 1, sizeof buf, fh)) > 0) text.append(buf, n);
+  fclose(fh);
+  const size_t list = text.find("\"entries\"");
+  if (list == std::string::npos) return fail(ctx, OZK_ERR_INVALID_ARG, 2);
+  std::map<ozk_cfg_key, ozk_cfg_entry> add;
+  size_t pos = text.find('[', list);
+  while (pos != std::string::npos) {
+    const size_t open = text.find('{', pos);
+    if (open == std::string::npos) break;
+    const size_t close = text.find('}', open);
+    if (close == std::string::npos) return fail(ctx, OZK_ERR_INVALID_ARG, 2);
+    const std::string obj = text.substr(open, close - open);
+    long v[10];
+    for (int i = 0; i < 10; ++i) {
+      const std::string key = std::string("\"") + CFG_FIELDS[i] + "\"";
+      const size_t at = obj.find(key);
+      if (at == std::string::npos) return fail(ctx, OZK_ERR_INVALID_ARG, 2);
+      const size_t colon = obj.find(':', at + key.size());
+      if (colon == std::string::npos) return fail(ctx, OZK_ERR_INVALID_ARG, 2);
+      char* end = nullptr;
+      v[i] = strtol(obj.c_str() + colon + 1, &end, 10);
+      if (end == obj.c_str() + colon + 1) return fail(ctx, OZK_ERR_INVALID_ARG, 2);
+    }
+    double ms = 0.0;
+    const size_t at = obj.find("\"ms\"");
+    if (at != std::string::npos) ms = strtod(obj.c_str() + obj.find(':', at) + 1, nullptr);
+    const ozk_gemm_config c{(int)v[6], (int)v[7], (int)v[8], (int)v[9]};
+    ozk_ctx probe;
+    if (check_target(&probe, (int)v[0], (int)v[1], (int)v[2]) != OZK_OK || !valid_config((int)v[1], c) ||
+        v[3] < 0 || v[3] > 62 || v[4] < 0 || v[4] > 62 || v[5] < 0 || v[5] > 62)
+      return fail(ctx, OZK_ERR_INVALID_ARG, 2);
+    add[ozk_cfg_key{(int)v[0], (int)v[1], (int)v[2], (int)v[3], (int)v[4], (int)v[5]}] = ozk_cfg_entry{c, (float)ms};
+    pos = close + 1;
+  }
+  for (const auto& kv : add) ctx->configs[kv.first] = kv.second;
+  return OZK_OK;
+}
+
+ozk_status ozk_tune_workspace_size(ozk_ctx* ctx, ozk_op op, ozk_scheme scheme, int p_or_s, int64_t M, int64_t N,
+                                   int64_t K, size_t* bytes) {
+  if (!ctx) return OZK_ERR_INVALID_ARG;
+  ctx->last_arg = 0;
+  ozk_status st = check_target(ctx, op, scheme, p_or_s);
+  if (st != OZK_OK) return st;
+  if (bad_dims(M, N, K)) return fail(ctx, OZK_ERR_INVALID_ARG, 5);
+  if (!bytes) return fail(ctx, OZK_ERR_INVALID_ARG, 8);
+  if (scheme == OZK_SCHEME1)
+    *bytes = s1_plan(ctx, p_or_s, M, N, K, tune_max_split(M, N, K)).total;
+  else
+    *bytes = s2_plan(p_or_s, op == OZK_OP_ZGEMM, M, N, K).total;
+  return OZK_OK;
+}
+
+ozk_status ozk_tune(ozk_ctx* ctx, ozk_op op, ozk_scheme scheme, int p_or_s, int64_t M, int64_t N, int64_t K,
+                    const double* A, int64_t lda, const double* B, int64_t ldb, double* C, int64_t ldc, void* ws,
+                    size_t ws_bytes, int reps, ozk_gemm_config* best, float* best_ms, hipStream_t stream) {
+  if (!ctx) return OZK_ERR_INVALID_ARG;
+  ctx->last_arg = 0;
+  ozk_status st = check_target(ctx, op, scheme, p_or_s);
+  if (st != OZK_OK) return st;
+  if (bad_dims(M, N, K)) return fail(ctx, OZK_ERR_INVALID_ARG, 5);
+  const int64_t ew = op == OZK_OP_ZGEMM ? 2 : 1;  // doubles per element
+  if (!A && M > 0 && K > 0) return fail(ctx, OZK_ERR_INVALID_ARG, 8);
+  if (lda < (K > 0 ? K : 1)) return fail(ctx, OZK_ERR_INVALID_ARG, 9);
+  if (!B && K > 0 && N > 0) return fail(ctx, OZK_ERR_INVALID_ARG, 10);
+  if (ldb < (N > 0 ? N : 1)) return fail(ctx, OZK_ERR_INVALID_ARG, 11);
+  if (!C && M > 0 && N > 0) return fail(ctx, OZK_ERR_INVALID_ARG, 12);
+  if (ldc < (N > 0 ? N : 1)) return fail(ctx, OZK_ERR_INVALID_ARG, 13);
+  if (reps < 1 || reps > 1000) return fail(ctx, OZK_ERR_INVALID_ARG, 16);
+  (void)ew;
+  const ozk_cfg_key key = cfg_key(op, scheme, p_or_s, M, N, K);
+  ozk_gemm_config top = default_config();
+  float top_ms = 0.f;
+  hipError_t err = hipSuccess;
+  char* w = (char*)ws;
+  if (scheme == OZK_SCHEME1) {
+    const int p = p_or_s;
+    const S1Plan base = s1_plan(ctx, p, M, N, K, 1);
+    if (!ws || ws_bytes < base.total) return fail(ctx, OZK_ERR_WORKSPACE, 15);
+    if (M > 0 && N > 0) {
+      int32_t* e = (int32_t*)(w + base.off_e);
+      int32_t* f = (int32_t*)(w + base.off_f);
+      int8_t* Ap = (int8_t*)(w + base.off_a);
+      int8_t* Bp = (int8_t*)(w + base.off_b);
+      err = ozk::s1_split_rows(p, A, lda, M, K, e, Ap, stream);
+      if (err == hipSuccess) err = ozk::s1_split_cols(p, B, ldb, K, N, f, Bp, stream);
+      const int max_split = tune_max_split(M, N, K);
+      float top_t = 0.f;
+      bool have = false;
+      for (int v = 0; v < OZK_S1_VARIANTS && err == hipSuccess; ++v)
+        for (int raster = 0; raster < 2 && err == hipSuccess; ++raster)
+          for (int group : {4, 8})
+            for (int split = 1; split <= max_split && err == hipSuccess; split *= 2) {
+              const S1Plan pl = s1_plan(ctx, p, M, N, K, split);
+              if (pl.total > ws_bytes) continue;
+              if (split > 1 && pl.nsplit == base.nsplit) continue;  // no change from split 1
+              ozk::S1GemmArgs g;
+              g.M = M;
+              g.N = N;
+              g.Ap = Ap;
+              g.Bp = Bp;
+              g.nchunk = pl.nchunk;
+              g.steps_per_split = pl.nsplit > 1 ? pl.steps_per_split : (pl.nchunk > 0 ? pl.nchunk : 1);
+              g.nsplit = pl.nsplit;
+              g.e = e;
+              g.f = f;
+              g.alpha = 1.0;
+              g.beta = 0.0;
+              g.C = C;
+              g.ldc = ldc;
+              g.zpart = pl.nsplit > 1 ? (int64_t*)(w + pl.off_z) : nullptr;
+              g.diag = nullptr;
+              g.variant = v;
+              g.raster = raster;
+              g.group = group;
+              float t = 0.f;
+              err = time_median(stream, reps, [&]() { return ozk::s1_gemm(p, g, stream); }, &t);
+              if (err == hipSuccess && (!have || t < top_t)) {
+                have = true;
+                top_t = t;
+                top = ozk_gemm_config{v, raster, group, split};
+              }
+            }
+      top_ms = top_t;
+      if (err == hipSuccess) {  // leave C = A B from the chosen configuration
+        ctx->configs[key] = ozk_cfg_entry{top, top_ms};
+        const S1Plan pl = s1_plan(ctx, p, M, N, K, top.split);
+        st = s1_gemm_common(ctx, p, M, N, K, Ap, e, Bp, f, 1.0, 0.0, C, ldc, w + pl.off_z, pl.total - pl.off_z,
+                            nullptr, stream, top);
+        if (st != OZK_OK) return st;
+      }
+    } else {
+      ctx->configs[key] = ozk_cfg_entry{top, 0.f};
+    }
+  } else {
+    const int s = p_or_s;
+    const bool cplx = op == OZK_OP_ZGEMM;
+    const S2Plan pl = s2_plan(s, cplx, M, N, K);
+    if (!ws || ws_bytes < pl.total) return fail(ctx, OZK_ERR_WORKSPACE, 15);
+    if (M > 0 && N > 0) {
+      int32_t* sig = (int32_t*)(w + pl.off_sig);
+      int32_t* tau = (int32_t*)(w + pl.off_tau);
+      int8_t* Ap = (int8_t*)(w + pl.off_a);
+      int8_t* Bp = (int8_t*)(w + pl.off_b);
+      int8_t* res = (int8_t*)(w + pl.off_res);
+      err = ozk::s2_split_rows(s, cplx, A, lda, M, K, sig, Ap, stream);
+      if (err == hipSuccess) err = ozk::s2_split_cols(s, cplx, B, ldb, K, N, tau, Bp, stream);
+      float top_t = 0.f;
+      bool have = false;
+      for (int v = 0; v < OZK_S2_VARIANTS && err == hipSuccess; ++v)
+        for (int raster = 0; raster < 2 && err == hipSuccess; ++raster)
+          for (int group : {4, 8}) {
+            float t = 0.f;
+            err = time_median(
+                stream, reps, [&]() { return ozk::s2_gemm_mod(s, cplx, M, N, K, Ap, Bp, res, stream, v, raster, group); },
+                &t);
+            if (err == hipSuccess && (!have || t < top_t)) {
+              have = true;
+              top_t = t;
+              top = ozk_gemm_config{v, raster, group, 1};
+            }
+          }
+      top_ms = top_t;
+      if (err == hipSuccess) {
+        ctx->configs[key] = ozk_cfg_entry{top, top_ms};
+        err = ozk::s2_gemm_mod(s, cplx, M, N, K, Ap, Bp, res, stream, top.variant, top.raster, top.group);
+        const double one[2] = {1.0, 0.0}, zero[2] = {0.0, 0.0};
+        if (err == hipSuccess) err = ozk::s2_crt(s, cplx, M, N, res, sig, tau, one, zero, C, ldc, stream);
+      }
+    } else {
+      ctx->configs[key] = ozk_cfg_entry{top, 0.f};
+    }
+  }
+  if (err != hipSuccess) return hip_status(ctx, err);
+  if (best) *best = top;
+  if (best_ms) *best_ms = top_ms;
   return OZK_OK;
 }
 

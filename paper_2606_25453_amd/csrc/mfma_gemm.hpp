@@ -15,8 +15,9 @@
 // Workgroup: 4 waves in a 2 x 2 grid, wave tile (32 TM) x (32 TN), P INT32
 // accumulators per 32 x 32 MFMA tile for the whole K loop.  NS LDS stages of
 // [P][BM][32] (A) + [P][BN][32] (B) bytes are filled with 16-byte
-// global-to-LDS loads (no staging registers) NS - 1 steps ahead of use; one
-// barrier per K step.  In LDS, 8 consecutive rows of one slab are 8 distinct
+// global-to-LDS loads (no staging registers) up to NS - 1 steps ahead of
+// use; one barrier per K step; the fragments of the next step are read from
+// LDS while the MFMAs of the current one run.  In LDS, 8 consecutive rows of one slab are 8 distinct
 // 32-byte lines, so the 16-byte fragment reads are bank-conflict free.
 #pragma once
 #include "ozk_device.hpp"
@@ -33,17 +34,22 @@ struct GemmTile {
   static constexpr int B_BYTES = P * BN * OZK_K_CHUNK;
   static constexpr int STAGE = A_BYTES + B_BYTES;
   static constexpr int LDS_BYTES = NS * STAGE;
-  static constexpr int CHUNKS = STAGE / 1024;    // 1 KB wave loads per stage
-  static constexpr int CHUNKS_MIN = CHUNKS / 4;  // loads every wave issues at least
+  static constexpr int CHUNKS = STAGE / 1024;       // 1 KB wave loads per stage
+  static constexpr int WAVE_LOADS = (CHUNKS + 3) / 4;  // loads each wave issues per stage
   static_assert(STAGE % 1024 == 0, "stage must be whole 1 KB chunks");
   static_assert(NS >= 2, "at least two stages");
 };
 
 // Workgroup barrier for LDS hand-over only: waits for this wave's LDS
-// operations, then s_barrier.  Unlike __syncthreads() it does not drain the
-// global loads in flight (the direct-to-LDS loads of later stages).  The
-// memory clobber keeps the compiler from moving LDS accesses across it.
-__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+// operations (lgkmcnt(0), through the builtin so that the compiler's own
+// wait insertion knows those reads have landed), then s_barrier.  Unlike
+// __syncthreads() it does not drain the global loads in flight (the
+// direct-to-LDS loads of later stages).  The memory clobber keeps the
+// compiler from moving LDS accesses across it.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_s_waitcnt(0xC07F);  // vmcnt 63, expcnt 7, lgkmcnt 0
+  asm volatile("s_barrier" ::: "memory");
+}
 
 // s_waitcnt with only the vector-memory counter constrained (vmcnt <= n).
 template <int N>
@@ -53,53 +59,137 @@ __device__ __forceinline__ void wait_vmcnt() {
 }
 
 // This wave's share of the direct-to-LDS loads of one stage: chunk j of the
-// wave is chunk q = 4 j + wave of the stage (A slabs first, then B).  The
-// wave index is made wave-uniform (readfirstlane) so that every address is
-// scalar except the 16-byte lane offset, and each chunk's source advances by
-// a fixed stride per K step.
+// wave is chunk q = 4 j + wave of the stage (A slabs first, then B).  When
+// the stage's chunk count is not a multiple of 4, the waves without a chunk
+// of their own reload the last one (the same bytes to the same LDS address),
+// so that every wave issues exactly NQ loads and the vmcnt thresholds below
+// are exact.  Addresses: a wave-uniform 64-bit base per operand that advances
+// by one K step per stage, a wave-uniform 32-bit offset per chunk, and the
+// lane's 16-byte offset as the only per-lane value.
 template <int P, int TM, int TN, int NS>
 struct StageLoads {
   using T = GemmTile<P, TM, TN, NS>;
   static constexpr int NQ = (T::CHUNKS + 3) / 4;
-  const int8_t* src[NQ];  // chunk source at step 0 (wave-uniform)
-  int64_t stride[NQ];     // bytes per K step
-  int dst[NQ];            // byte offset inside a stage
-  int count;              // chunks this wave issues (NQ or NQ - 1)
+  static constexpr int A_CH = T::A_BYTES / 1024;
+  const int8_t* a_next;  // A tile rows at the next K step to issue
+  const int8_t* b_next;
+  int64_t a_step, b_step;  // bytes per K step
+  uint32_t off[NQ];        // chunk offset from its operand's base
+  uint32_t dst[NQ];        // byte offset inside a stage
 
   __device__ __forceinline__ StageLoads(const int8_t* Ap, const int8_t* Bp, int64_t rows_a, int64_t rows_b,
-                                        int64_t m0, int64_t n0, int wave) {
-    constexpr int A_CH = T::A_BYTES / 1024;
-    count = 0;
+                                        int64_t m0, int64_t n0, int64_t step0, int wave) {
+    a_step = (int64_t)P * rows_a * OZK_K_CHUNK;
+    b_step = (int64_t)P * rows_b * OZK_K_CHUNK;
+    a_next = Ap + m0 * OZK_K_CHUNK + step0 * a_step;
+    b_next = Bp + n0 * OZK_K_CHUNK + step0 * b_step;
 #pragma unroll
     for (int j = 0; j < NQ; ++j) {
-      const int q = 4 * j + wave;
-      if (q < T::CHUNKS) count = j + 1;
+      int q = 4 * j + wave;
+      q = q < T::CHUNKS ? q : T::CHUNKS - 1;
       if (q < A_CH) {
         const int t = q / (T::BM / 32), blk = q % (T::BM / 32);
-        src[j] = Ap + ((int64_t)t * rows_a + m0 + 32 * blk) * OZK_K_CHUNK;
-        stride[j] = (int64_t)P * rows_a * OZK_K_CHUNK;
-        dst[j] = t * T::BM * OZK_K_CHUNK + blk * 1024;
+        off[j] = (uint32_t)(t * rows_a * OZK_K_CHUNK + blk * 1024);
+        dst[j] = (uint32_t)(t * T::BM * OZK_K_CHUNK + blk * 1024);
       } else {
-        const int qb = q < T::CHUNKS ? q - A_CH : 0;
+        const int qb = q - A_CH;
         const int t = qb / (T::BN / 32), blk = qb % (T::BN / 32);
-        src[j] = Bp + ((int64_t)t * rows_b + n0 + 32 * blk) * OZK_K_CHUNK;
-        stride[j] = (int64_t)P * rows_b * OZK_K_CHUNK;
-        dst[j] = T::A_BYTES + t * T::BN * OZK_K_CHUNK + blk * 1024;
+        off[j] = (uint32_t)(t * rows_b * OZK_K_CHUNK + blk * 1024);
+        dst[j] = (uint32_t)(T::A_BYTES + t * T::BN * OZK_K_CHUNK + blk * 1024);
       }
     }
   }
 
-  __device__ __forceinline__ void issue(int64_t step, int8_t* stage_lds, int lane16) const {
+  // Loads of the next K step into the stage at stage_lds.
+  __device__ __forceinline__ void issue(int8_t* stage_lds, uint32_t lane16, int wave) {
 #pragma unroll
-    for (int j = 0; j < NQ; ++j)
-      if (j < count)
-        __builtin_amdgcn_global_load_lds(reinterpret_cast<const void*>(src[j] + step * stride[j] + lane16),
-                                         reinterpret_cast<void*>(stage_lds + dst[j]), 16, 0, 0);
+    for (int j = 0; j < NQ; ++j) {
+      // A or B chunk: decided at compile time unless j's group of 4 chunks
+      // straddles the end of the A slabs
+      const bool is_a = (4 * j + 3 < A_CH) || (4 * j < A_CH && 4 * j + wave < A_CH);
+      const int8_t* base = is_a ? a_next : b_next;
+      __builtin_amdgcn_global_load_lds(reinterpret_cast<const void*>(base + off[j] + lane16),
+                                       reinterpret_cast<void*>(stage_lds + dst[j]), 16, 0, 0);
+    }
+    a_next += a_step;
+    b_next += b_step;
   }
 };
 
+// The MFMA operands of one K step for one wave: P planes of TM A fragments
+// and TN B fragments (16 bytes per lane each).
+template <int P, int TM, int TN>
+struct StepFrags {
+  v4i a[P][TM];
+  v4i b[P][TN];
+};
+
+// Read a step's fragments from its LDS stage (issued only: the caller's next
+// lds_barrier waits for them).  Order of first use: B plane 0, the A planes,
+// then B planes 1..P-1.
+template <int P, int TM, int TN, int NS>
+__device__ __forceinline__ void read_frags(StepFrags<P, TM, TN>& F, const int8_t* la, int wm, int wn, int lrow,
+                                           int lk) {
+  using T = GemmTile<P, TM, TN, NS>;
+  const int8_t* lb = la + T::A_BYTES;
+#pragma unroll
+  for (int b = 0; b < TN; ++b)
+    F.b[0][b] = *reinterpret_cast<const v4i*>(lb + (wn * 32 * TN + b * 32 + lrow) * OZK_K_CHUNK + lk);
+#pragma unroll
+  for (int t = 0; t < P; ++t)
+#pragma unroll
+    for (int a = 0; a < TM; ++a)
+      F.a[t][a] = *reinterpret_cast<const v4i*>(la + (t * T::BM + wm * 32 * TM + a * 32 + lrow) * OZK_K_CHUNK + lk);
+#pragma unroll
+  for (int u = 1; u < P; ++u)
+#pragma unroll
+    for (int b = 0; b < TN; ++b)
+      F.b[u][b] = *reinterpret_cast<const v4i*>(lb + (u * T::BN + wn * 32 * TN + b * 32 + lrow) * OZK_K_CHUNK + lk);
+}
+
+template <int P, int TM, int TN>
+__device__ __forceinline__ void zero_frags(StepFrags<P, TM, TN>& F) {
+#pragma unroll
+  for (int t = 0; t < P; ++t) {
+#pragma unroll
+    for (int a = 0; a < TM; ++a) F.a[t][a] = v4i{0, 0, 0, 0};
+#pragma unroll
+    for (int b = 0; b < TN; ++b) F.b[t][b] = v4i{0, 0, 0, 0};
+  }
+}
+
+template <int P, int TM, int TN, int PAIR>
+__device__ __forceinline__ void step_mfmas(const StepFrags<P, TM, TN>& F, v16i (&acc)[P][TM][TN]) {
+#pragma unroll
+  for (int u = 0; u < P; ++u) {
+    if (PAIR == TRIANGULAR) {
+#pragma unroll
+      for (int t = 0; t + u < P; ++t)
+#pragma unroll
+        for (int a = 0; a < TM; ++a)
+#pragma unroll
+          for (int b = 0; b < TN; ++b) acc[t + u][a][b] = mfma_i8_32x32x32(F.a[t][a], F.b[u][b], acc[t + u][a][b]);
+    } else {
+#pragma unroll
+      for (int a = 0; a < TM; ++a)
+#pragma unroll
+        for (int b = 0; b < TN; ++b) acc[u][a][b] = mfma_i8_32x32x32(F.a[u][a], F.b[u][b], acc[u][a][b]);
+    }
+  }
+}
+
 // Accumulate K steps [step0, step0 + nsteps) of the output tile at (m0, n0)
 // into acc.  rows_a / rows_b: padded row counts of the packed operands.
+//
+// K step r lives in LDS slot r mod NS.  Software pipeline, per step r (its
+// fragments already in registers): wait until stage r+1 has landed,
+// barrier (every wave is also done reading slot r mod NS), refill that slot
+// with stage r+NS, issue the fragment reads of step r+1 into the other
+// register set, then the MFMAs of step r, which run while those reads
+// complete.  The two register sets alternate, so steps are processed in
+// pairs; an odd step count is made even by a leading virtual step r = -1
+// with zero fragments (its MFMAs add nothing).  Inside the loop every step
+// has a real successor, so no branch there defines a register.
 template <int P, int TM, int TN, int NS, int PAIR>
 __device__ __forceinline__ void gemm_tile_accumulate(const int8_t* __restrict__ Ap, const int8_t* __restrict__ Bp,
                                                      int64_t rows_a, int64_t rows_b, int64_t m0, int64_t n0,
@@ -110,50 +200,45 @@ __device__ __forceinline__ void gemm_tile_accumulate(const int8_t* __restrict__ 
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int wm = wave >> 1, wn = wave & 1;
   const int lrow = lane & 31, lk = 16 * (lane >> 5);
-  const StageLoads<P, TM, TN, NS> ld(Ap, Bp, rows_a, rows_b, m0, n0, wave);
-  // prologue: stages 0 .. NS-2
+  StageLoads<P, TM, TN, NS> ld(Ap, Bp, rows_a, rows_b, m0, n0, step0, wave);
+  if (nsteps <= 0) return;
+  const uint32_t lane16 = 16u * (uint32_t)lane;
+  const int lead = (int)(nsteps & 1);  // 1: a virtual step -1 comes first
+  // stages issued ahead: 0 .. NS-1 (NS-2 with the virtual step, whose own
+  // refill issues stage NS-1)
 #pragma unroll
-  for (int s = 0; s < NS - 1; ++s)
-    if (s < nsteps) ld.issue(step0 + s, lds + s * T::STAGE, 16 * lane);
-  int cur = 0;           // stage holding K step s
-  int nxt = NS - 1;      // stage receiving K step s + NS - 1
-  for (int64_t s = 0; s < nsteps; ++s) {
-    // stage s complete for this wave: at most NS-2 later stages outstanding
-    if (s + NS - 2 < nsteps) wait_vmcnt<(NS - 2) * T::CHUNKS_MIN>();
+  for (int s = 0; s < NS; ++s)
+    if (s < nsteps && (s < NS - 1 || !lead)) ld.issue(lds + s * T::STAGE, lane16, wave);
+  StepFrags<P, TM, TN> F0, F1;
+  if (lead) {
+    zero_frags<P, TM, TN>(F0);
+  } else {
+    if (nsteps >= NS) wait_vmcnt<(NS - 1) * T::WAVE_LOADS>();
     else wait_vmcnt<0>();
-    lds_barrier();  // every wave's part of stage s is in LDS; stage s-1 is free
-    if (s + NS - 1 < nsteps) ld.issue(step0 + s + NS - 1, lds + nxt * T::STAGE, 16 * lane);
-    const int8_t* la = lds + cur * T::STAGE;
-    const int8_t* lb = la + T::A_BYTES;
-    cur = cur + 1 == NS ? 0 : cur + 1;
-    nxt = nxt + 1 == NS ? 0 : nxt + 1;
-    v4i fa[P][TM];
-#pragma unroll
-    for (int t = 0; t < P; ++t)
-#pragma unroll
-      for (int a = 0; a < TM; ++a)
-        fa[t][a] = *reinterpret_cast<const v4i*>(la + (t * T::BM + wm * 32 * TM + a * 32 + lrow) * OZK_K_CHUNK + lk);
-#pragma unroll
-    for (int u = 0; u < P; ++u) {
-      v4i fb[TN];
-#pragma unroll
-      for (int b = 0; b < TN; ++b)
-        fb[b] = *reinterpret_cast<const v4i*>(lb + (u * T::BN + wn * 32 * TN + b * 32 + lrow) * OZK_K_CHUNK + lk);
-      if (PAIR == TRIANGULAR) {
-#pragma unroll
-        for (int t = 0; t + u < P; ++t)
-#pragma unroll
-          for (int a = 0; a < TM; ++a)
-#pragma unroll
-            for (int b = 0; b < TN; ++b) acc[t + u][a][b] = mfma_i8_32x32x32(fa[t][a], fb[b], acc[t + u][a][b]);
-      } else {
-#pragma unroll
-        for (int a = 0; a < TM; ++a)
-#pragma unroll
-          for (int b = 0; b < TN; ++b) acc[u][a][b] = mfma_i8_32x32x32(fa[u][a], fb[b], acc[u][a][b]);
-      }
-    }
+    lds_barrier();
+    read_frags<P, TM, TN, NS>(F0, lds, wm, wn, lrow, lk);
   }
+  int slot = lead ? NS - 1 : 0;  // slot of step r (the virtual step: the slot stage NS-1 goes to)
+  // Step r = v - lead with a real successor q = r + 1: MFMAs from Fc, the
+  // fragments of q into Fn.
+  auto step = [&](int64_t v, const StepFrags<P, TM, TN>& Fc, StepFrags<P, TM, TN>& Fn) {
+    const int64_t r = v - lead, q = r + 1;
+    if (q + NS - 2 < nsteps) wait_vmcnt<(NS - 2) * T::WAVE_LOADS>();  // stages q+1 .. q+NS-2 may stay in flight
+    else wait_vmcnt<0>();
+    lds_barrier();
+    if (r + NS < nsteps) ld.issue(lds + slot * T::STAGE, lane16, wave);
+    slot = slot + 1 == NS ? 0 : slot + 1;
+    read_frags<P, TM, TN, NS>(Fn, lds + slot * T::STAGE, wm, wn, lrow, lk);
+    step_mfmas<P, TM, TN, PAIR>(Fc, acc);
+  };
+  const int64_t total = nsteps + lead;  // even, >= 2
+  int64_t v = 0;
+  for (; v + 2 < total; v += 2) {
+    step(v, F0, F1);
+    step(v + 1, F1, F0);
+  }
+  step(v, F0, F1);  // the last pair: its second step has no successor
+  step_mfmas<P, TM, TN, PAIR>(F1, acc);
   lds_barrier();  // LDS free for the caller's next use
 }
 
@@ -168,18 +253,20 @@ __device__ __forceinline__ void zero_acc(v16i (&acc)[P][TM][TN]) {
 }
 
 // Workgroup -> output tile.  Workgroups are dispatched round-robin over the
-// 8 XCDs (each with its own L2): when the tile count divides by 8, XCD x
-// takes a contiguous eighth of the tiles, walked in groups of G tile rows,
-// so the ~32 tiles an XCD runs at once form a compact block whose A rows and
-// B columns its L2 can keep.
-__device__ __forceinline__ void tile_of(int64_t id, int64_t tiles_m, int64_t tiles_n, int64_t& tm, int64_t& tn) {
+// 8 XCDs (each with its own L2).  raster 0: when the tile count divides by 8,
+// XCD x takes a contiguous eighth of the tiles, so the ~32 tiles an XCD runs
+// at once form a compact block whose A rows and B columns its L2 can keep;
+// raster 1: dispatch order as is.  Either way the linear order is walked in
+// groups of `group` tile rows (column-major inside a group).
+__device__ __forceinline__ void tile_of(int64_t id, int64_t tiles_m, int64_t tiles_n, int raster, int group,
+                                        int64_t& tm, int64_t& tn) {
   const int64_t T = tiles_m * tiles_n;
   int64_t lin = id;
-  if (T % 8 == 0) lin = (id % 8) * (T / 8) + id / 8;
-  const int64_t G = 4;
+  if (raster == 0 && T % 8 == 0) lin = (id % 8) * (T / 8) + id / 8;
+  const int64_t G = group > 0 ? group : 1;
   const int64_t per_group = G * tiles_n;
-  const int64_t group = lin / per_group;
-  const int64_t first = group * G;
+  const int64_t grp = lin / per_group;
+  const int64_t first = grp * G;
   const int64_t gm = tiles_m - first < G ? tiles_m - first : G;
   const int64_t r = lin % per_group;
   tm = first + r % gm;

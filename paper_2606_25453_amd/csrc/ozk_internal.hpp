@@ -23,6 +23,9 @@ struct S1GemmArgs {
   int64_t ldc;
   int64_t* zpart;  // nsplit x M x N x 2 int64 when nsplit > 1
   int32_t* diag;   // p x M x N int32 for the check entry point, else null
+  int variant = 0;  // tile variant (0 .. OZK_S1_VARIANTS - 1)
+  int raster = 0;   // 0: XCD-aware tile order, 1: plain
+  int group = 4;    // tile rows per raster group
 };
 
 hipError_t s1_split_rows(int p, const double* X, int64_t ldx, int64_t rows, int64_t K, int32_t* e,
@@ -89,7 +92,7 @@ hipError_t s2_split_rows(int s, bool cplx, const double* X, int64_t ldx, int64_t
 hipError_t s2_split_cols(int s, bool cplx, const double* X, int64_t ldx, int64_t K, int64_t cols, int32_t* tau,
                          int8_t* packed, hipStream_t st);
 hipError_t s2_gemm_mod(int s, bool cplx, int64_t M, int64_t N, int64_t K, const int8_t* Ap, const int8_t* Bp,
-                       int8_t* out, hipStream_t st);
+                       int8_t* out, hipStream_t st, int variant = 0, int raster = 0, int group = 4);
 hipError_t s2_crt(int s, bool cplx, int64_t M, int64_t N, const int8_t* res, const int32_t* sigma,
                   const int32_t* tau, const double* alpha, const double* beta, double* C, int64_t ldc,
                   hipStream_t st);

@@ -4,13 +4,14 @@
 //                     written in the interleaved packed layout (Eq. 11)
 //   k_s1_exp_cols     column exponents of a column operand (atomic max)
 //   k_s1_split_cols   slices of a column operand, transposed on the fly
-//   k_s1_gemm         fused kernel: p(p+1)/2 slice-pair MFMAs per K step into
-//                     p INT32 diagonals kept in registers (Alg. 1), then the
-//                     exact integer shift-reduce and one rounding per output
+//   k_s1_gemm         fused kernel (s1_gemm.hpp, instantiated per p in
+//                     s1_gemm_inst.hip): p(p+1)/2 slice-pair MFMAs per K step
+//                     into p INT32 diagonals kept in registers (Alg. 1), then
+//                     the exact integer shift-reduce and one rounding per output
 //   k_s1_fold         exact sum of the per-K-run 128-bit partials (long K)
-#include "mfma_gemm.hpp"
 #include "ozk_device.hpp"
 #include "ozk_internal.hpp"
+#include "s1_gemm.hpp"
 
 namespace ozk {
 
@@ -183,104 +184,6 @@ __global__ __launch_bounds__(256) void k_s1_split_cols_auto(const double* __rest
   }
 }
 
-// ------------------------------------------------------------- fused GEMM
-
-template <int P>
-struct S1Cfg {
-  // p <= 4: 2 x 2 MFMA tiles per wave (128 x 128 workgroup tile, 16p*4 acc
-  // registers); p >= 5: 2 x 1 (128 x 64).  Stages: as many as fit 160 KB.
-  static constexpr int TM = 2;
-  static constexpr int TN = P <= 4 ? 2 : 1;
-  static constexpr int NS = P <= 2 ? 4 : 3;
-};
-
-enum S1Out { S1_OUT_FINAL = 0, S1_OUT_PARTIAL = 1, S1_OUT_DIAG = 2 };
-
-struct S1KArgs {
-  const int8_t* Ap;
-  const int8_t* Bp;
-  int64_t rows_a, rows_b, nchunk_total, steps_per_split;
-  int M, N;
-  const int32_t* e_row;
-  const int32_t* f_col;
-  double alpha, beta;
-  double* C;
-  int64_t ldc;
-  int64_t* zpart;
-  int32_t* diag;
-};
-
-// One output tile (workgroup tile index `tile`, K run z): the triangular
-// MFMA accumulation, then the epilogue selected by OUT.
-template <int P, int OUT, int TM, int TN, int NS>
-__device__ __forceinline__ void s1_gemm_tile(const S1KArgs& g, int64_t tile, int64_t z, int8_t* lds) {
-  using T = GemmTile<P, TM, TN, NS>;
-  const int64_t M = g.M, N = g.N;
-  const int64_t tiles_m = (M + T::BM - 1) / T::BM, tiles_n = (N + T::BN - 1) / T::BN;
-  int64_t tm, tn;
-  tile_of(tile, tiles_m, tiles_n, tm, tn);
-  const int64_t m0 = tm * T::BM, n0 = tn * T::BN;
-  const int64_t step0 = z * g.steps_per_split;
-  int64_t nsteps = g.nchunk_total - step0;
-  if (nsteps > g.steps_per_split) nsteps = g.steps_per_split;
-
-  v16i acc[P][TM][TN];
-  zero_acc<P, TM, TN>(acc);
-  gemm_tile_accumulate<P, TM, TN, NS, TRIANGULAR>(g.Ap, g.Bp, g.rows_a, g.rows_b, m0, n0, step0, nsteps, lds, acc);
-
-  for_each_output<P, TM, TN>(acc, m0, n0, M, N, [&](int64_t row, int64_t col, const int* vals) {
-    if (OUT == S1_OUT_DIAG) {
-#pragma unroll
-      for (int d = 0; d < P; ++d) g.diag[((int64_t)d * M + row) * N + col] = vals[d];
-      return;
-    }
-    i128 Z = 0;
-#pragma unroll
-    for (int d = 0; d < P; ++d) Z += (i128)vals[d] << (8 * (P - 1 - d));
-    if (OUT == S1_OUT_PARTIAL) {
-      int64_t* zp = g.zpart + 2 * ((z * M + row) * N + col);
-      zp[0] = (int64_t)(uint64_t)(u128)Z;
-      zp[1] = (int64_t)(Z >> 64);
-      return;
-    }
-    const int er = g.e_row[row], fc = g.f_col[col];
-    double h;
-    if (er == OZK_EXP_NONFINITE || fc == OZK_EXP_NONFINITE) h = __builtin_nan("");
-    else if (er == OZK_EXP_ZERO || fc == OZK_EXP_ZERO) h = 0.0;
-    else h = round_scaled(Z, er + fc - 12 - 8 * (P - 1));
-    double* cp = g.C + row * g.ldc + col;
-    *cp = axpby(g.alpha, h, g.beta, cp);
-  });
-}
-
-template <int P, int OUT>
-__global__ __launch_bounds__(256, 1) void k_s1_gemm(S1KArgs g) {
-  using Cfg = S1Cfg<P>;
-  extern __shared__ __attribute__((aligned(1024))) int8_t lds[];
-  s1_gemm_tile<P, OUT, Cfg::TM, Cfg::TN, Cfg::NS>(g, blockIdx.x, blockIdx.z, lds);
-}
-
-// The slice count read from device memory: one tiling for every p (128 x 64,
-// 3 stages, LDS sized for p = 8).
-constexpr int S1_AUTO_TM = 2, S1_AUTO_TN = 1, S1_AUTO_NS = 3;
-using S1AutoTile = GemmTile<8, S1_AUTO_TM, S1_AUTO_TN, S1_AUTO_NS>;
-
-template <int OUT>
-__global__ __launch_bounds__(256, 1) void k_s1_gemm_auto(S1KArgs g, const int32_t* __restrict__ p_dev) {
-  extern __shared__ __attribute__((aligned(1024))) int8_t lds[];
-  const int64_t tile = blockIdx.x, z = blockIdx.z;
-  switch (*p_dev) {
-    case 1: s1_gemm_tile<1, OUT, S1_AUTO_TM, S1_AUTO_TN, S1_AUTO_NS>(g, tile, z, lds); break;
-    case 2: s1_gemm_tile<2, OUT, S1_AUTO_TM, S1_AUTO_TN, S1_AUTO_NS>(g, tile, z, lds); break;
-    case 3: s1_gemm_tile<3, OUT, S1_AUTO_TM, S1_AUTO_TN, S1_AUTO_NS>(g, tile, z, lds); break;
-    case 4: s1_gemm_tile<4, OUT, S1_AUTO_TM, S1_AUTO_TN, S1_AUTO_NS>(g, tile, z, lds); break;
-    case 5: s1_gemm_tile<5, OUT, S1_AUTO_TM, S1_AUTO_TN, S1_AUTO_NS>(g, tile, z, lds); break;
-    case 6: s1_gemm_tile<6, OUT, S1_AUTO_TM, S1_AUTO_TN, S1_AUTO_NS>(g, tile, z, lds); break;
-    case 7: s1_gemm_tile<7, OUT, S1_AUTO_TM, S1_AUTO_TN, S1_AUTO_NS>(g, tile, z, lds); break;
-    default: s1_gemm_tile<8, OUT, S1_AUTO_TM, S1_AUTO_TN, S1_AUTO_NS>(g, tile, z, lds); break;
-  }
-}
-
 // Exact fold of the K-run partials followed by the single rounding.
 __global__ __launch_bounds__(256) void k_s1_fold(const int64_t* __restrict__ zpart, int nsplit, int M, int N,
                                                  int p, const int32_t* __restrict__ p_dev,
@@ -334,60 +237,6 @@ static hipError_t launch_split_cols(const double* X, int64_t ldx, int64_t K, int
   return hipGetLastError();
 }
 
-static S1KArgs kargs_of(const S1GemmArgs& g) {
-  S1KArgs k;
-  k.Ap = g.Ap;
-  k.Bp = g.Bp;
-  k.rows_a = round_up(g.M, OZK_ROW_ALIGN);
-  k.rows_b = round_up(g.N, OZK_ROW_ALIGN);
-  k.nchunk_total = g.nchunk;
-  k.steps_per_split = g.steps_per_split;
-  k.M = (int)g.M;
-  k.N = (int)g.N;
-  k.e_row = g.e;
-  k.f_col = g.f;
-  k.alpha = g.alpha;
-  k.beta = g.beta;
-  k.C = g.C;
-  k.ldc = g.ldc;
-  k.zpart = g.zpart;
-  k.diag = g.diag;
-  return k;
-}
-
-template <int P, int OUT>
-static hipError_t launch_gemm_p(const S1GemmArgs& g, hipStream_t st) {
-  using Cfg = S1Cfg<P>;
-  using T = GemmTile<P, Cfg::TM, Cfg::TN, Cfg::NS>;
-  auto kern = k_s1_gemm<P, OUT>;
-  static bool attr_set = false;
-  if (!attr_set) {
-    hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
-                                         hipFuncAttributeMaxDynamicSharedMemorySize, T::LDS_BYTES);
-    if (err != hipSuccess) return err;
-    attr_set = true;
-  }
-  const int64_t tiles = ((g.M + T::BM - 1) / T::BM) * ((g.N + T::BN - 1) / T::BN);
-  const dim3 grid((unsigned)tiles, 1, (unsigned)g.nsplit);
-  hipLaunchKernelGGL(kern, grid, dim3(256), T::LDS_BYTES, st, kargs_of(g));
-  return hipGetLastError();
-}
-
-template <int OUT>
-static hipError_t launch_gemm_out(int p, const S1GemmArgs& g, hipStream_t st) {
-  switch (p) {
-    case 1: return launch_gemm_p<1, OUT>(g, st);
-    case 2: return launch_gemm_p<2, OUT>(g, st);
-    case 3: return launch_gemm_p<3, OUT>(g, st);
-    case 4: return launch_gemm_p<4, OUT>(g, st);
-    case 5: return launch_gemm_p<5, OUT>(g, st);
-    case 6: return launch_gemm_p<6, OUT>(g, st);
-    case 7: return launch_gemm_p<7, OUT>(g, st);
-    case 8: return launch_gemm_p<8, OUT>(g, st);
-  }
-  return hipErrorInvalidValue;
-}
-
 hipError_t s1_split_rows(int p, const double* X, int64_t ldx, int64_t rows, int64_t K, int32_t* e,
                          int8_t* packed, hipStream_t st) {
   switch (p) {
@@ -418,18 +267,35 @@ hipError_t s1_split_cols(int p, const double* X, int64_t ldx, int64_t K, int64_t
   return hipErrorInvalidValue;
 }
 
+static hipError_t gemm_launch(int p, int out, const S1GemmArgs& g, const int32_t* p_dev, hipStream_t st) {
+  switch (p) {
+    case 1: return s1_gemm_launch<1>(out, g, p_dev, st);
+    case 2: return s1_gemm_launch<2>(out, g, p_dev, st);
+    case 3: return s1_gemm_launch<3>(out, g, p_dev, st);
+    case 4: return s1_gemm_launch<4>(out, g, p_dev, st);
+    case 5: return s1_gemm_launch<5>(out, g, p_dev, st);
+    case 6: return s1_gemm_launch<6>(out, g, p_dev, st);
+    case 7: return s1_gemm_launch<7>(out, g, p_dev, st);
+    case 8: return s1_gemm_launch<8>(out, g, p_dev, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+static hipError_t launch_fold(int p, const int32_t* p_dev, const S1GemmArgs& g, hipStream_t st) {
+  const int64_t n = g.M * g.N;
+  hipLaunchKernelGGL(k_s1_fold, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, g.zpart, (int)g.nsplit,
+                     (int)g.M, (int)g.N, p, p_dev, g.e, g.f, g.alpha, g.beta, g.C, g.ldc);
+  return hipGetLastError();
+}
+
 hipError_t s1_gemm(int p, const S1GemmArgs& g, hipStream_t st) {
   if (g.M == 0 || g.N == 0) return hipSuccess;
-  if (g.diag) return launch_gemm_out<S1_OUT_DIAG>(p, g, st);
+  if (g.diag) return gemm_launch(p, S1_OUT_DIAG, g, nullptr, st);
   if (g.nsplit > 1) {
-    hipError_t err = launch_gemm_out<S1_OUT_PARTIAL>(p, g, st);
-    if (err != hipSuccess) return err;
-    const int64_t n = g.M * g.N;
-    hipLaunchKernelGGL(k_s1_fold, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, g.zpart, (int)g.nsplit,
-                       (int)g.M, (int)g.N, p, (const int32_t*)nullptr, g.e, g.f, g.alpha, g.beta, g.C, g.ldc);
-    return hipGetLastError();
+    hipError_t err = gemm_launch(p, S1_OUT_PARTIAL, g, nullptr, st);
+    return err == hipSuccess ? launch_fold(p, nullptr, g, st) : err;
   }
-  return launch_gemm_out<S1_OUT_FINAL>(p, g, st);
+  return gemm_launch(p, S1_OUT_FINAL, g, nullptr, st);
 }
 
 // ---------------------------------------------------- slice count on device
@@ -447,30 +313,20 @@ hipError_t s1_slice_auto(const int32_t* p_dev, const double* A, int64_t lda, int
   return hipGetLastError();
 }
 
+// Every fixed-p kernel is launched; each returns at once unless p_dev holds
+// its slice count, so the chosen p runs with its own tiling and no host
+// round trip.
+static hipError_t launch_gemm_all(int out, const int32_t* p_dev, const S1GemmArgs& g, hipStream_t st) {
+  hipError_t err = hipSuccess;
+  for (int p = 1; p <= OZK_MAX_P && err == hipSuccess; ++p) err = gemm_launch(p, out, g, p_dev, st);
+  return err;
+}
+
 hipError_t s1_gemm_auto(const int32_t* p_dev, const S1GemmArgs& g, hipStream_t st) {
   if (g.M == 0 || g.N == 0) return hipSuccess;
-  using T = S1AutoTile;
-  static bool attr[2] = {false, false};
-  const bool part = g.nsplit > 1;
-  if (!attr[part]) {
-    hipError_t err = part ? hipFuncSetAttribute(reinterpret_cast<const void*>(k_s1_gemm_auto<S1_OUT_PARTIAL>),
-                                                hipFuncAttributeMaxDynamicSharedMemorySize, T::LDS_BYTES)
-                          : hipFuncSetAttribute(reinterpret_cast<const void*>(k_s1_gemm_auto<S1_OUT_FINAL>),
-                                                hipFuncAttributeMaxDynamicSharedMemorySize, T::LDS_BYTES);
-    if (err != hipSuccess) return err;
-    attr[part] = true;
-  }
-  const int64_t tiles = ((g.M + T::BM - 1) / T::BM) * ((g.N + T::BN - 1) / T::BN);
-  const dim3 grid((unsigned)tiles, 1, (unsigned)g.nsplit);
-  if (!part) {
-    hipLaunchKernelGGL(k_s1_gemm_auto<S1_OUT_FINAL>, grid, dim3(256), T::LDS_BYTES, st, kargs_of(g), p_dev);
-    return hipGetLastError();
-  }
-  hipLaunchKernelGGL(k_s1_gemm_auto<S1_OUT_PARTIAL>, grid, dim3(256), T::LDS_BYTES, st, kargs_of(g), p_dev);
-  const int64_t n = g.M * g.N;
-  hipLaunchKernelGGL(k_s1_fold, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, g.zpart, (int)g.nsplit,
-                     (int)g.M, (int)g.N, 8, p_dev, g.e, g.f, g.alpha, g.beta, g.C, g.ldc);
-  return hipGetLastError();
+  if (g.nsplit <= 1) return launch_gemm_all(S1_OUT_FINAL, p_dev, g, st);
+  hipError_t err = launch_gemm_all(S1_OUT_PARTIAL, p_dev, g, st);
+  return err == hipSuccess ? launch_fold(OZK_MAX_P, p_dev, g, st) : err;
 }
 
 }  // namespace ozk

@@ -329,26 +329,27 @@ __global__ __launch_bounds__(256) void k_s2_split_cols(const double* __restrict_
 // reduction is exact because only the residue is kept.
 constexpr int64_t S2_RUN_STEPS = 4095;
 
-template <bool CPLX>
+// Tiling of the per-modulus GEMM; variant V = 1 uses one LDS stage fewer.
+template <bool CPLX, int V = 0>
 struct S2Cfg {
   static constexpr int P = CPLX ? 3 : 1;
   static constexpr int TM = 2, TN = CPLX ? 1 : 2;
-  static constexpr int NS = 4;
+  static constexpr int NS = 4 - V;
 };
 
 // One output tile of one modulus: the per-modulus products, then smod (3M:
 // the combination first) and the int8 output residues.
-template <bool CPLX>
+template <bool CPLX, int V>
 __device__ __forceinline__ void s2_gemm_tile(const int8_t* __restrict__ Ap, const int8_t* __restrict__ Bp,
                                              int64_t plane_a, int64_t plane_b, int64_t rows_a, int64_t rows_b,
                                              int64_t nsteps, int64_t M, int64_t N, int8_t* __restrict__ out,
-                                             int64_t tile, int l, int8_t* lds) {
-  using Cfg = S2Cfg<CPLX>;
+                                             int64_t tile, int l, int raster, int group, int8_t* lds) {
+  using Cfg = S2Cfg<CPLX, V>;
   constexpr int P = Cfg::P, TM = Cfg::TM, TN = Cfg::TN, NS = Cfg::NS;
   using T = GemmTile<P, TM, TN, NS>;
   const int64_t tiles_m = (M + T::BM - 1) / T::BM, tiles_n = (N + T::BN - 1) / T::BN;
   int64_t tm, tn;
-  tile_of(tile, tiles_m, tiles_n, tm, tn);
+  tile_of(tile, tiles_m, tiles_n, raster, group, tm, tn);
   const int64_t m0 = tm * T::BM, n0 = tn * T::BN;
   v16i acc[P][TM][TN];
   zero_acc<P, TM, TN>(acc);
@@ -385,14 +386,15 @@ __device__ __forceinline__ void s2_gemm_tile(const int8_t* __restrict__ Ap, cons
   });
 }
 
-template <bool CPLX>
+template <bool CPLX, int V>
 __global__ __launch_bounds__(256, 1) void k_s2_gemm_mod(const int8_t* __restrict__ Ap,
                                                        const int8_t* __restrict__ Bp, int64_t plane_a,
                                                        int64_t plane_b, int64_t rows_a, int64_t rows_b,
-                                                       int64_t nsteps, int M, int N, int8_t* __restrict__ out) {
+                                                       int64_t nsteps, int M, int N, int raster, int group,
+                                                       int8_t* __restrict__ out) {
   extern __shared__ __attribute__((aligned(1024))) int8_t lds[];
-  s2_gemm_tile<CPLX>(Ap, Bp, plane_a, plane_b, rows_a, rows_b, nsteps, M, N, out, blockIdx.x, (int)blockIdx.z,
-                     lds);
+  s2_gemm_tile<CPLX, V>(Ap, Bp, plane_a, plane_b, rows_a, rows_b, nsteps, M, N, out, blockIdx.x, (int)blockIdx.z,
+                        raster, group, lds);
 }
 
 // ------------------------------------------------------------------- CRT
@@ -695,13 +697,13 @@ hipError_t s2_split_cols(int s, bool cplx, const double* X, int64_t ldx, int64_t
   return hipGetLastError();
 }
 
-template <bool CPLX>
+template <bool CPLX, int V>
 static hipError_t launch_gemm_mod(int s, int64_t M, int64_t N, int64_t K, const int8_t* Ap, const int8_t* Bp,
-                                  int8_t* out, hipStream_t st) {
-  using Cfg = S2Cfg<CPLX>;
+                                  int8_t* out, int raster, int group, hipStream_t st) {
+  using Cfg = S2Cfg<CPLX, V>;
   constexpr int P = Cfg::P;
   using T = GemmTile<P, Cfg::TM, Cfg::TN, Cfg::NS>;
-  auto kern = k_s2_gemm_mod<CPLX>;
+  auto kern = k_s2_gemm_mod<CPLX, V>;
   static bool attr = false;
   if (!attr) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
@@ -715,15 +717,18 @@ static hipError_t launch_gemm_mod(int s, int64_t M, int64_t N, int64_t K, const 
   const int64_t tiles = ((M + T::BM - 1) / T::BM) * ((N + T::BN - 1) / T::BN);
   const dim3 grid((unsigned)tiles, 1, (unsigned)s);
   hipLaunchKernelGGL(kern, grid, dim3(256), T::LDS_BYTES, st, Ap, Bp, plane_a, plane_b, ra, rb, kp / OZK_K_CHUNK,
-                     (int)M, (int)N, out);
+                     (int)M, (int)N, raster, group, out);
   return hipGetLastError();
 }
 
 hipError_t s2_gemm_mod(int s, bool cplx, int64_t M, int64_t N, int64_t K, const int8_t* Ap, const int8_t* Bp,
-                       int8_t* out, hipStream_t st) {
+                       int8_t* out, hipStream_t st, int variant, int raster, int group) {
   if (M == 0 || N == 0) return hipSuccess;
-  return cplx ? launch_gemm_mod<true>(s, M, N, K, Ap, Bp, out, st)
-              : launch_gemm_mod<false>(s, M, N, K, Ap, Bp, out, st);
+  if (variant == 1)
+    return cplx ? launch_gemm_mod<true, 1>(s, M, N, K, Ap, Bp, out, raster, group, st)
+                : launch_gemm_mod<false, 1>(s, M, N, K, Ap, Bp, out, raster, group, st);
+  return cplx ? launch_gemm_mod<true, 0>(s, M, N, K, Ap, Bp, out, raster, group, st)
+              : launch_gemm_mod<false, 0>(s, M, N, K, Ap, Bp, out, raster, group, st);
 }
 
 hipError_t s2_crt(int s, bool cplx, int64_t M, int64_t N, const int8_t* res, const int32_t* sigma,
@@ -804,8 +809,8 @@ __global__ __launch_bounds__(256, 1) void k_b_gemm_mod(BatchDev bd, int8_t* __re
     const int64_t local = it - bd.item_start[i];
     const int l = (int)(local / q.tiles);
     const int64_t tile = local % q.tiles;
-    s2_gemm_tile<CPLX>(ws + q.off_a, ws + q.off_b, q.ra * q.Kp * NP, q.rb * q.Kp * NP, q.ra, q.rb,
-                       q.Kp / OZK_K_CHUNK, q.M, q.N, ws + q.off_res, tile, l, lds);
+    s2_gemm_tile<CPLX, 0>(ws + q.off_a, ws + q.off_b, q.ra * q.Kp * NP, q.rb * q.Kp * NP, q.ra, q.rb,
+                          q.Kp / OZK_K_CHUNK, q.M, q.N, ws + q.off_res, tile, l, 0, 4, lds);
   }
   (void)s;
 }

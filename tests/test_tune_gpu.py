@@ -1,0 +1,175 @@
+"""The autotuner through the C ABI: every candidate configuration (tile
+variant, raster order, raster group, K split) gives results bit-identical to
+the default configuration and to the oracle; ozk_tune stores its choice for
+the size class, later calls use it, and the table survives a JSON round
+trip."""
+import itertools
+import json
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2606_25453_amd as ozk
+import synth
+from oracle import scheme2 as s2
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture()
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = ozk.Context(0)
+    yield c
+    c.close()
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda:0")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+S1_CONFIGS = [c for c in itertools.product(range(ozk.OZK_S1_VARIANTS), (0, 1), (1, 4, 8), (1, 2, 3))]
+
+
+@pytest.mark.parametrize("p", [1, 3, 4, 5, 7, 8])
+def test_scheme1_every_config_is_bit_identical(ctx, p):
+    M, K, N = 200, 300, 137  # several tiles, ragged in every dimension
+    A = synth.phi_matrix(M, K, 1.0, 11 + p)
+    B = synth.phi_matrix(K, N, 1.0, 12 + p)
+    C0 = synth.phi_matrix(M, N, 1.0, 13)
+    dA, dB = dev(A), dev(B)
+    ref = ozk.ozk_dgemm(ctx, ozk.OZK_SCHEME1, p, dA, dB, dev(C0), alpha=0.5, beta=-2.0)
+    expect = oracle.s1_dgemm(A, B, p, alpha=0.5, beta=-2.0, C=C0)
+    assert np.array_equal(host(ref), expect)
+    for cfg in S1_CONFIGS:
+        ozk.ozk_config_set(ctx, ozk.OZK_OP_DGEMM, ozk.OZK_SCHEME1, p, M, N, K, cfg)
+        assert ozk.ozk_config_get(ctx, ozk.OZK_OP_DGEMM, ozk.OZK_SCHEME1, p, M, N, K)[0] == cfg
+        got = ozk.ozk_dgemm(ctx, ozk.OZK_SCHEME1, p, dA, dB, dev(C0), alpha=0.5, beta=-2.0)
+        assert torch.equal(got, ref), cfg
+
+
+def test_scheme1_configs_on_long_k_and_partial_tiles(ctx):
+    """K split on top of the runs INT32 exactness needs (K beyond k_split)."""
+    p = 6
+    K = ozk.ozk_s1_k_split(p) + 70
+    A = synth.phi_matrix(70, K, 0.5, 3)
+    B = synth.phi_matrix(K, 40, 0.5, 4)
+    dA, dB = dev(A), dev(B)
+    ref = ozk.ozk_dgemm(ctx, ozk.OZK_SCHEME1, p, dA, dB)
+    for cfg in [(1, 1, 2, 1), (2, 0, 4, 2), (3, 0, 1, 5)]:
+        ozk.ozk_config_set(ctx, ozk.OZK_OP_DGEMM, ozk.OZK_SCHEME1, p, 70, 40, K, cfg)
+        assert torch.equal(ozk.ozk_dgemm(ctx, ozk.OZK_SCHEME1, p, dA, dB), ref), cfg
+
+
+@pytest.mark.parametrize("cplx,s", [(False, 13), (True, 9)])
+def test_scheme2_every_config_is_bit_identical(ctx, cplx, s):
+    M, K, N = 150, 260, 99
+    if cplx:
+        A = synth.complex_phi_matrix(M, K, 1.0, 5, 6)
+        B = synth.complex_phi_matrix(K, N, 1.0, 7, 8)
+    else:
+        A = synth.phi_matrix(M, K, 1.0, 5)
+        B = synth.phi_matrix(K, N, 1.0, 7)
+    dA, dB = dev(A), dev(B)
+    op = ozk.OZK_OP_ZGEMM if cplx else ozk.OZK_OP_DGEMM
+
+    def run():
+        return ozk.ozk_zgemm_3m(ctx, s, dA, dB) if cplx else ozk.ozk_dgemm(ctx, ozk.OZK_SCHEME2, s, dA, dB)
+
+    ref = run()
+    expect = s2.z3m_gemm(A, B, s) if cplx else s2.s2_dgemm(A, B, s)
+    assert np.array_equal(host(ref), expect)
+    for cfg in itertools.product(range(ozk.OZK_S2_VARIANTS), (0, 1), (1, 4, 8), (1,)):
+        ozk.ozk_config_set(ctx, op, ozk.OZK_SCHEME2, s, M, N, K, cfg)
+        assert torch.equal(run(), ref), cfg
+
+
+@pytest.mark.parametrize("scheme,op,ps", [(ozk.OZK_SCHEME1, ozk.OZK_OP_DGEMM, 7),
+                                          (ozk.OZK_SCHEME2, ozk.OZK_OP_DGEMM, 14),
+                                          (ozk.OZK_SCHEME2, ozk.OZK_OP_ZGEMM, 16)])
+def test_tune_stores_choice_and_result_is_the_product(ctx, scheme, op, ps):
+    M, K, N = 520, 384, 270
+    if op == ozk.OZK_OP_ZGEMM:
+        A = synth.complex_phi_matrix(M, K, 1.0, 21, 22)
+        B = synth.complex_phi_matrix(K, N, 1.0, 23, 24)
+    else:
+        A = synth.phi_matrix(M, K, 1.0, 21)
+        B = synth.phi_matrix(K, N, 1.0, 23)
+    dA, dB = dev(A), dev(B)
+    assert not ozk.ozk_config_get(ctx, op, scheme, ps, M, N, K)[1]
+    C, best, ms = ozk.ozk_tune(ctx, op, scheme, ps, dA, dB, reps=2)
+    assert ms > 0
+    cfg, found, tms = ozk.ozk_config_get(ctx, op, scheme, ps, M, N, K)
+    assert found and cfg == best and tms == pytest.approx(ms)
+    # the same size class (M, N, K rounded up to powers of two) shares it
+    assert ozk.ozk_config_get(ctx, op, scheme, ps, 1000, 500, 300)[0] == best
+    if op == ozk.OZK_OP_ZGEMM:
+        default = ozk.ozk_zgemm_3m(ctx, ps, dA, dB)
+    else:
+        default = ozk.ozk_dgemm(ctx, scheme, ps, dA, dB)
+    assert torch.equal(C, default)
+    ozk.ozk_config_clear(ctx)
+    assert not ozk.ozk_config_get(ctx, op, scheme, ps, M, N, K)[1]
+    again = ozk.ozk_zgemm_3m(ctx, ps, dA, dB) if op == ozk.OZK_OP_ZGEMM else ozk.ozk_dgemm(ctx, scheme, ps, dA, dB)
+    assert torch.equal(again, C)
+
+
+def test_config_json_round_trip(ctx, tmp_path):
+    entries = [(ozk.OZK_OP_DGEMM, ozk.OZK_SCHEME1, 7, 8192, 8192, 8192, (2, 1, 8, 1)),
+               (ozk.OZK_OP_DGEMM, ozk.OZK_SCHEME1, 3, 100, 50, 70000, (1, 0, 4, 4)),
+               (ozk.OZK_OP_ZGEMM, ozk.OZK_SCHEME2, 16, 2048, 2048, 2048, (1, 1, 1, 1))]
+    for op, sch, ps, M, N, K, cfg in entries:
+        ozk.ozk_config_set(ctx, op, sch, ps, M, N, K, cfg)
+    path = str(tmp_path / "cfg.json")
+    ozk.ozk_config_save(ctx, path)
+    doc = json.load(open(path))
+    assert len(doc["entries"]) == 3
+    other = ozk.Context(0)
+    try:
+        ozk.ozk_config_load(other, path)
+        for op, sch, ps, M, N, K, cfg in entries:
+            got, found, _ = ozk.ozk_config_get(other, op, sch, ps, M, N, K)
+            assert found and got == cfg
+    finally:
+        other.close()
+
+
+def test_invalid_configs_and_targets(ctx, tmp_path):
+    bad = [(ozk.OZK_S1_VARIANTS, 0, 4, 1), (0, 2, 4, 1), (0, 0, 0, 1), (0, 0, 65, 1), (0, 0, 4, 0)]
+    for cfg in bad:
+        with pytest.raises(ozk.OzkError):
+            ozk.ozk_config_set(ctx, ozk.OZK_OP_DGEMM, ozk.OZK_SCHEME1, 4, 64, 64, 64, cfg)
+    with pytest.raises(ozk.OzkError):  # Scheme I has no complex path
+        ozk.ozk_config_set(ctx, ozk.OZK_OP_ZGEMM, ozk.OZK_SCHEME1, 4, 64, 64, 64, (0, 0, 4, 1))
+    with pytest.raises(ozk.OzkError):
+        ozk.ozk_config_set(ctx, ozk.OZK_OP_DGEMM, ozk.OZK_SCHEME1, 9, 64, 64, 64, (0, 0, 4, 1))
+    p = tmp_path / "broken.json"
+    p.write_text('{"entries": [{"op": 0, "scheme": 1}]}')
+    with pytest.raises(ozk.OzkError):
+        ozk.ozk_config_load(ctx, str(p))
+    with pytest.raises(ozk.OzkError):
+        ozk.ozk_dgemm(ctx, ozk.OZK_SCHEME1, 4, torch.zeros((ozk.OZK_MAX_ROWS + 1, 0), dtype=torch.float64,
+                                                              device="cuda:0"),
+                      torch.zeros((0, 1), dtype=torch.float64, device="cuda:0"))
+
+
+def test_workspace_follows_the_split(ctx):
+    p, M, N, K = 5, 64, 64, 4096
+    base = ozk.ozk_workspace_size(ctx, ozk.OZK_OP_DGEMM, ozk.OZK_SCHEME1, M, N, K, p)
+    ozk.ozk_config_set(ctx, ozk.OZK_OP_DGEMM, ozk.OZK_SCHEME1, p, M, N, K, (0, 0, 4, 4))
+    split = ozk.ozk_workspace_size(ctx, ozk.OZK_OP_DGEMM, ozk.OZK_SCHEME1, M, N, K, p)
+    assert split >= base + 16 * 4 * M * N
+    A = synth.phi_matrix(M, K, 1.0, 1)
+    B = synth.phi_matrix(K, N, 1.0, 2)
+    ws_small = torch.empty(base, dtype=torch.uint8, device="cuda:0")
+    with pytest.raises(ozk.OzkError):
+        ozk.ozk_dgemm(ctx, ozk.OZK_SCHEME1, p, dev(A), dev(B), ws=ws_small)
+    assert np.array_equal(host(ozk.ozk_dgemm(ctx, ozk.OZK_SCHEME1, p, dev(A), dev(B))), oracle.s1_dgemm(A, B, p))
