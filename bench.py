@@ -40,6 +40,8 @@ def parse():
     ap.add_argument("--save-config", default=None, help="write the tuned configuration table (JSON)")
     ap.add_argument("--load-config", default=None, help="use a saved configuration table instead of tuning")
     ap.add_argument("--err-samples", type=int, default=4096, help="outputs sampled for the accuracy check")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="also run one plain device copy of this many MiB (calibrates HBM byte counters)")
     return ap.parse_args()
 
 
@@ -158,6 +160,13 @@ def main():
         torch.cuda.synchronize()
         if args.save_config:
             ozk.ozk_config_save(ctx, args.save_config)
+
+    if args.copy_probe_mib > 0:  # a copy kernel of known size, for counter calibration
+        x = torch.ones(args.copy_probe_mib << 20, dtype=torch.uint8, device=dev)
+        y = torch.empty_like(x)
+        y.copy_(x)
+        torch.cuda.synchronize()
+        del x, y
 
     results = {}
     for pp in ps:

@@ -393,7 +393,7 @@ ozk_status ozk_tune_workspace_size(ozk_ctx* ctx, ozk_op op, ozk_scheme scheme,
                                    size_t* bytes);
 /* Tune the size class of (M, N, K) on these operands: run the pre-pass
  * once, time the INT8 GEMM step (with the K-run fold) of every candidate
- * configuration -- variants x rasters x groups {4, 8} x K splits 1, 2, 4, 8
+ * configuration -- variants x rasters x groups {2, 4, 8, 16} x K splits 1, 2, 4, 8
  * (Scheme I, while the partial sums fit 256 MiB) -- as the median of `reps`
  * runs after one warm-up, store the fastest in the table, and leave
  * C = A B (alpha 1, beta 0) computed with it.  Complex operands (ZGEMM,

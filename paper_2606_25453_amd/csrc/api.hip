@@ -958,7 +958,7 @@ ozk_status ozk_tune(ozk_ctx* ctx, ozk_op op, ozk_scheme scheme, int p_or_s, int6
       bool have = false;
       for (int v = 0; v < OZK_S1_VARIANTS && err == hipSuccess; ++v)
         for (int raster = 0; raster < 2 && err == hipSuccess; ++raster)
-          for (int group : {4, 8})
+          for (int group : {2, 4, 8, 16})
             for (int split = 1; split <= max_split && err == hipSuccess; split *= 2) {
               const S1Plan pl = s1_plan(ctx, p, M, N, K, split);
               if (pl.total > ws_bytes) continue;
@@ -1018,7 +1018,7 @@ ozk_status ozk_tune(ozk_ctx* ctx, ozk_op op, ozk_scheme scheme, int p_or_s, int6
       bool have = false;
       for (int v = 0; v < OZK_S2_VARIANTS && err == hipSuccess; ++v)
         for (int raster = 0; raster < 2 && err == hipSuccess; ++raster)
-          for (int group : {4, 8}) {
+          for (int group : {2, 4, 8, 16}) {
             float t = 0.f;
             err = time_median(
                 stream, reps, [&]() { return ozk::s2_gemm_mod(s, cplx, M, N, K, Ap, Bp, res, stream, v, raster, group); },

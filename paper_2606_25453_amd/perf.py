@@ -1,0 +1,155 @@
+"""Throughput of the library's paths on synthetic inputs (one JSON line each).
+
+    python -m paper_2606_25453_amd.perf [--quick] [--out FILE]
+
+Workloads (inputs resident in HBM, every kernel of the call timed with HIP
+events on the launch stream, after untimed warm-up calls and tuning):
+* Scheme I DGEMM, square n in {4096, 8192}, p in {6, 7, 8};
+* Scheme II DGEMM 4096^3 and 8192 x 8192 x 2048, s in {14, 16};
+* Scheme II 3M ZGEMM 4096^3 and 8192^3, s = 16;
+* a batch of 256 ZGEMMs with M, N, K log-uniform in [64, 1024], s = 16, one
+  graph replay per call.
+For each: emulated FP64 TFLOP/s (2MNK real, 8MNK complex per call), the INT8
+operations of the GEMM step and their rate against the dense INT8 peak.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+
+import paper_2606_25453_amd as ozk
+
+INT8_PEAK_TOPS = 5000.0
+
+
+def _events(torch, n):
+    return [torch.cuda.Event(enable_timing=True) for _ in range(n)]
+
+
+def time_call(torch, fn, reps: int, warm: int = 2) -> float:
+    """Mean ms of fn() over reps calls on the current stream."""
+    for _ in range(warm):
+        fn()
+    a, b = _events(torch, 2)
+    a.record()
+    for _ in range(reps):
+        fn()
+    b.record()
+    b.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def scheme1(torch, ctx, n, p, reps):
+    import synth
+    dev = "cuda:0"
+    A = torch.from_numpy(synth.phi_matrix(n, n, 1.0, synth.seed_for(2, n, 1.0, synth.ROLE_A))).to(dev)
+    B = torch.from_numpy(synth.phi_matrix(n, n, 1.0, synth.seed_for(2, n, 1.0, synth.ROLE_B))).to(dev)
+    C = torch.empty((n, n), dtype=torch.float64, device=dev)
+    _, cfg, gemm_ms = ozk.ozk_tune(ctx, ozk.OZK_OP_DGEMM, ozk.OZK_SCHEME1, p, A, B, C=C, reps=2)
+    ws = torch.empty(ozk.ozk_workspace_size(ctx, ozk.OZK_OP_DGEMM, ozk.OZK_SCHEME1, n, n, n, p), dtype=torch.uint8,
+                     device=dev)
+    ms = time_call(torch, lambda: ozk.ozk_dgemm(ctx, ozk.OZK_SCHEME1, p, A, B, C, ws=ws), reps)
+    ops = p * (p + 1) * n ** 3
+    return {"path": "scheme1_dgemm", "M": n, "N": n, "K": n, "p": p, "config": cfg, "ms": round(ms, 4),
+            "tflops": round(2.0 * n ** 3 / ms / 1e9, 3), "gemm_ms": round(gemm_ms, 4),
+            "int8_ops": ops, "gemm_frac_int8_peak": round(ops / gemm_ms / 1e9 / INT8_PEAK_TOPS, 4)}
+
+
+def scheme2(torch, ctx, M, N, K, s, cplx, reps):
+    import synth
+    dev = "cuda:0"
+    if cplx:
+        A = torch.from_numpy(synth.complex_phi_matrix(M, K, 1.0, 31, 32)).to(dev)
+        B = torch.from_numpy(synth.complex_phi_matrix(K, N, 1.0, 33, 34)).to(dev)
+        op, dt = ozk.OZK_OP_ZGEMM, torch.complex128
+    else:
+        A = torch.from_numpy(synth.phi_matrix(M, K, 1.0, 31)).to(dev)
+        B = torch.from_numpy(synth.phi_matrix(K, N, 1.0, 33)).to(dev)
+        op, dt = ozk.OZK_OP_DGEMM, torch.float64
+    C = torch.empty((M, N), dtype=dt, device=dev)
+    _, cfg, gemm_ms = ozk.ozk_tune(ctx, op, ozk.OZK_SCHEME2, s, A, B, C=C, reps=2)
+    ws = torch.empty(ozk.ozk_workspace_size(ctx, op, ozk.OZK_SCHEME2, M, N, K, s), dtype=torch.uint8, device=dev)
+    if cplx:
+        ms = time_call(torch, lambda: ozk.ozk_zgemm_3m(ctx, s, A, B, C, ws=ws), reps)
+    else:
+        ms = time_call(torch, lambda: ozk.ozk_dgemm(ctx, ozk.OZK_SCHEME2, s, A, B, C, ws=ws), reps)
+    flops = (8.0 if cplx else 2.0) * M * N * K
+    ops = (6 if cplx else 2) * s * M * N * K
+    return {"path": "scheme2_zgemm_3m" if cplx else "scheme2_dgemm", "M": M, "N": N, "K": K, "s": s,
+            "config": cfg, "ms": round(ms, 4), "tflops": round(flops / ms / 1e9, 3), "gemm_ms": round(gemm_ms, 4),
+            "int8_ops": ops, "gemm_frac_int8_peak": round(ops / gemm_ms / 1e9 / INT8_PEAK_TOPS, 4)}
+
+
+def batch(torch, ctx, count, s, reps):
+    import synth
+    dev = "cuda:0"
+    dims = synth.log_uniform_ints(3 * count, 64, 1024, synth.seed_for(4, count, 1.0, 0)).reshape(count, 3)
+    g = torch.Generator(device="cpu").manual_seed(4)
+    dA, dB, dC = [], [], []
+    flops = ops = 0
+    for (M, N, K) in dims:
+        M, N, K = int(M), int(N), int(K)
+        a = (torch.rand((M, K), generator=g, dtype=torch.float64) - 0.5) + 1j * (
+            torch.rand((M, K), generator=g, dtype=torch.float64) - 0.5)
+        b = (torch.rand((K, N), generator=g, dtype=torch.float64) - 0.5) + 1j * (
+            torch.rand((K, N), generator=g, dtype=torch.float64) - 0.5)
+        dA.append(a.to(dev))
+        dB.append(b.to(dev))
+        dC.append(torch.empty((M, N), dtype=torch.complex128, device=dev))
+        flops += 8.0 * M * N * K
+        ops += 6 * s * M * N * K
+    plan = ozk.BatchPlan(ctx, ozk.OZK_OP_ZGEMM, ozk.OZK_SCHEME2, s, list(zip(dA, dB, dC)))
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(side):
+        plan.run(stream=side)
+        torch.cuda.synchronize()
+        with torch.cuda.graph(graph, stream=side):
+            plan.run(stream=side)
+    torch.cuda.current_stream().wait_stream(side)
+    ms_graph = time_call(torch, graph.replay, reps)
+    ms_eager = time_call(torch, plan.run, reps)
+    plan.close()
+    return {"path": "batch_zgemm_3m", "count": count, "s": s, "ms_graph": round(ms_graph, 4),
+            "ms_eager": round(ms_eager, 4), "tflops": round(flops / ms_graph / 1e9, 3), "int8_ops": ops,
+            "end_to_end_frac_int8_peak": round(ops / ms_graph / 1e9 / INT8_PEAK_TOPS, 4)}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--quick", action="store_true", help="the smaller sizes only")
+    ap.add_argument("--reps", type=int, default=5)
+    ap.add_argument("--out", default=None, help="also append the lines to this file")
+    args = ap.parse_args()
+    import torch
+    ozk.library()
+    ctx = ozk.Context(0)
+    jobs = [("s1", 4096, p) for p in (6, 7, 8)]
+    jobs += [("s2", 4096, 4096, 4096, s, False) for s in (14, 16)]
+    jobs += [("s2", 8192, 8192, 2048, s, False) for s in (14, 16)]
+    jobs += [("s2", 4096, 4096, 4096, 16, True)]
+    jobs += [("batch", 256, 16)]
+    if not args.quick:
+        jobs += [("s1", 8192, p) for p in (6, 7, 8)]
+        jobs += [("s2", 8192, 8192, 8192, 16, True)]
+    out = open(args.out, "a") if args.out else None
+    for job in jobs:
+        if job[0] == "s1":
+            r = scheme1(torch, ctx, job[1], job[2], args.reps)
+        elif job[0] == "s2":
+            r = scheme2(torch, ctx, job[1], job[2], job[3], job[4], job[5], args.reps)
+        else:
+            r = batch(torch, ctx, job[1], job[2], args.reps)
+        line = json.dumps(r)
+        print(line, flush=True)
+        if out:
+            out.write(line + "\n")
+            out.flush()
+        torch.cuda.empty_cache()
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

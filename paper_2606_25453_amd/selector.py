@@ -2,8 +2,9 @@
 
 Everything numeric runs on the GPU through the library's C ABI:
 * problems: synthetic (u - 0.5) exp(phi g) matrices with phi ~ U(0, 4) for A
-  and B independently and M, N, K log-uniform (the paper's generator,
-  Sec. V-B, Eq. 19, with random conditioning);
+  and B independently, M, N log-uniform in [64, 512] and K log-uniform in
+  [64, 16384] (the paper's generator, Sec. V-B, Eq. 19, with random
+  conditioning);
 * labels: the componentwise error of the emulated product for p = 1..8
   against the double-double reference kernel, E_cw(p) = max |C_p - C_dd| /
   (|A||B|), and the smallest p with E_cw(p) <= tol (9 if none), for four
@@ -102,21 +103,23 @@ def features(ctx, A, B, tol: float):
     return feat, info, cnt
 
 
-def build_dataset(ctx, count: int, seed: int, lo: int = 64, hi: int = 768, tols_per_problem: int = 4,
+def build_dataset(ctx, count: int, seed: int, mn=(64, 512), k_range=(64, 16384), tols_per_problem: int = 4,
                   device="cuda:0"):
     """Features (n x 34), labels (n) and bound decisions for `count` random
-    problems, each used at `tols_per_problem` tolerances drawn log-uniformly
-    in [1e-16, 1e-5] (the range the selector is trusted in)."""
+    problems (M, N log-uniform in mn, K log-uniform in k_range: the K range
+    the selector is trusted in), each used at `tols_per_problem` tolerances
+    drawn log-uniformly in [1e-16, 1e-5]."""
     torch = _torch()
     host_gen = torch.Generator().manual_seed(seed)
     gen = torch.Generator(device=device).manual_seed(seed)
     X, labels, bounds, curves = [], [], [], []
-    log_lo, log_hi = math.log(lo), math.log(hi + 1)
     for i in range(count):
         if i % 250 == 0:
             print("dataset seed %d: problem %d of %d" % (seed, i, count), flush=True)
         u = torch.rand(3 + 2 + tols_per_problem, generator=host_gen, dtype=torch.float64).tolist()
-        M, N, K = (int(math.exp(log_lo + (log_hi - log_lo) * v)) for v in u[:3])
+        M, N = (int(math.exp(math.log(mn[0]) + (math.log(mn[1] + 1) - math.log(mn[0])) * v)) for v in u[:2])
+        K = int(math.exp(math.log(k_range[0]) + (math.log(k_range[1] + 1) - math.log(k_range[0])) * u[2]))
+        K = min(K, k_range[1])
         phi_a, phi_b = 4.0 * u[3], 4.0 * u[4]
         A, B = random_problem(gen, M, N, K, phi_a, phi_b, device)
         curve = error_curve(ctx, A, B)
@@ -257,7 +260,8 @@ def main():
     pbound = torch.clamp(bva, max=8)
     used = torch.clamp(torch.minimum(pva, bva), 1, 8)
     meta = {"train_problems": a.train, "val_problems": a.val, "steps": a.steps, "loss": hist[-5:],
-            "tols": "4 per problem, log-uniform in [1e-16, 1e-5]", "sizes": "M,N,K log-uniform in [64, 768]",
+            "tols": "4 per problem, log-uniform in [1e-16, 1e-5]",
+            "sizes": "M, N log-uniform in [64, 512], K log-uniform in [64, 16384]",
             "phi": "U(0,4) for A and for B", "threshold": thr, "margin": margin,
             "val_mean_p_selector": float(used.double().mean()), "val_mean_p_bound": float(pbound.double().mean()),
             "val_mean_p_needed": float(needed(yva).double().mean()),

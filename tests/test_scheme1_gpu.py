@@ -111,6 +111,19 @@ def test_dgemm_bit_exact(ctx, p, shape):
     assert np.array_equal(C, oracle.s1_dgemm(A, B, p))
 
 
+@pytest.mark.parametrize("p", [2, 5, 7])
+def test_dgemm_every_step_count(ctx, p):
+    """K from 1 to 8 steps of 32, full and ragged: the software pipeline's
+    prologue, the leading zero step of odd counts and the last pair."""
+    M, N = 130, 70
+    for steps in range(1, 9):
+        for K in (32 * steps, 32 * steps - 5):
+            A = synth.phi_matrix(M, K, 1.0, 5000 + K)
+            B = synth.phi_matrix(K, N, 1.0, 5100 + K)
+            C = host(ozk.ozk_dgemm(ctx, ozk.OZK_SCHEME1, p, dev(A), dev(B)))
+            assert np.array_equal(C, oracle.s1_dgemm(A, B, p)), (p, K)
+
+
 def test_config1_uniform_128(ctx):
     """128^3, entries uniform in (-1, 1), p = 4: bit-exact, and compared with
     the naive and double-double references."""
