@@ -160,15 +160,22 @@ def _ld(t) -> int:
 
 
 class Context:
-    """An ozk context bound to one device (ozk_create / ozk_destroy)."""
+    """An ozk context bound to one device (ozk_create / ozk_destroy).
 
-    def __init__(self, device: int = 0):
+    selector: None (no network: the auto path uses the a-priori bound),
+    "default" (the parameters shipped with the package) or a path to a
+    parameter file written by ``python -m paper_2606_25453_amd.selector``."""
+
+    def __init__(self, device: int = 0, selector: Optional[str] = None):
         h = ctypes.c_void_p()
         st = _lib().ozk_create(ctypes.byref(h), device)
         if st != OZK_OK:
             raise OzkError("ozk_create", st, 0)
         self.handle = h
         self.device = device
+        if selector is not None:
+            from . import selector as _sel
+            _sel.install(self, _sel.WEIGHTS if selector == "default" else selector)
 
     def close(self) -> None:
         if self.handle:
@@ -482,3 +489,42 @@ def ozk_tune(ctx: Context, op: int, scheme: int, p_or_s: int, A, B, C=None, reps
                          _ptr(ws), ws.numel(), reps, ctypes.byref(best), ctypes.byref(ms), _stream(stream))
     _check("ozk_tune", st, ctx)
     return C, best.as_tuple(), float(ms.value)
+
+
+# ------------------------------------------------------- slice-count selector
+
+def ozk_select(ctx: Context, tol: float, A, B, stream=None):
+    """Device statistics and decision for A B: (e, f, counters, info, features)
+    as device tensors; info = [p, p_net, p_bound, out_of_range]."""
+    import torch
+    M, K = A.shape
+    N = B.shape[1]
+    e = torch.empty(max(M, 1), dtype=torch.int32, device=A.device)
+    f = torch.empty(max(N, 1), dtype=torch.int32, device=A.device)
+    cnt = torch.empty(OZK_SELECTOR_COUNTERS, dtype=torch.int32, device=A.device)
+    info = torch.empty(4, dtype=torch.int32, device=A.device)
+    feat = torch.empty(34, dtype=torch.float32, device=A.device)
+    st = _lib().ozk_select(ctx.handle, float(tol), M, N, K, _ptr(A), _ld(A), _ptr(B), _ld(B), _ptr(e), _ptr(f),
+                           _ptr(cnt), _ptr(info), _ptr(feat), _stream(stream))
+    _check("ozk_select", st, ctx)
+    return e[:M], f[:N], cnt, info, feat
+
+
+def ozk_dgemm_auto(ctx: Context, tol: float, A, B, C=None, alpha: float = 1.0, beta: float = 0.0, ws=None,
+                   info=None, stream=None):
+    """Scheme I DGEMM with the slice count chosen on the device for the
+    componentwise tolerance tol; returns (C, info) with info the device
+    int32[4] decision [p, p_net, p_bound, out_of_range]."""
+    import torch
+    M, K = A.shape
+    N = B.shape[1]
+    if C is None:
+        C = torch.empty((M, N), dtype=torch.float64, device=A.device)
+    if ws is None:
+        ws = _workspace(ozk_workspace_size(ctx, OZK_OP_DGEMM, OZK_SCHEME1, M, N, K, 0), A.device)
+    if info is None:
+        info = torch.empty(4, dtype=torch.int32, device=A.device)
+    st = _lib().ozk_dgemm_auto(ctx.handle, float(tol), M, N, K, float(alpha), _ptr(A), _ld(A), _ptr(B), _ld(B),
+                               float(beta), _ptr(C), _ld(C), _ptr(ws), ws.numel(), _ptr(info), _stream(stream))
+    _check("ozk_dgemm_auto", st, ctx)
+    return C, info
