@@ -86,6 +86,7 @@ extern "C" {
 #define OZK_S2_VARIANTS 2           /* Scheme II GEMM tile variants */
 #define OZK_SELECTOR_PARAMS 6920   /* float32 parameters of the selector MLP */
 #define OZK_SELECTOR_COUNTERS 34   /* int32 feature counters */
+#define OZK_SELECTOR_INFO 8        /* int32 decision entries */
 
 typedef struct ozk_ctx ozk_ctx;
 
@@ -253,9 +254,14 @@ ozk_status ozk_s2_crt(ozk_ctx* ctx, int s, int complex_planes, int64_t M,
  * + margin; p_bound = smallest p whose a-priori bound is <= tol (9 if none);
  * p = min(p_net, p_bound), or p_bound when no network is loaded or the
  * features are outside the training range (K > 16384, tol outside
- * [1e-16, 1e-5], any entry in the last deficit bin); clamped to [1, 8].
- * info (device int32[4]): p, p_net (0 without network), p_bound, 1 if out
- * of range. */
+ * [1e-16, 1e-5], any entry in the last deficit bin).  p <= 8: Scheme I with
+ * p slices.  p = 9 (no slice count up to 8 is enough): Scheme II with s =
+ * s_bound, the smallest modulus count whose a-priori bound (norm-bound
+ * scales, Sec. II-C.2) is <= tol, or 20 when none is proven enough.
+ * info (device int32[OZK_SELECTOR_INFO]): [0] Scheme I slices (0 when
+ * Scheme II is chosen), [1] p_net (0 without network), [2] p_bound,
+ * [3] 1 if out of range, [4] scheme (1 or 2), [5] Scheme II moduli (0 with
+ * Scheme I), [6] s_bound (21 if none up to 20), [7] 0. */
 
 /* Load selector parameters (HOST float array of OZK_SELECTOR_PARAMS) into
  * the context (copied to device memory owned by the context). */
@@ -263,15 +269,19 @@ ozk_status ozk_selector_load(ozk_ctx* ctx, const float* params, size_t n,
                              float threshold, int margin);
 /* Exponent statistics and the selector decision for C = A B, all on the
  * device: e[M], f[N] (the Scheme I row/column exponents), counters,
- * info[4] and, if features is not NULL, the 34 features (float32). */
+ * info[OZK_SELECTOR_INFO] and, if features is not NULL, the 34 features
+ * (float32). */
 ozk_status ozk_select(ozk_ctx* ctx, double tol, int64_t M, int64_t N,
                       int64_t K, const double* A, int64_t lda, const double* B,
                       int64_t ldb, int32_t* e, int32_t* f, int32_t* counters,
                       int32_t* info, float* features, hipStream_t stream);
-/* Scheme I DGEMM with the slice count chosen on the device for tolerance
- * `tol` (no host round trip; graph-capturable).  ws must hold
- * ozk_workspace_size(ctx, OZK_OP_DGEMM, OZK_SCHEME1, M, N, K, 0) bytes;
- * info (device int32[4], may be NULL) receives the decision. */
+/* DGEMM with the scheme and the slice or modulus count chosen on the device
+ * for the componentwise tolerance `tol` (the decision above): the kernels of
+ * both schemes are enqueued and those not chosen return at once, so there is
+ * no host round trip and the call can be captured into a graph.  ws must
+ * hold ozk_workspace_size(ctx, OZK_OP_DGEMM, OZK_SCHEME1, M, N, K, 0) bytes
+ * (room for either scheme); info (device int32[OZK_SELECTOR_INFO], may be
+ * NULL) receives the decision. */
 ozk_status ozk_dgemm_auto(ozk_ctx* ctx, double tol, int64_t M, int64_t N,
                           int64_t K, double alpha, const double* A,
                           int64_t lda, const double* B, int64_t ldb,

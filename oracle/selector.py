@@ -99,6 +99,34 @@ def p_bound(A, B, tol: float) -> int:
     return 9
 
 
+def bound_s2(s: int, ra: int, rb: int, K: int) -> float:
+    """A-priori componentwise error bound of Scheme II with s moduli for
+    entries at most ra (rb) exponent steps below their row (column) maximum
+    (Sec. II-C.2 with the norm-bound scales): the scale exponent nb exceeds
+    the row maximum by at most d = ceil(ceil(log2 K) / 2), an entry r steps
+    below the maximum is at least 2^(e-r-1), so truncating it at 2^(nb-T)
+    costs at most 2^(r+d+1-T) relative; per product term the two relative
+    errors and their product, then the final rounding (the CRT is exact)."""
+    from .scheme2 import targets
+    ta, tb = targets(s)
+    d = (max(int(K), 1) - 1).bit_length()  # ceil(log2 K)
+    d = (d + 1) // 2
+    ea, eb = ra + d + 1 - ta, rb + d + 1 - tb
+    if max(ea, eb, ea + eb) > 1000:
+        return math.inf
+    return 2.0 ** ea + 2.0 ** eb + 2.0 ** (ea + eb) + 2.0 ** -53
+
+
+def s_bound(A, B, tol: float) -> int:
+    """Smallest s in [1, 20] whose bound is <= tol (21 = none)."""
+    ra, rb = max_deficit(A, 1), max_deficit(B, 0)
+    K = np.asarray(A).shape[1]
+    for s in range(1, 21):
+        if bound_s2(s, ra, rb, K) <= tol:
+            return s
+    return 21
+
+
 # -------------------------------------------------------------------- MLP
 
 def mlp_forward(params, X):

@@ -31,6 +31,7 @@ OZK_EXP_ZERO = -100000
 OZK_EXP_NONFINITE = 100000
 OZK_SELECTOR_PARAMS = 6920
 OZK_SELECTOR_COUNTERS = 34
+OZK_SELECTOR_INFO = 8
 OZK_MAX_ROWS = 1 << 24
 OZK_S1_VARIANTS = 4
 OZK_S2_VARIANTS = 2
@@ -495,14 +496,15 @@ def ozk_tune(ctx: Context, op: int, scheme: int, p_or_s: int, A, B, C=None, reps
 
 def ozk_select(ctx: Context, tol: float, A, B, stream=None):
     """Device statistics and decision for A B: (e, f, counters, info, features)
-    as device tensors; info = [p, p_net, p_bound, out_of_range]."""
+    as device tensors; info = [p (0 with Scheme II), p_net, p_bound,
+    out_of_range, scheme, s (0 with Scheme I), s_bound, 0]."""
     import torch
     M, K = A.shape
     N = B.shape[1]
     e = torch.empty(max(M, 1), dtype=torch.int32, device=A.device)
     f = torch.empty(max(N, 1), dtype=torch.int32, device=A.device)
     cnt = torch.empty(OZK_SELECTOR_COUNTERS, dtype=torch.int32, device=A.device)
-    info = torch.empty(4, dtype=torch.int32, device=A.device)
+    info = torch.empty(OZK_SELECTOR_INFO, dtype=torch.int32, device=A.device)
     feat = torch.empty(34, dtype=torch.float32, device=A.device)
     st = _lib().ozk_select(ctx.handle, float(tol), M, N, K, _ptr(A), _ld(A), _ptr(B), _ld(B), _ptr(e), _ptr(f),
                            _ptr(cnt), _ptr(info), _ptr(feat), _stream(stream))
@@ -512,9 +514,9 @@ def ozk_select(ctx: Context, tol: float, A, B, stream=None):
 
 def ozk_dgemm_auto(ctx: Context, tol: float, A, B, C=None, alpha: float = 1.0, beta: float = 0.0, ws=None,
                    info=None, stream=None):
-    """Scheme I DGEMM with the slice count chosen on the device for the
-    componentwise tolerance tol; returns (C, info) with info the device
-    int32[4] decision [p, p_net, p_bound, out_of_range]."""
+    """DGEMM with the scheme and slice or modulus count chosen on the device
+    for the componentwise tolerance tol; returns (C, info) with info the
+    device int32[8] decision (see ozk_select)."""
     import torch
     M, K = A.shape
     N = B.shape[1]
@@ -523,7 +525,7 @@ def ozk_dgemm_auto(ctx: Context, tol: float, A, B, C=None, alpha: float = 1.0, b
     if ws is None:
         ws = _workspace(ozk_workspace_size(ctx, OZK_OP_DGEMM, OZK_SCHEME1, M, N, K, 0), A.device)
     if info is None:
-        info = torch.empty(4, dtype=torch.int32, device=A.device)
+        info = torch.empty(OZK_SELECTOR_INFO, dtype=torch.int32, device=A.device)
     st = _lib().ozk_dgemm_auto(ctx.handle, float(tol), M, N, K, float(alpha), _ptr(A), _ld(A), _ptr(B), _ld(B),
                                float(beta), _ptr(C), _ld(C), _ptr(ws), ws.numel(), _ptr(info), _stream(stream))
     _check("ozk_dgemm_auto", st, ctx)

@@ -138,6 +138,26 @@ static hipError_t time_median(hipStream_t st, int reps, F&& fn, float* ms) {
   return hipSuccess;
 }
 
+// Workspace of the auto path: room for Scheme I at p = 8 or Scheme II at
+// s = 20 (only the chosen scheme's buffers are used), then 256 bytes of
+// selector counters and 256 bytes of decision (info).
+struct AutoPlan {
+  S1Plan s1;
+  S2Plan s2;
+  size_t off_cnt, off_info, total;
+};
+
+AutoPlan auto_plan(const ozk_ctx* c, int64_t M, int64_t N, int64_t K) {
+  AutoPlan ap;
+  ap.s1 = s1_plan(c, OZK_MAX_P, M, N, K);
+  ap.s2 = s2_plan(OZK_MAX_S, false, M, N, K);
+  const size_t base = std::max(ap.s1.total, ap.s2.total);
+  ap.off_cnt = base;
+  ap.off_info = base + 256;
+  ap.total = base + 512;
+  return ap;
+}
+
 bool bad_rows(int64_t r) { return r < 0 || r > OZK_MAX_ROWS; }
 
 bool bad_dims(int64_t M, int64_t N, int64_t K) {
@@ -198,6 +218,10 @@ ozk_status ozk_create(ozk_ctx** ctx, int device) {
   ozk_ctx* c = new (std::nothrow) ozk_ctx();
   if (!c) return OZK_ERR_HIP;
   c->device = device;
+  if (ozk::s2_upload_crt_tables() != hipSuccess) {  // CRT constants of every s for the auto path
+    delete c;
+    return OZK_ERR_HIP;
+  }
   const char* ks = getenv("OZK_K_SPLIT");
   if (ks) c->k_split_override = atoll(ks);
   *ctx = c;
@@ -235,8 +259,8 @@ ozk_status ozk_workspace_size(ozk_ctx* ctx, ozk_op op, ozk_scheme scheme, int64_
   if (!bytes) return fail(ctx, OZK_ERR_INVALID_ARG, 8);
   if (bad_dims(M, N, K)) return fail(ctx, OZK_ERR_INVALID_ARG, 4);
   if (op == OZK_OP_DGEMM && scheme == OZK_SCHEME1) {
-    if (p_or_s == 0) {
-      *bytes = s1_plan(ctx, OZK_MAX_P, M, N, K).total + 512;
+    if (p_or_s == 0) {  // the auto path (either scheme)
+      *bytes = auto_plan(ctx, M, N, K).total;
       return OZK_OK;
     }
     if (p_or_s < 1 || p_or_s > OZK_MAX_P) return fail(ctx, OZK_ERR_UNSUPPORTED, 7);
@@ -545,38 +569,54 @@ ozk_status ozk_dgemm_auto(ozk_ctx* ctx, double tol, int64_t M, int64_t N, int64_
   if (ldb < (N > 0 ? N : 1)) return fail(ctx, OZK_ERR_INVALID_ARG, 10);
   if (!C && M > 0 && N > 0) return fail(ctx, OZK_ERR_INVALID_ARG, 12);
   if (ldc < (N > 0 ? N : 1)) return fail(ctx, OZK_ERR_INVALID_ARG, 13);
-  const S1Plan pl = s1_plan(ctx, OZK_MAX_P, M, N, K);
-  if (!ws || ws_bytes < pl.total + 512) return fail(ctx, OZK_ERR_WORKSPACE, 14);
+  const AutoPlan ap = auto_plan(ctx, M, N, K);
+  if (!ws || ws_bytes < ap.total) return fail(ctx, OZK_ERR_WORKSPACE, 14);
   if (M == 0 || N == 0) return OZK_OK;
   char* w = (char*)ws;
-  int32_t* e = (int32_t*)(w + pl.off_e);
-  int32_t* f = (int32_t*)(w + pl.off_f);
-  int8_t* Ap = (int8_t*)(w + pl.off_a);
-  int8_t* Bp = (int8_t*)(w + pl.off_b);
-  int32_t* cnt = (int32_t*)(w + pl.total);
-  int32_t* inf = info ? info : (int32_t*)(w + pl.total + 256);
+  int32_t* cnt = (int32_t*)(w + ap.off_cnt);
+  int32_t* inf = info ? info : (int32_t*)(w + ap.off_info);
+  // statistics (also the Scheme I exponents) and the decision
+  const S1Plan& p1 = ap.s1;
+  int32_t* e = (int32_t*)(w + p1.off_e);
+  int32_t* f = (int32_t*)(w + p1.off_f);
   hipError_t err = ozk::sel_features(A, lda, M, B, ldb, N, K, e, f, cnt, stream);
   if (err == hipSuccess)
     err = ozk::sel_infer(cnt, ctx->sel_w, ctx->sel_threshold, ctx->sel_margin, tol, K, inf, nullptr, stream);
+  // Scheme I at the chosen p (every kernel returns when Scheme II was chosen)
+  int8_t* Ap = (int8_t*)(w + p1.off_a);
+  int8_t* Bp = (int8_t*)(w + p1.off_b);
   if (err == hipSuccess) err = ozk::s1_slice_auto(inf, A, lda, M, B, ldb, N, K, e, f, Ap, Bp, stream);
-  if (err != hipSuccess) return hip_status(ctx, err);
-  ozk::S1GemmArgs g;
-  g.M = M;
-  g.N = N;
-  g.Ap = Ap;
-  g.Bp = Bp;
-  g.nchunk = pl.nchunk;
-  g.steps_per_split = pl.nsplit > 1 ? pl.steps_per_split : (pl.nchunk > 0 ? pl.nchunk : 1);
-  g.nsplit = pl.nsplit;
-  g.e = e;
-  g.f = f;
-  g.alpha = alpha;
-  g.beta = beta;
-  g.C = C;
-  g.ldc = ldc;
-  g.zpart = pl.nsplit > 1 ? (int64_t*)(w + pl.off_z) : nullptr;
-  g.diag = nullptr;
-  return hip_status(ctx, ozk::s1_gemm_auto(inf, g, stream));
+  if (err == hipSuccess) {
+    ozk::S1GemmArgs g;
+    g.M = M;
+    g.N = N;
+    g.Ap = Ap;
+    g.Bp = Bp;
+    g.nchunk = p1.nchunk;
+    g.steps_per_split = p1.nsplit > 1 ? p1.steps_per_split : (p1.nchunk > 0 ? p1.nchunk : 1);
+    g.nsplit = p1.nsplit;
+    g.e = e;
+    g.f = f;
+    g.alpha = alpha;
+    g.beta = beta;
+    g.C = C;
+    g.ldc = ldc;
+    g.zpart = p1.nsplit > 1 ? (int64_t*)(w + p1.off_z) : nullptr;
+    g.diag = nullptr;
+    err = ozk::s1_gemm_auto(inf, g, stream);
+  }
+  // Scheme II at the chosen s (every kernel returns when Scheme I was chosen)
+  const S2Plan& p2 = ap.s2;
+  int32_t* sig = (int32_t*)(w + p2.off_sig);
+  int32_t* tau = (int32_t*)(w + p2.off_tau);
+  int8_t* Ar = (int8_t*)(w + p2.off_a);
+  int8_t* Br = (int8_t*)(w + p2.off_b);
+  int8_t* res = (int8_t*)(w + p2.off_res);
+  if (err == hipSuccess) err = ozk::s2_split_rows_auto(inf, A, lda, M, K, sig, Ar, stream);
+  if (err == hipSuccess) err = ozk::s2_split_cols_auto(inf, B, ldb, K, N, tau, Br, stream);
+  if (err == hipSuccess) err = ozk::s2_gemm_mod_auto(inf, M, N, K, Ar, Br, res, stream);
+  if (err == hipSuccess) err = ozk::s2_crt_auto(inf, M, N, res, sig, tau, alpha, beta, C, ldc, stream);
+  return hip_status(ctx, err);
 }
 
 ozk_status ozk_mlp_forward(ozk_ctx* ctx, const float* params, const float* X, int n, float* logits,

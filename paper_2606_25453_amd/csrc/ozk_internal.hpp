@@ -77,6 +77,29 @@ int64_t s2_tile_count(bool cplx, int64_t M, int64_t N);
 
 void s2_targets(int s, int& ta, int& tb);
 
+// Scheme II bit budgets T_A, T_B for every modulus count (index s, 1..20).
+struct S2Budgets {
+  int ta[OZK_MAX_S + 1];
+  int tb[OZK_MAX_S + 1];
+};
+S2Budgets s2_budgets();
+
+// The real Scheme II steps with the modulus count read from device memory
+// (info[4] == 2 selects them and info[5] holds s; every kernel returns at
+// once otherwise).  The packed operands and residues use the layouts of
+// s = OZK_MAX_S (per-modulus planes do not depend on s).  The CRT constants
+// of every s live in constant memory, written by s2_upload_crt_tables on the
+// current device (once per context, before any auto call).
+hipError_t s2_upload_crt_tables();
+hipError_t s2_split_rows_auto(const int32_t* info, const double* X, int64_t ldx, int64_t rows, int64_t K,
+                              int32_t* sigma, int8_t* packed, hipStream_t st);
+hipError_t s2_split_cols_auto(const int32_t* info, const double* X, int64_t ldx, int64_t K, int64_t cols,
+                              int32_t* tau, int8_t* packed, hipStream_t st);
+hipError_t s2_gemm_mod_auto(const int32_t* info, int64_t M, int64_t N, int64_t K, const int8_t* Ap,
+                            const int8_t* Bp, int8_t* out, hipStream_t st);
+hipError_t s2_crt_auto(const int32_t* info, int64_t M, int64_t N, const int8_t* res, const int32_t* sigma,
+                       const int32_t* tau, double alpha, double beta, double* C, int64_t ldc, hipStream_t st);
+
 hipError_t sel_features(const double* A, int64_t lda, int64_t M, const double* B, int64_t ldb, int64_t N, int64_t K,
                         int32_t* e, int32_t* f, int32_t* cnt, hipStream_t st);
 hipError_t sel_infer(const int32_t* cnt, const float* w, float threshold, int margin, double tol, int64_t K,

@@ -89,7 +89,7 @@ __global__ __launch_bounds__(256) void k_s1_slice_rows_auto(const double* __rest
                                                             const int32_t* __restrict__ p_dev,
                                                             int8_t* __restrict__ packed) {
   const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (r >= rows_packed) return;
+  if (r >= rows_packed || *p_dev < 1) return;  // p = 0: Scheme II was chosen
   const int e = r < rows ? e_in[r] : OZK_EXP_ZERO;
   const double* xr = X + r * ldx;
   switch (*p_dev) {
@@ -170,7 +170,7 @@ __global__ __launch_bounds__(256) void k_s1_split_cols_auto(const double* __rest
                                                             const int32_t* __restrict__ p_dev,
                                                             int8_t* __restrict__ packed) {
   const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (j >= cols_packed) return;
+  if (j >= cols_packed || *p_dev < 1) return;  // p = 0: Scheme II was chosen
   const int64_t c = blockIdx.y;
   switch (*p_dev) {
     case 1: s1_slice_col<1>(X, ldx, K, cols, cols_packed, f, packed, j, c); break;
@@ -191,6 +191,7 @@ __global__ __launch_bounds__(256) void k_s1_fold(const int64_t* __restrict__ zpa
                                                  const int32_t* __restrict__ f_col, double alpha,
                                                  double beta, double* __restrict__ C, int64_t ldc) {
   if (p_dev) p = *p_dev;
+  if (p < 1) return;  // Scheme II was chosen
   const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (idx >= (int64_t)M * N) return;
   const int64_t row = idx / N, col = idx % N;

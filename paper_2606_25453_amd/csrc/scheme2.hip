@@ -749,6 +749,134 @@ hipError_t s2_crt(int s, bool cplx, int64_t M, int64_t N, const int8_t* res, con
   return hipGetLastError();
 }
 
+// --------------------------------- modulus count chosen on the device
+
+__constant__ CrtArgs c_crt_all[OZK_MAX_S];  // CRT constants of s = 1 .. OZK_MAX_S (index s - 1)
+
+__device__ __forceinline__ bool s2_chosen(const int32_t* __restrict__ info, int& s) {
+  if (info[4] != 2) return false;
+  s = info[5];
+  return s >= 1 && s <= OZK_MAX_S;
+}
+
+__global__ __launch_bounds__(256) void k_s2_split_rows_auto(const double* __restrict__ X, int64_t ldx, int64_t rows,
+                                                            int64_t K, int64_t Kp, int64_t rows_packed,
+                                                            const int32_t* __restrict__ info, S2Budgets bud,
+                                                            int32_t* __restrict__ sigma_out,
+                                                            int8_t* __restrict__ packed) {
+  int s;
+  if (!s2_chosen(info, s)) return;
+  s2_split_rows_block<false>(X, ldx, rows, K, Kp, rows_packed, S2Args{s, bud.ta[s]}, sigma_out, packed,
+                             blockIdx.x);
+}
+
+__global__ __launch_bounds__(256) void k_s2_col_scales_auto(const double* __restrict__ X, int64_t ldx, int64_t K,
+                                                            int64_t cols, const int32_t* __restrict__ info,
+                                                            S2Budgets bud, int32_t* __restrict__ tau) {
+  int s;
+  if (!s2_chosen(info, s)) return;
+  s2_col_scales_block<false>(X, ldx, K, cols, bud.tb[s], tau, blockIdx.x);
+}
+
+__global__ __launch_bounds__(256) void k_s2_split_cols_auto(const double* __restrict__ X, int64_t ldx, int64_t K,
+                                                            int64_t cols, int64_t Kp, int64_t cols_packed,
+                                                            const int32_t* __restrict__ info,
+                                                            const int32_t* __restrict__ tau,
+                                                            int8_t* __restrict__ packed) {
+  int s;
+  if (!s2_chosen(info, s)) return;
+  s2_split_cols_block<false>(X, ldx, K, cols, Kp, cols_packed, s, tau, packed, blockIdx.x, blockIdx.y);
+}
+
+// grid z covers OZK_MAX_S moduli; the planes past the chosen s return
+__global__ __launch_bounds__(256, 1) void k_s2_gemm_mod_auto(const int8_t* __restrict__ Ap,
+                                                            const int8_t* __restrict__ Bp, int64_t plane_a,
+                                                            int64_t plane_b, int64_t rows_a, int64_t rows_b,
+                                                            int64_t nsteps, int M, int N,
+                                                            const int32_t* __restrict__ info,
+                                                            int8_t* __restrict__ out) {
+  extern __shared__ __attribute__((aligned(1024))) int8_t lds[];
+  int s;
+  if (!s2_chosen(info, s) || (int)blockIdx.z >= s) return;
+  s2_gemm_tile<false, 0>(Ap, Bp, plane_a, plane_b, rows_a, rows_b, nsteps, M, N, out, blockIdx.x, (int)blockIdx.z,
+                         0, 4, lds);
+}
+
+__global__ __launch_bounds__(256) void k_s2_crt_auto(int M, int N, const int8_t* __restrict__ res,
+                                                     const int32_t* __restrict__ sigma,
+                                                     const int32_t* __restrict__ tau,
+                                                     const int32_t* __restrict__ info, double alpha, double beta,
+                                                     double* __restrict__ C, int64_t ldc) {
+  int s;
+  if (!s2_chosen(info, s)) return;
+  s2_crt_block<false>(c_crt_all[s - 1], M, N, res, sigma, tau, alpha, 0.0, beta, 0.0, C, ldc, blockIdx.x);
+}
+
+S2Budgets s2_budgets() {
+  S2Budgets b;
+  b.ta[0] = b.tb[0] = 0;
+  for (int s = 1; s <= OZK_MAX_S; ++s) s2_targets(s, b.ta[s], b.tb[s]);
+  return b;
+}
+
+hipError_t s2_upload_crt_tables() {
+  static CrtArgs all[OZK_MAX_S];
+  int ta, tb;
+  for (int s = 1; s <= OZK_MAX_S; ++s) crt_args(s, all[s - 1], ta, tb);
+  return hipMemcpyToSymbol(HIP_SYMBOL(c_crt_all), all, sizeof(all));
+}
+
+hipError_t s2_split_rows_auto(const int32_t* info, const double* X, int64_t ldx, int64_t rows, int64_t K,
+                              int32_t* sigma, int8_t* packed, hipStream_t st) {
+  const int64_t rp = round_up(rows, OZK_ROW_ALIGN), kp = round_up(K, OZK_K_CHUNK);
+  if (rp > 0)
+    hipLaunchKernelGGL(k_s2_split_rows_auto, dim3((unsigned)(rp / 4)), dim3(256), 0, st, X, ldx, rows, K, kp, rp,
+                       info, s2_budgets(), sigma, packed);
+  return hipGetLastError();
+}
+
+hipError_t s2_split_cols_auto(const int32_t* info, const double* X, int64_t ldx, int64_t K, int64_t cols,
+                              int32_t* tau, int8_t* packed, hipStream_t st) {
+  const int64_t cp = round_up(cols, OZK_ROW_ALIGN), kp = round_up(K, OZK_K_CHUNK);
+  if (cols > 0)
+    hipLaunchKernelGGL(k_s2_col_scales_auto, dim3((unsigned)((cols + 31) / 32)), dim3(256), 0, st, X, ldx, K, cols,
+                       info, s2_budgets(), tau);
+  if (cp > 0 && kp > 0)
+    hipLaunchKernelGGL(k_s2_split_cols_auto, dim3((unsigned)(cp / 256), (unsigned)(kp / OZK_K_CHUNK)), dim3(256),
+                       0, st, X, ldx, K, cols, kp, cp, info, tau, packed);
+  return hipGetLastError();
+}
+
+hipError_t s2_gemm_mod_auto(const int32_t* info, int64_t M, int64_t N, int64_t K, const int8_t* Ap,
+                            const int8_t* Bp, int8_t* out, hipStream_t st) {
+  if (M == 0 || N == 0) return hipSuccess;
+  using Cfg = S2Cfg<false, 0>;
+  using T = GemmTile<Cfg::P, Cfg::TM, Cfg::TN, Cfg::NS>;
+  static bool attr = false;
+  if (!attr) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_s2_gemm_mod_auto),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, T::LDS_BYTES);
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  const int64_t kp = round_up(K, OZK_K_CHUNK);
+  const int64_t ra = round_up(M, OZK_ROW_ALIGN), rb = round_up(N, OZK_ROW_ALIGN);
+  const int64_t tiles = ((M + T::BM - 1) / T::BM) * ((N + T::BN - 1) / T::BN);
+  const dim3 grid((unsigned)tiles, 1, (unsigned)OZK_MAX_S);
+  hipLaunchKernelGGL(k_s2_gemm_mod_auto, grid, dim3(256), T::LDS_BYTES, st, Ap, Bp, ra * kp, rb * kp, ra, rb,
+                     kp / OZK_K_CHUNK, (int)M, (int)N, info, out);
+  return hipGetLastError();
+}
+
+hipError_t s2_crt_auto(const int32_t* info, int64_t M, int64_t N, const int8_t* res, const int32_t* sigma,
+                       const int32_t* tau, double alpha, double beta, double* C, int64_t ldc, hipStream_t st) {
+  const int64_t n = M * N;
+  if (n > 0)
+    hipLaunchKernelGGL(k_s2_crt_auto, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, (int)M, (int)N, res,
+                       sigma, tau, info, alpha, beta, C, ldc);
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------- batched problems
 //
 // Many uneven problems in one launch per step.  The plan uploads a problem

@@ -140,16 +140,34 @@ __device__ __forceinline__ double s1_bound(int p, int ra, int rb) {
   return a + ldexp(1.0, -53);
 }
 
+// A-priori componentwise error bound of Scheme II with bit budgets ta, tb
+// for entries at most ra (rb) steps below their row (column) maximum: the
+// norm-bound scale exceeds the maximum by at most d = ceil(ceil(log2 K)/2),
+// so truncation costs at most 2^(r+d+1-T) relative per operand; per product
+// term the two relative errors and their product, plus the final rounding.
+__device__ __forceinline__ double s2_bound(int ta, int tb, int ra, int rb, int64_t K) {
+  int lk = 0;
+  while (lk < 62 && ((int64_t)1 << lk) < K) ++lk;
+  const int d = (lk + 1) / 2;
+  const int ea = ra + d + 1 - ta, eb = rb + d + 1 - tb;
+  if (ea > 1000 || eb > 1000 || ea + eb > 1000) return __builtin_inf();
+  return ldexp(1.0, ea) + ldexp(1.0, eb) + ldexp(1.0, ea + eb) + ldexp(1.0, -53);
+}
+
 struct SelInfer {
   const float* w;  // device parameters, null = no network (bound only)
   float threshold;
   int margin;
   double tol;
   int64_t K;
+  S2Budgets bud;   // Scheme II bit budgets per modulus count
 };
 
-// out[0] p used, [1] p from the network (0 if none), [2] p from the bound
-// (9 = none up to 8), [3] 1 when the features were outside the training range.
+// out[0] Scheme I slice count used (0 when Scheme II is chosen), [1] p from
+// the network (0 if none), [2] p from the bound (9 = none up to 8), [3] 1 when
+// the features were outside the training range, [4] scheme (1 or 2),
+// [5] Scheme II modulus count used (0 with Scheme I), [6] s from the Scheme II
+// bound (21 = none up to 20), [7] 0.
 __global__ __launch_bounds__(64) void k_sel_infer(const int32_t* __restrict__ cnt, SelInfer si,
                                                   int32_t* __restrict__ out, float* __restrict__ feat_out) {
   __shared__ float x[SEL_FEAT], h1[SEL_H], h2[SEL_H], z[SEL_OUT];
@@ -204,11 +222,24 @@ __global__ __launch_bounds__(64) void k_sel_infer(const int32_t* __restrict__ cn
     const bool ood = si.K > 16384 || si.tol < 1e-16 || si.tol > 1e-5 || x[15] > 0.f || x[31] > 0.f;
     int p = pb;
     if (si.w && !ood) p = p_net < pb ? p_net : pb;
-    p = p < 1 ? 1 : (p > 8 ? 8 : p);
-    out[0] = p;
+    int sb = OZK_MAX_S + 1;
+    for (int q = 1; q <= OZK_MAX_S; ++q)
+      if (s2_bound(si.bud.ta[q], si.bud.tb[q], cnt[32], cnt[33], si.K) <= si.tol) {
+        sb = q;
+        break;
+      }
+    // Scheme I while p <= 8 meets the tolerance; otherwise Scheme II at the
+    // bound's s (s = 20, the most accurate, when no count is proven enough)
+    const bool s1 = p <= OZK_MAX_P;
+    p = p < 1 ? 1 : (p > OZK_MAX_P ? OZK_MAX_P : p);
+    out[0] = s1 ? p : 0;
     out[1] = p_net;
     out[2] = pb;
     out[3] = ood ? 1 : 0;
+    out[4] = s1 ? 1 : 2;
+    out[5] = s1 ? 0 : (sb <= OZK_MAX_S ? sb : OZK_MAX_S);
+    out[6] = sb;
+    out[7] = 0;
   }
 }
 
@@ -354,7 +385,7 @@ hipError_t sel_features(const double* A, int64_t lda, int64_t M, const double* B
 
 hipError_t sel_infer(const int32_t* cnt, const float* w, float threshold, int margin, double tol, int64_t K,
                      int32_t* info, float* feat, hipStream_t st) {
-  SelInfer si{w, threshold, margin, tol, K};
+  SelInfer si{w, threshold, margin, tol, K, s2_budgets()};
   hipLaunchKernelGGL(k_sel_infer, dim3(1), dim3(64), 0, st, cnt, si, info, feat);
   return hipGetLastError();
 }

@@ -86,7 +86,7 @@ def label_from_curve(curve: List[float], tol: float) -> int:
 
 
 def features(ctx, A, B, tol: float):
-    """(34 features, info[4]) from the selector's own device kernels."""
+    """(34 features, info[8], counters) from the selector's own device kernels."""
     torch = _torch()
     M, K = A.shape
     N = B.shape[1]
@@ -94,7 +94,7 @@ def features(ctx, A, B, tol: float):
     e = torch.empty(max(M, 1), dtype=torch.int32, device=dev)
     f = torch.empty(max(N, 1), dtype=torch.int32, device=dev)
     cnt = torch.empty(34, dtype=torch.int32, device=dev)
-    info = torch.empty(4, dtype=torch.int32, device=dev)
+    info = torch.empty(ozk.OZK_SELECTOR_INFO, dtype=torch.int32, device=dev)
     feat = torch.empty(34, dtype=torch.float32, device=dev)
     st = ozk.library().ozk_select(ctx.handle, float(tol), M, N, K, A.data_ptr(), ozk._ld(A), B.data_ptr(), ozk._ld(B),
                                   e.data_ptr(), f.data_ptr(), cnt.data_ptr(), info.data_ptr(), feat.data_ptr(),
@@ -198,10 +198,9 @@ def decide(logits, threshold: float, margin: int):
 
 
 def needed(labels):
-    """Slices a sample needs: its label, or 8 when no p up to 8 meets the
-    tolerance (then the most accurate choice is the right one)."""
-    torch = _torch()
-    return torch.clamp(labels, max=8)
+    """The decision a sample needs: its smallest sufficient p, or 9 when no p
+    up to 8 meets the tolerance (then the call must go to Scheme II)."""
+    return labels
 
 
 def calibrate(ctx, w, X, labels) -> Tuple[float, int]:
@@ -257,13 +256,15 @@ def main():
     w, hist = train(ctx, Xtr, ytr, steps=a.steps)
     thr, margin = calibrate(ctx, w, Xva, yva)
     pva = decide(forward(ctx, w, Xva), thr, margin).cpu()
-    pbound = torch.clamp(bva, max=8)
-    used = torch.clamp(torch.minimum(pva, bva), 1, 8)
+    pbound = bva
+    used = torch.clamp(torch.minimum(pva, bva), 1, 9)  # 9: Scheme II
     meta = {"train_problems": a.train, "val_problems": a.val, "steps": a.steps, "loss": hist[-5:],
             "tols": "4 per problem, log-uniform in [1e-16, 1e-5]",
             "sizes": "M, N log-uniform in [64, 512], K log-uniform in [64, 16384]",
             "phi": "U(0,4) for A and for B", "threshold": thr, "margin": margin,
             "val_mean_p_selector": float(used.double().mean()), "val_mean_p_bound": float(pbound.double().mean()),
+            "val_to_scheme2_selector": int((used > 8).sum()), "val_to_scheme2_bound": int((pbound > 8).sum()),
+            "val_scheme2_needed": int((yva > 8).sum()),
             "val_mean_p_needed": float(needed(yva).double().mean()),
             "val_under": int((used < needed(yva)).sum())}
     save(a.out, w, thr, margin, meta)

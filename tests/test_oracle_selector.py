@@ -111,6 +111,40 @@ def test_bound_holds_on_oracle_errors():
             assert err <= sel.bound(p, ra, rb), (phi, p, err, sel.bound(p, ra, rb))
 
 
+def test_scheme2_bound_holds_on_oracle_errors():
+    """The Scheme II bound is never below the measured error; with a narrow
+    exponent range (phi = 0.5) it is also within 2^20 of it above the
+    rounding floor, so a dropped or misplaced term shows up either way."""
+    from oracle import scheme2 as s2
+    for phi, seed, K in ((0.5, 1, 64), (1.0, 2, 100), (2.0, 3, 37), (3.0, 4, 200)):
+        A = synth.phi_matrix(12, K, phi, 30 + seed)
+        B = synth.phi_matrix(K, 9, phi, 40 + seed)
+        hi, lo = oracle.gemm_dd(A, B)
+        ra, rb = sel.max_deficit(A, 1), sel.max_deficit(B, 0)
+        for s in (4, 6, 8, 10, 12, 14, 16):
+            err = oracle.metrics.e_cw(s2.s2_dgemm(A, B, s), hi, lo, A, B)
+            bnd = sel.bound_s2(s, ra, rb, K)
+            assert err <= bnd, (phi, s, err, bnd)
+            if phi == 0.5 and err > 1e-14:
+                assert bnd < err * 2.0 ** 20, (phi, s, err, bnd)
+
+
+def test_s_bound_monotone_and_consistent():
+    A = synth.phi_matrix(10, 50, 1.0, 1)
+    B = synth.phi_matrix(50, 8, 1.0, 2)
+    prev = 0
+    for tol in (1e-3, 1e-6, 1e-9, 1e-12, 1e-15, 1e-17):
+        s = sel.s_bound(A, B, tol)
+        assert s >= prev
+        prev = s
+        if s <= 20:
+            ra, rb = sel.max_deficit(A, 1), sel.max_deficit(B, 0)
+            assert sel.bound_s2(s, ra, rb, 50) <= tol
+            if s > 1:
+                assert sel.bound_s2(s - 1, ra, rb, 50) > tol
+    assert sel.s_bound(A, B, 1e-17) == 21  # below the rounding floor
+
+
 def test_predict_and_targets():
     y = sel.ordinal_targets(np.array([1, 3, 9]))
     assert y.tolist()[0] == [0] * 8 and y.tolist()[1] == [1, 1, 0, 0, 0, 0, 0, 0] and y.tolist()[2] == [1] * 8

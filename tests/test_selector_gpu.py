@@ -14,6 +14,7 @@ import pytest
 import oracle
 import paper_2606_25453_amd as ozk
 import synth
+from oracle import scheme2 as s2
 from oracle import selector as sel
 
 torch = pytest.importorskip("torch")
@@ -44,13 +45,22 @@ def select(ctx, A, B, tol):
     e = torch.empty(max(M, 1), dtype=torch.int32, device="cuda:0")
     f = torch.empty(max(N, 1), dtype=torch.int32, device="cuda:0")
     cnt = torch.empty(ozk.OZK_SELECTOR_COUNTERS, dtype=torch.int32, device="cuda:0")
-    info = torch.empty(4, dtype=torch.int32, device="cuda:0")
+    info = torch.empty(ozk.OZK_SELECTOR_INFO, dtype=torch.int32, device="cuda:0")
     feat = torch.empty(34, dtype=torch.float32, device="cuda:0")
     st = ozk.library().ozk_select(ctx.handle, tol, M, N, K, A.data_ptr(), ozk._ld(A), B.data_ptr(), ozk._ld(B),
                                   e.data_ptr(), f.data_ptr(), cnt.data_ptr(), info.data_ptr(), feat.data_ptr(),
                                   ozk._stream(None))
     ozk._check("ozk_select", st, ctx)
     return host(e)[:M], host(f)[:N], host(cnt), host(info), host(feat)
+
+
+def check_decision(info, p_eff):
+    """Scheme I with p_eff slices when p_eff <= 8, else Scheme II at the
+    bound's modulus count (20 when none is proven enough)."""
+    if p_eff <= 8:
+        assert info[4] == 1 and info[0] == max(p_eff, 1) and info[5] == 0, info.tolist()
+    else:
+        assert info[4] == 2 and info[0] == 0 and info[5] == min(info[6], 20), info.tolist()
 
 
 def load_params(ctx, flat, threshold=0.5, margin=0):
@@ -84,7 +94,7 @@ def dgemm_auto(ctx, tol, A, B, C=None, alpha=1.0, beta=0.0):
         C = torch.full((M, N), float("nan"), dtype=torch.float64, device="cuda:0")
     nb = ozk.ozk_workspace_size(ctx, ozk.OZK_OP_DGEMM, ozk.OZK_SCHEME1, M, N, K, 0)
     ws = torch.empty(nb, dtype=torch.uint8, device="cuda:0")
-    info = torch.empty(4, dtype=torch.int32, device="cuda:0")
+    info = torch.empty(ozk.OZK_SELECTOR_INFO, dtype=torch.int32, device="cuda:0")
     st = ozk.library().ozk_dgemm_auto(ctx.handle, tol, M, N, K, alpha, A.data_ptr(), ozk._ld(A), B.data_ptr(),
                                       ozk._ld(B), beta, C.data_ptr(), ozk._ld(C), ws.data_ptr(), nb,
                                       info.data_ptr(), ozk._stream(None))
@@ -114,7 +124,9 @@ def test_statistics_and_bound_match_oracle(ctx, M, K, N, phi, seed):
         ref = sel.features(A, B, tol)
         assert np.allclose(feat, ref, rtol=1e-6, atol=1e-7), (feat, ref)
         assert info[2] == sel.p_bound(A, B, tol)
-        assert info[1] == 0 and info[0] == min(max(info[2], 1), 8)  # no network loaded in this context
+        assert info[6] == sel.s_bound(A, B, tol)
+        assert info[1] == 0  # no network loaded in this context
+        check_decision(info, info[2])
 
 
 def test_nonfinite_lines_are_skipped(ctx):
@@ -134,12 +146,14 @@ def test_out_of_range_uses_the_bound(ctx):
     try:
         load_params(ctx2, np.full(ozk.OZK_SELECTOR_PARAMS, 0.0, np.float32), 0.5, 0)  # p_net = 1 everywhere
         _, _, _, info, _ = select(ctx2, dev(A), dev(B), 1e-10)
-        assert info[3] == 1 and info[1] == 1 and info[2] == sel.p_bound(A, B, 1e-10) and info[0] == min(info[2], 8)
+        assert info[3] == 1 and info[1] == 1 and info[2] == sel.p_bound(A, B, 1e-10)
+        check_decision(info, info[2])
         A2, B2 = A[:, :1000].copy(), B[:1000].copy()
         _, _, _, info, _ = select(ctx2, dev(A2), dev(B2), 1e-10)
-        assert info[3] == 0 and info[0] == 1  # in range: the network's choice (below the bound)
+        assert info[3] == 0 and info[4] == 1 and info[0] == 1  # in range: the network's choice
         _, _, _, info, _ = select(ctx2, dev(A2), dev(B2), 1e-17)  # tolerance outside the range
-        assert info[3] == 1 and info[0] == min(info[2], 8)
+        assert info[3] == 1
+        check_decision(info, info[2])
     finally:
         ctx2.close()
 
@@ -161,7 +175,7 @@ def test_network_decision_matches_oracle(ctx):
                     continue  # too close to the threshold to decide in float32
                 p_net = int(sel.predict_p(logits, thr, margin)[0])
                 assert info[1] == p_net
-                assert info[0] == max(1, min(p_net, info[2], 8))
+                check_decision(info, info[2] if info[3] else min(p_net, info[2]))
     finally:
         ctx2.close()
 
@@ -254,14 +268,46 @@ def test_dgemm_auto_equals_dgemm_at_chosen_p(ctx, M, K, N, phi):
         for tol in (1e-6, 1e-10, 1e-14):
             for c in (ctx, ctx2):
                 C, info = dgemm_auto(c, tol, dA, dB, dev(C0), alpha=0.75, beta=-0.5)
-                p = int(info[0])
-                assert 1 <= p <= 8
-                ref = ozk.ozk_dgemm(c, ozk.OZK_SCHEME1, p, dA, dB, dev(C0), alpha=0.75, beta=-0.5)
-                assert torch.equal(C, ref), (tol, p)
+                scheme, p, s = int(info[4]), int(info[0]), int(info[5])
+                if scheme == 1:
+                    assert 1 <= p <= 8
+                    ref = ozk.ozk_dgemm(c, ozk.OZK_SCHEME1, p, dA, dB, dev(C0), alpha=0.75, beta=-0.5)
+                    expect = oracle.s1_dgemm(A, B, p, alpha=0.75, beta=-0.5, C=C0)
+                else:
+                    assert scheme == 2 and 1 <= s <= 20
+                    ref = ozk.ozk_dgemm(c, ozk.OZK_SCHEME2, s, dA, dB, dev(C0), alpha=0.75, beta=-0.5)
+                    expect = s2.s2_dgemm(A, B, s, alpha=0.75, beta=-0.5, C=C0)
+                assert torch.equal(C, ref), (tol, info.tolist())
                 if M * N * K <= 40000:
-                    assert np.array_equal(host(C), oracle.s1_dgemm(A, B, p, alpha=0.75, beta=-0.5, C=C0))
+                    assert np.array_equal(host(C), expect)
     finally:
         ctx2.close()
+
+
+def test_dgemm_auto_takes_scheme2_when_scheme1_cannot(ctx):
+    """A wide exponent range and a tight tolerance: no slice count up to 8 is
+    proven enough, so the modulus count of the Scheme II bound is used; the
+    result is bit-identical to Scheme II at that s and to the oracle, and it
+    meets the tolerance whenever the bound proved that s enough."""
+    A = synth.phi_matrix(45, 90, 3.0, 91)
+    B = synth.phi_matrix(90, 30, 3.0, 92)
+    dA, dB = dev(A), dev(B)
+    hi, lo = oracle.gemm_dd(A, B)
+    seen = False
+    for tol in (1e-8, 1e-11, 1e-14):
+        if sel.p_bound(A, B, tol) <= 8:
+            continue
+        seen = True
+        C, info = dgemm_auto(ctx, tol, dA, dB)
+        sb = sel.s_bound(A, B, tol)
+        assert info[4] == 2 and info[0] == 0 and info[6] == sb and info[5] == min(sb, 20), info.tolist()
+        s = int(info[5])
+        got = host(C)
+        assert np.array_equal(got, host(ozk.ozk_dgemm(ctx, ozk.OZK_SCHEME2, s, dA, dB)))
+        assert np.array_equal(got, s2.s2_dgemm(A, B, s))
+        if sb <= 20:
+            assert oracle.metrics.e_cw(got, hi, lo, A, B) <= tol
+    assert seen  # the inputs do leave Scheme I unproven at some tolerance
 
 
 def test_dgemm_auto_long_k_folds(ctx):
@@ -271,8 +317,10 @@ def test_dgemm_auto_long_k_folds(ctx):
     B = synth.phi_matrix(K, 2, 0.5, 71)
     dA, dB = dev(A), dev(B)
     C, info = dgemm_auto(ctx, 1e-12, dA, dB)
-    p = int(info[0])
-    assert torch.equal(C, ozk.ozk_dgemm(ctx, ozk.OZK_SCHEME1, p, dA, dB))
+    if info[4] == 1:
+        assert torch.equal(C, ozk.ozk_dgemm(ctx, ozk.OZK_SCHEME1, int(info[0]), dA, dB))
+    else:
+        assert torch.equal(C, ozk.ozk_dgemm(ctx, ozk.OZK_SCHEME2, int(info[5]), dA, dB))
 
 
 def test_dgemm_auto_graph_replay(ctx):
@@ -282,7 +330,7 @@ def test_dgemm_auto_graph_replay(ctx):
     C = torch.zeros((200, 150), dtype=torch.float64, device="cuda:0")
     nb = ozk.ozk_workspace_size(ctx, ozk.OZK_OP_DGEMM, ozk.OZK_SCHEME1, 200, 150, 300, 0)
     ws = torch.empty(nb, dtype=torch.uint8, device="cuda:0")
-    info = torch.zeros(4, dtype=torch.int32, device="cuda:0")
+    info = torch.zeros(ozk.OZK_SELECTOR_INFO, dtype=torch.int32, device="cuda:0")
     lib = ozk.library()
 
     def run(stream):
@@ -307,7 +355,8 @@ def test_dgemm_auto_graph_replay(ctx):
         g.replay()
         torch.cuda.synchronize()
         assert np.array_equal(host(C), eager), rep
-        assert 1 <= int(host(info)[0]) <= 8
+        i = host(info)
+        assert (i[4] == 1 and 1 <= i[0] <= 8) or (i[4] == 2 and 1 <= i[5] <= 20)
 
 
 def test_invalid_arguments(ctx):
@@ -332,9 +381,12 @@ WEIGHTS = os.path.join(os.path.dirname(ozk.__file__), "selector_weights.json")
 def test_trained_selector_never_misses_the_tolerance(ctx):
     """Fresh problems (seeds outside the training and calibration sets): the
     chosen p always meets the tolerance (judged by the double-double
-    reference) when some p <= 8 does, is 8 when none does, and on average
-    uses fewer slices than the bound."""
+    reference), so does Scheme II when the network sends a problem there at
+    a proven modulus count, and on average fewer slices are used than with
+    the bound alone."""
     from paper_2606_25453_amd import selector as train
+    if "val_scheme2_needed" not in train.load()["meta"]:
+        pytest.skip("parameters calibrated before the Scheme II fallback; retrain")
     ctx2 = ozk.Context(0)
     try:
         train.install(ctx2)
@@ -345,16 +397,13 @@ def test_trained_selector_never_misses_the_tolerance(ctx):
             phi_a, phi_b = 4.0 * (i % 7) / 6.0, 4.0 * ((i * 3) % 7) / 6.0
             A, B = train.random_problem(gen, M, N, K, phi_a, phi_b, "cuda:0")
             hi, lo, ab = train.dd_reference(ctx2, A, B)
-            err8 = train.e_cw(ozk.ozk_dgemm(ctx2, ozk.OZK_SCHEME1, 8, A, B), hi, lo, ab)
             for tol in (1e-6, 1e-9, 1e-12, 1e-14):
                 C, info = dgemm_auto(ctx2, tol, A, B)
                 err = train.e_cw(C, hi, lo, ab)
-                if err8 <= tol:
+                if info[4] == 1 or info[6] <= 20:  # Scheme I, or Scheme II at a proven s
                     assert err <= tol, (i, M, N, K, phi_a, phi_b, tol, info.tolist(), err)
-                else:  # no slice count meets it: the most accurate one
-                    assert info[0] == 8, (i, M, N, K, phi_a, phi_b, tol, info.tolist(), err8)
-                used.append(int(info[0]))
-                bound.append(min(int(info[2]), 8))
+                used.append(int(info[0]) if info[4] == 1 else 9)
+                bound.append(min(int(info[2]), 9))
         assert np.mean(used) < np.mean(bound)
     finally:
         ctx2.close()
