@@ -25,6 +25,16 @@ sys.path.insert(0, ROOT)
 INT8_PEAK_TOPS = 5000.0  # MI355X dense INT8 MFMA, TOP/s
 
 
+# HBM bytes per launch of the Scheme I GEMM kernel, measured with rocprofv3
+# FETCH_SIZE / WRITE_SIZE passes on this build's kernel (FETCH scaled by 2.0
+# and WRITE by 1.0, the factors a 1 GiB device copy gives the two counters);
+# keyed by (n, p, configuration).  Reported only when the run matches; a
+# changed kernel needs new counter passes.
+MEASURED_GEMM_TRAFFIC = {
+    (8192, 7, (1, 1, 16, 1)): 19334846464,
+}
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -36,7 +46,9 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
     ap.add_argument("--no-native", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (default configurations)")
+    ap.add_argument("--tune", action="store_true",
+                    help="run the autotuner in the warm-up instead of loading the shipped configuration table")
+    ap.add_argument("--no-tune", action="store_true", help="default configurations only (no table, no tuning)")
     ap.add_argument("--save-config", default=None, help="write the tuned configuration table (JSON)")
     ap.add_argument("--load-config", default=None, help="use a saved configuration table instead of tuning")
     ap.add_argument("--err-samples", type=int, default=4096, help="outputs sampled for the accuracy check")
@@ -145,6 +157,9 @@ def main():
 
     ps = sorted({p, 8} if p != 8 else {8})
     tuned = {}
+    shipped = os.path.join(os.path.dirname(os.path.abspath(ozk.__file__)), "gemm_configs.json")
+    if not args.load_config and not args.tune and not args.no_tune and os.path.exists(shipped):
+        args.load_config = shipped
     if args.load_config:
         ozk.ozk_config_load(ctx, args.load_config)
         for pp in ps:
@@ -152,7 +167,7 @@ def main():
             if found:
                 tuned[pp] = {"variant": cfg[0], "raster": cfg[1], "group": cfg[2], "split": cfg[3],
                              "tuned_gemm_ms": round(tms, 4), "loaded": True}
-    elif not args.no_tune:  # untimed: pick the GEMM configuration of this size class
+    elif args.tune:  # untimed: pick the GEMM configuration of this size class
         for pp in ps:
             _, cfg, tms = ozk.ozk_tune(ctx, ozk.OZK_OP_DGEMM, ozk.OZK_SCHEME1, pp, a, b, C=c, reps=2)
             tuned[pp] = {"variant": cfg[0], "raster": cfg[1], "group": cfg[2], "split": cfg[3],
@@ -213,6 +228,9 @@ def main():
     r = results[p]
     value = 2.0 * M * N * K / (r["ms"] * 1e-3) / 1e12
     ops = p * (p + 1) * M * N * K  # INT8 ops of the p(p+1)/2 slice-pair GEMMs
+    cfg = tuned.get(p)
+    cfg_key = None if cfg is None else (cfg["variant"], cfg["raster"], cfg["group"], cfg["split"])
+    traffic = MEASURED_GEMM_TRAFFIC.get((n, p, cfg_key)) if M == N == K else None
     achieved = ops / (r["gemm_ms"] * 1e-3) / 1e12
     line = {
         "metric": "emulated FP64 TFLOP/s + %INT8-MFMA peak vs native DGEMM at rel err <=1e-13",
@@ -230,7 +248,7 @@ def main():
         "config": {"workload": "Ozaki Scheme I DGEMM %dx%dx%d, phi=%g, p=%d" % (M, N, K, args.phi, p),
                    "M": M, "N": N, "K": K, "p": p, "phi": args.phi},
         "roofline": {"bound": "mfma", "achieved": round(achieved, 1), "peak": INT8_PEAK_TOPS,
-                     "unit": "TFLOP/s", "frac": round(achieved / INT8_PEAK_TOPS, 4), "traffic": None,
+                     "unit": "TFLOP/s", "frac": round(achieved / INT8_PEAK_TOPS, 4), "traffic": traffic,
                      "kernel": "k_s1_gemm", "kernel_ms": round(r["gemm_ms"], 4),
                      "algorithmic_ops_per_launch": ops},
         "pct_int8_peak_end_to_end": round(100.0 * ops / (r["ms"] * 1e-3) / 1e12 / INT8_PEAK_TOPS, 2),
