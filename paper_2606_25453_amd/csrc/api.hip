@@ -735,7 +735,7 @@ ozk_status ozk_batch_plan_create(ozk_ctx* ctx, ozk_op op, ozk_scheme scheme, int
     const bool live = q.M > 0 && q.N > 0;
     rows[i + 1] = rows[i] + (live ? q.ra / 4 : 0);
     cols[i + 1] = cols[i] + (live ? (q.N + 31) / 32 : 0);
-    split[i + 1] = split[i] + (live ? (q.rb / 256) * (q.Kp / OZK_K_CHUNK) : 0);
+    split[i + 1] = split[i] + (live ? (q.rb / 256) * (q.Kp / (OZK_K_CHUNK / 2)) : 0);  // 16-k half chunks
     crt[i + 1] = crt[i] + (live ? (q.M * q.N + 255) / 256 : 0);
   }
   for (int i = 0; i < count; ++i) items[i + 1] = items[i] + prob[order[i]].tiles * s;

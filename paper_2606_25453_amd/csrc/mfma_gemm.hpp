@@ -17,8 +17,15 @@
 // [P][BM][32] (A) + [P][BN][32] (B) bytes are filled with 16-byte
 // global-to-LDS loads (no staging registers) up to NS - 1 steps ahead of
 // use; one barrier per K step; the fragments of the next step are read from
-// LDS while the MFMAs of the current one run.  In LDS, 8 consecutive rows of one slab are 8 distinct
-// 32-byte lines, so the 16-byte fragment reads are bank-conflict free.
+// LDS while the MFMAs of the current one run.
+//
+// LDS swizzle.  A fragment read has lane l take row r = l % 32, 16-byte half
+// h = l / 32 of a slab; stored plainly, rows r and r + 4 (r + 8) of one
+// 8-lane (16-lane) group hit the same banks.  Each 32-byte row therefore
+// stores its halves in the order h ^ f(r), f(r) = bit 2 of r ^ bit 3 of r,
+// which spreads every group over all banks.  The direct-to-LDS load writes
+// lane i's 16 bytes to chunk offset 16 i, so the permutation is applied on
+// the global side: lane i loads the piece 16 (i ^ f(i / 2)) of its 1 KB chunk.
 #pragma once
 #include "ozk_device.hpp"
 
@@ -199,10 +206,11 @@ __device__ __forceinline__ void gemm_tile_accumulate(const int8_t* __restrict__ 
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int wm = wave >> 1, wn = wave & 1;
-  const int lrow = lane & 31, lk = 16 * (lane >> 5);
+  // fragment row and swizzled half (see the LDS swizzle above)
+  const int lrow = lane & 31, lk = 16 * ((lane >> 5) ^ (((lane >> 2) ^ (lane >> 3)) & 1));
   StageLoads<P, TM, TN, NS> ld(Ap, Bp, rows_a, rows_b, m0, n0, step0, wave);
   if (nsteps <= 0) return;
-  const uint32_t lane16 = 16u * (uint32_t)lane;
+  const uint32_t lane16 = 16u * (uint32_t)(lane ^ (((lane >> 3) ^ (lane >> 4)) & 1));  // source piece of lane
   const int lead = (int)(nsteps & 1);  // 1: a virtual step -1 comes first
   // stages issued ahead: 0 .. NS-1 (NS-2 with the virtual step, whose own
   // refill issues stage NS-1)

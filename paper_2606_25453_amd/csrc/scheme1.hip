@@ -39,6 +39,7 @@ template <int P>
 __device__ __forceinline__ void s1_slice_row(const double* __restrict__ xr, int64_t r, int64_t rows, int64_t K,
                                              int64_t Kp, int64_t rows_packed, int e, int8_t* __restrict__ packed) {
   const int lane = threadIdx.x & 63;
+#pragma unroll 4
   for (int64_t k0 = (int64_t)lane * 4; k0 < Kp; k0 += 256) {
     uint32_t word[P];
 #pragma unroll
@@ -71,6 +72,7 @@ __global__ __launch_bounds__(256) void k_s1_split_rows(const double* __restrict_
   int e = OZK_EXP_ZERO;
   const double* xr = X + r * ldx;
   if (r < rows) {
+#pragma unroll 8
     for (int64_t k = lane; k < K; k += 64) {
       const int ek = expo_of(xr[k]);
       e = ek > e ? ek : e;
@@ -117,6 +119,7 @@ __global__ __launch_bounds__(256) void k_s1_exp_cols(const double* __restrict__ 
   const int64_t k0 = (int64_t)blockIdx.y * 256;
   const int64_t k1 = k0 + 256 < K ? k0 + 256 : K;
   int e = OZK_EXP_ZERO;
+#pragma unroll 8
   for (int64_t k = k0; k < k1; ++k) {
     const int ek = expo_of(X[k * ldx + j]);
     e = ek > e ? ek : e;

@@ -163,6 +163,7 @@ __device__ __forceinline__ void s2_split_rows_block(const double* __restrict__ X
   int sigma = 0;
   if (r < rows) {
     int e = OZK_EXP_ZERO;
+#pragma unroll 8
     for (int64_t k = lane; k < K; k += 64) {
       const int ek = entry_expo<CPLX>(xr + k * W);
       e = ek > e ? ek : e;
@@ -170,6 +171,7 @@ __device__ __forceinline__ void s2_split_rows_block(const double* __restrict__ X
     e = wave_max(e);
     int64_t S = 0;
     if (e != OZK_EXP_NONFINITE && e != OZK_EXP_ZERO)
+#pragma unroll 8
       for (int64_t k = lane; k < K; k += 64) S += norm_term(entry_expo<CPLX>(xr + k * W), e);
     S = wave_sum64(S);
     sigma = scale_from(e, S, sa.T);
@@ -177,6 +179,7 @@ __device__ __forceinline__ void s2_split_rows_block(const double* __restrict__ X
   }
   const bool live = r < rows && sigma != OZK_EXP_NONFINITE;
   const int64_t plane = rows_packed * Kp * (CPLX ? 3 : 1);
+#pragma unroll 4
   for (int64_t k0 = (int64_t)lane * 4; k0 < Kp; k0 += 256) {
     ScaledInt vr[4], vi[4];
 #pragma unroll
@@ -236,6 +239,7 @@ __device__ __forceinline__ void s2_col_scales_block(const double* __restrict__ X
   const bool in = j < cols;
   int e = OZK_EXP_ZERO;
   if (in)
+#pragma unroll 8
     for (int64_t k = g; k < K; k += 8) {
       const int ek = entry_expo<CPLX>(X + (k * ldx + j) * W);
       e = ek > e ? ek : e;
@@ -247,6 +251,7 @@ __device__ __forceinline__ void s2_col_scales_block(const double* __restrict__ X
   for (int i = 1; i < 8; ++i) emax = red_e[i][cl] > emax ? red_e[i][cl] : emax;
   int64_t S = 0;
   if (in && emax != OZK_EXP_ZERO && emax != OZK_EXP_NONFINITE)
+#pragma unroll 8
     for (int64_t k = g; k < K; k += 8) S += norm_term(entry_expo<CPLX>(X + (k * ldx + j) * W), emax);
   red_s[g][cl] = S;
   __syncthreads();
@@ -264,21 +269,27 @@ __global__ __launch_bounds__(256) void k_s2_col_scales(const double* __restrict_
   s2_col_scales_block<CPLX>(X, ldx, K, cols, T, tau, blockIdx.x);
 }
 
-// Thread (j, c): the 32 k of chunk c of column j, residues for every modulus.
+// Thread (j, hc): the 16 k of half-chunk hc (chunk hc / 2, half hc % 2) of
+// column j, residues for every modulus, written as one 16-byte piece per
+// plane (half a 32-byte packed row; 16 k keep the per-thread state small
+// enough for several waves per SIMD).
+constexpr int S2_COL_K = OZK_K_CHUNK / 2;
+
 template <bool CPLX>
 __device__ __forceinline__ void s2_split_cols_block(const double* __restrict__ X, int64_t ldx, int64_t K,
                                                     int64_t cols, int64_t Kp, int64_t cols_packed, int s,
                                                     const int32_t* __restrict__ tau, int8_t* __restrict__ packed,
-                                                    int64_t jb, int64_t c) {
+                                                    int64_t jb, int64_t hc) {
   constexpr int W = CPLX ? 2 : 1;
   const int64_t j = jb * 256 + threadIdx.x;
   if (j >= cols_packed) return;
+  const int64_t c = hc >> 1, k0 = hc * S2_COL_K;
   const int t = j < cols ? tau[j] : 0;
   const bool live = j < cols && t != OZK_EXP_NONFINITE;
-  ScaledInt vr[OZK_K_CHUNK], vi[CPLX ? OZK_K_CHUNK : 1];
+  ScaledInt vr[S2_COL_K], vi[CPLX ? S2_COL_K : 1];
 #pragma unroll
-  for (int kk = 0; kk < OZK_K_CHUNK; ++kk) {
-    const int64_t k = c * OZK_K_CHUNK + kk;
+  for (int kk = 0; kk < S2_COL_K; ++kk) {
+    const int64_t k = k0 + kk;
     const bool in = live && k < K;
     vr[kk] = scaled_int(in ? X[(k * ldx + j) * W] : 0.0, t);
     if (CPLX) vi[CPLX ? kk : 0] = scaled_int(in ? X[(k * ldx + j) * W + 1] : 0.0, t);
@@ -286,9 +297,9 @@ __device__ __forceinline__ void s2_split_cols_block(const double* __restrict__ X
   const int64_t plane = cols_packed * Kp * (CPLX ? 3 : 1);
   for (int l = 0; l < s; ++l) {
     const int m = c_s2.m[l];
-    uint32_t w0[8] = {0, 0, 0, 0, 0, 0, 0, 0}, w1[8] = {0, 0, 0, 0, 0, 0, 0, 0}, w2[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    uint32_t w0[4] = {0, 0, 0, 0}, w1[4] = {0, 0, 0, 0}, w2[4] = {0, 0, 0, 0};
 #pragma unroll
-    for (int kk = 0; kk < OZK_K_CHUNK; ++kk) {
+    for (int kk = 0; kk < S2_COL_K; ++kk) {
       const int a = residue_of(vr[kk], l);
       w0[kk / 4] |= (uint32_t)(uint8_t)a << (8 * (kk % 4));
       if (CPLX) {
@@ -299,17 +310,11 @@ __device__ __forceinline__ void s2_split_cols_block(const double* __restrict__ X
     }
     constexpr int NP = CPLX ? 3 : 1;
     const int64_t slab = cols_packed * OZK_K_CHUNK;
-    int8_t* dst = packed + l * plane + c * NP * slab + j * OZK_K_CHUNK;
-    uint4* q0 = reinterpret_cast<uint4*>(dst);
-    q0[0] = make_uint4(w0[0], w0[1], w0[2], w0[3]);
-    q0[1] = make_uint4(w0[4], w0[5], w0[6], w0[7]);
+    int8_t* dst = packed + l * plane + c * NP * slab + j * OZK_K_CHUNK + (hc & 1) * S2_COL_K;
+    *reinterpret_cast<uint4*>(dst) = make_uint4(w0[0], w0[1], w0[2], w0[3]);
     if (CPLX) {
-      uint4* q1 = reinterpret_cast<uint4*>(dst + slab);
-      q1[0] = make_uint4(w1[0], w1[1], w1[2], w1[3]);
-      q1[1] = make_uint4(w1[4], w1[5], w1[6], w1[7]);
-      uint4* q2 = reinterpret_cast<uint4*>(dst + 2 * slab);
-      q2[0] = make_uint4(w2[0], w2[1], w2[2], w2[3]);
-      q2[1] = make_uint4(w2[4], w2[5], w2[6], w2[7]);
+      *reinterpret_cast<uint4*>(dst + slab) = make_uint4(w1[0], w1[1], w1[2], w1[3]);
+      *reinterpret_cast<uint4*>(dst + 2 * slab) = make_uint4(w2[0], w2[1], w2[2], w2[3]);
     }
   }
 }
@@ -411,11 +416,16 @@ struct CrtArgs {
 // Z = smod(sum_l W_l c_l, P) as a sign and magnitude limbs.
 __device__ __forceinline__ void crt_combine(const CrtArgs& ca, const int8_t* res, int64_t stride, uint32_t (&mag)[NL],
                                             bool& neg) {
+  // all residues first (independent loads in flight together), then the sum
+  int cv[OZK_MAX_S];
+#pragma unroll
+  for (int l = 0; l < OZK_MAX_S; ++l) cv[l] = l < ca.s ? (int)res[l * stride] : 0;
   uint64_t acc[NL] = {0, 0, 0, 0, 0, 0};
-  for (int l = 0; l < ca.s; ++l) {
-    const int m = c_s2.m[l];
-    int c = res[l * stride];
-    if (c < 0) c += m;
+#pragma unroll
+  for (int l = 0; l < OZK_MAX_S; ++l) {
+    if (l >= ca.s) break;
+    int c = cv[l];
+    if (c < 0) c += c_s2.m[l];
 #pragma unroll
     for (int i = 0; i < NL; ++i) acc[i] += (uint64_t)ca.W[l][i] * (uint32_t)c;
   }
@@ -688,10 +698,10 @@ hipError_t s2_split_cols(int s, bool cplx, const double* X, int64_t ldx, int64_t
   }
   if (cp > 0 && kp > 0) {
     if (cplx)
-      hipLaunchKernelGGL(k_s2_split_cols<true>, dim3((unsigned)(cp / 256), (unsigned)(kp / OZK_K_CHUNK)),
+      hipLaunchKernelGGL(k_s2_split_cols<true>, dim3((unsigned)(cp / 256), (unsigned)(kp / S2_COL_K)),
                          dim3(256), 0, st, X, ldx, K, cols, kp, cp, s, tau, packed);
     else
-      hipLaunchKernelGGL(k_s2_split_cols<false>, dim3((unsigned)(cp / 256), (unsigned)(kp / OZK_K_CHUNK)),
+      hipLaunchKernelGGL(k_s2_split_cols<false>, dim3((unsigned)(cp / 256), (unsigned)(kp / S2_COL_K)),
                          dim3(256), 0, st, X, ldx, K, cols, kp, cp, s, tau, packed);
   }
   return hipGetLastError();
@@ -842,7 +852,7 @@ hipError_t s2_split_cols_auto(const int32_t* info, const double* X, int64_t ldx,
     hipLaunchKernelGGL(k_s2_col_scales_auto, dim3((unsigned)((cols + 31) / 32)), dim3(256), 0, st, X, ldx, K, cols,
                        info, s2_budgets(), tau);
   if (cp > 0 && kp > 0)
-    hipLaunchKernelGGL(k_s2_split_cols_auto, dim3((unsigned)(cp / 256), (unsigned)(kp / OZK_K_CHUNK)), dim3(256),
+    hipLaunchKernelGGL(k_s2_split_cols_auto, dim3((unsigned)(cp / 256), (unsigned)(kp / S2_COL_K)), dim3(256),
                        0, st, X, ldx, K, cols, kp, cp, info, tau, packed);
   return hipGetLastError();
 }

@@ -62,6 +62,7 @@ __global__ __launch_bounds__(256) void k_sel_rows(const double* __restrict__ X, 
   if (r < rows) {
     const double* xr = X + r * ldx;
     int e = OZK_EXP_ZERO;
+#pragma unroll 8
     for (int64_t k = lane; k < K; k += 64) {
       const int ek = expo_of(xr[k]);
       e = ek > e ? ek : e;
@@ -70,6 +71,7 @@ __global__ __launch_bounds__(256) void k_sel_rows(const double* __restrict__ X, 
     if (lane == 0) e_out[r] = e;
     int dmax = 0;
     if (e != OZK_EXP_ZERO && e != OZK_EXP_NONFINITE) {
+#pragma unroll 8
       for (int64_t k = lane; k < K; k += 64) {
         const int ek = expo_of(xr[k]);
         if (ek == OZK_EXP_ZERO) continue;
@@ -101,6 +103,7 @@ __global__ __launch_bounds__(256) void k_sel_cols(const double* __restrict__ X, 
   if (threadIdx.x == 0) md = 0;
   int e = OZK_EXP_ZERO;
   if (in)
+#pragma unroll 8
     for (int64_t k = g; k < K; k += 8) {
       const int ek = expo_of(X[k * ldx + j]);
       e = ek > e ? ek : e;
@@ -113,6 +116,7 @@ __global__ __launch_bounds__(256) void k_sel_cols(const double* __restrict__ X, 
   if (in && g == 0) f_out[j] = emax;
   int dmax = 0;
   if (in && emax != OZK_EXP_ZERO && emax != OZK_EXP_NONFINITE)
+#pragma unroll 8
     for (int64_t k = g; k < K; k += 8) {
       const int ek = expo_of(X[k * ldx + j]);
       if (ek == OZK_EXP_ZERO) continue;

@@ -122,6 +122,7 @@ def main():
     ap.add_argument("--quick", action="store_true", help="the smaller sizes only")
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--out", default=None, help="also append the lines to this file")
+    ap.add_argument("--only", default=None, help="comma-separated subset of s1, s2, batch")
     args = ap.parse_args()
     import torch
     ozk.library()
@@ -134,6 +135,9 @@ def main():
     if not args.quick:
         jobs += [("s1", 8192, p) for p in (6, 7, 8)]
         jobs += [("s2", 8192, 8192, 8192, 16, True)]
+    if args.only:
+        keep = set(args.only.split(","))
+        jobs = [j for j in jobs if j[0] in keep]
     out = open(args.out, "a") if args.out else None
     for job in jobs:
         if job[0] == "s1":
