@@ -83,7 +83,7 @@ extern "C" {
 #define OZK_MAX_S 20
 #define OZK_MAX_ROWS 16777216       /* 2^24: largest M, N (32-bit packed offsets) */
 #define OZK_S1_VARIANTS 4           /* Scheme I GEMM tile variants */
-#define OZK_S2_VARIANTS 2           /* Scheme II GEMM tile variants */
+#define OZK_S2_VARIANTS 4           /* Scheme II GEMM tile variants */
 #define OZK_SELECTOR_PARAMS 6920   /* float32 parameters of the selector MLP */
 #define OZK_SELECTOR_COUNTERS 34   /* int32 feature counters */
 #define OZK_SELECTOR_INFO 8        /* int32 decision entries */
@@ -366,7 +366,10 @@ ozk_status ozk_batch_plan_destroy(ozk_batch_plan* plan);
  *   variant: tile variant, Scheme I 0 .. OZK_S1_VARIANTS-1 (bit 1: the other
  *            wave-tile orientation, 128x64 <-> 128x128 for p <= 4 and
  *            128x64 <-> 64x128 for p >= 5; bit 0: one LDS stage fewer),
- *            Scheme II 0 .. OZK_S2_VARIANTS-1 (1: one LDS stage fewer);
+ *            Scheme II 0 .. OZK_S2_VARIANTS-1 (bit 1: the large tile,
+ *            256x128 real, 128x128 3M, instead of 128x128 / 128x64, taken
+ *            only while K <= 131040 and replaced by the base tile beyond;
+ *            bit 0: one LDS stage fewer);
  *   raster:  0 = tiles of one XCD form a compact block, 1 = dispatch order;
  *   group:   tile rows per raster group, 1 .. 64;
  *   split:   Scheme I only: at least this many K runs (their 128-bit partial

@@ -735,7 +735,7 @@ ozk_status ozk_batch_plan_create(ozk_ctx* ctx, ozk_op op, ozk_scheme scheme, int
     const bool live = q.M > 0 && q.N > 0;
     rows[i + 1] = rows[i] + (live ? q.ra / 4 : 0);
     cols[i + 1] = cols[i] + (live ? (q.N + 31) / 32 : 0);
-    split[i + 1] = split[i] + (live ? (q.rb / 256) * (q.Kp / (OZK_K_CHUNK / 2)) : 0);  // 16-k half chunks
+    split[i + 1] = split[i] + (live ? ozk::s2_split_cols_blocks(q.rb, q.Kp) : 0);
     crt[i + 1] = crt[i] + (live ? (q.M * q.N + 255) / 256 : 0);
   }
   for (int i = 0; i < count; ++i) items[i + 1] = items[i] + prob[order[i]].tiles * s;
@@ -748,10 +748,27 @@ ozk_status ozk_batch_plan_create(ozk_ctx* ctx, ozk_op op, ozk_scheme scheme, int
   pl->count = count;
   pl->ws_bytes = o > 0 ? o : 256;
   pl->tot = {rows[count], cols[count], split[count], items[count], crt[count]};
-  // device tables: problems, then six int64 prefix arrays, then the order
+  // coarse indexes: hint[b] = the problem holding unit min(64 b, total - 1)
+  auto hints = [&](const std::vector<int64_t>& start) {
+    const int64_t tot = start[count];
+    std::vector<int32_t> h((size_t)((tot >> ozk::OZK_BATCH_HINT_SHIFT) + 2), 0);
+    int i = 0;
+    for (size_t b = 0; b < h.size(); ++b) {
+      const int64_t x = std::min<int64_t>((int64_t)b << ozk::OZK_BATCH_HINT_SHIFT, tot > 0 ? tot - 1 : 0);
+      while (i + 1 < count && start[i + 1] <= x) ++i;  // the largest i with start[i] <= x
+      h[b] = i;
+    }
+    return h;
+  };
+  const std::vector<int32_t> h_rows = hints(rows), h_cols = hints(cols), h_split = hints(split),
+                             h_items = hints(items), h_crt = hints(crt);
+  // device tables: problems, six int64 prefix arrays, the order, five hint arrays
   const size_t nprob = sizeof(ozk::BatchProb) * (count > 0 ? count : 1);
   const size_t npre = sizeof(int64_t) * (count + 1);
-  const size_t total = align256(nprob) + 6 * align256(npre) + align256(sizeof(int32_t) * (count > 0 ? count : 1));
+  size_t nhint = 0;
+  for (const auto* h : {&h_rows, &h_cols, &h_split, &h_items, &h_crt}) nhint += align256(sizeof(int32_t) * h->size());
+  const size_t total =
+      align256(nprob) + 6 * align256(npre) + align256(sizeof(int32_t) * (count > 0 ? count : 1)) + nhint;
   if (hipMalloc(&pl->dev, total) != hipSuccess) {
     free(pl);
     return fail(ctx, OZK_ERR_HIP, 0);
@@ -773,17 +790,22 @@ ozk_status ozk_batch_plan_create(ozk_ctx* ctx, ozk_op op, ozk_scheme scheme, int
   void* r5 = put(crt.data(), npre);
   off += align256(npre);  // spare
   void* r6 = put(order.data(), sizeof(int32_t) * count);
-  if ((count > 0 && (!pp || !r6)) || !r1 || !r2 || !r3 || !r4 || !r5) {
+  void* q1 = put(h_rows.data(), sizeof(int32_t) * h_rows.size());
+  void* q2 = put(h_cols.data(), sizeof(int32_t) * h_cols.size());
+  void* q3 = put(h_split.data(), sizeof(int32_t) * h_split.size());
+  void* q4 = put(h_items.data(), sizeof(int32_t) * h_items.size());
+  void* q5 = put(h_crt.data(), sizeof(int32_t) * h_crt.size());
+  if ((count > 0 && (!pp || !r6)) || !r1 || !r2 || !r3 || !r4 || !r5 || !q1 || !q2 || !q3 || !q4 || !q5) {
     (void)hipFree(pl->dev);
     free(pl);
     return fail(ctx, OZK_ERR_HIP, 0);
   }
   pl->bd.prob = (const ozk::BatchProb*)pp;
-  pl->bd.rows_start = (const int64_t*)r1;
-  pl->bd.cols_start = (const int64_t*)r2;
-  pl->bd.split_start = (const int64_t*)r3;
-  pl->bd.item_start = (const int64_t*)r4;
-  pl->bd.crt_start = (const int64_t*)r5;
+  pl->bd.rows = {(const int64_t*)r1, (const int32_t*)q1};
+  pl->bd.cols = {(const int64_t*)r2, (const int32_t*)q2};
+  pl->bd.split = {(const int64_t*)r3, (const int32_t*)q3};
+  pl->bd.items = {(const int64_t*)r4, (const int32_t*)q4};
+  pl->bd.crt = {(const int64_t*)r5, (const int32_t*)q5};
   pl->bd.order = (const int32_t*)r6;
   pl->bd.count = count;
   hipDeviceProp_t prop;

@@ -27,6 +27,8 @@
 // lane i's 16 bytes to chunk offset 16 i, so the permutation is applied on
 // the global side: lane i loads the piece 16 (i ^ f(i / 2)) of its 1 KB chunk.
 #pragma once
+#include <utility>
+
 #include "ozk_device.hpp"
 
 namespace ozk {
@@ -63,6 +65,19 @@ template <int N>
 __device__ __forceinline__ void wait_vmcnt() {
   static_assert(N >= 0 && N < 64, "vmcnt range");
   __builtin_amdgcn_s_waitcnt((N & 0xF) | ((N >> 4) << 14) | (0x7 << 4) | (0xF << 8));
+}
+
+// One 16-byte-per-lane direct-to-LDS load: lane i's 16 bytes at gsrc land at
+// lds_dst + 16 i.  Issued as inline assembly so that the compiler does not
+// track it as an LDS write: its own tracking cannot tell LDS stages apart and
+// would wait for every load in flight before each fragment read, which
+// defeats staging more than one step ahead.  Completion is therefore the
+// caller's business: an explicit vmcnt wait, then a barrier, before any wave
+// reads the stage (vmcnt counts these loads like any other).  M0 holds the
+// LDS base; one wait state separates its write from the load.
+__device__ __forceinline__ void lds_dma16(const int8_t* gsrc, int8_t* lds_dst) {
+  const uint32_t m0 = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) int8_t*)lds_dst;
+  asm volatile("s_mov_b32 m0, %0\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %1, off" ::"s"(m0), "v"(gsrc) : "memory", "m0");
 }
 
 // This wave's share of the direct-to-LDS loads of one stage: chunk j of the
@@ -115,8 +130,7 @@ struct StageLoads {
       // straddles the end of the A slabs
       const bool is_a = (4 * j + 3 < A_CH) || (4 * j < A_CH && 4 * j + wave < A_CH);
       const int8_t* base = is_a ? a_next : b_next;
-      __builtin_amdgcn_global_load_lds(reinterpret_cast<const void*>(base + off[j] + lane16),
-                                       reinterpret_cast<void*>(stage_lds + dst[j]), 16, 0, 0);
+      lds_dma16(base + off[j] + lane16, stage_lds + dst[j]);
     }
     a_next += a_step;
     b_next += b_step;
@@ -152,6 +166,25 @@ __device__ __forceinline__ void read_frags(StepFrags<P, TM, TN>& F, const int8_t
 #pragma unroll
     for (int b = 0; b < TN; ++b)
       F.b[u][b] = *reinterpret_cast<const v4i*>(lb + (u * T::BN + wn * 32 * TN + b * 32 + lrow) * OZK_K_CHUNK + lk);
+}
+
+// Instruction order of one K step after its barrier: one LDS fragment read,
+// then MPR MFMAs, repeated for all NR reads, then the remaining MFMAs.  The
+// reads of the next step thus start at once and are spread over most of the
+// step instead of being bunched at its end (where the next barrier's wait
+// would expose their latency), while never more than one read sits between
+// two MFMA issues.
+template <int MPR, int... I>
+__device__ __forceinline__ void sched_reads_mfmas(std::integer_sequence<int, I...>) {
+  (((void)I, __builtin_amdgcn_sched_group_barrier(0x100, 1, 0), __builtin_amdgcn_sched_group_barrier(0x008, MPR, 0)),
+   ...);
+}
+
+template <int NR, int NM>
+__device__ __forceinline__ void sched_step() {
+  constexpr int MPR = NM / NR >= 2 ? 2 : 1;
+  sched_reads_mfmas<MPR>(std::make_integer_sequence<int, NR>{});
+  if constexpr (NM > MPR * NR) __builtin_amdgcn_sched_group_barrier(0x008, NM - MPR * NR, 0);
 }
 
 template <int P, int TM, int TN>
@@ -238,6 +271,10 @@ __device__ __forceinline__ void gemm_tile_accumulate(const int8_t* __restrict__ 
     slot = slot + 1 == NS ? 0 : slot + 1;
     read_frags<P, TM, TN, NS>(Fn, lds + slot * T::STAGE, wm, wn, lrow, lk);
     step_mfmas<P, TM, TN, PAIR>(Fc, acc);
+    constexpr int NR = P * (TM + TN);
+    constexpr int NM = (PAIR == TRIANGULAR ? P * (P + 1) / 2 : P) * TM * TN;
+    sched_step<NR, NM>();
+    __builtin_amdgcn_sched_barrier(0);  // nothing of this step moves past the next barrier
   };
   const int64_t total = nsteps + lead;  // even, >= 2
   int64_t v = 0;

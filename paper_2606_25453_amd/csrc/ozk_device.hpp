@@ -30,10 +30,10 @@ __device__ __forceinline__ int expo_of(double x) {
   const uint64_t b = (uint64_t)__double_as_longlong(x);
   const int ef = (int)((b >> 52) & 0x7ff);
   const uint64_t man = b & 0xfffffffffffffull;
-  if (ef == 0x7ff) return OZK_EXP_NONFINITE;
-  if (ef != 0) return ef - 1022;
-  if (man == 0) return OZK_EXP_ZERO;
-  return (64 - __clzll(man)) - 1074;  // subnormal: man 2^-1074
+  // branch-free selects, so that unrolled loads are not serialised behind branches
+  const int sub = man == 0 ? OZK_EXP_ZERO : (64 - __clzll(man)) - 1074;  // subnormal: man 2^-1074
+  const int e = ef == 0 ? sub : ef - 1022;
+  return ef == 0x7ff ? OZK_EXP_NONFINITE : e;
 }
 
 // |x| = m 2^q with m an integer below 2^53 (signed result in m); x finite.
@@ -50,27 +50,38 @@ __device__ __forceinline__ void split_fp64(double x, int64_t& m, int& q) {
   m = (b >> 63) ? -(int64_t)man : (int64_t)man;
 }
 
-// X = floor(x 2^sh + 1/2) exactly for a finite x whose value times 2^sh is
-// below 2^62 in magnitude.
-__device__ __forceinline__ int64_t round_half_up_scaled(double x, int sh_extra) {
-  int64_t m;
-  int q;
-  split_fp64(x, m, q);
-  const int sh = q + sh_extra;
-  if (m == 0) return 0;
-  if (sh >= 0) return (int64_t)((uint64_t)m << sh);
-  if (sh <= -62) return 0;  // |m 2^sh| < 2^-9
-  return (m + ((int64_t)1 << (-sh - 1))) >> (-sh);  // arithmetic shift = floor
+// X = floor(x 2^sh + 1/2) as an int64, exactly, for a finite x whose value
+// times 2^sh is below 2^62 in magnitude; branch-free in FP64.  y = x 2^sh is
+// exact unless it underflows, and then |y| < 2^-1022 gives X = 0 either way.
+// f = floor(y) is exact, y - f is exact or (y in (-1/2, 0) with f = -1)
+// rounds within [1/2, 1], so the test y - f >= 1/2 is decided correctly and
+// X = f + [y - f >= 1/2] is an exact double (53 significant bits at most).
+// It is split as hi 2^32 + lo with lo in [0, 2^32), both exact.
+__device__ __forceinline__ int64_t round_half_up_scaled(double x, int sh) {
+  const double y = ldexp(x, sh);
+  const double f = floor(y);
+  const double X = f + (y - f >= 0.5 ? 1.0 : 0.0);
+  const double hi = floor(X * 0x1p-32);
+  const double lo = __fma_rn(-hi, 0x1p32, X);
+  return (int64_t)(((uint64_t)(uint32_t)(int32_t)hi << 32) | (uint64_t)(uint32_t)lo);
 }
 
-// Round-to-nearest-even of Z 2^E as one rounding (gradual underflow and
-// overflow included).
-__device__ __forceinline__ double round_scaled(i128 Z, int E) {
-  if (Z == 0) return 0.0;
-  const bool neg = Z < 0;
-  const u128 mag = neg ? (u128)0 - (u128)Z : (u128)Z;
+// Round-to-nearest-even of +-mag 2^E as one rounding (gradual underflow and
+// overflow included); round_scaled takes a signed Z.
+__device__ __forceinline__ double round_mag(u128 mag, bool neg, int E) {
+  if (mag == 0) return 0.0;
   const uint64_t hi = (uint64_t)(mag >> 64), lo = (uint64_t)mag;
   const int n = hi ? 128 - __clzll(hi) : 64 - __clzll(lo);
+  if (n + E >= -1021) {
+    // Normal (or overflowing) result: the top 64 bits of mag with the bits
+    // below folded into the lowest one (sticky; the 53-bit rounding never
+    // keeps it), one RN-even conversion to double, then an exact scaling.
+    const int sh = n > 64 ? n - 64 : 0;
+    const uint64_t w = sh ? (uint64_t)(mag >> sh) | (uint64_t)((lo << (64 - sh)) != 0) : lo;
+    const double r = ldexp((double)w, E + sh);
+    return neg ? -r : r;
+  }
+  // Subnormal result: round at the fixed position 2^-1074 directly.
   int drop = n - 53;
   if (-1074 - E > drop) drop = -1074 - E;
   uint64_t q;
@@ -90,6 +101,11 @@ __device__ __forceinline__ double round_scaled(i128 Z, int E) {
   const long long Eq = (long long)E + drop;
   const double r = (Eq > 2100) ? __builtin_inf() : ldexp((double)q, (int)Eq);
   return neg ? -r : r;
+}
+
+__device__ __forceinline__ double round_scaled(i128 Z, int E) {
+  const bool neg = Z < 0;
+  return round_mag(neg ? (u128)0 - (u128)Z : (u128)Z, neg, E);
 }
 
 // BLAS-style update: alpha*h when beta == 0 (c not read), else

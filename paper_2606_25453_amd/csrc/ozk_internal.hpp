@@ -53,16 +53,28 @@ struct BatchProb {
   int64_t off_sig, off_tau, off_a, off_b, off_res;
 };
 
-// Device view of a batch plan: the problem table and per-step prefix sums of
-// work units (count + 1 entries each, starting at 0).
+// Work units of one batched step: the prefix sums of the units of every
+// problem (count + 1 entries, from 0) and a coarse index, hint[b] = the
+// problem holding unit min(64 b, total - 1) (total / 64 + 2 entries), so that
+// a unit's problem is a binary search over the few problems between two
+// hints instead of over the whole table.
+constexpr int OZK_BATCH_HINT_SHIFT = 6;
+
+struct BatchUnits {
+  const int64_t* start;
+  const int32_t* hint;
+};
+
+// Device view of a batch plan: the problem table and the work units of each
+// step.
 struct BatchDev {
   const BatchProb* prob;
-  const int64_t* rows_start;   // row blocks of 4 rows (pre-pass of A)
-  const int64_t* cols_start;   // column blocks of 32 (column scales of B)
-  const int64_t* split_start;  // (256-column block, K chunk) pairs (residues of B)
-  const int64_t* item_start;   // GEMM items in the order below
-  const int32_t* order;        // GEMM item order -> problem index
-  const int64_t* crt_start;    // output blocks of 256 (CRT)
+  BatchUnits rows;   // row blocks of 4 rows (pre-pass of A)
+  BatchUnits cols;   // column blocks of 32 (column scales of B)
+  BatchUnits split;  // (64-column block, K chunk) pairs (residues of B)
+  BatchUnits items;  // GEMM items in the order below
+  BatchUnits crt;    // output blocks of 256 (CRT)
+  const int32_t* order;  // GEMM item order -> problem index
   int count;
 };
 
@@ -74,6 +86,7 @@ hipError_t s2_batched(int s, bool cplx, const BatchDev& bd, const BatchTotals& t
                       hipStream_t st);
 int s2_batch_gemm_blocks_per_cu(bool cplx);
 int64_t s2_tile_count(bool cplx, int64_t M, int64_t N);
+int64_t s2_split_cols_blocks(int64_t cols_packed, int64_t Kp);  // workgroups of the column residue pass
 
 void s2_targets(int s, int& ta, int& tb);
 

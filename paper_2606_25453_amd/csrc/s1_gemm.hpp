@@ -75,11 +75,13 @@ __device__ __forceinline__ void s1_gemm_tile(const S1KArgs& g, int64_t tile, int
       zp[1] = (int64_t)(Z >> 64);
       return;
     }
+    // Zero and non-finite lines have all-zero digits, so Z = 0 there: one
+    // rounding for every element, then the NaN of a non-finite line.
     const int er = g.e_row[row], fc = g.f_col[col];
-    double h;
-    if (er == OZK_EXP_NONFINITE || fc == OZK_EXP_NONFINITE) h = __builtin_nan("");
-    else if (er == OZK_EXP_ZERO || fc == OZK_EXP_ZERO) h = 0.0;
-    else h = round_scaled(Z, er + fc - 12 - 8 * (P - 1));
+    const bool bad = er == OZK_EXP_NONFINITE || fc == OZK_EXP_NONFINITE;
+    const bool live = !bad && er != OZK_EXP_ZERO && fc != OZK_EXP_ZERO;
+    double h = round_scaled(Z, live ? er + fc - 12 - 8 * (P - 1) : 0);
+    h = bad ? __builtin_nan("") : h;
     double* cp = g.C + row * g.ldc + col;
     *cp = axpby(g.alpha, h, g.beta, cp);
   });

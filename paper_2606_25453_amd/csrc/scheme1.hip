@@ -17,46 +17,77 @@ namespace ozk {
 
 // ---------------------------------------------------------------- pre-pass
 
-// Balanced base-256 digits of X = floor(x 2^(8p-2-e) + 1/2): digit t is
-// written to byte t of `out` (p bytes).
+// Balanced base-256 digits of X = floor(x 2^(8p-2-e) + 1/2) for 4
+// consecutive entries of a line with exponent e (finite, non-zero line),
+// packed per slice: word t holds digit t of entry j in byte j.  With
+// u = X + 128 (256^(p-2) + ... + 256 + 1), byte p-1-t of u is d_t + 128 for
+// t >= 1 (the biased low digits never borrow) and byte p-1, read as a signed
+// byte, is d_0 (|X| <= 2^(8p-2) keeps it in [-64, 64]).  Entries equal to
+// zero give zero words.
 template <int P>
-__device__ __forceinline__ void s1_digits(double x, int e, int8_t (&out)[P]) {
-  int64_t X = 0;
-  if (e != OZK_EXP_ZERO && e != OZK_EXP_NONFINITE) X = round_half_up_scaled(x, 8 * P - 2 - e);
+__device__ __forceinline__ void s1_words(const double (&x)[4], int e, uint32_t (&word)[P]) {
+  constexpr uint64_t BIAS = P > 1 ? 0x8080808080808080ull >> (8 * (9 - P)) : 0;
+  uint64_t u[4];
 #pragma unroll
-  for (int t = P - 1; t >= 1; --t) {
-    const int64_t d = ((X + 128) & 255) - 128;
-    out[t] = (int8_t)d;
-    X = (X - d) >> 8;  // exact
+  for (int j = 0; j < 4; ++j) u[j] = (uint64_t)round_half_up_scaled(x[j], 8 * P - 2 - e) + BIAS;
+#pragma unroll
+  for (int t = 0; t < P; ++t) {
+    const int b = 8 * (P - 1 - t);
+    uint32_t w = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) w |= (uint32_t)((u[j] >> b) & 255) << (8 * j);
+    word[t] = t ? w ^ 0x80808080u : w;
   }
-  out[0] = (int8_t)X;
 }
 
-// Slices of packed row r whose exponent is e: each lane turns 4 consecutive
-// k into p digits and stores 4 bytes per slice at packed[k/32][t][r][k%32].
-// Rows past `rows` and k past K are zero.
+__device__ __forceinline__ bool live_exponent(int e) { return e != OZK_EXP_ZERO && e != OZK_EXP_NONFINITE; }
+
+// Slices of packed row r whose exponent is e: each lane turns 8 consecutive
+// k into p digits and stores 8 bytes per slice at packed[k/32][t][r][k%32].
+// Rows past `rows`, zero or non-finite rows and k past K are zero.  The
+// branches are per row (wave-uniform) and per 4-k group (only the group that
+// straddles K takes the tail path), so the loads of the main path carry no
+// condition and are issued back to back.
+// 8 consecutive k of packed row r from k0 (a multiple of 8): two 4-entry
+// word groups, stored as one 8-byte piece per slice.
+template <int P>
+__device__ __forceinline__ void s1_store_row_words(int8_t* __restrict__ packed, int64_t rows_packed, int64_t r,
+                                                   int64_t k0, const uint32_t (&lo)[P], const uint32_t (&hi)[P]) {
+  const int64_t c = k0 / OZK_K_CHUNK, kk = k0 % OZK_K_CHUNK;
+#pragma unroll
+  for (int t = 0; t < P; ++t)
+    *reinterpret_cast<uint2*>(packed + ((c * P + t) * rows_packed + r) * OZK_K_CHUNK + kk) = make_uint2(lo[t], hi[t]);
+}
+
 template <int P>
 __device__ __forceinline__ void s1_slice_row(const double* __restrict__ xr, int64_t r, int64_t rows, int64_t K,
                                              int64_t Kp, int64_t rows_packed, int e, int8_t* __restrict__ packed) {
   const int lane = threadIdx.x & 63;
-#pragma unroll 4
-  for (int64_t k0 = (int64_t)lane * 4; k0 < Kp; k0 += 256) {
-    uint32_t word[P];
-#pragma unroll
-    for (int t = 0; t < P; ++t) word[t] = 0;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int64_t k = k0 + j;
-      const double v = (r < rows && k < K) ? xr[k] : 0.0;
-      int8_t d[P];
-      s1_digits<P>(v, e, d);
-#pragma unroll
-      for (int t = 0; t < P; ++t) word[t] |= (uint32_t)(uint8_t)d[t] << (8 * j);
+  int64_t k0 = (int64_t)lane * 8;
+  if (r < rows && live_exponent(e)) {
+    for (; k0 + 8 <= K; k0 += 512) {  // main path: 8 loads with no condition between them
+      const double a[4] = {xr[k0], xr[k0 + 1], xr[k0 + 2], xr[k0 + 3]};
+      const double b[4] = {xr[k0 + 4], xr[k0 + 5], xr[k0 + 6], xr[k0 + 7]};
+      uint32_t lo[P], hi[P];
+      s1_words<P>(a, e, lo);
+      s1_words<P>(b, e, hi);
+      s1_store_row_words<P>(packed, rows_packed, r, k0, lo, hi);
     }
-    const int64_t c = k0 / OZK_K_CHUNK, kk = k0 % OZK_K_CHUNK;
+    for (; k0 < Kp; k0 += 512) {  // the group straddling K, then the zero padding
+      double a[4], b[4];
 #pragma unroll
-    for (int t = 0; t < P; ++t)
-      *reinterpret_cast<uint32_t*>(packed + ((c * P + t) * rows_packed + r) * OZK_K_CHUNK + kk) = word[t];
+      for (int j = 0; j < 4; ++j) {
+        a[j] = k0 + j < K ? xr[k0 + j] : 0.0;
+        b[j] = k0 + 4 + j < K ? xr[k0 + 4 + j] : 0.0;
+      }
+      uint32_t lo[P], hi[P];
+      s1_words<P>(a, e, lo);
+      s1_words<P>(b, e, hi);
+      s1_store_row_words<P>(packed, rows_packed, r, k0, lo, hi);
+    }
+  } else {
+    const uint32_t zero[P] = {};
+    for (; k0 < Kp; k0 += 512) s1_store_row_words<P>(packed, rows_packed, r, k0, zero, zero);
   }
 }
 
@@ -70,7 +101,7 @@ __global__ __launch_bounds__(256) void k_s1_split_rows(const double* __restrict_
   const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (r >= rows_packed) return;
   int e = OZK_EXP_ZERO;
-  const double* xr = X + r * ldx;
+  const double* xr = X + r * ldx;  // read only for r < rows
   if (r < rows) {
 #pragma unroll 8
     for (int64_t k = lane; k < K; k += 64) {
@@ -93,7 +124,7 @@ __global__ __launch_bounds__(256) void k_s1_slice_rows_auto(const double* __rest
   const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (r >= rows_packed || *p_dev < 1) return;  // p = 0: Scheme II was chosen
   const int e = r < rows ? e_in[r] : OZK_EXP_ZERO;
-  const double* xr = X + r * ldx;
+  const double* xr = X + r * ldx;  // read only for r < rows
   switch (*p_dev) {
     case 1: s1_slice_row<1>(xr, r, rows, K, Kp, rows_packed, e, packed); break;
     case 2: s1_slice_row<2>(xr, r, rows, K, Kp, rows_packed, e, packed); break;
@@ -129,31 +160,47 @@ __global__ __launch_bounds__(256) void k_s1_exp_cols(const double* __restrict__ 
 
 // Column operand slices: thread (j, c) turns the 32 k of chunk c of column j
 // into p x 32 digits and stores 32 bytes per slice at packed[c][t][j][:]
-// (consecutive threads write consecutive 32-byte lines).
+// (consecutive threads write consecutive 32-byte lines).  Columns past
+// `cols`, zero or non-finite columns and k past K are zero; only the chunk
+// that straddles K takes the guarded path.
 template <int P>
 __device__ __forceinline__ void s1_slice_col(const double* __restrict__ X, int64_t ldx, int64_t K, int64_t cols,
                                              int64_t cols_packed, const int32_t* __restrict__ f,
                                              int8_t* __restrict__ packed, int64_t j, int64_t c) {
   const int e = j < cols ? f[j] : OZK_EXP_ZERO;
-  uint32_t word[P][8];
+  const int64_t kb = c * OZK_K_CHUNK;
+  uint32_t word[8][P];
+  if (live_exponent(e) && kb + OZK_K_CHUNK <= K) {
+    const double* x = X + kb * ldx + j;
+    double v[8][4];  // all 32 loads first
 #pragma unroll
-  for (int t = 0; t < P; ++t)
+    for (int g = 0; g < 8; ++g)
 #pragma unroll
-    for (int w = 0; w < 8; ++w) word[t][w] = 0;
+      for (int i = 0; i < 4; ++i) v[g][i] = x[(4 * g + i) * ldx];
 #pragma unroll
-  for (int kk = 0; kk < OZK_K_CHUNK; ++kk) {
-    const int64_t k = c * OZK_K_CHUNK + kk;
-    const double v = (j < cols && k < K) ? X[k * ldx + j] : 0.0;
-    int8_t d[P];
-    s1_digits<P>(v, e, d);
+    for (int g = 0; g < 8; ++g) s1_words<P>(v[g], e, word[g]);
+  } else if (live_exponent(e)) {
 #pragma unroll
-    for (int t = 0; t < P; ++t) word[t][kk / 4] |= (uint32_t)(uint8_t)d[t] << (8 * (kk % 4));
+    for (int g = 0; g < 8; ++g) {
+      double v[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int64_t k = kb + 4 * g + i;
+        v[i] = k < K ? X[k * ldx + j] : 0.0;
+      }
+      s1_words<P>(v, e, word[g]);
+    }
+  } else {
+#pragma unroll
+    for (int g = 0; g < 8; ++g)
+#pragma unroll
+      for (int t = 0; t < P; ++t) word[g][t] = 0;
   }
 #pragma unroll
   for (int t = 0; t < P; ++t) {
     uint4* q = reinterpret_cast<uint4*>(packed + ((c * P + t) * cols_packed + j) * OZK_K_CHUNK);
-    q[0] = make_uint4(word[t][0], word[t][1], word[t][2], word[t][3]);
-    q[1] = make_uint4(word[t][4], word[t][5], word[t][6], word[t][7]);
+    q[0] = make_uint4(word[0][t], word[1][t], word[2][t], word[3][t]);
+    q[1] = make_uint4(word[4][t], word[5][t], word[6][t], word[7][t]);
   }
 }
 

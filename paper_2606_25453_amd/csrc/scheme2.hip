@@ -20,8 +20,10 @@ namespace ozk {
 
 struct S2Tables {
   int m[OZK_MAX_S];
-  double inv_m[OZK_MAX_S];
-  uint8_t pow2[OZK_MAX_S][128];  // 2^k mod m_l
+  double md[OZK_MAX_S];     // m_l as a double
+  double inv_m[OZK_MAX_S];  // 1 / m_l rounded
+  double p26[OZK_MAX_S];    // 2^26 mod m_l
+  double p52[OZK_MAX_S];    // 2^52 mod m_l
 };
 
 constexpr int gcd_c(int a, int b) { return b == 0 ? a : gcd_c(b, a % b); }
@@ -37,12 +39,11 @@ constexpr S2Tables make_s2_tables() {
     if (ok) t.m[n++] = c;
   }
   for (int i = 0; i < OZK_MAX_S; ++i) {
+    t.md[i] = t.m[i];
     t.inv_m[i] = 1.0 / t.m[i];
-    int r = 1 % t.m[i];
-    for (int k = 0; k < 128; ++k) {
-      t.pow2[i][k] = (uint8_t)r;
-      r = (2 * r) % t.m[i];
-    }
+    const int64_t r26 = ((int64_t)1 << 26) % t.m[i];
+    t.p26[i] = (double)r26;
+    t.p52[i] = (double)((r26 * r26) % t.m[i]);
   }
   return t;
 }
@@ -52,59 +53,51 @@ __constant__ S2Tables c_s2 = kS2;
 
 int s2_modulus(int l) { return kS2.m[l]; }
 
-// x mod m in [0, m) for |x| < 2^53 given as an exact double.
-__device__ __forceinline__ int mod_small(double x, int m, double inv_m) {
-  const double q = floor(x * inv_m);
-  int r = (int)__fma_rn(-q, (double)m, x);
-  if (r < 0) r += m;
-  if (r >= m) r -= m;
+// smod(t, m_l) for an integer-valued double |t| < 2^40: with
+// q = floor(t / m + 1/2) the remainder t - q m lies in [-floor(m/2),
+// ceil(m/2) - 1].  For odd m, t / m is at least 1/(2m) >= 2^-9 away from a
+// half-integer while the computed t / m + 1/2 is within 2^-19 of its exact
+// value, so q is the nearest integer; for m = 256 everything is exact.  The
+// final fma is exact as well.
+__device__ __forceinline__ int smod_exact(double t, int l) {
+  const double q = floor(__fma_rn(t, c_s2.inv_m[l], 0.5));
+  return (int)__fma_rn(-q, c_s2.md[l], t);
+}
+
+// smod of an INT32 accumulator.
+__device__ __forceinline__ int smod_i32(int x, int l) { return smod_exact((double)x, l); }
+
+// smod(a + b, m_l) for a, b already symmetric residues of m_l.
+__device__ __forceinline__ int smod_sum(int a, int b, int l) {
+  const int m = c_s2.m[l];
+  int r = a + b;
+  r -= r > (m - 1) / 2 ? m : 0;
+  r += r < -(m / 2) ? m : 0;
   return r;
 }
 
-// smod: the representative of r (0 <= r < m) in [-floor(m/2), ceil(m/2)-1].
-__device__ __forceinline__ int sym(int r, int m) { return r >= (m + 1) / 2 ? r - m : r; }
-
-// smod of an INT32 accumulator.
-__device__ __forceinline__ int smod_i32(int x, int l) {
-  const int m = c_s2.m[l];
-  return sym(mod_small((double)x, m, c_s2.inv_m[l]), m);
-}
-
-// a' = trunc(a 2^sigma) as sign * u * 2^k with u < 2^53 an integer (as an
-// exact double) and k >= 0.
-struct ScaledInt {
-  double u;
-  int k;
-  bool neg;
+// a' = trunc(a 2^sigma) as three 26-bit limbs, exact doubles carrying the
+// sign of a: a' = x2 2^52 + x1 2^26 + x0.  The row (column) norm bound gives
+// |a'| < 2^T <= 2^77, so three limbs hold it; t = x2 (2^52 mod m) +
+// x1 (2^26 mod m) + x0 is then an exact double (|t| < 2^35) congruent to a'.
+// Branch-free in FP64: a 2^sigma is exact unless it underflows (then its
+// truncation is 0 either way), truncation is exact, and each limb split is an
+// exact scaling, truncation and fma (the remainders keep the sign of a').
+struct Limbs3 {
+  double x0, x1, x2;
 };
 
-__device__ __forceinline__ ScaledInt scaled_int(double a, int sigma) {
-  int64_t m;
-  int q;
-  split_fp64(a, m, q);
-  ScaledInt s;
-  s.neg = m < 0;
-  uint64_t am = s.neg ? (uint64_t)(-m) : (uint64_t)m;
-  const int sh = q + sigma;
-  if (am == 0) {
-    s.u = 0.0;
-    s.k = 0;
-  } else if (sh >= 0) {
-    s.u = (double)am;
-    s.k = sh;
-  } else {
-    s.u = (-sh >= 64) ? 0.0 : (double)(am >> (-sh));
-    s.k = 0;
-  }
-  return s;
+__device__ __forceinline__ Limbs3 scaled_limbs(double a, int sigma) {
+  const double y = trunc(ldexp(a, sigma));
+  const double x2 = trunc(y * 0x1p-52);
+  const double r1 = __fma_rn(-x2, 0x1p52, y);
+  const double x1 = trunc(r1 * 0x1p-26);
+  const double x0 = __fma_rn(-x1, 0x1p26, r1);
+  return Limbs3{x0, x1, x2};
 }
 
-__device__ __forceinline__ int residue_of(const ScaledInt& v, int l) {
-  const int m = c_s2.m[l];
-  int r = mod_small(v.u, m, c_s2.inv_m[l]);
-  if (v.k > 0) r = mod_small((double)(r * (int)c_s2.pow2[l][v.k < 128 ? v.k : 127]), m, c_s2.inv_m[l]);
-  if (v.neg && r) r = m - r;
-  return sym(r, m);
+__device__ __forceinline__ int residue_of(const Limbs3& v, int l) {
+  return smod_exact(__fma_rn(v.x2, c_s2.p52[l], __fma_rn(v.x1, c_s2.p26[l], v.x0)), l);
 }
 
 // Per-entry exponent for the scale bound: |entry| < 2^ex.  Complex entries
@@ -113,9 +106,8 @@ template <bool CPLX>
 __device__ __forceinline__ int entry_expo(const double* x) {
   if (!CPLX) return expo_of(x[0]);
   const int a = expo_of(x[0]), b = expo_of(x[1]);
-  if (a == OZK_EXP_NONFINITE || b == OZK_EXP_NONFINITE) return OZK_EXP_NONFINITE;
-  const int e = a > b ? a : b;
-  return e == OZK_EXP_ZERO ? OZK_EXP_ZERO : e + 1;
+  const int e = a > b ? a : b;  // the non-finite sentinel is the largest value
+  return (e == OZK_EXP_NONFINITE || e == OZK_EXP_ZERO) ? e : e + 1;
 }
 
 // ceil(2^40 4^(ex - emax)) for an entry with exponent ex <= emax; 0 for zero.
@@ -146,20 +138,54 @@ struct S2Args {
   int T;  // T_A for rows, T_B for columns
 };
 
+// Residues of 4 consecutive entries of a line with scale sigma for every
+// modulus, stored as one dword per plane at dst (plane stride `plane`; the
+// complex planes re, im, sum of one chunk are `slab` bytes apart).
+template <bool CPLX>
+__device__ __forceinline__ void s2_store_residues(const double (&re)[4], const double (&im)[4], int sigma, int s,
+                                                  int8_t* __restrict__ dst, int64_t plane, int64_t slab) {
+  Limbs3 vr[4], vi[CPLX ? 4 : 1];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    vr[j] = scaled_limbs(re[j], sigma);
+    if (CPLX) vi[CPLX ? j : 0] = scaled_limbs(im[j], sigma);
+  }
+  for (int l = 0; l < s; ++l, dst += plane) {
+    uint32_t w0 = 0, w1 = 0, w2 = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int a = residue_of(vr[j], l);
+      w0 |= (uint32_t)(uint8_t)a << (8 * j);
+      if (CPLX) {
+        const int b = residue_of(vi[CPLX ? j : 0], l);
+        w1 |= (uint32_t)(uint8_t)b << (8 * j);
+        w2 |= (uint32_t)(uint8_t)smod_sum(a, b, l) << (8 * j);
+      }
+    }
+    *reinterpret_cast<uint32_t*>(dst) = w0;
+    if (CPLX) {
+      *reinterpret_cast<uint32_t*>(dst + slab) = w1;
+      *reinterpret_cast<uint32_t*>(dst + 2 * slab) = w2;
+    }
+  }
+}
+
 // One wave per packed row: exponent max, norm-bound sum, then residues of 4
 // consecutive k per lane (one dword per plane).  Every modulus plane is a
 // packed operand of the shared GEMM core: real packed[l][c][r][32], complex
-// packed[l][c][q][r][32] (q = re, im, sum).
+// packed[l][c][q][r][32] (q = re, im, sum).  Padding rows, non-finite rows
+// and k past K get zero residues; the main loop has no condition between
+// its loads (only the 4-k group straddling K takes the guarded path).
 template <bool CPLX>
 __device__ __forceinline__ void s2_split_rows_block(const double* __restrict__ X, int64_t ldx, int64_t rows,
                                                     int64_t K, int64_t Kp, int64_t rows_packed, S2Args sa,
                                                     int32_t* __restrict__ sigma_out, int8_t* __restrict__ packed,
                                                     int64_t blk) {
-  constexpr int W = CPLX ? 2 : 1;
+  constexpr int W = CPLX ? 2 : 1, NP = CPLX ? 3 : 1;
   const int lane = threadIdx.x & 63;
   const int64_t r = blk * 4 + (threadIdx.x >> 6);
   if (r >= rows_packed) return;
-  const double* xr = X + r * ldx * W;
+  const double* xr = X + r * ldx * W;  // read only for r < rows
   int sigma = 0;
   if (r < rows) {
     int e = OZK_EXP_ZERO;
@@ -177,41 +203,35 @@ __device__ __forceinline__ void s2_split_rows_block(const double* __restrict__ X
     sigma = scale_from(e, S, sa.T);
     if (lane == 0) sigma_out[r] = sigma;
   }
-  const bool live = r < rows && sigma != OZK_EXP_NONFINITE;
-  const int64_t plane = rows_packed * Kp * (CPLX ? 3 : 1);
-#pragma unroll 4
-  for (int64_t k0 = (int64_t)lane * 4; k0 < Kp; k0 += 256) {
-    ScaledInt vr[4], vi[4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int64_t k = k0 + j;
-      const bool in = live && k < K;
-      vr[j] = scaled_int(in ? xr[k * W] : 0.0, sigma);
-      if (CPLX) vi[j] = scaled_int(in ? xr[k * W + 1] : 0.0, sigma);
-    }
-    for (int l = 0; l < sa.s; ++l) {
-      const int m = c_s2.m[l];
-      uint32_t w0 = 0, w1 = 0, w2 = 0;
+  const int64_t plane = rows_packed * Kp * NP, slab = rows_packed * OZK_K_CHUNK;
+  auto dst_of = [&](int64_t k0) { return packed + (k0 / OZK_K_CHUNK) * NP * slab + r * OZK_K_CHUNK + k0 % OZK_K_CHUNK; };
+  int64_t k0 = (int64_t)lane * 4;
+  if (r < rows && sigma != OZK_EXP_NONFINITE) {
+    for (; k0 + 4 <= K; k0 += 256) {
+      double re[4], im[4];
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const int a = residue_of(vr[j], l);
-        w0 |= (uint32_t)(uint8_t)a << (8 * j);
-        if (CPLX) {
-          const int b = residue_of(vi[j], l);
-          w1 |= (uint32_t)(uint8_t)b << (8 * j);
-          w2 |= (uint32_t)(uint8_t)sym(((a + b) % m + m) % m, m) << (8 * j);
-        }
+        re[j] = xr[(k0 + j) * W];
+        im[j] = CPLX ? xr[(k0 + j) * W + 1] : 0.0;
       }
-      int8_t* base = packed + l * plane;
-      const int64_t c = k0 / OZK_K_CHUNK, kk = k0 % OZK_K_CHUNK;
-      constexpr int NP = CPLX ? 3 : 1;
-      const int64_t slab = rows_packed * OZK_K_CHUNK;
-      int8_t* dst = base + c * NP * slab + r * OZK_K_CHUNK + kk;
-      *reinterpret_cast<uint32_t*>(dst) = w0;
-      if (CPLX) {
-        *reinterpret_cast<uint32_t*>(dst + slab) = w1;
-        *reinterpret_cast<uint32_t*>(dst + 2 * slab) = w2;
+      s2_store_residues<CPLX>(re, im, sigma, sa.s, dst_of(k0), plane, slab);
+    }
+    for (; k0 < Kp; k0 += 256) {
+      double re[4], im[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const bool in = k0 + j < K;
+        re[j] = in ? xr[(k0 + j) * W] : 0.0;
+        im[j] = CPLX && in ? xr[(k0 + j) * W + 1] : 0.0;
       }
+      s2_store_residues<CPLX>(re, im, sigma, sa.s, dst_of(k0), plane, slab);
+    }
+  } else {
+    for (; k0 < Kp; k0 += 256) {
+      int8_t* dst = dst_of(k0);
+      for (int l = 0; l < sa.s; ++l, dst += plane)
+#pragma unroll
+        for (int q = 0; q < NP; ++q) *reinterpret_cast<uint32_t*>(dst + q * slab) = 0u;
     }
   }
 }
@@ -269,35 +289,55 @@ __global__ __launch_bounds__(256) void k_s2_col_scales(const double* __restrict_
   s2_col_scales_block<CPLX>(X, ldx, K, cols, T, tau, blockIdx.x);
 }
 
-// Thread (j, hc): the 16 k of half-chunk hc (chunk hc / 2, half hc % 2) of
-// column j, residues for every modulus, written as one 16-byte piece per
-// plane (half a 32-byte packed row; 16 k keep the per-thread state small
-// enough for several waves per SIMD).
-constexpr int S2_COL_K = OZK_K_CHUNK / 2;
+// A block covers 64 columns of one K chunk.  Thread (column j, quarter q)
+// takes the 8 k of quarter q of the chunk in column j and writes one 8-byte
+// piece per plane: the four quarters of 16 consecutive columns are 512
+// contiguous bytes of a plane (16 packed rows of 32 bytes), and every load
+// reads 16 consecutive columns in 4 rows of B.
+constexpr int S2_COL_BLOCK = 64;
+constexpr int S2_COL_K = OZK_K_CHUNK / 4;
+
+int64_t s2_split_cols_blocks(int64_t cols_packed, int64_t Kp) {
+  return (cols_packed / S2_COL_BLOCK) * (Kp / OZK_K_CHUNK);
+}
 
 template <bool CPLX>
 __device__ __forceinline__ void s2_split_cols_block(const double* __restrict__ X, int64_t ldx, int64_t K,
                                                     int64_t cols, int64_t Kp, int64_t cols_packed, int s,
                                                     const int32_t* __restrict__ tau, int8_t* __restrict__ packed,
-                                                    int64_t jb, int64_t hc) {
-  constexpr int W = CPLX ? 2 : 1;
-  const int64_t j = jb * 256 + threadIdx.x;
-  if (j >= cols_packed) return;
-  const int64_t c = hc >> 1, k0 = hc * S2_COL_K;
+                                                    int64_t jb, int64_t c) {
+  constexpr int W = CPLX ? 2 : 1, NP = CPLX ? 3 : 1;
+  const int lane = threadIdx.x & 63, qk = lane & 3;
+  const int64_t j = jb * S2_COL_BLOCK + (threadIdx.x >> 6) * 16 + (lane >> 2);
+  const int64_t k0 = c * OZK_K_CHUNK + qk * S2_COL_K;
   const int t = j < cols ? tau[j] : 0;
   const bool live = j < cols && t != OZK_EXP_NONFINITE;
-  ScaledInt vr[S2_COL_K], vi[CPLX ? S2_COL_K : 1];
+  double re[S2_COL_K], im[S2_COL_K];
+  if (live && k0 + S2_COL_K <= K) {  // all loads first, no condition between them
+#pragma unroll
+    for (int kk = 0; kk < S2_COL_K; ++kk) {
+      const double* src = X + ((k0 + kk) * ldx + j) * W;
+      re[kk] = src[0];
+      im[kk] = CPLX ? src[1] : 0.0;
+    }
+  } else {
+#pragma unroll
+    for (int kk = 0; kk < S2_COL_K; ++kk) {
+      const bool in = live && k0 + kk < K;
+      re[kk] = in ? X[((k0 + kk) * ldx + j) * W] : 0.0;
+      im[kk] = CPLX && in ? X[((k0 + kk) * ldx + j) * W + 1] : 0.0;
+    }
+  }
+  Limbs3 vr[S2_COL_K], vi[CPLX ? S2_COL_K : 1];
 #pragma unroll
   for (int kk = 0; kk < S2_COL_K; ++kk) {
-    const int64_t k = k0 + kk;
-    const bool in = live && k < K;
-    vr[kk] = scaled_int(in ? X[(k * ldx + j) * W] : 0.0, t);
-    if (CPLX) vi[CPLX ? kk : 0] = scaled_int(in ? X[(k * ldx + j) * W + 1] : 0.0, t);
+    vr[kk] = scaled_limbs(re[kk], t);
+    if (CPLX) vi[CPLX ? kk : 0] = scaled_limbs(im[kk], t);
   }
-  const int64_t plane = cols_packed * Kp * (CPLX ? 3 : 1);
-  for (int l = 0; l < s; ++l) {
-    const int m = c_s2.m[l];
-    uint32_t w0[4] = {0, 0, 0, 0}, w1[4] = {0, 0, 0, 0}, w2[4] = {0, 0, 0, 0};
+  const int64_t plane = cols_packed * Kp * NP, slab = cols_packed * OZK_K_CHUNK;
+  int8_t* dst = packed + c * NP * slab + j * OZK_K_CHUNK + qk * S2_COL_K;
+  for (int l = 0; l < s; ++l, dst += plane) {
+    uint32_t w0[2] = {0, 0}, w1[2] = {0, 0}, w2[2] = {0, 0};
 #pragma unroll
     for (int kk = 0; kk < S2_COL_K; ++kk) {
       const int a = residue_of(vr[kk], l);
@@ -305,16 +345,13 @@ __device__ __forceinline__ void s2_split_cols_block(const double* __restrict__ X
       if (CPLX) {
         const int b = residue_of(vi[CPLX ? kk : 0], l);
         w1[kk / 4] |= (uint32_t)(uint8_t)b << (8 * (kk % 4));
-        w2[kk / 4] |= (uint32_t)(uint8_t)sym(((a + b) % m + m) % m, m) << (8 * (kk % 4));
+        w2[kk / 4] |= (uint32_t)(uint8_t)smod_sum(a, b, l) << (8 * (kk % 4));
       }
     }
-    constexpr int NP = CPLX ? 3 : 1;
-    const int64_t slab = cols_packed * OZK_K_CHUNK;
-    int8_t* dst = packed + l * plane + c * NP * slab + j * OZK_K_CHUNK + (hc & 1) * S2_COL_K;
-    *reinterpret_cast<uint4*>(dst) = make_uint4(w0[0], w0[1], w0[2], w0[3]);
+    *reinterpret_cast<uint2*>(dst) = make_uint2(w0[0], w0[1]);
     if (CPLX) {
-      *reinterpret_cast<uint4*>(dst + slab) = make_uint4(w1[0], w1[1], w1[2], w1[3]);
-      *reinterpret_cast<uint4*>(dst + 2 * slab) = make_uint4(w2[0], w2[1], w2[2], w2[3]);
+      *reinterpret_cast<uint2*>(dst + slab) = make_uint2(w1[0], w1[1]);
+      *reinterpret_cast<uint2*>(dst + 2 * slab) = make_uint2(w2[0], w2[1]);
     }
   }
 }
@@ -334,12 +371,20 @@ __global__ __launch_bounds__(256) void k_s2_split_cols(const double* __restrict_
 // reduction is exact because only the residue is kept.
 constexpr int64_t S2_RUN_STEPS = 4095;
 
-// Tiling of the per-modulus GEMM; variant V = 1 uses one LDS stage fewer.
+// Tiling of the per-modulus GEMM.  Variants: 0 the base tile (real 128 x 128,
+// 3M 128 x 64, 4 LDS stages), 1 the base tile with 3 stages, 2 the large tile
+// (real 256 x 128: 4 x 2 MFMA tiles per wave; 3M 128 x 128), 3 the large tile
+// with 3 stages.  The large tile reuses each operand fragment read from LDS
+// over more MFMAs; it holds one INT32-safe run only (no mid-run reduction,
+// which would push its accumulators out of the matrix registers), so the
+// launcher takes the base tile of the same stage count when K is longer.
 template <bool CPLX, int V = 0>
 struct S2Cfg {
   static constexpr int P = CPLX ? 3 : 1;
-  static constexpr int TM = 2, TN = CPLX ? 1 : 2;
-  static constexpr int NS = 4 - V;
+  static constexpr bool LARGE = V >= 2;
+  static constexpr int TM = LARGE && !CPLX ? 4 : 2;
+  static constexpr int TN = CPLX && !LARGE ? 1 : 2;
+  static constexpr int NS = 4 - (V & 1);
 };
 
 // One output tile of one modulus: the per-modulus products, then smod (3M:
@@ -358,6 +403,10 @@ __device__ __forceinline__ void s2_gemm_tile(const int8_t* __restrict__ Ap, cons
   const int64_t m0 = tm * T::BM, n0 = tn * T::BN;
   v16i acc[P][TM][TN];
   zero_acc<P, TM, TN>(acc);
+  if constexpr (Cfg::LARGE) {  // one INT32-safe run only (the launcher checks K)
+    gemm_tile_accumulate<P, TM, TN, NS, DIAGONAL>(Ap + l * plane_a, Bp + l * plane_b, rows_a, rows_b, m0, n0, 0,
+                                                  nsteps, lds, acc);
+  } else
   for (int64_t s0 = 0; s0 < nsteps || s0 == 0; s0 += S2_RUN_STEPS) {
     const int64_t n = nsteps - s0 < S2_RUN_STEPS ? nsteps - s0 : S2_RUN_STEPS;
     gemm_tile_accumulate<P, TM, TN, NS, DIAGONAL>(Ap + l * plane_a, Bp + l * plane_b, rows_a, rows_b, m0, n0, s0,
@@ -517,30 +566,25 @@ __device__ __forceinline__ void crt_combine(const CrtArgs& ca, const int8_t* res
   }
 }
 
-// RN-even of +-mag 2^E (one rounding, gradual underflow included).
+// RN-even of +-mag 2^E (one rounding, gradual underflow included).  A
+// magnitude of 2^128 or more is cut to the 128 bits from its leading one down,
+// with the bits below folded into the lowest of them (sticky): the rounding
+// keeps at most 53 of the 128, so its round bit is bit 74 or higher, the
+// sticky bit lies strictly below it and the result is the same.
 __device__ __forceinline__ double round_limbs(const uint32_t (&mag)[NL], bool neg, int E) {
-  int top = -1;
-#pragma unroll
-  for (int i = NL - 1; i >= 0; --i)
-    if (top < 0 && mag[i]) top = i;
-  if (top < 0) return 0.0;
-  const int n = 32 * top + (32 - __clz(mag[top]));
-  int drop = n - 53;
-  if (-1074 - E > drop) drop = -1074 - E;
-  auto bit = [&](int pos) -> uint32_t { return (pos < 0 || pos >= 32 * NL) ? 0u : (mag[pos >> 5] >> (pos & 31)) & 1u; };
-  uint64_t q = 0;
-  if (drop <= 0) {
-    for (int i = n - 1; i >= 0; --i) q = (q << 1) | bit(i);
-    drop = 0;
-  } else {
-    for (int i = n - 1; i >= drop; --i) q = (q << 1) | bit(i);
-    const uint32_t rb = bit(drop - 1);
-    bool sticky = false;
-    for (int i = 0; i < drop - 1 && i < n; ++i) sticky |= bit(i) != 0;
-    if (rb && (sticky || (q & 1))) q += 1;
+  static_assert(NL == 6, "three 64-bit words");
+  const uint64_t w2 = ((uint64_t)mag[5] << 32) | mag[4], w1 = ((uint64_t)mag[3] << 32) | mag[2],
+                 w0 = ((uint64_t)mag[1] << 32) | mag[0];
+  if (w2 == 0) return round_mag(((u128)w1 << 64) | w0, neg, E);
+  const int lz = __clzll(w2);
+  const int cut = 64 - lz;  // bits dropped
+  u128 top = ((u128)w2 << 64) | w1;
+  uint64_t rest = w0;
+  if (lz) {
+    top = (top << lz) | (w0 >> cut);
+    rest = w0 << lz;
   }
-  const double r = ldexp((double)q, E + drop);
-  return neg ? -r : r;
+  return round_mag(top | (rest != 0), neg, E + cut);
 }
 
 template <bool CPLX>
@@ -698,10 +742,10 @@ hipError_t s2_split_cols(int s, bool cplx, const double* X, int64_t ldx, int64_t
   }
   if (cp > 0 && kp > 0) {
     if (cplx)
-      hipLaunchKernelGGL(k_s2_split_cols<true>, dim3((unsigned)(cp / 256), (unsigned)(kp / S2_COL_K)),
+      hipLaunchKernelGGL(k_s2_split_cols<true>, dim3((unsigned)(cp / S2_COL_BLOCK), (unsigned)(kp / OZK_K_CHUNK)),
                          dim3(256), 0, st, X, ldx, K, cols, kp, cp, s, tau, packed);
     else
-      hipLaunchKernelGGL(k_s2_split_cols<false>, dim3((unsigned)(cp / 256), (unsigned)(kp / S2_COL_K)),
+      hipLaunchKernelGGL(k_s2_split_cols<false>, dim3((unsigned)(cp / S2_COL_BLOCK), (unsigned)(kp / OZK_K_CHUNK)),
                          dim3(256), 0, st, X, ldx, K, cols, kp, cp, s, tau, packed);
   }
   return hipGetLastError();
@@ -734,9 +778,19 @@ static hipError_t launch_gemm_mod(int s, int64_t M, int64_t N, int64_t K, const 
 hipError_t s2_gemm_mod(int s, bool cplx, int64_t M, int64_t N, int64_t K, const int8_t* Ap, const int8_t* Bp,
                        int8_t* out, hipStream_t st, int variant, int raster, int group) {
   if (M == 0 || N == 0) return hipSuccess;
-  if (variant == 1)
-    return cplx ? launch_gemm_mod<true, 1>(s, M, N, K, Ap, Bp, out, raster, group, st)
-                : launch_gemm_mod<false, 1>(s, M, N, K, Ap, Bp, out, raster, group, st);
+  static_assert(OZK_S2_VARIANTS == 4, "the variant switch below covers four variants");
+  if (variant >= 2 && round_up(K, OZK_K_CHUNK) / OZK_K_CHUNK > S2_RUN_STEPS) variant &= 1;  // large tiles: one run
+  switch (variant) {
+    case 1:
+      return cplx ? launch_gemm_mod<true, 1>(s, M, N, K, Ap, Bp, out, raster, group, st)
+                  : launch_gemm_mod<false, 1>(s, M, N, K, Ap, Bp, out, raster, group, st);
+    case 2:
+      return cplx ? launch_gemm_mod<true, 2>(s, M, N, K, Ap, Bp, out, raster, group, st)
+                  : launch_gemm_mod<false, 2>(s, M, N, K, Ap, Bp, out, raster, group, st);
+    case 3:
+      return cplx ? launch_gemm_mod<true, 3>(s, M, N, K, Ap, Bp, out, raster, group, st)
+                  : launch_gemm_mod<false, 3>(s, M, N, K, Ap, Bp, out, raster, group, st);
+  }
   return cplx ? launch_gemm_mod<true, 0>(s, M, N, K, Ap, Bp, out, raster, group, st)
               : launch_gemm_mod<false, 0>(s, M, N, K, Ap, Bp, out, raster, group, st);
 }
@@ -852,7 +906,7 @@ hipError_t s2_split_cols_auto(const int32_t* info, const double* X, int64_t ldx,
     hipLaunchKernelGGL(k_s2_col_scales_auto, dim3((unsigned)((cols + 31) / 32)), dim3(256), 0, st, X, ldx, K, cols,
                        info, s2_budgets(), tau);
   if (cp > 0 && kp > 0)
-    hipLaunchKernelGGL(k_s2_split_cols_auto, dim3((unsigned)(cp / 256), (unsigned)(kp / S2_COL_K)), dim3(256),
+    hipLaunchKernelGGL(k_s2_split_cols_auto, dim3((unsigned)(cp / S2_COL_BLOCK), (unsigned)(kp / OZK_K_CHUNK)), dim3(256),
                        0, st, X, ldx, K, cols, kp, cp, info, tau, packed);
   return hipGetLastError();
 }
@@ -898,11 +952,12 @@ hipError_t s2_crt_auto(const int32_t* info, int64_t M, int64_t N, const int8_t* 
 
 namespace {
 
-__device__ __forceinline__ int find_problem(const int64_t* __restrict__ start, int count, int64_t x) {
-  int lo = 0, hi = count - 1;  // largest i with start[i] <= x
+__device__ __forceinline__ int find_problem(const BatchUnits& u, int64_t x) {
+  const int64_t b = x >> OZK_BATCH_HINT_SHIFT;
+  int lo = u.hint[b], hi = u.hint[b + 1];  // the largest i with start[i] <= x lies in [lo, hi]
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
-    if (start[mid] <= x) lo = mid;
+    if (u.start[mid] <= x) lo = mid;
     else hi = mid - 1;
   }
   return lo;
@@ -912,26 +967,26 @@ __device__ __forceinline__ int find_problem(const int64_t* __restrict__ start, i
 
 template <bool CPLX>
 __global__ __launch_bounds__(256) void k_b_split_rows(BatchDev bd, int8_t* __restrict__ ws, S2Args sa) {
-  const int p = find_problem(bd.rows_start, bd.count, blockIdx.x);
+  const int p = find_problem(bd.rows, blockIdx.x);
   const BatchProb& q = bd.prob[p];
   s2_split_rows_block<CPLX>(q.A, q.lda, q.M, q.K, q.Kp, q.ra, sa, reinterpret_cast<int32_t*>(ws + q.off_sig),
-                            ws + q.off_a, blockIdx.x - bd.rows_start[p]);
+                            ws + q.off_a, blockIdx.x - bd.rows.start[p]);
 }
 
 template <bool CPLX>
 __global__ __launch_bounds__(256) void k_b_col_scales(BatchDev bd, int8_t* __restrict__ ws, int T) {
-  const int p = find_problem(bd.cols_start, bd.count, blockIdx.x);
+  const int p = find_problem(bd.cols, blockIdx.x);
   const BatchProb& q = bd.prob[p];
   s2_col_scales_block<CPLX>(q.B, q.ldb, q.K, q.N, T, reinterpret_cast<int32_t*>(ws + q.off_tau),
-                            blockIdx.x - bd.cols_start[p]);
+                            blockIdx.x - bd.cols.start[p]);
 }
 
 template <bool CPLX>
 __global__ __launch_bounds__(256) void k_b_split_cols(BatchDev bd, int8_t* __restrict__ ws, int s) {
-  const int p = find_problem(bd.split_start, bd.count, blockIdx.x);
+  const int p = find_problem(bd.split, blockIdx.x);
   const BatchProb& q = bd.prob[p];
-  const int64_t local = blockIdx.x - bd.split_start[p];
-  const int64_t jblocks = q.rb / 256;
+  const int64_t local = blockIdx.x - bd.split.start[p];
+  const int64_t jblocks = q.rb / S2_COL_BLOCK;
   s2_split_cols_block<CPLX>(q.B, q.ldb, q.K, q.N, q.Kp, q.rb, s, reinterpret_cast<const int32_t*>(ws + q.off_tau),
                             ws + q.off_b, local % jblocks, local / jblocks);
 }
@@ -940,11 +995,11 @@ template <bool CPLX>
 __global__ __launch_bounds__(256, 1) void k_b_gemm_mod(BatchDev bd, int8_t* __restrict__ ws, int s) {
   extern __shared__ __attribute__((aligned(1024))) int8_t lds[];
   constexpr int NP = CPLX ? 3 : 1;
-  const int64_t total = bd.item_start[bd.count];
+  const int64_t total = bd.items.start[bd.count];
   for (int64_t it = blockIdx.x; it < total; it += gridDim.x) {
-    const int i = find_problem(bd.item_start, bd.count, it);
+    const int i = find_problem(bd.items, it);
     const BatchProb& q = bd.prob[bd.order[i]];
-    const int64_t local = it - bd.item_start[i];
+    const int64_t local = it - bd.items.start[i];
     const int l = (int)(local / q.tiles);
     const int64_t tile = local % q.tiles;
     s2_gemm_tile<CPLX, 0>(ws + q.off_a, ws + q.off_b, q.ra * q.Kp * NP, q.rb * q.Kp * NP, q.ra, q.rb,
@@ -955,11 +1010,11 @@ __global__ __launch_bounds__(256, 1) void k_b_gemm_mod(BatchDev bd, int8_t* __re
 
 template <bool CPLX>
 __global__ __launch_bounds__(256) void k_b_crt(CrtArgs ca, BatchDev bd, int8_t* __restrict__ ws) {
-  const int p = find_problem(bd.crt_start, bd.count, blockIdx.x);
+  const int p = find_problem(bd.crt, blockIdx.x);
   const BatchProb& q = bd.prob[p];
   s2_crt_block<CPLX>(ca, q.M, q.N, ws + q.off_res, reinterpret_cast<const int32_t*>(ws + q.off_sig),
                      reinterpret_cast<const int32_t*>(ws + q.off_tau), q.a_re, q.a_im, q.b_re, q.b_im, q.C, q.ldc,
-                     blockIdx.x - bd.crt_start[p]);
+                     blockIdx.x - bd.crt.start[p]);
 }
 
 int64_t s2_tile_count(bool cplx, int64_t M, int64_t N) {

@@ -59,6 +59,8 @@ def test_split_rows_real(ctx, s, shape):
     X = synth.phi_matrix(rows, K, 2.0, 500 + s)
     X[min(2, rows - 1)] = 0
     X[min(4, rows - 1)] *= 1e-290
+    X[min(5, rows - 1), :3] = [5e-324, -1e-310, 2.0 ** -1060]  # subnormals beside normal entries
+    X[min(6, rows - 1)] = np.ldexp(X[min(6, rows - 1)], -1040)  # a row of subnormals
     sig, packed = ozk.ozk_s2_split_rows(ctx, s, dev(X))
     ta, _ = s2.targets(s)
     ref_sig, _ = s2.row_scales(X, ta)
@@ -84,9 +86,10 @@ def test_split_cols_real(ctx, s, shape):
     Xi = s2.integerise(X, ref_tau, 0)
     for l, m in enumerate(s2.moduli(s)):
         assert np.array_equal(R[l, :cols, :K], s2.residues(Xi, m).T), l
+    assert not R[:, cols:, :].any() and not R[:, :, K:].any()
 
 
-@pytest.mark.parametrize("s", [5, 16])
+@pytest.mark.parametrize("s", [5, 16, 20])
 def test_split_complex(ctx, s):
     rows, K = 45, 100
     X = synth.complex_phi_matrix(rows, K, 1.0, 700 + s, 710 + s)
@@ -154,14 +157,24 @@ def test_scheme2_alpha_beta_edges(ctx):
     A[1] *= 1e-300
     A[2] *= 1e300
     A[3, 4] = np.inf
+    A[4] *= 1e-160  # with B[:, 8] below: products in the subnormal range
+    A[5, :4] = [5e-324, -1e-310, 0.0, 2.0 ** -1060]
     B[:, 5] = 0
     B[7, 6] = np.nan
+    B[:, 8] *= 1e-160
+    B[:, 9] *= 1e10  # with A[2]: products past the largest double
     got = host(ozk.ozk_dgemm(ctx, ozk.OZK_SCHEME2, s, dev(A), dev(B), C=dev(C0), alpha=-1.5, beta=0.5))
     ref = s2.s2_dgemm(A, B, s, alpha=-1.5, beta=0.5, C=C0)
     assert np.array_equal(np.isnan(got), np.isnan(ref))
     ok = ~np.isnan(ref)
     assert np.array_equal(got[ok], ref[ok])
     assert np.isnan(got[3]).all() and np.isnan(got[:, 6]).all()
+    # without alpha/beta the subnormal (row 4, column 8) and infinite (2, 9) products show directly
+    got0 = host(ozk.ozk_dgemm(ctx, ozk.OZK_SCHEME2, s, dev(A), dev(B)))
+    ref0 = s2.s2_dgemm(A, B, s)
+    ok0 = ~np.isnan(ref0)
+    assert np.array_equal(np.isnan(got0), np.isnan(ref0)) and np.array_equal(got0[ok0], ref0[ok0])
+    assert 0 < abs(ref0[4, 8]) < np.finfo(np.float64).tiny and np.isinf(ref0[2, 9])
 
 
 @pytest.mark.parametrize("s", [4, 11, 16])

@@ -92,6 +92,28 @@ def test_scheme2_every_config_is_bit_identical(ctx, cplx, s):
         assert torch.equal(run(), ref), cfg
 
 
+@pytest.mark.parametrize("cplx", [False, True])
+@pytest.mark.parametrize("K", [131040, 131072 + 50])
+def test_scheme2_variants_at_the_int32_run_length(ctx, cplx, K):
+    """K = 131040 is the longest run the large tiles hold without a modular
+    reduction; one chunk beyond, they hand over to the base tile, whose
+    accumulators are reduced mid-run.  Every variant matches the oracle."""
+    M, N, s = 24, 20, 3
+    if cplx:
+        A = synth.complex_phi_matrix(M, K, 1.0, 15, 16)
+        B = synth.complex_phi_matrix(K, N, 1.0, 17, 18)
+    else:
+        A = synth.phi_matrix(M, K, 1.0, 15)
+        B = synth.phi_matrix(K, N, 1.0, 17)
+    dA, dB = dev(A), dev(B)
+    op = ozk.OZK_OP_ZGEMM if cplx else ozk.OZK_OP_DGEMM
+    expect = s2.z3m_gemm(A, B, s) if cplx else s2.s2_dgemm(A, B, s)
+    for v in range(ozk.OZK_S2_VARIANTS):
+        ozk.ozk_config_set(ctx, op, ozk.OZK_SCHEME2, s, M, N, K, (v, 0, 4, 1))
+        got = ozk.ozk_zgemm_3m(ctx, s, dA, dB) if cplx else ozk.ozk_dgemm(ctx, ozk.OZK_SCHEME2, s, dA, dB)
+        assert np.array_equal(host(got), expect), v
+
+
 @pytest.mark.parametrize("scheme,op,ps", [(ozk.OZK_SCHEME1, ozk.OZK_OP_DGEMM, 7),
                                           (ozk.OZK_SCHEME2, ozk.OZK_OP_DGEMM, 14),
                                           (ozk.OZK_SCHEME2, ozk.OZK_OP_ZGEMM, 16)])
