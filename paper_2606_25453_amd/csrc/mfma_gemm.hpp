@@ -122,18 +122,34 @@ struct StageLoads {
     }
   }
 
-  // Loads of the next K step into the stage at stage_lds.
-  __device__ __forceinline__ void issue(int8_t* stage_lds, uint32_t lane16, int wave) {
-#pragma unroll
-    for (int j = 0; j < NQ; ++j) {
-      // A or B chunk: decided at compile time unless j's group of 4 chunks
-      // straddles the end of the A slabs
-      const bool is_a = (4 * j + 3 < A_CH) || (4 * j < A_CH && 4 * j + wave < A_CH);
-      const int8_t* base = is_a ? a_next : b_next;
-      lds_dma16(base + off[j] + lane16, stage_lds + dst[j]);
+  // Bases of the next stage to issue.  A real stage (valid) advances the
+  // cursor; past the last real stage the last one is loaded again, into a
+  // slot that is never read, so that every step issues the same loads and
+  // the vmcnt thresholds stay fixed.
+  __device__ __forceinline__ void next(bool valid, const int8_t*& a_base, const int8_t*& b_base) {
+    a_base = valid ? a_next : a_next - a_step;
+    b_base = valid ? b_next : b_next - b_step;
+    if (valid) {
+      a_next += a_step;
+      b_next += b_step;
     }
-    a_next += a_step;
-    b_next += b_step;
+  }
+
+  // Chunk j of the stage with bases a_base / b_base into the stage at stage_lds.
+  __device__ __forceinline__ void issue_one(int j, const int8_t* a_base, const int8_t* b_base, int8_t* stage_lds,
+                                            uint32_t lane16, int wave) {
+    // A or B chunk: decided at compile time unless j's group of 4 chunks
+    // straddles the end of the A slabs
+    const bool is_a = (4 * j + 3 < A_CH) || (4 * j < A_CH && 4 * j + wave < A_CH);
+    lds_dma16((is_a ? a_base : b_base) + off[j] + lane16, stage_lds + dst[j]);
+  }
+
+  // All loads of the next stage.
+  __device__ __forceinline__ void issue(int8_t* stage_lds, uint32_t lane16, int wave, bool valid) {
+    const int8_t *a_base, *b_base;
+    next(valid, a_base, b_base);
+#pragma unroll
+    for (int j = 0; j < NQ; ++j) issue_one(j, a_base, b_base, stage_lds, lane16, wave);
   }
 };
 
@@ -168,12 +184,33 @@ __device__ __forceinline__ void read_frags(StepFrags<P, TM, TN>& F, const int8_t
       F.b[u][b] = *reinterpret_cast<const v4i*>(lb + (u * T::BN + wn * 32 * TN + b * 32 + lrow) * OZK_K_CHUNK + lk);
 }
 
+// Fragment read i of a step, in the order of read_frags (B plane 0, the A
+// planes, B planes 1..P-1); i is a compile-time constant after unrolling.
+template <int P, int TM, int TN, int NS>
+__device__ __forceinline__ void read_frag(StepFrags<P, TM, TN>& F, int i, const int8_t* la, int wm, int wn, int lrow,
+                                          int lk) {
+  using T = GemmTile<P, TM, TN, NS>;
+  const int8_t* lb = la + T::A_BYTES;
+  if (i < TN) {
+    F.b[0][i] = *reinterpret_cast<const v4i*>(lb + (wn * 32 * TN + i * 32 + lrow) * OZK_K_CHUNK + lk);
+  } else if (i < TN + P * TM) {
+    const int t = (i - TN) / TM, a = (i - TN) % TM;
+    F.a[t][a] = *reinterpret_cast<const v4i*>(la + (t * T::BM + wm * 32 * TM + a * 32 + lrow) * OZK_K_CHUNK + lk);
+  } else {
+    const int u = 1 + (i - TN - P * TM) / TN, b = (i - TN - P * TM) % TN;
+    F.b[u][b] = *reinterpret_cast<const v4i*>(lb + (u * T::BN + wn * 32 * TN + b * 32 + lrow) * OZK_K_CHUNK + lk);
+  }
+}
+
 // Instruction order of one K step after its barrier: one LDS fragment read,
 // then MPR MFMAs, repeated for all NR reads, then the remaining MFMAs.  The
 // reads of the next step thus start at once and are spread over most of the
 // step instead of being bunched at its end (where the next barrier's wait
 // would expose their latency), while never more than one read sits between
-// two MFMA issues.
+// two MFMA issues.  The direct-to-LDS loads of the refill sit in source order
+// between the reads (one before each of the first NQ reads; their memory
+// clobber pins them there), so they too are spread over the step instead of
+// queueing at the texture path before the first MFMA.
 template <int MPR, int... I>
 __device__ __forceinline__ void sched_reads_mfmas(std::integer_sequence<int, I...>) {
   (((void)I, __builtin_amdgcn_sched_group_barrier(0x100, 1, 0), __builtin_amdgcn_sched_group_barrier(0x008, MPR, 0)),
@@ -246,33 +283,41 @@ __device__ __forceinline__ void gemm_tile_accumulate(const int8_t* __restrict__ 
   const uint32_t lane16 = 16u * (uint32_t)(lane ^ (((lane >> 3) ^ (lane >> 4)) & 1));  // source piece of lane
   const int lead = (int)(nsteps & 1);  // 1: a virtual step -1 comes first
   // stages issued ahead: 0 .. NS-1 (NS-2 with the virtual step, whose own
-  // refill issues stage NS-1)
+  // refill issues stage NS-1); stages past the last one load it again
 #pragma unroll
   for (int s = 0; s < NS; ++s)
-    if (s < nsteps && (s < NS - 1 || !lead)) ld.issue(lds + s * T::STAGE, lane16, wave);
+    if (s < NS - 1 || !lead) ld.issue(lds + s * T::STAGE, lane16, wave, s < nsteps);
   StepFrags<P, TM, TN> F0, F1;
   if (lead) {
     zero_frags<P, TM, TN>(F0);
   } else {
-    if (nsteps >= NS) wait_vmcnt<(NS - 1) * T::WAVE_LOADS>();
-    else wait_vmcnt<0>();
+    wait_vmcnt<(NS - 1) * T::WAVE_LOADS>();
     lds_barrier();
     read_frags<P, TM, TN, NS>(F0, lds, wm, wn, lrow, lk);
   }
   int slot = lead ? NS - 1 : 0;  // slot of step r (the virtual step: the slot stage NS-1 goes to)
   // Step r = v - lead with a real successor q = r + 1: MFMAs from Fc, the
-  // fragments of q into Fn.
+  // fragments of q into Fn, the refill of slot r mod NS with stage r + NS.
+  // Every step issues one stage, so exactly NS - 2 stages follow stage q when
+  // it is waited for.
   auto step = [&](int64_t v, const StepFrags<P, TM, TN>& Fc, StepFrags<P, TM, TN>& Fn) {
-    const int64_t r = v - lead, q = r + 1;
-    if (q + NS - 2 < nsteps) wait_vmcnt<(NS - 2) * T::WAVE_LOADS>();  // stages q+1 .. q+NS-2 may stay in flight
-    else wait_vmcnt<0>();
-    lds_barrier();
-    if (r + NS < nsteps) ld.issue(lds + slot * T::STAGE, lane16, wave);
-    slot = slot + 1 == NS ? 0 : slot + 1;
-    read_frags<P, TM, TN, NS>(Fn, lds + slot * T::STAGE, wm, wn, lrow, lk);
-    step_mfmas<P, TM, TN, PAIR>(Fc, acc);
+    const int64_t r = v - lead;
+    constexpr int NQ = StageLoads<P, TM, TN, NS>::NQ;
     constexpr int NR = P * (TM + TN);
     constexpr int NM = (PAIR == TRIANGULAR ? P * (P + 1) / 2 : P) * TM * TN;
+    wait_vmcnt<(NS - 2) * T::WAVE_LOADS>();
+    lds_barrier();
+    const int8_t *a_base, *b_base;
+    ld.next(r + NS < nsteps, a_base, b_base);
+    int8_t* fill = lds + slot * T::STAGE;
+    slot = slot + 1 == NS ? 0 : slot + 1;
+    const int8_t* rd = lds + slot * T::STAGE;
+#pragma unroll
+    for (int i = 0; i < (NQ > NR ? NQ : NR); ++i) {
+      if (i < NQ) ld.issue_one(i, a_base, b_base, fill, lane16, wave);
+      if (i < NR) read_frag<P, TM, TN, NS>(Fn, i, rd, wm, wn, lrow, lk);
+    }
+    step_mfmas<P, TM, TN, PAIR>(Fc, acc);
     sched_step<NR, NM>();
     __builtin_amdgcn_sched_barrier(0);  // nothing of this step moves past the next barrier
   };
@@ -284,7 +329,8 @@ __device__ __forceinline__ void gemm_tile_accumulate(const int8_t* __restrict__ 
   }
   step(v, F0, F1);  // the last pair: its second step has no successor
   step_mfmas<P, TM, TN, PAIR>(F1, acc);
-  lds_barrier();  // LDS free for the caller's next use
+  wait_vmcnt<0>();  // the repeated last stages have landed too
+  lds_barrier();    // LDS free for the caller's next use
 }
 
 template <int P, int TM, int TN>
