@@ -10,7 +10,11 @@
 //
 // Pairing of the P planes:
 //   TRIANGULAR (Scheme I, Eq. 2):  acc[t + u] += A_t B_u  for t + u < P;
-//   DIAGONAL   (3M, Eq. 16):       acc[q] += A_q B_q.
+//   DIAGONAL   (3M, Eq. 16):       acc[q mod PACC] += A_q B_q.
+// With PACC < P the P planes of one K step are G = P / PACC consecutive K
+// chunks of a PACC-plane operand (in the block-column layout those are
+// consecutive slabs), summed into the same PACC accumulators: a stage then
+// carries G chunks and one barrier serves G times the MFMAs.
 //
 // Workgroup: 4 waves in a 2 x 2 grid, wave tile (32 TM) x (32 TN), P INT32
 // accumulators per 32 x 32 MFMA tile for the whole K loop.  NS LDS stages of
@@ -235,8 +239,8 @@ __device__ __forceinline__ void zero_frags(StepFrags<P, TM, TN>& F) {
   }
 }
 
-template <int P, int TM, int TN, int PAIR>
-__device__ __forceinline__ void step_mfmas(const StepFrags<P, TM, TN>& F, v16i (&acc)[P][TM][TN]) {
+template <int P, int TM, int TN, int PAIR, int PACC>
+__device__ __forceinline__ void step_mfmas(const StepFrags<P, TM, TN>& F, v16i (&acc)[PACC][TM][TN]) {
 #pragma unroll
   for (int u = 0; u < P; ++u) {
     if (PAIR == TRIANGULAR) {
@@ -250,7 +254,8 @@ __device__ __forceinline__ void step_mfmas(const StepFrags<P, TM, TN>& F, v16i (
 #pragma unroll
       for (int a = 0; a < TM; ++a)
 #pragma unroll
-        for (int b = 0; b < TN; ++b) acc[u][a][b] = mfma_i8_32x32x32(F.a[u][a], F.b[u][b], acc[u][a][b]);
+        for (int b = 0; b < TN; ++b)
+          acc[u % PACC][a][b] = mfma_i8_32x32x32(F.a[u][a], F.b[u][b], acc[u % PACC][a][b]);
     }
   }
 }
@@ -267,11 +272,12 @@ __device__ __forceinline__ void step_mfmas(const StepFrags<P, TM, TN>& F, v16i (
 // pairs; an odd step count is made even by a leading virtual step r = -1
 // with zero fragments (its MFMAs add nothing).  Inside the loop every step
 // has a real successor, so no branch there defines a register.
-template <int P, int TM, int TN, int NS, int PAIR>
+template <int P, int TM, int TN, int NS, int PAIR, int PACC = P>
 __device__ __forceinline__ void gemm_tile_accumulate(const int8_t* __restrict__ Ap, const int8_t* __restrict__ Bp,
                                                      int64_t rows_a, int64_t rows_b, int64_t m0, int64_t n0,
                                                      int64_t step0, int64_t nsteps, int8_t* lds,
-                                                     v16i (&acc)[P][TM][TN]) {
+                                                     v16i (&acc)[PACC][TM][TN]) {
+  static_assert(PAIR == DIAGONAL ? P % PACC == 0 : PACC == P, "accumulator planes");
   using T = GemmTile<P, TM, TN, NS>;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -317,7 +323,7 @@ __device__ __forceinline__ void gemm_tile_accumulate(const int8_t* __restrict__ 
       if (i < NQ) ld.issue_one(i, a_base, b_base, fill, lane16, wave);
       if (i < NR) read_frag<P, TM, TN, NS>(Fn, i, rd, wm, wn, lrow, lk);
     }
-    step_mfmas<P, TM, TN, PAIR>(Fc, acc);
+    step_mfmas<P, TM, TN, PAIR, PACC>(Fc, acc);
     sched_step<NR, NM>();
     __builtin_amdgcn_sched_barrier(0);  // nothing of this step moves past the next barrier
   };
@@ -328,7 +334,7 @@ __device__ __forceinline__ void gemm_tile_accumulate(const int8_t* __restrict__ 
     step(v + 1, F1, F0);
   }
   step(v, F0, F1);  // the last pair: its second step has no successor
-  step_mfmas<P, TM, TN, PAIR>(F1, acc);
+  step_mfmas<P, TM, TN, PAIR, PACC>(F1, acc);
   wait_vmcnt<0>();  // the repeated last stages have landed too
   lds_barrier();    // LDS free for the caller's next use
 }

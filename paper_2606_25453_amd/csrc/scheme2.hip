@@ -371,20 +371,28 @@ __global__ __launch_bounds__(256) void k_s2_split_cols(const double* __restrict_
 // reduction is exact because only the residue is kept.
 constexpr int64_t S2_RUN_STEPS = 4095;
 
-// Tiling of the per-modulus GEMM.  Variants: 0 the base tile (real 128 x 128,
-// 3M 128 x 64, 4 LDS stages), 1 the base tile with 3 stages, 2 the large tile
-// (real 256 x 128: 4 x 2 MFMA tiles per wave; 3M 128 x 128), 3 the large tile
-// with 3 stages.  The large tile reuses each operand fragment read from LDS
-// over more MFMAs; it holds one INT32-safe run only (no mid-run reduction,
-// which would push its accumulators out of the matrix registers), so the
-// launcher takes the base tile of the same stage count when K is longer.
+// Tiling of the per-modulus GEMM.  Base tile: real 128 x 128, 3M 128 x 64;
+// large tile: real 256 x 128 (4 x 2 MFMA tiles per wave), 3M 128 x 128.  An
+// LDS stage holds G consecutive K chunks (a stage of G P planes; one barrier
+// per G chunks):
+//   V0 base,  G = 2, 4 stages     V1 base,  G = 1, 4 stages
+//   V2 large, G = 2 (3M 1), 4 stages     V3 large, G = 4 (3M 2), 3 stages
+// The real base tile runs two workgroups per CU (its registers and its
+// 64 KB of LDS allow it), the others one.  The large tile reuses each operand
+// fragment read from LDS over more MFMAs; it holds one INT32-safe run only
+// (no mid-run reduction, which would push its accumulators out of the matrix
+// registers), so the launcher takes the base tile (variant - 2) when K is
+// longer.
 template <bool CPLX, int V = 0>
 struct S2Cfg {
   static constexpr int P = CPLX ? 3 : 1;
   static constexpr bool LARGE = V >= 2;
   static constexpr int TM = LARGE && !CPLX ? 4 : 2;
   static constexpr int TN = CPLX && !LARGE ? 1 : 2;
-  static constexpr int NS = 4 - (V & 1);
+  static constexpr int NS = V == 3 ? 3 : 4;
+  static constexpr int G = V == 0 ? 2 : V == 1 ? 1 : V == 2 ? (CPLX ? 1 : 2) : (CPLX ? 2 : 4);
+  static constexpr int LDS_BYTES = GemmTile<G * P, TM, TN, NS>::LDS_BYTES;
+  static_assert(LDS_BYTES <= 160 * 1024, "LDS budget");
 };
 
 // One output tile of one modulus: the per-modulus products, then smod (3M:
@@ -401,17 +409,23 @@ __device__ __forceinline__ void s2_gemm_tile(const int8_t* __restrict__ Ap, cons
   int64_t tm, tn;
   tile_of(tile, tiles_m, tiles_n, raster, group, tm, tn);
   const int64_t m0 = tm * T::BM, n0 = tn * T::BN;
+  constexpr int G = Cfg::G;
   v16i acc[P][TM][TN];
   zero_acc<P, TM, TN>(acc);
-  if constexpr (Cfg::LARGE) {  // one INT32-safe run only (the launcher checks K)
-    gemm_tile_accumulate<P, TM, TN, NS, DIAGONAL>(Ap + l * plane_a, Bp + l * plane_b, rows_a, rows_b, m0, n0, 0,
-                                                  nsteps, lds, acc);
-  } else
-  for (int64_t s0 = 0; s0 < nsteps || s0 == 0; s0 += S2_RUN_STEPS) {
-    const int64_t n = nsteps - s0 < S2_RUN_STEPS ? nsteps - s0 : S2_RUN_STEPS;
-    gemm_tile_accumulate<P, TM, TN, NS, DIAGONAL>(Ap + l * plane_a, Bp + l * plane_b, rows_a, rows_b, m0, n0, s0,
-                                                  n, lds, acc);
-    if (s0 + S2_RUN_STEPS >= nsteps) break;
+  // nsteps counts K chunks.  Runs of up to S2_RUN_STEPS chunks (a multiple of
+  // G; the large tiles have one run, the launcher checks K): G-chunk steps,
+  // then the chunks of the last run that do not fill one.
+  const int64_t run = Cfg::LARGE ? nsteps : (S2_RUN_STEPS / G) * G;
+  for (int64_t c0 = 0; c0 < nsteps || c0 == 0; c0 += run) {
+    const int64_t n = nsteps - c0 < run ? nsteps - c0 : run;
+    const int64_t full = n / G, rest = n - full * G;
+    if (full > 0 || G == 1)
+      gemm_tile_accumulate<G * P, TM, TN, NS, DIAGONAL, P>(Ap + l * plane_a, Bp + l * plane_b, rows_a, rows_b, m0,
+                                                           n0, c0 / G, full, lds, acc);
+    if (G > 1 && rest > 0)
+      gemm_tile_accumulate<P, TM, TN, NS, DIAGONAL, P>(Ap + l * plane_a, Bp + l * plane_b, rows_a, rows_b, m0, n0,
+                                                       c0 + full * G, rest, lds, acc);
+    if (c0 + run >= nsteps) break;
     // keep the accumulators small by subtracting a multiple of m (exact mod m)
     const int m = c_s2.m[l];
     const float inv = 1.0f / (float)m;
@@ -761,7 +775,7 @@ static hipError_t launch_gemm_mod(int s, int64_t M, int64_t N, int64_t K, const 
   static bool attr = false;
   if (!attr) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, T::LDS_BYTES);
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, Cfg::LDS_BYTES);
     if (e != hipSuccess) return e;
     attr = true;
   }
@@ -770,7 +784,7 @@ static hipError_t launch_gemm_mod(int s, int64_t M, int64_t N, int64_t K, const 
   const int64_t plane_a = ra * kp * P, plane_b = rb * kp * P;
   const int64_t tiles = ((M + T::BM - 1) / T::BM) * ((N + T::BN - 1) / T::BN);
   const dim3 grid((unsigned)tiles, 1, (unsigned)s);
-  hipLaunchKernelGGL(kern, grid, dim3(256), T::LDS_BYTES, st, Ap, Bp, plane_a, plane_b, ra, rb, kp / OZK_K_CHUNK,
+  hipLaunchKernelGGL(kern, grid, dim3(256), Cfg::LDS_BYTES, st, Ap, Bp, plane_a, plane_b, ra, rb, kp / OZK_K_CHUNK,
                      (int)M, (int)N, raster, group, out);
   return hipGetLastError();
 }
@@ -919,7 +933,7 @@ hipError_t s2_gemm_mod_auto(const int32_t* info, int64_t M, int64_t N, int64_t K
   static bool attr = false;
   if (!attr) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_s2_gemm_mod_auto),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, T::LDS_BYTES);
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, Cfg::LDS_BYTES);
     if (e != hipSuccess) return e;
     attr = true;
   }
@@ -927,7 +941,7 @@ hipError_t s2_gemm_mod_auto(const int32_t* info, int64_t M, int64_t N, int64_t K
   const int64_t ra = round_up(M, OZK_ROW_ALIGN), rb = round_up(N, OZK_ROW_ALIGN);
   const int64_t tiles = ((M + T::BM - 1) / T::BM) * ((N + T::BN - 1) / T::BN);
   const dim3 grid((unsigned)tiles, 1, (unsigned)OZK_MAX_S);
-  hipLaunchKernelGGL(k_s2_gemm_mod_auto, grid, dim3(256), T::LDS_BYTES, st, Ap, Bp, ra * kp, rb * kp, ra, rb,
+  hipLaunchKernelGGL(k_s2_gemm_mod_auto, grid, dim3(256), Cfg::LDS_BYTES, st, Ap, Bp, ra * kp, rb * kp, ra, rb,
                      kp / OZK_K_CHUNK, (int)M, (int)N, info, out);
   return hipGetLastError();
 }
@@ -991,6 +1005,10 @@ __global__ __launch_bounds__(256) void k_b_split_cols(BatchDev bd, int8_t* __res
                             ws + q.off_b, local % jblocks, local / jblocks);
 }
 
+// The batch GEMM takes variant 1 (one K chunk per stage): its problems are
+// short in K, so deeper stages only lengthen each item's prologue.
+constexpr int S2_BATCH_V = 1;
+
 template <bool CPLX>
 __global__ __launch_bounds__(256, 1) void k_b_gemm_mod(BatchDev bd, int8_t* __restrict__ ws, int s) {
   extern __shared__ __attribute__((aligned(1024))) int8_t lds[];
@@ -1002,7 +1020,7 @@ __global__ __launch_bounds__(256, 1) void k_b_gemm_mod(BatchDev bd, int8_t* __re
     const int64_t local = it - bd.items.start[i];
     const int l = (int)(local / q.tiles);
     const int64_t tile = local % q.tiles;
-    s2_gemm_tile<CPLX, 0>(ws + q.off_a, ws + q.off_b, q.ra * q.Kp * NP, q.rb * q.Kp * NP, q.ra, q.rb,
+    s2_gemm_tile<CPLX, S2_BATCH_V>(ws + q.off_a, ws + q.off_b, q.ra * q.Kp * NP, q.rb * q.Kp * NP, q.ra, q.rb,
                           q.Kp / OZK_K_CHUNK, q.M, q.N, ws + q.off_res, tile, l, 0, 4, lds);
   }
   (void)s;
@@ -1018,14 +1036,16 @@ __global__ __launch_bounds__(256) void k_b_crt(CrtArgs ca, BatchDev bd, int8_t* 
 }
 
 int64_t s2_tile_count(bool cplx, int64_t M, int64_t N) {
-  const int bm = cplx ? GemmTile<3, 2, 1, 4>::BM : GemmTile<1, 2, 2, 4>::BM;
-  const int bn = cplx ? GemmTile<3, 2, 1, 4>::BN : GemmTile<1, 2, 2, 4>::BN;
+  using TC = GemmTile<3, S2Cfg<true, S2_BATCH_V>::TM, S2Cfg<true, S2_BATCH_V>::TN, S2Cfg<true, S2_BATCH_V>::NS>;
+  using TR = GemmTile<1, S2Cfg<false, S2_BATCH_V>::TM, S2Cfg<false, S2_BATCH_V>::TN, S2Cfg<false, S2_BATCH_V>::NS>;
+  const int bm = cplx ? TC::BM : TR::BM;
+  const int bn = cplx ? TC::BN : TR::BN;
   return ((M + bm - 1) / bm) * ((N + bn - 1) / bn);
 }
 
 int s2_batch_gemm_blocks_per_cu(bool cplx) {
   int n = 0;
-  const int lds = cplx ? GemmTile<3, 2, 1, 4>::LDS_BYTES : GemmTile<1, 2, 2, 4>::LDS_BYTES;
+  const int lds = cplx ? S2Cfg<true, S2_BATCH_V>::LDS_BYTES : S2Cfg<false, S2_BATCH_V>::LDS_BYTES;
   hipError_t e = cplx ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_b_gemm_mod<true>, 256, lds)
                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_b_gemm_mod<false>, 256, lds);
   return (e == hipSuccess && n > 0) ? n : 1;
@@ -1038,7 +1058,7 @@ hipError_t s2_batched(int s, bool cplx, const BatchDev& bd, const BatchTotals& t
   crt_args(s, ca, ta, tb);
   if (tot.rows == 0 || tot.crt == 0) return hipSuccess;
   S2Args sa{s, ta};
-  const int lds = cplx ? GemmTile<3, 2, 1, 4>::LDS_BYTES : GemmTile<1, 2, 2, 4>::LDS_BYTES;
+  const int lds = cplx ? S2Cfg<true, S2_BATCH_V>::LDS_BYTES : S2Cfg<false, S2_BATCH_V>::LDS_BYTES;
   static bool attr[2] = {false, false};
   if (!attr[cplx]) {
     hipError_t e = cplx ? hipFuncSetAttribute(reinterpret_cast<const void*>(k_b_gemm_mod<true>),
