@@ -55,6 +55,22 @@ def test_split_rows_bit_exact(ctx, p, shape):
     assert not full[:, rows:, :].any() and not full[:, :, K:].any()
 
 
+@pytest.mark.parametrize("p", [3, 7])
+@pytest.mark.parametrize("shape", [(5, 8190), (6, 9000), (3, 16384), (4, 16500)])
+def test_split_rows_long_rows(ctx, p, shape):
+    """Long rows (K around 8192 and 16384, ragged tails) with zero and tiny
+    entries."""
+    rows, K = shape
+    X = synth.phi_matrix(rows, K, 2.0, 3000 + K)
+    X[1] = 0.0
+    X[2, : K // 2] *= 1e-200
+    e, packed = ozk.ozk_s1_split_rows(ctx, p, dev(X))
+    e = host(e)[:rows]
+    assert np.array_equal(e, oracle.s1_row_exponents(X))
+    D = host(ozk.unpack_s1(packed, rows, K, p))
+    assert np.array_equal(D, oracle.s1_digits_a(X, e, p))
+
+
 @pytest.mark.parametrize("p", [1, 2, 6, 8])
 @pytest.mark.parametrize("shape", [(70, 37), (128, 256), (513, 300)])
 def test_split_cols_bit_exact(ctx, p, shape):
