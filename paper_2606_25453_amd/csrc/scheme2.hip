@@ -383,14 +383,18 @@ constexpr int64_t S2_RUN_STEPS = 4095;
 // (no mid-run reduction, which would push its accumulators out of the matrix
 // registers), so the launcher takes the base tile (variant - 2) when K is
 // longer.
+// Variant 4 (the batch GEMM only): the small tile, 64 x 64 with one MFMA
+// tile per wave, one chunk per stage; it needs few registers, so several
+// workgroups share a CU and hide each other's per-item latency.
 template <bool CPLX, int V = 0>
 struct S2Cfg {
   static constexpr int P = CPLX ? 3 : 1;
-  static constexpr bool LARGE = V >= 2;
-  static constexpr int TM = LARGE && !CPLX ? 4 : 2;
-  static constexpr int TN = CPLX && !LARGE ? 1 : 2;
+  static constexpr bool LARGE = V == 2 || V == 3;
+  static constexpr bool SMALL = V == 4;
+  static constexpr int TM = SMALL ? 1 : LARGE && !CPLX ? 4 : 2;
+  static constexpr int TN = SMALL ? 1 : CPLX && !LARGE ? 1 : 2;
   static constexpr int NS = V == 3 ? 3 : 4;
-  static constexpr int G = V == 0 ? 2 : V == 1 ? 1 : V == 2 ? (CPLX ? 1 : 2) : (CPLX ? 2 : 4);
+  static constexpr int G = V == 0 ? 2 : V == 1 || V == 4 ? 1 : V == 2 ? (CPLX ? 1 : 2) : (CPLX ? 2 : 4);
   static constexpr int LDS_BYTES = GemmTile<G * P, TM, TN, NS>::LDS_BYTES;
   static_assert(LDS_BYTES <= 160 * 1024, "LDS budget");
 };
@@ -1005,12 +1009,13 @@ __global__ __launch_bounds__(256) void k_b_split_cols(BatchDev bd, int8_t* __res
                             ws + q.off_b, local % jblocks, local / jblocks);
 }
 
-// The batch GEMM takes variant 1 (one K chunk per stage): its problems are
-// short in K, so deeper stages only lengthen each item's prologue.
-constexpr int S2_BATCH_V = 1;
+// The batch GEMM takes the small tile (variant 4): its problems are small
+// and short in K, so each item is mostly prologue and epilogue latency, which
+// several resident workgroups per CU overlap.
+constexpr int S2_BATCH_V = 4;
 
 template <bool CPLX>
-__global__ __launch_bounds__(256, 1) void k_b_gemm_mod(BatchDev bd, int8_t* __restrict__ ws, int s) {
+__global__ __launch_bounds__(256, 2) void k_b_gemm_mod(BatchDev bd, int8_t* __restrict__ ws, int s) {
   extern __shared__ __attribute__((aligned(1024))) int8_t lds[];
   constexpr int NP = CPLX ? 3 : 1;
   const int64_t total = bd.items.start[bd.count];
