@@ -367,11 +367,11 @@ ozk_status ozk_batch_plan_destroy(ozk_batch_plan* plan);
  *            wave-tile orientation, 128x64 <-> 128x128 for p <= 4 and
  *            128x64 <-> 64x128 for p >= 5; bit 0: one LDS stage fewer),
  *            Scheme II 0 .. OZK_S2_VARIANTS-1 (bit 1: the large tile,
- *            256x128 real, 128x128 3M, instead of 128x128 / 128x64, taken
- *            only while K <= 131040 and replaced by the base tile beyond;
- *            bit 0: the other LDS staging depth: K chunks per stage and
- *            stages 2 x 4 (variant 0), 1 x 4 (1), 2 x 4 or 3M 1 x 4 (2),
- *            4 x 3 or 3M 2 x 3 (3));
+ *            256x128 real (variant 3: 256x256), 128x128 3M, instead of
+ *            128x128 / 128x64, taken only while K <= 131040 and replaced by
+ *            the base tile beyond; bit 0: the other LDS staging depth: K
+ *            chunks per stage and stages 2 x 4 (variant 0), 1 x 4 (1),
+ *            2 x 4 or 3M 1 x 4 (2), 2 x 3 (3));
  *   raster:  0 = tiles of one XCD form a compact block, 1 = dispatch order;
  *   group:   tile rows per raster group, 1 .. 64;
  *   split:   Scheme I only: at least this many K runs (their 128-bit partial

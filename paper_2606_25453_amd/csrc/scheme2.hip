@@ -372,11 +372,11 @@ __global__ __launch_bounds__(256) void k_s2_split_cols(const double* __restrict_
 constexpr int64_t S2_RUN_STEPS = 4095;
 
 // Tiling of the per-modulus GEMM.  Base tile: real 128 x 128, 3M 128 x 64;
-// large tile: real 256 x 128 (4 x 2 MFMA tiles per wave), 3M 128 x 128.  An
-// LDS stage holds G consecutive K chunks (a stage of G P planes; one barrier
-// per G chunks):
+// large tile: real 256 x 128 (4 x 2 MFMA tiles per wave; variant 3: 256 x 256,
+// 4 x 4, all 256 matrix registers), 3M 128 x 128.  An LDS stage holds G
+// consecutive K chunks (a stage of G P planes; one barrier per G chunks):
 //   V0 base,  G = 2, 4 stages     V1 base,  G = 1, 4 stages
-//   V2 large, G = 2 (3M 1), 4 stages     V3 large, G = 4 (3M 2), 3 stages
+//   V2 large, G = 2 (3M 1), 4 stages     V3 large, G = 2, 3 stages
 // The real base tile runs two workgroups per CU (its registers and its
 // 64 KB of LDS allow it), the others one.  The large tile reuses each operand
 // fragment read from LDS over more MFMAs; it holds one INT32-safe run only
@@ -392,9 +392,9 @@ struct S2Cfg {
   static constexpr bool LARGE = V == 2 || V == 3;
   static constexpr bool SMALL = V == 4;
   static constexpr int TM = SMALL ? 1 : LARGE && !CPLX ? 4 : 2;
-  static constexpr int TN = SMALL ? 1 : CPLX && !LARGE ? 1 : 2;
+  static constexpr int TN = SMALL ? 1 : (V == 3 && !CPLX) ? 4 : CPLX && !LARGE ? 1 : 2;
   static constexpr int NS = V == 3 ? 3 : 4;
-  static constexpr int G = V == 0 ? 2 : V == 1 || V == 4 ? 1 : V == 2 ? (CPLX ? 1 : 2) : (CPLX ? 2 : 4);
+  static constexpr int G = V == 0 ? 2 : V == 1 || V == 4 ? 1 : V == 2 ? (CPLX ? 1 : 2) : 2;
   static constexpr int LDS_BYTES = GemmTile<G * P, TM, TN, NS>::LDS_BYTES;
   static_assert(LDS_BYTES <= 160 * 1024, "LDS budget");
 };

@@ -8,7 +8,9 @@ events on the launch stream, after untimed warm-up calls and tuning):
 * Scheme II DGEMM 4096^3 and 8192 x 8192 x 2048, s in {14, 16};
 * Scheme II 3M ZGEMM 4096^3 and 8192^3, s = 16;
 * a batch of 256 ZGEMMs with M, N, K log-uniform in [64, 1024], s = 16, one
-  graph replay per call.
+  graph replay per call;
+* the automatic path (selector decision on the device) at 4096^3 and 8192^3
+  for a tolerance of 1e-13, against the fixed call at its decision.
 For each: emulated FP64 TFLOP/s (2MNK real, 8MNK complex per call), the INT8
 operations of the GEMM step and their rate against the dense INT8 peak.
 """
@@ -117,22 +119,52 @@ def batch(torch, ctx, count, s, reps):
             "end_to_end_frac_int8_peak": round(ops / ms_graph / 1e9 / INT8_PEAK_TOPS, 4)}
 
 
+def auto(torch, ctx, n, tol, reps):
+    """ozk_dgemm_auto (decision on the device, both pipelines enqueued, the
+    one not chosen returning at once) against ozk_dgemm at the decision."""
+    import synth
+    dev = "cuda:0"
+    A = torch.from_numpy(synth.phi_matrix(n, n, 1.0, synth.seed_for(2, n, 1.0, synth.ROLE_A))).to(dev)
+    B = torch.from_numpy(synth.phi_matrix(n, n, 1.0, synth.seed_for(2, n, 1.0, synth.ROLE_B))).to(dev)
+    C = torch.empty((n, n), dtype=torch.float64, device=dev)
+    info = torch.empty(ozk.OZK_SELECTOR_INFO, dtype=torch.int32, device=dev)
+    ws = torch.empty(ozk.ozk_workspace_size(ctx, ozk.OZK_OP_DGEMM, ozk.OZK_SCHEME1, n, n, n, 0), dtype=torch.uint8,
+                     device=dev)
+    ozk.ozk_dgemm_auto(ctx, tol, A, B, C, ws=ws, info=info)
+    torch.cuda.synchronize()
+    d = [int(x) for x in info.cpu()]
+    scheme, ps = (ozk.OZK_SCHEME1, d[0]) if d[4] == 1 else (ozk.OZK_SCHEME2, d[5])
+    ozk.ozk_tune(ctx, ozk.OZK_OP_DGEMM, scheme, ps, A, B, C=C, reps=2)
+    ms_auto = time_call(torch, lambda: ozk.ozk_dgemm_auto(ctx, tol, A, B, C, ws=ws, info=info), reps)
+    wsf = torch.empty(ozk.ozk_workspace_size(ctx, ozk.OZK_OP_DGEMM, scheme, n, n, n, ps), dtype=torch.uint8,
+                      device=dev)
+    ms_fixed = time_call(torch, lambda: ozk.ozk_dgemm(ctx, scheme, ps, A, B, C, ws=wsf), reps)
+    return {"path": "dgemm_auto", "M": n, "N": n, "K": n, "tol": tol,
+            "decision": {"scheme": "I" if scheme == ozk.OZK_SCHEME1 else "II", "p_or_s": ps, "p_net": d[1],
+                         "p_bound": d[2]},
+            "ms": round(ms_auto, 4), "tflops": round(2.0 * n ** 3 / ms_auto / 1e9, 3),
+            "ms_fixed_at_decision": round(ms_fixed, 4), "overhead_pct": round(100.0 * (ms_auto / ms_fixed - 1), 2)}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--quick", action="store_true", help="the smaller sizes only")
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--out", default=None, help="also append the lines to this file")
-    ap.add_argument("--only", default=None, help="comma-separated subset of s1, s2, batch")
+    ap.add_argument("--only", default=None, help="comma-separated subset of s1, s2, batch, auto")
     args = ap.parse_args()
     import torch
     ozk.library()
     ctx = ozk.Context(0)
+    actx = ozk.Context(0, selector="default")
     jobs = [("s1", 4096, p) for p in (6, 7, 8)]
     jobs += [("s2", 4096, 4096, 4096, s, False) for s in (14, 16)]
     jobs += [("s2", 8192, 8192, 2048, s, False) for s in (14, 16)]
     jobs += [("s2", 4096, 4096, 4096, 16, True)]
     jobs += [("batch", 256, 16)]
+    jobs += [("auto", 4096, 1e-13)]
     if not args.quick:
+        jobs += [("auto", 8192, 1e-13)]
         jobs += [("s1", 8192, p) for p in (6, 7, 8)]
         jobs += [("s2", 8192, 8192, 8192, 16, True)]
     if args.only:
@@ -144,6 +176,8 @@ def main():
             r = scheme1(torch, ctx, job[1], job[2], args.reps)
         elif job[0] == "s2":
             r = scheme2(torch, ctx, job[1], job[2], job[3], job[4], job[5], args.reps)
+        elif job[0] == "auto":
+            r = auto(torch, actx, job[1], job[2], args.reps)
         else:
             r = batch(torch, ctx, job[1], job[2], args.reps)
         line = json.dumps(r)
@@ -153,6 +187,7 @@ def main():
             out.flush()
         torch.cuda.empty_cache()
     ctx.close()
+    actx.close()
 
 
 if __name__ == "__main__":
