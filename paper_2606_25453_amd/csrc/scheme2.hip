@@ -289,6 +289,62 @@ __global__ __launch_bounds__(256) void k_s2_col_scales(const double* __restrict_
   s2_col_scales_block<CPLX>(X, ldx, K, cols, T, tau, blockIdx.x);
 }
 
+// Column scales for long K, split over K so that every CU has work: pass 1
+// the exponent maximum per column (integer atomic max), pass 2 the
+// norm-bound sum relative to it (integer atomic add), then the scale.  Both
+// reductions are exact integer operations, so the result equals that of
+// k_s2_col_scales whatever the order.  A block covers 64 columns x
+// S2_COLS_KB rows (4 row groups of 64 lanes, each lane one column).
+constexpr int S2_COLS_KB = 128;
+
+__global__ __launch_bounds__(256) void k_s2_col_stats_init(int64_t cols, int32_t* __restrict__ emax,
+                                                           unsigned long long* __restrict__ S) {
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (j >= cols) return;
+  emax[j] = OZK_EXP_ZERO;
+  S[j] = 0ull;
+}
+
+template <bool CPLX>
+__global__ __launch_bounds__(256) void k_s2_col_emax(const double* __restrict__ X, int64_t ldx, int64_t K,
+                                                     int64_t cols, int32_t* __restrict__ emax) {
+  constexpr int W = CPLX ? 2 : 1;
+  const int64_t j = (int64_t)blockIdx.x * 64 + (threadIdx.x & 63);
+  if (j >= cols) return;
+  const int64_t k0 = (int64_t)blockIdx.y * S2_COLS_KB, k1 = k0 + S2_COLS_KB < K ? k0 + S2_COLS_KB : K;
+  int e = OZK_EXP_ZERO;
+#pragma unroll 8
+  for (int64_t k = k0 + (threadIdx.x >> 6); k < k1; k += 4) {
+    const int ek = entry_expo<CPLX>(X + (k * ldx + j) * W);
+    e = ek > e ? ek : e;
+  }
+  if (e != OZK_EXP_ZERO) atomicMax(&emax[j], e);
+}
+
+template <bool CPLX>
+__global__ __launch_bounds__(256) void k_s2_col_norm(const double* __restrict__ X, int64_t ldx, int64_t K,
+                                                     int64_t cols, const int32_t* __restrict__ emax,
+                                                     unsigned long long* __restrict__ S) {
+  constexpr int W = CPLX ? 2 : 1;
+  const int64_t j = (int64_t)blockIdx.x * 64 + (threadIdx.x & 63);
+  if (j >= cols) return;
+  const int em = emax[j];
+  if (em == OZK_EXP_NONFINITE || em == OZK_EXP_ZERO) return;
+  const int64_t k0 = (int64_t)blockIdx.y * S2_COLS_KB, k1 = k0 + S2_COLS_KB < K ? k0 + S2_COLS_KB : K;
+  int64_t acc = 0;
+#pragma unroll 8
+  for (int64_t k = k0 + (threadIdx.x >> 6); k < k1; k += 4) acc += norm_term(entry_expo<CPLX>(X + (k * ldx + j) * W), em);
+  if (acc) atomicAdd(&S[j], (unsigned long long)acc);
+}
+
+__global__ __launch_bounds__(256) void k_s2_col_finish(int64_t cols, int T, const int32_t* __restrict__ emax,
+                                                       const unsigned long long* __restrict__ S,
+                                                       int32_t* __restrict__ tau) {
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (j >= cols) return;
+  tau[j] = scale_from(emax[j], (int64_t)S[j], T);
+}
+
 // A block covers 64 columns of one K chunk.  Thread (column j, quarter q)
 // takes the 8 k of quarter q of the chunk in column j and writes one 8-byte
 // piece per plane: the four quarters of 16 consecutive columns are 512
@@ -751,7 +807,23 @@ hipError_t s2_split_cols(int s, bool cplx, const double* X, int64_t ldx, int64_t
   int ta, tb;
   s2_targets(s, ta, tb);
   const int64_t cp = round_up(cols, OZK_ROW_ALIGN), kp = round_up(K, OZK_K_CHUNK);
-  if (cols > 0) {
+  if (cols > 0 && cp > 0 && kp >= 4 * S2_COLS_KB) {
+    // long K: split over K; the statistics live at the start of `packed`
+    // until the residues overwrite them (s Kp cp >= 12 cols bytes here)
+    unsigned long long* S = reinterpret_cast<unsigned long long*>(packed);
+    int32_t* emax = reinterpret_cast<int32_t*>(packed + 8 * cols);
+    const unsigned g1 = (unsigned)((cols + 255) / 256);
+    const dim3 g2((unsigned)((cols + 63) / 64), (unsigned)((K + S2_COLS_KB - 1) / S2_COLS_KB));
+    hipLaunchKernelGGL(k_s2_col_stats_init, dim3(g1), dim3(256), 0, st, cols, emax, S);
+    if (cplx) {
+      hipLaunchKernelGGL(k_s2_col_emax<true>, g2, dim3(256), 0, st, X, ldx, K, cols, emax);
+      hipLaunchKernelGGL(k_s2_col_norm<true>, g2, dim3(256), 0, st, X, ldx, K, cols, emax, S);
+    } else {
+      hipLaunchKernelGGL(k_s2_col_emax<false>, g2, dim3(256), 0, st, X, ldx, K, cols, emax);
+      hipLaunchKernelGGL(k_s2_col_norm<false>, g2, dim3(256), 0, st, X, ldx, K, cols, emax, S);
+    }
+    hipLaunchKernelGGL(k_s2_col_finish, dim3(g1), dim3(256), 0, st, cols, tb, emax, S, tau);
+  } else if (cols > 0) {
     const unsigned gx = (unsigned)((cols + 31) / 32);
     if (cplx)
       hipLaunchKernelGGL(k_s2_col_scales<true>, dim3(gx), dim3(256), 0, st, X, ldx, K, cols, tb, tau);

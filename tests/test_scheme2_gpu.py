@@ -73,11 +73,13 @@ def test_split_rows_real(ctx, s, shape):
 
 
 @pytest.mark.parametrize("s", [2, 14, 20])
-@pytest.mark.parametrize("shape", [(70, 37), (129, 300)])
+@pytest.mark.parametrize("shape", [(70, 37), (129, 300), (700, 77), (1100, 300)])
 def test_split_cols_real(ctx, s, shape):
     K, cols = shape
     X = synth.phi_matrix(K, cols, 2.0, 600 + s)
     X[:, min(3, cols - 1)] = 0
+    X[:, min(4, cols - 1)] *= 1e-300  # with long K the scales take the split-over-K path
+    X[: K // 3, min(5, cols - 1)] *= 1e-30
     tau, packed = ozk.ozk_s2_split_cols(ctx, s, dev(X))
     _, tb = s2.targets(s)
     ref_tau, _ = s2.col_scales(X, tb)
@@ -89,9 +91,9 @@ def test_split_cols_real(ctx, s, shape):
     assert not R[:, cols:, :].any() and not R[:, :, K:].any()
 
 
-@pytest.mark.parametrize("s", [5, 16, 20])
-def test_split_complex(ctx, s):
-    rows, K = 45, 100
+@pytest.mark.parametrize("s,K", [(5, 100), (16, 100), (20, 100), (16, 777)])
+def test_split_complex(ctx, s, K):
+    rows = 45
     X = synth.complex_phi_matrix(rows, K, 1.0, 700 + s, 710 + s)
     X[3] = X[3].real  # imaginary part zero in one row
     sig, packed = ozk.ozk_s2_split_rows(ctx, s, dev(X), complex_planes=1)
