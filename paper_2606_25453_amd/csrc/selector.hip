@@ -6,7 +6,7 @@
 // gathered in the pre-pass, on the device, so that the emulated GEMM stays a
 // stream-ordered, graph-capturable sequence:
 //
-//   k_sel_rows / k_sel_cols  row / column exponents (also the Scheme I scales)
+//   k_sel_rows / k_sel_cols_*  row / column exponents (also the Scheme I scales)
 //                            and histograms of the exponent deficits
 //                            e_i - expo(a_ik) over 16 bins, plus the largest
 //                            deficit (for the a-priori bound)
@@ -47,6 +47,36 @@ __global__ void k_sel_zero(int32_t* __restrict__ cnt) {
   if (threadIdx.x < OZK_SELECTOR_COUNTERS) cnt[threadIdx.x] = 0;
 }
 
+__global__ __launch_bounds__(256) void k_sel_fill(int32_t* __restrict__ p, int64_t n, int32_t v) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// Deficit histogram of one wave's 64 entries (valid lanes only), counted
+// with one ballot per bin: the counts are wave-uniform and no lane waits on
+// a shared counter (atomics on 16 bins serialise when most entries share a
+// bin, as they do).
+__device__ __forceinline__ void wave_bins(bool valid, int bin, int (&c)[SEL_BINS]) {
+#pragma unroll
+  for (int b = 0; b < SEL_BINS; ++b) c[b] += __popcll(__ballot(valid && bin == b));
+}
+
+// Per-wave counts into the block's shared bins, then one global add per bin.
+__device__ __forceinline__ void flush_bins(const int (&c)[SEL_BINS], int dmax, int* h, int* md,
+                                           int32_t* __restrict__ cnt_bins, int32_t* __restrict__ cnt_md) {
+  const int lane = threadIdx.x & 63;
+  if (lane < SEL_BINS) {
+    int v = 0;
+#pragma unroll
+    for (int b = 0; b < SEL_BINS; ++b) v = lane == b ? c[b] : v;
+    if (v) atomicAdd(&h[lane], v);
+  }
+  if (lane == 0 && dmax) atomicMax(md, dmax);
+  __syncthreads();
+  if (threadIdx.x < SEL_BINS && h[threadIdx.x]) atomicAdd(&cnt_bins[threadIdx.x], h[threadIdx.x]);
+  if (threadIdx.x == 0 && *md) atomicMax(cnt_md, *md);
+}
+
 // One wave per row: the row exponent (written to e_out), then the deficit
 // histogram of the row's nonzero entries.
 __global__ __launch_bounds__(256) void k_sel_rows(const double* __restrict__ X, int64_t ldx, int64_t rows,
@@ -59,7 +89,9 @@ __global__ __launch_bounds__(256) void k_sel_rows(const double* __restrict__ X, 
   __syncthreads();
   const int lane = threadIdx.x & 63;
   const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (r < rows) {
+  int c[SEL_BINS] = {};
+  int dmax = 0;
+  if (r < rows) {  // wave-uniform
     const double* xr = X + r * ldx;
     int e = OZK_EXP_ZERO;
 #pragma unroll 8
@@ -69,66 +101,81 @@ __global__ __launch_bounds__(256) void k_sel_rows(const double* __restrict__ X, 
     }
     e = wave_max(e);
     if (lane == 0) e_out[r] = e;
-    int dmax = 0;
     if (e != OZK_EXP_ZERO && e != OZK_EXP_NONFINITE) {
-#pragma unroll 8
-      for (int64_t k = lane; k < K; k += 64) {
-        const int ek = expo_of(xr[k]);
-        if (ek == OZK_EXP_ZERO) continue;
-        const int d = e - ek;
-        atomicAdd(&h[deficit_bin(d)], 1);
-        dmax = d > dmax ? d : dmax;
+      for (int64_t k0 = 0; k0 < K; k0 += 256) {  // four loads in flight, then their bins
+        int ek[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int64_t k = k0 + 64 * u + lane;
+          ek[u] = k < K ? expo_of(xr[k < K ? k : 0]) : OZK_EXP_ZERO;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const bool valid = ek[u] != OZK_EXP_ZERO;
+          const int d = e - ek[u];
+          wave_bins(valid, deficit_bin(d), c);
+          dmax = valid && d > dmax ? d : dmax;
+        }
       }
     }
     dmax = wave_max(dmax);
-    if (lane == 0) atomicMax(&md, dmax);
   }
-  __syncthreads();
-  if (threadIdx.x < SEL_BINS && h[threadIdx.x]) atomicAdd(&cnt[threadIdx.x], h[threadIdx.x]);
-  if (threadIdx.x == 0 && md) atomicMax(&cnt[32], md);
+  flush_bins(c, dmax, h, &md, cnt, &cnt[32]);
 }
 
-// 32 columns x 8 k-groups per block: column exponents (written to f_out),
-// then the deficit histogram.
-__global__ __launch_bounds__(256) void k_sel_cols(const double* __restrict__ X, int64_t ldx, int64_t K,
-                                                  int64_t cols, int32_t* __restrict__ f_out,
-                                                  int32_t* __restrict__ cnt) {
-  __shared__ int red[8][32];
+// Columns, split over K so that every CU has work: pass 1 the column
+// exponents (integer atomic max into f_out, filled with the zero sentinel
+// first), pass 2 the deficit histogram against them.  A block covers 64
+// columns x SEL_COL_KB rows (4 row groups, one column per lane).
+constexpr int SEL_COL_KB = 128;
+
+__global__ __launch_bounds__(256) void k_sel_cols_emax(const double* __restrict__ X, int64_t ldx, int64_t K,
+                                                       int64_t cols, int32_t* __restrict__ f_out) {
+  const int64_t j = (int64_t)blockIdx.x * 64 + (threadIdx.x & 63);
+  if (j >= cols) return;
+  const int64_t k0 = (int64_t)blockIdx.y * SEL_COL_KB, k1 = k0 + SEL_COL_KB < K ? k0 + SEL_COL_KB : K;
+  int e = OZK_EXP_ZERO;
+#pragma unroll 8
+  for (int64_t k = k0 + (threadIdx.x >> 6); k < k1; k += 4) {
+    const int ek = expo_of(X[k * ldx + j]);
+    e = ek > e ? ek : e;
+  }
+  if (e != OZK_EXP_ZERO) atomicMax(&f_out[j], e);
+}
+
+__global__ __launch_bounds__(256) void k_sel_cols_hist(const double* __restrict__ X, int64_t ldx, int64_t K,
+                                                       int64_t cols, const int32_t* __restrict__ f,
+                                                       int32_t* __restrict__ cnt) {
   __shared__ int h[SEL_BINS];
   __shared__ int md;
-  const int cl = threadIdx.x & 31, g = threadIdx.x >> 5;
-  const int64_t j = (int64_t)blockIdx.x * 32 + cl;
-  const bool in = j < cols;
   if (threadIdx.x < SEL_BINS) h[threadIdx.x] = 0;
   if (threadIdx.x == 0) md = 0;
-  int e = OZK_EXP_ZERO;
-  if (in)
-#pragma unroll 8
-    for (int64_t k = g; k < K; k += 8) {
-      const int ek = expo_of(X[k * ldx + j]);
-      e = ek > e ? ek : e;
-    }
-  red[g][cl] = e;
   __syncthreads();
-  int emax = red[0][cl];
-#pragma unroll
-  for (int i = 1; i < 8; ++i) emax = red[i][cl] > emax ? red[i][cl] : emax;
-  if (in && g == 0) f_out[j] = emax;
+  const int64_t j = (int64_t)blockIdx.x * 64 + (threadIdx.x & 63);
+  const int emax = j < cols ? f[j] : OZK_EXP_ZERO;
+  const bool col_ok = j < cols && emax != OZK_EXP_ZERO && emax != OZK_EXP_NONFINITE;
+  const int64_t k0 = (int64_t)blockIdx.y * SEL_COL_KB, k1 = k0 + SEL_COL_KB < K ? k0 + SEL_COL_KB : K;
+  int c[SEL_BINS] = {};
   int dmax = 0;
-  if (in && emax != OZK_EXP_ZERO && emax != OZK_EXP_NONFINITE)
-#pragma unroll 8
-    for (int64_t k = g; k < K; k += 8) {
-      const int ek = expo_of(X[k * ldx + j]);
-      if (ek == OZK_EXP_ZERO) continue;
-      const int d = emax - ek;
-      atomicAdd(&h[deficit_bin(d)], 1);
-      dmax = d > dmax ? d : dmax;
+  const int64_t jc = j < cols ? j : cols - 1;  // clamped: the loads need no condition
+  for (int64_t kb = k0 + (threadIdx.x >> 6); kb < k1; kb += 16) {  // the same trip count in every lane of a wave
+    int ek[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t k = kb + 4 * u;
+      const int x = expo_of(X[(k < k1 ? k : k0) * ldx + jc]);
+      ek[u] = col_ok && k < k1 ? x : OZK_EXP_ZERO;
     }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const bool valid = ek[u] != OZK_EXP_ZERO;
+      const int d = emax - ek[u];
+      wave_bins(valid, deficit_bin(d), c);
+      dmax = valid && d > dmax ? d : dmax;
+    }
+  }
   dmax = wave_max(dmax);
-  if ((threadIdx.x & 63) == 0 && dmax) atomicMax(&md, dmax);
-  __syncthreads();
-  if (threadIdx.x < SEL_BINS && h[threadIdx.x]) atomicAdd(&cnt[SEL_BINS + threadIdx.x], h[threadIdx.x]);
-  if (threadIdx.x == 0 && md) atomicMax(&cnt[33], md);
+  flush_bins(c, dmax, h, &md, &cnt[SEL_BINS], &cnt[33]);
 }
 
 // A-priori componentwise error bound of Scheme I with p balanced slices for
@@ -383,7 +430,14 @@ hipError_t sel_features(const double* A, int64_t lda, int64_t M, const double* B
                         int32_t* e, int32_t* f, int32_t* cnt, hipStream_t st) {
   hipLaunchKernelGGL(k_sel_zero, dim3(1), dim3(64), 0, st, cnt);
   if (M > 0) hipLaunchKernelGGL(k_sel_rows, dim3((unsigned)((M + 3) / 4)), dim3(256), 0, st, A, lda, M, K, e, cnt);
-  if (N > 0) hipLaunchKernelGGL(k_sel_cols, dim3((unsigned)((N + 31) / 32)), dim3(256), 0, st, B, ldb, K, N, f, cnt);
+  if (N > 0) {
+    hipLaunchKernelGGL(k_sel_fill, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st, f, N, (int32_t)OZK_EXP_ZERO);
+    if (K > 0) {
+      const dim3 g((unsigned)((N + 63) / 64), (unsigned)((K + SEL_COL_KB - 1) / SEL_COL_KB));
+      hipLaunchKernelGGL(k_sel_cols_emax, g, dim3(256), 0, st, B, ldb, K, N, f);
+      hipLaunchKernelGGL(k_sel_cols_hist, g, dim3(256), 0, st, B, ldb, K, N, f, cnt);
+    }
+  }
   return hipGetLastError();
 }
 
