@@ -1,6 +1,6 @@
 // Ozaki Scheme I on gfx950 INT8 MFMA (paper Sec. II-C.1 and Sec. III).
 //
-//   k_s1_split_rows   row exponents + balanced 8-bit slices of a row operand,
+//   k_s1_split_rows4  row exponents + balanced 8-bit slices of a row operand,
 //                     written in the interleaved packed layout (Eq. 11)
 //   k_s1_exp_cols     column exponents of a column operand (atomic max)
 //   k_s1_split_cols   slices of a column operand, transposed on the fly
@@ -91,27 +91,76 @@ __device__ __forceinline__ void s1_slice_row(const double* __restrict__ xr, int6
   }
 }
 
-// One wave per packed row: the row exponent (wave max), then the slices.
+// Four packed rows per wave (16 lanes per row, 8 consecutive k per lane,
+// 128 k per row per iteration): the row exponent by a 16-lane maximum, then
+// the slices.  Each store instruction of a wave writes, per slice, the four
+// rows' 32-byte pieces of 4 K chunks, and the four rows of one chunk are
+// adjacent in the packed layout: whole 128-byte lines instead of scattered
+// quarter lines.  Rows past `rows` (whole 16-lane groups) write zeros; the
+// loads of every lane are issued whatever its row, so that all lanes take
+// the same path through the shuffles.
+__device__ __forceinline__ int group16_max(int v) {
+#pragma unroll
+  for (int off = 8; off >= 1; off >>= 1) {
+    const int o = __shfl_xor(v, off, 64);
+    v = v > o ? v : o;
+  }
+  return v;
+}
+
 template <int P>
-__global__ __launch_bounds__(256) void k_s1_split_rows(const double* __restrict__ X, int64_t ldx,
-                                                       int64_t rows, int64_t K, int64_t Kp,
-                                                       int64_t rows_packed, int32_t* __restrict__ e_out,
-                                                       int8_t* __restrict__ packed) {
-  const int lane = threadIdx.x & 63;
-  const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (r >= rows_packed) return;
+__global__ __launch_bounds__(256) void k_s1_split_rows4(const double* __restrict__ X, int64_t ldx,
+                                                        int64_t rows, int64_t K, int64_t Kp,
+                                                        int64_t rows_packed, int32_t* __restrict__ e_out,
+                                                        int8_t* __restrict__ packed) {
+  const int lane = threadIdx.x & 63, q = lane & 15;
+  const int64_t r = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 4 + (lane >> 4);
+  const bool in = r < rows;
+  const double* xr = X + (in ? r : 0) * ldx;  // rows past the end load row 0 and discard it
   int e = OZK_EXP_ZERO;
-  const double* xr = X + r * ldx;  // read only for r < rows
-  if (r < rows) {
-#pragma unroll 8
-    for (int64_t k = lane; k < K; k += 64) {
-      const int ek = expo_of(xr[k]);
+  for (int64_t k0 = 8 * q; k0 < K; k0 += 128) {
+    double v[8];
+    if (k0 + 8 <= K) {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) v[j] = xr[k0 + j];
+    } else {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) v[j] = k0 + j < K ? xr[k0 + j] : 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int ek = expo_of(v[j]);
       e = ek > e ? ek : e;
     }
-    e = wave_max(e);
-    if (lane == 0) e_out[r] = e;
   }
-  s1_slice_row<P>(xr, r, rows, K, Kp, rows_packed, e, packed);
+  e = group16_max(in ? e : OZK_EXP_ZERO);
+  if (in && q == 0) e_out[r] = e;
+  const bool live = in && live_exponent(e);
+  for (int64_t k0 = 8 * q; k0 < Kp; k0 += 128) {
+    uint32_t lo[P], hi[P];
+    if (live) {
+      double a[4], b[4];
+      if (k0 + 8 <= K) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          a[j] = xr[k0 + j];
+          b[j] = xr[k0 + 4 + j];
+        }
+      } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          a[j] = k0 + j < K ? xr[k0 + j] : 0.0;
+          b[j] = k0 + 4 + j < K ? xr[k0 + 4 + j] : 0.0;
+        }
+      }
+      s1_words<P>(a, e, lo);
+      s1_words<P>(b, e, hi);
+    } else {
+#pragma unroll
+      for (int t = 0; t < P; ++t) lo[t] = hi[t] = 0;
+    }
+    if (r < rows_packed) s1_store_row_words<P>(packed, rows_packed, r, k0, lo, hi);
+  }
 }
 
 // Slices with p and the row exponents read from device memory (the slice
@@ -266,7 +315,7 @@ static hipError_t launch_split_rows(const double* X, int64_t ldx, int64_t rows, 
                                     int8_t* packed, hipStream_t st) {
   const int64_t rp = round_up(rows, OZK_ROW_ALIGN), kp = round_up(K, OZK_K_CHUNK);
   if (rp == 0) return hipSuccess;  // with K == 0 the launch still writes the exponents
-  hipLaunchKernelGGL(k_s1_split_rows<P>, dim3((unsigned)(rp / 4)), dim3(256), 0, st, X, ldx, rows, K, kp, rp, e,
+  hipLaunchKernelGGL(k_s1_split_rows4<P>, dim3((unsigned)(rp / 16)), dim3(256), 0, st, X, ldx, rows, K, kp, rp, e,
                      packed);
   return hipGetLastError();
 }

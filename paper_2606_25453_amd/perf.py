@@ -12,7 +12,8 @@ events on the launch stream, after untimed warm-up calls and tuning):
 * the automatic path (selector decision on the device) at 4096^3 and 8192^3
   for a tolerance of 1e-13, against the fixed call at its decision.
 For each: emulated FP64 TFLOP/s (2MNK real, 8MNK complex per call), the INT8
-operations of the GEMM step and their rate against the dense INT8 peak.
+operations of the GEMM step and their rate against the dense INT8 peak, and
+the native float64 / complex128 torch.matmul on the same inputs.
 """
 from __future__ import annotations
 
@@ -52,10 +53,12 @@ def scheme1(torch, ctx, n, p, reps):
     ws = torch.empty(ozk.ozk_workspace_size(ctx, ozk.OZK_OP_DGEMM, ozk.OZK_SCHEME1, n, n, n, p), dtype=torch.uint8,
                      device=dev)
     ms = time_call(torch, lambda: ozk.ozk_dgemm(ctx, ozk.OZK_SCHEME1, p, A, B, C, ws=ws), reps)
+    ms_nat = time_call(torch, lambda: torch.matmul(A, B, out=C), reps)
     ops = p * (p + 1) * n ** 3
     return {"path": "scheme1_dgemm", "M": n, "N": n, "K": n, "p": p, "config": cfg, "ms": round(ms, 4),
             "tflops": round(2.0 * n ** 3 / ms / 1e9, 3), "gemm_ms": round(gemm_ms, 4),
-            "int8_ops": ops, "gemm_frac_int8_peak": round(ops / gemm_ms / 1e9 / INT8_PEAK_TOPS, 4)}
+            "int8_ops": ops, "gemm_frac_int8_peak": round(ops / gemm_ms / 1e9 / INT8_PEAK_TOPS, 4),
+            "native_tflops": round(2.0 * n ** 3 / ms_nat / 1e9, 3)}
 
 
 def scheme2(torch, ctx, M, N, K, s, cplx, reps):
@@ -76,11 +79,13 @@ def scheme2(torch, ctx, M, N, K, s, cplx, reps):
         ms = time_call(torch, lambda: ozk.ozk_zgemm_3m(ctx, s, A, B, C, ws=ws), reps)
     else:
         ms = time_call(torch, lambda: ozk.ozk_dgemm(ctx, ozk.OZK_SCHEME2, s, A, B, C, ws=ws), reps)
+    ms_nat = time_call(torch, lambda: torch.matmul(A, B, out=C), reps)
     flops = (8.0 if cplx else 2.0) * M * N * K
     ops = (6 if cplx else 2) * s * M * N * K
     return {"path": "scheme2_zgemm_3m" if cplx else "scheme2_dgemm", "M": M, "N": N, "K": K, "s": s,
             "config": cfg, "ms": round(ms, 4), "tflops": round(flops / ms / 1e9, 3), "gemm_ms": round(gemm_ms, 4),
-            "int8_ops": ops, "gemm_frac_int8_peak": round(ops / gemm_ms / 1e9 / INT8_PEAK_TOPS, 4)}
+            "int8_ops": ops, "gemm_frac_int8_peak": round(ops / gemm_ms / 1e9 / INT8_PEAK_TOPS, 4),
+            "native_tflops": round(flops / ms_nat / 1e9, 3)}
 
 
 def batch(torch, ctx, count, s, reps):
