@@ -733,7 +733,7 @@ ozk_status ozk_batch_plan_create(ozk_ctx* ctx, ozk_op op, ozk_scheme scheme, int
   for (int i = 0; i < count; ++i) {
     const ozk::BatchProb& q = prob[i];
     const bool live = q.M > 0 && q.N > 0;
-    rows[i + 1] = rows[i] + (live ? q.ra / 4 : 0);
+    rows[i + 1] = rows[i] + (live ? ozk::s2_split_rows_blocks(q.ra) : 0);
     cols[i + 1] = cols[i] + (live ? (q.N + 31) / 32 : 0);
     split[i + 1] = split[i] + (live ? ozk::s2_split_cols_blocks(q.rb, q.Kp) : 0);
     crt[i + 1] = crt[i] + (live ? (q.M * q.N + 255) / 256 : 0);

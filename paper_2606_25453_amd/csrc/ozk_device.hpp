@@ -116,6 +116,22 @@ __device__ __forceinline__ double axpby(double alpha, double h, double beta, con
   return __fma_rn(alpha, h, bc);
 }
 
+// Maximum / sum over each aligned group of 16 lanes.
+__device__ __forceinline__ int group16_max(int v) {
+#pragma unroll
+  for (int off = 8; off >= 1; off >>= 1) {
+    const int o = __shfl_xor(v, off, 64);
+    v = v > o ? v : o;
+  }
+  return v;
+}
+
+__device__ __forceinline__ int64_t group16_sum64(int64_t v) {
+#pragma unroll
+  for (int off = 8; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
 __device__ __forceinline__ int wave_max(int v) {
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) {

@@ -69,7 +69,7 @@ struct BatchUnits {
 // step.
 struct BatchDev {
   const BatchProb* prob;
-  BatchUnits rows;   // row blocks of 4 rows (pre-pass of A)
+  BatchUnits rows;   // row blocks of 16 rows (pre-pass of A)
   BatchUnits cols;   // column blocks of 32 (column scales of B)
   BatchUnits split;  // (64-column block, K chunk) pairs (residues of B)
   BatchUnits items;  // GEMM items in the order below
@@ -86,6 +86,7 @@ hipError_t s2_batched(int s, bool cplx, const BatchDev& bd, const BatchTotals& t
                       hipStream_t st);
 int s2_batch_gemm_blocks_per_cu(bool cplx);
 int64_t s2_tile_count(bool cplx, int64_t M, int64_t N);
+int64_t s2_split_rows_blocks(int64_t rows_packed);             // workgroups of the row residue pass
 int64_t s2_split_cols_blocks(int64_t cols_packed, int64_t Kp);  // workgroups of the column residue pass
 
 void s2_targets(int s, int& ta, int& tb);

@@ -99,15 +99,6 @@ __device__ __forceinline__ void s1_slice_row(const double* __restrict__ xr, int6
 // quarter lines.  Rows past `rows` (whole 16-lane groups) write zeros; the
 // loads of every lane are issued whatever its row, so that all lanes take
 // the same path through the shuffles.
-__device__ __forceinline__ int group16_max(int v) {
-#pragma unroll
-  for (int off = 8; off >= 1; off >>= 1) {
-    const int o = __shfl_xor(v, off, 64);
-    v = v > o ? v : o;
-  }
-  return v;
-}
-
 template <int P>
 __global__ __launch_bounds__(256) void k_s1_split_rows4(const double* __restrict__ X, int64_t ldx,
                                                         int64_t rows, int64_t K, int64_t Kp,

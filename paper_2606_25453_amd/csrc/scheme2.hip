@@ -170,44 +170,48 @@ __device__ __forceinline__ void s2_store_residues(const double (&re)[4], const d
   }
 }
 
-// One wave per packed row: exponent max, norm-bound sum, then residues of 4
-// consecutive k per lane (one dword per plane).  Every modulus plane is a
-// packed operand of the shared GEMM core: real packed[l][c][r][32], complex
-// packed[l][c][q][r][32] (q = re, im, sum).  Padding rows, non-finite rows
-// and k past K get zero residues; the main loop has no condition between
-// its loads (only the 4-k group straddling K takes the guarded path).
+// Four packed rows per wave, 16 lanes per row: exponent max and norm-bound
+// sum by 16-lane reductions, then residues of 4 consecutive k per lane (one
+// dword per plane).  The four rows of one chunk are adjacent in the packed
+// layout, so every store instruction writes whole 128-byte lines.  Every
+// modulus plane is a packed operand of the shared GEMM core: real
+// packed[l][c][r][32], complex packed[l][c][q][r][32] (q = re, im, sum).
+// Padding rows, non-finite rows and k past K get zero residues; the main
+// loop has no condition between its loads (only the 4-k group straddling K
+// takes the guarded path).  Rows past `rows` load row 0 and discard it, so
+// that every lane takes part in the reductions.
+constexpr int S2_ROWS_PER_BLOCK = 16;
+
 template <bool CPLX>
 __device__ __forceinline__ void s2_split_rows_block(const double* __restrict__ X, int64_t ldx, int64_t rows,
                                                     int64_t K, int64_t Kp, int64_t rows_packed, S2Args sa,
                                                     int32_t* __restrict__ sigma_out, int8_t* __restrict__ packed,
                                                     int64_t blk) {
   constexpr int W = CPLX ? 2 : 1, NP = CPLX ? 3 : 1;
-  const int lane = threadIdx.x & 63;
-  const int64_t r = blk * 4 + (threadIdx.x >> 6);
-  if (r >= rows_packed) return;
-  const double* xr = X + r * ldx * W;  // read only for r < rows
-  int sigma = 0;
-  if (r < rows) {
-    int e = OZK_EXP_ZERO;
+  const int lane = threadIdx.x & 63, q = lane & 15;
+  const int64_t r = (blk * 4 + (threadIdx.x >> 6)) * 4 + (lane >> 4);
+  if (r >= rows_packed) return;  // whole waves only (rows_packed is a multiple of 16)
+  const bool in = r < rows;
+  const double* xr = X + (in ? r : 0) * ldx * W;
+  int e = OZK_EXP_ZERO;
 #pragma unroll 8
-    for (int64_t k = lane; k < K; k += 64) {
-      const int ek = entry_expo<CPLX>(xr + k * W);
-      e = ek > e ? ek : e;
-    }
-    e = wave_max(e);
-    int64_t S = 0;
-    if (e != OZK_EXP_NONFINITE && e != OZK_EXP_ZERO)
-#pragma unroll 8
-      for (int64_t k = lane; k < K; k += 64) S += norm_term(entry_expo<CPLX>(xr + k * W), e);
-    S = wave_sum64(S);
-    sigma = scale_from(e, S, sa.T);
-    if (lane == 0) sigma_out[r] = sigma;
+  for (int64_t k = q; k < K; k += 16) {
+    const int ek = entry_expo<CPLX>(xr + k * W);
+    e = ek > e ? ek : e;
   }
+  e = group16_max(in ? e : OZK_EXP_ZERO);
+  int64_t S = 0;
+  if (e != OZK_EXP_NONFINITE && e != OZK_EXP_ZERO)
+#pragma unroll 8
+    for (int64_t k = q; k < K; k += 16) S += norm_term(entry_expo<CPLX>(xr + k * W), e);
+  S = group16_sum64(S);
+  const int sigma = in ? scale_from(e, S, sa.T) : 0;
+  if (in && q == 0) sigma_out[r] = sigma;
   const int64_t plane = rows_packed * Kp * NP, slab = rows_packed * OZK_K_CHUNK;
   auto dst_of = [&](int64_t k0) { return packed + (k0 / OZK_K_CHUNK) * NP * slab + r * OZK_K_CHUNK + k0 % OZK_K_CHUNK; };
-  int64_t k0 = (int64_t)lane * 4;
-  if (r < rows && sigma != OZK_EXP_NONFINITE) {
-    for (; k0 + 4 <= K; k0 += 256) {
+  int64_t k0 = (int64_t)q * 4;
+  if (in && sigma != OZK_EXP_NONFINITE) {
+    for (; k0 + 4 <= K; k0 += 64) {
       double re[4], im[4];
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
@@ -216,22 +220,22 @@ __device__ __forceinline__ void s2_split_rows_block(const double* __restrict__ X
       }
       s2_store_residues<CPLX>(re, im, sigma, sa.s, dst_of(k0), plane, slab);
     }
-    for (; k0 < Kp; k0 += 256) {
+    for (; k0 < Kp; k0 += 64) {
       double re[4], im[4];
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const bool in = k0 + j < K;
-        re[j] = in ? xr[(k0 + j) * W] : 0.0;
-        im[j] = CPLX && in ? xr[(k0 + j) * W + 1] : 0.0;
+        const bool kin = k0 + j < K;
+        re[j] = kin ? xr[(k0 + j) * W] : 0.0;
+        im[j] = CPLX && kin ? xr[(k0 + j) * W + 1] : 0.0;
       }
       s2_store_residues<CPLX>(re, im, sigma, sa.s, dst_of(k0), plane, slab);
     }
   } else {
-    for (; k0 < Kp; k0 += 256) {
+    for (; k0 < Kp; k0 += 64) {
       int8_t* dst = dst_of(k0);
       for (int l = 0; l < sa.s; ++l, dst += plane)
 #pragma unroll
-        for (int q = 0; q < NP; ++q) *reinterpret_cast<uint32_t*>(dst + q * slab) = 0u;
+        for (int qq = 0; qq < NP; ++qq) *reinterpret_cast<uint32_t*>(dst + qq * slab) = 0u;
     }
   }
 }
@@ -352,6 +356,8 @@ __global__ __launch_bounds__(256) void k_s2_col_finish(int64_t cols, int T, cons
 // reads 16 consecutive columns in 4 rows of B.
 constexpr int S2_COL_BLOCK = 64;
 constexpr int S2_COL_K = OZK_K_CHUNK / 4;
+
+int64_t s2_split_rows_blocks(int64_t rows_packed) { return rows_packed / S2_ROWS_PER_BLOCK; }
 
 int64_t s2_split_cols_blocks(int64_t cols_packed, int64_t Kp) {
   return (cols_packed / S2_COL_BLOCK) * (Kp / OZK_K_CHUNK);
@@ -794,10 +800,10 @@ hipError_t s2_split_rows(int s, bool cplx, const double* X, int64_t ldx, int64_t
   if (rp == 0) return hipSuccess;
   S2Args sa{s, ta};
   if (cplx)
-    hipLaunchKernelGGL(k_s2_split_rows<true>, dim3((unsigned)(rp / 4)), dim3(256), 0, st, X, ldx, rows, K, kp, rp,
+    hipLaunchKernelGGL(k_s2_split_rows<true>, dim3((unsigned)(rp / S2_ROWS_PER_BLOCK)), dim3(256), 0, st, X, ldx, rows, K, kp, rp,
                        sa, sigma, packed);
   else
-    hipLaunchKernelGGL(k_s2_split_rows<false>, dim3((unsigned)(rp / 4)), dim3(256), 0, st, X, ldx, rows, K, kp,
+    hipLaunchKernelGGL(k_s2_split_rows<false>, dim3((unsigned)(rp / S2_ROWS_PER_BLOCK)), dim3(256), 0, st, X, ldx, rows, K, kp,
                        rp, sa, sigma, packed);
   return hipGetLastError();
 }
@@ -984,7 +990,7 @@ hipError_t s2_split_rows_auto(const int32_t* info, const double* X, int64_t ldx,
                               int32_t* sigma, int8_t* packed, hipStream_t st) {
   const int64_t rp = round_up(rows, OZK_ROW_ALIGN), kp = round_up(K, OZK_K_CHUNK);
   if (rp > 0)
-    hipLaunchKernelGGL(k_s2_split_rows_auto, dim3((unsigned)(rp / 4)), dim3(256), 0, st, X, ldx, rows, K, kp, rp,
+    hipLaunchKernelGGL(k_s2_split_rows_auto, dim3((unsigned)(rp / S2_ROWS_PER_BLOCK)), dim3(256), 0, st, X, ldx, rows, K, kp, rp,
                        info, s2_budgets(), sigma, packed);
   return hipGetLastError();
 }
