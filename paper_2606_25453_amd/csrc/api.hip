@@ -705,8 +705,8 @@ ozk_status ozk_batch_plan_create(ozk_ctx* ctx, ozk_op op, ozk_scheme scheme, int
     q.N = d.N;
     q.K = d.K;
     q.Kp = round_up(d.K, OZK_K_CHUNK);
-    q.ra = round_up(d.M, OZK_ROW_ALIGN);
-    q.rb = round_up(d.N, OZK_ROW_ALIGN);
+    q.ra = round_up(d.M, ozk::OZK_BATCH_ROW_ALIGN);
+    q.rb = round_up(d.N, ozk::OZK_BATCH_ROW_ALIGN);
     q.tiles = (d.M > 0 && d.N > 0) ? ozk::s2_tile_count(cplx, d.M, d.N) : 0;
     q.A = d.A;
     q.lda = d.lda;
@@ -720,8 +720,8 @@ ozk_status ozk_batch_plan_create(ozk_ctx* ctx, ozk_op op, ozk_scheme scheme, int
     q.b_im = cplx ? d.beta[1] : 0.0;
     q.off_sig = o; o = align256(o + 4 * (size_t)(d.M > 0 ? d.M : 1));
     q.off_tau = o; o = align256(o + 4 * (size_t)(d.N > 0 ? d.N : 1));
-    q.off_a = o; o = align256(o + ozk_s2_packed_bytes(d.M, d.K, s, cplx));
-    q.off_b = o; o = align256(o + ozk_s2_packed_bytes(d.N, d.K, s, cplx));
+    q.off_a = o; o = align256(o + (size_t)q.ra * q.Kp * s * (cplx ? 3 : 1));
+    q.off_b = o; o = align256(o + (size_t)q.rb * q.Kp * s * (cplx ? 3 : 1));
     q.off_res = o; o = align256(o + (size_t)s * (cplx ? 2 : 1) * d.M * d.N);
   }
   // GEMM item order: problems by decreasing K (stable), so the longest items go first

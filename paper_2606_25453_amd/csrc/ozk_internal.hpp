@@ -39,6 +39,11 @@ hipError_t s1_slice_auto(const int32_t* p_dev, const double* A, int64_t lda, int
                          hipStream_t st);
 hipError_t s1_gemm_auto(const int32_t* p_dev, const S1GemmArgs& g, hipStream_t st);
 
+// Packed rows of a batched problem are padded to 64 (the batch GEMM tile, a
+// multiple of the 16-row and 64-column pre-pass blocks), not to
+// OZK_ROW_ALIGN: small problems then carry far fewer padding rows.
+constexpr int OZK_BATCH_ROW_ALIGN = 64;
+
 // One problem of a batch; workspace parts are byte offsets from the
 // workspace base passed to each launch.
 struct BatchProb {

@@ -1091,6 +1091,10 @@ __global__ __launch_bounds__(256) void k_b_split_cols(BatchDev bd, int8_t* __res
 // and short in K, so each item is mostly prologue and epilogue latency, which
 // several resident workgroups per CU overlap.
 constexpr int S2_BATCH_V = 4;
+static_assert(OZK_BATCH_ROW_ALIGN % GemmTile<1, S2Cfg<false, S2_BATCH_V>::TM, S2Cfg<false, S2_BATCH_V>::TN, 4>::BM == 0 &&
+                  OZK_BATCH_ROW_ALIGN % GemmTile<1, S2Cfg<true, S2_BATCH_V>::TM, S2Cfg<true, S2_BATCH_V>::TN, 4>::BN == 0 &&
+                  OZK_BATCH_ROW_ALIGN % S2_ROWS_PER_BLOCK == 0 && OZK_BATCH_ROW_ALIGN % S2_COL_BLOCK == 0,
+              "batched packed rows cover whole tiles and pre-pass blocks");
 
 template <bool CPLX>
 __global__ __launch_bounds__(256, 2) void k_b_gemm_mod(BatchDev bd, int8_t* __restrict__ ws, int s) {
