@@ -446,8 +446,9 @@ constexpr int64_t S2_RUN_STEPS = 4095;
 // registers), so the launcher takes the base tile (variant - 2) when K is
 // longer.
 // Variant 4 (the batch GEMM only): the small tile, 64 x 64 with one MFMA
-// tile per wave, one chunk per stage; it needs few registers, so several
-// workgroups share a CU and hide each other's per-item latency.
+// tile per wave, one chunk per stage, two stages; it needs few registers and
+// little LDS, so four workgroups share a CU and hide each other's per-item
+// latency.
 template <bool CPLX, int V = 0>
 struct S2Cfg {
   static constexpr int P = CPLX ? 3 : 1;
@@ -455,7 +456,7 @@ struct S2Cfg {
   static constexpr bool SMALL = V == 4;
   static constexpr int TM = SMALL ? 1 : LARGE && !CPLX ? 4 : 2;
   static constexpr int TN = SMALL ? 1 : (V == 3 && !CPLX) ? 4 : CPLX && !LARGE ? 1 : 2;
-  static constexpr int NS = V == 3 ? 3 : 4;
+  static constexpr int NS = V == 3 ? 3 : V == 4 ? 2 : 4;
   static constexpr int G = V == 0 ? 2 : V == 1 || V == 4 ? 1 : V == 2 ? (CPLX ? 1 : 2) : 2;
   static constexpr int LDS_BYTES = GemmTile<G * P, TM, TN, NS>::LDS_BYTES;
   static_assert(LDS_BYTES <= 160 * 1024, "LDS budget");
@@ -1097,7 +1098,7 @@ static_assert(OZK_BATCH_ROW_ALIGN % GemmTile<1, S2Cfg<false, S2_BATCH_V>::TM, S2
               "batched packed rows cover whole tiles and pre-pass blocks");
 
 template <bool CPLX>
-__global__ __launch_bounds__(256, 2) void k_b_gemm_mod(BatchDev bd, int8_t* __restrict__ ws, int s) {
+__global__ __launch_bounds__(256, 4) void k_b_gemm_mod(BatchDev bd, int8_t* __restrict__ ws, int s) {
   extern __shared__ __attribute__((aligned(1024))) int8_t lds[];
   constexpr int NP = CPLX ? 3 : 1;
   const int64_t total = bd.items.start[bd.count];
