@@ -11,6 +11,10 @@ events on the launch stream, after untimed warm-up calls and tuning):
   graph replay per call;
 * the automatic path (selector decision on the device) at 4096^3 and 8192^3
   for a tolerance of 1e-13, against the fixed call at its decision.
+With --sweep instead: the paper's size sweeps (Sec. V-B), Scheme I square n in
+{1024, ..., 16384} with p in 3..8, Scheme II s in {8, ..., 16} at 4096^3 and
+8192 x 8192 x 2048, 3M ZGEMM n in {2048, 4096, 8192}, and s = 15 at 16384^3
+(real and complex), on inputs drawn on the device.
 For each: emulated FP64 TFLOP/s (2MNK real, 8MNK complex per call), the INT8
 operations of the GEMM step and their rate against the dense INT8 peak, and
 the native float64 / complex128 torch.matmul on the same inputs.
@@ -43,11 +47,27 @@ def time_call(torch, fn, reps: int, warm: int = 2) -> float:
     return a.elapsed_time(b) / reps
 
 
-def scheme1(torch, ctx, n, p, reps):
+def device_phi(torch, rows, cols, phi, seed, cplx=False):
+    """(u - 0.5) exp(phi g) with u ~ U(0, 1), g ~ N(0, 1), drawn on the device
+    (the recipe of the host generator, other random streams): the sweep's
+    16384^2 inputs would take minutes on the host."""
+    g = torch.Generator(device="cuda:0").manual_seed(seed)
+
+    def part():
+        u = torch.rand((rows, cols), generator=g, dtype=torch.float64, device="cuda:0")
+        n = torch.randn((rows, cols), generator=g, dtype=torch.float64, device="cuda:0")
+        return (u - 0.5) * torch.exp(phi * n)
+    return torch.complex(part(), part()) if cplx else part()
+
+
+def scheme1(torch, ctx, n, p, reps, inputs=None):
     import synth
     dev = "cuda:0"
-    A = torch.from_numpy(synth.phi_matrix(n, n, 1.0, synth.seed_for(2, n, 1.0, synth.ROLE_A))).to(dev)
-    B = torch.from_numpy(synth.phi_matrix(n, n, 1.0, synth.seed_for(2, n, 1.0, synth.ROLE_B))).to(dev)
+    if inputs is None:
+        A = torch.from_numpy(synth.phi_matrix(n, n, 1.0, synth.seed_for(2, n, 1.0, synth.ROLE_A))).to(dev)
+        B = torch.from_numpy(synth.phi_matrix(n, n, 1.0, synth.seed_for(2, n, 1.0, synth.ROLE_B))).to(dev)
+    else:
+        A, B = inputs
     C = torch.empty((n, n), dtype=torch.float64, device=dev)
     _, cfg, gemm_ms = ozk.ozk_tune(ctx, ozk.OZK_OP_DGEMM, ozk.OZK_SCHEME1, p, A, B, C=C, reps=2)
     ws = torch.empty(ozk.ozk_workspace_size(ctx, ozk.OZK_OP_DGEMM, ozk.OZK_SCHEME1, n, n, n, p), dtype=torch.uint8,
@@ -61,10 +81,13 @@ def scheme1(torch, ctx, n, p, reps):
             "native_tflops": round(2.0 * n ** 3 / ms_nat / 1e9, 3)}
 
 
-def scheme2(torch, ctx, M, N, K, s, cplx, reps):
+def scheme2(torch, ctx, M, N, K, s, cplx, reps, inputs=None):
     import synth
     dev = "cuda:0"
-    if cplx:
+    if inputs is not None:
+        A, B = inputs
+        op, dt = (ozk.OZK_OP_ZGEMM, torch.complex128) if cplx else (ozk.OZK_OP_DGEMM, torch.float64)
+    elif cplx:
         A = torch.from_numpy(synth.complex_phi_matrix(M, K, 1.0, 31, 32)).to(dev)
         B = torch.from_numpy(synth.complex_phi_matrix(K, N, 1.0, 33, 34)).to(dev)
         op, dt = ozk.OZK_OP_ZGEMM, torch.complex128
@@ -157,10 +180,15 @@ def main():
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--out", default=None, help="also append the lines to this file")
     ap.add_argument("--only", default=None, help="comma-separated subset of s1, s2, batch, auto")
+    ap.add_argument("--sweep", action="store_true", help="the size sweeps instead of the default workloads")
     args = ap.parse_args()
     import torch
     ozk.library()
     ctx = ozk.Context(0)
+    if args.sweep:
+        sweep(torch, ctx, args)
+        ctx.close()
+        return
     actx = ozk.Context(0, selector="default")
     jobs = [("s1", 4096, p) for p in (6, 7, 8)]
     jobs += [("s2", 4096, 4096, 4096, s, False) for s in (14, 16)]
@@ -193,6 +221,37 @@ def main():
         torch.cuda.empty_cache()
     ctx.close()
     actx.close()
+
+
+def sweep(torch, ctx, args):
+    out = open(args.out, "a") if args.out else None
+    jobs = [("s1", n, p) for n in (1024, 2048, 4096, 8192, 16384) for p in range(3, 9)]
+    jobs += [("s2", 4096, 4096, 4096, s, False) for s in (8, 10, 12, 14, 16)]
+    jobs += [("s2", 8192, 8192, 2048, s, False) for s in (8, 10, 12, 14, 16)]
+    jobs += [("s2", n, n, n, 16, True) for n in (2048, 4096, 8192)]
+    jobs += [("s2", 16384, 16384, 16384, 15, False), ("s2", 16384, 16384, 16384, 15, True)]
+    if args.only:
+        keep = set(args.only.split(","))
+        jobs = [j for j in jobs if j[0] in keep]
+    key, inputs = None, None
+    for job in jobs:
+        shape = (job[1], job[1], job[1], False) if job[0] == "s1" else job[1:4] + (job[5],)
+        if shape != key:
+            inputs = None
+            torch.cuda.empty_cache()
+            M, N, K, cplx = shape
+            inputs = (device_phi(torch, M, K, 1.0, 71, cplx), device_phi(torch, K, N, 1.0, 72, cplx))
+            key = shape
+        if job[0] == "s1":
+            r = scheme1(torch, ctx, job[1], job[2], args.reps, inputs)
+        else:
+            r = scheme2(torch, ctx, job[1], job[2], job[3], job[4], job[5], args.reps, inputs)
+        r["inputs"] = "device phi = 1"
+        line = json.dumps(r)
+        print(line, flush=True)
+        if out:
+            out.write(line + "\n")
+            out.flush()
 
 
 if __name__ == "__main__":
