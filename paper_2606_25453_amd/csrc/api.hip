@@ -738,7 +738,7 @@ ozk_status ozk_batch_plan_create(ozk_ctx* ctx, ozk_op op, ozk_scheme scheme, int
     split[i + 1] = split[i] + (live ? ozk::s2_split_cols_blocks(q.rb, q.Kp) : 0);
     crt[i + 1] = crt[i] + (live ? (q.M * q.N + 255) / 256 : 0);
   }
-  for (int i = 0; i < count; ++i) items[i + 1] = items[i] + prob[order[i]].tiles * s;
+  for (int i = 0; i < count; ++i) items[i + 1] = items[i] + prob[order[i]].tiles;  // all s moduli per item
   ozk_batch_plan* pl = (ozk_batch_plan*)calloc(1, sizeof(ozk_batch_plan));
   if (!pl) return fail(ctx, OZK_ERR_HIP, 0);
   pl->device = ctx->device;

@@ -272,11 +272,20 @@ __device__ __forceinline__ void step_mfmas(const StepFrags<P, TM, TN>& F, v16i (
 // pairs; an odd step count is made even by a leading virtual step r = -1
 // with zero fragments (its MFMAs add nothing).  Inside the loop every step
 // has a real successor, so no branch there defines a register.
-template <int P, int TM, int TN, int NS, int PAIR, int PACC = P>
+//
+// hook(r) runs after the MFMAs of every step r (-1 for the virtual step): a
+// caller that walks several independent sums along one K axis (the moduli of
+// one output tile) stores and clears the accumulators there, while the loads
+// of the following steps are already in flight.
+struct NoStepHook {
+  __device__ __forceinline__ void operator()(int64_t) const {}
+};
+
+template <int P, int TM, int TN, int NS, int PAIR, int PACC = P, class Hook = NoStepHook>
 __device__ __forceinline__ void gemm_tile_accumulate(const int8_t* __restrict__ Ap, const int8_t* __restrict__ Bp,
                                                      int64_t rows_a, int64_t rows_b, int64_t m0, int64_t n0,
                                                      int64_t step0, int64_t nsteps, int8_t* lds,
-                                                     v16i (&acc)[PACC][TM][TN]) {
+                                                     v16i (&acc)[PACC][TM][TN], Hook hook = Hook()) {
   static_assert(PAIR == DIAGONAL ? P % PACC == 0 : PACC == P, "accumulator planes");
   using T = GemmTile<P, TM, TN, NS>;
   const int lane = threadIdx.x & 63;
@@ -326,6 +335,7 @@ __device__ __forceinline__ void gemm_tile_accumulate(const int8_t* __restrict__ 
     step_mfmas<P, TM, TN, PAIR, PACC>(Fc, acc);
     sched_step<NR, NM>();
     __builtin_amdgcn_sched_barrier(0);  // nothing of this step moves past the next barrier
+    hook(r);
   };
   const int64_t total = nsteps + lead;  // even, >= 2
   int64_t v = 0;
@@ -335,6 +345,7 @@ __device__ __forceinline__ void gemm_tile_accumulate(const int8_t* __restrict__ 
   }
   step(v, F0, F1);  // the last pair: its second step has no successor
   step_mfmas<P, TM, TN, PAIR, PACC>(F1, acc);
+  hook(nsteps - 1);
   wait_vmcnt<0>();  // the repeated last stages have landed too
   lds_barrier();    // LDS free for the caller's next use
 }

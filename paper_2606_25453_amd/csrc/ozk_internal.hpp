@@ -77,7 +77,7 @@ struct BatchDev {
   BatchUnits rows;   // row blocks of 16 rows (pre-pass of A)
   BatchUnits cols;   // column blocks of 32 (column scales of B)
   BatchUnits split;  // (64-column block, K chunk) pairs (residues of B)
-  BatchUnits items;  // GEMM items in the order below
+  BatchUnits items;  // GEMM items (output tiles, all moduli each) in the order below
   BatchUnits crt;    // output blocks of 256 (CRT)
   const int32_t* order;  // GEMM item order -> problem index
   int count;

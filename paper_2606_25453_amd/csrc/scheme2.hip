@@ -464,6 +464,58 @@ struct S2Cfg {
 
 // One output tile of one modulus: the per-modulus products, then smod (3M:
 // the combination first) and the int8 output residues.
+// Keep the accumulators small by subtracting a multiple of m_l (exact mod m_l).
+template <int P, int TM, int TN>
+__device__ __forceinline__ void s2_reduce_acc(v16i (&acc)[P][TM][TN], int l) {
+  const int m = c_s2.m[l];
+  const float inv = 1.0f / (float)m;
+#pragma unroll
+  for (int d = 0; d < P; ++d)
+#pragma unroll
+    for (int a = 0; a < TM; ++a)
+#pragma unroll
+      for (int b = 0; b < TN; ++b)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          const int x = acc[d][a][b][v];
+          acc[d][a][b][v] = x - m * (int)rintf((float)x * inv);
+        }
+}
+
+// The residues mod m_l of a finished tile (Eq. 7); for 3M the real and
+// imaginary parts from the three products (Eq. 16).
+// The output positions are derived from a lane index the compiler cannot see
+// through: inside a K loop (the batched tiles store every modulus there) it
+// would otherwise keep all of them live across the loop.
+template <bool CPLX, int P, int TM, int TN>
+__device__ __forceinline__ void s2_store_tile(const v16i (&acc)[P][TM][TN], int64_t m0, int64_t n0, int64_t M,
+                                              int64_t N, int8_t* __restrict__ out, int l) {
+  const int64_t mn = (int64_t)M * N;
+  int tid = (int)threadIdx.x;
+  asm volatile("" : "+v"(tid));
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+#pragma unroll
+  for (int a = 0; a < TM; ++a)
+#pragma unroll
+    for (int b = 0; b < TN; ++b)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        // the layout of for_each_output
+        const int64_t row = m0 + wm * 32 * TM + a * 32 + 8 * (v / 4) + 4 * (lane >> 5) + (v % 4);
+        const int64_t col = n0 + wn * 32 * TN + b * 32 + (lane & 31);
+        if (row >= M || col >= N) continue;
+        if (!CPLX) {
+          out[l * mn + row * N + col] = (int8_t)smod_i32(acc[0][a][b][v], l);
+        } else {
+          const int t1 = smod_i32(acc[0][a][b][v], l), t2 = smod_i32(acc[CPLX ? 1 : 0][a][b][v], l),
+                    t3 = smod_i32(acc[CPLX ? 2 : 0][a][b][v], l);
+          out[(2 * l) * mn + row * N + col] = (int8_t)smod_i32(t1 - t2, l);
+          out[(2 * l + 1) * mn + row * N + col] = (int8_t)smod_i32(t3 - t1 - t2, l);
+        }
+      }
+}
+
 template <bool CPLX, int V>
 __device__ __forceinline__ void s2_gemm_tile(const int8_t* __restrict__ Ap, const int8_t* __restrict__ Bp,
                                              int64_t plane_a, int64_t plane_b, int64_t rows_a, int64_t rows_b,
@@ -493,32 +545,9 @@ __device__ __forceinline__ void s2_gemm_tile(const int8_t* __restrict__ Ap, cons
       gemm_tile_accumulate<P, TM, TN, NS, DIAGONAL, P>(Ap + l * plane_a, Bp + l * plane_b, rows_a, rows_b, m0, n0,
                                                        c0 + full * G, rest, lds, acc);
     if (c0 + run >= nsteps) break;
-    // keep the accumulators small by subtracting a multiple of m (exact mod m)
-    const int m = c_s2.m[l];
-    const float inv = 1.0f / (float)m;
-#pragma unroll
-    for (int d = 0; d < P; ++d)
-#pragma unroll
-      for (int a = 0; a < TM; ++a)
-#pragma unroll
-        for (int b = 0; b < TN; ++b)
-#pragma unroll
-          for (int v = 0; v < 16; ++v) {
-            const int x = acc[d][a][b][v];
-            acc[d][a][b][v] = x - m * (int)rintf((float)x * inv);
-          }
+    s2_reduce_acc<P, TM, TN>(acc, l);
   }
-  const int64_t mn = (int64_t)M * N;
-  for_each_output<P, TM, TN>(acc, m0, n0, M, N, [&](int64_t row, int64_t col, const int* vals) {
-    if (!CPLX) {
-      out[l * mn + row * N + col] = (int8_t)smod_i32(vals[0], l);
-    } else {
-      const int t1 = smod_i32(vals[0], l), t2 = smod_i32(vals[CPLX ? 1 : 0], l),
-                t3 = smod_i32(vals[CPLX ? 2 : 0], l);
-      out[(2 * l) * mn + row * N + col] = (int8_t)smod_i32(t1 - t2, l);
-      out[(2 * l + 1) * mn + row * N + col] = (int8_t)smod_i32(t3 - t1 - t2, l);
-    }
-  });
+  s2_store_tile<CPLX, P, TM, TN>(acc, m0, n0, M, N, out, l);
 }
 
 template <bool CPLX, int V>
@@ -1043,9 +1072,10 @@ hipError_t s2_crt_auto(const int32_t* info, int64_t M, int64_t N, const int8_t* 
 // Many uneven problems in one launch per step.  The plan uploads a problem
 // table and, per step, the prefix sums of the work units of each problem;
 // a workgroup finds its problem by binary search.  The GEMM step is one
-// persistent launch: the (problem, modulus, tile) items are enumerated with
-// the problems in decreasing K (longest items first) and workgroup w takes
-// items w, w + G, w + 2G, ... so that the load is balanced without atomics.
+// persistent launch: the (problem, output tile) items, each running all s
+// moduli in one K loop, are enumerated with the problems in decreasing K
+// (longest items first) and workgroup w takes items w, w + G, w + 2G, ... so
+// that the load is balanced without atomics.
 
 namespace {
 
@@ -1097,21 +1127,61 @@ static_assert(OZK_BATCH_ROW_ALIGN % GemmTile<1, S2Cfg<false, S2_BATCH_V>::TM, S2
                   OZK_BATCH_ROW_ALIGN % S2_ROWS_PER_BLOCK == 0 && OZK_BATCH_ROW_ALIGN % S2_COL_BLOCK == 0,
               "batched packed rows cover whole tiles and pre-pass blocks");
 
+// One output tile of a batched problem for all s moduli.  The residue planes
+// of consecutive moduli are consecutive K chunks of the packed operands, so
+// the s GEMMs run as one K loop of s nsteps chunks whose load pipeline never
+// drains between moduli; the step hook stores a modulus's residues once its
+// last chunk is in (and reduces the sums at run ends, as above).
 template <bool CPLX>
-__global__ __launch_bounds__(256, 4) void k_b_gemm_mod(BatchDev bd, int8_t* __restrict__ ws, int s) {
+__device__ __forceinline__ void s2_gemm_tile_moduli(const int8_t* __restrict__ Ap, const int8_t* __restrict__ Bp,
+                                                    int64_t rows_a, int64_t rows_b, int64_t nsteps, int64_t M,
+                                                    int64_t N, int8_t* __restrict__ out, int64_t tile, int s,
+                                                    int8_t* lds) {
+  using Cfg = S2Cfg<CPLX, S2_BATCH_V>;
+  static_assert(Cfg::G == 1, "one K chunk per stage");
+  constexpr int P = Cfg::P, TM = Cfg::TM, TN = Cfg::TN, NS = Cfg::NS;
+  using T = GemmTile<P, TM, TN, NS>;
+  const int64_t tiles_m = (M + T::BM - 1) / T::BM, tiles_n = (N + T::BN - 1) / T::BN;
+  int64_t tm, tn;
+  tile_of(tile, tiles_m, tiles_n, 0, 4, tm, tn);
+  const int64_t m0 = tm * T::BM, n0 = tn * T::BN;
+  v16i acc[P][TM][TN];
+  zero_acc<P, TM, TN>(acc);
+  if (nsteps == 0) {  // K = 0: every residue is 0
+    for (int l = 0; l < s; ++l) s2_store_tile<CPLX, P, TM, TN>(acc, m0, n0, M, N, out, l);
+    return;
+  }
+  int l = 0;
+  int64_t in_mod = 0, in_run = 0;  // chunks of modulus l, of its current run
+  auto hook = [&](int64_t r) {
+    if (r < 0) return;
+    ++in_mod;
+    ++in_run;
+    if (in_mod == nsteps) {
+      s2_store_tile<CPLX, P, TM, TN>(acc, m0, n0, M, N, out, l);
+      zero_acc<P, TM, TN>(acc);
+      ++l;
+      in_mod = 0;
+      in_run = 0;
+    } else if (in_run == S2_RUN_STEPS) {
+      s2_reduce_acc<P, TM, TN>(acc, l);
+      in_run = 0;
+    }
+  };
+  gemm_tile_accumulate<P, TM, TN, NS, DIAGONAL, P>(Ap, Bp, rows_a, rows_b, m0, n0, 0, (int64_t)s * nsteps, lds, acc,
+                                                   hook);
+}
+
+template <bool CPLX>
+__global__ __launch_bounds__(256, 3) void k_b_gemm_mod(BatchDev bd, int8_t* __restrict__ ws, int s) {
   extern __shared__ __attribute__((aligned(1024))) int8_t lds[];
-  constexpr int NP = CPLX ? 3 : 1;
   const int64_t total = bd.items.start[bd.count];
   for (int64_t it = blockIdx.x; it < total; it += gridDim.x) {
     const int i = find_problem(bd.items, it);
     const BatchProb& q = bd.prob[bd.order[i]];
-    const int64_t local = it - bd.items.start[i];
-    const int l = (int)(local / q.tiles);
-    const int64_t tile = local % q.tiles;
-    s2_gemm_tile<CPLX, S2_BATCH_V>(ws + q.off_a, ws + q.off_b, q.ra * q.Kp * NP, q.rb * q.Kp * NP, q.ra, q.rb,
-                          q.Kp / OZK_K_CHUNK, q.M, q.N, ws + q.off_res, tile, l, 0, 4, lds);
+    s2_gemm_tile_moduli<CPLX>(ws + q.off_a, ws + q.off_b, q.ra, q.rb, q.Kp / OZK_K_CHUNK, q.M, q.N, ws + q.off_res,
+                              it - bd.items.start[i], s, lds);
   }
-  (void)s;
 }
 
 template <bool CPLX>

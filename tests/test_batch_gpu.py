@@ -50,6 +50,7 @@ def make_batch(count, lo, hi, seed, cplx):
 def test_batch_matches_single_calls_and_oracle(ctx, cplx, s):
     probs = make_batch(12, 1, 300, 77 + s, cplx)
     probs.append((np.zeros((0, 5), probs[0][0].dtype), np.zeros((5, 3), probs[0][0].dtype)))  # empty M
+    probs.append((np.zeros((70, 0), probs[0][0].dtype), np.zeros((0, 9), probs[0][0].dtype)))  # empty K
     dA = [dev(A) for A, _ in probs]
     dB = [dev(B) for _, B in probs]
     dtype = torch.complex128 if cplx else torch.float64
