@@ -510,8 +510,8 @@ __device__ __forceinline__ void s2_store_tile(const v16i (&acc)[P][TM][TN], int6
         } else {
           const int t1 = smod_i32(acc[0][a][b][v], l), t2 = smod_i32(acc[CPLX ? 1 : 0][a][b][v], l),
                     t3 = smod_i32(acc[CPLX ? 2 : 0][a][b][v], l);
-          out[(2 * l) * mn + row * N + col] = (int8_t)smod_i32(t1 - t2, l);
-          out[(2 * l + 1) * mn + row * N + col] = (int8_t)smod_i32(t3 - t1 - t2, l);
+          out[(2 * l) * mn + row * N + col] = (int8_t)smod_sum(t1, -t2, l);
+          out[(2 * l + 1) * mn + row * N + col] = (int8_t)smod_sum(smod_sum(t3, -t1, l), -t2, l);
         }
       }
 }
