@@ -31,7 +31,7 @@ INT8_PEAK_TOPS = 5000.0  # MI355X dense INT8 MFMA, TOP/s
 # keyed by (n, p, configuration).  Reported only when the run matches; a
 # changed kernel needs new counter passes.
 MEASURED_GEMM_TRAFFIC = {
-    (8192, 7, (1, 0, 2, 1)): 19360902554,
+    (8192, 7, (1, 0, 2, 1)): 19360901973,
 }
 
 
