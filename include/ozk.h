@@ -83,7 +83,8 @@ extern "C" {
 #define OZK_MAX_S 20
 #define OZK_MAX_ROWS 16777216       /* 2^24: largest M, N (32-bit packed offsets) */
 #define OZK_S1_VARIANTS 4           /* Scheme I GEMM tile variants */
-#define OZK_S2_VARIANTS 4           /* Scheme II GEMM tile variants */
+#define OZK_S2_VARIANTS 5           /* Scheme II GEMM variants (the last: fused CRT) */
+#define OZK_S2_FUSED_CRT 4          /* Scheme II variant with the CRT fused into the GEMM (real only) */
 #define OZK_SELECTOR_PARAMS 6920   /* float32 parameters of the selector MLP */
 #define OZK_SELECTOR_COUNTERS 34   /* int32 feature counters */
 #define OZK_SELECTOR_INFO 8        /* int32 decision entries */
@@ -371,7 +372,13 @@ ozk_status ozk_batch_plan_destroy(ozk_batch_plan* plan);
  *            128x128 / 128x64, taken only while K <= 131040 and replaced by
  *            the base tile beyond; bit 0: the other LDS staging depth: K
  *            chunks per stage and stages 2 x 4 (variant 0), 1 x 4 (1),
- *            2 x 4 or 3M 1 x 4 (2), 2 x 3 (3));
+ *            2 x 4 or 3M 1 x 4 (2), 2 x 3 (3)); variant OZK_S2_FUSED_CRT (4)
+ *            fuses the CRT into the GEMM of a real product (64x64 tiles
+ *            running all s moduli, the CRT sums in registers, C written
+ *            directly, no residue planes; the paper keeps the CRT in a
+ *            kernel of its own for the register budget, Sec. IV-C) -- 3M
+ *            products and the step entry points run variant 0 in its place,
+ *            and ozk_tune does not try it;
  *   raster:  0 = tiles of one XCD form a compact block, 1 = dispatch order;
  *   group:   tile rows per raster group, 1 .. 64;
  *   split:   Scheme I only: at least this many K runs (their 128-bit partial

@@ -34,7 +34,8 @@ OZK_SELECTOR_COUNTERS = 34
 OZK_SELECTOR_INFO = 8
 OZK_MAX_ROWS = 1 << 24
 OZK_S1_VARIANTS = 4
-OZK_S2_VARIANTS = 4
+OZK_S2_VARIANTS = 5
+OZK_S2_FUSED_CRT = 4
 
 
 class OzkGemmConfig(ctypes.Structure):

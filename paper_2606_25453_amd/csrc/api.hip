@@ -398,6 +398,11 @@ ozk_status ozk_dgemm(ozk_ctx* ctx, ozk_scheme scheme, int p_or_s, int64_t M, int
     hipError_t err = ozk::s2_split_rows(s, false, A, lda, M, K, sig, Ap, stream);
     if (err == hipSuccess) err = ozk::s2_split_cols(s, false, B, ldb, K, N, tau, Bp, stream);
     const ozk_gemm_config cfg = config_for(ctx, OZK_OP_DGEMM, OZK_SCHEME2, s, M, N, K);
+    if (cfg.variant == OZK_S2_FUSED_CRT) {
+      if (err == hipSuccess)
+        err = ozk::s2_gemm_crt(s, M, N, K, Ap, Bp, sig, tau, alpha, beta, C, ldc, cfg.raster, cfg.group, stream);
+      return hip_status(ctx, err);
+    }
     if (err == hipSuccess)
       err = ozk::s2_gemm_mod(s, false, M, N, K, Ap, Bp, res, stream, cfg.variant, cfg.raster, cfg.group);
     const double al[2] = {alpha, 0.0}, be[2] = {beta, 0.0};
@@ -1079,7 +1084,7 @@ ozk_status ozk_tune(ozk_ctx* ctx, ozk_op op, ozk_scheme scheme, int p_or_s, int6
       float top_t = 0.f;
       bool have = false;
       for (int v = 0; v < OZK_S2_VARIANTS && err == hipSuccess; ++v)
-        for (int raster = 0; raster < 2 && err == hipSuccess; ++raster)
+        for (int raster = 0; raster < 2 && err == hipSuccess && v != OZK_S2_FUSED_CRT; ++raster)
           for (int group : {2, 4, 8, 16}) {
             float t = 0.f;
             err = time_median(

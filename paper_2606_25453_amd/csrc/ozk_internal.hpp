@@ -138,5 +138,9 @@ hipError_t s2_gemm_mod(int s, bool cplx, int64_t M, int64_t N, int64_t K, const 
 hipError_t s2_crt(int s, bool cplx, int64_t M, int64_t N, const int8_t* res, const int32_t* sigma,
                   const int32_t* tau, const double* alpha, const double* beta, double* C, int64_t ldc,
                   hipStream_t st);
+// GEMM and CRT in one kernel (real products; no residue planes).
+hipError_t s2_gemm_crt(int s, int64_t M, int64_t N, int64_t K, const int8_t* Ap, const int8_t* Bp,
+                       const int32_t* sigma, const int32_t* tau, double alpha, double beta, double* C, int64_t ldc,
+                       int raster, int group, hipStream_t st);
 
 }  // namespace ozk

@@ -572,31 +572,10 @@ struct CrtArgs {
   double Pf;
 };
 
-// Z = smod(sum_l W_l c_l, P) as a sign and magnitude limbs.
-__device__ __forceinline__ void crt_combine(const CrtArgs& ca, const int8_t* res, int64_t stride, uint32_t (&mag)[NL],
-                                            bool& neg) {
-  // all residues first (independent loads in flight together), then the sum
-  int cv[OZK_MAX_S];
-#pragma unroll
-  for (int l = 0; l < OZK_MAX_S; ++l) cv[l] = l < ca.s ? (int)res[l * stride] : 0;
-  uint64_t acc[NL] = {0, 0, 0, 0, 0, 0};
-#pragma unroll
-  for (int l = 0; l < OZK_MAX_S; ++l) {
-    if (l >= ca.s) break;
-    int c = cv[l];
-    if (c < 0) c += c_s2.m[l];
-#pragma unroll
-    for (int i = 0; i < NL; ++i) acc[i] += (uint64_t)ca.W[l][i] * (uint32_t)c;
-  }
-  uint32_t v[NL + 1];
-  uint64_t carry = 0;
-#pragma unroll
-  for (int i = 0; i < NL; ++i) {
-    const uint64_t t = acc[i] + carry;
-    v[i] = (uint32_t)t;
-    carry = t >> 32;
-  }
-  v[NL] = (uint32_t)carry;
+// Z = smod(V, P) as a sign and magnitude limbs, for V = sum_l W_l c_l >= 0
+// given as NL + 1 32-bit limbs.
+__device__ __forceinline__ void crt_reduce(const CrtArgs& ca, const uint32_t (&v)[NL + 1], uint32_t (&mag)[NL],
+                                           bool& neg) {
   // quotient estimate by floating point, then exact correction
   double vf = 0.0;
 #pragma unroll
@@ -676,6 +655,61 @@ __device__ __forceinline__ void crt_combine(const CrtArgs& ca, const int8_t* res
   }
 }
 
+// Z = smod(sum_l W_l c_l, P) from the s residue planes at res (stride apart).
+__device__ __forceinline__ void crt_combine(const CrtArgs& ca, const int8_t* res, int64_t stride, uint32_t (&mag)[NL],
+                                            bool& neg) {
+  // all residues first (independent loads in flight together), then the sum
+  int cv[OZK_MAX_S];
+#pragma unroll
+  for (int l = 0; l < OZK_MAX_S; ++l) cv[l] = l < ca.s ? (int)res[l * stride] : 0;
+  uint64_t acc[NL] = {0, 0, 0, 0, 0, 0};
+#pragma unroll
+  for (int l = 0; l < OZK_MAX_S; ++l) {
+    if (l >= ca.s) break;
+    int c = cv[l];
+    if (c < 0) c += c_s2.m[l];
+#pragma unroll
+    for (int i = 0; i < NL; ++i) acc[i] += (uint64_t)ca.W[l][i] * (uint32_t)c;
+  }
+  uint32_t v[NL + 1];
+  uint64_t carry = 0;
+#pragma unroll
+  for (int i = 0; i < NL; ++i) {
+    const uint64_t t = acc[i] + carry;
+    v[i] = (uint32_t)t;
+    carry = t >> 32;
+  }
+  v[NL] = (uint32_t)carry;
+  crt_reduce(ca, v, mag, neg);
+}
+
+// The CRT sum of one output kept in registers while the moduli stream by
+// (the fused variant): W_l in NZ 16-bit pieces (W_l < P <= 256^s, so NZ >=
+// s / 2 pieces hold it) times the residue taken in [0, m_l) stays below 2^24,
+// so the sums of s <= 20 such products fit 32 bits.
+
+template <int NZ>
+__device__ __forceinline__ void crt_add16(uint32_t (&z)[NZ], const CrtArgs& ca, int l, int c) {
+  static_assert(NZ <= 2 * NL, "pieces of the NL limbs");
+  const uint32_t u = (uint32_t)(c < 0 ? c + c_s2.m[l] : c);
+#pragma unroll
+  for (int i = 0; i < NZ; ++i) z[i] += __umul24((ca.W[l][i / 2] >> (16 * (i % 2))) & 0xFFFFu, u);
+}
+
+// The 16-bit-piece sums as NL + 1 32-bit limbs (exact carries).
+template <int NZ>
+__device__ __forceinline__ void crt_limbs16(const uint32_t (&z)[NZ], uint32_t (&v)[NL + 1]) {
+  uint64_t carry = 0;
+#pragma unroll
+  for (int j = 0; j < NL; ++j) {
+    const uint64_t lo = 2 * j < NZ ? z[2 * j] : 0, hi = 2 * j + 1 < NZ ? z[2 * j + 1] : 0;
+    const uint64_t t = carry + lo + (hi << 16);
+    v[j] = (uint32_t)t;
+    carry = t >> 32;
+  }
+  v[NL] = (uint32_t)carry;
+}
+
 // RN-even of +-mag 2^E (one rounding, gradual underflow included).  A
 // magnitude of 2^128 or more is cut to the 128 bits from its leading one down,
 // with the bits below folded into the lowest of them (sticky): the rounding
@@ -695,6 +729,28 @@ __device__ __forceinline__ double round_limbs(const uint32_t (&mag)[NL], bool ne
     rest = w0 << lz;
   }
   return round_mag(top | (rest != 0), neg, E + cut);
+}
+
+// C = alpha h + beta C for one output (complex: the fixed FMA sequence).
+template <bool CPLX>
+__device__ __forceinline__ void s2_store_c(const double (&h)[2], int64_t row, int64_t col, double a_re, double a_im,
+                                           double b_re, double b_im, double* __restrict__ C, int64_t ldc) {
+  if (!CPLX) {
+    double* cp = C + row * ldc + col;
+    *cp = axpby(a_re, h[0], b_re, cp);
+  } else {
+    double* cp = C + 2 * (row * ldc + col);
+    double bre = 0.0, bim = 0.0;
+    if (!(b_re == 0.0 && b_im == 0.0)) {
+      const double cre = cp[0], cim = cp[1];
+      bre = __fma_rn(b_re, cre, -(b_im * cim));
+      bim = __fma_rn(b_re, cim, b_im * cre);
+    }
+    const double ore = __fma_rn(a_re, h[0], __fma_rn(-a_im, h[1], bre));
+    const double oim = __fma_rn(a_re, h[1], __fma_rn(a_im, h[0], bim));
+    cp[0] = ore;
+    cp[1] = oim;
+  }
 }
 
 template <bool CPLX>
@@ -721,22 +777,7 @@ __device__ __forceinline__ void s2_crt_block(const CrtArgs& ca, int64_t M, int64
     crt_combine(ca, res + (CPLX ? q * mn : 0) + idx, CPLX ? 2 * mn : mn, mag, neg);
     h[q] = round_limbs(mag, neg, E);
   }
-  if (!CPLX) {
-    double* cp = C + row * ldc + col;
-    *cp = axpby(a_re, h[0], b_re, cp);
-  } else {
-    double* cp = C + 2 * (row * ldc + col);
-    double bre = 0.0, bim = 0.0;
-    if (!(b_re == 0.0 && b_im == 0.0)) {
-      const double cre = cp[0], cim = cp[1];
-      bre = __fma_rn(b_re, cre, -(b_im * cim));
-      bim = __fma_rn(b_re, cim, b_im * cre);
-    }
-    const double ore = __fma_rn(a_re, h[0], __fma_rn(-a_im, h[1], bre));
-    const double oim = __fma_rn(a_re, h[1], __fma_rn(a_im, h[0], bim));
-    cp[0] = ore;
-    cp[1] = oim;
-  }
+  s2_store_c<CPLX>(h, row, col, a_re, a_im, b_re, b_im, C, ldc);
 }
 
 template <bool CPLX>
@@ -904,7 +945,8 @@ static hipError_t launch_gemm_mod(int s, int64_t M, int64_t N, int64_t K, const 
 hipError_t s2_gemm_mod(int s, bool cplx, int64_t M, int64_t N, int64_t K, const int8_t* Ap, const int8_t* Bp,
                        int8_t* out, hipStream_t st, int variant, int raster, int group) {
   if (M == 0 || N == 0) return hipSuccess;
-  static_assert(OZK_S2_VARIANTS == 4, "the variant switch below covers four variants");
+  static_assert(OZK_S2_VARIANTS == 5 && OZK_S2_FUSED_CRT == 4, "the variant switch below covers four tile variants");
+  if (variant == OZK_S2_FUSED_CRT) variant = 0;  // residue planes wanted: the separate-kernel form
   if (variant >= 2 && round_up(K, OZK_K_CHUNK) / OZK_K_CHUNK > S2_RUN_STEPS) variant &= 1;  // large tiles: one run
   switch (variant) {
     case 1:
@@ -937,6 +979,110 @@ hipError_t s2_crt(int s, bool cplx, int64_t M, int64_t N, const int8_t* res, con
     hipLaunchKernelGGL(k_s2_crt<false>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, ca, (int)M, (int)N,
                        res, sigma, tau, alpha[0], ai, beta[0], bi, C, ldc);
   return hipGetLastError();
+}
+
+// ------------------------------------------------- fused CRT epilogue
+//
+// The real-GEMM variant that never writes residue planes: one workgroup per
+// 64 x 64 output tile runs all s moduli in one K loop (the residue planes of
+// consecutive moduli are consecutive K chunks of the packed operands), adds
+// each modulus's residue times W_l into per-output CRT sums held in registers
+// (crt_add16) as soon as its last chunk is in, and after the last modulus
+// reduces, rounds and writes C like k_s2_crt.  Bit-identical to the separate
+// kernels.  The register budget (up to ten 32-bit sums for each of the 16
+// outputs a lane holds) allows only this small tile, which moves about four
+// times the operand bytes per MFMA of the large tiles; for 3M (two sums per
+// output) it does not fit without spilling, so complex products keep the
+// separate kernels.
+constexpr int S2_FUSED_V = 4;
+
+template <int NZ>
+__global__ __launch_bounds__(256, 1) void k_s2_gemm_crt(CrtArgs ca, const int8_t* __restrict__ Ap,
+                                                       const int8_t* __restrict__ Bp, int64_t rows_a, int64_t rows_b,
+                                                       int64_t nsteps, int M, int N, const int32_t* __restrict__ sigma,
+                                                       const int32_t* __restrict__ tau, double alpha, double beta,
+                                                       double* __restrict__ C, int64_t ldc, int raster, int group) {
+  extern __shared__ __attribute__((aligned(1024))) int8_t lds[];
+  using Cfg = S2Cfg<false, S2_FUSED_V>;
+  static_assert(Cfg::P == 1 && Cfg::G == 1 && Cfg::TM == 1 && Cfg::TN == 1,
+                "one plane, one 32 x 32 MFMA tile per wave, one chunk per stage");
+  constexpr int NS = Cfg::NS;
+  using T = GemmTile<1, 1, 1, NS>;
+  const int64_t tiles_m = (M + T::BM - 1) / T::BM, tiles_n = (N + T::BN - 1) / T::BN;
+  int64_t tm, tn;
+  tile_of(blockIdx.x, tiles_m, tiles_n, raster, group, tm, tn);
+  const int64_t m0 = tm * T::BM, n0 = tn * T::BN;
+  v16i acc[1][1][1];
+  zero_acc<1, 1, 1>(acc);
+  uint32_t z[16][NZ];
+#pragma unroll
+  for (int v = 0; v < 16; ++v)
+#pragma unroll
+    for (int i = 0; i < NZ; ++i) z[v][i] = 0;
+  int l = 0;
+  int64_t in_mod = 0, in_run = 0;  // chunks of modulus l, of its current run
+  auto hook = [&](int64_t r) {
+    if (r < 0) return;
+    ++in_mod;
+    ++in_run;
+    if (in_mod == nsteps) {
+#pragma unroll
+      for (int v = 0; v < 16; ++v) crt_add16(z[v], ca, l, smod_i32(acc[0][0][0][v], l));
+      zero_acc<1, 1, 1>(acc);
+      ++l;
+      in_mod = 0;
+      in_run = 0;
+    } else if (in_run == S2_RUN_STEPS) {
+      s2_reduce_acc<1, 1, 1>(acc, l);
+      in_run = 0;
+    }
+  };
+  gemm_tile_accumulate<1, 1, 1, NS, DIAGONAL, 1>(Ap, Bp, rows_a, rows_b, m0, n0, 0, (int64_t)ca.s * nsteps, lds, acc,
+                                                 hook);
+  // K = 0 runs no step: every sum stays 0, as the residues would be.
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+    // the output layout of for_each_output
+    const int64_t row = m0 + wm * 32 + 8 * (v / 4) + 4 * (lane >> 5) + (v % 4);
+    const int64_t col = n0 + wn * 32 + (lane & 31);
+    if (row >= M || col >= N) continue;
+    const int si = sigma[row], tj = tau[col];
+    const bool bad = si == OZK_EXP_NONFINITE || tj == OZK_EXP_NONFINITE;
+    uint32_t vl[NL + 1], mag[NL];
+    bool neg;
+    crt_limbs16(z[v], vl);
+    crt_reduce(ca, vl, mag, neg);
+    const double h[2] = {bad ? __builtin_nan("") : round_limbs(mag, neg, -si - tj), 0.0};
+    s2_store_c<false>(h, row, col, alpha, 0.0, beta, 0.0, C, ldc);
+  }
+}
+
+hipError_t s2_gemm_crt(int s, int64_t M, int64_t N, int64_t K, const int8_t* Ap, const int8_t* Bp,
+                       const int32_t* sigma, const int32_t* tau, double alpha, double beta, double* C, int64_t ldc,
+                       int raster, int group, hipStream_t st) {
+  if (M == 0 || N == 0) return hipSuccess;
+  CrtArgs ca;
+  int ta, tb;
+  crt_args(s, ca, ta, tb);
+  using Cfg = S2Cfg<false, S2_FUSED_V>;
+  using T = GemmTile<1, Cfg::TM, Cfg::TN, Cfg::NS>;
+  const int64_t kp = round_up(K, OZK_K_CHUNK);
+  const int64_t ra = round_up(M, OZK_ROW_ALIGN), rb = round_up(N, OZK_ROW_ALIGN);
+  const int64_t tiles = ((M + T::BM - 1) / T::BM) * ((N + T::BN - 1) / T::BN);
+  auto launch = [&](auto kern) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       Cfg::LDS_BYTES);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kern, dim3((unsigned)tiles), dim3(256), Cfg::LDS_BYTES, st, ca, Ap, Bp, ra, rb,
+                       kp / OZK_K_CHUNK, (int)M, (int)N, sigma, tau, alpha, beta, C, ldc, raster, group);
+    return hipGetLastError();
+  };
+  // 16-bit pieces of W_l < P <= 256^s
+  if (s <= 12) return launch(k_s2_gemm_crt<6>);
+  if (s <= 16) return launch(k_s2_gemm_crt<8>);
+  return launch(k_s2_gemm_crt<10>);
 }
 
 // --------------------------------- modulus count chosen on the device

@@ -7,6 +7,8 @@ events on the launch stream, after untimed warm-up calls and tuning):
 * Scheme I DGEMM, square n in {4096, 8192}, p in {6, 7, 8};
 * Scheme II DGEMM 4096^3 and 8192 x 8192 x 2048, s in {14, 16};
 * Scheme II 3M ZGEMM 4096^3 and 8192^3, s = 16;
+* Scheme II DGEMM with the CRT fused into the GEMM against the separate
+  kernels, 4096^3 at s = 14 and 8192 x 8192 x 2048 at s = 16;
 * a batch of 256 ZGEMMs with M, N, K log-uniform in [64, 1024], s = 16, one
   graph replay per call;
 * the automatic path (selector decision on the device) at 4096^3 and 8192^3
@@ -111,6 +113,29 @@ def scheme2(torch, ctx, M, N, K, s, cplx, reps, inputs=None):
             "native_tflops": round(flops / ms_nat / 1e9, 3)}
 
 
+def fused_crt(torch, ctx, M, N, K, s, reps):
+    """Scheme II DGEMM with the CRT fused into the GEMM (variant
+    OZK_S2_FUSED_CRT) against the separate kernels at the tuned variant."""
+    import synth
+    dev = "cuda:0"
+    A = torch.from_numpy(synth.phi_matrix(M, K, 1.0, 31)).to(dev)
+    B = torch.from_numpy(synth.phi_matrix(K, N, 1.0, 33)).to(dev)
+    C = torch.empty((M, N), dtype=torch.float64, device=dev)
+    _, cfg, _ = ozk.ozk_tune(ctx, ozk.OZK_OP_DGEMM, ozk.OZK_SCHEME2, s, A, B, C=C, reps=2)
+    ws = torch.empty(ozk.ozk_workspace_size(ctx, ozk.OZK_OP_DGEMM, ozk.OZK_SCHEME2, M, N, K, s), dtype=torch.uint8,
+                     device=dev)
+    ms_sep = time_call(torch, lambda: ozk.ozk_dgemm(ctx, ozk.OZK_SCHEME2, s, A, B, C, ws=ws), reps)
+    sep = C.clone()
+    ozk.ozk_config_set(ctx, ozk.OZK_OP_DGEMM, ozk.OZK_SCHEME2, s, M, N, K, (ozk.OZK_S2_FUSED_CRT, 0, 4, 1))
+    ms_fused = time_call(torch, lambda: ozk.ozk_dgemm(ctx, ozk.OZK_SCHEME2, s, A, B, C, ws=ws), reps)
+    same = bool(torch.equal(C, sep))
+    ozk.ozk_config_set(ctx, ozk.OZK_OP_DGEMM, ozk.OZK_SCHEME2, s, M, N, K, cfg)
+    flops = 2.0 * M * N * K
+    return {"path": "scheme2_dgemm_fused_crt", "M": M, "N": N, "K": K, "s": s, "ms_fused": round(ms_fused, 4),
+            "tflops_fused": round(flops / ms_fused / 1e9, 3), "ms_separate": round(ms_sep, 4),
+            "tflops_separate": round(flops / ms_sep / 1e9, 3), "separate_config": cfg, "bit_identical": same}
+
+
 def batch(torch, ctx, count, s, reps):
     import synth
     dev = "cuda:0"
@@ -179,7 +204,7 @@ def main():
     ap.add_argument("--quick", action="store_true", help="the smaller sizes only")
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--out", default=None, help="also append the lines to this file")
-    ap.add_argument("--only", default=None, help="comma-separated subset of s1, s2, batch, auto")
+    ap.add_argument("--only", default=None, help="comma-separated subset of s1, s2, fused, batch, auto")
     ap.add_argument("--sweep", action="store_true", help="the size sweeps instead of the default workloads")
     args = ap.parse_args()
     import torch
@@ -194,6 +219,7 @@ def main():
     jobs += [("s2", 4096, 4096, 4096, s, False) for s in (14, 16)]
     jobs += [("s2", 8192, 8192, 2048, s, False) for s in (14, 16)]
     jobs += [("s2", 4096, 4096, 4096, 16, True)]
+    jobs += [("fused", 4096, 4096, 4096, 14), ("fused", 8192, 8192, 2048, 16)]
     jobs += [("batch", 256, 16)]
     jobs += [("auto", 4096, 1e-13)]
     if not args.quick:
@@ -211,6 +237,8 @@ def main():
             r = scheme2(torch, ctx, job[1], job[2], job[3], job[4], job[5], args.reps)
         elif job[0] == "auto":
             r = auto(torch, actx, job[1], job[2], args.reps)
+        elif job[0] == "fused":
+            r = fused_crt(torch, ctx, job[1], job[2], job[3], job[4], args.reps)
         else:
             r = batch(torch, ctx, job[1], job[2], args.reps)
         line = json.dumps(r)

@@ -52,3 +52,15 @@ def test_null_context_is_rejected(lib):
     assert lib.ozk_status_string(ozk.OZK_ERR_WORKSPACE).decode() == "workspace missing or too small"
     assert lib.ozk_version().decode().count(".") == 2
     assert lib.ozk_last_arg(None) == 0
+
+
+def test_header_constants_match_the_binding():
+    """Every integer #define of the header that the binding mirrors has the
+    same value there."""
+    import re
+    text = open(os.path.join(ROOT, "include", "ozk.h")).read()
+    defines = dict((k, int(v)) for k, v in re.findall(r"^#define (OZK_\w+) \(?(-?\d+)\)?", text, re.M))
+    mirrored = [k for k in defines if hasattr(ozk, k)]
+    assert {"OZK_S1_VARIANTS", "OZK_S2_VARIANTS", "OZK_S2_FUSED_CRT", "OZK_K_CHUNK", "OZK_ROW_ALIGN"} <= set(mirrored)
+    for k in mirrored:
+        assert getattr(ozk, k) == defines[k], k

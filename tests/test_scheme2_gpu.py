@@ -247,3 +247,86 @@ def test_large_zgemm_3m_sampled(ctx):
     rows = rng.integers(0, n, 16)
     cols = rng.integers(0, n, 16)
     assert np.array_equal(C[rows, cols], s2.z3m_entries(A, B, s, rows, cols))
+
+
+def fused(ctx, s, M, N, K, variant=ozk.OZK_S2_FUSED_CRT):
+    ozk.ozk_config_set(ctx, ozk.OZK_OP_DGEMM, ozk.OZK_SCHEME2, s, M, N, K, (variant, 0, 4, 1))
+
+
+@pytest.mark.parametrize("s", [1, 7, 12, 13, 16, 17, 20])
+@pytest.mark.parametrize("shape", [(1, 1, 1), (63, 65, 127), (129, 200, 95), (70, 64, 0)])
+def test_fused_crt_bit_exact(s, shape):
+    """The GEMM with the CRT fused into it (no residue planes; 6, 8 or 10
+    16-bit pieces per CRT sum by s) equals the oracle and the separate
+    kernels, over several tiles with ragged edges and K = 0."""
+    c = ozk.Context(0)
+    try:
+        M, N, K = shape
+        A = synth.phi_matrix(M, K, 1.0, 1400 + s + M)
+        B = synth.phi_matrix(K, N, 1.0, 1500 + s + N)
+        fused(c, s, M, N, K)
+        got = host(ozk.ozk_dgemm(c, ozk.OZK_SCHEME2, s, dev(A), dev(B), C=dev(np.full((M, N), np.nan))))
+        # K = 0: the empty sum (beta = 0, so the NaNs of C are not read)
+        assert np.array_equal(got, s2.s2_dgemm(A, B, s) if K else np.zeros((M, N)))
+        fused(c, s, M, N, K, variant=3)
+        assert np.array_equal(got, host(ozk.ozk_dgemm(c, ozk.OZK_SCHEME2, s, dev(A), dev(B))))
+    finally:
+        c.close()
+
+
+def test_fused_crt_alpha_beta_edges():
+    """Zero, tiny, huge, non-finite rows and columns, subnormal and overflowing
+    products, alpha and beta: the fused epilogue rounds and scales like the
+    separate CRT kernel."""
+    s, M, N, K = 14, 70, 66, 50
+    A = synth.phi_matrix(M, K, 1.0, 11)
+    B = synth.phi_matrix(K, N, 1.0, 12)
+    C0 = synth.phi_matrix(M, N, 1.0, 13)
+    A[0] = 0
+    A[1] *= 1e-300
+    A[2] *= 1e300
+    A[3, 4] = np.inf
+    A[4] *= 1e-160
+    A[65, :4] = [5e-324, -1e-310, 0.0, 2.0 ** -1060]
+    B[:, 5] = 0
+    B[7, 6] = np.nan
+    B[:, 8] *= 1e-160
+    B[:, 64] *= 1e10
+    c = ozk.Context(0)
+    try:
+        fused(c, s, M, N, K)
+        got = host(ozk.ozk_dgemm(c, ozk.OZK_SCHEME2, s, dev(A), dev(B), C=dev(C0), alpha=-1.5, beta=0.5))
+        ref = s2.s2_dgemm(A, B, s, alpha=-1.5, beta=0.5, C=C0)
+        assert np.array_equal(np.isnan(got), np.isnan(ref))
+        ok = ~np.isnan(ref)
+        assert np.array_equal(got[ok], ref[ok])
+        got0 = host(ozk.ozk_dgemm(c, ozk.OZK_SCHEME2, s, dev(A), dev(B)))
+        ref0 = s2.s2_dgemm(A, B, s)
+        ok0 = ~np.isnan(ref0)
+        assert np.array_equal(np.isnan(got0), np.isnan(ref0)) and np.array_equal(got0[ok0], ref0[ok0])
+        assert 0 < abs(ref0[4, 8]) < np.finfo(np.float64).tiny and np.isinf(ref0[2, 64])
+    finally:
+        c.close()
+
+
+def test_fused_crt_large_sampled():
+    """8192 x 8192 x 2048 with s = 16, the shape where the residue planes are
+    largest against the GEMM: sampled outputs against the oracle and the
+    whole result against the separate kernels."""
+    M, N, K, s = 8192, 8192, 2048, 16
+    A = synth.phi_matrix(M, K, 1.0, synth.seed_for(3, M, 1.0, synth.ROLE_A))
+    B = synth.phi_matrix(K, N, 1.0, synth.seed_for(3, N, 1.0, synth.ROLE_B))
+    a, b = dev(A), dev(B)
+    c = ozk.Context(0)
+    try:
+        fused(c, s, M, N, K)
+        got = ozk.ozk_dgemm(c, ozk.OZK_SCHEME2, s, a, b)
+        fused(c, s, M, N, K, variant=3)
+        assert torch.equal(got, ozk.ozk_dgemm(c, ozk.OZK_SCHEME2, s, a, b))
+        C = host(got)
+        rng = np.random.default_rng(7)
+        rows = np.concatenate([rng.integers(0, M, 30), [0, M - 1]])
+        cols = np.concatenate([rng.integers(0, N, 30), [N - 1, 0]])
+        assert np.array_equal(C[rows, cols], s2.s2_entries(A, B, s, rows, cols))
+    finally:
+        c.close()
