@@ -33,6 +33,12 @@ INT8_PEAK_TOPS = 5000.0  # MI355X dense INT8 MFMA, TOP/s
 MEASURED_GEMM_TRAFFIC = {
     (8192, 7, (1, 0, 2, 1)): 19360901973,
 }
+# HBM bytes of the Scheme I pre-pass kernels of one call (k_s1_split_rows4,
+# k_s1_exp_cols, k_s1_split_cols, k_fill_i32), same counters and scales.
+MEASURED_PREPASS_TRAFFIC = {
+    (8192, 7): 3088509589,
+}
+HBM_PEAK_GBS = 8000.0
 
 
 def parse():
@@ -232,6 +238,8 @@ def main():
     cfg_key = None if cfg is None else (cfg["variant"], cfg["raster"], cfg["group"], cfg["split"])
     traffic = MEASURED_GEMM_TRAFFIC.get((n, p, cfg_key)) if M == N == K else None
     achieved = ops / (r["gemm_ms"] * 1e-3) / 1e12
+    # pre-pass: both operands read twice (exponents, then slices), p bytes per element written, the scales
+    pre_bytes = (16 + p) * (M * K + K * N) + 4 * (M + N)
     line = {
         "metric": "emulated FP64 TFLOP/s + %INT8-MFMA peak vs native DGEMM at rel err <=1e-13",
         "value": round(value, 3),
@@ -253,6 +261,11 @@ def main():
                      "algorithmic_ops_per_launch": ops},
         "pct_int8_peak_end_to_end": round(100.0 * ops / (r["ms"] * 1e-3) / 1e12 / INT8_PEAK_TOPS, 2),
         "prepass_ms": round(r["pre_ms"], 4),
+        "prepass_roofline": {"bound": "hbm", "achieved": round(pre_bytes / (r["pre_ms"] * 1e-3) / 1e9, 1),
+                             "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                             "frac": round(pre_bytes / (r["pre_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                             "traffic": MEASURED_PREPASS_TRAFFIC.get((n, p)) if M == N == K else None,
+                             "algorithmic_bytes": pre_bytes},
         "native_dgemm_tflops": None if native is None else round(native, 2),
         "speedup_vs_native": None if native is None else round(value / native, 3),
         "whole_call_matches_steps": same,
