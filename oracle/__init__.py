@@ -77,6 +77,8 @@ def _load():
         "orc_s1_dgemm": (I, [I64, I64, I64, I, D, P, P, D, P]),
         "orc_s1_entries": (None, [I64, I64, I64, I, D, P, P, P, P, I64, P, P, P, D, P]),
         "orc_round_scaled_parts": (D, [I64, I64, I64]),
+        "orc_round_scaled_f32_parts": (ctypes.c_float, [I64, I64, I64]),
+        "orc_s1_sgemm": (I, [I64, I64, I64, I, ctypes.c_float, P, P, ctypes.c_float, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -260,3 +262,27 @@ def k_split_s1(p: int) -> int:
 
 
 from . import scheme2, metrics, selector  # noqa: E402,F401
+
+
+def round_scaled_f32(Z: int, E: int) -> np.float32:
+    """The C oracle's RN(Z 2^E) to binary32 for |Z| < 2^127 (exposed for pinning)."""
+    lo = Z & ((1 << 64) - 1)
+    hi = Z >> 64
+    if lo >= 1 << 63:
+        lo -= 1 << 64
+    return np.float32(_load().orc_round_scaled_f32_parts(lo, hi, E))
+
+
+def s1_sgemm(A, B, p: int, alpha=1.0, beta=0.0, C=None) -> np.ndarray:
+    """Whole Scheme I SGEMM on binary32 operands: the binary64 pipeline on the
+    exactly widened operands, one rounding of Z 2^E to binary32, then
+    C = alpha * h + beta * C in binary32."""
+    A = np.ascontiguousarray(A, np.float32)
+    B = np.ascontiguousarray(B, np.float32)
+    M, K = A.shape
+    N = B.shape[1]
+    out = np.zeros((M, N), np.float32) if C is None else np.ascontiguousarray(C, np.float32).copy()
+    rc = _load().orc_s1_sgemm(M, N, K, p, float(alpha), _p(A), _p(B), float(beta), _p(out))
+    if rc != 0:
+        raise ValueError("orc_s1_sgemm failed (%d)" % rc)
+    return out

@@ -370,3 +370,97 @@ double orc_round_scaled_parts(int64_t zlo, int64_t zhi, int64_t E) {
   i128 Z = ((i128)zhi << 64) | (i128)(uint64_t)zlo;
   return orc_round_scaled(Z, E);
 }
+
+/* ------------------------------------------------------------------ */
+/* Scheme I with binary32 operands and result                          */
+/* ------------------------------------------------------------------ */
+/* The FP32-level operating points of Scheme I (the paper's low slice
+ * counts, Sec. V-D) on binary32 matrices: every binary32 value is a binary64
+ * value, so the operands are widened exactly and the exponents, slices,
+ * diagonals and Z are those of the binary64 path; only the final rounding
+ * differs: RN-even of Z 2^E to binary32 (24 significant bits, gradual
+ * underflow at 2^-149, overflow to infinity), then alpha/beta in binary32. */
+
+float orc_round_scaled_f32(i128 Z, int64_t E) {
+  if (Z == 0) return 0.0f;
+  int neg = Z < 0;
+  u128 mag = neg ? (u128)0 - (u128)Z : (u128)Z;
+  int n = 0;
+  for (u128 t = mag; t != 0; t >>= 1) ++n;
+  /* keep 24 significant bits, never below 2^-149 */
+  int64_t drop = n - 24;
+  if (-149 - E > drop) drop = -149 - E;
+  u128 q;
+  int64_t Eq = E;
+  if (drop <= 0) {
+    q = mag;
+  } else if (drop > 128) {
+    return neg ? -0.0f : 0.0f;
+  } else if (drop == 128) {
+    /* the kept part is 0; round up only above half = 2^127 */
+    q = mag > ((u128)1 << 127) ? 1 : 0;
+    Eq = E + drop;
+  } else {
+    u128 rem = mag & (((u128)1 << drop) - 1);
+    u128 half = (u128)1 << (drop - 1);
+    q = mag >> drop;
+    if (rem > half || (rem == half && (q & 1))) q += 1;
+    Eq = E + drop;
+  }
+  /* q <= 2^24 here; q 2^Eq is exact in binary32 unless it overflows */
+  if (Eq > 300) return neg ? -INFINITY : INFINITY;
+  float r = ldexpf((float)(uint64_t)q, (int)Eq);
+  return neg ? -r : r;
+}
+
+float orc_round_scaled_f32_parts(int64_t zlo, int64_t zhi, int64_t E) {
+  i128 Z = ((i128)zhi << 64) | (i128)(uint64_t)zlo;
+  return orc_round_scaled_f32(Z, E);
+}
+
+static float orc_axpby_f32(float alpha, float h, float beta, const float* c) {
+  if (beta == 0.0f) return alpha * h;
+  float bc = beta * (*c);
+  return fmaf(alpha, h, bc);
+}
+
+/* Whole Scheme I SGEMM, C = alpha*A*B + beta*C in binary32, 1 <= p <= 8. */
+int orc_s1_sgemm(int64_t M, int64_t N, int64_t K, int p, float alpha,
+                 const float* A, const float* B, float beta, float* C) {
+  if (p < 1 || p > 8) return -1;
+  double* Aw = (double*)malloc(sizeof(double) * ((size_t)M * K + 1));
+  double* Bw = (double*)malloc(sizeof(double) * ((size_t)K * N + 1));
+  int32_t* e = (int32_t*)malloc(sizeof(int32_t) * (M > 0 ? M : 1));
+  int32_t* f = (int32_t*)malloc(sizeof(int32_t) * (N > 0 ? N : 1));
+  int8_t* V = (int8_t*)malloc((size_t)p * M * K + 1);
+  int8_t* W = (int8_t*)malloc((size_t)p * K * N + 1);
+  int64_t* Cd = (int64_t*)malloc(sizeof(int64_t) * ((size_t)p * M * N + 1));
+  if (!Aw || !Bw || !e || !f || !V || !W || !Cd) {
+    free(Aw); free(Bw); free(e); free(f); free(V); free(W); free(Cd);
+    return -2;
+  }
+  for (int64_t i = 0; i < M * K; ++i) Aw[i] = (double)A[i];
+  for (int64_t i = 0; i < K * N; ++i) Bw[i] = (double)B[i];
+  orc_s1_row_exponents(M, K, Aw, e);
+  orc_s1_col_exponents(K, N, Bw, f);
+  orc_s1_digits_a(M, K, Aw, e, p, V);
+  orc_s1_digits_b(K, N, Bw, f, p, W);
+  orc_s1_diagonals(M, N, K, p, V, W, Cd);
+  for (int64_t i = 0; i < M; ++i)
+    for (int64_t j = 0; j < N; ++j) {
+      float h;
+      if (e[i] == ORC_NONFINITE_EXP || f[j] == ORC_NONFINITE_EXP) {
+        h = NAN;
+      } else if (e[i] == ORC_ZERO_EXP || f[j] == ORC_ZERO_EXP) {
+        h = 0.0f;
+      } else {
+        i128 Z = 0;
+        for (int d = 0; d < p; ++d)
+          Z += (i128)Cd[(int64_t)d * M * N + i * N + j] * ((i128)1 << (8 * (p - 1 - d)));
+        h = orc_round_scaled_f32(Z, orc_s1_scale(e[i], f[j], p));
+      }
+      C[i * N + j] = orc_axpby_f32(alpha, h, beta, &C[i * N + j]);
+    }
+  free(Aw); free(Bw); free(e); free(f); free(V); free(W); free(Cd);
+  return 0;
+}

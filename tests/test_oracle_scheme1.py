@@ -314,3 +314,62 @@ def test_error_falls_to_fp64_level_as_p_grows():
     nat = oracle.metrics.e_cw(oracle.gemm_naive(A, B), hi, lo, A, B)
     assert errs[6] < 1e-13, errs  # the 1e-13 gate from p = 7
     assert errs[7] <= 2 * nat, (errs, nat)  # within 2x of native FP64 at p = 8
+
+
+# ------------------------------------------------ binary32 operands and result
+
+def test_round_scaled_f32_matches_numpy_conversion():
+    """For |Z| < 2^53, Z 2^E is an exact binary64 value and numpy's
+    binary64 -> binary32 conversion is a correctly rounded one (ties to even,
+    gradual underflow, overflow to infinity): the oracle's direct rounding
+    must agree, including ties and the subnormal and overflow edges."""
+    rng = random.Random(11)
+    cases = [(1, -149), (1, -150), (3, -151), (2 ** 24 + 1, 0), (2 ** 24 + 3, 0), (2 ** 25 - 1, 103),
+             ((2 ** 24 - 1) * 2, 103), (2 ** 24 - 1, 104), (5, -152), (2 ** 52 + 1, -200)]
+    for _ in range(3000):
+        z = rng.randrange(1, 2 ** rng.randrange(1, 53))
+        cases.append((z, rng.randrange(-230, 110)))
+    for z, E in cases:
+        for sz in (z, -z):
+            want = np.float32(np.ldexp(np.float64(sz), E))
+            got = oracle.round_scaled_f32(sz, E)
+            assert got.tobytes() == want.tobytes(), (sz, E, got, want)
+
+
+def test_sgemm_exact_for_small_integers():
+    """Integer entries of at most 7 bits occupy the two leading digits of the
+    balanced format (slice 0 carries 6 bits and the sign), so from p = 3 on
+    every digit pair is kept; sums below 2^24 are exact binary32 values, so
+    the emulated SGEMM is the exact integer product.  Zero rows and columns
+    give zeros and a non-finite entry gives NaN in its row (A) and column
+    (B)."""
+    rng = np.random.default_rng(3)
+    for p in (3, 5, 8):
+        M, N, K = 9, 7, 40
+        A = rng.integers(-127, 128, (M, K)).astype(np.float32)
+        B = rng.integers(-127, 128, (K, N)).astype(np.float32)
+        A[2] = 0
+        B[:, 3] = 0
+        want = (A.astype(np.int64) @ B.astype(np.int64)).astype(np.float32)
+        assert np.array_equal(oracle.s1_sgemm(A, B, p), want)
+        assert np.array_equal(oracle.s1_sgemm(A, B, p, alpha=2.0), 2 * want)
+        A[4, 5] = np.inf
+        B[6, 1] = np.nan
+        got = oracle.s1_sgemm(A, B, p)
+        bad = np.zeros((M, N), bool)
+        bad[4, :] = True
+        bad[:, 1] = True
+        assert np.isnan(got[bad]).all() and np.array_equal(got[~bad], want[~bad])
+
+
+def test_sgemm_is_the_binary64_result_rounded_once():
+    """The binary32 result is the exact Z 2^E rounded once; rounding the
+    binary64 path's result again can differ only by double rounding, i.e. by
+    at most one binary32 ulp, and only rarely."""
+    A = synth.phi_matrix(60, 90, 1.0, 21).astype(np.float32)
+    B = synth.phi_matrix(90, 50, 1.0, 22).astype(np.float32)
+    for p in (1, 2, 3, 4, 6):
+        got = oracle.s1_sgemm(A, B, p)
+        twice = oracle.s1_dgemm(A.astype(np.float64), B.astype(np.float64), p).astype(np.float32)
+        diff = got.view(np.int32).astype(np.int64) - twice.view(np.int32).astype(np.int64)
+        assert np.abs(diff).max() <= 1 and np.count_nonzero(diff) <= got.size // 100, p
