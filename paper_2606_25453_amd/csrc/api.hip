@@ -309,7 +309,7 @@ ozk_status ozk_s1_split_cols(ozk_ctx* ctx, int p, int64_t K, int64_t cols, const
 static ozk_status s1_gemm_common(ozk_ctx* ctx, int p, int64_t M, int64_t N, int64_t K, const int8_t* Ap,
                                  const int32_t* e, const int8_t* Bp, const int32_t* f, double alpha,
                                  double beta, double* C, int64_t ldc, void* ws, size_t ws_bytes,
-                                 int32_t* diag, hipStream_t stream, ozk_gemm_config cfg) {
+                                 int32_t* diag, hipStream_t stream, ozk_gemm_config cfg, float* C32 = nullptr) {
   if (diag) cfg = default_config();
   const S1Plan pl = s1_plan(ctx, p, M, N, K, cfg.split);
   ozk::S1GemmArgs g;
@@ -331,6 +331,7 @@ static ozk_status s1_gemm_common(ozk_ctx* ctx, int p, int64_t M, int64_t N, int6
   g.ldc = ldc;
   g.zpart = nullptr;
   g.diag = diag;
+  g.C32 = C32;
   if (!diag && pl.nsplit > 1) {
     const size_t need = 16 * (size_t)pl.nsplit * M * N;
     if (!ws || ws_bytes < need) return fail(ctx, OZK_ERR_WORKSPACE, 15);
@@ -425,6 +426,36 @@ ozk_status ozk_dgemm(ozk_ctx* ctx, ozk_scheme scheme, int p_or_s, int64_t M, int
   if (err != hipSuccess) return hip_status(ctx, err);
   return s1_gemm_common(ctx, p, M, N, K, Ap, e, Bp, f, alpha, beta, C, ldc, w + pl.off_z,
                         pl.total - pl.off_z, nullptr, stream, cfg);
+}
+
+ozk_status ozk_sgemm(ozk_ctx* ctx, int p, int64_t M, int64_t N, int64_t K, float alpha, const float* A,
+                     int64_t lda, const float* B, int64_t ldb, float beta, float* C, int64_t ldc, void* ws,
+                     size_t ws_bytes, hipStream_t stream) {
+  if (!ctx) return OZK_ERR_INVALID_ARG;
+  ctx->last_arg = 0;
+  if (p < 1 || p > OZK_MAX_P) return fail(ctx, OZK_ERR_UNSUPPORTED, 2);
+  if (bad_dims(M, N, K)) return fail(ctx, OZK_ERR_INVALID_ARG, M < 0 ? 3 : (N < 0 ? 4 : 5));
+  if (!A && M > 0 && K > 0) return fail(ctx, OZK_ERR_INVALID_ARG, 7);
+  if (lda < (K > 0 ? K : 1)) return fail(ctx, OZK_ERR_INVALID_ARG, 8);
+  if (!B && K > 0 && N > 0) return fail(ctx, OZK_ERR_INVALID_ARG, 9);
+  if (ldb < (N > 0 ? N : 1)) return fail(ctx, OZK_ERR_INVALID_ARG, 10);
+  if (!C && M > 0 && N > 0) return fail(ctx, OZK_ERR_INVALID_ARG, 12);
+  if (ldc < (N > 0 ? N : 1)) return fail(ctx, OZK_ERR_INVALID_ARG, 13);
+  // the GEMM step is the DGEMM one (same packed operands), so it shares its configurations
+  const ozk_gemm_config cfg = config_for(ctx, OZK_OP_DGEMM, OZK_SCHEME1, p, M, N, K);
+  const S1Plan pl = s1_plan(ctx, p, M, N, K, cfg.split);
+  if (!ws || ws_bytes < pl.total) return fail(ctx, OZK_ERR_WORKSPACE, 14);
+  if (M == 0 || N == 0) return OZK_OK;
+  char* w = (char*)ws;
+  int32_t* e = (int32_t*)(w + pl.off_e);
+  int32_t* f = (int32_t*)(w + pl.off_f);
+  int8_t* Ap = (int8_t*)(w + pl.off_a);
+  int8_t* Bp = (int8_t*)(w + pl.off_b);
+  hipError_t err = ozk::s1_split_rows(p, A, lda, M, K, e, Ap, stream);
+  if (err == hipSuccess) err = ozk::s1_split_cols(p, B, ldb, K, N, f, Bp, stream);
+  if (err != hipSuccess) return hip_status(ctx, err);
+  return s1_gemm_common(ctx, p, M, N, K, Ap, e, Bp, f, alpha, beta, nullptr, ldc, w + pl.off_z, pl.total - pl.off_z,
+                        nullptr, stream, cfg, C);
 }
 
 ozk_status ozk_zgemm_3m(ozk_ctx* ctx, int s, int64_t M, int64_t N, int64_t K, const double* alpha,

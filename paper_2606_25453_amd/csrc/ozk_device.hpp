@@ -103,6 +103,46 @@ __device__ __forceinline__ double round_mag(u128 mag, bool neg, int E) {
   return neg ? -r : r;
 }
 
+// The same single rounding to binary32 (24 significant bits, gradual
+// underflow at 2^-149, overflow to infinity).
+__device__ __forceinline__ float round_mag_f32(u128 mag, bool neg, int E) {
+  if (mag == 0) return 0.0f;
+  const uint64_t hi = (uint64_t)(mag >> 64), lo = (uint64_t)mag;
+  const int n = hi ? 128 - __clzll(hi) : 64 - __clzll(lo);
+  if (n + E >= -125) {
+    // normal or overflowing: top 64 bits with a sticky bit, one RN-even
+    // conversion to binary32, an exact scaling
+    const int sh = n > 64 ? n - 64 : 0;
+    const uint64_t w = sh ? (uint64_t)(mag >> sh) | (uint64_t)((lo << (64 - sh)) != 0) : lo;
+    const float r = ldexpf((float)w, E + sh);
+    return neg ? -r : r;
+  }
+  // subnormal: round at the fixed position 2^-149
+  int drop = n - 24;
+  if (-149 - E > drop) drop = -149 - E;
+  uint64_t q;
+  if (drop <= 0) {
+    q = lo;  // n <= 24
+    drop = 0;
+  } else if (drop >= 128) {
+    if (drop > 128) return neg ? -0.0f : 0.0f;
+    q = (mag > ((u128)1 << 127)) ? 1 : 0;
+  } else {
+    const u128 qq = mag >> drop;
+    const u128 rem = mag & (((u128)1 << drop) - 1);
+    const u128 half = (u128)1 << (drop - 1);
+    q = (uint64_t)qq;
+    if (rem > half || (rem == half && (q & 1))) q += 1;
+  }
+  const float r = ldexpf((float)q, E + drop);
+  return neg ? -r : r;
+}
+
+__device__ __forceinline__ float round_scaled_f32(i128 Z, int E) {
+  const bool neg = Z < 0;
+  return round_mag_f32(neg ? (u128)0 - (u128)Z : (u128)Z, neg, E);
+}
+
 __device__ __forceinline__ double round_scaled(i128 Z, int E) {
   const bool neg = Z < 0;
   return round_mag(neg ? (u128)0 - (u128)Z : (u128)Z, neg, E);
@@ -114,6 +154,12 @@ __device__ __forceinline__ double axpby(double alpha, double h, double beta, con
   if (beta == 0.0) return alpha * h;
   const double bc = beta * (*c);
   return __fma_rn(alpha, h, bc);
+}
+
+__device__ __forceinline__ float axpby_f32(float alpha, float h, float beta, const float* c) {
+  if (beta == 0.0f) return alpha * h;
+  const float bc = beta * (*c);
+  return __fmaf_rn(alpha, h, bc);
 }
 
 // Maximum / sum over each aligned group of 16 lanes.

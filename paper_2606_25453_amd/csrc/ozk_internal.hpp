@@ -22,6 +22,7 @@ struct S1GemmArgs {
   double* C;
   int64_t ldc;
   int64_t* zpart;  // nsplit x M x N x 2 int64 when nsplit > 1
+  float* C32 = nullptr;  // binary32 output instead of C (alpha, beta then hold binary32 values)
   int32_t* diag;   // p x M x N int32 for the check entry point, else null
   int variant = 0;  // tile variant (0 .. OZK_S1_VARIANTS - 1)
   int raster = 0;   // 0: XCD-aware tile order, 1: plain
@@ -31,6 +32,11 @@ struct S1GemmArgs {
 hipError_t s1_split_rows(int p, const double* X, int64_t ldx, int64_t rows, int64_t K, int32_t* e,
                          int8_t* packed, hipStream_t st);
 hipError_t s1_split_cols(int p, const double* X, int64_t ldx, int64_t K, int64_t cols, int32_t* f,
+                         int8_t* packed, hipStream_t st);
+// binary32 operands (each entry widened exactly to binary64 on load)
+hipError_t s1_split_rows(int p, const float* X, int64_t ldx, int64_t rows, int64_t K, int32_t* e,
+                         int8_t* packed, hipStream_t st);
+hipError_t s1_split_cols(int p, const float* X, int64_t ldx, int64_t K, int64_t cols, int32_t* f,
                          int8_t* packed, hipStream_t st);
 hipError_t s1_gemm(int p, const S1GemmArgs& g, hipStream_t st);
 // slice count read from device memory (selector output)

@@ -24,7 +24,7 @@ struct S1Cfg {
   static constexpr int NS = (P <= 2 ? 4 : 3) - (V & 1);
 };
 
-enum S1Out { S1_OUT_FINAL = 0, S1_OUT_PARTIAL = 1, S1_OUT_DIAG = 2 };
+enum S1Out { S1_OUT_FINAL = 0, S1_OUT_PARTIAL = 1, S1_OUT_DIAG = 2, S1_OUT_FINAL_F32 = 3 };
 
 struct S1KArgs {
   const int8_t* Ap;
@@ -38,6 +38,7 @@ struct S1KArgs {
   int64_t ldc;
   int64_t* zpart;
   int32_t* diag;
+  float* C32;
   const int32_t* p_dev;  // slice count chosen on the device; the kernel runs only if it equals P (null: always)
   int raster, group;     // workgroup -> tile order
 };
@@ -80,6 +81,13 @@ __device__ __forceinline__ void s1_gemm_tile(const S1KArgs& g, int64_t tile, int
     const int er = g.e_row[row], fc = g.f_col[col];
     const bool bad = er == OZK_EXP_NONFINITE || fc == OZK_EXP_NONFINITE;
     const bool live = !bad && er != OZK_EXP_ZERO && fc != OZK_EXP_ZERO;
+    if (OUT == S1_OUT_FINAL_F32) {
+      float h = round_scaled_f32(Z, live ? er + fc - 12 - 8 * (P - 1) : 0);
+      h = bad ? __builtin_nanf("") : h;
+      float* cp = g.C32 + row * g.ldc + col;
+      *cp = axpby_f32((float)g.alpha, h, (float)g.beta, cp);
+      return;
+    }
     double h = round_scaled(Z, live ? er + fc - 12 - 8 * (P - 1) : 0);
     h = bad ? __builtin_nan("") : h;
     double* cp = g.C + row * g.ldc + col;
@@ -133,6 +141,7 @@ hipError_t s1_launch_pov(const S1GemmArgs& g, const int32_t* p_dev, hipStream_t 
   k.ldc = g.ldc;
   k.zpart = g.zpart;
   k.diag = g.diag;
+  k.C32 = g.C32;
   k.p_dev = p_dev;
   k.raster = g.raster;
   k.group = g.group;
@@ -156,6 +165,8 @@ hipError_t s1_gemm_launch(int out, const S1GemmArgs& g, const int32_t* p_dev, hi
   }
   if (out == S1_OUT_PARTIAL) {
     OZK_S1_VARIANT_CASES(S1_OUT_PARTIAL)
+  } else if (out == S1_OUT_FINAL_F32) {
+    OZK_S1_VARIANT_CASES(S1_OUT_FINAL_F32)
   } else {
     OZK_S1_VARIANT_CASES(S1_OUT_FINAL)
   }

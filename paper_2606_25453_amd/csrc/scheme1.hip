@@ -99,15 +99,15 @@ __device__ __forceinline__ void s1_slice_row(const double* __restrict__ xr, int6
 // quarter lines.  Rows past `rows` (whole 16-lane groups) write zeros; the
 // loads of every lane are issued whatever its row, so that all lanes take
 // the same path through the shuffles.
-template <int P>
-__global__ __launch_bounds__(256) void k_s1_split_rows4(const double* __restrict__ X, int64_t ldx,
+template <int P, typename T>
+__global__ __launch_bounds__(256) void k_s1_split_rows4(const T* __restrict__ X, int64_t ldx,
                                                         int64_t rows, int64_t K, int64_t Kp,
                                                         int64_t rows_packed, int32_t* __restrict__ e_out,
                                                         int8_t* __restrict__ packed) {
   const int lane = threadIdx.x & 63, q = lane & 15;
   const int64_t r = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 4 + (lane >> 4);
   const bool in = r < rows;
-  const double* xr = X + (in ? r : 0) * ldx;  // rows past the end load row 0 and discard it
+  const T* xr = X + (in ? r : 0) * ldx;  // rows past the end load row 0 and discard it
   int e = OZK_EXP_ZERO;
   for (int64_t k0 = 8 * q; k0 < K; k0 += 128) {
     double v[8];
@@ -183,7 +183,8 @@ __global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v) {
 }
 
 // Column exponents: thread j scans a run of 256 rows of column j.
-__global__ __launch_bounds__(256) void k_s1_exp_cols(const double* __restrict__ X, int64_t ldx,
+template <typename T>
+__global__ __launch_bounds__(256) void k_s1_exp_cols(const T* __restrict__ X, int64_t ldx,
                                                      int64_t K, int64_t cols, int32_t* __restrict__ f) {
   const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (j >= cols) return;
@@ -192,7 +193,7 @@ __global__ __launch_bounds__(256) void k_s1_exp_cols(const double* __restrict__ 
   int e = OZK_EXP_ZERO;
 #pragma unroll 8
   for (int64_t k = k0; k < k1; ++k) {
-    const int ek = expo_of(X[k * ldx + j]);
+    const int ek = expo_of((double)X[k * ldx + j]);
     e = ek > e ? ek : e;
   }
   if (e != OZK_EXP_ZERO) atomicMax(&f[j], e);
@@ -203,15 +204,15 @@ __global__ __launch_bounds__(256) void k_s1_exp_cols(const double* __restrict__ 
 // (consecutive threads write consecutive 32-byte lines).  Columns past
 // `cols`, zero or non-finite columns and k past K are zero; only the chunk
 // that straddles K takes the guarded path.
-template <int P>
-__device__ __forceinline__ void s1_slice_col(const double* __restrict__ X, int64_t ldx, int64_t K, int64_t cols,
+template <int P, typename T>
+__device__ __forceinline__ void s1_slice_col(const T* __restrict__ X, int64_t ldx, int64_t K, int64_t cols,
                                              int64_t cols_packed, const int32_t* __restrict__ f,
                                              int8_t* __restrict__ packed, int64_t j, int64_t c) {
   const int e = j < cols ? f[j] : OZK_EXP_ZERO;
   const int64_t kb = c * OZK_K_CHUNK;
   uint32_t word[8][P];
   if (live_exponent(e) && kb + OZK_K_CHUNK <= K) {
-    const double* x = X + kb * ldx + j;
+    const T* x = X + kb * ldx + j;
     double v[8][4];  // all 32 loads first
 #pragma unroll
     for (int g = 0; g < 8; ++g)
@@ -244,14 +245,14 @@ __device__ __forceinline__ void s1_slice_col(const double* __restrict__ X, int64
   }
 }
 
-template <int P>
-__global__ __launch_bounds__(256) void k_s1_split_cols(const double* __restrict__ X, int64_t ldx,
+template <int P, typename T>
+__global__ __launch_bounds__(256) void k_s1_split_cols(const T* __restrict__ X, int64_t ldx,
                                                        int64_t K, int64_t cols, int64_t Kp,
                                                        int64_t cols_packed, const int32_t* __restrict__ f,
                                                        int8_t* __restrict__ packed) {
   const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (j >= cols_packed) return;
-  s1_slice_col<P>(X, ldx, K, cols, cols_packed, f, packed, j, blockIdx.y);
+  s1_slice_col<P, T>(X, ldx, K, cols, cols_packed, f, packed, j, blockIdx.y);
 }
 
 __global__ __launch_bounds__(256) void k_s1_split_cols_auto(const double* __restrict__ X, int64_t ldx, int64_t K,
@@ -275,11 +276,13 @@ __global__ __launch_bounds__(256) void k_s1_split_cols_auto(const double* __rest
 }
 
 // Exact fold of the K-run partials followed by the single rounding.
+// TO = float: the binary32 rounding and update (alpha, beta hold binary32 values).
+template <typename TO>
 __global__ __launch_bounds__(256) void k_s1_fold(const int64_t* __restrict__ zpart, int nsplit, int M, int N,
                                                  int p, const int32_t* __restrict__ p_dev,
                                                  const int32_t* __restrict__ e_row,
                                                  const int32_t* __restrict__ f_col, double alpha,
-                                                 double beta, double* __restrict__ C, int64_t ldc) {
+                                                 double beta, TO* __restrict__ C, int64_t ldc) {
   if (p_dev) p = *p_dev;
   if (p < 1) return;  // Scheme II was chosen
   const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -291,45 +294,51 @@ __global__ __launch_bounds__(256) void k_s1_fold(const int64_t* __restrict__ zpa
     Z += ((i128)zp[1] << 64) | (i128)(uint64_t)zp[0];
   }
   const int er = e_row[row], fc = f_col[col];
-  double h;
-  if (er == OZK_EXP_NONFINITE || fc == OZK_EXP_NONFINITE) h = __builtin_nan("");
-  else if (er == OZK_EXP_ZERO || fc == OZK_EXP_ZERO) h = 0.0;
-  else h = round_scaled(Z, er + fc - 12 - 8 * (p - 1));
-  double* cp = C + row * ldc + col;
-  *cp = axpby(alpha, h, beta, cp);
+  const bool bad = er == OZK_EXP_NONFINITE || fc == OZK_EXP_NONFINITE;
+  const bool zero = er == OZK_EXP_ZERO || fc == OZK_EXP_ZERO;
+  const int E = er + fc - 12 - 8 * (p - 1);
+  TO* cp = C + row * ldc + col;
+  if constexpr (sizeof(TO) == 4) {
+    const float h = bad ? __builtin_nanf("") : zero ? 0.0f : round_scaled_f32(Z, E);
+    *cp = axpby_f32((float)alpha, h, (float)beta, cp);
+  } else {
+    const double h = bad ? __builtin_nan("") : zero ? 0.0 : round_scaled(Z, E);
+    *cp = axpby(alpha, h, beta, cp);
+  }
 }
 
 // ------------------------------------------------------------- launchers
 
-template <int P>
-static hipError_t launch_split_rows(const double* X, int64_t ldx, int64_t rows, int64_t K, int32_t* e,
+template <int P, typename T>
+static hipError_t launch_split_rows(const T* X, int64_t ldx, int64_t rows, int64_t K, int32_t* e,
                                     int8_t* packed, hipStream_t st) {
   const int64_t rp = round_up(rows, OZK_ROW_ALIGN), kp = round_up(K, OZK_K_CHUNK);
   if (rp == 0) return hipSuccess;  // with K == 0 the launch still writes the exponents
-  hipLaunchKernelGGL(k_s1_split_rows4<P>, dim3((unsigned)(rp / 16)), dim3(256), 0, st, X, ldx, rows, K, kp, rp, e,
-                     packed);
+  hipLaunchKernelGGL((k_s1_split_rows4<P, T>), dim3((unsigned)(rp / 16)), dim3(256), 0, st, X, ldx, rows, K, kp,
+                     rp, e, packed);
   return hipGetLastError();
 }
 
-template <int P>
-static hipError_t launch_split_cols(const double* X, int64_t ldx, int64_t K, int64_t cols, int32_t* f,
+template <int P, typename T>
+static hipError_t launch_split_cols(const T* X, int64_t ldx, int64_t K, int64_t cols, int32_t* f,
                                     int8_t* packed, hipStream_t st) {
   const int64_t cp = round_up(cols, OZK_ROW_ALIGN), kp = round_up(K, OZK_K_CHUNK);
   if (cols > 0) {
     hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((cols + 255) / 256)), dim3(256), 0, st, f, cols,
                        (int32_t)OZK_EXP_ZERO);
     if (K > 0)
-      hipLaunchKernelGGL(k_s1_exp_cols, dim3((unsigned)((cols + 255) / 256), (unsigned)((K + 255) / 256)),
+      hipLaunchKernelGGL(k_s1_exp_cols<T>, dim3((unsigned)((cols + 255) / 256), (unsigned)((K + 255) / 256)),
                          dim3(256), 0, st, X, ldx, K, cols, f);
   }
   if (cp > 0 && kp > 0)
-    hipLaunchKernelGGL(k_s1_split_cols<P>, dim3((unsigned)(cp / 256), (unsigned)(kp / OZK_K_CHUNK)), dim3(256),
-                       0, st, X, ldx, K, cols, kp, cp, f, packed);
+    hipLaunchKernelGGL((k_s1_split_cols<P, T>), dim3((unsigned)(cp / 256), (unsigned)(kp / OZK_K_CHUNK)),
+                       dim3(256), 0, st, X, ldx, K, cols, kp, cp, f, packed);
   return hipGetLastError();
 }
 
-hipError_t s1_split_rows(int p, const double* X, int64_t ldx, int64_t rows, int64_t K, int32_t* e,
-                         int8_t* packed, hipStream_t st) {
+template <typename T>
+static hipError_t split_rows_any(int p, const T* X, int64_t ldx, int64_t rows, int64_t K, int32_t* e,
+                                 int8_t* packed, hipStream_t st) {
   switch (p) {
     case 1: return launch_split_rows<1>(X, ldx, rows, K, e, packed, st);
     case 2: return launch_split_rows<2>(X, ldx, rows, K, e, packed, st);
@@ -343,8 +352,9 @@ hipError_t s1_split_rows(int p, const double* X, int64_t ldx, int64_t rows, int6
   return hipErrorInvalidValue;
 }
 
-hipError_t s1_split_cols(int p, const double* X, int64_t ldx, int64_t K, int64_t cols, int32_t* f,
-                         int8_t* packed, hipStream_t st) {
+template <typename T>
+static hipError_t split_cols_any(int p, const T* X, int64_t ldx, int64_t K, int64_t cols, int32_t* f,
+                                 int8_t* packed, hipStream_t st) {
   switch (p) {
     case 1: return launch_split_cols<1>(X, ldx, K, cols, f, packed, st);
     case 2: return launch_split_cols<2>(X, ldx, K, cols, f, packed, st);
@@ -356,6 +366,26 @@ hipError_t s1_split_cols(int p, const double* X, int64_t ldx, int64_t K, int64_t
     case 8: return launch_split_cols<8>(X, ldx, K, cols, f, packed, st);
   }
   return hipErrorInvalidValue;
+}
+
+hipError_t s1_split_rows(int p, const double* X, int64_t ldx, int64_t rows, int64_t K, int32_t* e,
+                         int8_t* packed, hipStream_t st) {
+  return split_rows_any(p, X, ldx, rows, K, e, packed, st);
+}
+
+hipError_t s1_split_rows(int p, const float* X, int64_t ldx, int64_t rows, int64_t K, int32_t* e,
+                         int8_t* packed, hipStream_t st) {
+  return split_rows_any(p, X, ldx, rows, K, e, packed, st);
+}
+
+hipError_t s1_split_cols(int p, const double* X, int64_t ldx, int64_t K, int64_t cols, int32_t* f,
+                         int8_t* packed, hipStream_t st) {
+  return split_cols_any(p, X, ldx, K, cols, f, packed, st);
+}
+
+hipError_t s1_split_cols(int p, const float* X, int64_t ldx, int64_t K, int64_t cols, int32_t* f,
+                         int8_t* packed, hipStream_t st) {
+  return split_cols_any(p, X, ldx, K, cols, f, packed, st);
 }
 
 static hipError_t gemm_launch(int p, int out, const S1GemmArgs& g, const int32_t* p_dev, hipStream_t st) {
@@ -374,8 +404,12 @@ static hipError_t gemm_launch(int p, int out, const S1GemmArgs& g, const int32_t
 
 static hipError_t launch_fold(int p, const int32_t* p_dev, const S1GemmArgs& g, hipStream_t st) {
   const int64_t n = g.M * g.N;
-  hipLaunchKernelGGL(k_s1_fold, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, g.zpart, (int)g.nsplit,
-                     (int)g.M, (int)g.N, p, p_dev, g.e, g.f, g.alpha, g.beta, g.C, g.ldc);
+  if (g.C32)
+    hipLaunchKernelGGL(k_s1_fold<float>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, g.zpart,
+                       (int)g.nsplit, (int)g.M, (int)g.N, p, p_dev, g.e, g.f, g.alpha, g.beta, g.C32, g.ldc);
+  else
+    hipLaunchKernelGGL(k_s1_fold<double>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, g.zpart,
+                       (int)g.nsplit, (int)g.M, (int)g.N, p, p_dev, g.e, g.f, g.alpha, g.beta, g.C, g.ldc);
   return hipGetLastError();
 }
 
@@ -386,7 +420,7 @@ hipError_t s1_gemm(int p, const S1GemmArgs& g, hipStream_t st) {
     hipError_t err = gemm_launch(p, S1_OUT_PARTIAL, g, nullptr, st);
     return err == hipSuccess ? launch_fold(p, nullptr, g, st) : err;
   }
-  return gemm_launch(p, S1_OUT_FINAL, g, nullptr, st);
+  return gemm_launch(p, g.C32 ? S1_OUT_FINAL_F32 : S1_OUT_FINAL, g, nullptr, st);
 }
 
 // ---------------------------------------------------- slice count on device

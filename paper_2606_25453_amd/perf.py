@@ -5,6 +5,8 @@
 Workloads (inputs resident in HBM, every kernel of the call timed with HIP
 events on the launch stream, after untimed warm-up calls and tuning):
 * Scheme I DGEMM, square n in {4096, 8192}, p in {6, 7, 8};
+* Scheme I SGEMM (binary32 in and out), square n in {4096, 8192}, p in {2, 3, 4},
+  against native float32 torch.matmul;
 * Scheme II DGEMM 4096^3 and 8192 x 8192 x 2048, s in {14, 16};
 * Scheme II 3M ZGEMM 4096^3 and 8192^3, s = 16;
 * Scheme II DGEMM with the CRT fused into the GEMM against the separate
@@ -81,6 +83,34 @@ def scheme1(torch, ctx, n, p, reps, inputs=None):
             "tflops": round(2.0 * n ** 3 / ms / 1e9, 3), "gemm_ms": round(gemm_ms, 4),
             "int8_ops": ops, "gemm_frac_int8_peak": round(ops / gemm_ms / 1e9 / INT8_PEAK_TOPS, 4),
             "native_tflops": round(2.0 * n ** 3 / ms_nat / 1e9, 3)}
+
+
+def sgemm(torch, ctx, n, p, reps, inputs=None):
+    """Scheme I SGEMM (binary32 in and out) against native float32
+    torch.matmul (TF32 off).  The GEMM step is the DGEMM one, so its size
+    class is tuned on the widened operands."""
+    import synth
+    dev = "cuda:0"
+    if inputs is None:
+        A = torch.from_numpy(synth.phi_matrix(n, n, 1.0, synth.seed_for(2, n, 1.0, synth.ROLE_A))).to(dev)
+        B = torch.from_numpy(synth.phi_matrix(n, n, 1.0, synth.seed_for(2, n, 1.0, synth.ROLE_B))).to(dev)
+    else:
+        A, B = inputs
+    A32, B32 = A.float(), B.float()
+    A64, B64 = A32.double(), B32.double()
+    _, cfg, gemm_ms = ozk.ozk_tune(ctx, ozk.OZK_OP_DGEMM, ozk.OZK_SCHEME1, p, A64, B64, reps=2)
+    del A64, B64
+    C = torch.empty((n, n), dtype=torch.float32, device=dev)
+    ws = torch.empty(ozk.ozk_workspace_size(ctx, ozk.OZK_OP_DGEMM, ozk.OZK_SCHEME1, n, n, n, p), dtype=torch.uint8,
+                     device=dev)
+    ms = time_call(torch, lambda: ozk.ozk_sgemm(ctx, p, A32, B32, C, ws=ws), reps)
+    torch.backends.cuda.matmul.allow_tf32 = False
+    ms_nat = time_call(torch, lambda: torch.matmul(A32, B32, out=C), reps)
+    ops = p * (p + 1) * n ** 3
+    return {"path": "scheme1_sgemm", "M": n, "N": n, "K": n, "p": p, "config": cfg, "ms": round(ms, 4),
+            "tflops": round(2.0 * n ** 3 / ms / 1e9, 3), "gemm_ms": round(gemm_ms, 4),
+            "int8_ops": ops, "gemm_frac_int8_peak": round(ops / gemm_ms / 1e9 / INT8_PEAK_TOPS, 4),
+            "native_fp32_tflops": round(2.0 * n ** 3 / ms_nat / 1e9, 3)}
 
 
 def scheme2(torch, ctx, M, N, K, s, cplx, reps, inputs=None):
@@ -204,7 +234,7 @@ def main():
     ap.add_argument("--quick", action="store_true", help="the smaller sizes only")
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--out", default=None, help="also append the lines to this file")
-    ap.add_argument("--only", default=None, help="comma-separated subset of s1, s2, fused, batch, auto")
+    ap.add_argument("--only", default=None, help="comma-separated subset of s1, sgemm, s2, fused, batch, auto")
     ap.add_argument("--sweep", action="store_true", help="the size sweeps instead of the default workloads")
     args = ap.parse_args()
     import torch
@@ -220,11 +250,13 @@ def main():
     jobs += [("s2", 8192, 8192, 2048, s, False) for s in (14, 16)]
     jobs += [("s2", 4096, 4096, 4096, 16, True)]
     jobs += [("fused", 4096, 4096, 4096, 14), ("fused", 8192, 8192, 2048, 16)]
+    jobs += [("sgemm", 4096, p) for p in (2, 3, 4)]
     jobs += [("batch", 256, 16)]
     jobs += [("auto", 4096, 1e-13)]
     if not args.quick:
         jobs += [("auto", 8192, 1e-13)]
         jobs += [("s1", 8192, p) for p in (6, 7, 8)]
+        jobs += [("sgemm", 8192, p) for p in (2, 3, 4)]
         jobs += [("s2", 8192, 8192, 8192, 16, True)]
     if args.only:
         keep = set(args.only.split(","))
@@ -239,6 +271,8 @@ def main():
             r = auto(torch, actx, job[1], job[2], args.reps)
         elif job[0] == "fused":
             r = fused_crt(torch, ctx, job[1], job[2], job[3], job[4], args.reps)
+        elif job[0] == "sgemm":
+            r = sgemm(torch, ctx, job[1], job[2], args.reps)
         else:
             r = batch(torch, ctx, job[1], job[2], args.reps)
         line = json.dumps(r)
@@ -258,12 +292,13 @@ def sweep(torch, ctx, args):
     jobs += [("s2", 8192, 8192, 2048, s, False) for s in (8, 10, 12, 14, 16)]
     jobs += [("s2", n, n, n, 16, True) for n in (2048, 4096, 8192)]
     jobs += [("s2", 16384, 16384, 16384, 15, False), ("s2", 16384, 16384, 16384, 15, True)]
+    jobs += [("sgemm", n, p) for n in (4096, 8192, 16384) for p in (1, 2, 3, 4)]
     if args.only:
         keep = set(args.only.split(","))
         jobs = [j for j in jobs if j[0] in keep]
     key, inputs = None, None
     for job in jobs:
-        shape = (job[1], job[1], job[1], False) if job[0] == "s1" else job[1:4] + (job[5],)
+        shape = (job[1], job[1], job[1], False) if job[0] in ("s1", "sgemm") else job[1:4] + (job[5],)
         if shape != key:
             inputs = None
             torch.cuda.empty_cache()
@@ -272,6 +307,8 @@ def sweep(torch, ctx, args):
             key = shape
         if job[0] == "s1":
             r = scheme1(torch, ctx, job[1], job[2], args.reps, inputs)
+        elif job[0] == "sgemm":
+            r = sgemm(torch, ctx, job[1], job[2], args.reps, inputs)
         else:
             r = scheme2(torch, ctx, job[1], job[2], job[3], job[4], job[5], args.reps, inputs)
         r["inputs"] = "device phi = 1"

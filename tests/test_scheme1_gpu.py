@@ -269,3 +269,90 @@ def test_large_sampled_bit_exact(ctx, n, p):
     assert err < 1e-13
     if p == 8:
         assert err <= 2 * err_nat, (err, err_nat)
+
+
+# ------------------------------------------------ binary32 operands and result
+
+def f32(x):
+    return np.ascontiguousarray(x, np.float32)
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4, 6, 8])
+@pytest.mark.parametrize("shape", SHAPES)
+def test_sgemm_bit_exact(ctx, p, shape):
+    """ozk_sgemm (binary32 in and out) equals the oracle bit for bit over
+    several tiles with ragged edges."""
+    M, N, K = shape
+    A = f32(synth.phi_matrix(M, K, 1.0, 6000 + 10 * p + M))
+    B = f32(synth.phi_matrix(K, N, 1.0, 6100 + 10 * p + N))
+    C = host(ozk.ozk_sgemm(ctx, p, dev(A), dev(B), C=dev(np.full((M, N), np.nan, np.float32))))
+    assert C.dtype == np.float32 and np.array_equal(C, oracle.s1_sgemm(A, B, p))
+
+
+def test_sgemm_edges_alpha_beta_and_empty(ctx):
+    """Zero, tiny (binary32 subnormal) and huge rows, products that underflow
+    to binary32 subnormals or overflow to infinity, non-finite entries,
+    alpha/beta, and K = 0."""
+    p, M, N, K = 4, 70, 66, 50
+    A = f32(synth.phi_matrix(M, K, 1.0, 31))
+    B = f32(synth.phi_matrix(K, N, 1.0, 32))
+    C0 = f32(synth.phi_matrix(M, N, 1.0, 33))
+    A[0] = 0
+    A[1] *= np.float32(1e-38)
+    A[2] *= np.float32(1e30)
+    A[3, 4] = np.inf
+    A[4, :3] = [1e-45, -3e-44, 0.0]
+    A[65] *= np.float32(1e-20)
+    B[:, 5] = 0
+    B[7, 6] = np.nan
+    B[:, 8] *= np.float32(1e-20)
+    B[:, 64] *= np.float32(1e20)
+    got = host(ozk.ozk_sgemm(ctx, p, dev(A), dev(B), C=dev(C0), alpha=-1.5, beta=0.5))
+    ref = oracle.s1_sgemm(A, B, p, alpha=-1.5, beta=0.5, C=C0)
+    assert np.array_equal(np.isnan(got), np.isnan(ref))
+    ok = ~np.isnan(ref)
+    assert np.array_equal(got[ok], ref[ok])
+    got0 = host(ozk.ozk_sgemm(ctx, p, dev(A), dev(B)))
+    ref0 = oracle.s1_sgemm(A, B, p)
+    ok0 = ~np.isnan(ref0)
+    assert np.array_equal(np.isnan(got0), np.isnan(ref0)) and np.array_equal(got0[ok0], ref0[ok0])
+    assert 0 < abs(ref0[65, 8]) < np.finfo(np.float32).tiny and np.isinf(ref0[2, 64])
+    C = dev(np.full((5, 3), 7.0, np.float32))
+    ozk.ozk_sgemm(ctx, p, dev(np.ones((5, 0), np.float32)), dev(np.ones((0, 3), np.float32)), C=C)
+    assert np.array_equal(host(C), np.zeros((5, 3), np.float32))
+
+
+def test_sgemm_k_runs_and_configs(ctx):
+    """The K split (128-bit partials folded exactly, then the binary32
+    rounding) and every tile variant give the same binary32 result."""
+    p, M, N, K = 3, 130, 70, 700
+    A = f32(synth.phi_matrix(M, K, 1.0, 41))
+    B = f32(synth.phi_matrix(K, N, 1.0, 42))
+    ref = oracle.s1_sgemm(A, B, p)
+    c = ozk.Context(0)
+    try:
+        for cfg in [(0, 0, 4, 1), (1, 1, 2, 3), (2, 0, 8, 5), (3, 1, 1, 2)]:
+            ozk.ozk_config_set(c, ozk.OZK_OP_DGEMM, ozk.OZK_SCHEME1, p, M, N, K, cfg)
+            assert np.array_equal(host(ozk.ozk_sgemm(c, p, dev(A), dev(B))), ref), cfg
+    finally:
+        c.close()
+
+
+def test_sgemm_1024_against_oracle_and_native_error(ctx):
+    """1024 x 1024 x 512 at p = 4: bit-exact against the oracle, and the error
+    against the double-double reference at the level of native binary32
+    (p = 3 leaves about 2^-16: the slices carry 8p - 2 bits relative to the
+    row's largest entry)."""
+    p, M, N, K = 4, 1024, 1024, 512
+    A = f32(synth.phi_matrix(M, K, 1.0, 51))
+    B = f32(synth.phi_matrix(K, N, 1.0, 52))
+    a, b = dev(A), dev(B)
+    C = host(ozk.ozk_sgemm(ctx, p, a, b))
+    assert np.array_equal(C, oracle.s1_sgemm(A, B, p))
+    A64, B64 = A.astype(np.float64), B.astype(np.float64)
+    ri, ci = np.arange(0, M, 97), np.arange(0, N, 89)
+    hi, lo = oracle.gemm_dd(A64[ri], B64[:, ci])
+    err = oracle.metrics.e_cw(C[np.ix_(ri, ci)].astype(np.float64), hi, lo, A64[ri], B64[:, ci])
+    nat = host(torch.matmul(a, b))[np.ix_(ri, ci)].astype(np.float64)
+    err_nat = oracle.metrics.e_cw(nat, hi, lo, A64[ri], B64[:, ci])
+    assert err < 4 * max(err_nat, 2.0 ** -24), (err, err_nat)
