@@ -320,6 +320,15 @@ def test_sgemm_edges_alpha_beta_and_empty(ctx):
     C = dev(np.full((5, 3), 7.0, np.float32))
     ozk.ozk_sgemm(ctx, p, dev(np.ones((5, 0), np.float32)), dev(np.ones((0, 3), np.float32)), C=C)
     assert np.array_equal(host(C), np.zeros((5, 3), np.float32))
+    one = dev(np.ones((4, 4), np.float32))
+    big = torch.empty(1 << 20, dtype=torch.uint8, device="cuda:0")
+    for bad in (0, 9):
+        with pytest.raises(ozk.OzkError) as ei:
+            ozk.ozk_sgemm(ctx, bad, one, one, ws=big)
+        assert ei.value.status == ozk.OZK_ERR_UNSUPPORTED
+    with pytest.raises(ozk.OzkError) as ei:
+        ozk.ozk_sgemm(ctx, p, one, one, ws=torch.empty(1, dtype=torch.uint8, device="cuda:0"))
+    assert ei.value.status == ozk.OZK_ERR_WORKSPACE
 
 
 def test_sgemm_k_runs_and_configs(ctx):
