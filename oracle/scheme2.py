@@ -438,3 +438,111 @@ def z3m_entries(A, B, s: int, rows, cols) -> np.ndarray:
         h = complex(scaled_round(int(crt(cre, s)[0, 0]), E), scaled_round(int(crt(cim, s)[0, 0]), E))
         out[n] = zaxpby(1.0, np.array([h]), 0.0, None)[0]
     return out
+
+
+# ------------------------------------------- binary32 operands and results
+
+def rn_f32(x: Fraction) -> np.float32:
+    """Round-to-nearest-even of an exact rational to binary32: 24 significant
+    bits, gradual underflow at 2^-149, overflow to infinity."""
+    if x == 0:
+        return np.float32(0.0)
+    neg = x < 0
+    num, den = abs(x.numerator), x.denominator
+    e = num.bit_length() - den.bit_length()  # 2^e <= |x| < 2^(e+1) after the correction
+    if (num << max(0, -e)) < (den << max(0, e)):
+        e -= 1
+    sh = 23 - max(e, -126)  # q = |x| 2^sh has 24 bits (fewer when subnormal)
+    n2, d2 = (num << sh, den) if sh >= 0 else (num, den << -sh)
+    q, r = divmod(n2, d2)
+    if 2 * r > d2 or (2 * r == d2 and q & 1):
+        q += 1
+    if q.bit_length() - sh > 128:
+        v = math.inf
+    else:
+        v = math.ldexp(q, -sh)  # q <= 2^24: exact in binary64 and in binary32
+    return np.float32(-v if neg else v)
+
+
+def scaled_round_f32(z: int, E: int) -> np.float32:
+    """RN-even of z 2^E to binary32."""
+    return rn_f32(Fraction(z) * (Fraction(2) ** E))
+
+
+def _fmaf(a, b, c) -> np.float32:
+    """Correctly rounded binary32 fused multiply-add through exact rationals."""
+    a, b, c = np.float32(a), np.float32(b), np.float32(c)
+    if not (np.isfinite(a) and np.isfinite(b) and np.isfinite(c)):
+        return np.float32(a * b + c)
+    return rn_f32(Fraction(float(a)) * Fraction(float(b)) + Fraction(float(c)))
+
+
+def _round_all_f32(Z: np.ndarray, sig: np.ndarray, tau: np.ndarray) -> np.ndarray:
+    M, N = Z.shape
+    out = np.empty((M, N), np.float32)
+    for i in range(M):
+        for j in range(N):
+            out[i, j] = scaled_round_f32(int(Z[i, j]), -int(sig[i]) - int(tau[j]))
+    return out
+
+
+def axpby_f32(alpha: float, H: np.ndarray, beta: float, C) -> np.ndarray:
+    """alpha*H if beta == 0 (C not read), else fmaf(alpha, H, beta*C), in binary32."""
+    alpha, beta = np.float32(alpha), np.float32(beta)
+    if beta == 0:
+        return alpha * H
+    bc = beta * np.asarray(C, np.float32)
+    out = np.empty_like(H)
+    for idx in np.ndindex(H.shape):
+        out[idx] = _fmaf(alpha, H[idx], bc[idx])
+    return out
+
+
+def s2_sgemm(A, B, s: int, alpha=1.0, beta=0.0, C=None):
+    """Scheme II SGEMM: steps 1-6 on the exactly widened binary32 operands,
+    one rounding of Z 2^E to binary32, then alpha/beta in binary32."""
+    A = np.asarray(A, np.float32).astype(np.float64)
+    B = np.asarray(B, np.float32).astype(np.float64)
+    st = s2_prepare(A, B, s)
+    Cl = [modular_product(ra, rb, m) for ra, rb, m in zip(st["RA"], st["RB"], st["ms"])]
+    H = _round_all_f32(crt(Cl, s), st["sig"], st["tau"])
+    H[st["bad_r"], :] = np.nan
+    H[:, st["bad_c"]] = np.nan
+    return axpby_f32(alpha, H, beta, C)
+
+
+def z3m_cgemm(A, B, s: int, alpha=1.0, beta=0.0, C=None):
+    """Scheme II 3M CGEMM: the 3M steps on the exactly widened complex64
+    operands, binary32 roundings, and the fixed FMA sequence of zaxpby in
+    binary32 (fmaf)."""
+    A = np.asarray(A, np.complex64).astype(np.complex128)
+    B = np.asarray(B, np.complex64).astype(np.complex128)
+    st = z3m_prepare(A, B, s)
+    cre, cim = [], []
+    for (RA, RB), m in zip(st["planes"], st["ms"]):
+        r, i = z3m_modular(RA, RB, m)
+        cre.append(r)
+        cim.append(i)
+    Hre = _round_all_f32(crt(cre, s), st["sig"], st["tau"])
+    Him = _round_all_f32(crt(cim, s), st["sig"], st["tau"])
+    Hre[st["bad_r"], :] = np.nan
+    Him[st["bad_r"], :] = np.nan
+    Hre[:, st["bad_c"]] = np.nan
+    Him[:, st["bad_c"]] = np.nan
+    al, be = complex(alpha), complex(beta)
+    ar, ai, br, bi = (np.float32(v) for v in (al.real, al.imag, be.real, be.imag))
+    out = np.empty(Hre.shape, np.complex64)
+    Cc = None if be == 0 else np.asarray(C, np.complex64)
+    for idx in np.ndindex(Hre.shape):
+        hr, hi = Hre[idx], Him[idx]
+        if be == 0:
+            bre = bim = np.float32(0.0)
+        else:
+            c = Cc[idx]
+            cr, ci = np.float32(c.real), np.float32(c.imag)
+            bre = _fmaf(br, cr, -(bi * ci))
+            bim = _fmaf(br, ci, bi * cr)
+        ore = _fmaf(ar, hr, _fmaf(-ai, hi, bre))
+        oim = _fmaf(ar, hi, _fmaf(ai, hr, bim))
+        out[idx] = np.complex64(complex(float(ore), float(oim)))
+    return out

@@ -244,3 +244,58 @@ def test_entries_match_full_results():
     fz = s2.z3m_gemm(Z, W, 11)
     assert np.array_equal(s2.z3m_entries(Z, W, 11, rows[[0, 2, 3, 4]] % 10, cols[[0, 2, 3, 4]] % 8),
                           fz[rows[[0, 2, 3, 4]] % 10, cols[[0, 2, 3, 4]] % 8])
+
+
+# ------------------------------------------------ binary32 operands and results
+
+def test_rn_f32_matches_numpy_and_the_c_oracle():
+    """The rational rounding to binary32 equals numpy's correctly rounded
+    binary64 -> binary32 conversion on exact binary64 values (ties,
+    subnormals, overflow), and the C oracle's independent integer rounding."""
+    from fractions import Fraction
+    import random
+    import oracle
+    rng = random.Random(5)
+    for _ in range(3000):
+        x = np.float64(rng.uniform(1, 2)) * 2.0 ** rng.randrange(-160, 130)
+        for v in (x, -x):
+            assert s2.rn_f32(Fraction(float(v))).tobytes() == np.float32(v).tobytes(), v
+    for z, E in [(1, -150), (3, -151), (2 ** 24 + 1, 0), (2 ** 24 - 1, 104), (7, -300)]:
+        assert s2.scaled_round_f32(z, E).tobytes() == oracle.round_scaled_f32(z, E).tobytes()
+    for _ in range(2000):
+        z = rng.randrange(1, 2 ** rng.randrange(1, 120))
+        E = rng.randrange(-300, 40)
+        assert s2.scaled_round_f32(-z, E).tobytes() == oracle.round_scaled_f32(-z, E).tobytes()
+
+
+def test_fmaf_single_rounding():
+    """fmaf rounds a*b + c once: where binary64 holds a*b + c exactly, it is
+    numpy's conversion of that binary64 value."""
+    from fractions import Fraction
+    rng = np.random.default_rng(8)
+    n = 0
+    for _ in range(3000):
+        a, b, c = (np.float32(v) for v in rng.standard_normal(3) * 2.0 ** rng.integers(-20, 20, 3))
+        exact = Fraction(float(a)) * Fraction(float(b)) + Fraction(float(c))
+        d = np.float64(a) * np.float64(b) + np.float64(c)
+        if Fraction(float(d)) == exact:
+            n += 1
+            assert s2._fmaf(a, b, c).tobytes() == np.float32(d).tobytes()
+    assert n > 1000
+
+
+def test_sgemm_and_cgemm_exact_for_small_integers():
+    """Small integer operands are integerised without loss, so the binary32
+    Scheme II and 3M results are the exact integer products (below 2^24)."""
+    rng = np.random.default_rng(9)
+    A = rng.integers(-100, 101, (7, 30)).astype(np.float32)
+    B = rng.integers(-100, 101, (30, 6)).astype(np.float32)
+    want = (A.astype(np.int64) @ B.astype(np.int64)).astype(np.float32)
+    for s in (8, 12, 20):
+        assert np.array_equal(s2.s2_sgemm(A, B, s), want)
+    Ac = (A + 1j * rng.integers(-100, 101, A.shape)).astype(np.complex64)
+    Bc = (B + 1j * rng.integers(-100, 101, B.shape)).astype(np.complex64)
+    wre = Ac.real.astype(np.int64) @ Bc.real.astype(np.int64) - Ac.imag.astype(np.int64) @ Bc.imag.astype(np.int64)
+    wim = Ac.real.astype(np.int64) @ Bc.imag.astype(np.int64) + Ac.imag.astype(np.int64) @ Bc.real.astype(np.int64)
+    got = s2.z3m_cgemm(Ac, Bc, 10)
+    assert np.array_equal(got.real, wre.astype(np.float32)) and np.array_equal(got.imag, wim.astype(np.float32))
