@@ -155,25 +155,42 @@ ozk_status ozk_dgemm(ozk_ctx* ctx, ozk_scheme scheme, int p_or_s, int64_t M,
                      double* C, int64_t ldc, void* ws, size_t ws_bytes,
                      hipStream_t stream);
 
-/* Emulated SGEMM, C = alpha*A*B + beta*C in binary32, by Scheme I with
- * 1 <= p <= 8 slices (paper Sec. II-C.1; its FP32-level operating points
- * are p = 1..4, Sec. V-D): A (M x K, lda) and B (K x N, ldb) are row-major
- * binary32, widened exactly to binary64 for the exponent and slice steps, so
- * the slices, the INT32 products and the exact integer Z are those of
- * ozk_dgemm on the widened operands; the one rounding of Z 2^E goes to
- * binary32 (round to nearest even, gradual underflow, overflow to infinity),
- * then C = alpha*h (beta == 0, C not read) or fmaf(alpha, h, beta*C), in
- * binary32.  Non-finite rows of A or columns of B give NaN.  The workspace is
- * that of ozk_dgemm with OZK_SCHEME1 (ozk_workspace_size(ctx, OZK_OP_DGEMM,
- * OZK_SCHEME1, M, N, K, p)), and the GEMM step takes the DGEMM
- * configuration of the size class.  Device pointers; the caller owns all
- * memory; asynchronous on `stream`.  Errors: OZK_ERR_UNSUPPORTED (arg 2) for
- * p outside 1..8, OZK_ERR_INVALID_ARG with the argument index for bad
- * sizes, leading dimensions or null pointers, OZK_ERR_WORKSPACE (arg 14). */
-ozk_status ozk_sgemm(ozk_ctx* ctx, int p, int64_t M, int64_t N, int64_t K,
-                     float alpha, const float* A, int64_t lda, const float* B,
-                     int64_t ldb, float beta, float* C, int64_t ldc, void* ws,
-                     size_t ws_bytes, hipStream_t stream);
+/* Emulated SGEMM, C = alpha*A*B + beta*C in binary32 (the paper's FP32-level
+ * operating points: Scheme I with p = 1..4, Scheme II with s = 8..11;
+ * Sec. V-D).  A (M x K, lda) and B (K x N, ldb) are row-major binary32,
+ * widened exactly to binary64 for the exponent, slice and residue steps, so
+ * the slices or residues, the INT32 products and the exact integer result
+ * Z are those of ozk_dgemm on the widened operands; the one rounding of
+ * Z 2^E goes to binary32 (round to nearest even, gradual underflow,
+ * overflow to infinity), then C = alpha*h (beta == 0, C not read) or
+ * fmaf(alpha, h, beta*C), in binary32.  Non-finite rows of A or columns of
+ * B give NaN.  Scheme I: 1 <= p_or_s <= 8; Scheme II: 1 <= p_or_s <= 20
+ * (with the separate CRT kernel whatever the configuration).  The
+ * workspace is that of ozk_dgemm with the same scheme and count
+ * (ozk_workspace_size(ctx, OZK_OP_DGEMM, scheme, M, N, K, p_or_s)), and the
+ * GEMM step takes the DGEMM configuration of the size class.  Device
+ * pointers; the caller owns all memory; asynchronous on `stream`.  Errors:
+ * OZK_ERR_INVALID_ARG with the argument index for a bad scheme, sizes,
+ * leading dimensions or null pointers, OZK_ERR_UNSUPPORTED (arg 3) for a
+ * count out of range, OZK_ERR_WORKSPACE (arg 15). */
+ozk_status ozk_sgemm(ozk_ctx* ctx, ozk_scheme scheme, int p_or_s, int64_t M,
+                     int64_t N, int64_t K, float alpha, const float* A,
+                     int64_t lda, const float* B, int64_t ldb, float beta,
+                     float* C, int64_t ldc, void* ws, size_t ws_bytes,
+                     hipStream_t stream);
+
+/* Emulated CGEMM by Scheme II and 3M, binary32 complex (interleaved re, im;
+ * torch.complex64) in and out: ozk_zgemm_3m on the exactly widened operands
+ * with the final roundings to binary32 and the complex alpha/beta update of
+ * ozk_zgemm_3m's fixed FMA sequence in binary32 (fmaf).  alpha and beta
+ * point to {re, im} on the host.  Workspace ozk_workspace_size(ctx,
+ * OZK_OP_ZGEMM, OZK_SCHEME2, M, N, K, s); the GEMM step takes the ZGEMM
+ * configuration.  Errors as ozk_zgemm_3m. */
+ozk_status ozk_cgemm_3m(ozk_ctx* ctx, int s, int64_t M, int64_t N, int64_t K,
+                        const float* alpha, const float* A, int64_t lda,
+                        const float* B, int64_t ldb, const float* beta,
+                        float* C, int64_t ldc, void* ws, size_t ws_bytes,
+                        hipStream_t stream);
 
 /* C = alpha*A*B + beta*C in complex128 with Scheme II and the 3M identity
  * (Sec. IV-B, Eq. 16): three modular products per modulus, exact.  alpha and

@@ -50,7 +50,7 @@ class OzkGemmConfig(ctypes.Structure):
 EXPORTS = (
     "ozk_create", "ozk_destroy", "ozk_last_arg", "ozk_status_string", "ozk_version",
     "ozk_s1_packed_bytes", "ozk_s2_packed_bytes", "ozk_s1_k_split", "ozk_workspace_size",
-    "ozk_dgemm", "ozk_sgemm", "ozk_zgemm_3m", "ozk_s1_split_rows", "ozk_s1_split_cols", "ozk_s1_gemm",
+    "ozk_dgemm", "ozk_sgemm", "ozk_zgemm_3m", "ozk_cgemm_3m", "ozk_s1_split_rows", "ozk_s1_split_cols", "ozk_s1_gemm",
     "ozk_s1_diagonals", "ozk_s2_split_rows", "ozk_s2_split_cols", "ozk_s2_gemm_mod", "ozk_s2_crt",
     "ozk_selector_load", "ozk_select", "ozk_dgemm_auto", "ozk_mlp_forward", "ozk_mlp_grad", "ozk_mlp_adam",
     "ozk_ref_dd", "ozk_batch_plan_create", "ozk_gemm_batched", "ozk_batch_plan_destroy",
@@ -89,7 +89,8 @@ def _lib() -> ctypes.CDLL:
         "ozk_s1_k_split": (I64, [I]),
         "ozk_workspace_size": (I, [P, I, I, I64, I64, I64, I, ctypes.POINTER(SZ)]),
         "ozk_dgemm": (I, [P, I, I, I64, I64, I64, D, P, I64, P, I64, D, P, I64, P, SZ, P]),
-        "ozk_sgemm": (I, [P, I, I64, I64, I64, ctypes.c_float, P, I64, P, I64, ctypes.c_float, P, I64, P, SZ, P]),
+        "ozk_sgemm": (I, [P, I, I, I64, I64, I64, ctypes.c_float, P, I64, P, I64, ctypes.c_float, P, I64, P, SZ, P]),
+        "ozk_cgemm_3m": (I, [P, I, I64, I64, I64, P, P, I64, P, I64, P, P, I64, P, SZ, P]),
         "ozk_zgemm_3m": (I, [P, I, I64, I64, I64, P, P, I64, P, I64, P, P, I64, P, SZ, P]),
         "ozk_s1_split_rows": (I, [P, I, I64, I64, P, I64, P, P, P]),
         "ozk_s1_split_cols": (I, [P, I, I64, I64, P, I64, P, P, P]),
@@ -238,18 +239,39 @@ def ozk_dgemm(ctx: Context, scheme: int, p_or_s: int, A, B, C=None, alpha: float
     return C
 
 
-def ozk_sgemm(ctx: Context, p: int, A, B, C=None, alpha: float = 1.0, beta: float = 0.0, ws=None, stream=None):
-    """C = alpha*A*B + beta*C (float32 CUDA tensors) by Scheme I with p slices; returns C."""
+def ozk_sgemm(ctx: Context, scheme: int, p_or_s: int, A, B, C=None, alpha: float = 1.0, beta: float = 0.0,
+              ws=None, stream=None):
+    """C = alpha*A*B + beta*C (float32 CUDA tensors) by Scheme I (p slices) or
+    Scheme II (s moduli); returns C."""
     import torch
     M, K = A.shape
     N = B.shape[1]
     if C is None:
         C = torch.empty((M, N), dtype=torch.float32, device=A.device)
     if ws is None:
-        ws = _workspace(ozk_workspace_size(ctx, OZK_OP_DGEMM, OZK_SCHEME1, M, N, K, p), A.device)
-    st = _lib().ozk_sgemm(ctx.handle, p, M, N, K, float(alpha), _ptr(A), _ld(A), _ptr(B), _ld(B), float(beta),
-                          _ptr(C), _ld(C), _ptr(ws), ws.numel(), _stream(stream))
+        ws = _workspace(ozk_workspace_size(ctx, OZK_OP_DGEMM, scheme, M, N, K, p_or_s), A.device)
+    st = _lib().ozk_sgemm(ctx.handle, scheme, p_or_s, M, N, K, float(alpha), _ptr(A), _ld(A), _ptr(B), _ld(B),
+                          float(beta), _ptr(C), _ld(C), _ptr(ws), ws.numel(), _stream(stream))
     _check("ozk_sgemm", st, ctx)
+    return C
+
+
+def ozk_cgemm_3m(ctx: Context, s: int, A, B, C=None, alpha: complex = 1.0, beta: complex = 0.0, ws=None,
+                 stream=None):
+    """C = alpha*A*B + beta*C (complex64 CUDA tensors) with Scheme II + 3M."""
+    import torch
+    M, K = A.shape
+    N = B.shape[1]
+    if C is None:
+        C = torch.empty((M, N), dtype=torch.complex64, device=A.device)
+    if ws is None:
+        ws = _workspace(ozk_workspace_size(ctx, OZK_OP_ZGEMM, OZK_SCHEME2, M, N, K, s), A.device)
+    al = (ctypes.c_float * 2)(complex(alpha).real, complex(alpha).imag)
+    be = (ctypes.c_float * 2)(complex(beta).real, complex(beta).imag)
+    st = _lib().ozk_cgemm_3m(ctx.handle, s, M, N, K, ctypes.cast(al, ctypes.c_void_p), _ptr(A), _ld(A), _ptr(B),
+                             _ld(B), ctypes.cast(be, ctypes.c_void_p), _ptr(C), _ld(C), _ptr(ws), ws.numel(),
+                             _stream(stream))
+    _check("ozk_cgemm_3m", st, ctx)
     return C
 
 

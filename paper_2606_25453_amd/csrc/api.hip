@@ -428,23 +428,46 @@ ozk_status ozk_dgemm(ozk_ctx* ctx, ozk_scheme scheme, int p_or_s, int64_t M, int
                         pl.total - pl.off_z, nullptr, stream, cfg);
 }
 
-ozk_status ozk_sgemm(ozk_ctx* ctx, int p, int64_t M, int64_t N, int64_t K, float alpha, const float* A,
-                     int64_t lda, const float* B, int64_t ldb, float beta, float* C, int64_t ldc, void* ws,
-                     size_t ws_bytes, hipStream_t stream) {
+ozk_status ozk_sgemm(ozk_ctx* ctx, ozk_scheme scheme, int p_or_s, int64_t M, int64_t N, int64_t K, float alpha,
+                     const float* A, int64_t lda, const float* B, int64_t ldb, float beta, float* C, int64_t ldc,
+                     void* ws, size_t ws_bytes, hipStream_t stream) {
   if (!ctx) return OZK_ERR_INVALID_ARG;
   ctx->last_arg = 0;
-  if (p < 1 || p > OZK_MAX_P) return fail(ctx, OZK_ERR_UNSUPPORTED, 2);
-  if (bad_dims(M, N, K)) return fail(ctx, OZK_ERR_INVALID_ARG, M < 0 ? 3 : (N < 0 ? 4 : 5));
-  if (!A && M > 0 && K > 0) return fail(ctx, OZK_ERR_INVALID_ARG, 7);
-  if (lda < (K > 0 ? K : 1)) return fail(ctx, OZK_ERR_INVALID_ARG, 8);
-  if (!B && K > 0 && N > 0) return fail(ctx, OZK_ERR_INVALID_ARG, 9);
-  if (ldb < (N > 0 ? N : 1)) return fail(ctx, OZK_ERR_INVALID_ARG, 10);
-  if (!C && M > 0 && N > 0) return fail(ctx, OZK_ERR_INVALID_ARG, 12);
-  if (ldc < (N > 0 ? N : 1)) return fail(ctx, OZK_ERR_INVALID_ARG, 13);
-  // the GEMM step is the DGEMM one (same packed operands), so it shares its configurations
+  if (scheme != OZK_SCHEME1 && scheme != OZK_SCHEME2) return fail(ctx, OZK_ERR_INVALID_ARG, 2);
+  if (bad_dims(M, N, K)) return fail(ctx, OZK_ERR_INVALID_ARG, M < 0 ? 4 : (N < 0 ? 5 : 6));
+  if (!A && M > 0 && K > 0) return fail(ctx, OZK_ERR_INVALID_ARG, 8);
+  if (lda < (K > 0 ? K : 1)) return fail(ctx, OZK_ERR_INVALID_ARG, 9);
+  if (!B && K > 0 && N > 0) return fail(ctx, OZK_ERR_INVALID_ARG, 10);
+  if (ldb < (N > 0 ? N : 1)) return fail(ctx, OZK_ERR_INVALID_ARG, 11);
+  if (!C && M > 0 && N > 0) return fail(ctx, OZK_ERR_INVALID_ARG, 13);
+  if (ldc < (N > 0 ? N : 1)) return fail(ctx, OZK_ERR_INVALID_ARG, 14);
+  // the GEMM steps are the DGEMM ones (same packed operands), so they share their configurations
+  if (scheme == OZK_SCHEME2) {
+    const int s = p_or_s;
+    if (s < 1 || s > OZK_MAX_S) return fail(ctx, OZK_ERR_UNSUPPORTED, 3);
+    const S2Plan pl = s2_plan(s, false, M, N, K);
+    if (!ws || ws_bytes < pl.total) return fail(ctx, OZK_ERR_WORKSPACE, 15);
+    if (M == 0 || N == 0) return OZK_OK;
+    char* w = (char*)ws;
+    int32_t* sig = (int32_t*)(w + pl.off_sig);
+    int32_t* tau = (int32_t*)(w + pl.off_tau);
+    int8_t* Ap = (int8_t*)(w + pl.off_a);
+    int8_t* Bp = (int8_t*)(w + pl.off_b);
+    int8_t* res = (int8_t*)(w + pl.off_res);
+    hipError_t err = ozk::s2_split_rows(s, false, A, lda, M, K, sig, Ap, stream);
+    if (err == hipSuccess) err = ozk::s2_split_cols(s, false, B, ldb, K, N, tau, Bp, stream);
+    const ozk_gemm_config cfg = config_for(ctx, OZK_OP_DGEMM, OZK_SCHEME2, s, M, N, K);
+    if (err == hipSuccess)  // the fused-CRT variant writes binary64: the separate kernels here
+      err = ozk::s2_gemm_mod(s, false, M, N, K, Ap, Bp, res, stream, cfg.variant, cfg.raster, cfg.group);
+    const float al[2] = {alpha, 0.0f}, be[2] = {beta, 0.0f};
+    if (err == hipSuccess) err = ozk::s2_crt(s, false, M, N, res, sig, tau, al, be, C, ldc, stream);
+    return hip_status(ctx, err);
+  }
+  const int p = p_or_s;
+  if (p < 1 || p > OZK_MAX_P) return fail(ctx, OZK_ERR_UNSUPPORTED, 3);
   const ozk_gemm_config cfg = config_for(ctx, OZK_OP_DGEMM, OZK_SCHEME1, p, M, N, K);
   const S1Plan pl = s1_plan(ctx, p, M, N, K, cfg.split);
-  if (!ws || ws_bytes < pl.total) return fail(ctx, OZK_ERR_WORKSPACE, 14);
+  if (!ws || ws_bytes < pl.total) return fail(ctx, OZK_ERR_WORKSPACE, 15);
   if (M == 0 || N == 0) return OZK_OK;
   char* w = (char*)ws;
   int32_t* e = (int32_t*)(w + pl.off_e);
@@ -456,6 +479,39 @@ ozk_status ozk_sgemm(ozk_ctx* ctx, int p, int64_t M, int64_t N, int64_t K, float
   if (err != hipSuccess) return hip_status(ctx, err);
   return s1_gemm_common(ctx, p, M, N, K, Ap, e, Bp, f, alpha, beta, nullptr, ldc, w + pl.off_z, pl.total - pl.off_z,
                         nullptr, stream, cfg, C);
+}
+
+ozk_status ozk_cgemm_3m(ozk_ctx* ctx, int s, int64_t M, int64_t N, int64_t K, const float* alpha, const float* A,
+                        int64_t lda, const float* B, int64_t ldb, const float* beta, float* C, int64_t ldc, void* ws,
+                        size_t ws_bytes, hipStream_t stream) {
+  if (!ctx) return OZK_ERR_INVALID_ARG;
+  ctx->last_arg = 0;
+  if (s < 1 || s > OZK_MAX_S) return fail(ctx, OZK_ERR_UNSUPPORTED, 2);
+  if (bad_dims(M, N, K)) return fail(ctx, OZK_ERR_INVALID_ARG, M < 0 ? 3 : (N < 0 ? 4 : 5));
+  if (!alpha) return fail(ctx, OZK_ERR_INVALID_ARG, 6);
+  if (!A && M > 0 && K > 0) return fail(ctx, OZK_ERR_INVALID_ARG, 7);
+  if (lda < (K > 0 ? K : 1)) return fail(ctx, OZK_ERR_INVALID_ARG, 8);
+  if (!B && K > 0 && N > 0) return fail(ctx, OZK_ERR_INVALID_ARG, 9);
+  if (ldb < (N > 0 ? N : 1)) return fail(ctx, OZK_ERR_INVALID_ARG, 10);
+  if (!beta) return fail(ctx, OZK_ERR_INVALID_ARG, 11);
+  if (!C && M > 0 && N > 0) return fail(ctx, OZK_ERR_INVALID_ARG, 12);
+  if (ldc < (N > 0 ? N : 1)) return fail(ctx, OZK_ERR_INVALID_ARG, 13);
+  const S2Plan pl = s2_plan(s, true, M, N, K);
+  if (!ws || ws_bytes < pl.total) return fail(ctx, OZK_ERR_WORKSPACE, 14);
+  if (M == 0 || N == 0) return OZK_OK;
+  char* w = (char*)ws;
+  int32_t* sig = (int32_t*)(w + pl.off_sig);
+  int32_t* tau = (int32_t*)(w + pl.off_tau);
+  int8_t* Ap = (int8_t*)(w + pl.off_a);
+  int8_t* Bp = (int8_t*)(w + pl.off_b);
+  int8_t* res = (int8_t*)(w + pl.off_res);
+  hipError_t err = ozk::s2_split_rows(s, true, A, lda, M, K, sig, Ap, stream);
+  if (err == hipSuccess) err = ozk::s2_split_cols(s, true, B, ldb, K, N, tau, Bp, stream);
+  const ozk_gemm_config cfg = config_for(ctx, OZK_OP_ZGEMM, OZK_SCHEME2, s, M, N, K);
+  if (err == hipSuccess)
+    err = ozk::s2_gemm_mod(s, true, M, N, K, Ap, Bp, res, stream, cfg.variant, cfg.raster, cfg.group);
+  if (err == hipSuccess) err = ozk::s2_crt(s, true, M, N, res, sig, tau, alpha, beta, C, ldc, stream);
+  return hip_status(ctx, err);
 }
 
 ozk_status ozk_zgemm_3m(ozk_ctx* ctx, int s, int64_t M, int64_t N, int64_t K, const double* alpha,

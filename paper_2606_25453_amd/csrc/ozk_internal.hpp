@@ -144,6 +144,14 @@ hipError_t s2_gemm_mod(int s, bool cplx, int64_t M, int64_t N, int64_t K, const 
 hipError_t s2_crt(int s, bool cplx, int64_t M, int64_t N, const int8_t* res, const int32_t* sigma,
                   const int32_t* tau, const double* alpha, const double* beta, double* C, int64_t ldc,
                   hipStream_t st);
+// binary32 operands (widened exactly on load) and binary32 results
+hipError_t s2_split_rows(int s, bool cplx, const float* X, int64_t ldx, int64_t rows, int64_t K, int32_t* sigma,
+                         int8_t* packed, hipStream_t st);
+hipError_t s2_split_cols(int s, bool cplx, const float* X, int64_t ldx, int64_t K, int64_t cols, int32_t* tau,
+                         int8_t* packed, hipStream_t st);
+hipError_t s2_crt(int s, bool cplx, int64_t M, int64_t N, const int8_t* res, const int32_t* sigma,
+                  const int32_t* tau, const float* alpha, const float* beta, float* C, int64_t ldc,
+                  hipStream_t st);
 // GEMM and CRT in one kernel (real products; no residue planes).
 hipError_t s2_gemm_crt(int s, int64_t M, int64_t N, int64_t K, const int8_t* Ap, const int8_t* Bp,
                        const int32_t* sigma, const int32_t* tau, double alpha, double beta, double* C, int64_t ldc,

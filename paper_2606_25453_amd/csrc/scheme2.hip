@@ -102,10 +102,10 @@ __device__ __forceinline__ int residue_of(const Limbs3& v, int l) {
 
 // Per-entry exponent for the scale bound: |entry| < 2^ex.  Complex entries
 // bound |re| + |im| < 2^(max(expo re, expo im) + 1).
-template <bool CPLX>
-__device__ __forceinline__ int entry_expo(const double* x) {
-  if (!CPLX) return expo_of(x[0]);
-  const int a = expo_of(x[0]), b = expo_of(x[1]);
+template <bool CPLX, typename T>
+__device__ __forceinline__ int entry_expo(const T* x) {
+  if (!CPLX) return expo_of((double)x[0]);
+  const int a = expo_of((double)x[0]), b = expo_of((double)x[1]);
   const int e = a > b ? a : b;  // the non-finite sentinel is the largest value
   return (e == OZK_EXP_NONFINITE || e == OZK_EXP_ZERO) ? e : e + 1;
 }
@@ -182,8 +182,8 @@ __device__ __forceinline__ void s2_store_residues(const double (&re)[4], const d
 // that every lane takes part in the reductions.
 constexpr int S2_ROWS_PER_BLOCK = 16;
 
-template <bool CPLX>
-__device__ __forceinline__ void s2_split_rows_block(const double* __restrict__ X, int64_t ldx, int64_t rows,
+template <bool CPLX, typename T = double>
+__device__ __forceinline__ void s2_split_rows_block(const T* __restrict__ X, int64_t ldx, int64_t rows,
                                                     int64_t K, int64_t Kp, int64_t rows_packed, S2Args sa,
                                                     int32_t* __restrict__ sigma_out, int8_t* __restrict__ packed,
                                                     int64_t blk) {
@@ -192,7 +192,7 @@ __device__ __forceinline__ void s2_split_rows_block(const double* __restrict__ X
   const int64_t r = (blk * 4 + (threadIdx.x >> 6)) * 4 + (lane >> 4);
   if (r >= rows_packed) return;  // whole waves only (rows_packed is a multiple of 16)
   const bool in = r < rows;
-  const double* xr = X + (in ? r : 0) * ldx * W;
+  const T* xr = X + (in ? r : 0) * ldx * W;
   int e = OZK_EXP_ZERO;
 #pragma unroll 8
   for (int64_t k = q; k < K; k += 16) {
@@ -240,20 +240,20 @@ __device__ __forceinline__ void s2_split_rows_block(const double* __restrict__ X
   }
 }
 
-template <bool CPLX>
-__global__ __launch_bounds__(256) void k_s2_split_rows(const double* __restrict__ X, int64_t ldx, int64_t rows,
+template <bool CPLX, typename T = double>
+__global__ __launch_bounds__(256) void k_s2_split_rows(const T* __restrict__ X, int64_t ldx, int64_t rows,
                                                        int64_t K, int64_t Kp, int64_t rows_packed, S2Args sa,
                                                        int32_t* __restrict__ sigma_out,
                                                        int8_t* __restrict__ packed) {
-  s2_split_rows_block<CPLX>(X, ldx, rows, K, Kp, rows_packed, sa, sigma_out, packed, blockIdx.x);
+  s2_split_rows_block<CPLX, T>(X, ldx, rows, K, Kp, rows_packed, sa, sigma_out, packed, blockIdx.x);
 }
 
 // Column scales: a block of 256 threads covers 32 consecutive columns with 8
 // k-groups per column (coalesced 32-column row segments); the max exponent
 // and then the norm-bound sum are reduced through LDS, so no atomics and no
 // scratch memory are needed and the result does not depend on the order.
-template <bool CPLX>
-__device__ __forceinline__ void s2_col_scales_block(const double* __restrict__ X, int64_t ldx, int64_t K,
+template <bool CPLX, typename TX = double>
+__device__ __forceinline__ void s2_col_scales_block(const TX* __restrict__ X, int64_t ldx, int64_t K,
                                                     int64_t cols, int T, int32_t* __restrict__ tau, int64_t blk) {
   constexpr int W = CPLX ? 2 : 1;
   __shared__ int red_e[8][32];
@@ -287,10 +287,10 @@ __device__ __forceinline__ void s2_col_scales_block(const double* __restrict__ X
   }
 }
 
-template <bool CPLX>
-__global__ __launch_bounds__(256) void k_s2_col_scales(const double* __restrict__ X, int64_t ldx, int64_t K,
+template <bool CPLX, typename TX = double>
+__global__ __launch_bounds__(256) void k_s2_col_scales(const TX* __restrict__ X, int64_t ldx, int64_t K,
                                                        int64_t cols, int T, int32_t* __restrict__ tau) {
-  s2_col_scales_block<CPLX>(X, ldx, K, cols, T, tau, blockIdx.x);
+  s2_col_scales_block<CPLX, TX>(X, ldx, K, cols, T, tau, blockIdx.x);
 }
 
 // Column scales for long K, split over K so that every CU has work: pass 1
@@ -309,8 +309,8 @@ __global__ __launch_bounds__(256) void k_s2_col_stats_init(int64_t cols, int32_t
   S[j] = 0ull;
 }
 
-template <bool CPLX>
-__global__ __launch_bounds__(256) void k_s2_col_emax(const double* __restrict__ X, int64_t ldx, int64_t K,
+template <bool CPLX, typename T = double>
+__global__ __launch_bounds__(256) void k_s2_col_emax(const T* __restrict__ X, int64_t ldx, int64_t K,
                                                      int64_t cols, int32_t* __restrict__ emax) {
   constexpr int W = CPLX ? 2 : 1;
   const int64_t j = (int64_t)blockIdx.x * 64 + (threadIdx.x & 63);
@@ -325,8 +325,8 @@ __global__ __launch_bounds__(256) void k_s2_col_emax(const double* __restrict__ 
   if (e != OZK_EXP_ZERO) atomicMax(&emax[j], e);
 }
 
-template <bool CPLX>
-__global__ __launch_bounds__(256) void k_s2_col_norm(const double* __restrict__ X, int64_t ldx, int64_t K,
+template <bool CPLX, typename T = double>
+__global__ __launch_bounds__(256) void k_s2_col_norm(const T* __restrict__ X, int64_t ldx, int64_t K,
                                                      int64_t cols, const int32_t* __restrict__ emax,
                                                      unsigned long long* __restrict__ S) {
   constexpr int W = CPLX ? 2 : 1;
@@ -363,8 +363,8 @@ int64_t s2_split_cols_blocks(int64_t cols_packed, int64_t Kp) {
   return (cols_packed / S2_COL_BLOCK) * (Kp / OZK_K_CHUNK);
 }
 
-template <bool CPLX>
-__device__ __forceinline__ void s2_split_cols_block(const double* __restrict__ X, int64_t ldx, int64_t K,
+template <bool CPLX, typename T = double>
+__device__ __forceinline__ void s2_split_cols_block(const T* __restrict__ X, int64_t ldx, int64_t K,
                                                     int64_t cols, int64_t Kp, int64_t cols_packed, int s,
                                                     const int32_t* __restrict__ tau, int8_t* __restrict__ packed,
                                                     int64_t jb, int64_t c) {
@@ -378,7 +378,7 @@ __device__ __forceinline__ void s2_split_cols_block(const double* __restrict__ X
   if (live && k0 + S2_COL_K <= K) {  // all loads first, no condition between them
 #pragma unroll
     for (int kk = 0; kk < S2_COL_K; ++kk) {
-      const double* src = X + ((k0 + kk) * ldx + j) * W;
+      const T* src = X + ((k0 + kk) * ldx + j) * W;
       re[kk] = src[0];
       im[kk] = CPLX ? src[1] : 0.0;
     }
@@ -418,12 +418,12 @@ __device__ __forceinline__ void s2_split_cols_block(const double* __restrict__ X
   }
 }
 
-template <bool CPLX>
-__global__ __launch_bounds__(256) void k_s2_split_cols(const double* __restrict__ X, int64_t ldx, int64_t K,
+template <bool CPLX, typename T = double>
+__global__ __launch_bounds__(256) void k_s2_split_cols(const T* __restrict__ X, int64_t ldx, int64_t K,
                                                        int64_t cols, int64_t Kp, int64_t cols_packed, int s,
                                                        const int32_t* __restrict__ tau,
                                                        int8_t* __restrict__ packed) {
-  s2_split_cols_block<CPLX>(X, ldx, K, cols, Kp, cols_packed, s, tau, packed, blockIdx.x, blockIdx.y);
+  s2_split_cols_block<CPLX, T>(X, ldx, K, cols, Kp, cols_packed, s, tau, packed, blockIdx.x, blockIdx.y);
 }
 
 // ----------------------------------------------------------- modular GEMM
@@ -715,11 +715,17 @@ __device__ __forceinline__ void crt_limbs16(const uint32_t (&z)[NZ], uint32_t (&
 // with the bits below folded into the lowest of them (sticky): the rounding
 // keeps at most 53 of the 128, so its round bit is bit 74 or higher, the
 // sticky bit lies strictly below it and the result is the same.
-__device__ __forceinline__ double round_limbs(const uint32_t (&mag)[NL], bool neg, int E) {
+// TO = float: the rounding to binary32 (round_mag_f32).
+template <typename TO = double>
+__device__ __forceinline__ TO round_limbs(const uint32_t (&mag)[NL], bool neg, int E) {
   static_assert(NL == 6, "three 64-bit words");
+  auto rnd = [](u128 m, bool n, int e) -> TO {
+    if constexpr (sizeof(TO) == 4) return round_mag_f32(m, n, e);
+    else return round_mag(m, n, e);
+  };
   const uint64_t w2 = ((uint64_t)mag[5] << 32) | mag[4], w1 = ((uint64_t)mag[3] << 32) | mag[2],
                  w0 = ((uint64_t)mag[1] << 32) | mag[0];
-  if (w2 == 0) return round_mag(((u128)w1 << 64) | w0, neg, E);
+  if (w2 == 0) return rnd(((u128)w1 << 64) | w0, neg, E);
   const int lz = __clzll(w2);
   const int cut = 64 - lz;  // bits dropped
   u128 top = ((u128)w2 << 64) | w1;
@@ -728,36 +734,41 @@ __device__ __forceinline__ double round_limbs(const uint32_t (&mag)[NL], bool ne
     top = (top << lz) | (w0 >> cut);
     rest = w0 << lz;
   }
-  return round_mag(top | (rest != 0), neg, E + cut);
+  return rnd(top | (rest != 0), neg, E + cut);
 }
 
-// C = alpha h + beta C for one output (complex: the fixed FMA sequence).
-template <bool CPLX>
-__device__ __forceinline__ void s2_store_c(const double (&h)[2], int64_t row, int64_t col, double a_re, double a_im,
-                                           double b_re, double b_im, double* __restrict__ C, int64_t ldc) {
+// C = alpha h + beta C for one output (complex: the fixed FMA sequence), in
+// the output's precision (TO = float: alpha, beta and h hold binary32 values).
+__device__ __forceinline__ double fma_t(double a, double b, double c) { return __fma_rn(a, b, c); }
+__device__ __forceinline__ float fma_t(float a, float b, float c) { return __fmaf_rn(a, b, c); }
+
+template <bool CPLX, typename TO = double>
+__device__ __forceinline__ void s2_store_c(const TO (&h)[2], int64_t row, int64_t col, TO a_re, TO a_im, TO b_re,
+                                           TO b_im, TO* __restrict__ C, int64_t ldc) {
   if (!CPLX) {
-    double* cp = C + row * ldc + col;
-    *cp = axpby(a_re, h[0], b_re, cp);
+    TO* cp = C + row * ldc + col;
+    if constexpr (sizeof(TO) == 4) *cp = axpby_f32(a_re, h[0], b_re, cp);
+    else *cp = axpby(a_re, h[0], b_re, cp);
   } else {
-    double* cp = C + 2 * (row * ldc + col);
-    double bre = 0.0, bim = 0.0;
-    if (!(b_re == 0.0 && b_im == 0.0)) {
-      const double cre = cp[0], cim = cp[1];
-      bre = __fma_rn(b_re, cre, -(b_im * cim));
-      bim = __fma_rn(b_re, cim, b_im * cre);
+    TO* cp = C + 2 * (row * ldc + col);
+    TO bre = 0, bim = 0;
+    if (!(b_re == 0 && b_im == 0)) {
+      const TO cre = cp[0], cim = cp[1];
+      bre = fma_t(b_re, cre, -(b_im * cim));
+      bim = fma_t(b_re, cim, b_im * cre);
     }
-    const double ore = __fma_rn(a_re, h[0], __fma_rn(-a_im, h[1], bre));
-    const double oim = __fma_rn(a_re, h[1], __fma_rn(a_im, h[0], bim));
+    const TO ore = fma_t(a_re, h[0], fma_t(-a_im, h[1], bre));
+    const TO oim = fma_t(a_re, h[1], fma_t(a_im, h[0], bim));
     cp[0] = ore;
     cp[1] = oim;
   }
 }
 
-template <bool CPLX>
+template <bool CPLX, typename TO = double>
 __device__ __forceinline__ void s2_crt_block(const CrtArgs& ca, int64_t M, int64_t N, const int8_t* __restrict__ res,
                                              const int32_t* __restrict__ sigma, const int32_t* __restrict__ tau,
-                                             double a_re, double a_im, double b_re, double b_im,
-                                             double* __restrict__ C, int64_t ldc, int64_t blk) {
+                                             TO a_re, TO a_im, TO b_re, TO b_im, TO* __restrict__ C, int64_t ldc,
+                                             int64_t blk) {
   const int64_t idx = blk * 256 + threadIdx.x;
   const int64_t mn = (int64_t)M * N;
   if (idx >= mn) return;
@@ -765,27 +776,26 @@ __device__ __forceinline__ void s2_crt_block(const CrtArgs& ca, int64_t M, int64
   const int si = sigma[row], tj = tau[col];
   const bool bad = si == OZK_EXP_NONFINITE || tj == OZK_EXP_NONFINITE;
   const int E = -si - tj;
-  double h[2];
+  TO h[2];
 #pragma unroll
   for (int q = 0; q < (CPLX ? 2 : 1); ++q) {
     if (bad) {
-      h[q] = __builtin_nan("");
+      h[q] = (TO)__builtin_nan("");
       continue;
     }
     uint32_t mag[NL];
     bool neg;
     crt_combine(ca, res + (CPLX ? q * mn : 0) + idx, CPLX ? 2 * mn : mn, mag, neg);
-    h[q] = round_limbs(mag, neg, E);
+    h[q] = round_limbs<TO>(mag, neg, E);
   }
-  s2_store_c<CPLX>(h, row, col, a_re, a_im, b_re, b_im, C, ldc);
+  s2_store_c<CPLX, TO>(h, row, col, a_re, a_im, b_re, b_im, C, ldc);
 }
 
-template <bool CPLX>
+template <bool CPLX, typename TO = double>
 __global__ __launch_bounds__(256) void k_s2_crt(CrtArgs ca, int M, int N, const int8_t* __restrict__ res,
                                                 const int32_t* __restrict__ sigma, const int32_t* __restrict__ tau,
-                                                double a_re, double a_im, double b_re, double b_im,
-                                                double* __restrict__ C, int64_t ldc) {
-  s2_crt_block<CPLX>(ca, M, N, res, sigma, tau, a_re, a_im, b_re, b_im, C, ldc, blockIdx.x);
+                                                TO a_re, TO a_im, TO b_re, TO b_im, TO* __restrict__ C, int64_t ldc) {
+  s2_crt_block<CPLX, TO>(ca, M, N, res, sigma, tau, a_re, a_im, b_re, b_im, C, ldc, blockIdx.x);
 }
 
 // ------------------------------------------------------------ host side
@@ -863,7 +873,8 @@ void s2_targets(int s, int& ta, int& tb) {
   crt_args(s, ca, ta, tb);
 }
 
-hipError_t s2_split_rows(int s, bool cplx, const double* X, int64_t ldx, int64_t rows, int64_t K, int32_t* sigma,
+template <typename T>
+static hipError_t split_rows_t(int s, bool cplx, const T* X, int64_t ldx, int64_t rows, int64_t K, int32_t* sigma,
                          int8_t* packed, hipStream_t st) {
   int ta, tb;
   s2_targets(s, ta, tb);
@@ -871,15 +882,16 @@ hipError_t s2_split_rows(int s, bool cplx, const double* X, int64_t ldx, int64_t
   if (rp == 0) return hipSuccess;
   S2Args sa{s, ta};
   if (cplx)
-    hipLaunchKernelGGL(k_s2_split_rows<true>, dim3((unsigned)(rp / S2_ROWS_PER_BLOCK)), dim3(256), 0, st, X, ldx, rows, K, kp, rp,
+    hipLaunchKernelGGL((k_s2_split_rows<true, T>), dim3((unsigned)(rp / S2_ROWS_PER_BLOCK)), dim3(256), 0, st, X, ldx, rows, K, kp, rp,
                        sa, sigma, packed);
   else
-    hipLaunchKernelGGL(k_s2_split_rows<false>, dim3((unsigned)(rp / S2_ROWS_PER_BLOCK)), dim3(256), 0, st, X, ldx, rows, K, kp,
+    hipLaunchKernelGGL((k_s2_split_rows<false, T>), dim3((unsigned)(rp / S2_ROWS_PER_BLOCK)), dim3(256), 0, st, X, ldx, rows, K, kp,
                        rp, sa, sigma, packed);
   return hipGetLastError();
 }
 
-hipError_t s2_split_cols(int s, bool cplx, const double* X, int64_t ldx, int64_t K, int64_t cols, int32_t* tau,
+template <typename T>
+static hipError_t split_cols_t(int s, bool cplx, const T* X, int64_t ldx, int64_t K, int64_t cols, int32_t* tau,
                          int8_t* packed, hipStream_t st) {
   int ta, tb;
   s2_targets(s, ta, tb);
@@ -893,29 +905,49 @@ hipError_t s2_split_cols(int s, bool cplx, const double* X, int64_t ldx, int64_t
     const dim3 g2((unsigned)((cols + 63) / 64), (unsigned)((K + S2_COLS_KB - 1) / S2_COLS_KB));
     hipLaunchKernelGGL(k_s2_col_stats_init, dim3(g1), dim3(256), 0, st, cols, emax, S);
     if (cplx) {
-      hipLaunchKernelGGL(k_s2_col_emax<true>, g2, dim3(256), 0, st, X, ldx, K, cols, emax);
-      hipLaunchKernelGGL(k_s2_col_norm<true>, g2, dim3(256), 0, st, X, ldx, K, cols, emax, S);
+      hipLaunchKernelGGL((k_s2_col_emax<true, T>), g2, dim3(256), 0, st, X, ldx, K, cols, emax);
+      hipLaunchKernelGGL((k_s2_col_norm<true, T>), g2, dim3(256), 0, st, X, ldx, K, cols, emax, S);
     } else {
-      hipLaunchKernelGGL(k_s2_col_emax<false>, g2, dim3(256), 0, st, X, ldx, K, cols, emax);
-      hipLaunchKernelGGL(k_s2_col_norm<false>, g2, dim3(256), 0, st, X, ldx, K, cols, emax, S);
+      hipLaunchKernelGGL((k_s2_col_emax<false, T>), g2, dim3(256), 0, st, X, ldx, K, cols, emax);
+      hipLaunchKernelGGL((k_s2_col_norm<false, T>), g2, dim3(256), 0, st, X, ldx, K, cols, emax, S);
     }
     hipLaunchKernelGGL(k_s2_col_finish, dim3(g1), dim3(256), 0, st, cols, tb, emax, S, tau);
   } else if (cols > 0) {
     const unsigned gx = (unsigned)((cols + 31) / 32);
     if (cplx)
-      hipLaunchKernelGGL(k_s2_col_scales<true>, dim3(gx), dim3(256), 0, st, X, ldx, K, cols, tb, tau);
+      hipLaunchKernelGGL((k_s2_col_scales<true, T>), dim3(gx), dim3(256), 0, st, X, ldx, K, cols, tb, tau);
     else
-      hipLaunchKernelGGL(k_s2_col_scales<false>, dim3(gx), dim3(256), 0, st, X, ldx, K, cols, tb, tau);
+      hipLaunchKernelGGL((k_s2_col_scales<false, T>), dim3(gx), dim3(256), 0, st, X, ldx, K, cols, tb, tau);
   }
   if (cp > 0 && kp > 0) {
     if (cplx)
-      hipLaunchKernelGGL(k_s2_split_cols<true>, dim3((unsigned)(cp / S2_COL_BLOCK), (unsigned)(kp / OZK_K_CHUNK)),
+      hipLaunchKernelGGL((k_s2_split_cols<true, T>), dim3((unsigned)(cp / S2_COL_BLOCK), (unsigned)(kp / OZK_K_CHUNK)),
                          dim3(256), 0, st, X, ldx, K, cols, kp, cp, s, tau, packed);
     else
-      hipLaunchKernelGGL(k_s2_split_cols<false>, dim3((unsigned)(cp / S2_COL_BLOCK), (unsigned)(kp / OZK_K_CHUNK)),
+      hipLaunchKernelGGL((k_s2_split_cols<false, T>), dim3((unsigned)(cp / S2_COL_BLOCK), (unsigned)(kp / OZK_K_CHUNK)),
                          dim3(256), 0, st, X, ldx, K, cols, kp, cp, s, tau, packed);
   }
   return hipGetLastError();
+}
+
+hipError_t s2_split_rows(int s, bool cplx, const double* X, int64_t ldx, int64_t rows, int64_t K, int32_t* sigma,
+                         int8_t* packed, hipStream_t st) {
+  return split_rows_t(s, cplx, X, ldx, rows, K, sigma, packed, st);
+}
+
+hipError_t s2_split_rows(int s, bool cplx, const float* X, int64_t ldx, int64_t rows, int64_t K, int32_t* sigma,
+                         int8_t* packed, hipStream_t st) {
+  return split_rows_t(s, cplx, X, ldx, rows, K, sigma, packed, st);
+}
+
+hipError_t s2_split_cols(int s, bool cplx, const double* X, int64_t ldx, int64_t K, int64_t cols, int32_t* tau,
+                         int8_t* packed, hipStream_t st) {
+  return split_cols_t(s, cplx, X, ldx, K, cols, tau, packed, st);
+}
+
+hipError_t s2_split_cols(int s, bool cplx, const float* X, int64_t ldx, int64_t K, int64_t cols, int32_t* tau,
+                         int8_t* packed, hipStream_t st) {
+  return split_cols_t(s, cplx, X, ldx, K, cols, tau, packed, st);
 }
 
 template <bool CPLX, int V>
@@ -963,22 +995,34 @@ hipError_t s2_gemm_mod(int s, bool cplx, int64_t M, int64_t N, int64_t K, const 
               : launch_gemm_mod<false, 0>(s, M, N, K, Ap, Bp, out, raster, group, st);
 }
 
-hipError_t s2_crt(int s, bool cplx, int64_t M, int64_t N, const int8_t* res, const int32_t* sigma,
-                  const int32_t* tau, const double* alpha, const double* beta, double* C, int64_t ldc,
-                  hipStream_t st) {
+template <typename TO>
+static hipError_t crt_t(int s, bool cplx, int64_t M, int64_t N, const int8_t* res, const int32_t* sigma,
+                       const int32_t* tau, const TO* alpha, const TO* beta, TO* C, int64_t ldc, hipStream_t st) {
   if (M == 0 || N == 0) return hipSuccess;
   CrtArgs ca;
   int ta, tb;
   crt_args(s, ca, ta, tb);
   const int64_t n = M * N;
-  const double ai = cplx ? alpha[1] : 0.0, bi = cplx ? beta[1] : 0.0;
+  const TO ai = cplx ? alpha[1] : (TO)0, bi = cplx ? beta[1] : (TO)0;
   if (cplx)
-    hipLaunchKernelGGL(k_s2_crt<true>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, ca, (int)M, (int)N,
+    hipLaunchKernelGGL((k_s2_crt<true, TO>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, ca, (int)M, (int)N,
                        res, sigma, tau, alpha[0], ai, beta[0], bi, C, ldc);
   else
-    hipLaunchKernelGGL(k_s2_crt<false>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, ca, (int)M, (int)N,
+    hipLaunchKernelGGL((k_s2_crt<false, TO>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, ca, (int)M, (int)N,
                        res, sigma, tau, alpha[0], ai, beta[0], bi, C, ldc);
   return hipGetLastError();
+}
+
+hipError_t s2_crt(int s, bool cplx, int64_t M, int64_t N, const int8_t* res, const int32_t* sigma,
+                  const int32_t* tau, const double* alpha, const double* beta, double* C, int64_t ldc,
+                  hipStream_t st) {
+  return crt_t(s, cplx, M, N, res, sigma, tau, alpha, beta, C, ldc, st);
+}
+
+hipError_t s2_crt(int s, bool cplx, int64_t M, int64_t N, const int8_t* res, const int32_t* sigma,
+                  const int32_t* tau, const float* alpha, const float* beta, float* C, int64_t ldc,
+                  hipStream_t st) {
+  return crt_t(s, cplx, M, N, res, sigma, tau, alpha, beta, C, ldc, st);
 }
 
 // ------------------------------------------------- fused CRT epilogue

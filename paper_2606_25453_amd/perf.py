@@ -6,7 +6,8 @@ Workloads (inputs resident in HBM, every kernel of the call timed with HIP
 events on the launch stream, after untimed warm-up calls and tuning):
 * Scheme I DGEMM, square n in {4096, 8192}, p in {6, 7, 8};
 * Scheme I SGEMM (binary32 in and out), square n in {4096, 8192}, p in {2, 3, 4},
-  against native float32 torch.matmul;
+  against native float32 torch.matmul; Scheme II SGEMM (s = 8, 10) and 3M
+  CGEMM (s = 8) at 4096^3 against native float32 / complex64;
 * Scheme II DGEMM 4096^3 and 8192 x 8192 x 2048, s in {14, 16};
 * Scheme II 3M ZGEMM 4096^3 and 8192^3, s = 16;
 * Scheme II DGEMM with the CRT fused into the GEMM against the separate
@@ -103,7 +104,7 @@ def sgemm(torch, ctx, n, p, reps, inputs=None):
     C = torch.empty((n, n), dtype=torch.float32, device=dev)
     ws = torch.empty(ozk.ozk_workspace_size(ctx, ozk.OZK_OP_DGEMM, ozk.OZK_SCHEME1, n, n, n, p), dtype=torch.uint8,
                      device=dev)
-    ms = time_call(torch, lambda: ozk.ozk_sgemm(ctx, p, A32, B32, C, ws=ws), reps)
+    ms = time_call(torch, lambda: ozk.ozk_sgemm(ctx, ozk.OZK_SCHEME1, p, A32, B32, C, ws=ws), reps)
     torch.backends.cuda.matmul.allow_tf32 = False
     ms_nat = time_call(torch, lambda: torch.matmul(A32, B32, out=C), reps)
     ops = p * (p + 1) * n ** 3
@@ -111,6 +112,33 @@ def sgemm(torch, ctx, n, p, reps, inputs=None):
             "tflops": round(2.0 * n ** 3 / ms / 1e9, 3), "gemm_ms": round(gemm_ms, 4),
             "int8_ops": ops, "gemm_frac_int8_peak": round(ops / gemm_ms / 1e9 / INT8_PEAK_TOPS, 4),
             "native_fp32_tflops": round(2.0 * n ** 3 / ms_nat / 1e9, 3)}
+
+
+def scheme2_f32(torch, ctx, n, s, cplx, reps):
+    """Scheme II SGEMM or 3M CGEMM (binary32 in and out) against native
+    float32 / complex64 torch.matmul (TF32 off); the GEMM step is tuned on
+    the widened operands."""
+    A = device_phi(torch, n, n, 1.0, 81, cplx)
+    B = device_phi(torch, n, n, 1.0, 82, cplx)
+    op = ozk.OZK_OP_ZGEMM if cplx else ozk.OZK_OP_DGEMM
+    _, cfg, gemm_ms = ozk.ozk_tune(ctx, op, ozk.OZK_SCHEME2, s, A, B, reps=2)
+    A32 = A.to(torch.complex64 if cplx else torch.float32)
+    B32 = B.to(torch.complex64 if cplx else torch.float32)
+    del A, B
+    C = torch.empty((n, n), dtype=A32.dtype, device="cuda:0")
+    ws = torch.empty(ozk.ozk_workspace_size(ctx, op, ozk.OZK_SCHEME2, n, n, n, s), dtype=torch.uint8, device="cuda:0")
+    if cplx:
+        ms = time_call(torch, lambda: ozk.ozk_cgemm_3m(ctx, s, A32, B32, C, ws=ws), reps)
+    else:
+        ms = time_call(torch, lambda: ozk.ozk_sgemm(ctx, ozk.OZK_SCHEME2, s, A32, B32, C, ws=ws), reps)
+    torch.backends.cuda.matmul.allow_tf32 = False
+    ms_nat = time_call(torch, lambda: torch.matmul(A32, B32, out=C), reps)
+    flops = (8.0 if cplx else 2.0) * n ** 3
+    ops = (6 if cplx else 2) * s * n ** 3
+    return {"path": "scheme2_cgemm_3m" if cplx else "scheme2_sgemm", "M": n, "N": n, "K": n, "s": s, "config": cfg,
+            "ms": round(ms, 4), "tflops": round(flops / ms / 1e9, 3), "gemm_ms": round(gemm_ms, 4),
+            "int8_ops": ops, "gemm_frac_int8_peak": round(ops / gemm_ms / 1e9 / INT8_PEAK_TOPS, 4),
+            "native_tflops": round(flops / ms_nat / 1e9, 3)}
 
 
 def scheme2(torch, ctx, M, N, K, s, cplx, reps, inputs=None):
@@ -234,7 +262,8 @@ def main():
     ap.add_argument("--quick", action="store_true", help="the smaller sizes only")
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--out", default=None, help="also append the lines to this file")
-    ap.add_argument("--only", default=None, help="comma-separated subset of s1, sgemm, s2, fused, batch, auto")
+    ap.add_argument("--only", default=None,
+                    help="comma-separated subset of s1, sgemm, s2, s2f32, fused, batch, auto")
     ap.add_argument("--sweep", action="store_true", help="the size sweeps instead of the default workloads")
     args = ap.parse_args()
     import torch
@@ -251,6 +280,7 @@ def main():
     jobs += [("s2", 4096, 4096, 4096, 16, True)]
     jobs += [("fused", 4096, 4096, 4096, 14), ("fused", 8192, 8192, 2048, 16)]
     jobs += [("sgemm", 4096, p) for p in (2, 3, 4)]
+    jobs += [("s2f32", 4096, s, False) for s in (8, 10)] + [("s2f32", 4096, 8, True)]
     jobs += [("batch", 256, 16)]
     jobs += [("auto", 4096, 1e-13)]
     if not args.quick:
@@ -273,6 +303,8 @@ def main():
             r = fused_crt(torch, ctx, job[1], job[2], job[3], job[4], args.reps)
         elif job[0] == "sgemm":
             r = sgemm(torch, ctx, job[1], job[2], args.reps)
+        elif job[0] == "s2f32":
+            r = scheme2_f32(torch, ctx, job[1], job[2], job[3], args.reps)
         else:
             r = batch(torch, ctx, job[1], job[2], args.reps)
         line = json.dumps(r)

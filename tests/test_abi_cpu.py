@@ -49,7 +49,7 @@ def test_packed_sizes_and_k_split(lib):
 def test_null_context_is_rejected(lib):
     assert lib.ozk_dgemm(None, 1, 4, 1, 1, 1, 1.0, None, 1, None, 1, 0.0, None, 1, None, 0, None) == \
         ozk.OZK_ERR_INVALID_ARG
-    assert lib.ozk_sgemm(None, 4, 1, 1, 1, 1.0, None, 1, None, 1, 0.0, None, 1, None, 0, None) == \
+    assert lib.ozk_sgemm(None, 1, 4, 1, 1, 1, 1.0, None, 1, None, 1, 0.0, None, 1, None, 0, None) == \
         ozk.OZK_ERR_INVALID_ARG
     assert lib.ozk_status_string(ozk.OZK_ERR_WORKSPACE).decode() == "workspace missing or too small"
     assert lib.ozk_version().decode().count(".") == 2

@@ -285,7 +285,7 @@ def test_sgemm_bit_exact(ctx, p, shape):
     M, N, K = shape
     A = f32(synth.phi_matrix(M, K, 1.0, 6000 + 10 * p + M))
     B = f32(synth.phi_matrix(K, N, 1.0, 6100 + 10 * p + N))
-    C = host(ozk.ozk_sgemm(ctx, p, dev(A), dev(B), C=dev(np.full((M, N), np.nan, np.float32))))
+    C = host(ozk.ozk_sgemm(ctx, ozk.OZK_SCHEME1, p, dev(A), dev(B), C=dev(np.full((M, N), np.nan, np.float32))))
     assert C.dtype == np.float32 and np.array_equal(C, oracle.s1_sgemm(A, B, p))
 
 
@@ -307,27 +307,27 @@ def test_sgemm_edges_alpha_beta_and_empty(ctx):
     B[7, 6] = np.nan
     B[:, 8] *= np.float32(1e-20)
     B[:, 64] *= np.float32(1e20)
-    got = host(ozk.ozk_sgemm(ctx, p, dev(A), dev(B), C=dev(C0), alpha=-1.5, beta=0.5))
+    got = host(ozk.ozk_sgemm(ctx, ozk.OZK_SCHEME1, p, dev(A), dev(B), C=dev(C0), alpha=-1.5, beta=0.5))
     ref = oracle.s1_sgemm(A, B, p, alpha=-1.5, beta=0.5, C=C0)
     assert np.array_equal(np.isnan(got), np.isnan(ref))
     ok = ~np.isnan(ref)
     assert np.array_equal(got[ok], ref[ok])
-    got0 = host(ozk.ozk_sgemm(ctx, p, dev(A), dev(B)))
+    got0 = host(ozk.ozk_sgemm(ctx, ozk.OZK_SCHEME1, p, dev(A), dev(B)))
     ref0 = oracle.s1_sgemm(A, B, p)
     ok0 = ~np.isnan(ref0)
     assert np.array_equal(np.isnan(got0), np.isnan(ref0)) and np.array_equal(got0[ok0], ref0[ok0])
     assert 0 < abs(ref0[65, 8]) < np.finfo(np.float32).tiny and np.isinf(ref0[2, 64])
     C = dev(np.full((5, 3), 7.0, np.float32))
-    ozk.ozk_sgemm(ctx, p, dev(np.ones((5, 0), np.float32)), dev(np.ones((0, 3), np.float32)), C=C)
+    ozk.ozk_sgemm(ctx, ozk.OZK_SCHEME1, p, dev(np.ones((5, 0), np.float32)), dev(np.ones((0, 3), np.float32)), C=C)
     assert np.array_equal(host(C), np.zeros((5, 3), np.float32))
     one = dev(np.ones((4, 4), np.float32))
     big = torch.empty(1 << 20, dtype=torch.uint8, device="cuda:0")
     for bad in (0, 9):
         with pytest.raises(ozk.OzkError) as ei:
-            ozk.ozk_sgemm(ctx, bad, one, one, ws=big)
+            ozk.ozk_sgemm(ctx, ozk.OZK_SCHEME1, bad, one, one, ws=big)
         assert ei.value.status == ozk.OZK_ERR_UNSUPPORTED
     with pytest.raises(ozk.OzkError) as ei:
-        ozk.ozk_sgemm(ctx, p, one, one, ws=torch.empty(1, dtype=torch.uint8, device="cuda:0"))
+        ozk.ozk_sgemm(ctx, ozk.OZK_SCHEME1, p, one, one, ws=torch.empty(1, dtype=torch.uint8, device="cuda:0"))
     assert ei.value.status == ozk.OZK_ERR_WORKSPACE
 
 
@@ -342,7 +342,7 @@ def test_sgemm_k_runs_and_configs(ctx):
     try:
         for cfg in [(0, 0, 4, 1), (1, 1, 2, 3), (2, 0, 8, 5), (3, 1, 1, 2)]:
             ozk.ozk_config_set(c, ozk.OZK_OP_DGEMM, ozk.OZK_SCHEME1, p, M, N, K, cfg)
-            assert np.array_equal(host(ozk.ozk_sgemm(c, p, dev(A), dev(B))), ref), cfg
+            assert np.array_equal(host(ozk.ozk_sgemm(c, ozk.OZK_SCHEME1, p, dev(A), dev(B))), ref), cfg
     finally:
         c.close()
 
@@ -356,7 +356,7 @@ def test_sgemm_1024_against_oracle_and_native_error(ctx):
     A = f32(synth.phi_matrix(M, K, 1.0, 51))
     B = f32(synth.phi_matrix(K, N, 1.0, 52))
     a, b = dev(A), dev(B)
-    C = host(ozk.ozk_sgemm(ctx, p, a, b))
+    C = host(ozk.ozk_sgemm(ctx, ozk.OZK_SCHEME1, p, a, b))
     assert np.array_equal(C, oracle.s1_sgemm(A, B, p))
     A64, B64 = A.astype(np.float64), B.astype(np.float64)
     ri, ci = np.arange(0, M, 97), np.arange(0, N, 89)

@@ -330,3 +330,74 @@ def test_fused_crt_large_sampled():
         assert np.array_equal(C[rows, cols], s2.s2_entries(A, B, s, rows, cols))
     finally:
         c.close()
+
+
+# ------------------------------------------------ binary32 operands and results
+
+@pytest.mark.parametrize("s", [1, 8, 11, 16, 20])
+@pytest.mark.parametrize("shape", [(1, 1, 1), (63, 65, 127), (129, 130, 95)])
+def test_sgemm_scheme2_bit_exact(ctx, s, shape):
+    M, N, K = shape
+    A = synth.phi_matrix(M, K, 1.0, 1600 + s + M).astype(np.float32)
+    B = synth.phi_matrix(K, N, 1.0, 1700 + s + N).astype(np.float32)
+    C = host(ozk.ozk_sgemm(ctx, ozk.OZK_SCHEME2, s, dev(A), dev(B)))
+    assert C.dtype == np.float32 and np.array_equal(C, s2.s2_sgemm(A, B, s))
+
+
+def test_sgemm_scheme2_edges_and_long_k():
+    """Zero, tiny and huge rows, non-finite entries, binary32 underflow and
+    overflow, alpha/beta; and K past the column-scale split (long-K path)."""
+    s, M, N, K = 10, 40, 30, 50
+    A = synth.phi_matrix(M, K, 1.0, 61).astype(np.float32)
+    B = synth.phi_matrix(K, N, 1.0, 62).astype(np.float32)
+    C0 = synth.phi_matrix(M, N, 1.0, 63).astype(np.float32)
+    A[0] = 0
+    A[1] *= np.float32(1e-38)
+    A[2] *= np.float32(1e30)
+    A[3, 4] = np.inf
+    A[4] *= np.float32(1e-20)
+    B[:, 5] = 0
+    B[7, 6] = np.nan
+    B[:, 8] *= np.float32(1e-20)
+    B[:, 9] *= np.float32(1e20)
+    c = ozk.Context(0)
+    try:
+        got = host(ozk.ozk_sgemm(c, ozk.OZK_SCHEME2, s, dev(A), dev(B), C=dev(C0), alpha=-1.5, beta=0.5))
+        ref = s2.s2_sgemm(A, B, s, alpha=-1.5, beta=0.5, C=C0)
+        assert np.array_equal(np.isnan(got), np.isnan(ref))
+        ok = ~np.isnan(ref)
+        assert np.array_equal(got[ok], ref[ok])
+        ref0 = s2.s2_sgemm(A, B, s)
+        got0 = host(ozk.ozk_sgemm(c, ozk.OZK_SCHEME2, s, dev(A), dev(B)))
+        ok0 = ~np.isnan(ref0)
+        assert np.array_equal(got0[ok0], ref0[ok0]) and np.isinf(ref0[2, 9]) and 0 < abs(ref0[4, 8]) < 1.2e-38
+        # long K: the split column statistics
+        A2 = synth.phi_matrix(20, 1100, 1.0, 64).astype(np.float32)
+        B2 = synth.phi_matrix(1100, 300, 1.0, 65).astype(np.float32)
+        assert np.array_equal(host(ozk.ozk_sgemm(c, ozk.OZK_SCHEME2, 9, dev(A2), dev(B2))), s2.s2_sgemm(A2, B2, 9))
+    finally:
+        c.close()
+
+
+@pytest.mark.parametrize("s", [4, 9, 16])
+@pytest.mark.parametrize("shape", [(1, 1, 1), (63, 65, 70), (130, 40, 96)])
+def test_cgemm_3m_bit_exact(ctx, s, shape):
+    M, N, K = shape
+    A = synth.complex_phi_matrix(M, K, 1.0, 1800 + s, 1801 + s).astype(np.complex64)
+    B = synth.complex_phi_matrix(K, N, 1.0, 1802 + s, 1803 + s).astype(np.complex64)
+    C = host(ozk.ozk_cgemm_3m(ctx, s, dev(A), dev(B)))
+    assert C.dtype == np.complex64 and np.array_equal(C, s2.z3m_cgemm(A, B, s))
+
+
+def test_cgemm_3m_alpha_beta():
+    s, M, N, K = 10, 30, 20, 40
+    A = synth.complex_phi_matrix(M, K, 1.0, 1900, 1901).astype(np.complex64)
+    B = synth.complex_phi_matrix(K, N, 1.0, 1902, 1903).astype(np.complex64)
+    C0 = synth.complex_phi_matrix(M, N, 1.0, 1904, 1905).astype(np.complex64)
+    al, be = 0.5 - 2j, -1 + 0.25j
+    c = ozk.Context(0)
+    try:
+        got = host(ozk.ozk_cgemm_3m(c, s, dev(A), dev(B), C=dev(C0), alpha=al, beta=be))
+        assert np.array_equal(got, s2.z3m_cgemm(A, B, s, alpha=al, beta=be, C=C0))
+    finally:
+        c.close()
