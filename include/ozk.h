@@ -155,6 +155,26 @@ ozk_status ozk_dgemm(ozk_ctx* ctx, ozk_scheme scheme, int p_or_s, int64_t M,
                      double* C, int64_t ldc, void* ws, size_t ws_bytes,
                      hipStream_t stream);
 
+/* The unfused Scheme I baseline, as an ablation of the fused kernel (the
+ * naive scheme of the paper's traffic model, Sec. III, Eq. 9): the same
+ * pre-pass as ozk_dgemm, then one INT8 GEMM per slice pair (t, u), t + u < p,
+ * each writing its INT32 result to HBM, then a pass that reads the
+ * p(p+1)/2 planes back, forms Z exactly and rounds once.  The result is
+ * bit-identical to ozk_dgemm(OZK_SCHEME1, p); only the INT32 round trip
+ * (4 p(p+1) M N bytes written and read) and the p(p+1)/2 operand passes
+ * differ.  1 <= p <= 8, K <= 131072 (one INT32 plane per pair stays exact).
+ * Workspace: ozk_s1_unfused_workspace_size bytes (the packed operands plus
+ * 2 p(p+1) M N bytes of planes).  Device pointers, caller-owned memory,
+ * asynchronous on `stream`; errors as ozk_dgemm (OZK_ERR_UNSUPPORTED, arg 5,
+ * for K > 131072). */
+ozk_status ozk_s1_unfused_workspace_size(ozk_ctx* ctx, int p, int64_t M,
+                                         int64_t N, int64_t K, size_t* bytes);
+ozk_status ozk_s1_dgemm_unfused(ozk_ctx* ctx, int p, int64_t M, int64_t N,
+                                int64_t K, double alpha, const double* A,
+                                int64_t lda, const double* B, int64_t ldb,
+                                double beta, double* C, int64_t ldc, void* ws,
+                                size_t ws_bytes, hipStream_t stream);
+
 /* Emulated SGEMM, C = alpha*A*B + beta*C in binary32 (the paper's FP32-level
  * operating points: Scheme I with p = 1..4, Scheme II with s = 8..11;
  * Sec. V-D).  A (M x K, lda) and B (K x N, ldb) are row-major binary32,

@@ -50,7 +50,7 @@ class OzkGemmConfig(ctypes.Structure):
 EXPORTS = (
     "ozk_create", "ozk_destroy", "ozk_last_arg", "ozk_status_string", "ozk_version",
     "ozk_s1_packed_bytes", "ozk_s2_packed_bytes", "ozk_s1_k_split", "ozk_workspace_size",
-    "ozk_dgemm", "ozk_sgemm", "ozk_zgemm_3m", "ozk_cgemm_3m", "ozk_s1_split_rows", "ozk_s1_split_cols", "ozk_s1_gemm",
+    "ozk_dgemm", "ozk_sgemm", "ozk_zgemm_3m", "ozk_cgemm_3m", "ozk_s1_dgemm_unfused", "ozk_s1_unfused_workspace_size", "ozk_s1_split_rows", "ozk_s1_split_cols", "ozk_s1_gemm",
     "ozk_s1_diagonals", "ozk_s2_split_rows", "ozk_s2_split_cols", "ozk_s2_gemm_mod", "ozk_s2_crt",
     "ozk_selector_load", "ozk_select", "ozk_dgemm_auto", "ozk_mlp_forward", "ozk_mlp_grad", "ozk_mlp_adam",
     "ozk_ref_dd", "ozk_batch_plan_create", "ozk_gemm_batched", "ozk_batch_plan_destroy",
@@ -91,6 +91,8 @@ def _lib() -> ctypes.CDLL:
         "ozk_dgemm": (I, [P, I, I, I64, I64, I64, D, P, I64, P, I64, D, P, I64, P, SZ, P]),
         "ozk_sgemm": (I, [P, I, I, I64, I64, I64, ctypes.c_float, P, I64, P, I64, ctypes.c_float, P, I64, P, SZ, P]),
         "ozk_cgemm_3m": (I, [P, I, I64, I64, I64, P, P, I64, P, I64, P, P, I64, P, SZ, P]),
+        "ozk_s1_dgemm_unfused": (I, [P, I, I64, I64, I64, D, P, I64, P, I64, D, P, I64, P, SZ, P]),
+        "ozk_s1_unfused_workspace_size": (I, [P, I, I64, I64, I64, ctypes.POINTER(SZ)]),
         "ozk_zgemm_3m": (I, [P, I, I64, I64, I64, P, P, I64, P, I64, P, P, I64, P, SZ, P]),
         "ozk_s1_split_rows": (I, [P, I, I64, I64, P, I64, P, P, P]),
         "ozk_s1_split_cols": (I, [P, I, I64, I64, P, I64, P, P, P]),
@@ -253,6 +255,30 @@ def ozk_sgemm(ctx: Context, scheme: int, p_or_s: int, A, B, C=None, alpha: float
     st = _lib().ozk_sgemm(ctx.handle, scheme, p_or_s, M, N, K, float(alpha), _ptr(A), _ld(A), _ptr(B), _ld(B),
                           float(beta), _ptr(C), _ld(C), _ptr(ws), ws.numel(), _stream(stream))
     _check("ozk_sgemm", st, ctx)
+    return C
+
+
+def ozk_s1_unfused_workspace_size(ctx: Context, p: int, M: int, N: int, K: int) -> int:
+    size = ctypes.c_size_t()
+    _check("ozk_s1_unfused_workspace_size",
+           _lib().ozk_s1_unfused_workspace_size(ctx.handle, p, M, N, K, ctypes.byref(size)), ctx)
+    return int(size.value)
+
+
+def ozk_s1_dgemm_unfused(ctx: Context, p: int, A, B, C=None, alpha: float = 1.0, beta: float = 0.0, ws=None,
+                         stream=None):
+    """The unfused Scheme I baseline (one GEMM per slice pair, INT32 planes
+    through HBM); bit-identical to ozk_dgemm(OZK_SCHEME1, p)."""
+    import torch
+    M, K = A.shape
+    N = B.shape[1]
+    if C is None:
+        C = torch.empty((M, N), dtype=torch.float64, device=A.device)
+    if ws is None:
+        ws = _workspace(ozk_s1_unfused_workspace_size(ctx, p, M, N, K), A.device)
+    st = _lib().ozk_s1_dgemm_unfused(ctx.handle, p, M, N, K, float(alpha), _ptr(A), _ld(A), _ptr(B), _ld(B),
+                                     float(beta), _ptr(C), _ld(C), _ptr(ws), ws.numel(), _stream(stream))
+    _check("ozk_s1_dgemm_unfused", st, ctx)
     return C
 
 

@@ -428,6 +428,54 @@ ozk_status ozk_dgemm(ozk_ctx* ctx, ozk_scheme scheme, int p_or_s, int64_t M, int
                         pl.total - pl.off_z, nullptr, stream, cfg);
 }
 
+// The unfused baseline: the DGEMM pre-pass, then one INT8 GEMM per slice
+// pair writing INT32 planes, then the reconstruction.
+static size_t s1_unfused_ws(const ozk_ctx* ctx, int p, int64_t M, int64_t N, int64_t K, S1Plan& pl) {
+  pl = s1_plan(ctx, p, M, N, K, 1);
+  return align256(pl.off_z) + (size_t)ozk::s1_unfused_planes_bytes(p, M, N);
+}
+
+ozk_status ozk_s1_unfused_workspace_size(ozk_ctx* ctx, int p, int64_t M, int64_t N, int64_t K, size_t* bytes) {
+  if (!ctx || !bytes) return OZK_ERR_INVALID_ARG;
+  ctx->last_arg = 0;
+  if (p < 1 || p > OZK_MAX_P) return fail(ctx, OZK_ERR_UNSUPPORTED, 2);
+  if (bad_dims(M, N, K)) return fail(ctx, OZK_ERR_INVALID_ARG, 3);
+  S1Plan pl;
+  *bytes = s1_unfused_ws(ctx, p, M, N, K, pl);
+  return OZK_OK;
+}
+
+ozk_status ozk_s1_dgemm_unfused(ozk_ctx* ctx, int p, int64_t M, int64_t N, int64_t K, double alpha, const double* A,
+                                int64_t lda, const double* B, int64_t ldb, double beta, double* C, int64_t ldc,
+                                void* ws, size_t ws_bytes, hipStream_t stream) {
+  if (!ctx) return OZK_ERR_INVALID_ARG;
+  ctx->last_arg = 0;
+  if (p < 1 || p > OZK_MAX_P) return fail(ctx, OZK_ERR_UNSUPPORTED, 2);
+  if (bad_dims(M, N, K)) return fail(ctx, OZK_ERR_INVALID_ARG, M < 0 ? 3 : (N < 0 ? 4 : 5));
+  if (K > 131072) return fail(ctx, OZK_ERR_UNSUPPORTED, 5);
+  if (!A && M > 0 && K > 0) return fail(ctx, OZK_ERR_INVALID_ARG, 7);
+  if (lda < (K > 0 ? K : 1)) return fail(ctx, OZK_ERR_INVALID_ARG, 8);
+  if (!B && K > 0 && N > 0) return fail(ctx, OZK_ERR_INVALID_ARG, 9);
+  if (ldb < (N > 0 ? N : 1)) return fail(ctx, OZK_ERR_INVALID_ARG, 10);
+  if (!C && M > 0 && N > 0) return fail(ctx, OZK_ERR_INVALID_ARG, 12);
+  if (ldc < (N > 0 ? N : 1)) return fail(ctx, OZK_ERR_INVALID_ARG, 13);
+  S1Plan pl;
+  const size_t need = s1_unfused_ws(ctx, p, M, N, K, pl);
+  if (!ws || ws_bytes < need) return fail(ctx, OZK_ERR_WORKSPACE, 15);
+  if (M == 0 || N == 0) return OZK_OK;
+  char* w = (char*)ws;
+  int32_t* e = (int32_t*)(w + pl.off_e);
+  int32_t* f = (int32_t*)(w + pl.off_f);
+  int8_t* Ap = (int8_t*)(w + pl.off_a);
+  int8_t* Bp = (int8_t*)(w + pl.off_b);
+  int32_t* planes = (int32_t*)(w + align256(pl.off_z));
+  hipError_t err = ozk::s1_split_rows(p, A, lda, M, K, e, Ap, stream);
+  if (err == hipSuccess) err = ozk::s1_split_cols(p, B, ldb, K, N, f, Bp, stream);
+  if (err == hipSuccess)
+    err = ozk::s1_gemm_unfused(p, M, N, K, Ap, e, Bp, f, alpha, beta, C, ldc, planes, stream);
+  return hip_status(ctx, err);
+}
+
 ozk_status ozk_sgemm(ozk_ctx* ctx, ozk_scheme scheme, int p_or_s, int64_t M, int64_t N, int64_t K, float alpha,
                      const float* A, int64_t lda, const float* B, int64_t ldb, float beta, float* C, int64_t ldc,
                      void* ws, size_t ws_bytes, hipStream_t stream) {

@@ -39,6 +39,12 @@ hipError_t s1_split_rows(int p, const float* X, int64_t ldx, int64_t rows, int64
 hipError_t s1_split_cols(int p, const float* X, int64_t ldx, int64_t K, int64_t cols, int32_t* f,
                          int8_t* packed, hipStream_t st);
 hipError_t s1_gemm(int p, const S1GemmArgs& g, hipStream_t st);
+// The unfused baseline (one GEMM per slice pair, INT32 planes through HBM,
+// then the exact reconstruction); K <= 131072 keeps each plane exact.
+int64_t s1_unfused_planes_bytes(int p, int64_t M, int64_t N);
+hipError_t s1_gemm_unfused(int p, int64_t M, int64_t N, int64_t K, const int8_t* Ap, const int32_t* e,
+                           const int8_t* Bp, const int32_t* f, double alpha, double beta, double* C, int64_t ldc,
+                           int32_t* planes, hipStream_t st);
 // slice count read from device memory (selector output)
 hipError_t s1_slice_auto(const int32_t* p_dev, const double* A, int64_t lda, int64_t M, const double* B, int64_t ldb,
                          int64_t N, int64_t K, const int32_t* e, const int32_t* f, int8_t* Ap, int8_t* Bp,

@@ -10,6 +10,8 @@ events on the launch stream, after untimed warm-up calls and tuning):
   CGEMM (s = 8) at 4096^3 against native float32 / complex64;
 * Scheme II DGEMM 4096^3 and 8192 x 8192 x 2048, s in {14, 16};
 * Scheme II 3M ZGEMM 4096^3 and 8192^3, s = 16;
+* Scheme I DGEMM fused against the unfused baseline (one GEMM per slice
+  pair, INT32 planes through HBM), p = 7 at 4096^3 and 8192^3;
 * Scheme II DGEMM with the CRT fused into the GEMM against the separate
   kernels, 4096^3 at s = 14 and 8192 x 8192 x 2048 at s = 16;
 * a batch of 256 ZGEMMs with M, N, K log-uniform in [64, 1024], s = 16, one
@@ -112,6 +114,28 @@ def sgemm(torch, ctx, n, p, reps, inputs=None):
             "tflops": round(2.0 * n ** 3 / ms / 1e9, 3), "gemm_ms": round(gemm_ms, 4),
             "int8_ops": ops, "gemm_frac_int8_peak": round(ops / gemm_ms / 1e9 / INT8_PEAK_TOPS, 4),
             "native_fp32_tflops": round(2.0 * n ** 3 / ms_nat / 1e9, 3)}
+
+
+def unfused(torch, ctx, n, p, reps):
+    """The fused Scheme I DGEMM against the unfused baseline (one GEMM per
+    slice pair, INT32 planes through HBM; the paper's Eq. 9 against Eq. 10)."""
+    A = device_phi(torch, n, n, 1.0, 91)
+    B = device_phi(torch, n, n, 1.0, 92)
+    C = torch.empty((n, n), dtype=torch.float64, device="cuda:0")
+    _, cfg, gemm_ms = ozk.ozk_tune(ctx, ozk.OZK_OP_DGEMM, ozk.OZK_SCHEME1, p, A, B, C=C, reps=2)
+    ws = torch.empty(ozk.ozk_workspace_size(ctx, ozk.OZK_OP_DGEMM, ozk.OZK_SCHEME1, n, n, n, p), dtype=torch.uint8,
+                     device="cuda:0")
+    ms_fused = time_call(torch, lambda: ozk.ozk_dgemm(ctx, ozk.OZK_SCHEME1, p, A, B, C, ws=ws), reps)
+    ref = C.clone()
+    del ws
+    wsu = torch.empty(ozk.ozk_s1_unfused_workspace_size(ctx, p, n, n, n), dtype=torch.uint8, device="cuda:0")
+    ms_unf = time_call(torch, lambda: ozk.ozk_s1_dgemm_unfused(ctx, p, A, B, C, ws=wsu), reps)
+    pairs = p * (p + 1) // 2
+    return {"path": "scheme1_fused_vs_unfused", "M": n, "N": n, "K": n, "p": p, "ms_fused": round(ms_fused, 4),
+            "tflops_fused": round(2.0 * n ** 3 / ms_fused / 1e9, 3), "ms_unfused": round(ms_unf, 4),
+            "tflops_unfused": round(2.0 * n ** 3 / ms_unf / 1e9, 3), "bit_identical": bool(torch.equal(C, ref)),
+            "model_bytes_fused": p * 2 * n * n + 8 * n * n,
+            "model_bytes_unfused": pairs * 2 * n * n + 8 * pairs * n * n + 8 * n * n}
 
 
 def scheme2_f32(torch, ctx, n, s, cplx, reps):
@@ -263,7 +287,7 @@ def main():
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--out", default=None, help="also append the lines to this file")
     ap.add_argument("--only", default=None,
-                    help="comma-separated subset of s1, sgemm, s2, s2f32, fused, batch, auto")
+                    help="comma-separated subset of s1, sgemm, unfused, s2, s2f32, fused, batch, auto")
     ap.add_argument("--sweep", action="store_true", help="the size sweeps instead of the default workloads")
     args = ap.parse_args()
     import torch
@@ -281,12 +305,14 @@ def main():
     jobs += [("fused", 4096, 4096, 4096, 14), ("fused", 8192, 8192, 2048, 16)]
     jobs += [("sgemm", 4096, p) for p in (2, 3, 4)]
     jobs += [("s2f32", 4096, s, False) for s in (8, 10)] + [("s2f32", 4096, 8, True)]
+    jobs += [("unfused", 4096, 7)]
     jobs += [("batch", 256, 16)]
     jobs += [("auto", 4096, 1e-13)]
     if not args.quick:
         jobs += [("auto", 8192, 1e-13)]
         jobs += [("s1", 8192, p) for p in (6, 7, 8)]
         jobs += [("sgemm", 8192, p) for p in (2, 3, 4)]
+        jobs += [("unfused", 8192, 7)]
         jobs += [("s2", 8192, 8192, 8192, 16, True)]
     if args.only:
         keep = set(args.only.split(","))
@@ -303,6 +329,8 @@ def main():
             r = fused_crt(torch, ctx, job[1], job[2], job[3], job[4], args.reps)
         elif job[0] == "sgemm":
             r = sgemm(torch, ctx, job[1], job[2], args.reps)
+        elif job[0] == "unfused":
+            r = unfused(torch, ctx, job[1], job[2], args.reps)
         elif job[0] == "s2f32":
             r = scheme2_f32(torch, ctx, job[1], job[2], job[3], args.reps)
         else:

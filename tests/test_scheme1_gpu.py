@@ -365,3 +365,21 @@ def test_sgemm_1024_against_oracle_and_native_error(ctx):
     nat = host(torch.matmul(a, b))[np.ix_(ri, ci)].astype(np.float64)
     err_nat = oracle.metrics.e_cw(nat, hi, lo, A64[ri], B64[:, ci])
     assert err < 4 * max(err_nat, 2.0 ** -24), (err, err_nat)
+
+
+# ------------------------------------------------ unfused baseline (ablation)
+
+@pytest.mark.parametrize("p", [1, 3, 7, 8])
+@pytest.mark.parametrize("shape", [(1, 1, 1), (129, 257, 95), (300, 200, 513), (70, 40, 0)])
+def test_unfused_baseline_equals_fused(ctx, p, shape):
+    """One GEMM per slice pair with INT32 planes through HBM, then the
+    reconstruction: the same result as the fused kernel and the oracle."""
+    M, N, K = shape
+    A = synth.phi_matrix(M, K, 1.0, 7000 + p + M)
+    B = synth.phi_matrix(K, N, 1.0, 7100 + p + N)
+    C0 = synth.phi_matrix(M, N, 1.0, 7200 + p)
+    got = host(ozk.ozk_s1_dgemm_unfused(ctx, p, dev(A), dev(B), C=dev(C0), alpha=0.75, beta=-2.0))
+    fused = host(ozk.ozk_dgemm(ctx, ozk.OZK_SCHEME1, p, dev(A), dev(B), C=dev(C0), alpha=0.75, beta=-2.0))
+    assert np.array_equal(got, fused)
+    if K:
+        assert np.array_equal(got, oracle.s1_dgemm(A, B, p, alpha=0.75, beta=-2.0, C=C0))
