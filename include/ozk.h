@@ -155,6 +155,23 @@ ozk_status ozk_dgemm(ozk_ctx* ctx, ozk_scheme scheme, int p_or_s, int64_t M,
                      double* C, int64_t ldc, void* ws, size_t ws_bytes,
                      hipStream_t stream);
 
+/* ozk_dgemm with transposed operands: C = alpha*op(A)*op(B) + beta*C where
+ * op(A) = A (trans_a = 0: A stored M x K, lda >= K) or A^T (trans_a = 1: A
+ * stored K x M, lda >= M), and op(B) = B (trans_b = 0: B stored K x N,
+ * ldb >= N) or B^T (trans_b = 1: B stored N x K, ldb >= K), all row-major.
+ * A transposed operand is read by the other pre-pass kernel (the column
+ * pass for A^T, the row pass for B^T), which writes the same packed layout
+ * and scales, so the result is bit-identical to ozk_dgemm on the explicit
+ * transposes.  Both schemes; workspace as ozk_dgemm.  Errors as ozk_dgemm,
+ * with the argument indices of this signature (trans flags other than 0 or
+ * 1: OZK_ERR_INVALID_ARG, arg 4 or 5; workspace: arg 19). */
+ozk_status ozk_dgemm_t(ozk_ctx* ctx, ozk_scheme scheme, int p_or_s, int trans_a,
+                       int trans_b, int64_t M, int64_t N, int64_t K,
+                       double alpha, const double* A, int64_t lda,
+                       const double* B, int64_t ldb, double beta, double* C,
+                       int64_t ldc, void* ws, size_t ws_bytes,
+                       hipStream_t stream);
+
 /* The unfused Scheme I baseline, as an ablation of the fused kernel (the
  * naive scheme of the paper's traffic model, Sec. III, Eq. 9): the same
  * pre-pass as ozk_dgemm, then one INT8 GEMM per slice pair (t, u), t + u < p,

@@ -50,7 +50,7 @@ class OzkGemmConfig(ctypes.Structure):
 EXPORTS = (
     "ozk_create", "ozk_destroy", "ozk_last_arg", "ozk_status_string", "ozk_version",
     "ozk_s1_packed_bytes", "ozk_s2_packed_bytes", "ozk_s1_k_split", "ozk_workspace_size",
-    "ozk_dgemm", "ozk_sgemm", "ozk_zgemm_3m", "ozk_cgemm_3m", "ozk_s1_dgemm_unfused", "ozk_s1_unfused_workspace_size", "ozk_s1_split_rows", "ozk_s1_split_cols", "ozk_s1_gemm",
+    "ozk_dgemm", "ozk_dgemm_t", "ozk_sgemm", "ozk_zgemm_3m", "ozk_cgemm_3m", "ozk_s1_dgemm_unfused", "ozk_s1_unfused_workspace_size", "ozk_s1_split_rows", "ozk_s1_split_cols", "ozk_s1_gemm",
     "ozk_s1_diagonals", "ozk_s2_split_rows", "ozk_s2_split_cols", "ozk_s2_gemm_mod", "ozk_s2_crt",
     "ozk_selector_load", "ozk_select", "ozk_dgemm_auto", "ozk_mlp_forward", "ozk_mlp_grad", "ozk_mlp_adam",
     "ozk_ref_dd", "ozk_batch_plan_create", "ozk_gemm_batched", "ozk_batch_plan_destroy",
@@ -89,6 +89,7 @@ def _lib() -> ctypes.CDLL:
         "ozk_s1_k_split": (I64, [I]),
         "ozk_workspace_size": (I, [P, I, I, I64, I64, I64, I, ctypes.POINTER(SZ)]),
         "ozk_dgemm": (I, [P, I, I, I64, I64, I64, D, P, I64, P, I64, D, P, I64, P, SZ, P]),
+        "ozk_dgemm_t": (I, [P, I, I, I, I, I64, I64, I64, D, P, I64, P, I64, D, P, I64, P, SZ, P]),
         "ozk_sgemm": (I, [P, I, I, I64, I64, I64, ctypes.c_float, P, I64, P, I64, ctypes.c_float, P, I64, P, SZ, P]),
         "ozk_cgemm_3m": (I, [P, I, I64, I64, I64, P, P, I64, P, I64, P, P, I64, P, SZ, P]),
         "ozk_s1_dgemm_unfused": (I, [P, I, I64, I64, I64, D, P, I64, P, I64, D, P, I64, P, SZ, P]),
@@ -238,6 +239,24 @@ def ozk_dgemm(ctx: Context, scheme: int, p_or_s: int, A, B, C=None, alpha: float
     st = _lib().ozk_dgemm(ctx.handle, scheme, p_or_s, M, N, K, float(alpha), _ptr(A), _ld(A), _ptr(B), _ld(B),
                           float(beta), _ptr(C), _ld(C), _ptr(ws), ws.numel(), _stream(stream))
     _check("ozk_dgemm", st, ctx)
+    return C
+
+
+def ozk_dgemm_t(ctx: Context, scheme: int, p_or_s: int, A, B, trans_a: bool = False, trans_b: bool = False, C=None,
+                alpha: float = 1.0, beta: float = 0.0, ws=None, stream=None):
+    """C = alpha*op(A)*op(B) + beta*C with op(X) = X.T when its flag is set
+    (A, B as stored: float64 CUDA tensors, row-major); returns C."""
+    import torch
+    M, K = (A.shape[1], A.shape[0]) if trans_a else A.shape
+    N = B.shape[0] if trans_b else B.shape[1]
+    if C is None:
+        C = torch.empty((M, N), dtype=torch.float64, device=A.device)
+    if ws is None:
+        ws = _workspace(ozk_workspace_size(ctx, OZK_OP_DGEMM, scheme, M, N, K, p_or_s), A.device)
+    st = _lib().ozk_dgemm_t(ctx.handle, scheme, p_or_s, int(bool(trans_a)), int(bool(trans_b)), M, N, K, float(alpha),
+                            _ptr(A), _ld(A), _ptr(B), _ld(B), float(beta), _ptr(C), _ld(C), _ptr(ws), ws.numel(),
+                            _stream(stream))
+    _check("ozk_dgemm_t", st, ctx)
     return C
 
 

@@ -371,24 +371,17 @@ ozk_status ozk_s1_diagonals(ozk_ctx* ctx, int p, int64_t M, int64_t N, int64_t K
                         nullptr, 0, Cd, stream, default_config());
 }
 
-ozk_status ozk_dgemm(ozk_ctx* ctx, ozk_scheme scheme, int p_or_s, int64_t M, int64_t N, int64_t K,
-                     double alpha, const double* A, int64_t lda, const double* B, int64_t ldb, double beta,
-                     double* C, int64_t ldc, void* ws, size_t ws_bytes, hipStream_t stream) {
-  if (!ctx) return OZK_ERR_INVALID_ARG;
-  ctx->last_arg = 0;
-  if (scheme != OZK_SCHEME1 && scheme != OZK_SCHEME2) return fail(ctx, OZK_ERR_INVALID_ARG, 2);
-  if (bad_dims(M, N, K)) return fail(ctx, OZK_ERR_INVALID_ARG, M < 0 ? 4 : (N < 0 ? 5 : 6));
-  if (!A && M > 0 && K > 0) return fail(ctx, OZK_ERR_INVALID_ARG, 8);
-  if (lda < (K > 0 ? K : 1)) return fail(ctx, OZK_ERR_INVALID_ARG, 9);
-  if (!B && K > 0 && N > 0) return fail(ctx, OZK_ERR_INVALID_ARG, 10);
-  if (ldb < (N > 0 ? N : 1)) return fail(ctx, OZK_ERR_INVALID_ARG, 11);
-  if (!C && M > 0 && N > 0) return fail(ctx, OZK_ERR_INVALID_ARG, 13);
-  if (ldc < (N > 0 ? N : 1)) return fail(ctx, OZK_ERR_INVALID_ARG, 14);
+// The DGEMM pipeline after argument checks; trans_a / trans_b: the operand
+// is stored transposed (A as K x M, B as N x K, row-major).
+static ozk_status dgemm_run(ozk_ctx* ctx, ozk_scheme scheme, int p_or_s, bool trans_a, bool trans_b, int64_t M,
+                            int64_t N, int64_t K, double alpha, const double* A, int64_t lda, const double* B,
+                            int64_t ldb, double beta, double* C, int64_t ldc, void* ws, size_t ws_bytes,
+                            hipStream_t stream, int ws_arg) {
   if (scheme == OZK_SCHEME2) {
     const int s = p_or_s;
     if (s < 1 || s > OZK_MAX_S) return fail(ctx, OZK_ERR_UNSUPPORTED, 3);
     const S2Plan pl = s2_plan(s, false, M, N, K);
-    if (!ws || ws_bytes < pl.total) return fail(ctx, OZK_ERR_WORKSPACE, 15);
+    if (!ws || ws_bytes < pl.total) return fail(ctx, OZK_ERR_WORKSPACE, ws_arg);
     if (M == 0 || N == 0) return OZK_OK;
     char* w = (char*)ws;
     int32_t* sig = (int32_t*)(w + pl.off_sig);
@@ -396,8 +389,14 @@ ozk_status ozk_dgemm(ozk_ctx* ctx, ozk_scheme scheme, int p_or_s, int64_t M, int
     int8_t* Ap = (int8_t*)(w + pl.off_a);
     int8_t* Bp = (int8_t*)(w + pl.off_b);
     int8_t* res = (int8_t*)(w + pl.off_res);
-    hipError_t err = ozk::s2_split_rows(s, false, A, lda, M, K, sig, Ap, stream);
-    if (err == hipSuccess) err = ozk::s2_split_cols(s, false, B, ldb, K, N, tau, Bp, stream);
+    int ta_bits, tb_bits;
+    ozk::s2_targets(s, ta_bits, tb_bits);
+    // a transposed operand is read by the other pass, with its own bit budget
+    hipError_t err = trans_a ? ozk::s2_split_cols(s, false, A, lda, K, M, sig, Ap, stream, ta_bits)
+                             : ozk::s2_split_rows(s, false, A, lda, M, K, sig, Ap, stream);
+    if (err == hipSuccess)
+      err = trans_b ? ozk::s2_split_rows(s, false, B, ldb, N, K, tau, Bp, stream, tb_bits)
+                    : ozk::s2_split_cols(s, false, B, ldb, K, N, tau, Bp, stream);
     const ozk_gemm_config cfg = config_for(ctx, OZK_OP_DGEMM, OZK_SCHEME2, s, M, N, K);
     if (cfg.variant == OZK_S2_FUSED_CRT) {
       if (err == hipSuccess)
@@ -414,18 +413,61 @@ ozk_status ozk_dgemm(ozk_ctx* ctx, ozk_scheme scheme, int p_or_s, int64_t M, int
   if (p < 1 || p > OZK_MAX_P) return fail(ctx, OZK_ERR_UNSUPPORTED, 3);
   const ozk_gemm_config cfg = config_for(ctx, OZK_OP_DGEMM, OZK_SCHEME1, p, M, N, K);
   const S1Plan pl = s1_plan(ctx, p, M, N, K, cfg.split);
-  if (!ws || ws_bytes < pl.total) return fail(ctx, OZK_ERR_WORKSPACE, 15);
+  if (!ws || ws_bytes < pl.total) return fail(ctx, OZK_ERR_WORKSPACE, ws_arg);
   if (M == 0 || N == 0) return OZK_OK;
   char* w = (char*)ws;
   int32_t* e = (int32_t*)(w + pl.off_e);
   int32_t* f = (int32_t*)(w + pl.off_f);
   int8_t* Ap = (int8_t*)(w + pl.off_a);
   int8_t* Bp = (int8_t*)(w + pl.off_b);
-  hipError_t err = ozk::s1_split_rows(p, A, lda, M, K, e, Ap, stream);
-  if (err == hipSuccess) err = ozk::s1_split_cols(p, B, ldb, K, N, f, Bp, stream);
+  // a transposed operand is read by the other pass (same packed layout)
+  hipError_t err = trans_a ? ozk::s1_split_cols(p, A, lda, K, M, e, Ap, stream)
+                           : ozk::s1_split_rows(p, A, lda, M, K, e, Ap, stream);
+  if (err == hipSuccess)
+    err = trans_b ? ozk::s1_split_rows(p, B, ldb, N, K, f, Bp, stream) : ozk::s1_split_cols(p, B, ldb, K, N, f, Bp, stream);
   if (err != hipSuccess) return hip_status(ctx, err);
   return s1_gemm_common(ctx, p, M, N, K, Ap, e, Bp, f, alpha, beta, C, ldc, w + pl.off_z,
                         pl.total - pl.off_z, nullptr, stream, cfg);
+}
+
+ozk_status ozk_dgemm(ozk_ctx* ctx, ozk_scheme scheme, int p_or_s, int64_t M, int64_t N, int64_t K,
+                     double alpha, const double* A, int64_t lda, const double* B, int64_t ldb, double beta,
+                     double* C, int64_t ldc, void* ws, size_t ws_bytes, hipStream_t stream) {
+  if (!ctx) return OZK_ERR_INVALID_ARG;
+  ctx->last_arg = 0;
+  if (scheme != OZK_SCHEME1 && scheme != OZK_SCHEME2) return fail(ctx, OZK_ERR_INVALID_ARG, 2);
+  if (bad_dims(M, N, K)) return fail(ctx, OZK_ERR_INVALID_ARG, M < 0 ? 4 : (N < 0 ? 5 : 6));
+  if (!A && M > 0 && K > 0) return fail(ctx, OZK_ERR_INVALID_ARG, 8);
+  if (lda < (K > 0 ? K : 1)) return fail(ctx, OZK_ERR_INVALID_ARG, 9);
+  if (!B && K > 0 && N > 0) return fail(ctx, OZK_ERR_INVALID_ARG, 10);
+  if (ldb < (N > 0 ? N : 1)) return fail(ctx, OZK_ERR_INVALID_ARG, 11);
+  if (!C && M > 0 && N > 0) return fail(ctx, OZK_ERR_INVALID_ARG, 13);
+  if (ldc < (N > 0 ? N : 1)) return fail(ctx, OZK_ERR_INVALID_ARG, 14);
+  return dgemm_run(ctx, scheme, p_or_s, false, false, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, ws, ws_bytes,
+                   stream, 15);
+}
+
+ozk_status ozk_dgemm_t(ozk_ctx* ctx, ozk_scheme scheme, int p_or_s, int trans_a, int trans_b, int64_t M, int64_t N,
+                       int64_t K, double alpha, const double* A, int64_t lda, const double* B, int64_t ldb,
+                       double beta, double* C, int64_t ldc, void* ws, size_t ws_bytes, hipStream_t stream) {
+  if (!ctx) return OZK_ERR_INVALID_ARG;
+  ctx->last_arg = 0;
+  if (scheme != OZK_SCHEME1 && scheme != OZK_SCHEME2) return fail(ctx, OZK_ERR_INVALID_ARG, 2);
+  if (trans_a != 0 && trans_a != 1) return fail(ctx, OZK_ERR_INVALID_ARG, 4);
+  if (trans_b != 0 && trans_b != 1) return fail(ctx, OZK_ERR_INVALID_ARG, 5);
+  if (bad_dims(M, N, K)) return fail(ctx, OZK_ERR_INVALID_ARG, M < 0 ? 6 : (N < 0 ? 7 : 8));
+  const int64_t acols = trans_a ? M : K, bcols = trans_b ? K : N;  // row lengths as stored
+  const bool a_empty = M == 0 || K == 0, b_empty = K == 0 || N == 0;
+  if (!A && !a_empty) return fail(ctx, OZK_ERR_INVALID_ARG, 10);
+  if (lda < (acols > 0 ? acols : 1)) return fail(ctx, OZK_ERR_INVALID_ARG, 11);
+  if (!B && !b_empty) return fail(ctx, OZK_ERR_INVALID_ARG, 12);
+  if (ldb < (bcols > 0 ? bcols : 1)) return fail(ctx, OZK_ERR_INVALID_ARG, 13);
+  if (!C && M > 0 && N > 0) return fail(ctx, OZK_ERR_INVALID_ARG, 15);
+  if (ldc < (N > 0 ? N : 1)) return fail(ctx, OZK_ERR_INVALID_ARG, 16);
+  if (scheme == OZK_SCHEME2 && (p_or_s < 1 || p_or_s > OZK_MAX_S)) return fail(ctx, OZK_ERR_UNSUPPORTED, 3);
+  if (scheme == OZK_SCHEME1 && (p_or_s < 1 || p_or_s > OZK_MAX_P)) return fail(ctx, OZK_ERR_UNSUPPORTED, 3);
+  return dgemm_run(ctx, scheme, p_or_s, trans_a != 0, trans_b != 0, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, ws,
+                   ws_bytes, stream, 19);
 }
 
 // The unfused baseline: the DGEMM pre-pass, then one INT8 GEMM per slice

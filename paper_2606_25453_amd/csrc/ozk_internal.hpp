@@ -142,19 +142,21 @@ hipError_t ref_dd(int64_t M, int64_t N, int64_t K, const double* A, int64_t lda,
                   int64_t n, const int64_t* rows, const int64_t* cols, double* hi, double* lo, double* absab,
                   hipStream_t st);
 hipError_t s2_split_rows(int s, bool cplx, const double* X, int64_t ldx, int64_t rows, int64_t K, int32_t* sigma,
-                         int8_t* packed, hipStream_t st);
+                         int8_t* packed, hipStream_t st, int budget = -1);
 hipError_t s2_split_cols(int s, bool cplx, const double* X, int64_t ldx, int64_t K, int64_t cols, int32_t* tau,
-                         int8_t* packed, hipStream_t st);
+                         int8_t* packed, hipStream_t st, int budget = -1);
 hipError_t s2_gemm_mod(int s, bool cplx, int64_t M, int64_t N, int64_t K, const int8_t* Ap, const int8_t* Bp,
                        int8_t* out, hipStream_t st, int variant = 0, int raster = 0, int group = 4);
 hipError_t s2_crt(int s, bool cplx, int64_t M, int64_t N, const int8_t* res, const int32_t* sigma,
                   const int32_t* tau, const double* alpha, const double* beta, double* C, int64_t ldc,
                   hipStream_t st);
+// budget: the bit budget of the scale (default: T_A for the row pass, T_B for
+// the column pass; a transposed operand takes the other pass with its own).
 // binary32 operands (widened exactly on load) and binary32 results
 hipError_t s2_split_rows(int s, bool cplx, const float* X, int64_t ldx, int64_t rows, int64_t K, int32_t* sigma,
-                         int8_t* packed, hipStream_t st);
+                         int8_t* packed, hipStream_t st, int budget = -1);
 hipError_t s2_split_cols(int s, bool cplx, const float* X, int64_t ldx, int64_t K, int64_t cols, int32_t* tau,
-                         int8_t* packed, hipStream_t st);
+                         int8_t* packed, hipStream_t st, int budget = -1);
 hipError_t s2_crt(int s, bool cplx, int64_t M, int64_t N, const int8_t* res, const int32_t* sigma,
                   const int32_t* tau, const float* alpha, const float* beta, float* C, int64_t ldc,
                   hipStream_t st);

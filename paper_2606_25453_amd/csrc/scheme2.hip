@@ -875,9 +875,10 @@ void s2_targets(int s, int& ta, int& tb) {
 
 template <typename T>
 static hipError_t split_rows_t(int s, bool cplx, const T* X, int64_t ldx, int64_t rows, int64_t K, int32_t* sigma,
-                         int8_t* packed, hipStream_t st) {
+                         int8_t* packed, hipStream_t st, int budget) {
   int ta, tb;
   s2_targets(s, ta, tb);
+  if (budget >= 0) ta = budget;
   const int64_t rp = round_up(rows, OZK_ROW_ALIGN), kp = round_up(K, OZK_K_CHUNK);
   if (rp == 0) return hipSuccess;
   S2Args sa{s, ta};
@@ -892,9 +893,10 @@ static hipError_t split_rows_t(int s, bool cplx, const T* X, int64_t ldx, int64_
 
 template <typename T>
 static hipError_t split_cols_t(int s, bool cplx, const T* X, int64_t ldx, int64_t K, int64_t cols, int32_t* tau,
-                         int8_t* packed, hipStream_t st) {
+                         int8_t* packed, hipStream_t st, int budget) {
   int ta, tb;
   s2_targets(s, ta, tb);
+  if (budget >= 0) tb = budget;
   const int64_t cp = round_up(cols, OZK_ROW_ALIGN), kp = round_up(K, OZK_K_CHUNK);
   if (cols > 0 && cp > 0 && kp >= 4 * S2_COLS_KB) {
     // long K: split over K; the statistics live at the start of `packed`
@@ -931,23 +933,23 @@ static hipError_t split_cols_t(int s, bool cplx, const T* X, int64_t ldx, int64_
 }
 
 hipError_t s2_split_rows(int s, bool cplx, const double* X, int64_t ldx, int64_t rows, int64_t K, int32_t* sigma,
-                         int8_t* packed, hipStream_t st) {
-  return split_rows_t(s, cplx, X, ldx, rows, K, sigma, packed, st);
+                         int8_t* packed, hipStream_t st, int budget) {
+  return split_rows_t(s, cplx, X, ldx, rows, K, sigma, packed, st, budget);
 }
 
 hipError_t s2_split_rows(int s, bool cplx, const float* X, int64_t ldx, int64_t rows, int64_t K, int32_t* sigma,
-                         int8_t* packed, hipStream_t st) {
-  return split_rows_t(s, cplx, X, ldx, rows, K, sigma, packed, st);
+                         int8_t* packed, hipStream_t st, int budget) {
+  return split_rows_t(s, cplx, X, ldx, rows, K, sigma, packed, st, budget);
 }
 
 hipError_t s2_split_cols(int s, bool cplx, const double* X, int64_t ldx, int64_t K, int64_t cols, int32_t* tau,
-                         int8_t* packed, hipStream_t st) {
-  return split_cols_t(s, cplx, X, ldx, K, cols, tau, packed, st);
+                         int8_t* packed, hipStream_t st, int budget) {
+  return split_cols_t(s, cplx, X, ldx, K, cols, tau, packed, st, budget);
 }
 
 hipError_t s2_split_cols(int s, bool cplx, const float* X, int64_t ldx, int64_t K, int64_t cols, int32_t* tau,
-                         int8_t* packed, hipStream_t st) {
-  return split_cols_t(s, cplx, X, ldx, K, cols, tau, packed, st);
+                         int8_t* packed, hipStream_t st, int budget) {
+  return split_cols_t(s, cplx, X, ldx, K, cols, tau, packed, st, budget);
 }
 
 template <bool CPLX, int V>

@@ -195,3 +195,23 @@ def test_workspace_follows_the_split(ctx):
     with pytest.raises(ozk.OzkError):
         ozk.ozk_dgemm(ctx, ozk.OZK_SCHEME1, p, dev(A), dev(B), ws=ws_small)
     assert np.array_equal(host(ozk.ozk_dgemm(ctx, ozk.OZK_SCHEME1, p, dev(A), dev(B))), oracle.s1_dgemm(A, B, p))
+
+
+@pytest.mark.parametrize("scheme,ps", [(ozk.OZK_SCHEME1, 5), (ozk.OZK_SCHEME2, 13)])
+@pytest.mark.parametrize("shape", [(70, 130, 45), (257, 64, 700), (1, 1, 1)])
+def test_transposed_operands_are_bit_identical(ctx, scheme, ps, shape):
+    """ozk_dgemm_t on stored transposes (the other pre-pass kernel per
+    operand, the long-K column statistics included) equals ozk_dgemm on the
+    explicit operands, and the oracle."""
+    M, N, K = shape
+    A = synth.phi_matrix(M, K, 1.0, 301 + M)
+    B = synth.phi_matrix(K, N, 1.0, 302 + N)
+    ref = ozk.ozk_dgemm(ctx, scheme, ps, dev(A), dev(B))
+    expect = oracle.s1_dgemm(A, B, ps) if scheme == ozk.OZK_SCHEME1 else s2.s2_dgemm(A, B, ps)
+    assert np.array_equal(host(ref), expect)
+    for ta in (False, True):
+        for tb in (False, True):
+            a = dev(A.T.copy()) if ta else dev(A)
+            b = dev(B.T.copy()) if tb else dev(B)
+            got = ozk.ozk_dgemm_t(ctx, scheme, ps, a, b, trans_a=ta, trans_b=tb)
+            assert torch.equal(got, ref), (ta, tb)
