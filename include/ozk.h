@@ -179,11 +179,11 @@ ozk_status ozk_dgemm_t(ozk_ctx* ctx, ozk_scheme scheme, int p_or_s, int trans_a,
  * p(p+1)/2 planes back, forms Z exactly and rounds once.  The result is
  * bit-identical to ozk_dgemm(OZK_SCHEME1, p); only the INT32 round trip
  * (4 p(p+1) M N bytes written and read) and the p(p+1)/2 operand passes
- * differ.  1 <= p <= 8, K <= 131072 (one INT32 plane per pair stays exact).
+ * differ.  1 <= p <= 8, K <= 131071 (|sum| <= K 2^14 keeps each INT32 plane exact).
  * Workspace: ozk_s1_unfused_workspace_size bytes (the packed operands plus
  * 2 p(p+1) M N bytes of planes).  Device pointers, caller-owned memory,
  * asynchronous on `stream`; errors as ozk_dgemm (OZK_ERR_UNSUPPORTED, arg 5,
- * for K > 131072). */
+ * for K > 131071). */
 ozk_status ozk_s1_unfused_workspace_size(ozk_ctx* ctx, int p, int64_t M,
                                          int64_t N, int64_t K, size_t* bytes);
 ozk_status ozk_s1_dgemm_unfused(ozk_ctx* ctx, int p, int64_t M, int64_t N,

@@ -494,7 +494,7 @@ ozk_status ozk_s1_dgemm_unfused(ozk_ctx* ctx, int p, int64_t M, int64_t N, int64
   ctx->last_arg = 0;
   if (p < 1 || p > OZK_MAX_P) return fail(ctx, OZK_ERR_UNSUPPORTED, 2);
   if (bad_dims(M, N, K)) return fail(ctx, OZK_ERR_INVALID_ARG, M < 0 ? 3 : (N < 0 ? 4 : 5));
-  if (K > 131072) return fail(ctx, OZK_ERR_UNSUPPORTED, 5);
+  if (K > 131071) return fail(ctx, OZK_ERR_UNSUPPORTED, 5);  // |sum| <= K 2^14 < 2^31
   if (!A && M > 0 && K > 0) return fail(ctx, OZK_ERR_INVALID_ARG, 7);
   if (lda < (K > 0 ? K : 1)) return fail(ctx, OZK_ERR_INVALID_ARG, 8);
   if (!B && K > 0 && N > 0) return fail(ctx, OZK_ERR_INVALID_ARG, 9);

@@ -40,7 +40,7 @@ hipError_t s1_split_cols(int p, const float* X, int64_t ldx, int64_t K, int64_t 
                          int8_t* packed, hipStream_t st);
 hipError_t s1_gemm(int p, const S1GemmArgs& g, hipStream_t st);
 // The unfused baseline (one GEMM per slice pair, INT32 planes through HBM,
-// then the exact reconstruction); K <= 131072 keeps each plane exact.
+// then the exact reconstruction); K <= 131071 keeps each plane exact.
 int64_t s1_unfused_planes_bytes(int p, int64_t M, int64_t N);
 hipError_t s1_gemm_unfused(int p, int64_t M, int64_t N, int64_t K, const int8_t* Ap, const int32_t* e,
                            const int8_t* Bp, const int32_t* f, double alpha, double beta, double* C, int64_t ldc,

@@ -383,3 +383,16 @@ def test_unfused_baseline_equals_fused(ctx, p, shape):
     assert np.array_equal(got, fused)
     if K:
         assert np.array_equal(got, oracle.s1_dgemm(A, B, p, alpha=0.75, beta=-2.0, C=C0))
+
+
+def test_unfused_baseline_k_limit(ctx):
+    """K = 131071 is the longest single INT32 plane per pair; beyond it the
+    baseline refuses (the fused path splits K instead)."""
+    A = synth.phi_matrix(2, 131071, 1.0, 7300)
+    B = synth.phi_matrix(131071, 3, 1.0, 7301)
+    got = host(ozk.ozk_s1_dgemm_unfused(ctx, 2, dev(A), dev(B)))
+    assert np.array_equal(got, host(ozk.ozk_dgemm(ctx, ozk.OZK_SCHEME1, 2, dev(A), dev(B))))
+    A2, B2 = dev(np.ones((2, 131072))), dev(np.ones((131072, 3)))
+    with pytest.raises(ozk.OzkError) as ei:
+        ozk.ozk_s1_dgemm_unfused(ctx, 2, A2, B2, ws=torch.empty(1 << 24, dtype=torch.uint8, device="cuda:0"))
+    assert ei.value.status == ozk.OZK_ERR_UNSUPPORTED
