@@ -10,6 +10,8 @@
 //                       combination T1-T2, T3-T1-T2 before the reduction
 //   k_s2_crt            CRT recombination in multiword integers (Eq. 8) with
 //                       the symmetric lift, then one rounding of Z 2^-(sigma+tau)
+#include <type_traits>
+
 #include "mfma_gemm.hpp"
 #include "ozk_device.hpp"
 #include "ozk_internal.hpp"
@@ -574,41 +576,43 @@ struct CrtArgs {
 
 // Z = smod(V, P) as a sign and magnitude limbs, for V = sum_l W_l c_l >= 0
 // given as NL + 1 32-bit limbs.
+template <int U = NL>
 __device__ __forceinline__ void crt_reduce(const CrtArgs& ca, const uint32_t (&v)[NL + 1], uint32_t (&mag)[NL],
                                            bool& neg) {
+  static_assert(U >= 1 && U <= NL, "limbs used");
   // quotient estimate by floating point, then exact correction
   double vf = 0.0;
 #pragma unroll
-  for (int i = NL; i >= 0; --i) vf = vf * 4294967296.0 + (double)v[i];
+  for (int i = U; i >= 0; --i) vf = vf * 4294967296.0 + (double)v[i];
   int64_t q = (int64_t)floor(vf / ca.Pf);
   if (q < 0) q = 0;
-  // r = v - q P (signed, NL+1 limbs, two's complement)
+  // r = v - q P (signed, U+1 limbs, two's complement)
   int64_t borrow = 0;
   uint32_t r[NL + 1];
   uint64_t mc = 0;
 #pragma unroll
-  for (int i = 0; i <= NL; ++i) {
-    const uint64_t pi = i < NL ? ca.P[i] : 0;
+  for (int i = 0; i <= U; ++i) {
+    const uint64_t pi = i < U ? ca.P[i] : 0;
     const uint64_t prod = pi * (uint64_t)q + mc;
     mc = prod >> 32;
     const int64_t d = (int64_t)v[i] - (int64_t)(uint32_t)prod + borrow;
     r[i] = (uint32_t)d;
     borrow = d >> 32;  // 0 or -1
   }
-  auto negative = [&]() { return (int32_t)r[NL] < 0; };
+  auto negative = [&]() { return (int32_t)r[U] < 0; };
   auto add_p = [&](int sign) {  // r += sign * P
     int64_t cy = 0;
 #pragma unroll
-    for (int i = 0; i <= NL; ++i) {
-      const int64_t pi = i < NL ? (int64_t)ca.P[i] : 0;
+    for (int i = 0; i <= U; ++i) {
+      const int64_t pi = i < U ? (int64_t)ca.P[i] : 0;
       const int64_t d = (int64_t)r[i] + sign * pi + cy;
       r[i] = (uint32_t)d;
       cy = d >> 32;
     }
   };
   auto ge_p = [&]() {  // r >= P (r non-negative)
-    if (r[NL]) return true;
-    for (int i = NL - 1; i >= 0; --i) {
+    if (r[U]) return true;
+    for (int i = U - 1; i >= 0; --i) {
       if (r[i] != ca.P[i]) return r[i] > ca.P[i];
     }
     return true;
@@ -619,18 +623,18 @@ __device__ __forceinline__ void crt_reduce(const CrtArgs& ca, const uint32_t (&v
   uint32_t tw[NL + 1];
   uint32_t cy2 = 0;
 #pragma unroll
-  for (int i = 0; i <= NL; ++i) {
+  for (int i = 0; i <= U; ++i) {
     tw[i] = (r[i] << 1) | cy2;
     cy2 = r[i] >> 31;
   }
   bool ge = false;
   {
     bool decided = false;
-    if (tw[NL]) {
+    if (tw[U]) {
       ge = true;
       decided = true;
     }
-    for (int i = NL - 1; i >= 0 && !decided; --i) {
+    for (int i = U - 1; i >= 0 && !decided; --i) {
       if (tw[i] != ca.P[i]) {
         ge = tw[i] > ca.P[i];
         decided = true;
@@ -642,7 +646,7 @@ __device__ __forceinline__ void crt_reduce(const CrtArgs& ca, const uint32_t (&v
     // magnitude = P - r
     int64_t b = 0;
 #pragma unroll
-    for (int i = 0; i < NL; ++i) {
+    for (int i = 0; i < U; ++i) {
       const int64_t d = (int64_t)ca.P[i] - (int64_t)r[i] + b;
       mag[i] = (uint32_t)d;
       b = d >> 32;
@@ -650,37 +654,40 @@ __device__ __forceinline__ void crt_reduce(const CrtArgs& ca, const uint32_t (&v
     neg = true;
   } else {
 #pragma unroll
-    for (int i = 0; i < NL; ++i) mag[i] = r[i];
+    for (int i = 0; i < U; ++i) mag[i] = r[i];
     neg = false;
   }
+#pragma unroll
+  for (int i = U; i < NL; ++i) mag[i] = 0;
 }
 
 // Z = smod(sum_l W_l c_l, P) from the s residue planes at res (stride apart).
+template <int U = NL>
 __device__ __forceinline__ void crt_combine(const CrtArgs& ca, const int8_t* res, int64_t stride, uint32_t (&mag)[NL],
                                             bool& neg) {
   // all residues first (independent loads in flight together), then the sum
   int cv[OZK_MAX_S];
 #pragma unroll
   for (int l = 0; l < OZK_MAX_S; ++l) cv[l] = l < ca.s ? (int)res[l * stride] : 0;
-  uint64_t acc[NL] = {0, 0, 0, 0, 0, 0};
+  uint64_t acc[U] = {};
 #pragma unroll
   for (int l = 0; l < OZK_MAX_S; ++l) {
     if (l >= ca.s) break;
     int c = cv[l];
     if (c < 0) c += c_s2.m[l];
 #pragma unroll
-    for (int i = 0; i < NL; ++i) acc[i] += (uint64_t)ca.W[l][i] * (uint32_t)c;
+    for (int i = 0; i < U; ++i) acc[i] += (uint64_t)ca.W[l][i] * (uint32_t)c;
   }
-  uint32_t v[NL + 1];
+  uint32_t v[NL + 1] = {};
   uint64_t carry = 0;
 #pragma unroll
-  for (int i = 0; i < NL; ++i) {
+  for (int i = 0; i < U; ++i) {
     const uint64_t t = acc[i] + carry;
     v[i] = (uint32_t)t;
     carry = t >> 32;
   }
-  v[NL] = (uint32_t)carry;
-  crt_reduce(ca, v, mag, neg);
+  v[U] = (uint32_t)carry;
+  crt_reduce<U>(ca, v, mag, neg);
 }
 
 // The CRT sum of one output kept in registers while the moduli stream by
@@ -764,7 +771,7 @@ __device__ __forceinline__ void s2_store_c(const TO (&h)[2], int64_t row, int64_
   }
 }
 
-template <bool CPLX, typename TO = double>
+template <bool CPLX, typename TO = double, int U = NL>
 __device__ __forceinline__ void s2_crt_block(const CrtArgs& ca, int64_t M, int64_t N, const int8_t* __restrict__ res,
                                              const int32_t* __restrict__ sigma, const int32_t* __restrict__ tau,
                                              TO a_re, TO a_im, TO b_re, TO b_im, TO* __restrict__ C, int64_t ldc,
@@ -785,17 +792,18 @@ __device__ __forceinline__ void s2_crt_block(const CrtArgs& ca, int64_t M, int64
     }
     uint32_t mag[NL];
     bool neg;
-    crt_combine(ca, res + (CPLX ? q * mn : 0) + idx, CPLX ? 2 * mn : mn, mag, neg);
+    crt_combine<U>(ca, res + (CPLX ? q * mn : 0) + idx, CPLX ? 2 * mn : mn, mag, neg);
     h[q] = round_limbs<TO>(mag, neg, E);
   }
   s2_store_c<CPLX, TO>(h, row, col, a_re, a_im, b_re, b_im, C, ldc);
 }
 
-template <bool CPLX, typename TO = double>
+// U: 32-bit limbs in use (P and the sums of s W_l c_l < s 2^8 P fit U limbs).
+template <bool CPLX, typename TO = double, int U = NL>
 __global__ __launch_bounds__(256) void k_s2_crt(CrtArgs ca, int M, int N, const int8_t* __restrict__ res,
                                                 const int32_t* __restrict__ sigma, const int32_t* __restrict__ tau,
                                                 TO a_re, TO a_im, TO b_re, TO b_im, TO* __restrict__ C, int64_t ldc) {
-  s2_crt_block<CPLX, TO>(ca, M, N, res, sigma, tau, a_re, a_im, b_re, b_im, C, ldc, blockIdx.x);
+  s2_crt_block<CPLX, TO, U>(ca, M, N, res, sigma, tau, a_re, a_im, b_re, b_im, C, ldc, blockIdx.x);
 }
 
 // ------------------------------------------------------------ host side
@@ -1006,13 +1014,28 @@ static hipError_t crt_t(int s, bool cplx, int64_t M, int64_t N, const int8_t* re
   crt_args(s, ca, ta, tb);
   const int64_t n = M * N;
   const TO ai = cplx ? alpha[1] : (TO)0, bi = cplx ? beta[1] : (TO)0;
-  if (cplx)
-    hipLaunchKernelGGL((k_s2_crt<true, TO>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, ca, (int)M, (int)N,
-                       res, sigma, tau, alpha[0], ai, beta[0], bi, C, ldc);
-  else
-    hipLaunchKernelGGL((k_s2_crt<false, TO>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, ca, (int)M, (int)N,
-                       res, sigma, tau, alpha[0], ai, beta[0], bi, C, ldc);
-  return hipGetLastError();
+  // limbs in use: sum_l W_l c_l < s 2^8 P < 2^(bits(P) + 13) for s <= 20
+  int pbits = 0;
+  for (int i = NL - 1; i >= 0 && !pbits; --i)
+    if (ca.P[i]) pbits = 32 * i + (32 - __builtin_clz(ca.P[i]));
+  const int u = (pbits + 13 + 31) / 32;
+  auto launch = [&](auto kern) {
+    hipLaunchKernelGGL(kern, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, ca, (int)M, (int)N, res, sigma, tau,
+                       alpha[0], ai, beta[0], bi, C, ldc);
+    return hipGetLastError();
+  };
+  auto pick = [&](auto cplx_c) {
+    constexpr bool CP = decltype(cplx_c)::value;
+    switch (u) {
+      case 1: return launch(k_s2_crt<CP, TO, 1>);
+      case 2: return launch(k_s2_crt<CP, TO, 2>);
+      case 3: return launch(k_s2_crt<CP, TO, 3>);
+      case 4: return launch(k_s2_crt<CP, TO, 4>);
+      case 5: return launch(k_s2_crt<CP, TO, 5>);
+    }
+    return launch(k_s2_crt<CP, TO, NL>);
+  };
+  return cplx ? pick(std::true_type{}) : pick(std::false_type{});
 }
 
 hipError_t s2_crt(int s, bool cplx, int64_t M, int64_t N, const int8_t* res, const int32_t* sigma,
