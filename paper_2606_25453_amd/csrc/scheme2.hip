@@ -1005,6 +1005,14 @@ hipError_t s2_gemm_mod(int s, bool cplx, int64_t M, int64_t N, int64_t K, const 
               : launch_gemm_mod<false, 0>(s, M, N, K, Ap, Bp, out, raster, group, st);
 }
 
+// 32-bit limbs the CRT sums need: sum_l W_l c_l < s 2^8 P < 2^(bits(P) + 13) for s <= 20.
+static int crt_limbs(const CrtArgs& ca) {
+  int pbits = 0;
+  for (int i = NL - 1; i >= 0 && !pbits; --i)
+    if (ca.P[i]) pbits = 32 * i + (32 - __builtin_clz(ca.P[i]));
+  return (pbits + 13 + 31) / 32;
+}
+
 template <typename TO>
 static hipError_t crt_t(int s, bool cplx, int64_t M, int64_t N, const int8_t* res, const int32_t* sigma,
                        const int32_t* tau, const TO* alpha, const TO* beta, TO* C, int64_t ldc, hipStream_t st) {
@@ -1014,11 +1022,7 @@ static hipError_t crt_t(int s, bool cplx, int64_t M, int64_t N, const int8_t* re
   crt_args(s, ca, ta, tb);
   const int64_t n = M * N;
   const TO ai = cplx ? alpha[1] : (TO)0, bi = cplx ? beta[1] : (TO)0;
-  // limbs in use: sum_l W_l c_l < s 2^8 P < 2^(bits(P) + 13) for s <= 20
-  int pbits = 0;
-  for (int i = NL - 1; i >= 0 && !pbits; --i)
-    if (ca.P[i]) pbits = 32 * i + (32 - __builtin_clz(ca.P[i]));
-  const int u = (pbits + 13 + 31) / 32;
+  const int u = crt_limbs(ca);
   auto launch = [&](auto kern) {
     hipLaunchKernelGGL(kern, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, ca, (int)M, (int)N, res, sigma, tau,
                        alpha[0], ai, beta[0], bi, C, ldc);
@@ -1399,11 +1403,11 @@ __global__ __launch_bounds__(256, 3) void k_b_gemm_mod(BatchDev bd, int8_t* __re
   }
 }
 
-template <bool CPLX>
+template <bool CPLX, int U = NL>
 __global__ __launch_bounds__(256) void k_b_crt(CrtArgs ca, BatchDev bd, int8_t* __restrict__ ws) {
   const int p = find_problem(bd.crt, blockIdx.x);
   const BatchProb& q = bd.prob[p];
-  s2_crt_block<CPLX>(ca, q.M, q.N, ws + q.off_res, reinterpret_cast<const int32_t*>(ws + q.off_sig),
+  s2_crt_block<CPLX, double, U>(ca, q.M, q.N, ws + q.off_res, reinterpret_cast<const int32_t*>(ws + q.off_sig),
                      reinterpret_cast<const int32_t*>(ws + q.off_tau), q.a_re, q.a_im, q.b_re, q.b_im, q.C, q.ldc,
                      blockIdx.x - bd.crt.start[p]);
 }
@@ -1446,14 +1450,24 @@ hipError_t s2_batched(int s, bool cplx, const BatchDev& bd, const BatchTotals& t
     hipLaunchKernelGGL(k_b_col_scales<true>, dim3((unsigned)tot.cols), dim3(256), 0, st, bd, ws, tb);
     if (tot.split) hipLaunchKernelGGL(k_b_split_cols<true>, dim3((unsigned)tot.split), dim3(256), 0, st, bd, ws, s);
     if (tot.items) hipLaunchKernelGGL(k_b_gemm_mod<true>, dim3((unsigned)gemm_grid), dim3(256), lds, st, bd, ws, s);
-    hipLaunchKernelGGL(k_b_crt<true>, dim3((unsigned)tot.crt), dim3(256), 0, st, ca, bd, ws);
+    switch (crt_limbs(ca)) {
+      case 1: case 2: case 3: case 4:
+        hipLaunchKernelGGL((k_b_crt<true, 4>), dim3((unsigned)tot.crt), dim3(256), 0, st, ca, bd, ws); break;
+      case 5: hipLaunchKernelGGL((k_b_crt<true, 5>), dim3((unsigned)tot.crt), dim3(256), 0, st, ca, bd, ws); break;
+      default: hipLaunchKernelGGL((k_b_crt<true, NL>), dim3((unsigned)tot.crt), dim3(256), 0, st, ca, bd, ws);
+    }
   } else {
     hipLaunchKernelGGL(k_b_split_rows<false>, dim3((unsigned)tot.rows), dim3(256), 0, st, bd, ws, sa);
     hipLaunchKernelGGL(k_b_col_scales<false>, dim3((unsigned)tot.cols), dim3(256), 0, st, bd, ws, tb);
     if (tot.split) hipLaunchKernelGGL(k_b_split_cols<false>, dim3((unsigned)tot.split), dim3(256), 0, st, bd, ws, s);
     if (tot.items)
       hipLaunchKernelGGL(k_b_gemm_mod<false>, dim3((unsigned)gemm_grid), dim3(256), lds, st, bd, ws, s);
-    hipLaunchKernelGGL(k_b_crt<false>, dim3((unsigned)tot.crt), dim3(256), 0, st, ca, bd, ws);
+    switch (crt_limbs(ca)) {
+      case 1: case 2: case 3: case 4:
+        hipLaunchKernelGGL((k_b_crt<false, 4>), dim3((unsigned)tot.crt), dim3(256), 0, st, ca, bd, ws); break;
+      case 5: hipLaunchKernelGGL((k_b_crt<false, 5>), dim3((unsigned)tot.crt), dim3(256), 0, st, ca, bd, ws); break;
+      default: hipLaunchKernelGGL((k_b_crt<false, NL>), dim3((unsigned)tot.crt), dim3(256), 0, st, ca, bd, ws);
+    }
   }
   return hipGetLastError();
 }
