@@ -185,35 +185,45 @@ __device__ __forceinline__ void s2_store_residues(const double (&re)[4], const d
 constexpr int S2_ROWS_PER_BLOCK = 16;
 
 template <bool CPLX, typename T = double>
+// kb0, kb1 (multiples of 64): the K range whose residues this block writes
+// (kb1 < 0: to Kp); sigma_in: the row scales already computed (the residue
+// pass split over K), else this block computes and stores them.
 __device__ __forceinline__ void s2_split_rows_block(const T* __restrict__ X, int64_t ldx, int64_t rows,
                                                     int64_t K, int64_t Kp, int64_t rows_packed, S2Args sa,
                                                     int32_t* __restrict__ sigma_out, int8_t* __restrict__ packed,
-                                                    int64_t blk) {
+                                                    int64_t blk, int64_t kb0 = 0, int64_t kb1 = -1,
+                                                    const int32_t* __restrict__ sigma_in = nullptr) {
   constexpr int W = CPLX ? 2 : 1, NP = CPLX ? 3 : 1;
   const int lane = threadIdx.x & 63, q = lane & 15;
   const int64_t r = (blk * 4 + (threadIdx.x >> 6)) * 4 + (lane >> 4);
   if (r >= rows_packed) return;  // whole waves only (rows_packed is a multiple of 16)
   const bool in = r < rows;
   const T* xr = X + (in ? r : 0) * ldx * W;
-  int e = OZK_EXP_ZERO;
+  int sigma = 0;
+  if (sigma_in) {
+    sigma = in ? sigma_in[r] : 0;
+  } else {
+    int e = OZK_EXP_ZERO;
 #pragma unroll 8
-  for (int64_t k = q; k < K; k += 16) {
-    const int ek = entry_expo<CPLX>(xr + k * W);
-    e = ek > e ? ek : e;
+    for (int64_t k = q; k < K; k += 16) {
+      const int ek = entry_expo<CPLX>(xr + k * W);
+      e = ek > e ? ek : e;
+    }
+    e = group16_max(in ? e : OZK_EXP_ZERO);
+    int64_t S = 0;
+    if (e != OZK_EXP_NONFINITE && e != OZK_EXP_ZERO)
+#pragma unroll 8
+      for (int64_t k = q; k < K; k += 16) S += norm_term(entry_expo<CPLX>(xr + k * W), e);
+    S = group16_sum64(S);
+    sigma = in ? scale_from(e, S, sa.T) : 0;
+    if (in && q == 0) sigma_out[r] = sigma;
   }
-  e = group16_max(in ? e : OZK_EXP_ZERO);
-  int64_t S = 0;
-  if (e != OZK_EXP_NONFINITE && e != OZK_EXP_ZERO)
-#pragma unroll 8
-    for (int64_t k = q; k < K; k += 16) S += norm_term(entry_expo<CPLX>(xr + k * W), e);
-  S = group16_sum64(S);
-  const int sigma = in ? scale_from(e, S, sa.T) : 0;
-  if (in && q == 0) sigma_out[r] = sigma;
+  const int64_t kend = kb1 < 0 || kb1 > Kp ? Kp : kb1, kfull = K < kend ? K : kend;
   const int64_t plane = rows_packed * Kp * NP, slab = rows_packed * OZK_K_CHUNK;
   auto dst_of = [&](int64_t k0) { return packed + (k0 / OZK_K_CHUNK) * NP * slab + r * OZK_K_CHUNK + k0 % OZK_K_CHUNK; };
-  int64_t k0 = (int64_t)q * 4;
+  int64_t k0 = kb0 + (int64_t)q * 4;
   if (in && sigma != OZK_EXP_NONFINITE) {
-    for (; k0 + 4 <= K; k0 += 64) {
+    for (; k0 + 4 <= kfull; k0 += 64) {
       double re[4], im[4];
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
@@ -222,7 +232,7 @@ __device__ __forceinline__ void s2_split_rows_block(const T* __restrict__ X, int
       }
       s2_store_residues<CPLX>(re, im, sigma, sa.s, dst_of(k0), plane, slab);
     }
-    for (; k0 < Kp; k0 += 64) {
+    for (; k0 < kend; k0 += 64) {
       double re[4], im[4];
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
@@ -233,7 +243,7 @@ __device__ __forceinline__ void s2_split_rows_block(const T* __restrict__ X, int
       s2_store_residues<CPLX>(re, im, sigma, sa.s, dst_of(k0), plane, slab);
     }
   } else {
-    for (; k0 < Kp; k0 += 64) {
+    for (; k0 < kend; k0 += 64) {
       int8_t* dst = dst_of(k0);
       for (int l = 0; l < sa.s; ++l, dst += plane)
 #pragma unroll
@@ -248,6 +258,21 @@ __global__ __launch_bounds__(256) void k_s2_split_rows(const T* __restrict__ X, 
                                                        int32_t* __restrict__ sigma_out,
                                                        int8_t* __restrict__ packed) {
   s2_split_rows_block<CPLX, T>(X, ldx, rows, K, Kp, rows_packed, sa, sigma_out, packed, blockIdx.x);
+}
+
+// The residues of a row block over one K range per grid y (the row scales
+// computed beforehand): enough workgroups to fill the GPU when the rows are
+// few and long.
+constexpr int64_t S2_ROW_KR = 512;
+
+template <bool CPLX, typename T = double>
+__global__ __launch_bounds__(256) void k_s2_row_residues(const T* __restrict__ X, int64_t ldx, int64_t rows,
+                                                         int64_t K, int64_t Kp, int64_t rows_packed, S2Args sa,
+                                                         const int32_t* __restrict__ sigma,
+                                                         int8_t* __restrict__ packed) {
+  const int64_t kb0 = (int64_t)blockIdx.y * S2_ROW_KR;
+  s2_split_rows_block<CPLX, T>(X, ldx, rows, K, Kp, rows_packed, sa, nullptr, packed, blockIdx.x, kb0, kb0 + S2_ROW_KR,
+                               sigma);
 }
 
 // Column scales: a block of 256 threads covers 32 consecutive columns with 8
@@ -890,11 +915,29 @@ static hipError_t split_rows_t(int s, bool cplx, const T* X, int64_t ldx, int64_
   const int64_t rp = round_up(rows, OZK_ROW_ALIGN), kp = round_up(K, OZK_K_CHUNK);
   if (rp == 0) return hipSuccess;
   S2Args sa{s, ta};
+  const int64_t blocks = rp / S2_ROWS_PER_BLOCK;
+  if (blocks < 1024 && kp >= 2 * S2_ROW_KR) {
+    // few long rows: the scales first (a launch that writes no residues),
+    // then the residues over (row block, K range)
+    const dim3 g2((unsigned)blocks, (unsigned)((kp + S2_ROW_KR - 1) / S2_ROW_KR));
+    if (cplx) {
+      hipLaunchKernelGGL((k_s2_split_rows<true, T>), dim3((unsigned)blocks), dim3(256), 0, st, X, ldx, rows, K, 0, rp,
+                         sa, sigma, packed);
+      hipLaunchKernelGGL((k_s2_row_residues<true, T>), g2, dim3(256), 0, st, X, ldx, rows, K, kp, rp, sa, sigma,
+                         packed);
+    } else {
+      hipLaunchKernelGGL((k_s2_split_rows<false, T>), dim3((unsigned)blocks), dim3(256), 0, st, X, ldx, rows, K, 0, rp,
+                         sa, sigma, packed);
+      hipLaunchKernelGGL((k_s2_row_residues<false, T>), g2, dim3(256), 0, st, X, ldx, rows, K, kp, rp, sa, sigma,
+                         packed);
+    }
+    return hipGetLastError();
+  }
   if (cplx)
-    hipLaunchKernelGGL((k_s2_split_rows<true, T>), dim3((unsigned)(rp / S2_ROWS_PER_BLOCK)), dim3(256), 0, st, X, ldx, rows, K, kp, rp,
+    hipLaunchKernelGGL((k_s2_split_rows<true, T>), dim3((unsigned)blocks), dim3(256), 0, st, X, ldx, rows, K, kp, rp,
                        sa, sigma, packed);
   else
-    hipLaunchKernelGGL((k_s2_split_rows<false, T>), dim3((unsigned)(rp / S2_ROWS_PER_BLOCK)), dim3(256), 0, st, X, ldx, rows, K, kp,
+    hipLaunchKernelGGL((k_s2_split_rows<false, T>), dim3((unsigned)blocks), dim3(256), 0, st, X, ldx, rows, K, kp,
                        rp, sa, sigma, packed);
   return hipGetLastError();
 }

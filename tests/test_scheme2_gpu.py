@@ -401,3 +401,23 @@ def test_cgemm_3m_alpha_beta():
         assert np.array_equal(got, s2.z3m_cgemm(A, B, s, alpha=al, beta=be, C=C0))
     finally:
         c.close()
+
+
+@pytest.mark.parametrize("cplx", [False, True])
+def test_row_pass_split_over_k(ctx, cplx):
+    """Few long rows: the scales first, then the residues over (row block,
+    K range) -- ragged K, padding rows and a non-finite row included."""
+    M, N, K, s = 40, 30, 1500, 12
+    if cplx:
+        A = synth.complex_phi_matrix(M, K, 1.0, 2000, 2001)
+        B = synth.complex_phi_matrix(K, N, 1.0, 2002, 2003)
+    else:
+        A = synth.phi_matrix(M, K, 1.0, 2000)
+        B = synth.phi_matrix(K, N, 1.0, 2002)
+    A[3, 1234] = np.nan
+    A[5] = 0
+    got = host(ozk.ozk_zgemm_3m(ctx, s, dev(A), dev(B)) if cplx else ozk.ozk_dgemm(ctx, ozk.OZK_SCHEME2, s, dev(A), dev(B)))
+    ref = s2.z3m_gemm(A, B, s) if cplx else s2.s2_dgemm(A, B, s)
+    assert np.array_equal(np.isnan(got), np.isnan(ref))
+    ok = ~np.isnan(ref)
+    assert np.array_equal(got[ok], ref[ok])
