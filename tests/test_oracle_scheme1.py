@@ -331,7 +331,8 @@ def test_round_scaled_f32_matches_numpy_conversion():
         cases.append((z, rng.randrange(-230, 110)))
     for z, E in cases:
         for sz in (z, -z):
-            want = np.float32(np.ldexp(np.float64(sz), E))
+            with np.errstate(over="ignore"):  # the overflow to infinity is one of the cases
+                want = np.float32(np.ldexp(np.float64(sz), E))
             got = oracle.round_scaled_f32(sz, E)
             assert got.tobytes() == want.tobytes(), (sz, E, got, want)
 

@@ -259,7 +259,9 @@ def test_rn_f32_matches_numpy_and_the_c_oracle():
     for _ in range(3000):
         x = np.float64(rng.uniform(1, 2)) * 2.0 ** rng.randrange(-160, 130)
         for v in (x, -x):
-            assert s2.rn_f32(Fraction(float(v))).tobytes() == np.float32(v).tobytes(), v
+            with np.errstate(over="ignore"):  # the overflow to infinity is one of the cases
+                want = np.float32(v)
+            assert s2.rn_f32(Fraction(float(v))).tobytes() == want.tobytes(), v
     for z, E in [(1, -150), (3, -151), (2 ** 24 + 1, 0), (2 ** 24 - 1, 104), (7, -300)]:
         assert s2.scaled_round_f32(z, E).tobytes() == oracle.round_scaled_f32(z, E).tobytes()
     for _ in range(2000):
