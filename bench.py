@@ -26,7 +26,7 @@ INT8_PEAK_TOPS = 5000.0  # MI355X dense INT8 MFMA, TOP/s
 
 
 # HBM bytes per launch of the Scheme I GEMM kernel, measured with rocprofv3
-# FETCH_SIZE / WRITE_SIZE passes on this build's kernel (FETCH scaled by 2.0
+# FETCH_SIZE / WRITE_SIZE passes on the current kernel (FETCH scaled by 2.0
 # and WRITE by 1.0, the factors a 1 GiB device copy gives the two counters);
 # keyed by (n, p, configuration).  Reported only when the run matches; a
 # changed kernel needs new counter passes.
@@ -122,8 +122,8 @@ def cpu_baseline(A, B, p, seconds):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build runs on a single MI355X; "
-              "multi-GPU sharding is described in DESIGN.md but not run", file=sys.stderr)
+        print("bench.py measures one GPU only: the emulated GEMM runs on a single MI355X; "
+              "sharding across GPUs is not implemented", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
