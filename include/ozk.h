@@ -25,6 +25,10 @@
  *   valid: with K == 0 the product is exactly zero.  M and N (rows and
  *   columns of packed operands) are at most OZK_MAX_ROWS = 2^24, K at most
  *   2^40; larger sizes return OZK_ERR_INVALID_ARG.
+ * - Scheme II (and every call that may run it) takes K <= OZK_S2_MAX_K =
+ *   2^22: its row/column scales come from an exact integer bound on the 2-norm
+ *   that adds up to 2^40 per entry in 64-bit integers, which stays exact for
+ *   K < 2^23.  Longer K returns OZK_ERR_UNSUPPORTED.
  * - A row of A or a column of B that holds a NaN or an infinity yields NaN
  *   in the corresponding row/column of alpha*A*B (the paper does not define
  *   this case); finite rows and columns are unaffected.
@@ -82,6 +86,7 @@ extern "C" {
 #define OZK_MAX_P 8
 #define OZK_MAX_S 20
 #define OZK_MAX_ROWS 16777216       /* 2^24: largest M, N (32-bit packed offsets) */
+#define OZK_S2_MAX_K 4194304        /* 2^22: longest K of a Scheme II product (see below) */
 #define OZK_S1_VARIANTS 4           /* Scheme I GEMM tile variants */
 #define OZK_S2_VARIANTS 5           /* Scheme II GEMM variants (the last: fused CRT) */
 #define OZK_S2_FUSED_CRT 4          /* Scheme II variant with the CRT fused into the GEMM (real only) */
@@ -118,6 +123,13 @@ int ozk_last_arg(const ozk_ctx* ctx);
 const char* ozk_status_string(ozk_status s);
 /* Library version, "major.minor.patch". */
 const char* ozk_version(void);
+/* Testing hook: make every Scheme I call on this context fold its K runs
+ * every k values of K instead of every ozk_s1_k_split(p) (whichever is
+ * shorter), which exercises the exact 128-bit fold on small problems.  k is
+ * 0 (back to the default) or a positive multiple of OZK_K_CHUNK; anything
+ * else returns OZK_ERR_INVALID_ARG (arg 2).  Query workspace sizes after
+ * setting it. */
+ozk_status ozk_set_k_split(ozk_ctx* ctx, int64_t k);
 
 /* ---------------------------------------------------------- sizes / layout */
 

@@ -4,9 +4,13 @@ TEST INFRASTRUCTURE ONLY (see the package docstring).
 
 The paper reports "effective bits", the magnitude of the base-2 exponent of
 the relative error, without naming the norm (Sec. V-B).  Reading used here:
-* E_cw = max_ij |C - C_ref|_ij / (|A| |B|)_ij  (componentwise, the gate),
-* E_nw = ||C - C_ref||_F / ||C_ref||_F          (normwise, reported),
-* bits = -log2(E).
+* E_cw = max_ij |C - C_ref|_ij / (|A| |B|)_ij  (componentwise, the gate); for
+  complex data the real and imaginary parts are scaled separately by the
+  magnitude sums of the terms forming them, |Ar||Br| + |Ai||Bi| for the real
+  part and |Ar||Bi| + |Ai||Br| for the imaginary part;
+* E_nw = ||C - C_ref||_F / ||C_ref||_F          (normwise, reported);
+* bits = -log2(E);
+* the median over outputs of |C - C_ref| / |C_ref|  (reported).
 """
 from __future__ import annotations
 
@@ -46,6 +50,8 @@ def _ratio(err, den) -> float:
 
 
 def e_nw(C, ref_hi, ref_lo) -> float:
+    """Frobenius norm of the error over that of the reference (complex
+    entries by their modulus)."""
     C = np.asarray(C)
     diff = (C - ref_hi) - ref_lo
     num = np.sqrt(np.sum(np.abs(diff) ** 2))
@@ -53,5 +59,17 @@ def e_nw(C, ref_hi, ref_lo) -> float:
     return float(num / den) if den > 0 else float(num)
 
 
+def median_rel(C, ref_hi, ref_lo) -> float:
+    """Median over the outputs with a nonzero reference of |C - ref| / |ref|."""
+    C = np.asarray(C)
+    ref = np.asarray(ref_hi) + np.asarray(ref_lo)
+    diff = np.abs((C - ref_hi) - ref_lo)
+    ok = (np.abs(ref) > 0) & np.isfinite(diff)
+    if not ok.any():
+        return 0.0
+    return float(np.median(diff[ok] / np.abs(ref[ok])))
+
+
 def bits(err: float) -> float:
+    """Effective bits of an error: -log2(err), infinite for an exact result."""
     return math.inf if err <= 0 else -math.log2(err)

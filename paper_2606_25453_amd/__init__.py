@@ -33,6 +33,7 @@ OZK_SELECTOR_PARAMS = 6920
 OZK_SELECTOR_COUNTERS = 34
 OZK_SELECTOR_INFO = 8
 OZK_MAX_ROWS = 1 << 24
+OZK_S2_MAX_K = 1 << 22
 OZK_S1_VARIANTS = 4
 OZK_S2_VARIANTS = 5
 OZK_S2_FUSED_CRT = 4
@@ -48,7 +49,7 @@ class OzkGemmConfig(ctypes.Structure):
 
 # every symbol include/ozk.h declares
 EXPORTS = (
-    "ozk_create", "ozk_destroy", "ozk_last_arg", "ozk_status_string", "ozk_version",
+    "ozk_create", "ozk_destroy", "ozk_last_arg", "ozk_status_string", "ozk_version", "ozk_set_k_split",
     "ozk_s1_packed_bytes", "ozk_s2_packed_bytes", "ozk_s1_k_split", "ozk_workspace_size",
     "ozk_dgemm", "ozk_dgemm_t", "ozk_sgemm", "ozk_zgemm_3m", "ozk_cgemm_3m", "ozk_s1_dgemm_unfused", "ozk_s1_unfused_workspace_size", "ozk_s1_split_rows", "ozk_s1_split_cols", "ozk_s1_gemm",
     "ozk_s1_diagonals", "ozk_s2_split_rows", "ozk_s2_split_cols", "ozk_s2_gemm_mod", "ozk_s2_crt",
@@ -84,6 +85,7 @@ def _lib() -> ctypes.CDLL:
         "ozk_last_arg": (I, [P]),
         "ozk_status_string": (ctypes.c_char_p, [I]),
         "ozk_version": (ctypes.c_char_p, []),
+        "ozk_set_k_split": (I, [P, I64]),
         "ozk_s1_packed_bytes": (SZ, [I64, I64, I]),
         "ozk_s2_packed_bytes": (SZ, [I64, I64, I, I]),
         "ozk_s1_k_split": (I64, [I]),
@@ -157,6 +159,50 @@ def _check(fn: str, status: int, ctx) -> None:
         raise OzkError(fn, status, arg)
 
 
+def _need(t, name: str, dtypes, ctx, shape=None, min_numel: int = 0, dim: int = None, on_device: bool = True):
+    """Raise ValueError unless t is a tensor of one of `dtypes`, of `shape`
+    (when given; else of `dim` dimensions when given) and at least
+    `min_numel` elements, on the CUDA device of ctx.  The checks run before
+    anything is enqueued, so a wrong tensor never reaches a kernel."""
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise ValueError("%s must be a torch tensor, got %s" % (name, type(t).__name__))
+    if not isinstance(dtypes, (tuple, list)):
+        dtypes = (dtypes,)
+    if t.dtype not in dtypes:
+        raise ValueError("%s must have dtype %s, got %s" % (name, " or ".join(str(d) for d in dtypes), t.dtype))
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError("%s must have shape %s, got %s" % (name, tuple(shape), tuple(t.shape)))
+    if shape is None and dim is not None and t.dim() != dim:
+        raise ValueError("%s must be %d-dimensional, got shape %s" % (name, dim, tuple(t.shape)))
+    if t.numel() < min_numel:
+        raise ValueError("%s holds %d elements, at least %d are needed" % (name, t.numel(), min_numel))
+    if on_device and (t.device.type != "cuda" or t.device.index != ctx.device):
+        raise ValueError("%s must be on cuda:%d, got %s" % (name, ctx.device, t.device))
+
+
+def _mats(ctx, dtype, A, B, C, trans_a: bool = False, trans_b: bool = False):
+    """Check the operands of C = op(A) op(B) and return (M, N, K)."""
+    _need(A, "A", dtype, ctx, dim=2, on_device=False)
+    _need(B, "B", dtype, ctx, dim=2, on_device=False)
+    M, K = (A.shape[1], A.shape[0]) if trans_a else A.shape
+    Kb, N = (B.shape[1], B.shape[0]) if trans_b else B.shape
+    if Kb != K:
+        raise ValueError("inner dimensions differ: A gives K = %d, B gives %d" % (K, Kb))
+    if C is not None:
+        _need(C, "C", dtype, ctx, shape=(M, N), on_device=False)
+    for t, name in ((A, "A"), (B, "B"), (C, "C")):
+        if t is not None:
+            _need(t, name, dtype, ctx)
+    return M, N, K
+
+
+def _ws(ws, ctx):
+    import torch
+    if ws is not None:
+        _need(ws, "ws", (torch.uint8, torch.int8), ctx, dim=1)
+
+
 def _ld(t) -> int:
     """Leading dimension of a row-major (unit column stride) matrix view."""
     if t.dim() == 2 and t.numel() == 0:
@@ -200,6 +246,11 @@ def ozk_version() -> str:
     return _lib().ozk_version().decode()
 
 
+def ozk_set_k_split(ctx: Context, k: int) -> None:
+    """Testing hook: fold Scheme I K runs every k values of K (0: default)."""
+    _check("ozk_set_k_split", _lib().ozk_set_k_split(ctx.handle, k), ctx)
+
+
 def ozk_s1_packed_bytes(rows: int, K: int, p: int) -> int:
     return int(_lib().ozk_s1_packed_bytes(rows, K, p))
 
@@ -230,8 +281,8 @@ def ozk_dgemm(ctx: Context, scheme: int, p_or_s: int, A, B, C=None, alpha: float
               beta: float = 0.0, ws=None, stream=None):
     """C = alpha*A*B + beta*C (float64 CUDA tensors); returns C."""
     import torch
-    M, K = A.shape
-    N = B.shape[1]
+    M, N, K = _mats(ctx, torch.float64, A, B, C)
+    _ws(ws, ctx)
     if C is None:
         C = torch.empty((M, N), dtype=torch.float64, device=A.device)
     if ws is None:
@@ -247,8 +298,8 @@ def ozk_dgemm_t(ctx: Context, scheme: int, p_or_s: int, A, B, trans_a: bool = Fa
     """C = alpha*op(A)*op(B) + beta*C with op(X) = X.T when its flag is set
     (A, B as stored: float64 CUDA tensors, row-major); returns C."""
     import torch
-    M, K = (A.shape[1], A.shape[0]) if trans_a else A.shape
-    N = B.shape[0] if trans_b else B.shape[1]
+    M, N, K = _mats(ctx, torch.float64, A, B, C, bool(trans_a), bool(trans_b))
+    _ws(ws, ctx)
     if C is None:
         C = torch.empty((M, N), dtype=torch.float64, device=A.device)
     if ws is None:
@@ -265,8 +316,8 @@ def ozk_sgemm(ctx: Context, scheme: int, p_or_s: int, A, B, C=None, alpha: float
     """C = alpha*A*B + beta*C (float32 CUDA tensors) by Scheme I (p slices) or
     Scheme II (s moduli); returns C."""
     import torch
-    M, K = A.shape
-    N = B.shape[1]
+    M, N, K = _mats(ctx, torch.float32, A, B, C)
+    _ws(ws, ctx)
     if C is None:
         C = torch.empty((M, N), dtype=torch.float32, device=A.device)
     if ws is None:
@@ -289,8 +340,8 @@ def ozk_s1_dgemm_unfused(ctx: Context, p: int, A, B, C=None, alpha: float = 1.0,
     """The unfused Scheme I baseline (one GEMM per slice pair, INT32 planes
     through HBM); bit-identical to ozk_dgemm(OZK_SCHEME1, p)."""
     import torch
-    M, K = A.shape
-    N = B.shape[1]
+    M, N, K = _mats(ctx, torch.float64, A, B, C)
+    _ws(ws, ctx)
     if C is None:
         C = torch.empty((M, N), dtype=torch.float64, device=A.device)
     if ws is None:
@@ -305,8 +356,8 @@ def ozk_cgemm_3m(ctx: Context, s: int, A, B, C=None, alpha: complex = 1.0, beta:
                  stream=None):
     """C = alpha*A*B + beta*C (complex64 CUDA tensors) with Scheme II + 3M."""
     import torch
-    M, K = A.shape
-    N = B.shape[1]
+    M, N, K = _mats(ctx, torch.complex64, A, B, C)
+    _ws(ws, ctx)
     if C is None:
         C = torch.empty((M, N), dtype=torch.complex64, device=A.device)
     if ws is None:
@@ -324,8 +375,8 @@ def ozk_zgemm_3m(ctx: Context, s: int, A, B, C=None, alpha: complex = 1.0, beta:
                  stream=None):
     """C = alpha*A*B + beta*C (complex128 CUDA tensors) with Scheme II + 3M."""
     import torch
-    M, K = A.shape
-    N = B.shape[1]
+    M, N, K = _mats(ctx, torch.complex128, A, B, C)
+    _ws(ws, ctx)
     if C is None:
         C = torch.empty((M, N), dtype=torch.complex128, device=A.device)
     if ws is None:
@@ -344,7 +395,12 @@ def ozk_zgemm_3m(ctx: Context, s: int, A, B, C=None, alpha: complex = 1.0, beta:
 def ozk_s1_split_rows(ctx: Context, p: int, X, e=None, packed=None, stream=None):
     """Row exponents and packed slices of a row operand; returns (e, packed)."""
     import torch
+    _need(X, "X", torch.float64, ctx, dim=2)
     rows, K = X.shape
+    if e is not None:
+        _need(e, "e", torch.int32, ctx, min_numel=rows)
+    if packed is not None:
+        _need(packed, "packed", torch.int8, ctx, min_numel=ozk_s1_packed_bytes(rows, K, p))
     if e is None:
         e = torch.empty(max(rows, 1), dtype=torch.int32, device=X.device)
     if packed is None:
@@ -357,7 +413,12 @@ def ozk_s1_split_rows(ctx: Context, p: int, X, e=None, packed=None, stream=None)
 def ozk_s1_split_cols(ctx: Context, p: int, X, f=None, packed=None, stream=None):
     """Column exponents and packed (transposed) slices of a column operand."""
     import torch
+    _need(X, "X", torch.float64, ctx, dim=2)
     K, cols = X.shape
+    if f is not None:
+        _need(f, "f", torch.int32, ctx, min_numel=cols)
+    if packed is not None:
+        _need(packed, "packed", torch.int8, ctx, min_numel=ozk_s1_packed_bytes(cols, K, p))
     if f is None:
         f = torch.empty(max(cols, 1), dtype=torch.int32, device=X.device)
     if packed is None:
@@ -369,6 +430,13 @@ def ozk_s1_split_cols(ctx: Context, p: int, X, f=None, packed=None, stream=None)
 
 def ozk_s1_gemm(ctx: Context, p: int, M: int, N: int, K: int, packedA, e, packedB, f, C, alpha: float = 1.0,
                 beta: float = 0.0, ws=None, stream=None):
+    import torch
+    _need(packedA, "packedA", torch.int8, ctx, min_numel=ozk_s1_packed_bytes(M, K, p))
+    _need(packedB, "packedB", torch.int8, ctx, min_numel=ozk_s1_packed_bytes(N, K, p))
+    _need(e, "e", torch.int32, ctx, min_numel=M)
+    _need(f, "f", torch.int32, ctx, min_numel=N)
+    _need(C, "C", torch.float64, ctx, shape=(M, N))
+    _ws(ws, ctx)
     st = _lib().ozk_s1_gemm(ctx.handle, p, M, N, K, _ptr(packedA), _ptr(e), _ptr(packedB), _ptr(f), float(alpha),
                             float(beta), _ptr(C), _ld(C), _ptr(ws), 0 if ws is None else ws.numel(),
                             _stream(stream))
@@ -379,6 +447,10 @@ def ozk_s1_gemm(ctx: Context, p: int, M: int, N: int, K: int, packedA, e, packed
 def ozk_s1_diagonals(ctx: Context, p: int, M: int, N: int, K: int, packedA, packedB, Cd=None, stream=None):
     """Raw INT32 diagonals [p][M][N] of the fused kernel."""
     import torch
+    _need(packedA, "packedA", torch.int8, ctx, min_numel=ozk_s1_packed_bytes(M, K, p))
+    _need(packedB, "packedB", torch.int8, ctx, min_numel=ozk_s1_packed_bytes(N, K, p))
+    if Cd is not None:
+        _need(Cd, "Cd", torch.int32, ctx, shape=(p, M, N))
     if Cd is None:
         Cd = torch.empty((p, M, N), dtype=torch.int32, device=packedA.device)
     st = _lib().ozk_s1_diagonals(ctx.handle, p, M, N, K, _ptr(packedA), _ptr(packedB), _ptr(Cd), _stream(stream))
@@ -390,7 +462,12 @@ def ozk_s1_diagonals(ctx: Context, p: int, M: int, N: int, K: int, packedA, pack
 
 def ozk_s2_split_rows(ctx: Context, s: int, X, complex_planes: int = 0, sigma=None, packed=None, stream=None):
     import torch
+    _need(X, "X", torch.complex128 if complex_planes else torch.float64, ctx, dim=2)
     rows, K = X.shape
+    if sigma is not None:
+        _need(sigma, "sigma", torch.int32, ctx, min_numel=rows)
+    if packed is not None:
+        _need(packed, "packed", torch.int8, ctx, min_numel=ozk_s2_packed_bytes(rows, K, s, complex_planes))
     if sigma is None:
         sigma = torch.empty(max(rows, 1), dtype=torch.int32, device=X.device)
     if packed is None:
@@ -404,7 +481,12 @@ def ozk_s2_split_rows(ctx: Context, s: int, X, complex_planes: int = 0, sigma=No
 
 def ozk_s2_split_cols(ctx: Context, s: int, X, complex_planes: int = 0, tau=None, packed=None, stream=None):
     import torch
+    _need(X, "X", torch.complex128 if complex_planes else torch.float64, ctx, dim=2)
     K, cols = X.shape
+    if tau is not None:
+        _need(tau, "tau", torch.int32, ctx, min_numel=cols)
+    if packed is not None:
+        _need(packed, "packed", torch.int8, ctx, min_numel=ozk_s2_packed_bytes(cols, K, s, complex_planes))
     if tau is None:
         tau = torch.empty(max(cols, 1), dtype=torch.int32, device=X.device)
     if packed is None:
@@ -419,6 +501,10 @@ def ozk_s2_split_cols(ctx: Context, s: int, X, complex_planes: int = 0, tau=None
 def ozk_s2_gemm_mod(ctx: Context, s: int, M: int, N: int, K: int, packedA, packedB, complex_planes: int = 0,
                     Cres=None, stream=None):
     import torch
+    _need(packedA, "packedA", torch.int8, ctx, min_numel=ozk_s2_packed_bytes(M, K, s, complex_planes))
+    _need(packedB, "packedB", torch.int8, ctx, min_numel=ozk_s2_packed_bytes(N, K, s, complex_planes))
+    if Cres is not None:
+        _need(Cres, "Cres", torch.int8, ctx, shape=(s * (2 if complex_planes else 1), M, N))
     if Cres is None:
         Cres = torch.empty((s * (2 if complex_planes else 1), M, N), dtype=torch.int8, device=packedA.device)
     st = _lib().ozk_s2_gemm_mod(ctx.handle, s, complex_planes, M, N, K, _ptr(packedA), _ptr(packedB), _ptr(Cres),
@@ -429,6 +515,11 @@ def ozk_s2_gemm_mod(ctx: Context, s: int, M: int, N: int, K: int, packedA, packe
 
 def ozk_s2_crt(ctx: Context, s: int, M: int, N: int, Cres, sigma, tau, C, alpha=1.0, beta=0.0,
                complex_planes: int = 0, stream=None):
+    import torch
+    _need(Cres, "Cres", torch.int8, ctx, shape=(s * (2 if complex_planes else 1), M, N))
+    _need(sigma, "sigma", torch.int32, ctx, min_numel=M)
+    _need(tau, "tau", torch.int32, ctx, min_numel=N)
+    _need(C, "C", torch.complex128 if complex_planes else torch.float64, ctx, shape=(M, N))
     al = (ctypes.c_double * 2)(complex(alpha).real, complex(alpha).imag)
     be = (ctypes.c_double * 2)(complex(beta).real, complex(beta).imag)
     st = _lib().ozk_s2_crt(ctx.handle, s, complex_planes, M, N, _ptr(Cres), _ptr(sigma), _ptr(tau),
@@ -491,6 +582,12 @@ class BatchPlan:
         self.ctx = ctx
         self.keep = list(problems)  # the plan keeps raw pointers to these tensors
         al, be = complex(alpha), complex(beta)
+        dtype = torch.complex128 if op == OZK_OP_ZGEMM else torch.float64
+        for i, (A, B, C) in enumerate(self.keep):
+            try:
+                _mats(ctx, dtype, A, B, C)
+            except ValueError as err:
+                raise ValueError("problem %d: %s" % (i, err)) from None
         descs = []
         for A, B, C in self.keep:
             d = OzkGemmDesc()
@@ -562,8 +659,8 @@ def ozk_tune(ctx: Context, op: int, scheme: int, p_or_s: int, A, B, C=None, reps
     """Tune the size class of A B (float64 or complex128 CUDA tensors); returns
     (C = A B, best config tuple, best ms)."""
     import torch
-    M, K = A.shape
-    N = B.shape[1]
+    M, N, K = _mats(ctx, torch.complex128 if op == OZK_OP_ZGEMM else torch.float64, A, B, C)
+    _ws(ws, ctx)
     if C is None:
         C = torch.empty((M, N), dtype=A.dtype, device=A.device)
     if ws is None:
@@ -583,8 +680,7 @@ def ozk_select(ctx: Context, tol: float, A, B, stream=None):
     as device tensors; info = [p (0 with Scheme II), p_net, p_bound,
     out_of_range, scheme, s (0 with Scheme I), s_bound, 0]."""
     import torch
-    M, K = A.shape
-    N = B.shape[1]
+    M, N, K = _mats(ctx, torch.float64, A, B, None)
     e = torch.empty(max(M, 1), dtype=torch.int32, device=A.device)
     f = torch.empty(max(N, 1), dtype=torch.int32, device=A.device)
     cnt = torch.empty(OZK_SELECTOR_COUNTERS, dtype=torch.int32, device=A.device)
@@ -602,8 +698,10 @@ def ozk_dgemm_auto(ctx: Context, tol: float, A, B, C=None, alpha: float = 1.0, b
     for the componentwise tolerance tol; returns (C, info) with info the
     device int32[8] decision (see ozk_select)."""
     import torch
-    M, K = A.shape
-    N = B.shape[1]
+    M, N, K = _mats(ctx, torch.float64, A, B, C)
+    _ws(ws, ctx)
+    if info is not None:
+        _need(info, "info", torch.int32, ctx, min_numel=OZK_SELECTOR_INFO)
     if C is None:
         C = torch.empty((M, N), dtype=torch.float64, device=A.device)
     if ws is None:

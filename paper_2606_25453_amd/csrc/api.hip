@@ -164,6 +164,9 @@ bool bad_dims(int64_t M, int64_t N, int64_t K) {
   return bad_rows(M) || bad_rows(N) || K < 0 || K > ((int64_t)1 << 40);
 }
 
+// Scheme II scales need K <= OZK_S2_MAX_K (exact 64-bit norm-bound sums).
+bool s2_long_k(int64_t K) { return K > OZK_S2_MAX_K; }
+
 int log2_class(int64_t x) {
   int b = 0;
   while (b < 62 && ((int64_t)1 << b) < x) ++b;
@@ -222,8 +225,6 @@ ozk_status ozk_create(ozk_ctx** ctx, int device) {
     delete c;
     return OZK_ERR_HIP;
   }
-  const char* ks = getenv("OZK_K_SPLIT");
-  if (ks) c->k_split_override = atoll(ks);
   *ctx = c;
   return OZK_OK;
 }
@@ -235,6 +236,14 @@ ozk_status ozk_destroy(ozk_ctx* ctx) {
 }
 
 int ozk_last_arg(const ozk_ctx* ctx) { return ctx ? ctx->last_arg : 0; }
+
+ozk_status ozk_set_k_split(ozk_ctx* ctx, int64_t k) {
+  if (!ctx) return OZK_ERR_INVALID_ARG;
+  ctx->last_arg = 0;
+  if (k < 0 || k % OZK_K_CHUNK != 0) return fail(ctx, OZK_ERR_INVALID_ARG, 2);
+  ctx->k_split_override = k;
+  return OZK_OK;
+}
 
 size_t ozk_s1_packed_bytes(int64_t rows, int64_t K, int p) {
   if (rows < 0 || K < 0 || p < 1) return 0;
@@ -380,6 +389,8 @@ static ozk_status dgemm_run(ozk_ctx* ctx, ozk_scheme scheme, int p_or_s, bool tr
   if (scheme == OZK_SCHEME2) {
     const int s = p_or_s;
     if (s < 1 || s > OZK_MAX_S) return fail(ctx, OZK_ERR_UNSUPPORTED, 3);
+    // K is argument 6 of ozk_dgemm (workspace 15) and 8 of ozk_dgemm_t (workspace 19)
+    if (s2_long_k(K)) return fail(ctx, OZK_ERR_UNSUPPORTED, ws_arg == 15 ? 6 : 8);
     const S2Plan pl = s2_plan(s, false, M, N, K);
     if (!ws || ws_bytes < pl.total) return fail(ctx, OZK_ERR_WORKSPACE, ws_arg);
     if (M == 0 || N == 0) return OZK_OK;
@@ -535,6 +546,7 @@ ozk_status ozk_sgemm(ozk_ctx* ctx, ozk_scheme scheme, int p_or_s, int64_t M, int
   if (scheme == OZK_SCHEME2) {
     const int s = p_or_s;
     if (s < 1 || s > OZK_MAX_S) return fail(ctx, OZK_ERR_UNSUPPORTED, 3);
+    if (s2_long_k(K)) return fail(ctx, OZK_ERR_UNSUPPORTED, 6);
     const S2Plan pl = s2_plan(s, false, M, N, K);
     if (!ws || ws_bytes < pl.total) return fail(ctx, OZK_ERR_WORKSPACE, 15);
     if (M == 0 || N == 0) return OZK_OK;
@@ -586,6 +598,7 @@ ozk_status ozk_cgemm_3m(ozk_ctx* ctx, int s, int64_t M, int64_t N, int64_t K, co
   if (!beta) return fail(ctx, OZK_ERR_INVALID_ARG, 11);
   if (!C && M > 0 && N > 0) return fail(ctx, OZK_ERR_INVALID_ARG, 12);
   if (ldc < (N > 0 ? N : 1)) return fail(ctx, OZK_ERR_INVALID_ARG, 13);
+  if (s2_long_k(K)) return fail(ctx, OZK_ERR_UNSUPPORTED, 5);
   const S2Plan pl = s2_plan(s, true, M, N, K);
   if (!ws || ws_bytes < pl.total) return fail(ctx, OZK_ERR_WORKSPACE, 14);
   if (M == 0 || N == 0) return OZK_OK;
@@ -619,6 +632,7 @@ ozk_status ozk_zgemm_3m(ozk_ctx* ctx, int s, int64_t M, int64_t N, int64_t K, co
   if (!beta) return fail(ctx, OZK_ERR_INVALID_ARG, 11);
   if (!C && M > 0 && N > 0) return fail(ctx, OZK_ERR_INVALID_ARG, 12);
   if (ldc < (N > 0 ? N : 1)) return fail(ctx, OZK_ERR_INVALID_ARG, 13);
+  if (s2_long_k(K)) return fail(ctx, OZK_ERR_UNSUPPORTED, 5);
   const S2Plan pl = s2_plan(s, true, M, N, K);
   if (!ws || ws_bytes < pl.total) return fail(ctx, OZK_ERR_WORKSPACE, 14);
   if (M == 0 || N == 0) return OZK_OK;
@@ -646,6 +660,7 @@ ozk_status ozk_s2_split_rows(ozk_ctx* ctx, int s, int complex_planes, int64_t ro
   if (complex_planes != 0 && complex_planes != 1) return fail(ctx, OZK_ERR_INVALID_ARG, 3);
   if (bad_rows(rows)) return fail(ctx, OZK_ERR_INVALID_ARG, 4);
   if (K < 0 || K > ((int64_t)1 << 40)) return fail(ctx, OZK_ERR_INVALID_ARG, 5);
+  if (s2_long_k(K)) return fail(ctx, OZK_ERR_UNSUPPORTED, 5);
   if (!X && rows > 0 && K > 0) return fail(ctx, OZK_ERR_INVALID_ARG, 6);
   if (ldx < (K > 0 ? K : 1)) return fail(ctx, OZK_ERR_INVALID_ARG, 7);
   if (!sigma && rows > 0) return fail(ctx, OZK_ERR_INVALID_ARG, 8);
@@ -661,6 +676,7 @@ ozk_status ozk_s2_split_cols(ozk_ctx* ctx, int s, int complex_planes, int64_t K,
   if (s < 1 || s > OZK_MAX_S) return fail(ctx, OZK_ERR_UNSUPPORTED, 2);
   if (complex_planes != 0 && complex_planes != 1) return fail(ctx, OZK_ERR_INVALID_ARG, 3);
   if (K < 0 || K > ((int64_t)1 << 40)) return fail(ctx, OZK_ERR_INVALID_ARG, 4);
+  if (s2_long_k(K)) return fail(ctx, OZK_ERR_UNSUPPORTED, 4);
   if (bad_rows(cols)) return fail(ctx, OZK_ERR_INVALID_ARG, 5);
   if (!X && cols > 0 && K > 0) return fail(ctx, OZK_ERR_INVALID_ARG, 6);
   if (ldx < (cols > 0 ? cols : 1)) return fail(ctx, OZK_ERR_INVALID_ARG, 7);
@@ -751,6 +767,7 @@ ozk_status ozk_dgemm_auto(ozk_ctx* ctx, double tol, int64_t M, int64_t N, int64_
   if (ldb < (N > 0 ? N : 1)) return fail(ctx, OZK_ERR_INVALID_ARG, 10);
   if (!C && M > 0 && N > 0) return fail(ctx, OZK_ERR_INVALID_ARG, 12);
   if (ldc < (N > 0 ? N : 1)) return fail(ctx, OZK_ERR_INVALID_ARG, 13);
+  if (s2_long_k(K)) return fail(ctx, OZK_ERR_UNSUPPORTED, 5);  // Scheme II may be chosen
   const AutoPlan ap = auto_plan(ctx, M, N, K);
   if (!ws || ws_bytes < ap.total) return fail(ctx, OZK_ERR_WORKSPACE, 14);
   if (M == 0 || N == 0) return OZK_OK;
@@ -877,6 +894,7 @@ ozk_status ozk_batch_plan_create(ozk_ctx* ctx, ozk_op op, ozk_scheme scheme, int
         d.ldc < (d.N > 0 ? d.N : 1) || (!d.A && d.M > 0 && d.K > 0) || (!d.B && d.K > 0 && d.N > 0) ||
         (!d.C && d.M > 0 && d.N > 0))
       return fail(ctx, OZK_ERR_INVALID_ARG, 6);
+    if (s2_long_k(d.K)) return fail(ctx, OZK_ERR_UNSUPPORTED, 6);
   }
   std::vector<ozk::BatchProb> prob(count);
   size_t o = 0;
@@ -1248,6 +1266,7 @@ ozk_status ozk_tune(ozk_ctx* ctx, ozk_op op, ozk_scheme scheme, int p_or_s, int6
   } else {
     const int s = p_or_s;
     const bool cplx = op == OZK_OP_ZGEMM;
+    if (s2_long_k(K)) return fail(ctx, OZK_ERR_UNSUPPORTED, 7);
     const S2Plan pl = s2_plan(s, cplx, M, N, K);
     if (!ws || ws_bytes < pl.total) return fail(ctx, OZK_ERR_WORKSPACE, 15);
     if (M > 0 && N > 0) {

@@ -66,3 +66,40 @@ def test_header_constants_match_the_binding():
     assert {"OZK_S1_VARIANTS", "OZK_S2_VARIANTS", "OZK_S2_FUSED_CRT", "OZK_K_CHUNK", "OZK_ROW_ALIGN"} <= set(mirrored)
     for k in mirrored:
         assert getattr(ozk, k) == defines[k], k
+
+
+def _fake_ctx():
+    """A Context object that was never created on a device: the binding's
+    argument checks must reject the tensors below before it is used."""
+    c = ozk.Context.__new__(ozk.Context)
+    c.handle = None
+    c.device = 0
+    return c
+
+
+def test_binding_rejects_bad_tensors_before_any_call():
+    torch = pytest.importorskip("torch")
+    ctx = _fake_ctx()
+    f64 = lambda *s: torch.zeros(*s, dtype=torch.float64)  # noqa: E731
+    cases = [
+        (lambda: ozk.ozk_dgemm(ctx, 1, 4, f64(4, 5), f64(6, 3)), "inner dimensions"),
+        (lambda: ozk.ozk_dgemm(ctx, 1, 4, f64(4, 5).float(), f64(5, 3)), "dtype"),
+        (lambda: ozk.ozk_dgemm(ctx, 1, 4, f64(4, 5), f64(5, 3), C=f64(4, 2)), "shape"),
+        (lambda: ozk.ozk_dgemm(ctx, 1, 4, f64(20), f64(5, 3)), "2-dimensional"),
+        (lambda: ozk.ozk_dgemm(ctx, 1, 4, f64(4, 5), f64(5, 3)), "cuda:0"),
+        (lambda: ozk.ozk_dgemm(ctx, 1, 4, [[1.0]], f64(5, 3)), "torch tensor"),
+        (lambda: ozk.ozk_dgemm_t(ctx, 1, 4, f64(5, 4), f64(5, 3), trans_a=True, C=f64(3, 4)), "shape"),
+        (lambda: ozk.ozk_sgemm(ctx, 1, 4, f64(4, 5), f64(5, 3)), "dtype"),
+        (lambda: ozk.ozk_zgemm_3m(ctx, 8, f64(4, 5), f64(5, 3)), "dtype"),
+        (lambda: ozk.ozk_cgemm_3m(ctx, 8, f64(4, 5).to(torch.complex128), f64(5, 3).to(torch.complex128)), "dtype"),
+        (lambda: ozk.ozk_s1_dgemm_unfused(ctx, 3, f64(4, 5), f64(4, 3)), "inner dimensions"),
+        (lambda: ozk.ozk_s2_split_rows(ctx, 8, f64(4, 5), complex_planes=1), "dtype"),
+        (lambda: ozk.ozk_s1_diagonals(ctx, 3, 4, 4, 4, torch.zeros(10, dtype=torch.int8),
+                                      torch.zeros(10, dtype=torch.int8)), "elements"),
+        (lambda: ozk.BatchPlan(ctx, ozk.OZK_OP_ZGEMM, ozk.OZK_SCHEME2, 8, [(f64(2, 2), f64(2, 2), f64(2, 2))]),
+         "problem 0"),
+    ]
+    for fn, what in cases:
+        with pytest.raises(ValueError) as ei:
+            fn()
+        assert what in str(ei.value), (what, str(ei.value))

@@ -219,13 +219,22 @@ def test_3m_sum_plane_and_exactness_condition():
         assert ((s_sum.astype(int) - s_re - s_im) % m == 0).all()
 
 
-def test_zaxpby_sequence():
-    H = np.array([[1.5 + 2j, -3 - 0.25j]])
-    C = np.array([[0.1 + 0.2j, 7 - 1j]])
-    out = s2.zaxpby(2 - 1j, H, 0.5 + 0.5j, C)
-    ref = (2 - 1j) * H + (0.5 + 0.5j) * C
-    assert np.allclose(out, ref, rtol=1e-15, atol=0)
-    assert np.array_equal(s2.zaxpby(1.0, H, 0.0, np.full((1, 2), np.nan)), H)
+def test_scale_formula_at_the_k_limit():
+    """K = 2^22 entries of one exponent push the norm-bound sum S to 2^62 (the
+    largest K the library takes for Scheme II keeps it below 2^63): nb =
+    e + ceil((62 - 40) / 2) = e + 11, and the scaled row norm stays below
+    2^T as the exactness condition needs (exact check in integers)."""
+    K = 1 << 22
+    ta, _ = s2.targets(16)
+    A = np.full((1, K), -0.75)  # e = 0
+    sig, _ = s2.row_scales(A, ta)
+    assert int(sig[0]) == ta - 11
+    # ||a||^2 4^sigma = K (3/4)^2 4^(ta - 11) < 4^ta  <=>  9 K < 16 4^11
+    assert 9 * K < 16 * 4 ** 11
+    # one entry twice as large moves e up by one and nb with it
+    A[0, 5] = -1.5
+    sig2, _ = s2.row_scales(A, ta)
+    assert int(sig2[0]) == ta - 12
 
 
 def test_entries_match_full_results():

@@ -151,3 +151,23 @@ def test_predict_and_targets():
     logits = np.where(y > 0, 5.0, -5.0)
     assert sel.predict_p(logits).tolist() == [1, 3, 9]
     assert sel.predict_p(logits, margin=1).tolist() == [2, 4, 9]
+
+
+def test_forward_on_a_hand_evaluated_network():
+    """x = (3, 1, 2, 0, ...): layer 1 gives z = (2*3 - 1, 2 - 5) = (5, -3) ->
+    ReLU (5, 0); layer 2 gives (0.5*5 + 1, 7*0 - 1) = (3.5, -1) -> (3.5, 0);
+    head t (t = 0..7) is 3.5 t + 0.25.  A missing bias, a missing ReLU or a
+    transposed weight changes some head."""
+    W1 = np.zeros((sel.N_FEAT, sel.HIDDEN))
+    b1 = np.zeros(sel.HIDDEN)
+    W2 = np.zeros((sel.HIDDEN, sel.HIDDEN))
+    b2 = np.zeros(sel.HIDDEN)
+    W3 = np.zeros((sel.HIDDEN, sel.N_OUT))
+    b3 = np.full(sel.N_OUT, 0.25)
+    W1[0, 0], W1[1, 0], W1[2, 1], b1[1] = 2.0, -1.0, 1.0, -5.0
+    W2[0, 0], b2[0], W2[1, 1], b2[1] = 0.5, 1.0, 7.0, -1.0
+    W3[0, :] = np.arange(sel.N_OUT)
+    X = np.zeros((1, sel.N_FEAT))
+    X[0, :3] = (3.0, 1.0, 2.0)
+    out, _ = sel.mlp_forward((W1, b1, W2, b2, W3, b3), X)
+    assert np.array_equal(out[0], 3.5 * np.arange(sel.N_OUT) + 0.25)

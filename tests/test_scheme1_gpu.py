@@ -204,13 +204,13 @@ def test_empty_dimensions(ctx):
 
 
 def test_k_runs_fold_exactly():
-    """Shorter overflow-free K runs (forced through OZK_K_SPLIT) fold into the
-    same result as one run."""
-    os.environ["OZK_K_SPLIT"] = "64"
-    try:
-        c2 = ozk.Context(0)
-    finally:
-        del os.environ["OZK_K_SPLIT"]
+    """Shorter overflow-free K runs (forced through ozk_set_k_split) fold into
+    the same result as one run."""
+    c2 = ozk.Context(0)
+    for bad in (-32, 1, 31, 33):
+        with pytest.raises(ozk.OzkError):
+            ozk.ozk_set_k_split(c2, bad)
+    ozk.ozk_set_k_split(c2, 64)
     M, N, K, p = 150, 70, 333, 8
     A = synth.phi_matrix(M, K, 1.0, 21)
     B = synth.phi_matrix(K, N, 1.0, 22)
