@@ -75,3 +75,16 @@ def with_structure(X: np.ndarray, seed: int, zero_rows=(), zero_cols=(),
         for i, e in scale_rows.items():
             Y[i, :] = np.ldexp(Y[i, :], e)
     return Y
+
+
+def phi_matrix_device(rows: int, cols: int, phi: float, seed: int, device="cuda:0"):
+    """The same distribution drawn on the GPU with torch's seeded generator
+    (for full-size problems; tests copy the rows and columns they check back
+    to the host, so both sides see identical bits).  Returns a float64
+    torch tensor."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    u = torch.rand((rows, cols), generator=g, dtype=torch.float64, device=device)
+    n = torch.randn((rows, cols), generator=g, dtype=torch.float64, device=device)
+    return (u - 0.5) * torch.exp(phi * n)
