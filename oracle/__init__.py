@@ -286,3 +286,51 @@ def s1_sgemm(A, B, p: int, alpha=1.0, beta=0.0, C=None) -> np.ndarray:
     if rc != 0:
         raise ValueError("orc_s1_sgemm failed (%d)" % rc)
     return out
+
+
+# ------------------------------------------------- Scheme I complex (4M)
+
+def s1_complex_embed(A, B):
+    """The real matrices whose product holds the four real products of the
+    4M complex product (Sec. IV-B): A' = [Re A, Im A] (M x 2K) and B'' (2K x
+    2N) with, for k < K,
+        B''[k, 2j] = Re B[k, j],      B''[k, 2j+1] = Im B[k, j],
+        B''[K+k, 2j] = -Im B[k, j],   B''[K+k, 2j+1] = Re B[k, j],
+    so that (A' B'')[i, 2j] = Re(A B)[i, j] and (A' B'')[i, 2j+1] = Im(A B)[i, j]
+    (Re = Ar Br - Ai Bi, Im = Ar Bi + Ai Br).  Row i of A' holds both parts of
+    row i of A, so its Scheme I exponent is shared by them; columns 2j and
+    2j+1 of B'' hold the same magnitudes, so they share one exponent."""
+    A = np.asarray(A)
+    B = np.asarray(B)
+    real = np.float32 if A.dtype == np.complex64 else np.float64
+    M, K = A.shape
+    N = B.shape[1]
+    A2 = np.concatenate([A.real, A.imag], axis=1).astype(real)
+    B2 = np.empty((2 * K, 2 * N), real)
+    B2[:K, 0::2] = B.real
+    B2[:K, 1::2] = B.imag
+    B2[K:, 0::2] = -B.imag
+    B2[K:, 1::2] = B.real
+    return np.ascontiguousarray(A2), B2
+
+
+def s1_zgemm(A, B, p: int, alpha=1.0, beta=0.0, C=None) -> np.ndarray:
+    """Scheme I ZGEMM by 4M: Scheme I (p slices) on the embedded real
+    matrices, whose exact integer products are the four real products with
+    the subtraction and addition of 4M done before the one rounding of each
+    part; then the complex alpha/beta update of zaxpby."""
+    from .scheme2 import zaxpby
+    A2, B2 = s1_complex_embed(np.asarray(A, np.complex128), np.asarray(B, np.complex128))
+    H2 = s1_dgemm(A2, B2, p)
+    H = H2[:, 0::2] + 1j * H2[:, 1::2]
+    return zaxpby(alpha, H, beta, C)
+
+
+def s1_cgemm(A, B, p: int, alpha=1.0, beta=0.0, C=None) -> np.ndarray:
+    """Scheme I CGEMM (complex64 in and out) by 4M: the embedded binary32
+    matrices through the Scheme I SGEMM steps (one rounding of each part to
+    binary32), then the complex alpha/beta update in binary32."""
+    from .scheme2 import zaxpby_f32
+    A2, B2 = s1_complex_embed(np.asarray(A, np.complex64), np.asarray(B, np.complex64))
+    H2 = s1_sgemm(A2, B2, p)
+    return zaxpby_f32(alpha, H2[:, 0::2], H2[:, 1::2], beta, C)

@@ -529,12 +529,18 @@ def z3m_cgemm(A, B, s: int, alpha=1.0, beta=0.0, C=None):
     Him[st["bad_r"], :] = np.nan
     Hre[:, st["bad_c"]] = np.nan
     Him[:, st["bad_c"]] = np.nan
+    return zaxpby_f32(alpha, Hre, Him, beta, C)
+
+
+def zaxpby_f32(alpha: complex, Hre: np.ndarray, Him: np.ndarray, beta: complex, C) -> np.ndarray:
+    """The fixed FMA sequence of zaxpby in binary32 (fmaf), for the binary32
+    parts Hre, Him of the complex result; beta == 0: C is not read."""
     al, be = complex(alpha), complex(beta)
     ar, ai, br, bi = (np.float32(v) for v in (al.real, al.imag, be.real, be.imag))
     out = np.empty(Hre.shape, np.complex64)
     Cc = None if be == 0 else np.asarray(C, np.complex64)
     for idx in np.ndindex(Hre.shape):
-        hr, hi = Hre[idx], Him[idx]
+        hr, hi = np.float32(Hre[idx]), np.float32(Him[idx])
         if be == 0:
             bre = bim = np.float32(0.0)
         else:
