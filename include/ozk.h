@@ -90,6 +90,7 @@ extern "C" {
 #define OZK_S1_VARIANTS 4           /* Scheme I GEMM tile variants */
 #define OZK_S2_VARIANTS 5           /* Scheme II GEMM variants (the last: fused CRT) */
 #define OZK_S2_FUSED_CRT 4          /* Scheme II variant with the CRT fused into the GEMM (real only) */
+#define OZK_NOALLOC_SCRATCH_BYTES 67108864  /* 64 MiB: the fixed buffer of ozk_dgemm_noalloc */
 #define OZK_SELECTOR_PARAMS 6920   /* float32 parameters of the selector MLP */
 #define OZK_SELECTOR_COUNTERS 34   /* int32 feature counters */
 #define OZK_SELECTOR_INFO 8        /* int32 decision entries */
@@ -166,6 +167,28 @@ ozk_status ozk_dgemm(ozk_ctx* ctx, ozk_scheme scheme, int p_or_s, int64_t M,
                      int64_t lda, const double* B, int64_t ldb, double beta,
                      double* C, int64_t ldc, void* ws, size_t ws_bytes,
                      hipStream_t stream);
+
+/* ozk_dgemm for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same computation, argument meanings, layouts and errors as ozk_dgemm,
+ * bit-identical results, but no workspace argument.  The workspace ozk_dgemm
+ * would take lives in a fixed buffer of OZK_NOALLOC_SCRATCH_BYTES (64 MiB)
+ * inside the library, a static device array of which every device the
+ * library runs on holds its own copy until the process ends; its address is
+ * looked up once per device when a context is created.  Problems whose
+ * ozk_workspace_size(ctx, OZK_OP_DGEMM, scheme, M, N, K, p_or_s) exceeds the
+ * buffer return OZK_ERR_WORKSPACE (ozk_last_arg() = 4) before anything is
+ * enqueued; e.g. Scheme I at p = 7 fits up to M = N = K = 2048.  The call
+ * allocates and frees nothing, and needs no zeroed memory (every kernel
+ * initialises what it accumulates into).  All calls on one device share the
+ * buffer and it keeps the last call's contents: calls that overlap on one
+ * device (other streams, other host threads) race and must be ordered by
+ * the caller, e.g. by issuing them on one stream. */
+ozk_status ozk_dgemm_noalloc(ozk_ctx* ctx, ozk_scheme scheme, int p_or_s,
+                             int64_t M, int64_t N, int64_t K, double alpha,
+                             const double* A, int64_t lda, const double* B,
+                             int64_t ldb, double beta, double* C, int64_t ldc,
+                             hipStream_t stream);
 
 /* ozk_dgemm with transposed operands: C = alpha*op(A)*op(B) + beta*C where
  * op(A) = A (trans_a = 0: A stored M x K, lda >= K) or A^T (trans_a = 1: A

@@ -37,6 +37,7 @@ OZK_S2_MAX_K = 1 << 22
 OZK_S1_VARIANTS = 4
 OZK_S2_VARIANTS = 5
 OZK_S2_FUSED_CRT = 4
+OZK_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
 class OzkGemmConfig(ctypes.Structure):
@@ -51,7 +52,7 @@ class OzkGemmConfig(ctypes.Structure):
 EXPORTS = (
     "ozk_create", "ozk_destroy", "ozk_last_arg", "ozk_status_string", "ozk_version", "ozk_set_k_split",
     "ozk_s1_packed_bytes", "ozk_s2_packed_bytes", "ozk_s1_k_split", "ozk_workspace_size",
-    "ozk_dgemm", "ozk_dgemm_t", "ozk_sgemm", "ozk_zgemm_3m", "ozk_cgemm_3m", "ozk_s1_dgemm_unfused", "ozk_s1_unfused_workspace_size", "ozk_s1_split_rows", "ozk_s1_split_cols", "ozk_s1_gemm",
+    "ozk_dgemm", "ozk_dgemm_noalloc", "ozk_dgemm_t", "ozk_sgemm", "ozk_zgemm_3m", "ozk_cgemm_3m", "ozk_s1_dgemm_unfused", "ozk_s1_unfused_workspace_size", "ozk_s1_split_rows", "ozk_s1_split_cols", "ozk_s1_gemm",
     "ozk_s1_diagonals", "ozk_s2_split_rows", "ozk_s2_split_cols", "ozk_s2_gemm_mod", "ozk_s2_crt",
     "ozk_selector_load", "ozk_select", "ozk_dgemm_auto", "ozk_mlp_forward", "ozk_mlp_grad", "ozk_mlp_adam",
     "ozk_ref_dd", "ozk_batch_plan_create", "ozk_gemm_batched", "ozk_batch_plan_destroy",
@@ -91,6 +92,7 @@ def _lib() -> ctypes.CDLL:
         "ozk_s1_k_split": (I64, [I]),
         "ozk_workspace_size": (I, [P, I, I, I64, I64, I64, I, ctypes.POINTER(SZ)]),
         "ozk_dgemm": (I, [P, I, I, I64, I64, I64, D, P, I64, P, I64, D, P, I64, P, SZ, P]),
+        "ozk_dgemm_noalloc": (I, [P, I, I, I64, I64, I64, D, P, I64, P, I64, D, P, I64, P]),
         "ozk_dgemm_t": (I, [P, I, I, I, I, I64, I64, I64, D, P, I64, P, I64, D, P, I64, P, SZ, P]),
         "ozk_sgemm": (I, [P, I, I, I64, I64, I64, ctypes.c_float, P, I64, P, I64, ctypes.c_float, P, I64, P, SZ, P]),
         "ozk_cgemm_3m": (I, [P, I, I64, I64, I64, P, P, I64, P, I64, P, P, I64, P, SZ, P]),
@@ -290,6 +292,21 @@ def ozk_dgemm(ctx: Context, scheme: int, p_or_s: int, A, B, C=None, alpha: float
     st = _lib().ozk_dgemm(ctx.handle, scheme, p_or_s, M, N, K, float(alpha), _ptr(A), _ld(A), _ptr(B), _ld(B),
                           float(beta), _ptr(C), _ld(C), _ptr(ws), ws.numel(), _stream(stream))
     _check("ozk_dgemm", st, ctx)
+    return C
+
+
+def ozk_dgemm_noalloc(ctx: Context, scheme: int, p_or_s: int, A, B, C=None, alpha: float = 1.0,
+                      beta: float = 0.0, stream=None):
+    """ozk_dgemm on the library's fixed device buffer instead of a workspace
+    (nothing is allocated by the library; C is allocated here only when it
+    is not given); returns C."""
+    import torch
+    M, N, K = _mats(ctx, torch.float64, A, B, C)
+    if C is None:
+        C = torch.empty((M, N), dtype=torch.float64, device=A.device)
+    st = _lib().ozk_dgemm_noalloc(ctx.handle, scheme, p_or_s, M, N, K, float(alpha), _ptr(A), _ld(A), _ptr(B),
+                                  _ld(B), float(beta), _ptr(C), _ld(C), _stream(stream))
+    _check("ozk_dgemm_noalloc", st, ctx)
     return C
 
 

@@ -7,6 +7,7 @@
 
 #include <algorithm>
 #include <map>
+#include <mutex>
 #include <new>
 #include <numeric>
 #include <string>
@@ -30,9 +31,17 @@ struct ozk_cfg_entry {
   float ms;  // tuned time of the GEMM kernel(s), 0 if set by hand
 };
 
+// The workspace of ozk_dgemm_noalloc: a fixed buffer in device memory, one
+// copy per device, held by every device the library runs on until the
+// process ends.  In host code `scratch` only names the symbol; its device
+// address comes from hipGetSymbolAddress (scratch_of) and is the only form
+// that reaches a kernel or a copy.
+static __device__ __align__(256) unsigned char scratch[OZK_NOALLOC_SCRATCH_BYTES];
+
 struct ozk_ctx {
   int device = 0;
   int last_arg = 0;
+  void* scratch = nullptr;       // device address of `scratch` on this device
   int64_t k_split_override = 0;  // > 0: shorter K runs (testing the fold path)
   float* sel_w = nullptr;        // selector parameters on the device (or null)
   float sel_threshold = 0.5f;
@@ -47,6 +56,23 @@ namespace {
 ozk_status fail(ozk_ctx* c, ozk_status s, int arg) {
   if (c) c->last_arg = arg;
   return s;
+}
+
+// Device address of `scratch` on the current device `device`, looked up once
+// per device (each device holds its own copy at its own address).
+hipError_t scratch_of(int device, void** out) {
+  static std::mutex mu;
+  static std::map<int, void*> addr;
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = addr.find(device);
+  if (it == addr.end()) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return e != hipSuccess ? e : hipErrorInvalidSymbol;
+    it = addr.emplace(device, p).first;
+  }
+  *out = it->second;
+  return hipSuccess;
 }
 
 ozk_status hip_status(ozk_ctx* c, hipError_t e) {
@@ -222,6 +248,10 @@ ozk_status ozk_create(ozk_ctx** ctx, int device) {
   if (!c) return OZK_ERR_HIP;
   c->device = device;
   if (ozk::s2_upload_crt_tables() != hipSuccess) {  // CRT constants of every s for the auto path
+    delete c;
+    return OZK_ERR_HIP;
+  }
+  if (scratch_of(device, &c->scratch) != hipSuccess) {  // the buffer of ozk_dgemm_noalloc
     delete c;
     return OZK_ERR_HIP;
   }
@@ -456,6 +486,32 @@ ozk_status ozk_dgemm(ozk_ctx* ctx, ozk_scheme scheme, int p_or_s, int64_t M, int
   if (ldc < (N > 0 ? N : 1)) return fail(ctx, OZK_ERR_INVALID_ARG, 14);
   return dgemm_run(ctx, scheme, p_or_s, false, false, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, ws, ws_bytes,
                    stream, 15);
+}
+
+ozk_status ozk_dgemm_noalloc(ozk_ctx* ctx, ozk_scheme scheme, int p_or_s, int64_t M, int64_t N, int64_t K,
+                             double alpha, const double* A, int64_t lda, const double* B, int64_t ldb,
+                             double beta, double* C, int64_t ldc, hipStream_t stream) {
+  if (!ctx) return OZK_ERR_INVALID_ARG;
+  ctx->last_arg = 0;
+  if (scheme != OZK_SCHEME1 && scheme != OZK_SCHEME2) return fail(ctx, OZK_ERR_INVALID_ARG, 2);
+  if (bad_dims(M, N, K)) return fail(ctx, OZK_ERR_INVALID_ARG, M < 0 ? 4 : (N < 0 ? 5 : 6));
+  if (!A && M > 0 && K > 0) return fail(ctx, OZK_ERR_INVALID_ARG, 8);
+  if (lda < (K > 0 ? K : 1)) return fail(ctx, OZK_ERR_INVALID_ARG, 9);
+  if (!B && K > 0 && N > 0) return fail(ctx, OZK_ERR_INVALID_ARG, 10);
+  if (ldb < (N > 0 ? N : 1)) return fail(ctx, OZK_ERR_INVALID_ARG, 11);
+  if (!C && M > 0 && N > 0) return fail(ctx, OZK_ERR_INVALID_ARG, 13);
+  if (ldc < (N > 0 ? N : 1)) return fail(ctx, OZK_ERR_INVALID_ARG, 14);
+  if (scheme == OZK_SCHEME2 && (p_or_s < 1 || p_or_s > OZK_MAX_S)) return fail(ctx, OZK_ERR_UNSUPPORTED, 3);
+  if (scheme == OZK_SCHEME1 && (p_or_s < 1 || p_or_s > OZK_MAX_P)) return fail(ctx, OZK_ERR_UNSUPPORTED, 3);
+  if (scheme == OZK_SCHEME2 && s2_long_k(K)) return fail(ctx, OZK_ERR_UNSUPPORTED, 6);
+  if (!ctx->scratch) return fail(ctx, OZK_ERR_HIP, 0);
+  // the workspace ozk_dgemm would take must fit the fixed buffer
+  size_t need = 0;
+  const ozk_status st = ozk_workspace_size(ctx, OZK_OP_DGEMM, scheme, M, N, K, p_or_s, &need);
+  if (st != OZK_OK) return fail(ctx, st, 4);
+  if (need > (size_t)OZK_NOALLOC_SCRATCH_BYTES) return fail(ctx, OZK_ERR_WORKSPACE, 4);
+  return dgemm_run(ctx, scheme, p_or_s, false, false, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, ctx->scratch,
+                   OZK_NOALLOC_SCRATCH_BYTES, stream, 15);
 }
 
 ozk_status ozk_dgemm_t(ozk_ctx* ctx, ozk_scheme scheme, int p_or_s, int trans_a, int trans_b, int64_t M, int64_t N,
