@@ -91,9 +91,16 @@ extern "C" {
 #define OZK_S2_VARIANTS 5           /* Scheme II GEMM variants (the last: fused CRT) */
 #define OZK_S2_FUSED_CRT 4          /* Scheme II variant with the CRT fused into the GEMM (real only) */
 #define OZK_NOALLOC_SCRATCH_BYTES 67108864  /* 64 MiB: the fixed buffer of ozk_dgemm_noalloc */
-#define OZK_SELECTOR_PARAMS 6920   /* float32 parameters of the selector MLP */
+#define OZK_SELECTOR_PARAMS 8220   /* float32 parameters of the selector MLP */
+#define OZK_SELECTOR_HEADS 28      /* ordinal heads: 8 for p, 20 for s */
 #define OZK_SELECTOR_COUNTERS 34   /* int32 feature counters */
 #define OZK_SELECTOR_INFO 8        /* int32 decision entries */
+
+/* Condition bits of a context's flag word (ozk_get_flags). */
+#define OZK_FLAG_NONFINITE 1u          /* an input row of A or column of B held a NaN or an infinity */
+#define OZK_FLAG_SELECTOR_FALLBACK 2u  /* an automatic call decided by the a-priori bound alone */
+#define OZK_FLAG_SCHEME2_CHOSEN 4u     /* an automatic call found no slice count <= 8 enough: Scheme II ran */
+#define OZK_FLAG_S_UNPROVEN 8u         /* ... with s = 20, no modulus count <= 20 proven enough */
 
 typedef struct ozk_ctx ozk_ctx;
 
@@ -132,6 +139,35 @@ const char* ozk_version(void);
  * setting it. */
 ozk_status ozk_set_k_split(ozk_ctx* ctx, int64_t k);
 
+/* Conditions found on the device, which no synchronous status can report
+ * because the library never reads device data on the host (the paper
+ * defines none of them: they are this library's): every whole call (DGEMM,
+ * SGEMM, ZGEMM, CGEMM, the unfused, transposed, allocation-free, automatic
+ * and batched calls) ORs bits into a device flag word of its context, on
+ * its stream, after its pre-pass:
+ *   OZK_FLAG_NONFINITE         a row of A or a column of B held a NaN or an
+ *                              infinity (its row / column of the result is
+ *                              NaN; the other outputs are unaffected);
+ *   OZK_FLAG_SELECTOR_FALLBACK an automatic call (ozk_dgemm_auto,
+ *                              ozk_zgemm_auto) decided by the a-priori bound
+ *                              alone: no network loaded, or its features
+ *                              outside the network's training range;
+ *   OZK_FLAG_SCHEME2_CHOSEN    an automatic DGEMM found no slice count up to
+ *                              8 that meets the tolerance and ran Scheme II
+ *                              (Scheme I "infeasible");
+ *   OZK_FLAG_S_UNPROVEN        an automatic call ran Scheme II with s = 20
+ *                              although no modulus count up to 20 is proven
+ *                              to meet the tolerance.
+ * ozk_get_flags waits for the work enqueued on `stream` (hipStreamSynchronize),
+ * then atomically takes the word, clearing it, and stores it in *flags (a
+ * HOST pointer): the OR of the conditions raised since the context was
+ * created or its flags were last taken, by every call whose work has
+ * completed.  Work on other streams still running may raise bits after the
+ * take; they are kept for the next one.  Synchronises, so it must not be
+ * captured into a graph.  Errors: OZK_ERR_INVALID_ARG (arg 3) for a null
+ * flags pointer, OZK_ERR_HIP. */
+ozk_status ozk_get_flags(ozk_ctx* ctx, hipStream_t stream, uint32_t* flags);
+
 /* ---------------------------------------------------------- sizes / layout */
 
 /* Bytes of a Scheme I packed operand with `rows` rows, contraction length K
@@ -150,7 +186,9 @@ int64_t ozk_s1_k_split(int p);
  * exceeds ozk_s1_k_split(p), 16 bytes per output per K run; for Scheme II
  * the scales, the residue planes and s (or 2s for complex) int8 output
  * residue planes.  Scheme I with p_or_s = 0: the size ozk_dgemm_auto needs
- * (room for p = 8 plus the selector counters). */
+ * (room for p = 8 plus the selector counters).  OZK_OP_ZGEMM with Scheme I:
+ * the 4M workspace of ozk_zgemm / ozk_cgemm; with Scheme II and p_or_s = 0:
+ * the workspace of ozk_zgemm_auto. */
 ozk_status ozk_workspace_size(ozk_ctx* ctx, ozk_op op, ozk_scheme scheme,
                               int64_t M, int64_t N, int64_t K, int p_or_s,
                               size_t* bytes);
@@ -276,6 +314,70 @@ ozk_status ozk_zgemm_3m(ozk_ctx* ctx, int s, int64_t M, int64_t N, int64_t K,
                         double* C, int64_t ldc, void* ws, size_t ws_bytes,
                         hipStream_t stream);
 
+/* Complex GEMM, C = alpha*A*B + beta*C, by either scheme (ZGEMM: complex128,
+ * CGEMM: complex64 in and out; interleaved (re, im); leading dimensions in
+ * complex elements; alpha and beta are HOST arrays {re, im}).
+ *   OZK_SCHEME2: Scheme II with 3M (exactly ozk_zgemm_3m / ozk_cgemm_3m;
+ *     p_or_s = s moduli, 1..20).
+ *   OZK_SCHEME1: Scheme I with the 4M formulation (Sec. IV-B names 4M as the
+ *     standard four-product form; Sec. V-D reports Scheme I complex GEMMs):
+ *     the four real products Re A Re B, Im A Im B, Re A Im B, Im A Re B and
+ *     the subtraction and addition that combine them are one Scheme I
+ *     product of real embeddings, A' = (M x 2K: row i holds Re a_ik, Im a_ik
+ *     for k = 0..K-1, i.e. A as stored viewed as reals) and B'' (2K x 2N: row
+ *     2k holds (Re b_kj, Im b_kj) at columns (2j, 2j+1), row 2k+1 holds
+ *     (-Im b_kj, Re b_kj)), whose product's columns 2j and 2j+1 are Re and
+ *     Im of (AB)_ij.  So each part is formed exactly in integers and rounded
+ *     once; a row of A has one exponent for both parts, and so has a column
+ *     of B.  p_or_s = p slices, 1..8; the INT8 work is 4 p(p+1) MNK.  The
+ *     GEMM step takes the DGEMM configuration of the embedded size class
+ *     (M, 2N, 2K); it writes the M x 2N real parts to the workspace and a
+ *     final pass applies the complex update with the fixed FMA sequence of
+ *     ozk_zgemm_3m (in binary32 for CGEMM, whose operands are widened
+ *     exactly and whose parts are rounded once to binary32).  N <= 2^23.
+ * Workspace: ozk_workspace_size(ctx, OZK_OP_ZGEMM, scheme, M, N, K, p_or_s)
+ * bytes (Scheme I: the Scheme I workspace of the embedded product plus
+ * 16 MN bytes).  Device pointers, caller-owned memory, asynchronous on
+ * `stream`.  Errors: OZK_ERR_INVALID_ARG with the argument index (2 scheme,
+ * 4-6 sizes, 7 alpha, 8-11 A, B, 12 beta, 13-14 C), OZK_ERR_UNSUPPORTED
+ * (arg 3) for a count out of range, OZK_ERR_WORKSPACE (arg 15). */
+ozk_status ozk_zgemm(ozk_ctx* ctx, ozk_scheme scheme, int p_or_s, int64_t M,
+                     int64_t N, int64_t K, const double* alpha,
+                     const double* A, int64_t lda, const double* B,
+                     int64_t ldb, const double* beta, double* C, int64_t ldc,
+                     void* ws, size_t ws_bytes, hipStream_t stream);
+ozk_status ozk_cgemm(ozk_ctx* ctx, ozk_scheme scheme, int p_or_s, int64_t M,
+                     int64_t N, int64_t K, const float* alpha, const float* A,
+                     int64_t lda, const float* B, int64_t ldb,
+                     const float* beta, float* C, int64_t ldc, void* ws,
+                     size_t ws_bytes, hipStream_t stream);
+
+/* The unfused Scheme II baseline, as an ablation of the fused kernels (the
+ * naive forms of the paper's traffic models: Sec. IV-A, Eq. 14 for real
+ * products and Sec. IV-B, Eq. 17 for 3M): the same pre-pass and CRT as
+ * ozk_dgemm(OZK_SCHEME2, s) (complex_planes = 0) or ozk_zgemm_3m
+ * (complex_planes = 1), but every modular product -- one per modulus, or
+ * T1, T2, T3 per modulus for 3M -- is an INT8 GEMM writing its INT32
+ * result to HBM, and a pass reads the planes back and reduces them mod m
+ * (3M: forms smod(T1 - T2) and smod(T3 - T1 - T2)) into the residue planes
+ * the CRT reads.  Bit-identical to the fused call; only the INT32 round trip
+ * (4 MN bytes per product, written and read) differs.  X, C real (FP64) or
+ * complex (interleaved complex128) by complex_planes; alpha, beta HOST
+ * arrays {re, im} (the imaginary part ignored for real data).
+ * 1 <= s <= 20, K <= 131071 (|sum| <= K 2^14 keeps each INT32 plane exact;
+ * longer K returns OZK_ERR_UNSUPPORTED, arg 6).  Workspace:
+ * ozk_s2_unfused_workspace_size bytes (the fused call's workspace plus
+ * 4 s MN bytes of planes, 12 s MN for 3M).  Errors as ozk_zgemm. */
+ozk_status ozk_s2_unfused_workspace_size(ozk_ctx* ctx, int s, int complex_planes,
+                                         int64_t M, int64_t N, int64_t K,
+                                         size_t* bytes);
+ozk_status ozk_s2_gemm_unfused(ozk_ctx* ctx, int s, int complex_planes,
+                               int64_t M, int64_t N, int64_t K,
+                               const double* alpha, const double* A,
+                               int64_t lda, const double* B, int64_t ldb,
+                               const double* beta, double* C, int64_t ldc,
+                               void* ws, size_t ws_bytes, hipStream_t stream);
+
 /* ------------------------------------------------ Scheme I, step by step */
 
 /* Pre-pass for a row operand (A): e[i] = row exponent (smallest e with
@@ -346,37 +448,45 @@ ozk_status ozk_s2_crt(ozk_ctx* ctx, int s, int complex_planes, int64_t M,
                       const double* beta, double* C, int64_t ldc,
                       hipStream_t stream);
 
-/* ------------------------------------------ learned slice-count selector */
+/* ---------------------------------- learned slice / modulus count selector */
 /* The paper's implementation has no automatic precision selection (it is
  * named as missing, Sec. VI); this library predicts the smallest Scheme I
- * slice count p meeting a componentwise tolerance with a small MLP
- * (34 -> 64 -> 64 -> 8, ReLU, 8 ordinal heads "p > t") from exponent
- * statistics gathered on the device, bounded by an a-priori error bound.
+ * slice count p and the smallest Scheme II modulus count s meeting a
+ * componentwise tolerance with a small MLP (34 -> 64 -> 64 -> 28, ReLU; 8
+ * ordinal heads "p > t", t = 1..8, then 20 heads "s > t", t = 1..20) from
+ * exponent statistics gathered on the device, each bounded by an a-priori
+ * error bound.
  *
  * Parameter layout (float32, OZK_SELECTOR_PARAMS values, weights [in][out]):
- * W1[34][64], b1[64], W2[64][64], b2[64], W3[64][8], b3[8].
+ * W1[34][64], b1[64], W2[64][64], b2[64], W3[64][28], b3[28].
  * Features: for A's rows and B's columns, the fractions of nonzero entries
  * whose exponent deficit e_i - expo(a_ik) falls in the bins [0] [1] [2] [3]
  * [4,6) [6,8) [8,12) [12,16) [16,24) [24,32) [32,48) [48,64) [64,96)
  * [96,128) [128,256) [256,inf); then log2(K)/14 and -log10(tol)/16.
  * Counters (int32, OZK_SELECTOR_COUNTERS): 16 + 16 bin counts, the largest
- * deficit of A, of B.  Decision: p_net = 1 + #{t : sigmoid(z_t) > threshold}
- * + margin; p_bound = smallest p whose a-priori bound is <= tol (9 if none);
- * p = min(p_net, p_bound), or p_bound when no network is loaded or the
- * features are outside the training range (K > 16384, tol outside
- * [1e-16, 1e-5], any entry in the last deficit bin).  p <= 8: Scheme I with
- * p slices.  p = 9 (no slice count up to 8 is enough): Scheme II with s =
- * s_bound, the smallest modulus count whose a-priori bound (norm-bound
- * scales, Sec. II-C.2) is <= tol, or 20 when none is proven enough.
+ * deficit of A, of B.  Decision, with thr_h the per-head thresholds:
+ * p_net = 1 + #{t <= 8 : sigmoid(z_t) > thr_t} + margin (at most 9),
+ * s_net = 1 + #{t <= 20 : sigmoid(z_{8+t}) > thr_{8+t}} + margin (at most
+ * 21); p_bound (s_bound) = the smallest p (s) whose a-priori bound is <= tol
+ * (9, resp. 21, if none); p = min(p_net, p_bound) and s = min(s_net,
+ * s_bound), or the bounds alone when no network is loaded or the features
+ * are outside the training range (K > 16384, tol outside [1e-16, 1e-5], any
+ * entry in the last deficit bin).  p <= 8: Scheme I with p slices.  p = 9
+ * (no slice count up to 8 is enough): Scheme II with s moduli (the Scheme II
+ * bound uses the norm-bound scales, Sec. II-C.2), or s = 20 when s = 21.
  * info (device int32[OZK_SELECTOR_INFO]): [0] Scheme I slices (0 when
  * Scheme II is chosen), [1] p_net (0 without network), [2] p_bound,
  * [3] 1 if out of range, [4] scheme (1 or 2), [5] Scheme II moduli (0 with
- * Scheme I), [6] s_bound (21 if none up to 20), [7] 0. */
+ * Scheme I), [6] s_bound (21 if none up to 20), [7] s_net (0 without
+ * network). */
 
-/* Load selector parameters (HOST float array of OZK_SELECTOR_PARAMS) into
- * the context (copied to device memory owned by the context). */
+/* Load selector parameters (HOST float array of OZK_SELECTOR_PARAMS) and the
+ * OZK_SELECTOR_HEADS decision thresholds (HOST floats, each in (0, 1)) into
+ * the context (the parameters are copied to device memory owned by the
+ * context).  margin: 0..8 counts added to p_net and s_net.  Errors:
+ * OZK_ERR_INVALID_ARG (arg 2 parameters, 4 thresholds, 5 margin). */
 ozk_status ozk_selector_load(ozk_ctx* ctx, const float* params, size_t n,
-                             float threshold, int margin);
+                             const float* thresholds, int margin);
 /* Exponent statistics and the selector decision for C = A B, all on the
  * device: e[M], f[N] (the Scheme I row/column exponents), counters,
  * info[OZK_SELECTOR_INFO] and, if features is not NULL, the 34 features
@@ -398,8 +508,30 @@ ozk_status ozk_dgemm_auto(ozk_ctx* ctx, double tol, int64_t M, int64_t N,
                           double beta, double* C, int64_t ldc, void* ws,
                           size_t ws_bytes, int32_t* info, hipStream_t stream);
 
+/* ZGEMM (complex128, interleaved; alpha, beta HOST {re, im}) with the
+ * modulus count chosen on the device for the componentwise tolerance `tol`
+ * (the complex E_cw: the real and imaginary parts scaled by the magnitude
+ * sums of the products forming them): Scheme II with 3M (Sec. IV-B) at the
+ * smallest s whose a-priori bound meets tol -- the Scheme II bound above
+ * with the largest deficits of the real and imaginary parts below the
+ * largest part exponent of their row of A (column of B), plus one (the
+ * shared per-row scale is taken from |re| + |im|) -- or s = 20 when none is
+ * proven (OZK_FLAG_S_UNPROVEN).  The network is trained on real products
+ * and is not used, so the call raises OZK_FLAG_SELECTOR_FALLBACK.  Every
+ * kernel reads s from the device; no host round trip, graph-capturable.
+ * ws: ozk_workspace_size(ctx, OZK_OP_ZGEMM, OZK_SCHEME2, M, N, K, 0) bytes;
+ * info (device int32[OZK_SELECTOR_INFO], may be NULL): [4] = 2, [5] s,
+ * [6] the bound's s (21 if none), the other entries 0 (and [2] 9).
+ * Errors as ozk_zgemm_3m (arg 2 a tolerance outside (0, 1), workspace 14). */
+ozk_status ozk_zgemm_auto(ozk_ctx* ctx, double tol, int64_t M, int64_t N,
+                          int64_t K, const double* alpha, const double* A,
+                          int64_t lda, const double* B, int64_t ldb,
+                          const double* beta, double* C, int64_t ldc,
+                          void* ws, size_t ws_bytes, int32_t* info,
+                          hipStream_t stream);
+
 /* Training kernels of the selector network (device float32 arrays; X is
- * n x 34, Y n x 8 ordinal targets, logits n x 8).  ozk_mlp_grad writes the
+ * n x 34, Y n x 28 ordinal targets, logits n x 28).  ozk_mlp_grad writes the
  * gradient of the mean binary cross-entropy into grad (OZK_SELECTOR_PARAMS)
  * and the loss into *loss; ozk_mlp_adam applies one bias-corrected Adam
  * step (beta1 0.9, beta2 0.999, eps 1e-8; step counts from 1). */

@@ -11,8 +11,11 @@ be checked:
   relative to the row (column) exponent, log2(K) / 14 and -log10(tol) / 16;
 * p_bound(A, B, tol): the smallest p whose a-priori componentwise error
   bound for the balanced 8-bit slices is below tol (9 = none up to 8);
-* a plain fp64 MLP 34 -> 64 -> 64 -> 8 (ReLU), ordinal heads z_t ~ P(p > t),
-  its binary cross-entropy loss, analytic backward pass and one Adam step.
+* a plain fp64 MLP 34 -> 64 -> 64 -> 28 (ReLU) with ordinal heads: z_t ~
+  P(p > t) for the Scheme I slice count (t = 1..8, heads 0..7) and z_t ~
+  P(s > t) for the Scheme II modulus count (t = 1..20, heads 8..27), its
+  binary cross-entropy loss, analytic backward pass and one Adam step, and
+  the decision rule (per-head thresholds plus a margin).
 """
 from __future__ import annotations
 
@@ -25,7 +28,9 @@ BIN_EDGES = (0, 1, 2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128, 256)
 N_BINS = len(BIN_EDGES)
 N_FEAT = 2 * N_BINS + 2
 HIDDEN = 64
-N_OUT = 8
+P_HEADS = 8    # Scheme I: p > t, t = 1..8
+S_HEADS = 20   # Scheme II: s > t, t = 1..20
+N_OUT = P_HEADS + S_HEADS
 
 
 def deficit_bin(d: int) -> int:
@@ -127,11 +132,39 @@ def s_bound(A, B, tol: float) -> int:
     return 21
 
 
+def complex_max_deficits(A, B):
+    """The largest exponent deficit of a nonzero real or imaginary part below
+    the largest part exponent of its row of A (column of B): the real
+    deficits of [Re A, Im A] by rows and of [Re B; Im B] by columns."""
+    A = np.asarray(A, np.complex128)
+    B = np.asarray(B, np.complex128)
+    ra = max_deficit(np.concatenate([A.real, A.imag], axis=1), 1)
+    rb = max_deficit(np.concatenate([B.real, B.imag], axis=0), 0)
+    return ra, rb
+
+
+def s_bound_complex(A, B, tol: float) -> int:
+    """Smallest s in [1, 20] whose Scheme II bound for the 3M product is <=
+    tol (21 = none): the real bound with each part deficit one more, since the
+    shared per-row (per-column) scale is taken from |re| + |im| < 2^(max(expo
+    re, expo im) + 1) -- an entry part r steps below the row's largest part
+    exponent lies r + 1 steps below the complex entry exponent the scale
+    uses.  Each part of the result is a sum of real products whose
+    magnitudes are the scale of that part in the complex E_cw, so the
+    per-term relative errors carry over."""
+    ra, rb = complex_max_deficits(A, B)
+    K = np.asarray(A).shape[1]
+    for s in range(1, 21):
+        if bound_s2(s, ra + 1, rb + 1, K) <= tol:
+            return s
+    return 21
+
+
 # -------------------------------------------------------------------- MLP
 
 def mlp_forward(params, X):
     """params = (W1, b1, W2, b2, W3, b3) with W as [in][out]; X [n][34].
-    Returns logits [n][8] and the cache for backward."""
+    Returns logits [n][28] and the cache for backward."""
     W1, b1, W2, b2, W3, b3 = params
     z1 = X @ W1 + b1
     h1 = np.maximum(z1, 0.0)
@@ -141,11 +174,15 @@ def mlp_forward(params, X):
     return out, (X, z1, h1, z2, h2)
 
 
-def ordinal_targets(p: np.ndarray) -> np.ndarray:
-    """y[n][t-1] = 1 if p > t (t = 1..8)."""
+def ordinal_targets(p: np.ndarray, s: np.ndarray = None) -> np.ndarray:
+    """y[n][t-1] = 1 if p > t (t = 1..8) and y[n][7+t] = 1 if s > t
+    (t = 1..20); p = 9 means no slice count up to 8 meets the tolerance, s =
+    21 no modulus count up to 20 (s defaults to 21)."""
     p = np.asarray(p).reshape(-1, 1)
-    t = np.arange(1, N_OUT + 1).reshape(1, -1)
-    return (p > t).astype(np.float64)
+    s = np.full(p.shape, 21) if s is None else np.asarray(s).reshape(-1, 1)
+    tp = np.arange(1, P_HEADS + 1).reshape(1, -1)
+    ts = np.arange(1, S_HEADS + 1).reshape(1, -1)
+    return np.concatenate([(p > tp), (s > ts)], axis=1).astype(np.float64)
 
 
 def bce_loss(logits, y) -> float:
@@ -188,7 +225,32 @@ def adam_step(params, grads, m, v, t: int, lr=1e-3, beta1=0.9, beta2=0.999, eps=
     return tuple(out_p), tuple(out_m), tuple(out_v)
 
 
+def predict(logits, thresholds=0.5, margin: int = 0):
+    """The network's counts: p_net = 1 + #{t : sigmoid(z_t) > thr_t over the
+    Scheme I heads} + margin, capped at 9, and s_net the same over the
+    Scheme II heads, capped at 21.  thresholds: one value or one per head."""
+    sig = 1.0 / (1.0 + np.exp(-np.asarray(logits, np.float64)))
+    thr = np.broadcast_to(np.asarray(thresholds, np.float64), (N_OUT,))
+    up = sig > thr.reshape(1, -1)
+    p = np.minimum(1 + up[:, :P_HEADS].sum(axis=1) + margin, 9)
+    s = np.minimum(1 + up[:, P_HEADS:].sum(axis=1) + margin, 21)
+    return p, s
+
+
 def predict_p(logits, threshold: float = 0.5, margin: int = 0) -> np.ndarray:
-    """p = 1 + #{t : sigmoid(z_t) > threshold} + margin, capped at 9."""
-    sig = 1.0 / (1.0 + np.exp(-np.asarray(logits)))
-    return np.minimum(1 + (sig > threshold).sum(axis=1) + margin, 9)
+    """The Scheme I count alone (see predict)."""
+    return predict(logits, threshold, margin)[0]
+
+
+def decide(p_net: int, s_net: int, p_b: int, s_b: int, in_range: bool, have_net: bool = True):
+    """The library's decision from the network counts and the a-priori
+    bounds: p = min(p_net, p_bound) (the bound alone without a network or
+    outside the training range); Scheme I with p while p <= 8, else Scheme II
+    with s = min(s_net, s_bound) (the bound alone likewise), s = 20 when no
+    count up to 20 is proven.  Returns (scheme, count)."""
+    use_net = have_net and in_range
+    p = min(p_net, p_b) if use_net else p_b
+    if p <= 8:
+        return 1, p
+    s = min(s_net, s_b) if use_net else s_b
+    return 2, min(s, 20)

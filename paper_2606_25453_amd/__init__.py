@@ -29,7 +29,8 @@ OZK_ROW_ALIGN = 256
 OZK_K_CHUNK = 32
 OZK_EXP_ZERO = -100000
 OZK_EXP_NONFINITE = 100000
-OZK_SELECTOR_PARAMS = 6920
+OZK_SELECTOR_PARAMS = 8220
+OZK_SELECTOR_HEADS = 28
 OZK_SELECTOR_COUNTERS = 34
 OZK_SELECTOR_INFO = 8
 OZK_MAX_ROWS = 1 << 24
@@ -38,6 +39,10 @@ OZK_S1_VARIANTS = 4
 OZK_S2_VARIANTS = 5
 OZK_S2_FUSED_CRT = 4
 OZK_NOALLOC_SCRATCH_BYTES = 64 << 20
+OZK_FLAG_NONFINITE = 1
+OZK_FLAG_SELECTOR_FALLBACK = 2
+OZK_FLAG_SCHEME2_CHOSEN = 4
+OZK_FLAG_S_UNPROVEN = 8
 
 
 class OzkGemmConfig(ctypes.Structure):
@@ -52,6 +57,7 @@ class OzkGemmConfig(ctypes.Structure):
 EXPORTS = (
     "ozk_create", "ozk_destroy", "ozk_last_arg", "ozk_status_string", "ozk_version", "ozk_set_k_split",
     "ozk_s1_packed_bytes", "ozk_s2_packed_bytes", "ozk_s1_k_split", "ozk_workspace_size",
+    "ozk_get_flags", "ozk_zgemm", "ozk_cgemm", "ozk_zgemm_auto", "ozk_s2_unfused_workspace_size", "ozk_s2_gemm_unfused",
     "ozk_dgemm", "ozk_dgemm_noalloc", "ozk_dgemm_t", "ozk_sgemm", "ozk_zgemm_3m", "ozk_cgemm_3m", "ozk_s1_dgemm_unfused", "ozk_s1_unfused_workspace_size", "ozk_s1_split_rows", "ozk_s1_split_cols", "ozk_s1_gemm",
     "ozk_s1_diagonals", "ozk_s2_split_rows", "ozk_s2_split_cols", "ozk_s2_gemm_mod", "ozk_s2_crt",
     "ozk_selector_load", "ozk_select", "ozk_dgemm_auto", "ozk_mlp_forward", "ozk_mlp_grad", "ozk_mlp_adam",
@@ -92,6 +98,12 @@ def _lib() -> ctypes.CDLL:
         "ozk_s1_k_split": (I64, [I]),
         "ozk_workspace_size": (I, [P, I, I, I64, I64, I64, I, ctypes.POINTER(SZ)]),
         "ozk_dgemm": (I, [P, I, I, I64, I64, I64, D, P, I64, P, I64, D, P, I64, P, SZ, P]),
+        "ozk_get_flags": (I, [P, P, ctypes.POINTER(ctypes.c_uint32)]),
+        "ozk_zgemm_auto": (I, [P, D, I64, I64, I64, P, P, I64, P, I64, P, P, I64, P, SZ, P, P]),
+        "ozk_zgemm": (I, [P, I, I, I64, I64, I64, P, P, I64, P, I64, P, P, I64, P, SZ, P]),
+        "ozk_cgemm": (I, [P, I, I, I64, I64, I64, P, P, I64, P, I64, P, P, I64, P, SZ, P]),
+        "ozk_s2_unfused_workspace_size": (I, [P, I, I, I64, I64, I64, ctypes.POINTER(SZ)]),
+        "ozk_s2_gemm_unfused": (I, [P, I, I, I64, I64, I64, P, P, I64, P, I64, P, P, I64, P, SZ, P]),
         "ozk_dgemm_noalloc": (I, [P, I, I, I64, I64, I64, D, P, I64, P, I64, D, P, I64, P]),
         "ozk_dgemm_t": (I, [P, I, I, I, I, I64, I64, I64, D, P, I64, P, I64, D, P, I64, P, SZ, P]),
         "ozk_sgemm": (I, [P, I, I, I64, I64, I64, ctypes.c_float, P, I64, P, I64, ctypes.c_float, P, I64, P, SZ, P]),
@@ -107,7 +119,7 @@ def _lib() -> ctypes.CDLL:
         "ozk_s2_split_cols": (I, [P, I, I, I64, I64, P, I64, P, P, P]),
         "ozk_s2_gemm_mod": (I, [P, I, I, I64, I64, I64, P, P, P, P]),
         "ozk_s2_crt": (I, [P, I, I, I64, I64, P, P, P, P, P, P, I64, P]),
-        "ozk_selector_load": (I, [P, P, SZ, ctypes.c_float, I]),
+        "ozk_selector_load": (I, [P, P, SZ, P, I]),
         "ozk_select": (I, [P, D, I64, I64, I64, P, I64, P, I64, P, P, P, P, P, P]),
         "ozk_dgemm_auto": (I, [P, D, I64, I64, I64, D, P, I64, P, I64, D, P, I64, P, SZ, P, P]),
         "ozk_mlp_forward": (I, [P, P, P, I, P, P]),
@@ -405,6 +417,100 @@ def ozk_zgemm_3m(ctx: Context, s: int, A, B, C=None, alpha: complex = 1.0, beta:
                              _stream(stream))
     _check("ozk_zgemm_3m", st, ctx)
     return C
+
+
+def ozk_get_flags(ctx: Context, stream=None) -> int:
+    """Wait for `stream`, then take (and clear) the context's condition flags."""
+    out = ctypes.c_uint32()
+    _check("ozk_get_flags", _lib().ozk_get_flags(ctx.handle, _stream(stream), ctypes.byref(out)), ctx)
+    return int(out.value)
+
+
+def _complex_call(name: str, dtype, real, ctx: Context, scheme: int, count: int, A, B, C, alpha, beta, ws, stream):
+    import torch
+    M, N, K = _mats(ctx, dtype, A, B, C)
+    _ws(ws, ctx)
+    if C is None:
+        C = torch.empty((M, N), dtype=dtype, device=A.device)
+    if ws is None:
+        ws = _workspace(ozk_workspace_size(ctx, OZK_OP_ZGEMM, scheme, M, N, K, count), A.device)
+    al = (real * 2)(complex(alpha).real, complex(alpha).imag)
+    be = (real * 2)(complex(beta).real, complex(beta).imag)
+    st = getattr(_lib(), name)(ctx.handle, scheme, count, M, N, K, ctypes.cast(al, ctypes.c_void_p), _ptr(A), _ld(A),
+                               _ptr(B), _ld(B), ctypes.cast(be, ctypes.c_void_p), _ptr(C), _ld(C), _ptr(ws),
+                               ws.numel(), _stream(stream))
+    _check(name, st, ctx)
+    return C
+
+
+def ozk_zgemm(ctx: Context, scheme: int, p_or_s: int, A, B, C=None, alpha: complex = 1.0, beta: complex = 0.0,
+              ws=None, stream=None):
+    """C = alpha*A*B + beta*C (complex128 CUDA tensors) by Scheme I with 4M
+    (p slices) or Scheme II with 3M (s moduli); returns C."""
+    import torch
+    return _complex_call("ozk_zgemm", torch.complex128, ctypes.c_double, ctx, scheme, p_or_s, A, B, C, alpha, beta,
+                         ws, stream)
+
+
+def ozk_cgemm(ctx: Context, scheme: int, p_or_s: int, A, B, C=None, alpha: complex = 1.0, beta: complex = 0.0,
+              ws=None, stream=None):
+    """ozk_zgemm in complex64 (binary32 parts in and out); returns C."""
+    import torch
+    return _complex_call("ozk_cgemm", torch.complex64, ctypes.c_float, ctx, scheme, p_or_s, A, B, C, alpha, beta,
+                         ws, stream)
+
+
+def ozk_s2_unfused_workspace_size(ctx: Context, s: int, complex_planes: int, M: int, N: int, K: int) -> int:
+    out = ctypes.c_size_t()
+    _check("ozk_s2_unfused_workspace_size",
+           _lib().ozk_s2_unfused_workspace_size(ctx.handle, s, complex_planes, M, N, K, ctypes.byref(out)), ctx)
+    return int(out.value)
+
+
+def ozk_s2_gemm_unfused(ctx: Context, s: int, A, B, C=None, alpha: complex = 1.0, beta: complex = 0.0, ws=None,
+                        stream=None):
+    """The unfused Scheme II baseline (INT32 planes through HBM): float64
+    operands give the real product, complex128 ones the 3M product; returns C."""
+    import torch
+    cplx = A.dtype == torch.complex128
+    dtype = torch.complex128 if cplx else torch.float64
+    M, N, K = _mats(ctx, dtype, A, B, C)
+    _ws(ws, ctx)
+    if C is None:
+        C = torch.empty((M, N), dtype=dtype, device=A.device)
+    if ws is None:
+        ws = _workspace(ozk_s2_unfused_workspace_size(ctx, s, int(cplx), M, N, K), A.device)
+    al = (ctypes.c_double * 2)(complex(alpha).real, complex(alpha).imag)
+    be = (ctypes.c_double * 2)(complex(beta).real, complex(beta).imag)
+    st = _lib().ozk_s2_gemm_unfused(ctx.handle, s, int(cplx), M, N, K, ctypes.cast(al, ctypes.c_void_p), _ptr(A),
+                                    _ld(A), _ptr(B), _ld(B), ctypes.cast(be, ctypes.c_void_p), _ptr(C), _ld(C),
+                                    _ptr(ws), ws.numel(), _stream(stream))
+    _check("ozk_s2_gemm_unfused", st, ctx)
+    return C
+
+
+def ozk_zgemm_auto(ctx: Context, tol: float, A, B, C=None, alpha: complex = 1.0, beta: complex = 0.0, ws=None,
+                   info=None, stream=None):
+    """ZGEMM (complex128 CUDA tensors) by 3M with the modulus count chosen on
+    the device for the tolerance; returns (C, info)."""
+    import torch
+    M, N, K = _mats(ctx, torch.complex128, A, B, C)
+    _ws(ws, ctx)
+    if info is not None:
+        _need(info, "info", torch.int32, ctx, min_numel=OZK_SELECTOR_INFO)
+    if C is None:
+        C = torch.empty((M, N), dtype=torch.complex128, device=A.device)
+    if ws is None:
+        ws = _workspace(ozk_workspace_size(ctx, OZK_OP_ZGEMM, OZK_SCHEME2, M, N, K, 0), A.device)
+    if info is None:
+        info = torch.empty(OZK_SELECTOR_INFO, dtype=torch.int32, device=A.device)
+    al = (ctypes.c_double * 2)(complex(alpha).real, complex(alpha).imag)
+    be = (ctypes.c_double * 2)(complex(beta).real, complex(beta).imag)
+    st = _lib().ozk_zgemm_auto(ctx.handle, float(tol), M, N, K, ctypes.cast(al, ctypes.c_void_p), _ptr(A), _ld(A),
+                               _ptr(B), _ld(B), ctypes.cast(be, ctypes.c_void_p), _ptr(C), _ld(C), _ptr(ws),
+                               ws.numel(), _ptr(info), _stream(stream))
+    _check("ozk_zgemm_auto", st, ctx)
+    return C, info
 
 
 # ---------------------------------------------------------- Scheme I steps

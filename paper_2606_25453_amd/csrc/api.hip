@@ -42,9 +42,10 @@ struct ozk_ctx {
   int device = 0;
   int last_arg = 0;
   void* scratch = nullptr;       // device address of `scratch` on this device
+  uint32_t* dflags = nullptr;    // device: [0] condition flags, [1] the last value taken
   int64_t k_split_override = 0;  // > 0: shorter K runs (testing the fold path)
   float* sel_w = nullptr;        // selector parameters on the device (or null)
-  float sel_threshold = 0.5f;
+  float sel_thr[OZK_SELECTOR_HEADS];  // per-head decision thresholds
   int sel_margin = 0;
   std::map<ozk_cfg_key, ozk_cfg_entry> configs;  // tuned or set GEMM configurations
 };
@@ -136,6 +137,17 @@ S2Plan s2_plan(int s, bool cplx, int64_t M, int64_t N, int64_t K) {
   return pl;
 }
 
+// Workspace of the 4M Scheme I complex product: the Scheme I plan of the
+// real embedding (M x 2K times 2K x 2N), then the M x 2N real parts of the
+// product before the complex alpha/beta update (16 MN bytes).
+struct S1ZPlan {
+  S1Plan s1;
+  ozk_gemm_config cfg;
+  size_t off_h, total;
+};
+
+S1ZPlan s1z_plan(const ozk_ctx* c, int p, int64_t M, int64_t N, int64_t K);
+
 // Median time (ms) of `reps` runs of fn on the stream, after one untimed run.
 template <class F>
 static hipError_t time_median(hipStream_t st, int reps, F&& fn, float* ms) {
@@ -214,6 +226,15 @@ ozk_gemm_config config_for(const ozk_ctx* c, int op, int scheme, int p_or_s, int
   return default_config();
 }
 
+S1ZPlan s1z_plan(const ozk_ctx* c, int p, int64_t M, int64_t N, int64_t K) {
+  S1ZPlan z;
+  z.cfg = config_for(c, OZK_OP_DGEMM, OZK_SCHEME1, p, M, 2 * N, 2 * K);  // the embedded real product's class
+  z.s1 = s1_plan(c, p, M, 2 * N, 2 * K, z.cfg.split);
+  z.off_h = z.s1.total;
+  z.total = align256(z.off_h + 16 * (size_t)(M > 0 ? M : 1) * (size_t)(N > 0 ? N : 1));
+  return z;
+}
+
 bool valid_config(int scheme, const ozk_gemm_config& g) {
   const int nv = scheme == OZK_SCHEME1 ? OZK_S1_VARIANTS : OZK_S2_VARIANTS;
   return g.variant >= 0 && g.variant < nv && (g.raster == 0 || g.raster == 1) && g.group >= 1 && g.group <= 64 &&
@@ -255,17 +276,42 @@ ozk_status ozk_create(ozk_ctx** ctx, int device) {
     delete c;
     return OZK_ERR_HIP;
   }
+  if (hipMalloc(&c->dflags, 256) != hipSuccess) {
+    c->dflags = nullptr;
+    delete c;
+    return OZK_ERR_HIP;
+  }
+  if (hipMemset(c->dflags, 0, 256) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+    (void)hipFree(c->dflags);
+    delete c;
+    return OZK_ERR_HIP;
+  }
   *ctx = c;
   return OZK_OK;
 }
 
 ozk_status ozk_destroy(ozk_ctx* ctx) {
   if (ctx && ctx->sel_w) (void)hipFree(ctx->sel_w);
+  if (ctx && ctx->dflags) (void)hipFree(ctx->dflags);
   delete ctx;
   return OZK_OK;
 }
 
 int ozk_last_arg(const ozk_ctx* ctx) { return ctx ? ctx->last_arg : 0; }
+
+ozk_status ozk_get_flags(ozk_ctx* ctx, hipStream_t stream, uint32_t* flags) {
+  if (!ctx) return OZK_ERR_INVALID_ARG;
+  ctx->last_arg = 0;
+  if (!flags) return fail(ctx, OZK_ERR_INVALID_ARG, 3);
+  hipError_t err = hipSetDevice(ctx->device);
+  if (err == hipSuccess) err = ozk::flag_take(ctx->dflags, ctx->dflags + 1, stream);
+  if (err == hipSuccess) err = hipStreamSynchronize(stream);
+  uint32_t v = 0;
+  if (err == hipSuccess) err = hipMemcpy(&v, ctx->dflags + 1, sizeof(v), hipMemcpyDeviceToHost);
+  if (err != hipSuccess) return hip_status(ctx, err);
+  *flags = v;
+  return OZK_OK;
+}
 
 ozk_status ozk_set_k_split(ozk_ctx* ctx, int64_t k) {
   if (!ctx) return OZK_ERR_INVALID_ARG;
@@ -304,6 +350,16 @@ ozk_status ozk_workspace_size(ozk_ctx* ctx, ozk_op op, ozk_scheme scheme, int64_
     }
     if (p_or_s < 1 || p_or_s > OZK_MAX_P) return fail(ctx, OZK_ERR_UNSUPPORTED, 7);
     *bytes = s1_plan(ctx, p_or_s, M, N, K, config_for(ctx, op, scheme, p_or_s, M, N, K).split).total;
+    return OZK_OK;
+  }
+  if (op == OZK_OP_ZGEMM && scheme == OZK_SCHEME1) {  // 4M on the real embedding
+    if (p_or_s < 1 || p_or_s > OZK_MAX_P) return fail(ctx, OZK_ERR_UNSUPPORTED, 7);
+    if (2 * N > OZK_MAX_ROWS || 2 * K > ((int64_t)1 << 40)) return fail(ctx, OZK_ERR_INVALID_ARG, 5);
+    *bytes = s1z_plan(ctx, p_or_s, M, N, K).total;
+    return OZK_OK;
+  }
+  if (op == OZK_OP_ZGEMM && scheme == OZK_SCHEME2 && p_or_s == 0) {  // the automatic ZGEMM
+    *bytes = align256(s2_plan(OZK_MAX_S, true, M, N, K).total) + 512;
     return OZK_OK;
   }
   if (scheme == OZK_SCHEME2 && (op == OZK_OP_DGEMM || op == OZK_OP_ZGEMM)) {
@@ -438,6 +494,7 @@ static ozk_status dgemm_run(ozk_ctx* ctx, ozk_scheme scheme, int p_or_s, bool tr
     if (err == hipSuccess)
       err = trans_b ? ozk::s2_split_rows(s, false, B, ldb, N, K, tau, Bp, stream, tb_bits)
                     : ozk::s2_split_cols(s, false, B, ldb, K, N, tau, Bp, stream);
+    if (err == hipSuccess) err = ozk::flag_nonfinite(sig, M, tau, N, ctx->dflags, stream);
     const ozk_gemm_config cfg = config_for(ctx, OZK_OP_DGEMM, OZK_SCHEME2, s, M, N, K);
     if (cfg.variant == OZK_S2_FUSED_CRT) {
       if (err == hipSuccess)
@@ -466,6 +523,7 @@ static ozk_status dgemm_run(ozk_ctx* ctx, ozk_scheme scheme, int p_or_s, bool tr
                            : ozk::s1_split_rows(p, A, lda, M, K, e, Ap, stream);
   if (err == hipSuccess)
     err = trans_b ? ozk::s1_split_rows(p, B, ldb, N, K, f, Bp, stream) : ozk::s1_split_cols(p, B, ldb, K, N, f, Bp, stream);
+  if (err == hipSuccess) err = ozk::flag_nonfinite(e, M, f, N, ctx->dflags, stream);
   if (err != hipSuccess) return hip_status(ctx, err);
   return s1_gemm_common(ctx, p, M, N, K, Ap, e, Bp, f, alpha, beta, C, ldc, w + pl.off_z,
                         pl.total - pl.off_z, nullptr, stream, cfg);
@@ -580,6 +638,7 @@ ozk_status ozk_s1_dgemm_unfused(ozk_ctx* ctx, int p, int64_t M, int64_t N, int64
   int32_t* planes = (int32_t*)(w + align256(pl.off_z));
   hipError_t err = ozk::s1_split_rows(p, A, lda, M, K, e, Ap, stream);
   if (err == hipSuccess) err = ozk::s1_split_cols(p, B, ldb, K, N, f, Bp, stream);
+  if (err == hipSuccess) err = ozk::flag_nonfinite(e, M, f, N, ctx->dflags, stream);
   if (err == hipSuccess)
     err = ozk::s1_gemm_unfused(p, M, N, K, Ap, e, Bp, f, alpha, beta, C, ldc, planes, stream);
   return hip_status(ctx, err);
@@ -614,6 +673,7 @@ ozk_status ozk_sgemm(ozk_ctx* ctx, ozk_scheme scheme, int p_or_s, int64_t M, int
     int8_t* res = (int8_t*)(w + pl.off_res);
     hipError_t err = ozk::s2_split_rows(s, false, A, lda, M, K, sig, Ap, stream);
     if (err == hipSuccess) err = ozk::s2_split_cols(s, false, B, ldb, K, N, tau, Bp, stream);
+    if (err == hipSuccess) err = ozk::flag_nonfinite(sig, M, tau, N, ctx->dflags, stream);
     const ozk_gemm_config cfg = config_for(ctx, OZK_OP_DGEMM, OZK_SCHEME2, s, M, N, K);
     if (err == hipSuccess)  // the fused-CRT variant writes binary64: the separate kernels here
       err = ozk::s2_gemm_mod(s, false, M, N, K, Ap, Bp, res, stream, cfg.variant, cfg.raster, cfg.group);
@@ -634,6 +694,7 @@ ozk_status ozk_sgemm(ozk_ctx* ctx, ozk_scheme scheme, int p_or_s, int64_t M, int
   int8_t* Bp = (int8_t*)(w + pl.off_b);
   hipError_t err = ozk::s1_split_rows(p, A, lda, M, K, e, Ap, stream);
   if (err == hipSuccess) err = ozk::s1_split_cols(p, B, ldb, K, N, f, Bp, stream);
+  if (err == hipSuccess) err = ozk::flag_nonfinite(e, M, f, N, ctx->dflags, stream);
   if (err != hipSuccess) return hip_status(ctx, err);
   return s1_gemm_common(ctx, p, M, N, K, Ap, e, Bp, f, alpha, beta, nullptr, ldc, w + pl.off_z, pl.total - pl.off_z,
                         nullptr, stream, cfg, C);
@@ -666,6 +727,7 @@ ozk_status ozk_cgemm_3m(ozk_ctx* ctx, int s, int64_t M, int64_t N, int64_t K, co
   int8_t* res = (int8_t*)(w + pl.off_res);
   hipError_t err = ozk::s2_split_rows(s, true, A, lda, M, K, sig, Ap, stream);
   if (err == hipSuccess) err = ozk::s2_split_cols(s, true, B, ldb, K, N, tau, Bp, stream);
+  if (err == hipSuccess) err = ozk::flag_nonfinite(sig, M, tau, N, ctx->dflags, stream);
   const ozk_gemm_config cfg = config_for(ctx, OZK_OP_ZGEMM, OZK_SCHEME2, s, M, N, K);
   if (err == hipSuccess)
     err = ozk::s2_gemm_mod(s, true, M, N, K, Ap, Bp, res, stream, cfg.variant, cfg.raster, cfg.group);
@@ -700,10 +762,159 @@ ozk_status ozk_zgemm_3m(ozk_ctx* ctx, int s, int64_t M, int64_t N, int64_t K, co
   int8_t* res = (int8_t*)(w + pl.off_res);
   hipError_t err = ozk::s2_split_rows(s, true, A, lda, M, K, sig, Ap, stream);
   if (err == hipSuccess) err = ozk::s2_split_cols(s, true, B, ldb, K, N, tau, Bp, stream);
+  if (err == hipSuccess) err = ozk::flag_nonfinite(sig, M, tau, N, ctx->dflags, stream);
   const ozk_gemm_config cfg = config_for(ctx, OZK_OP_ZGEMM, OZK_SCHEME2, s, M, N, K);
   if (err == hipSuccess)
     err = ozk::s2_gemm_mod(s, true, M, N, K, Ap, Bp, res, stream, cfg.variant, cfg.raster, cfg.group);
   if (err == hipSuccess) err = ozk::s2_crt(s, true, M, N, res, sig, tau, alpha, beta, C, ldc, stream);
+  return hip_status(ctx, err);
+}
+
+}  // extern "C"
+
+// The complex product by Scheme I and 4M (T = double: ZGEMM, float: CGEMM):
+// the real embedding's pre-pass (A's rows as they are stored, B through the
+// embedding kernel), the Scheme I GEMM of the M x 2K by 2K x 2N real product
+// into the parts H, then the complex update.  Arguments checked by the caller.
+template <typename T>
+static ozk_status zgemm4m_run(ozk_ctx* ctx, int p, int64_t M, int64_t N, int64_t K, const T* alpha, const T* A,
+                              int64_t lda, const T* B, int64_t ldb, const T* beta, T* C, int64_t ldc, void* ws,
+                              size_t ws_bytes, hipStream_t stream, int ws_arg) {
+  if (2 * N > OZK_MAX_ROWS) return fail(ctx, OZK_ERR_INVALID_ARG, 5);
+  const S1ZPlan zp = s1z_plan(ctx, p, M, N, K);
+  if (!ws || ws_bytes < zp.total) return fail(ctx, OZK_ERR_WORKSPACE, ws_arg);
+  if (M == 0 || N == 0) return OZK_OK;
+  char* w = (char*)ws;
+  const S1Plan& pl = zp.s1;
+  int32_t* e = (int32_t*)(w + pl.off_e);
+  int32_t* f = (int32_t*)(w + pl.off_f);
+  int8_t* Ap = (int8_t*)(w + pl.off_a);
+  int8_t* Bp = (int8_t*)(w + pl.off_b);
+  T* H = (T*)(w + zp.off_h);
+  // row i of A viewed as 2K reals (re, im, re, im, ...) is row i of the embedding
+  hipError_t err = ozk::s1_split_rows(p, A, 2 * lda, M, 2 * K, e, Ap, stream);
+  if (err == hipSuccess) err = ozk::s1_split_cols_4m(p, B, ldb, K, N, f, Bp, stream);
+  if (err == hipSuccess) err = ozk::flag_nonfinite(e, M, f, 2 * N, ctx->dflags, stream);
+  if (err != hipSuccess) return hip_status(ctx, err);
+  ozk_status st;
+  if constexpr (sizeof(T) == 8)
+    st = s1_gemm_common(ctx, p, M, 2 * N, 2 * K, Ap, e, Bp, f, 1.0, 0.0, (double*)H, 2 * N, w + pl.off_z,
+                        zp.off_h - pl.off_z, nullptr, stream, zp.cfg);
+  else
+    st = s1_gemm_common(ctx, p, M, 2 * N, 2 * K, Ap, e, Bp, f, 1.0, 0.0, nullptr, 2 * N, w + pl.off_z,
+                        zp.off_h - pl.off_z, nullptr, stream, zp.cfg, (float*)H);
+  if (st != OZK_OK) return st;
+  return hip_status(ctx, ozk::zaxpby(H, 2 * N, M, N, alpha, beta, C, ldc, stream));
+}
+
+extern "C" {
+
+// Shared checks of ozk_zgemm / ozk_cgemm (argument positions of their signature).
+static ozk_status check_complex_call(ozk_ctx* ctx, int scheme, int p_or_s, int64_t M, int64_t N, int64_t K,
+                                     const void* alpha, const void* A, int64_t lda, const void* B, int64_t ldb,
+                                     const void* beta, const void* C, int64_t ldc) {
+  if (scheme != OZK_SCHEME1 && scheme != OZK_SCHEME2) return fail(ctx, OZK_ERR_INVALID_ARG, 2);
+  if (bad_dims(M, N, K)) return fail(ctx, OZK_ERR_INVALID_ARG, M < 0 ? 4 : (N < 0 ? 5 : 6));
+  if (!alpha) return fail(ctx, OZK_ERR_INVALID_ARG, 7);
+  if (!A && M > 0 && K > 0) return fail(ctx, OZK_ERR_INVALID_ARG, 8);
+  if (lda < (K > 0 ? K : 1)) return fail(ctx, OZK_ERR_INVALID_ARG, 9);
+  if (!B && K > 0 && N > 0) return fail(ctx, OZK_ERR_INVALID_ARG, 10);
+  if (ldb < (N > 0 ? N : 1)) return fail(ctx, OZK_ERR_INVALID_ARG, 11);
+  if (!beta) return fail(ctx, OZK_ERR_INVALID_ARG, 12);
+  if (!C && M > 0 && N > 0) return fail(ctx, OZK_ERR_INVALID_ARG, 13);
+  if (ldc < (N > 0 ? N : 1)) return fail(ctx, OZK_ERR_INVALID_ARG, 14);
+  const int hi = scheme == OZK_SCHEME1 ? OZK_MAX_P : OZK_MAX_S;
+  if (p_or_s < 1 || p_or_s > hi) return fail(ctx, OZK_ERR_UNSUPPORTED, 3);
+  if (scheme == OZK_SCHEME2 && s2_long_k(K)) return fail(ctx, OZK_ERR_UNSUPPORTED, 6);
+  return OZK_OK;
+}
+
+ozk_status ozk_zgemm(ozk_ctx* ctx, ozk_scheme scheme, int p_or_s, int64_t M, int64_t N, int64_t K,
+                     const double* alpha, const double* A, int64_t lda, const double* B, int64_t ldb,
+                     const double* beta, double* C, int64_t ldc, void* ws, size_t ws_bytes, hipStream_t stream) {
+  if (!ctx) return OZK_ERR_INVALID_ARG;
+  ctx->last_arg = 0;
+  const ozk_status st = check_complex_call(ctx, scheme, p_or_s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
+  if (st != OZK_OK) return st;
+  if (scheme == OZK_SCHEME2) {
+    const ozk_status r = ozk_zgemm_3m(ctx, p_or_s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, ws, ws_bytes, stream);
+    if (r == OZK_ERR_WORKSPACE) ctx->last_arg = 15;
+    return r;
+  }
+  return zgemm4m_run<double>(ctx, p_or_s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, ws, ws_bytes, stream, 15);
+}
+
+ozk_status ozk_cgemm(ozk_ctx* ctx, ozk_scheme scheme, int p_or_s, int64_t M, int64_t N, int64_t K,
+                     const float* alpha, const float* A, int64_t lda, const float* B, int64_t ldb, const float* beta,
+                     float* C, int64_t ldc, void* ws, size_t ws_bytes, hipStream_t stream) {
+  if (!ctx) return OZK_ERR_INVALID_ARG;
+  ctx->last_arg = 0;
+  const ozk_status st = check_complex_call(ctx, scheme, p_or_s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
+  if (st != OZK_OK) return st;
+  if (scheme == OZK_SCHEME2) {
+    const ozk_status r = ozk_cgemm_3m(ctx, p_or_s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, ws, ws_bytes, stream);
+    if (r == OZK_ERR_WORKSPACE) ctx->last_arg = 15;
+    return r;
+  }
+  return zgemm4m_run<float>(ctx, p_or_s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, ws, ws_bytes, stream, 15);
+}
+
+// The unfused Scheme II / 3M baseline: the fused path's pre-pass and CRT
+// around one GEMM per modular product with INT32 planes through HBM.
+static size_t s2_unfused_ws(int s, bool cplx, int64_t M, int64_t N, int64_t K, S2Plan& pl) {
+  pl = s2_plan(s, cplx, M, N, K);
+  return align256(pl.total) + (size_t)ozk::s2_unfused_planes_bytes(s, cplx, M, N);
+}
+
+ozk_status ozk_s2_unfused_workspace_size(ozk_ctx* ctx, int s, int complex_planes, int64_t M, int64_t N, int64_t K,
+                                         size_t* bytes) {
+  if (!ctx) return OZK_ERR_INVALID_ARG;
+  ctx->last_arg = 0;
+  if (s < 1 || s > OZK_MAX_S) return fail(ctx, OZK_ERR_UNSUPPORTED, 2);
+  if (complex_planes != 0 && complex_planes != 1) return fail(ctx, OZK_ERR_INVALID_ARG, 3);
+  if (bad_dims(M, N, K)) return fail(ctx, OZK_ERR_INVALID_ARG, 4);
+  if (!bytes) return fail(ctx, OZK_ERR_INVALID_ARG, 7);
+  S2Plan pl;
+  *bytes = s2_unfused_ws(s, complex_planes != 0, M, N, K, pl);
+  return OZK_OK;
+}
+
+ozk_status ozk_s2_gemm_unfused(ozk_ctx* ctx, int s, int complex_planes, int64_t M, int64_t N, int64_t K,
+                               const double* alpha, const double* A, int64_t lda, const double* B, int64_t ldb,
+                               const double* beta, double* C, int64_t ldc, void* ws, size_t ws_bytes,
+                               hipStream_t stream) {
+  if (!ctx) return OZK_ERR_INVALID_ARG;
+  ctx->last_arg = 0;
+  if (s < 1 || s > OZK_MAX_S) return fail(ctx, OZK_ERR_UNSUPPORTED, 2);
+  if (complex_planes != 0 && complex_planes != 1) return fail(ctx, OZK_ERR_INVALID_ARG, 3);
+  if (bad_dims(M, N, K)) return fail(ctx, OZK_ERR_INVALID_ARG, M < 0 ? 4 : (N < 0 ? 5 : 6));
+  if (K > 131071) return fail(ctx, OZK_ERR_UNSUPPORTED, 6);  // |sum| <= K 2^14 < 2^31
+  if (!alpha) return fail(ctx, OZK_ERR_INVALID_ARG, 7);
+  if (!A && M > 0 && K > 0) return fail(ctx, OZK_ERR_INVALID_ARG, 8);
+  if (lda < (K > 0 ? K : 1)) return fail(ctx, OZK_ERR_INVALID_ARG, 9);
+  if (!B && K > 0 && N > 0) return fail(ctx, OZK_ERR_INVALID_ARG, 10);
+  if (ldb < (N > 0 ? N : 1)) return fail(ctx, OZK_ERR_INVALID_ARG, 11);
+  if (!beta) return fail(ctx, OZK_ERR_INVALID_ARG, 12);
+  if (!C && M > 0 && N > 0) return fail(ctx, OZK_ERR_INVALID_ARG, 13);
+  if (ldc < (N > 0 ? N : 1)) return fail(ctx, OZK_ERR_INVALID_ARG, 14);
+  const bool cplx = complex_planes != 0;
+  S2Plan pl;
+  const size_t need = s2_unfused_ws(s, cplx, M, N, K, pl);
+  if (!ws || ws_bytes < need) return fail(ctx, OZK_ERR_WORKSPACE, 15);
+  if (M == 0 || N == 0) return OZK_OK;
+  char* w = (char*)ws;
+  int32_t* sig = (int32_t*)(w + pl.off_sig);
+  int32_t* tau = (int32_t*)(w + pl.off_tau);
+  int8_t* Ap = (int8_t*)(w + pl.off_a);
+  int8_t* Bp = (int8_t*)(w + pl.off_b);
+  int8_t* res = (int8_t*)(w + pl.off_res);
+  int32_t* planes = (int32_t*)(w + align256(pl.total));
+  hipError_t err = ozk::s2_split_rows(s, cplx, A, lda, M, K, sig, Ap, stream);
+  if (err == hipSuccess) err = ozk::s2_split_cols(s, cplx, B, ldb, K, N, tau, Bp, stream);
+  if (err == hipSuccess) err = ozk::flag_nonfinite(sig, M, tau, N, ctx->dflags, stream);
+  if (err == hipSuccess) err = ozk::s2_gemm_mod_unfused(s, cplx, M, N, K, Ap, Bp, planes, res, stream);
+  const double al[2] = {alpha[0], cplx ? alpha[1] : 0.0}, be[2] = {beta[0], cplx ? beta[1] : 0.0};
+  if (err == hipSuccess) err = ozk::s2_crt(s, cplx, M, N, res, sig, tau, al, be, C, ldc, stream);
   return hip_status(ctx, err);
 }
 
@@ -771,11 +982,13 @@ ozk_status ozk_s2_crt(ozk_ctx* ctx, int s, int complex_planes, int64_t M, int64_
   return hip_status(ctx, ozk::s2_crt(s, complex_planes != 0, M, N, Cres, sigma, tau, alpha, beta, C, ldc, stream));
 }
 
-ozk_status ozk_selector_load(ozk_ctx* ctx, const float* params, size_t n, float threshold, int margin) {
+ozk_status ozk_selector_load(ozk_ctx* ctx, const float* params, size_t n, const float* thresholds, int margin) {
   if (!ctx) return OZK_ERR_INVALID_ARG;
   ctx->last_arg = 0;
   if (!params || n != OZK_SELECTOR_PARAMS) return fail(ctx, OZK_ERR_INVALID_ARG, 2);
-  if (!(threshold > 0.f && threshold < 1.f)) return fail(ctx, OZK_ERR_INVALID_ARG, 4);
+  if (!thresholds) return fail(ctx, OZK_ERR_INVALID_ARG, 4);
+  for (int i = 0; i < OZK_SELECTOR_HEADS; ++i)
+    if (!(thresholds[i] > 0.f && thresholds[i] < 1.f)) return fail(ctx, OZK_ERR_INVALID_ARG, 4);
   if (margin < 0 || margin > 8) return fail(ctx, OZK_ERR_INVALID_ARG, 5);
   if (!ctx->sel_w && hipMalloc(&ctx->sel_w, sizeof(float) * OZK_SELECTOR_PARAMS) != hipSuccess) {
     ctx->sel_w = nullptr;
@@ -783,7 +996,7 @@ ozk_status ozk_selector_load(ozk_ctx* ctx, const float* params, size_t n, float 
   }
   if (hipMemcpy(ctx->sel_w, params, sizeof(float) * OZK_SELECTOR_PARAMS, hipMemcpyHostToDevice) != hipSuccess)
     return fail(ctx, OZK_ERR_HIP, 0);
-  ctx->sel_threshold = threshold;
+  for (int i = 0; i < OZK_SELECTOR_HEADS; ++i) ctx->sel_thr[i] = thresholds[i];
   ctx->sel_margin = margin;
   return OZK_OK;
 }
@@ -806,7 +1019,7 @@ ozk_status ozk_select(ozk_ctx* ctx, double tol, int64_t M, int64_t N, int64_t K,
   if (!info) return fail(ctx, OZK_ERR_INVALID_ARG, 13);
   hipError_t err = ozk::sel_features(A, lda, M, B, ldb, N, K, e, f, counters, stream);
   if (err == hipSuccess)
-    err = ozk::sel_infer(counters, ctx->sel_w, ctx->sel_threshold, ctx->sel_margin, tol, K, info, features, stream);
+    err = ozk::sel_infer(counters, ctx->sel_w, ctx->sel_thr, ctx->sel_margin, tol, K, info, features, stream);
   return hip_status(ctx, err);
 }
 
@@ -836,7 +1049,9 @@ ozk_status ozk_dgemm_auto(ozk_ctx* ctx, double tol, int64_t M, int64_t N, int64_
   int32_t* f = (int32_t*)(w + p1.off_f);
   hipError_t err = ozk::sel_features(A, lda, M, B, ldb, N, K, e, f, cnt, stream);
   if (err == hipSuccess)
-    err = ozk::sel_infer(cnt, ctx->sel_w, ctx->sel_threshold, ctx->sel_margin, tol, K, inf, nullptr, stream);
+    err = ozk::sel_infer(cnt, ctx->sel_w, ctx->sel_thr, ctx->sel_margin, tol, K, inf, nullptr, stream);
+  if (err == hipSuccess) err = ozk::flag_nonfinite(e, M, f, N, ctx->dflags, stream);
+  if (err == hipSuccess) err = ozk::flag_decision(inf, ctx->dflags, stream);
   // Scheme I at the chosen p (every kernel returns when Scheme II was chosen)
   int8_t* Ap = (int8_t*)(w + p1.off_a);
   int8_t* Bp = (int8_t*)(w + p1.off_b);
@@ -867,10 +1082,51 @@ ozk_status ozk_dgemm_auto(ozk_ctx* ctx, double tol, int64_t M, int64_t N, int64_
   int8_t* Ar = (int8_t*)(w + p2.off_a);
   int8_t* Br = (int8_t*)(w + p2.off_b);
   int8_t* res = (int8_t*)(w + p2.off_res);
-  if (err == hipSuccess) err = ozk::s2_split_rows_auto(inf, A, lda, M, K, sig, Ar, stream);
-  if (err == hipSuccess) err = ozk::s2_split_cols_auto(inf, B, ldb, K, N, tau, Br, stream);
-  if (err == hipSuccess) err = ozk::s2_gemm_mod_auto(inf, M, N, K, Ar, Br, res, stream);
-  if (err == hipSuccess) err = ozk::s2_crt_auto(inf, M, N, res, sig, tau, alpha, beta, C, ldc, stream);
+  const double al[2] = {alpha, 0.0}, be[2] = {beta, 0.0};
+  if (err == hipSuccess) err = ozk::s2_split_rows_auto(inf, false, A, lda, M, K, sig, Ar, stream);
+  if (err == hipSuccess) err = ozk::s2_split_cols_auto(inf, false, B, ldb, K, N, tau, Br, stream);
+  if (err == hipSuccess) err = ozk::s2_gemm_mod_auto(inf, false, M, N, K, Ar, Br, res, stream);
+  if (err == hipSuccess) err = ozk::s2_crt_auto(inf, false, M, N, res, sig, tau, al, be, C, ldc, stream);
+  return hip_status(ctx, err);
+}
+
+ozk_status ozk_zgemm_auto(ozk_ctx* ctx, double tol, int64_t M, int64_t N, int64_t K, const double* alpha,
+                          const double* A, int64_t lda, const double* B, int64_t ldb, const double* beta, double* C,
+                          int64_t ldc, void* ws, size_t ws_bytes, int32_t* info, hipStream_t stream) {
+  if (!ctx) return OZK_ERR_INVALID_ARG;
+  ctx->last_arg = 0;
+  if (bad_tol(tol)) return fail(ctx, OZK_ERR_INVALID_ARG, 2);
+  if (bad_dims(M, N, K)) return fail(ctx, OZK_ERR_INVALID_ARG, M < 0 ? 3 : (N < 0 ? 4 : 5));
+  if (!alpha) return fail(ctx, OZK_ERR_INVALID_ARG, 6);
+  if (!A && M > 0 && K > 0) return fail(ctx, OZK_ERR_INVALID_ARG, 7);
+  if (lda < (K > 0 ? K : 1)) return fail(ctx, OZK_ERR_INVALID_ARG, 8);
+  if (!B && K > 0 && N > 0) return fail(ctx, OZK_ERR_INVALID_ARG, 9);
+  if (ldb < (N > 0 ? N : 1)) return fail(ctx, OZK_ERR_INVALID_ARG, 10);
+  if (!beta) return fail(ctx, OZK_ERR_INVALID_ARG, 11);
+  if (!C && M > 0 && N > 0) return fail(ctx, OZK_ERR_INVALID_ARG, 12);
+  if (ldc < (N > 0 ? N : 1)) return fail(ctx, OZK_ERR_INVALID_ARG, 13);
+  if (s2_long_k(K)) return fail(ctx, OZK_ERR_UNSUPPORTED, 5);
+  const S2Plan pl = s2_plan(OZK_MAX_S, true, M, N, K);  // per-modulus planes do not depend on s
+  const size_t off_cnt = align256(pl.total), off_info = off_cnt + 256;
+  if (!ws || ws_bytes < off_cnt + 512) return fail(ctx, OZK_ERR_WORKSPACE, 14);
+  if (M == 0 || N == 0) return OZK_OK;
+  char* w = (char*)ws;
+  int32_t* sig = (int32_t*)(w + pl.off_sig);
+  int32_t* tau = (int32_t*)(w + pl.off_tau);
+  int8_t* Ap = (int8_t*)(w + pl.off_a);
+  int8_t* Bp = (int8_t*)(w + pl.off_b);
+  int8_t* res = (int8_t*)(w + pl.off_res);
+  int32_t* cnt = (int32_t*)(w + off_cnt);
+  int32_t* inf = info ? info : (int32_t*)(w + off_info);
+  // statistics (tau serves as the column-exponent scratch) and the decision
+  hipError_t err = ozk::zsel_features(A, lda, M, B, ldb, N, K, tau, cnt, stream);
+  if (err == hipSuccess) err = ozk::zsel_decide(cnt, tol, K, inf, stream);
+  if (err == hipSuccess) err = ozk::flag_decision(inf, ctx->dflags, stream);
+  if (err == hipSuccess) err = ozk::s2_split_rows_auto(inf, true, A, lda, M, K, sig, Ap, stream);
+  if (err == hipSuccess) err = ozk::s2_split_cols_auto(inf, true, B, ldb, K, N, tau, Bp, stream);
+  if (err == hipSuccess) err = ozk::flag_nonfinite(sig, M, tau, N, ctx->dflags, stream);
+  if (err == hipSuccess) err = ozk::s2_gemm_mod_auto(inf, true, M, N, K, Ap, Bp, res, stream);
+  if (err == hipSuccess) err = ozk::s2_crt_auto(inf, true, M, N, res, sig, tau, alpha, beta, C, ldc, stream);
   return hip_status(ctx, err);
 }
 
@@ -1081,8 +1337,10 @@ ozk_status ozk_gemm_batched(ozk_ctx* ctx, const ozk_batch_plan* plan, void* ws, 
   if (!plan) return fail(ctx, OZK_ERR_INVALID_ARG, 2);
   if (!ws || ws_bytes < plan->ws_bytes) return fail(ctx, OZK_ERR_WORKSPACE, 3);
   if (plan->count == 0) return OZK_OK;
-  return hip_status(ctx, ozk::s2_batched(plan->s, plan->op == OZK_OP_ZGEMM, plan->bd, plan->tot, (int8_t*)ws,
-                                         plan->gemm_grid, stream));
+  hipError_t err = ozk::s2_batched(plan->s, plan->op == OZK_OP_ZGEMM, plan->bd, plan->tot, (int8_t*)ws,
+                                   plan->gemm_grid, stream);
+  if (err == hipSuccess) err = ozk::flag_batch(plan->bd, (const int8_t*)ws, ctx->dflags, stream);
+  return hip_status(ctx, err);
 }
 
 ozk_status ozk_batch_plan_destroy(ozk_batch_plan* plan) {

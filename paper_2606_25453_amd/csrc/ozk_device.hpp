@@ -162,6 +162,10 @@ __device__ __forceinline__ float axpby_f32(float alpha, float h, float beta, con
   return __fmaf_rn(alpha, h, bc);
 }
 
+// Fused multiply-add in the precision of the operands.
+__device__ __forceinline__ double fma_any(double a, double b, double c) { return __fma_rn(a, b, c); }
+__device__ __forceinline__ float fma_any(float a, float b, float c) { return __fmaf_rn(a, b, c); }
+
 // Maximum / sum over each aligned group of 16 lanes.
 __device__ __forceinline__ int group16_max(int v) {
 #pragma unroll

@@ -39,6 +39,19 @@ hipError_t s1_split_rows(int p, const float* X, int64_t ldx, int64_t rows, int64
 hipError_t s1_split_cols(int p, const float* X, int64_t ldx, int64_t K, int64_t cols, int32_t* f,
                          int8_t* packed, hipStream_t st);
 hipError_t s1_gemm(int p, const S1GemmArgs& g, hipStream_t st);
+// The 4M complex column operand: the slices and column exponents of the real
+// 2K x 2N embedding of complex B (K x N, interleaved, ldx in complex
+// elements); f has 2N entries and the packed operand 2N columns of 2K.
+hipError_t s1_split_cols_4m(int p, const double* X, int64_t ldx, int64_t K, int64_t N, int32_t* f, int8_t* packed,
+                            hipStream_t st);
+hipError_t s1_split_cols_4m(int p, const float* X, int64_t ldx, int64_t K, int64_t N, int32_t* f, int8_t* packed,
+                            hipStream_t st);
+// Complex update C = alpha H + beta C from the (Re, Im) pairs of H (M x 2N,
+// row stride ldh), with the fixed FMA sequence; alpha, beta host {re, im}.
+hipError_t zaxpby(const double* H, int64_t ldh, int64_t M, int64_t N, const double* alpha, const double* beta,
+                  double* C, int64_t ldc, hipStream_t st);
+hipError_t zaxpby(const float* H, int64_t ldh, int64_t M, int64_t N, const float* alpha, const float* beta,
+                  float* C, int64_t ldc, hipStream_t st);
 // The unfused baseline (one GEMM per slice pair, INT32 planes through HBM,
 // then the exact reconstruction); K <= 131071 keeps each plane exact.
 int64_t s1_unfused_planes_bytes(int p, int64_t M, int64_t N);
@@ -122,18 +135,30 @@ S2Budgets s2_budgets();
 // of every s live in constant memory, written by s2_upload_crt_tables on the
 // current device (once per context, before any auto call).
 hipError_t s2_upload_crt_tables();
-hipError_t s2_split_rows_auto(const int32_t* info, const double* X, int64_t ldx, int64_t rows, int64_t K,
+hipError_t s2_split_rows_auto(const int32_t* info, bool cplx, const double* X, int64_t ldx, int64_t rows, int64_t K,
                               int32_t* sigma, int8_t* packed, hipStream_t st);
-hipError_t s2_split_cols_auto(const int32_t* info, const double* X, int64_t ldx, int64_t K, int64_t cols,
+hipError_t s2_split_cols_auto(const int32_t* info, bool cplx, const double* X, int64_t ldx, int64_t K, int64_t cols,
                               int32_t* tau, int8_t* packed, hipStream_t st);
-hipError_t s2_gemm_mod_auto(const int32_t* info, int64_t M, int64_t N, int64_t K, const int8_t* Ap,
+hipError_t s2_gemm_mod_auto(const int32_t* info, bool cplx, int64_t M, int64_t N, int64_t K, const int8_t* Ap,
                             const int8_t* Bp, int8_t* out, hipStream_t st);
-hipError_t s2_crt_auto(const int32_t* info, int64_t M, int64_t N, const int8_t* res, const int32_t* sigma,
-                       const int32_t* tau, double alpha, double beta, double* C, int64_t ldc, hipStream_t st);
+// alpha, beta: host {re, im} (the imaginary parts unused for real products)
+hipError_t s2_crt_auto(const int32_t* info, bool cplx, int64_t M, int64_t N, const int8_t* res, const int32_t* sigma,
+                       const int32_t* tau, const double* alpha, const double* beta, double* C, int64_t ldc,
+                       hipStream_t st);
+
+// Statistics of a complex product for the automatic ZGEMM: the largest
+// exponent deficit of a nonzero real or imaginary part below its row's
+// (column's) largest part exponent, for the rows of A and the columns of B
+// (counters [32] and [33]; [0, 32) zeroed), and the decision info of the
+// Scheme II a-priori bound (3M; the deficits relative to the complex entry
+// exponent max(expo re, expo im) + 1 are one more).
+hipError_t zsel_features(const double* A, int64_t lda, int64_t M, const double* B, int64_t ldb, int64_t N, int64_t K,
+                         int32_t* f_scratch, int32_t* cnt, hipStream_t st);
+hipError_t zsel_decide(const int32_t* cnt, double tol, int64_t K, int32_t* info, hipStream_t st);
 
 hipError_t sel_features(const double* A, int64_t lda, int64_t M, const double* B, int64_t ldb, int64_t N, int64_t K,
                         int32_t* e, int32_t* f, int32_t* cnt, hipStream_t st);
-hipError_t sel_infer(const int32_t* cnt, const float* w, float threshold, int margin, double tol, int64_t K,
+hipError_t sel_infer(const int32_t* cnt, const float* w, const float* thresholds, int margin, double tol, int64_t K,
                      int32_t* info, float* feat, hipStream_t st);
 hipError_t mlp_forward(const float* w, const float* X, int n, float* logits, hipStream_t st);
 hipError_t mlp_grad(const float* w, const float* X, const float* Y, int n, float* grad, float* loss, hipStream_t st);
@@ -160,9 +185,22 @@ hipError_t s2_split_cols(int s, bool cplx, const float* X, int64_t ldx, int64_t 
 hipError_t s2_crt(int s, bool cplx, int64_t M, int64_t N, const int8_t* res, const int32_t* sigma,
                   const int32_t* tau, const float* alpha, const float* beta, float* C, int64_t ldc,
                   hipStream_t st);
+// The unfused Scheme II / 3M baseline: one INT8 GEMM per modular product
+// writing INT32 planes (s x M x N, 3M: 3s), then the reduction to the
+// residue planes of s2_gemm_mod (K <= 131071).
+int64_t s2_unfused_planes_bytes(int s, bool cplx, int64_t M, int64_t N);
+hipError_t s2_gemm_mod_unfused(int s, bool cplx, int64_t M, int64_t N, int64_t K, const int8_t* Ap, const int8_t* Bp,
+                               int32_t* planes, int8_t* out, hipStream_t st);
 // GEMM and CRT in one kernel (real products; no residue planes).
 hipError_t s2_gemm_crt(int s, int64_t M, int64_t N, int64_t K, const int8_t* Ap, const int8_t* Bp,
                        const int32_t* sigma, const int32_t* tau, double alpha, double beta, double* C, int64_t ldc,
                        int raster, int group, hipStream_t st);
+
+// Condition flags (flags.hip): OR bits into the context's device word.
+hipError_t flag_nonfinite(const int32_t* a, int64_t na, const int32_t* b, int64_t nb, uint32_t* flags,
+                          hipStream_t st);
+hipError_t flag_batch(const BatchDev& bd, const int8_t* ws, uint32_t* flags, hipStream_t st);
+hipError_t flag_decision(const int32_t* info, uint32_t* flags, hipStream_t st);
+hipError_t flag_take(uint32_t* flags, uint32_t* out, hipStream_t st);
 
 }  // namespace ozk

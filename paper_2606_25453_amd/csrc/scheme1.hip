@@ -275,6 +275,101 @@ __global__ __launch_bounds__(256) void k_s1_split_cols_auto(const double* __rest
   }
 }
 
+// ------------------------------------------- 4M complex column operand
+
+// Entry (k2, c) of the real embedding that turns a complex product into one
+// real product (the four real products of 4M, Sec. IV-B, with their
+// subtraction and addition inside the exact integer sums): for the complex
+// column operand B (K x N, interleaved, ldx in complex elements) the 2K x 2N
+// matrix whose row 2k holds (Re b_kj, Im b_kj) at columns (2j, 2j+1) and row
+// 2k+1 holds (-Im b_kj, Re b_kj).  The complex row operand A needs no such
+// step: its row i viewed as 2K reals, (Re a_i0, Im a_i0, Re a_i1, ...), is
+// the embedded row, so column 2j of the product is Re (AB)_ij and column
+// 2j+1 is Im (AB)_ij -- the interleaved complex result.  Columns 2j and 2j+1
+// hold the same magnitudes, so they share one exponent; a row of A shares
+// one exponent between its parts.
+template <typename T>
+__device__ __forceinline__ double embed4m(const T* __restrict__ X, int64_t ldx, int64_t k2, int64_t c) {
+  const bool odd_k = (k2 & 1) != 0, odd_c = (c & 1) != 0;
+  const T* z = X + 2 * ((k2 >> 1) * ldx + (c >> 1));
+  const double v = (double)z[odd_k != odd_c ? 1 : 0];  // Re on the diagonal of the 2 x 2 block, else Im
+  return odd_k && !odd_c ? -v : v;
+}
+
+// Column exponents of the embedding: thread c scans 256 rows k2 of column c.
+template <typename T>
+__global__ __launch_bounds__(256) void k_s1_exp_cols_4m(const T* __restrict__ X, int64_t ldx, int64_t K2,
+                                                        int64_t cols2, int32_t* __restrict__ f) {
+  const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (c >= cols2) return;
+  const int64_t k0 = (int64_t)blockIdx.y * 256;
+  const int64_t k1 = k0 + 256 < K2 ? k0 + 256 : K2;
+  int e = OZK_EXP_ZERO;
+  for (int64_t k = k0; k < k1; ++k) {
+    const int ek = expo_of(embed4m(X, ldx, k, c));
+    e = ek > e ? ek : e;
+  }
+  if (e != OZK_EXP_ZERO) atomicMax(&f[c], e);
+}
+
+// Slices of the embedding, thread (c, chunk) as in k_s1_split_cols.
+template <int P, typename T>
+__global__ __launch_bounds__(256) void k_s1_split_cols_4m(const T* __restrict__ X, int64_t ldx, int64_t K2,
+                                                          int64_t cols2, int64_t cols_packed,
+                                                          const int32_t* __restrict__ f,
+                                                          int8_t* __restrict__ packed) {
+  const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (c >= cols_packed) return;
+  const int64_t ch = blockIdx.y, kb = ch * OZK_K_CHUNK;
+  const int e = c < cols2 ? f[c] : OZK_EXP_ZERO;
+  uint32_t word[8][P];
+  if (live_exponent(e)) {
+#pragma unroll
+    for (int g = 0; g < 8; ++g) {
+      double v[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int64_t k = kb + 4 * g + i;
+        v[i] = k < K2 ? embed4m(X, ldx, k, c) : 0.0;
+      }
+      s1_words<P>(v, e, word[g]);
+    }
+  } else {
+#pragma unroll
+    for (int g = 0; g < 8; ++g)
+#pragma unroll
+      for (int t = 0; t < P; ++t) word[g][t] = 0;
+  }
+#pragma unroll
+  for (int t = 0; t < P; ++t) {
+    uint4* q = reinterpret_cast<uint4*>(packed + ((ch * P + t) * cols_packed + c) * OZK_K_CHUNK);
+    q[0] = make_uint4(word[0][t], word[1][t], word[2][t], word[3][t]);
+    q[1] = make_uint4(word[4][t], word[5][t], word[6][t], word[7][t]);
+  }
+}
+
+// C = alpha H + beta C for a complex result whose parts H (M x 2N reals,
+// row stride ldh) hold (Re, Im) pairs: the fixed FMA sequence of the
+// complex calls (beta == 0: C is not read), in the output's precision.
+template <typename TO>
+__global__ __launch_bounds__(256) void k_zaxpby(const TO* __restrict__ H, int64_t ldh, int64_t M, int64_t N,
+                                                TO a_re, TO a_im, TO b_re, TO b_im, TO* __restrict__ C,
+                                                int64_t ldc) {
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= M * N) return;
+  const int64_t i = idx / N, j = idx % N;
+  const TO hre = H[i * ldh + 2 * j], him = H[i * ldh + 2 * j + 1];
+  TO* cp = C + 2 * (i * ldc + j);
+  TO bre = 0, bim = 0;
+  if (!(b_re == 0 && b_im == 0)) {
+    const TO cre = cp[0], cim = cp[1];
+    bre = fma_any(b_re, cre, -(b_im * cim));
+    bim = fma_any(b_re, cim, b_im * cre);
+  }
+  cp[0] = fma_any(a_re, hre, fma_any(-a_im, him, bre));
+  cp[1] = fma_any(a_re, him, fma_any(a_im, hre, bim));
+}
+
 // Exact fold of the K-run partials followed by the single rounding.
 // TO = float: the binary32 rounding and update (alpha, beta hold binary32 values).
 template <typename TO>
@@ -366,6 +461,70 @@ static hipError_t split_cols_any(int p, const T* X, int64_t ldx, int64_t K, int6
     case 8: return launch_split_cols<8>(X, ldx, K, cols, f, packed, st);
   }
   return hipErrorInvalidValue;
+}
+
+template <int P, typename T>
+static hipError_t launch_split_cols_4m(const T* X, int64_t ldx, int64_t K, int64_t N, int32_t* f, int8_t* packed,
+                                       hipStream_t st) {
+  const int64_t K2 = 2 * K, cols2 = 2 * N;
+  const int64_t cp = round_up(cols2, OZK_ROW_ALIGN), kp = round_up(K2, OZK_K_CHUNK);
+  if (cols2 > 0) {
+    hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((cols2 + 255) / 256)), dim3(256), 0, st, f, cols2,
+                       (int32_t)OZK_EXP_ZERO);
+    if (K2 > 0)
+      hipLaunchKernelGGL(k_s1_exp_cols_4m<T>, dim3((unsigned)((cols2 + 255) / 256), (unsigned)((K2 + 255) / 256)),
+                         dim3(256), 0, st, X, ldx, K2, cols2, f);
+  }
+  if (cp > 0 && kp > 0)
+    hipLaunchKernelGGL((k_s1_split_cols_4m<P, T>), dim3((unsigned)(cp / 256), (unsigned)(kp / OZK_K_CHUNK)),
+                       dim3(256), 0, st, X, ldx, K2, cols2, cp, f, packed);
+  return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t split_cols_4m_any(int p, const T* X, int64_t ldx, int64_t K, int64_t N, int32_t* f,
+                                    int8_t* packed, hipStream_t st) {
+  switch (p) {
+    case 1: return launch_split_cols_4m<1>(X, ldx, K, N, f, packed, st);
+    case 2: return launch_split_cols_4m<2>(X, ldx, K, N, f, packed, st);
+    case 3: return launch_split_cols_4m<3>(X, ldx, K, N, f, packed, st);
+    case 4: return launch_split_cols_4m<4>(X, ldx, K, N, f, packed, st);
+    case 5: return launch_split_cols_4m<5>(X, ldx, K, N, f, packed, st);
+    case 6: return launch_split_cols_4m<6>(X, ldx, K, N, f, packed, st);
+    case 7: return launch_split_cols_4m<7>(X, ldx, K, N, f, packed, st);
+    case 8: return launch_split_cols_4m<8>(X, ldx, K, N, f, packed, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t s1_split_cols_4m(int p, const double* X, int64_t ldx, int64_t K, int64_t N, int32_t* f, int8_t* packed,
+                            hipStream_t st) {
+  return split_cols_4m_any(p, X, ldx, K, N, f, packed, st);
+}
+
+hipError_t s1_split_cols_4m(int p, const float* X, int64_t ldx, int64_t K, int64_t N, int32_t* f, int8_t* packed,
+                            hipStream_t st) {
+  return split_cols_4m_any(p, X, ldx, K, N, f, packed, st);
+}
+
+template <typename TO>
+static hipError_t launch_zaxpby(const TO* H, int64_t ldh, int64_t M, int64_t N, const TO* alpha, const TO* beta,
+                                TO* C, int64_t ldc, hipStream_t st) {
+  const int64_t n = M * N;
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zaxpby<TO>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, H, ldh, M, N, alpha[0],
+                     alpha[1], beta[0], beta[1], C, ldc);
+  return hipGetLastError();
+}
+
+hipError_t zaxpby(const double* H, int64_t ldh, int64_t M, int64_t N, const double* alpha, const double* beta,
+                  double* C, int64_t ldc, hipStream_t st) {
+  return launch_zaxpby(H, ldh, M, N, alpha, beta, C, ldc, st);
+}
+
+hipError_t zaxpby(const float* H, int64_t ldh, int64_t M, int64_t N, const float* alpha, const float* beta,
+                  float* C, int64_t ldc, hipStream_t st) {
+  return launch_zaxpby(H, ldh, M, N, alpha, beta, C, ldc, st);
 }
 
 hipError_t s1_split_rows(int p, const double* X, int64_t ldx, int64_t rows, int64_t K, int32_t* e,

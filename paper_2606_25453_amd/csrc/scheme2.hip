@@ -1048,6 +1048,93 @@ hipError_t s2_gemm_mod(int s, bool cplx, int64_t M, int64_t N, int64_t K, const 
               : launch_gemm_mod<false, 0>(s, M, N, K, Ap, Bp, out, raster, group, st);
 }
 
+// ------------------------------------------ unfused baselines (ablation)
+//
+// The naive Scheme II of the paper's traffic model (Sec. IV-A, Eq. 14) and
+// its 3M form (Sec. IV-B, Eq. 17), kept as an ablation of the fused kernels:
+// every modular product (3M: T1, T2, T3 of each modulus) is its own INT8
+// GEMM whose INT32 result goes to HBM, and a second pass reads the planes
+// back, reduces them mod m_l (3M: forms the combination) and writes the
+// INT8 residues of the fused path, which the shared CRT kernel then reads.
+// Same operands and result as the fused path; only the INT32 round trip
+// (4 MN bytes per product written and read) differs.  |acc| <= K 2^14 stays
+// exact in INT32 for K <= 131071.
+
+constexpr int NAIVE_TM = 2, NAIVE_TN = 2, NAIVE_NS = 4;  // 128 x 128 tiles, four stages
+using NaiveTile = GemmTile<1, NAIVE_TM, NAIVE_TN, NAIVE_NS>;
+
+// Product z = l Q + q (Q = 1 real, 3 for 3M: q = 0 re x re, 1 im x im, 2 the
+// sums): plane q of modulus l is every Q-th slab of that modulus's packed
+// operand, from slab q.
+__global__ __launch_bounds__(256, 1) void k_s2_plane_gemm(const int8_t* __restrict__ Ap,
+                                                         const int8_t* __restrict__ Bp, int64_t rows_a,
+                                                         int64_t rows_b, int Q, int64_t nchunk, int M, int N,
+                                                         int32_t* __restrict__ planes) {
+  extern __shared__ __attribute__((aligned(1024))) int8_t lds[];
+  const int z = blockIdx.z, l = z / Q, q = z % Q;
+  const int64_t tiles_m = (M + NaiveTile::BM - 1) / NaiveTile::BM, tiles_n = (N + NaiveTile::BN - 1) / NaiveTile::BN;
+  int64_t tm, tn;
+  tile_of(blockIdx.x, tiles_m, tiles_n, 0, 4, tm, tn);
+  const int64_t m0 = tm * NaiveTile::BM, n0 = tn * NaiveTile::BN;
+  const int64_t kp = nchunk * OZK_K_CHUNK;
+  v16i acc[1][NAIVE_TM][NAIVE_TN];
+  zero_acc<1, NAIVE_TM, NAIVE_TN>(acc);
+  gemm_tile_accumulate<1, NAIVE_TM, NAIVE_TN, NAIVE_NS, DIAGONAL, 1>(
+      Ap + (int64_t)l * Q * rows_a * kp + (int64_t)q * rows_a * OZK_K_CHUNK,
+      Bp + (int64_t)l * Q * rows_b * kp + (int64_t)q * rows_b * OZK_K_CHUNK, Q * rows_a, Q * rows_b, m0, n0, 0,
+      nchunk, lds, acc);
+  int32_t* out = planes + (int64_t)z * M * N;
+  for_each_output<1, NAIVE_TM, NAIVE_TN>(acc, m0, n0, M, N,
+                                          [&](int64_t row, int64_t col, const int* vals) { out[row * N + col] = vals[0]; });
+}
+
+// The INT32 planes back from HBM, reduced to the residues the fused kernel
+// writes: [l][M][N] (3M: [l][2][M][N], re = smod(T1 - T2), im = smod(T3 - T1 - T2)).
+template <bool CPLX>
+__global__ __launch_bounds__(256) void k_s2_planes_mod(const int32_t* __restrict__ planes, int s, int64_t mn,
+                                                       int8_t* __restrict__ out) {
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= mn) return;
+  for (int l = 0; l < s; ++l) {
+    if (!CPLX) {
+      out[l * mn + idx] = (int8_t)smod_i32(planes[l * mn + idx], l);
+    } else {
+      const int t1 = smod_i32(planes[(3 * l) * mn + idx], l), t2 = smod_i32(planes[(3 * l + 1) * mn + idx], l),
+                t3 = smod_i32(planes[(3 * l + 2) * mn + idx], l);
+      out[(2 * l) * mn + idx] = (int8_t)smod_sum(t1, -t2, l);
+      out[(2 * l + 1) * mn + idx] = (int8_t)smod_sum(smod_sum(t3, -t1, l), -t2, l);
+    }
+  }
+}
+
+int64_t s2_unfused_planes_bytes(int s, bool cplx, int64_t M, int64_t N) { return (int64_t)s * (cplx ? 3 : 1) * M * N * 4; }
+
+hipError_t s2_gemm_mod_unfused(int s, bool cplx, int64_t M, int64_t N, int64_t K, const int8_t* Ap, const int8_t* Bp,
+                               int32_t* planes, int8_t* out, hipStream_t st) {
+  if (M == 0 || N == 0) return hipSuccess;
+  static bool attr = false;
+  if (!attr) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_s2_plane_gemm),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, NaiveTile::LDS_BYTES);
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  const int Q = cplx ? 3 : 1;
+  const int64_t ra = round_up(M, OZK_ROW_ALIGN), rb = round_up(N, OZK_ROW_ALIGN);
+  const int64_t nchunk = round_up(K, OZK_K_CHUNK) / OZK_K_CHUNK;
+  const int64_t tiles = ((M + NaiveTile::BM - 1) / NaiveTile::BM) * ((N + NaiveTile::BN - 1) / NaiveTile::BN);
+  hipLaunchKernelGGL(k_s2_plane_gemm, dim3((unsigned)tiles, 1, (unsigned)(s * Q)), dim3(256), NaiveTile::LDS_BYTES,
+                     st, Ap, Bp, ra, rb, Q, nchunk, (int)M, (int)N, planes);
+  const int64_t mn = M * N;
+  if (cplx)
+    hipLaunchKernelGGL(k_s2_planes_mod<true>, dim3((unsigned)((mn + 255) / 256)), dim3(256), 0, st, planes, s, mn,
+                       out);
+  else
+    hipLaunchKernelGGL(k_s2_planes_mod<false>, dim3((unsigned)((mn + 255) / 256)), dim3(256), 0, st, planes, s, mn,
+                       out);
+  return hipGetLastError();
+}
+
 // 32-bit limbs the CRT sums need: sum_l W_l c_l < s 2^8 P < 2^(bits(P) + 13) for s <= 20.
 static int crt_limbs(const CrtArgs& ca) {
   int pbits = 0;
@@ -1211,6 +1298,7 @@ __device__ __forceinline__ bool s2_chosen(const int32_t* __restrict__ info, int&
   return s >= 1 && s <= OZK_MAX_S;
 }
 
+template <bool CPLX>
 __global__ __launch_bounds__(256) void k_s2_split_rows_auto(const double* __restrict__ X, int64_t ldx, int64_t rows,
                                                             int64_t K, int64_t Kp, int64_t rows_packed,
                                                             const int32_t* __restrict__ info, S2Budgets bud,
@@ -1218,18 +1306,20 @@ __global__ __launch_bounds__(256) void k_s2_split_rows_auto(const double* __rest
                                                             int8_t* __restrict__ packed) {
   int s;
   if (!s2_chosen(info, s)) return;
-  s2_split_rows_block<false>(X, ldx, rows, K, Kp, rows_packed, S2Args{s, bud.ta[s]}, sigma_out, packed,
-                             blockIdx.x);
+  s2_split_rows_block<CPLX>(X, ldx, rows, K, Kp, rows_packed, S2Args{s, bud.ta[s]}, sigma_out, packed,
+                            blockIdx.x);
 }
 
+template <bool CPLX>
 __global__ __launch_bounds__(256) void k_s2_col_scales_auto(const double* __restrict__ X, int64_t ldx, int64_t K,
                                                             int64_t cols, const int32_t* __restrict__ info,
                                                             S2Budgets bud, int32_t* __restrict__ tau) {
   int s;
   if (!s2_chosen(info, s)) return;
-  s2_col_scales_block<false>(X, ldx, K, cols, bud.tb[s], tau, blockIdx.x);
+  s2_col_scales_block<CPLX>(X, ldx, K, cols, bud.tb[s], tau, blockIdx.x);
 }
 
+template <bool CPLX>
 __global__ __launch_bounds__(256) void k_s2_split_cols_auto(const double* __restrict__ X, int64_t ldx, int64_t K,
                                                             int64_t cols, int64_t Kp, int64_t cols_packed,
                                                             const int32_t* __restrict__ info,
@@ -1237,10 +1327,11 @@ __global__ __launch_bounds__(256) void k_s2_split_cols_auto(const double* __rest
                                                             int8_t* __restrict__ packed) {
   int s;
   if (!s2_chosen(info, s)) return;
-  s2_split_cols_block<false>(X, ldx, K, cols, Kp, cols_packed, s, tau, packed, blockIdx.x, blockIdx.y);
+  s2_split_cols_block<CPLX>(X, ldx, K, cols, Kp, cols_packed, s, tau, packed, blockIdx.x, blockIdx.y);
 }
 
 // grid z covers OZK_MAX_S moduli; the planes past the chosen s return
+template <bool CPLX>
 __global__ __launch_bounds__(256, 1) void k_s2_gemm_mod_auto(const int8_t* __restrict__ Ap,
                                                             const int8_t* __restrict__ Bp, int64_t plane_a,
                                                             int64_t plane_b, int64_t rows_a, int64_t rows_b,
@@ -1250,18 +1341,19 @@ __global__ __launch_bounds__(256, 1) void k_s2_gemm_mod_auto(const int8_t* __res
   extern __shared__ __attribute__((aligned(1024))) int8_t lds[];
   int s;
   if (!s2_chosen(info, s) || (int)blockIdx.z >= s) return;
-  s2_gemm_tile<false, 0>(Ap, Bp, plane_a, plane_b, rows_a, rows_b, nsteps, M, N, out, blockIdx.x, (int)blockIdx.z,
-                         0, 4, lds);
+  s2_gemm_tile<CPLX, 0>(Ap, Bp, plane_a, plane_b, rows_a, rows_b, nsteps, M, N, out, blockIdx.x, (int)blockIdx.z,
+                        0, 4, lds);
 }
 
+template <bool CPLX>
 __global__ __launch_bounds__(256) void k_s2_crt_auto(int M, int N, const int8_t* __restrict__ res,
                                                      const int32_t* __restrict__ sigma,
                                                      const int32_t* __restrict__ tau,
-                                                     const int32_t* __restrict__ info, double alpha, double beta,
-                                                     double* __restrict__ C, int64_t ldc) {
+                                                     const int32_t* __restrict__ info, double a_re, double a_im,
+                                                     double b_re, double b_im, double* __restrict__ C, int64_t ldc) {
   int s;
   if (!s2_chosen(info, s)) return;
-  s2_crt_block<false>(c_crt_all[s - 1], M, N, res, sigma, tau, alpha, 0.0, beta, 0.0, C, ldc, blockIdx.x);
+  s2_crt_block<CPLX>(c_crt_all[s - 1], M, N, res, sigma, tau, a_re, a_im, b_re, b_im, C, ldc, blockIdx.x);
 }
 
 S2Budgets s2_budgets() {
@@ -1278,35 +1370,52 @@ hipError_t s2_upload_crt_tables() {
   return hipMemcpyToSymbol(HIP_SYMBOL(c_crt_all), all, sizeof(all));
 }
 
-hipError_t s2_split_rows_auto(const int32_t* info, const double* X, int64_t ldx, int64_t rows, int64_t K,
+hipError_t s2_split_rows_auto(const int32_t* info, bool cplx, const double* X, int64_t ldx, int64_t rows, int64_t K,
                               int32_t* sigma, int8_t* packed, hipStream_t st) {
   const int64_t rp = round_up(rows, OZK_ROW_ALIGN), kp = round_up(K, OZK_K_CHUNK);
-  if (rp > 0)
-    hipLaunchKernelGGL(k_s2_split_rows_auto, dim3((unsigned)(rp / S2_ROWS_PER_BLOCK)), dim3(256), 0, st, X, ldx, rows, K, kp, rp,
-                       info, s2_budgets(), sigma, packed);
+  if (rp > 0) {
+    const dim3 grid((unsigned)(rp / S2_ROWS_PER_BLOCK));
+    if (cplx)
+      hipLaunchKernelGGL(k_s2_split_rows_auto<true>, grid, dim3(256), 0, st, X, ldx, rows, K, kp, rp, info,
+                         s2_budgets(), sigma, packed);
+    else
+      hipLaunchKernelGGL(k_s2_split_rows_auto<false>, grid, dim3(256), 0, st, X, ldx, rows, K, kp, rp, info,
+                         s2_budgets(), sigma, packed);
+  }
   return hipGetLastError();
 }
 
-hipError_t s2_split_cols_auto(const int32_t* info, const double* X, int64_t ldx, int64_t K, int64_t cols,
+hipError_t s2_split_cols_auto(const int32_t* info, bool cplx, const double* X, int64_t ldx, int64_t K, int64_t cols,
                               int32_t* tau, int8_t* packed, hipStream_t st) {
   const int64_t cp = round_up(cols, OZK_ROW_ALIGN), kp = round_up(K, OZK_K_CHUNK);
-  if (cols > 0)
-    hipLaunchKernelGGL(k_s2_col_scales_auto, dim3((unsigned)((cols + 31) / 32)), dim3(256), 0, st, X, ldx, K, cols,
-                       info, s2_budgets(), tau);
-  if (cp > 0 && kp > 0)
-    hipLaunchKernelGGL(k_s2_split_cols_auto, dim3((unsigned)(cp / S2_COL_BLOCK), (unsigned)(kp / OZK_K_CHUNK)), dim3(256),
-                       0, st, X, ldx, K, cols, kp, cp, info, tau, packed);
+  if (cols > 0) {
+    const dim3 grid((unsigned)((cols + 31) / 32));
+    if (cplx)
+      hipLaunchKernelGGL(k_s2_col_scales_auto<true>, grid, dim3(256), 0, st, X, ldx, K, cols, info, s2_budgets(), tau);
+    else
+      hipLaunchKernelGGL(k_s2_col_scales_auto<false>, grid, dim3(256), 0, st, X, ldx, K, cols, info, s2_budgets(),
+                         tau);
+  }
+  if (cp > 0 && kp > 0) {
+    const dim3 grid((unsigned)(cp / S2_COL_BLOCK), (unsigned)(kp / OZK_K_CHUNK));
+    if (cplx)
+      hipLaunchKernelGGL(k_s2_split_cols_auto<true>, grid, dim3(256), 0, st, X, ldx, K, cols, kp, cp, info, tau,
+                         packed);
+    else
+      hipLaunchKernelGGL(k_s2_split_cols_auto<false>, grid, dim3(256), 0, st, X, ldx, K, cols, kp, cp, info, tau,
+                         packed);
+  }
   return hipGetLastError();
 }
 
-hipError_t s2_gemm_mod_auto(const int32_t* info, int64_t M, int64_t N, int64_t K, const int8_t* Ap,
-                            const int8_t* Bp, int8_t* out, hipStream_t st) {
-  if (M == 0 || N == 0) return hipSuccess;
-  using Cfg = S2Cfg<false, 0>;
+template <bool CPLX>
+static hipError_t launch_gemm_mod_auto(const int32_t* info, int64_t M, int64_t N, int64_t K, const int8_t* Ap,
+                                       const int8_t* Bp, int8_t* out, hipStream_t st) {
+  using Cfg = S2Cfg<CPLX, 0>;
   using T = GemmTile<Cfg::P, Cfg::TM, Cfg::TN, Cfg::NS>;
   static bool attr = false;
   if (!attr) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_s2_gemm_mod_auto),
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_s2_gemm_mod_auto<CPLX>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, Cfg::LDS_BYTES);
     if (e != hipSuccess) return e;
     attr = true;
@@ -1315,17 +1424,30 @@ hipError_t s2_gemm_mod_auto(const int32_t* info, int64_t M, int64_t N, int64_t K
   const int64_t ra = round_up(M, OZK_ROW_ALIGN), rb = round_up(N, OZK_ROW_ALIGN);
   const int64_t tiles = ((M + T::BM - 1) / T::BM) * ((N + T::BN - 1) / T::BN);
   const dim3 grid((unsigned)tiles, 1, (unsigned)OZK_MAX_S);
-  hipLaunchKernelGGL(k_s2_gemm_mod_auto, grid, dim3(256), Cfg::LDS_BYTES, st, Ap, Bp, ra * kp, rb * kp, ra, rb,
-                     kp / OZK_K_CHUNK, (int)M, (int)N, info, out);
+  hipLaunchKernelGGL(k_s2_gemm_mod_auto<CPLX>, grid, dim3(256), Cfg::LDS_BYTES, st, Ap, Bp, ra * kp * Cfg::P,
+                     rb * kp * Cfg::P, ra, rb, kp / OZK_K_CHUNK, (int)M, (int)N, info, out);
   return hipGetLastError();
 }
 
-hipError_t s2_crt_auto(const int32_t* info, int64_t M, int64_t N, const int8_t* res, const int32_t* sigma,
-                       const int32_t* tau, double alpha, double beta, double* C, int64_t ldc, hipStream_t st) {
+hipError_t s2_gemm_mod_auto(const int32_t* info, bool cplx, int64_t M, int64_t N, int64_t K, const int8_t* Ap,
+                            const int8_t* Bp, int8_t* out, hipStream_t st) {
+  if (M == 0 || N == 0) return hipSuccess;
+  return cplx ? launch_gemm_mod_auto<true>(info, M, N, K, Ap, Bp, out, st)
+              : launch_gemm_mod_auto<false>(info, M, N, K, Ap, Bp, out, st);
+}
+
+hipError_t s2_crt_auto(const int32_t* info, bool cplx, int64_t M, int64_t N, const int8_t* res, const int32_t* sigma,
+                       const int32_t* tau, const double* alpha, const double* beta, double* C, int64_t ldc,
+                       hipStream_t st) {
   const int64_t n = M * N;
-  if (n > 0)
-    hipLaunchKernelGGL(k_s2_crt_auto, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, (int)M, (int)N, res,
-                       sigma, tau, info, alpha, beta, C, ldc);
+  if (n <= 0) return hipSuccess;
+  const dim3 grid((unsigned)((n + 255) / 256));
+  if (cplx)
+    hipLaunchKernelGGL(k_s2_crt_auto<true>, grid, dim3(256), 0, st, (int)M, (int)N, res, sigma, tau, info, alpha[0],
+                       alpha[1], beta[0], beta[1], C, ldc);
+  else
+    hipLaunchKernelGGL(k_s2_crt_auto<false>, grid, dim3(256), 0, st, (int)M, (int)N, res, sigma, tau, info, alpha[0],
+                       0.0, beta[0], 0.0, C, ldc);
   return hipGetLastError();
 }
 

@@ -1,20 +1,24 @@
-// Learned slice-count selector for Scheme I and the tools it is trained with.
+// Learned slice / modulus count selector and the tools it is trained with.
 //
 // The paper's implementation has no automatic precision selection (it names
 // the runtime estimate of the slice count as missing, Sec. VI).  Here a small
-// MLP predicts the smallest p meeting a tolerance from exponent statistics
-// gathered in the pre-pass, on the device, so that the emulated GEMM stays a
+// MLP predicts the smallest Scheme I slice count p and the smallest Scheme II
+// modulus count s meeting a tolerance from exponent statistics gathered in
+// the pre-pass, on the device, so that the emulated GEMM stays a
 // stream-ordered, graph-capturable sequence:
 //
 //   k_sel_rows / k_sel_cols_*  row / column exponents (also the Scheme I scales)
 //                            and histograms of the exponent deficits
 //                            e_i - expo(a_ik) over 16 bins, plus the largest
 //                            deficit (for the a-priori bound)
-//   k_sel_infer              features -> MLP 34 -> 64 -> 64 -> 8 (ReLU) ->
-//                            ordinal decision p = 1 + #{t : sigmoid(z_t) > thr}
-//                            + margin; the a-priori bound p_b; p = min(p, p_b),
-//                            or p_b when the features are outside the training
-//                            range; written to device memory
+//   k_sel_infer              features -> MLP 34 -> 64 -> 64 -> 28 (ReLU) ->
+//                            ordinal counts p_net = 1 + #{t : sigmoid(z_t) >
+//                            thr_t} + margin over the 8 heads "p > t", s_net
+//                            likewise over the 20 heads "s > t"; the a-priori
+//                            bounds p_b, s_b; p = min(p_net, p_b) and s =
+//                            min(s_net, s_b), or the bounds alone when the
+//                            features are outside the training range; written
+//                            to device memory
 //   k_mlp_forward / k_mlp_grad / k_mlp_adam   training kernels (FP32)
 //   k_ref_dd                 double-double dot products of chosen outputs
 //                            (labels and accuracy measurement)
@@ -23,10 +27,11 @@
 
 namespace ozk {
 
-constexpr int SEL_BINS = 16, SEL_FEAT = 34, SEL_H = 64, SEL_OUT = 8;
+constexpr int SEL_BINS = 16, SEL_FEAT = 34, SEL_H = 64, SEL_PH = 8, SEL_SH = 20, SEL_OUT = SEL_PH + SEL_SH;
+static_assert(SEL_OUT == OZK_SELECTOR_HEADS, "head count");
 constexpr int OFF_W1 = 0, OFF_B1 = OFF_W1 + SEL_FEAT * SEL_H, OFF_W2 = OFF_B1 + SEL_H,
               OFF_B2 = OFF_W2 + SEL_H * SEL_H, OFF_W3 = OFF_B2 + SEL_H, OFF_B3 = OFF_W3 + SEL_H * SEL_OUT,
-              SEL_NPARAM = OFF_B3 + SEL_OUT;  // 6920
+              SEL_NPARAM = OFF_B3 + SEL_OUT;  // 8220
 static_assert(SEL_NPARAM == OZK_SELECTOR_PARAMS, "parameter count");
 
 // bins: [0] [1] [2] [3] [4,6) [6,8) [8,12) [12,16) [16,24) [24,32) [32,48)
@@ -207,7 +212,7 @@ __device__ __forceinline__ double s2_bound(int ta, int tb, int ra, int rb, int64
 
 struct SelInfer {
   const float* w;  // device parameters, null = no network (bound only)
-  float threshold;
+  float thr[SEL_OUT];  // per-head decision thresholds
   int margin;
   double tol;
   int64_t K;
@@ -218,7 +223,7 @@ struct SelInfer {
 // the network (0 if none), [2] p from the bound (9 = none up to 8), [3] 1 when
 // the features were outside the training range, [4] scheme (1 or 2),
 // [5] Scheme II modulus count used (0 with Scheme I), [6] s from the Scheme II
-// bound (21 = none up to 20), [7] 0.
+// bound (21 = none up to 20), [7] s from the network (0 if none).
 __global__ __launch_bounds__(64) void k_sel_infer(const int32_t* __restrict__ cnt, SelInfer si,
                                                   int32_t* __restrict__ out, float* __restrict__ feat_out) {
   __shared__ float x[SEL_FEAT], h1[SEL_H], h2[SEL_H], z[SEL_OUT];
@@ -240,7 +245,7 @@ __global__ __launch_bounds__(64) void k_sel_infer(const int32_t* __restrict__ cn
   }
   __syncthreads();
   if (feat_out && t < SEL_FEAT) feat_out[t] = x[t];
-  int p_net = 0;
+  int p_net = 0, s_net = 0;
   if (si.w) {
     float a = si.w[OFF_B1 + t];
     for (int i = 0; i < SEL_FEAT; ++i) a += si.w[OFF_W1 + i * SEL_H + t] * x[i];
@@ -256,10 +261,13 @@ __global__ __launch_bounds__(64) void k_sel_infer(const int32_t* __restrict__ cn
       z[t] = a;
     }
     __syncthreads();
-    int c = 0;
-    for (int i = 0; i < SEL_OUT; ++i) c += (1.f / (1.f + expf(-z[i]))) > si.threshold ? 1 : 0;
-    p_net = 1 + c + si.margin;
+    int cp = 0, cs = 0;
+    for (int i = 0; i < SEL_PH; ++i) cp += (1.f / (1.f + expf(-z[i]))) > si.thr[i] ? 1 : 0;
+    for (int i = SEL_PH; i < SEL_OUT; ++i) cs += (1.f / (1.f + expf(-z[i]))) > si.thr[i] ? 1 : 0;
+    p_net = 1 + cp + si.margin;
     p_net = p_net > 9 ? 9 : p_net;
+    s_net = 1 + cs + si.margin;
+    s_net = s_net > OZK_MAX_S + 1 ? OZK_MAX_S + 1 : s_net;
   }
   if (t == 0) {
     int pb = 9;
@@ -279,8 +287,10 @@ __global__ __launch_bounds__(64) void k_sel_infer(const int32_t* __restrict__ cn
         sb = q;
         break;
       }
-    // Scheme I while p <= 8 meets the tolerance; otherwise Scheme II at the
-    // bound's s (s = 20, the most accurate, when no count is proven enough)
+    int sc = sb;
+    if (si.w && !ood) sc = s_net < sb ? s_net : sb;
+    // Scheme I while p <= 8 meets the tolerance; otherwise Scheme II at
+    // min(s_net, s_bound) (s = 20, the most accurate, when nothing is proven)
     const bool s1 = p <= OZK_MAX_P;
     p = p < 1 ? 1 : (p > OZK_MAX_P ? OZK_MAX_P : p);
     out[0] = s1 ? p : 0;
@@ -288,10 +298,99 @@ __global__ __launch_bounds__(64) void k_sel_infer(const int32_t* __restrict__ cn
     out[2] = pb;
     out[3] = ood ? 1 : 0;
     out[4] = s1 ? 1 : 2;
-    out[5] = s1 ? 0 : (sb <= OZK_MAX_S ? sb : OZK_MAX_S);
+    out[5] = s1 ? 0 : (sc <= OZK_MAX_S ? (sc < 1 ? 1 : sc) : OZK_MAX_S);
     out[6] = sb;
-    out[7] = 0;
+    out[7] = s_net;
   }
+}
+
+// ----------------------------------------- automatic complex product (3M)
+//
+// The largest exponent deficit of a nonzero real or imaginary part below
+// the largest part exponent of its row of A (column of B); rows and columns
+// holding a non-finite part are skipped (their outputs are NaN whatever s).
+
+// One wave per row of complex A (its 2K parts are contiguous).
+__global__ __launch_bounds__(256) void k_zsel_rows(const double* __restrict__ X, int64_t ldx, int64_t rows,
+                                                   int64_t K, int32_t* __restrict__ cnt) {
+  const int lane = threadIdx.x & 63;
+  const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (r >= rows) return;  // wave-uniform
+  const double* xr = X + 2 * r * ldx;
+  const int64_t n = 2 * K;
+  int e = OZK_EXP_ZERO;
+  for (int64_t k = lane; k < n; k += 64) {
+    const int ek = expo_of(xr[k]);
+    e = ek > e ? ek : e;
+  }
+  e = wave_max(e);
+  if (e == OZK_EXP_ZERO || e == OZK_EXP_NONFINITE) return;
+  int dmax = 0;
+  for (int64_t k = lane; k < n; k += 64) {
+    const int ek = expo_of(xr[k]);
+    if (ek != OZK_EXP_ZERO && e - ek > dmax) dmax = e - ek;
+  }
+  dmax = wave_max(dmax);
+  if (lane == 0 && dmax) atomicMax(&cnt[32], dmax);
+}
+
+// Column maxima of the part exponents of complex B, split over K.
+__global__ __launch_bounds__(256) void k_zsel_cols_emax(const double* __restrict__ X, int64_t ldx, int64_t K,
+                                                        int64_t cols, int32_t* __restrict__ f) {
+  const int64_t j = (int64_t)blockIdx.x * 64 + (threadIdx.x & 63);
+  if (j >= cols) return;
+  const int64_t k0 = (int64_t)blockIdx.y * SEL_COL_KB, k1 = k0 + SEL_COL_KB < K ? k0 + SEL_COL_KB : K;
+  int e = OZK_EXP_ZERO;
+  for (int64_t k = k0 + (threadIdx.x >> 6); k < k1; k += 4) {
+    const double* z = X + 2 * (k * ldx + j);
+    const int a = expo_of(z[0]), b = expo_of(z[1]);
+    e = a > e ? a : e;
+    e = b > e ? b : e;
+  }
+  if (e != OZK_EXP_ZERO) atomicMax(&f[j], e);
+}
+
+__global__ __launch_bounds__(256) void k_zsel_cols_dmax(const double* __restrict__ X, int64_t ldx, int64_t K,
+                                                        int64_t cols, const int32_t* __restrict__ f,
+                                                        int32_t* __restrict__ cnt) {
+  const int64_t j = (int64_t)blockIdx.x * 64 + (threadIdx.x & 63);
+  const int emax = j < cols ? f[j] : OZK_EXP_ZERO;
+  int dmax = 0;
+  if (j < cols && emax != OZK_EXP_ZERO && emax != OZK_EXP_NONFINITE) {
+    const int64_t k0 = (int64_t)blockIdx.y * SEL_COL_KB, k1 = k0 + SEL_COL_KB < K ? k0 + SEL_COL_KB : K;
+    for (int64_t k = k0 + (threadIdx.x >> 6); k < k1; k += 4) {
+      const double* z = X + 2 * (k * ldx + j);
+      const int a = expo_of(z[0]), b = expo_of(z[1]);
+      if (a != OZK_EXP_ZERO && emax - a > dmax) dmax = emax - a;
+      if (b != OZK_EXP_ZERO && emax - b > dmax) dmax = emax - b;
+    }
+  }
+  dmax = wave_max(dmax);
+  if ((threadIdx.x & 63) == 0 && dmax) atomicMax(&cnt[33], dmax);
+}
+
+// The decision of the automatic ZGEMM: Scheme II (3M) at the smallest s
+// whose a-priori bound meets tol, with the deficits one more than the part
+// deficits (the scales are taken from |re| + |im| < 2^(max(expo re, expo
+// im) + 1)); s = 20 when none is proven.  info as k_sel_infer writes it,
+// with no network: [1] 0, [2] 9, [7] 0.
+__global__ void k_zsel_decide(const int32_t* __restrict__ cnt, double tol, int64_t K, S2Budgets bud,
+                              int32_t* __restrict__ out) {
+  if (threadIdx.x != 0) return;
+  int sb = OZK_MAX_S + 1;
+  for (int q = 1; q <= OZK_MAX_S; ++q)
+    if (s2_bound(bud.ta[q], bud.tb[q], cnt[32] + 1, cnt[33] + 1, K) <= tol) {
+      sb = q;
+      break;
+    }
+  out[0] = 0;
+  out[1] = 0;
+  out[2] = 9;
+  out[3] = 0;
+  out[4] = 2;
+  out[5] = sb <= OZK_MAX_S ? sb : OZK_MAX_S;
+  out[6] = sb;
+  out[7] = 0;
 }
 
 // ------------------------------------------------------------- training
@@ -329,7 +428,7 @@ __global__ __launch_bounds__(64) void k_mlp_forward(const float* __restrict__ w,
   if (threadIdx.x < SEL_OUT) logits[(int64_t)s * SEL_OUT + threadIdx.x] = out[threadIdx.x];
 }
 
-// Gradient of the mean binary cross-entropy over samples and the 8 ordinal
+// Gradient of the mean binary cross-entropy over samples and the 28 ordinal
 // heads, accumulated into grad (zeroed beforehand); loss sum into *loss.
 __global__ __launch_bounds__(64) void k_mlp_grad(const float* __restrict__ w, const float* __restrict__ X,
                                                  const float* __restrict__ Y, int n, float* __restrict__ grad,
@@ -441,10 +540,35 @@ hipError_t sel_features(const double* A, int64_t lda, int64_t M, const double* B
   return hipGetLastError();
 }
 
-hipError_t sel_infer(const int32_t* cnt, const float* w, float threshold, int margin, double tol, int64_t K,
+hipError_t sel_infer(const int32_t* cnt, const float* w, const float* thresholds, int margin, double tol, int64_t K,
                      int32_t* info, float* feat, hipStream_t st) {
-  SelInfer si{w, threshold, margin, tol, K, s2_budgets()};
+  SelInfer si;
+  si.w = w;
+  for (int i = 0; i < SEL_OUT; ++i) si.thr[i] = thresholds ? thresholds[i] : 0.5f;
+  si.margin = margin;
+  si.tol = tol;
+  si.K = K;
+  si.bud = s2_budgets();
   hipLaunchKernelGGL(k_sel_infer, dim3(1), dim3(64), 0, st, cnt, si, info, feat);
+  return hipGetLastError();
+}
+
+hipError_t zsel_features(const double* A, int64_t lda, int64_t M, const double* B, int64_t ldb, int64_t N, int64_t K,
+                         int32_t* f_scratch, int32_t* cnt, hipStream_t st) {
+  hipLaunchKernelGGL(k_sel_zero, dim3(1), dim3(64), 0, st, cnt);
+  if (M > 0 && K > 0) hipLaunchKernelGGL(k_zsel_rows, dim3((unsigned)((M + 3) / 4)), dim3(256), 0, st, A, lda, M, K, cnt);
+  if (N > 0 && K > 0) {
+    hipLaunchKernelGGL(k_sel_fill, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st, f_scratch, N,
+                       (int32_t)OZK_EXP_ZERO);
+    const dim3 g((unsigned)((N + 63) / 64), (unsigned)((K + SEL_COL_KB - 1) / SEL_COL_KB));
+    hipLaunchKernelGGL(k_zsel_cols_emax, g, dim3(256), 0, st, B, ldb, K, N, f_scratch);
+    hipLaunchKernelGGL(k_zsel_cols_dmax, g, dim3(256), 0, st, B, ldb, K, N, f_scratch, cnt);
+  }
+  return hipGetLastError();
+}
+
+hipError_t zsel_decide(const int32_t* cnt, double tol, int64_t K, int32_t* info, hipStream_t st) {
+  hipLaunchKernelGGL(k_zsel_decide, dim3(1), dim3(64), 0, st, cnt, tol, K, s2_budgets(), info);
   return hipGetLastError();
 }
 

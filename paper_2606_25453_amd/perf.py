@@ -12,6 +12,9 @@ events on the launch stream, after untimed warm-up calls and tuning):
 * Scheme II 3M ZGEMM 4096^3 and 8192^3, s = 16;
 * Scheme I DGEMM fused against the unfused baseline (one GEMM per slice
   pair, INT32 planes through HBM), p = 7 at 4096^3 and 8192^3;
+* Scheme II DGEMM (s = 14) and 3M ZGEMM (s = 16) fused against their
+  unfused baselines (one GEMM per modular product, INT32 planes), 4096^3;
+* Scheme I ZGEMM by 4M, p = 7, 4096^3 and 8192^3;
 * Scheme II DGEMM with the CRT fused into the GEMM against the separate
   kernels, 4096^3 at s = 14 and 8192 x 8192 x 2048 at s = 16;
 * a batch of 256 ZGEMMs with M, N, K log-uniform in [64, 1024], s = 16, one
@@ -136,6 +139,70 @@ def unfused(torch, ctx, n, p, reps):
             "tflops_unfused": round(2.0 * n ** 3 / ms_unf / 1e9, 3), "bit_identical": bool(torch.equal(C, ref)),
             "model_bytes_fused": p * 2 * n * n + 8 * n * n,
             "model_bytes_unfused": pairs * 2 * n * n + 8 * pairs * n * n + 8 * n * n}
+
+
+def embed4m(torch, A, B):
+    """The real matrices whose product holds the 4M complex product (the
+    layout ozk_zgemm uses for Scheme I): A viewed as M x 2K reals, and the
+    2K x 2N matrix with rows 2k = (Re b, Im b), 2k+1 = (-Im b, Re b).  Used
+    only to tune the GEMM step's size class on the embedded shape."""
+    M, K = A.shape
+    N = B.shape[1]
+    A2 = torch.view_as_real(A).reshape(M, 2 * K)
+    Br, Bi = B.real, B.imag
+    B2 = torch.stack([torch.stack([Br, Bi], dim=2), torch.stack([-Bi, Br], dim=2)], dim=1).reshape(2 * K, 2 * N)
+    return A2.contiguous(), B2.contiguous()
+
+
+def zgemm4m(torch, ctx, n, p, reps):
+    """Scheme I ZGEMM by 4M (4 p(p+1) MNK INT8 operations) against native
+    complex128 torch.matmul and the Scheme II 3M call at s = 16."""
+    A = device_phi(torch, n, n, 1.0, 61, True)
+    B = device_phi(torch, n, n, 1.0, 62, True)
+    A2, B2 = embed4m(torch, A, B)
+    _, cfg, gemm_ms = ozk.ozk_tune(ctx, ozk.OZK_OP_DGEMM, ozk.OZK_SCHEME1, p, A2, B2, reps=2)
+    del A2, B2
+    torch.cuda.empty_cache()
+    C = torch.empty((n, n), dtype=torch.complex128, device="cuda:0")
+    ws = torch.empty(ozk.ozk_workspace_size(ctx, ozk.OZK_OP_ZGEMM, ozk.OZK_SCHEME1, n, n, n, p), dtype=torch.uint8,
+                     device="cuda:0")
+    ms = time_call(torch, lambda: ozk.ozk_zgemm(ctx, ozk.OZK_SCHEME1, p, A, B, C, ws=ws), reps)
+    ms_nat = time_call(torch, lambda: torch.matmul(A, B, out=C), reps)
+    flops = 8.0 * n ** 3
+    ops = 4 * p * (p + 1) * n ** 3
+    return {"path": "scheme1_zgemm_4m", "M": n, "N": n, "K": n, "p": p, "config": cfg, "ms": round(ms, 4),
+            "tflops": round(flops / ms / 1e9, 3), "gemm_ms": round(gemm_ms, 4), "int8_ops": ops,
+            "gemm_frac_int8_peak": round(ops / gemm_ms / 1e9 / INT8_PEAK_TOPS, 4),
+            "native_tflops": round(flops / ms_nat / 1e9, 3)}
+
+
+def s2_unfused(torch, ctx, n, s, cplx, reps):
+    """The fused Scheme II (or 3M) call against the unfused baseline (INT32
+    planes through HBM; the paper's Eq. 14 against Eq. 15, Eq. 17 against
+    Eq. 18)."""
+    A = device_phi(torch, n, n, 1.0, 51, cplx)
+    B = device_phi(torch, n, n, 1.0, 52, cplx)
+    op = ozk.OZK_OP_ZGEMM if cplx else ozk.OZK_OP_DGEMM
+    C = torch.empty((n, n), dtype=A.dtype, device="cuda:0")
+    _, cfg, _ = ozk.ozk_tune(ctx, op, ozk.OZK_SCHEME2, s, A, B, C=C, reps=2)
+    ws = torch.empty(ozk.ozk_workspace_size(ctx, op, ozk.OZK_SCHEME2, n, n, n, s), dtype=torch.uint8, device="cuda:0")
+    if cplx:
+        ms_fused = time_call(torch, lambda: ozk.ozk_zgemm_3m(ctx, s, A, B, C, ws=ws), reps)
+    else:
+        ms_fused = time_call(torch, lambda: ozk.ozk_dgemm(ctx, ozk.OZK_SCHEME2, s, A, B, C, ws=ws), reps)
+    ref = C.clone()
+    del ws
+    wsu = torch.empty(ozk.ozk_s2_unfused_workspace_size(ctx, s, int(cplx), n, n, n), dtype=torch.uint8,
+                      device="cuda:0")
+    ms_unf = time_call(torch, lambda: ozk.ozk_s2_gemm_unfused(ctx, s, A, B, C, ws=wsu), reps)
+    q = 3 if cplx else 1
+    flops = (8.0 if cplx else 2.0) * n ** 3
+    return {"path": "scheme2_3m_fused_vs_unfused" if cplx else "scheme2_fused_vs_unfused", "M": n, "N": n, "K": n,
+            "s": s, "ms_fused": round(ms_fused, 4), "tflops_fused": round(flops / ms_fused / 1e9, 3),
+            "ms_unfused": round(ms_unf, 4), "tflops_unfused": round(flops / ms_unf / 1e9, 3),
+            "bit_identical": bool(torch.equal(C, ref)),
+            "model_bytes_fused": s * (q * 2 * n * n + (2 if cplx else 1) * n * n),
+            "model_bytes_unfused": s * (q * 2 * n * n + 8 * q * n * n + (2 if cplx else 1) * n * n)}
 
 
 def scheme2_f32(torch, ctx, n, s, cplx, reps):
@@ -287,7 +354,7 @@ def main():
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--out", default=None, help="also append the lines to this file")
     ap.add_argument("--only", default=None,
-                    help="comma-separated subset of s1, sgemm, unfused, s2, s2f32, fused, batch, auto")
+                    help="comma-separated subset of s1, sgemm, unfused, s2, s2f32, fused, s2unf, z4m, batch, auto")
     ap.add_argument("--sweep", action="store_true", help="the size sweeps instead of the default workloads")
     args = ap.parse_args()
     import torch
@@ -297,7 +364,12 @@ def main():
         sweep(torch, ctx, args)
         ctx.close()
         return
-    actx = ozk.Context(0, selector="default")
+    try:
+        actx = ozk.Context(0, selector="default")
+        net = True
+    except ValueError:  # shipped parameters of another network shape: the bounds decide
+        actx = ozk.Context(0)
+        net = False
     jobs = [("s1", 4096, p) for p in (6, 7, 8)]
     jobs += [("s2", 4096, 4096, 4096, s, False) for s in (14, 16)]
     jobs += [("s2", 8192, 8192, 2048, s, False) for s in (14, 16)]
@@ -306,14 +378,17 @@ def main():
     jobs += [("sgemm", 4096, p) for p in (2, 3, 4)]
     jobs += [("s2f32", 4096, s, False) for s in (8, 10)] + [("s2f32", 4096, 8, True)]
     jobs += [("unfused", 4096, 7)]
+    jobs += [("s2unf", 4096, 14, False), ("s2unf", 4096, 16, True)]
+    jobs += [("z4m", 4096, 7)]
     jobs += [("batch", 256, 16)]
     jobs += [("auto", 4096, 1e-13)]
     if not args.quick:
-        jobs += [("auto", 8192, 1e-13)]
+        jobs += [("auto", 8192, 1e-13), ("auto", 8192, 1e-10)]
         jobs += [("s1", 8192, p) for p in (6, 7, 8)]
         jobs += [("sgemm", 8192, p) for p in (2, 3, 4)]
         jobs += [("unfused", 8192, 7)]
         jobs += [("s2", 8192, 8192, 8192, 16, True)]
+        jobs += [("z4m", 8192, 7)]
     if args.only:
         keep = set(args.only.split(","))
         jobs = [j for j in jobs if j[0] in keep]
@@ -325,6 +400,7 @@ def main():
             r = scheme2(torch, ctx, job[1], job[2], job[3], job[4], job[5], args.reps)
         elif job[0] == "auto":
             r = auto(torch, actx, job[1], job[2], args.reps)
+            r["network"] = net
         elif job[0] == "fused":
             r = fused_crt(torch, ctx, job[1], job[2], job[3], job[4], args.reps)
         elif job[0] == "sgemm":
@@ -333,6 +409,10 @@ def main():
             r = unfused(torch, ctx, job[1], job[2], args.reps)
         elif job[0] == "s2f32":
             r = scheme2_f32(torch, ctx, job[1], job[2], job[3], args.reps)
+        elif job[0] == "z4m":
+            r = zgemm4m(torch, ctx, job[1], job[2], args.reps)
+        elif job[0] == "s2unf":
+            r = s2_unfused(torch, ctx, job[1], job[2], job[3], args.reps)
         else:
             r = batch(torch, ctx, job[1], job[2], args.reps)
         line = json.dumps(r)

@@ -129,6 +129,46 @@ def test_scheme2_bound_holds_on_oracle_errors():
                 assert bnd < err * 2.0 ** 20, (phi, s, err, bnd)
 
 
+def test_complex_scheme2_bound_holds_on_oracle_3m_errors():
+    """The 3M bound (part deficits plus one) is never below the complex E_cw
+    of the oracle's 3M product, including parts of very different size
+    within an entry and the re ~ im cancellation case, and with a narrow
+    exponent range it stays within 2^21 of the error above the rounding
+    floor; the part deficits on a hand-evaluated case."""
+    from oracle import scheme2 as s2
+    rng = np.random.default_rng(7)
+    cases = []
+    for phi, seed, K in ((0.5, 1, 40), (1.0, 2, 64), (2.5, 3, 23)):
+        cases.append((synth.complex_phi_matrix(10, K, phi, 50 + seed, 60 + seed),
+                      synth.complex_phi_matrix(K, 7, phi, 70 + seed, 80 + seed)))
+    X = rng.standard_normal((8, 30))
+    cases.append((X + 1j * X * (1 + 2.0 ** -30), synth.complex_phi_matrix(30, 6, 1.0, 90, 91)))
+    A = synth.complex_phi_matrix(9, 33, 0.5, 92, 93)
+    A.imag *= 2.0 ** -20  # imaginary parts far below the real parts of the same entries
+    cases.append((A, synth.complex_phi_matrix(33, 5, 0.5, 94, 95)))
+    for A, B in cases:
+        K = A.shape[1]
+        hi, lo = oracle.zgemm_dd(A, B)
+        ra, rb = sel.complex_max_deficits(A, B)
+        for s in (6, 8, 10, 12, 14, 16):
+            err = oracle.metrics.e_cw(s2.z3m_gemm(A, B, s), hi, lo, A, B)
+            bnd = sel.bound_s2(s, ra + 1, rb + 1, K)
+            assert err <= bnd, (s, err, bnd)
+            if A is cases[0][0] and err > 1e-14:
+                assert bnd < err * 2.0 ** 21, (s, err, bnd)
+    # parts 1, 0.25, 2^-10 in a row: deficits 0, 2, 10; a column of 1j and 0.5: 0, 1
+    Ah = np.array([[1 + 0.25j, 2.0 ** -10 * 1j], [0.0, 3.0]])
+    Bh = np.array([[1j, 0.0], [0.5, 0.0]])
+    assert sel.complex_max_deficits(Ah, Bh) == (10, 1)
+    A, B = cases[0]
+    prev = 0
+    for tol in (1e-4, 1e-8, 1e-12, 1e-15, 1e-17):
+        s = sel.s_bound_complex(A, B, tol)
+        assert s >= prev
+        prev = s
+    assert sel.s_bound_complex(A, B, 1e-17) == 21
+
+
 def test_s_bound_monotone_and_consistent():
     A = synth.phi_matrix(10, 50, 1.0, 1)
     B = synth.phi_matrix(50, 8, 1.0, 2)
@@ -146,11 +186,36 @@ def test_s_bound_monotone_and_consistent():
 
 
 def test_predict_and_targets():
-    y = sel.ordinal_targets(np.array([1, 3, 9]))
-    assert y.tolist()[0] == [0] * 8 and y.tolist()[1] == [1, 1, 0, 0, 0, 0, 0, 0] and y.tolist()[2] == [1] * 8
+    y = sel.ordinal_targets(np.array([1, 3, 9]), np.array([21, 1, 5]))
+    assert y.shape == (3, sel.N_OUT)
+    assert y[0, :8].tolist() == [0] * 8 and y[1, :8].tolist() == [1, 1, 0, 0, 0, 0, 0, 0] and y[2, :8].tolist() == [1] * 8
+    assert y[0, 8:].tolist() == [1] * 20 and y[1, 8:].tolist() == [0] * 20
+    assert y[2, 8:].tolist() == [1, 1, 1, 1] + [0] * 16  # s = 5: heads s > 1 .. s > 4
     logits = np.where(y > 0, 5.0, -5.0)
+    p, s = sel.predict(logits)
+    assert p.tolist() == [1, 3, 9] and s.tolist() == [21, 1, 5]
+    p, s = sel.predict(logits, margin=1)
+    assert p.tolist() == [2, 4, 9] and s.tolist() == [21, 2, 6]
+    # per-head thresholds: raising one head's threshold above its sigmoid drops exactly that head
+    thr = np.full(sel.N_OUT, 0.5)
+    thr[1] = 0.9999  # head "p > 2" of the second sample (sigmoid(5) = 0.9933) no longer counts
+    p, s = sel.predict(logits, thr)
+    assert p.tolist() == [1, 2, 8] and s.tolist() == [21, 1, 5]
     assert sel.predict_p(logits).tolist() == [1, 3, 9]
-    assert sel.predict_p(logits, margin=1).tolist() == [2, 4, 9]
+
+
+def test_decision_rule():
+    # in range with a network: the smaller of the network and the bound
+    assert sel.decide(5, 12, 7, 16, True) == (1, 5)
+    assert sel.decide(8, 12, 6, 16, True) == (1, 6)
+    # Scheme I infeasible: Scheme II at the smaller count
+    assert sel.decide(9, 12, 9, 16, True) == (2, 12)
+    assert sel.decide(9, 18, 9, 16, True) == (2, 16)
+    # out of range or no network: the bounds alone
+    assert sel.decide(3, 4, 7, 16, False) == (1, 7)
+    assert sel.decide(9, 4, 9, 16, True, have_net=False) == (2, 16)
+    # nothing proven: the most accurate Scheme II
+    assert sel.decide(9, 21, 9, 21, False) == (2, 20)
 
 
 def test_forward_on_a_hand_evaluated_network():

@@ -1,9 +1,11 @@
-"""The learned slice-count selector through the C ABI: the device exponent
-statistics and the a-priori bound equal the oracle's exactly, the training
-kernels (MLP forward, gradient, Adam) agree with the fp64 oracle to float32
-accuracy, ozk_dgemm_auto is bit-identical to ozk_dgemm at the slice count it
+"""The learned slice / modulus count selector through the C ABI: the device
+exponent statistics and the a-priori bounds equal the oracle's exactly, the
+network's decision follows the oracle's rule, the training kernels (MLP
+forward, gradient, Adam) agree with the fp64 oracle to float32 accuracy,
+ozk_dgemm_auto is bit-identical to ozk_dgemm at the scheme and count it
 chose, and with the shipped parameters it never misses the tolerance on fresh
-problems while using fewer slices than the bound alone."""
+problems (judged by the CPU oracle's double-double product) while using
+fewer slices and moduli than the bounds alone."""
 import ctypes
 import math
 import os
@@ -54,25 +56,29 @@ def select(ctx, A, B, tol):
     return host(e)[:M], host(f)[:N], host(cnt), host(info), host(feat)
 
 
-def check_decision(info, p_eff):
-    """Scheme I with p_eff slices when p_eff <= 8, else Scheme II at the
-    bound's modulus count (20 when none is proven enough)."""
+def check_decision(info, p_eff, s_eff=None):
+    """Scheme I with p_eff slices when p_eff <= 8, else Scheme II with s_eff
+    moduli (default: the bound's count; 20 when none is proven enough)."""
     if p_eff <= 8:
         assert info[4] == 1 and info[0] == max(p_eff, 1) and info[5] == 0, info.tolist()
     else:
-        assert info[4] == 2 and info[0] == 0 and info[5] == min(info[6], 20), info.tolist()
+        s_eff = info[6] if s_eff is None else s_eff
+        assert info[4] == 2 and info[0] == 0 and info[5] == min(s_eff, 20), info.tolist()
 
 
 def load_params(ctx, flat, threshold=0.5, margin=0):
     arr = (ctypes.c_float * len(flat))(*[float(x) for x in flat])
-    st = ozk.library().ozk_selector_load(ctx.handle, ctypes.cast(arr, ctypes.c_void_p), len(flat), threshold, margin)
+    thr = np.broadcast_to(np.asarray(threshold, np.float32), (ozk.OZK_SELECTOR_HEADS,))
+    tarr = (ctypes.c_float * ozk.OZK_SELECTOR_HEADS)(*[float(x) for x in thr])
+    st = ozk.library().ozk_selector_load(ctx.handle, ctypes.cast(arr, ctypes.c_void_p), len(flat),
+                                         ctypes.cast(tarr, ctypes.c_void_p), margin)
     ozk._check("ozk_selector_load", st, ctx)
 
 
 def oracle_params(flat):
     """Split the flat float32 parameter vector into the oracle's tuple."""
     flat = np.asarray(flat, np.float64)
-    shapes = [(34, 64), (64,), (64, 64), (64,), (64, 8), (8,)]
+    shapes = [(34, 64), (64,), (64, 64), (64,), (64, sel.N_OUT), (sel.N_OUT,)]
     out, o = [], 0
     for sh in shapes:
         n = int(np.prod(sh))
@@ -144,9 +150,9 @@ def test_out_of_range_uses_the_bound(ctx):
     B = synth.phi_matrix(16400, 3, 0.5, 12)
     ctx2 = ozk.Context(0)
     try:
-        load_params(ctx2, np.full(ozk.OZK_SELECTOR_PARAMS, 0.0, np.float32), 0.5, 0)  # p_net = 1 everywhere
+        load_params(ctx2, np.full(ozk.OZK_SELECTOR_PARAMS, 0.0, np.float32), 0.5, 0)  # p_net = s_net = 1
         _, _, _, info, _ = select(ctx2, dev(A), dev(B), 1e-10)
-        assert info[3] == 1 and info[1] == 1 and info[2] == sel.p_bound(A, B, 1e-10)
+        assert info[3] == 1 and info[1] == 1 and info[7] == 1 and info[2] == sel.p_bound(A, B, 1e-10)
         check_decision(info, info[2])
         A2, B2 = A[:, :1000].copy(), B[:1000].copy()
         _, _, _, info, _ = select(ctx2, dev(A2), dev(B2), 1e-10)
@@ -159,12 +165,15 @@ def test_out_of_range_uses_the_bound(ctx):
 
 
 def test_network_decision_matches_oracle(ctx):
+    """p_net, s_net and the (scheme, count) decision equal the oracle's rule
+    for a random network, scalar and per-head thresholds and a margin."""
     flat = random_flat(5, 0.4)
     ctx2 = ozk.Context(0)
+    per_head = np.linspace(0.2, 0.8, ozk.OZK_SELECTOR_HEADS).astype(np.float32)
     try:
-        for thr, margin in ((0.5, 0), (0.3, 1)):
+        for thr, margin in ((0.5, 0), (0.3, 1), (per_head, 0)):
             load_params(ctx2, flat, thr, margin)
-            for seed in range(6):
+            for seed in range(8):
                 A = synth.phi_matrix(50, 120, 0.5 * seed, 30 + seed)
                 B = synth.phi_matrix(120, 40, 0.5 * seed, 40 + seed)
                 tol = 10.0 ** -(6 + seed)
@@ -172,10 +181,12 @@ def test_network_decision_matches_oracle(ctx):
                 logits, _ = sel.mlp_forward(oracle_params(flat), feat.astype(np.float64).reshape(1, -1))
                 z = logits[0]
                 if np.min(np.abs(1.0 / (1.0 + np.exp(-z)) - thr)) < 1e-4:
-                    continue  # too close to the threshold to decide in float32
-                p_net = int(sel.predict_p(logits, thr, margin)[0])
-                assert info[1] == p_net
-                check_decision(info, info[2] if info[3] else min(p_net, info[2]))
+                    continue  # too close to a threshold to decide in float32
+                p_net, s_net = (int(v[0]) for v in sel.predict(logits, thr, margin))
+                assert info[1] == p_net and info[7] == s_net, (info.tolist(), p_net, s_net)
+                assert info[6] == sel.s_bound(A, B, tol)
+                scheme, count = sel.decide(p_net, s_net, int(info[2]), int(info[6]), not info[3])
+                assert info[4] == scheme and (info[0] if scheme == 1 else info[5]) == count, info.tolist()
     finally:
         ctx2.close()
 
@@ -184,7 +195,7 @@ def test_mlp_forward_matches_oracle(ctx):
     flat = random_flat(1)
     r = np.random.default_rng(2)
     X = r.random((300, 34)).astype(np.float32)
-    out = torch.empty((300, 8), dtype=torch.float32, device="cuda:0")
+    out = torch.empty((300, sel.N_OUT), dtype=torch.float32, device="cuda:0")
     w, x = dev(flat), dev(X)
     st = ozk.library().ozk_mlp_forward(ctx.handle, w.data_ptr(), x.data_ptr(), 300, out.data_ptr(),
                                        ozk._stream(None))
@@ -198,8 +209,7 @@ def test_mlp_grad_and_adam_match_oracle(ctx):
     r = np.random.default_rng(4)
     n = 257
     X = r.random((n, 34)).astype(np.float32)
-    labels = r.integers(1, 10, n)
-    Y = sel.ordinal_targets(labels).astype(np.float32)
+    Y = sel.ordinal_targets(r.integers(1, 10, n), r.integers(1, 22, n)).astype(np.float32)
     w, x, y = dev(flat), dev(X), dev(Y)
     g = torch.empty(ozk.OZK_SELECTOR_PARAMS, dtype=torch.float32, device="cuda:0")
     loss = torch.empty(1, dtype=torch.float32, device="cuda:0")
@@ -362,7 +372,14 @@ def test_dgemm_auto_graph_replay(ctx):
 def test_invalid_arguments(ctx):
     lib = ozk.library()
     bad = (ctypes.c_float * 3)(1.0, 2.0, 3.0)
-    assert lib.ozk_selector_load(ctx.handle, ctypes.cast(bad, ctypes.c_void_p), 3, 0.5, 0) == ozk.OZK_ERR_INVALID_ARG
+    thr = (ctypes.c_float * ozk.OZK_SELECTOR_HEADS)(*([0.5] * ozk.OZK_SELECTOR_HEADS))
+    assert lib.ozk_selector_load(ctx.handle, ctypes.cast(bad, ctypes.c_void_p), 3, ctypes.cast(thr, ctypes.c_void_p),
+                                 0) == ozk.OZK_ERR_INVALID_ARG
+    good = (ctypes.c_float * ozk.OZK_SELECTOR_PARAMS)()
+    thr[5] = 1.0  # thresholds must lie in (0, 1)
+    assert lib.ozk_selector_load(ctx.handle, ctypes.cast(good, ctypes.c_void_p), ozk.OZK_SELECTOR_PARAMS,
+                                 ctypes.cast(thr, ctypes.c_void_p), 0) == ozk.OZK_ERR_INVALID_ARG
+    assert lib.ozk_last_arg(ctx.handle) == 4
     A = dev(synth.phi_matrix(4, 4, 1.0, 1))
     i32 = torch.empty(64, dtype=torch.int32, device="cuda:0")
     for tol in (0.0, -1.0, 1.0, float("nan")):
@@ -377,33 +394,66 @@ def test_invalid_arguments(ctx):
 WEIGHTS = os.path.join(os.path.dirname(ozk.__file__), "selector_weights.json")
 
 
-@pytest.mark.skipif(not os.path.exists(WEIGHTS), reason="no trained selector parameters")
-def test_trained_selector_never_misses_the_tolerance(ctx):
-    """Fresh problems (seeds outside the training and calibration sets): the
-    chosen p always meets the tolerance (judged by the double-double
-    reference), so does Scheme II when the network sends a problem there at
-    a proven modulus count, and on average fewer slices are used than with
-    the bound alone."""
+def trained_meta():
     from paper_2606_25453_amd import selector as train
-    if "val_scheme2_needed" not in train.load()["meta"]:
-        pytest.skip("parameters calibrated before the Scheme II fallback; retrain")
+    if not os.path.exists(WEIGHTS):
+        return None
+    d = train.load()
+    return d if len(d.get("thresholds", ())) == ozk.OZK_SELECTOR_HEADS else None
+
+
+@pytest.mark.skipif(trained_meta() is None, reason="no trained parameters of this network shape")
+def test_trained_selector_never_misses_the_tolerance(ctx):
+    """Fresh problems from the training distribution (M, N in [256, 4096], K
+    in [256, 16384] log-uniform, phi_A, phi_B in [0, 4]; seeds outside the
+    training and calibration sets) at four tolerances: whenever the decision
+    is Scheme I, or Scheme II at a count the network or the bound chose below
+    the proven maximum, the result meets the tolerance -- judged by the CPU
+    oracle's double-double product on sampled outputs (an 24 x 24 block of
+    rows and columns, the per-row and per-column scales make them exactly the
+    full product's), and by the library's double-double kernel on every
+    output of the smaller problems.  On average fewer slices and moduli are
+    used than with the bounds alone."""
+    from oracle import metrics
+    from paper_2606_25453_amd import selector as train
     ctx2 = ozk.Context(0)
     try:
         train.install(ctx2)
         gen = torch.Generator(device="cuda:0").manual_seed(987654)
-        used, bound = [], []
-        for i in range(60):
-            M, N, K = (int(v) for v in synth.log_uniform_ints(3, 32, 600, 5000 + i))
-            phi_a, phi_b = 4.0 * (i % 7) / 6.0, 4.0 * ((i * 3) % 7) / 6.0
+        used_p, bound_p, used_s, bound_s = [], [], [], []
+        rng = np.random.default_rng(123457)
+        for i in range(40):
+            M, N = (int(v) for v in synth.log_uniform_ints(2, 256, 4096, 7000 + i))
+            K = int(synth.log_uniform_ints(1, 256, 16384, 8000 + i)[0])
+            phi_a, phi_b = (float(v) for v in rng.uniform(0.0, 4.0, 2))
             A, B = train.random_problem(gen, M, N, K, phi_a, phi_b, "cuda:0")
-            hi, lo, ab = train.dd_reference(ctx2, A, B)
+            rows = np.unique(np.concatenate([rng.integers(0, M, 22), [0, M - 1]]))
+            cols = np.unique(np.concatenate([rng.integers(0, N, 22), [0, N - 1]]))
+            r, c = torch.from_numpy(rows).cuda(), torch.from_numpy(cols).cuda()
+            As, Bs = A.index_select(0, r).cpu().numpy(), B.index_select(1, c).cpu().numpy()
+            hi, lo = oracle.gemm_dd(As, Bs)
+            full = train.dd_reference(ctx2, A, B) if M * N <= (1 << 21) else None
             for tol in (1e-6, 1e-9, 1e-12, 1e-14):
                 C, info = dgemm_auto(ctx2, tol, A, B)
-                err = train.e_cw(C, hi, lo, ab)
-                if info[4] == 1 or info[6] <= 20:  # Scheme I, or Scheme II at a proven s
-                    assert err <= tol, (i, M, N, K, phi_a, phi_b, tol, info.tolist(), err)
-                used.append(int(info[0]) if info[4] == 1 else 9)
-                bound.append(min(int(info[2]), 9))
-        assert np.mean(used) < np.mean(bound)
+                got = C.index_select(0, r).index_select(1, c).cpu().numpy()
+                err = metrics.e_cw(got, hi, lo, As, Bs)
+                err_full = train.e_cw(C, *full) if full is not None else 0.0
+                proven = info[4] == 1 or info[6] <= 20
+                case = (i, M, N, K, round(phi_a, 3), round(phi_b, 3), tol, info.tolist(), err, err_full)
+                if proven:
+                    assert err <= tol and err_full <= tol, case
+                if info[3] == 0:  # in range: the network took part
+                    used_p.append(int(info[0]) if info[4] == 1 else 9)
+                    bound_p.append(min(int(info[2]), 9))
+                    if info[4] == 2:
+                        used_s.append(int(info[5]))
+                        bound_s.append(min(int(info[6]), 20))
+            del A, B, C
+        assert np.mean(used_p) < np.mean(bound_p)
+        if used_s:
+            assert np.mean(used_s) <= np.mean(bound_s)
+        print("mean p (9 = Scheme II) %.2f against %.2f for the bound; mean s %.2f against %.2f (%d in Scheme II)"
+              % (np.mean(used_p), np.mean(bound_p), np.mean(used_s) if used_s else 0,
+                 np.mean(bound_s) if bound_s else 0, len(used_s)), flush=True)
     finally:
         ctx2.close()
