@@ -113,7 +113,20 @@ typedef enum {
 } ozk_status;
 
 typedef enum { OZK_SCHEME1 = 1, OZK_SCHEME2 = 2 } ozk_scheme;
-typedef enum { OZK_OP_DGEMM = 0, OZK_OP_ZGEMM = 1 } ozk_op;
+/* Element types of ozk_gemm_ex: binary64, binary32, and complex numbers of
+ * them (interleaved re, im). */
+typedef enum { OZK_F64 = 0, OZK_F32 = 1, OZK_C128 = 2, OZK_C64 = 3 } ozk_dtype;
+/* Storage of every matrix of an ozk_gemm_ex call. */
+typedef enum { OZK_ROW_MAJOR = 0, OZK_COL_MAJOR = 1 } ozk_layout;
+/* Operations.  The _BATCHED codes only key the tuned table's entries that
+ * choose the GEMM tile of a batched problem's size class (see
+ * ozk_batch_plan_create). */
+typedef enum {
+  OZK_OP_DGEMM = 0,
+  OZK_OP_ZGEMM = 1,
+  OZK_OP_DGEMM_BATCHED = 2,
+  OZK_OP_ZGEMM_BATCHED = 3
+} ozk_op;
 
 /* ---------------------------------------------------------------- context */
 
@@ -242,6 +255,40 @@ ozk_status ozk_dgemm_t(ozk_ctx* ctx, ozk_scheme scheme, int p_or_s, int trans_a,
                        int trans_b, int64_t M, int64_t N, int64_t K,
                        double alpha, const double* A, int64_t lda,
                        const double* B, int64_t ldb, double beta, double* C,
+                       int64_t ldc, void* ws, size_t ws_bytes,
+                       hipStream_t stream);
+
+/* The general form of the whole calls: C = alpha*op(A)*op(B) + beta*C for
+ * every element type, both storage orders and transposed operands (the
+ * paper's problem statement, Sec. II-B, with the BLAS options; non-square
+ * shapes are untested in the paper, Sec. V-G).  op(X) = X (trans = 0) or
+ * X^T (trans = 1; no conjugation), op(A) is M x K and op(B) K x N; A is
+ * stored M x K (trans_a = 0) or K x M, B is stored K x N (trans_b = 0) or
+ * N x K, C is M x N, all in `layout`, with leading dimensions in elements
+ * (complex elements for complex types) at least the length of a stored row
+ * (row-major) or column (column-major).  alpha, beta: HOST pointers to one
+ * value of the element's real type (F64, F32) or to {re, im} (C128, C64).
+ * A column-major problem is run as the row-major product C^T = op(B)^T
+ * op(A)^T of the same memory (the operands swap, each transposed exactly
+ * when the other one was), and a transposed operand is read by the other
+ * pre-pass kernel: each row of op(A) and each column of op(B) keeps its
+ * scale, the integer sums are the same, so results are bit-identical to
+ * ozk_dgemm / ozk_sgemm / ozk_zgemm / ozk_cgemm on the explicit row-major
+ * operands.  Schemes and counts as those calls; Scheme I complex (4M) takes
+ * no transposed operand (OZK_ERR_UNSUPPORTED, arg 4 or 5: its embedding is
+ * built from stored rows of op(A) and columns of op(B)).  Workspace:
+ * ozk_workspace_size(ctx, F64/F32 -> OZK_OP_DGEMM, C128/C64 -> OZK_OP_ZGEMM,
+ * scheme, M', N', K, p_or_s) with (M', N') = (M, N) for row-major and
+ * (N, M) for column-major storage.  Device pointers, caller-owned memory,
+ * asynchronous on `stream`.  Errors: OZK_ERR_INVALID_ARG with the argument
+ * index (2 dtype, 3 layout, 4-5 trans, 6 scheme, 8-10 sizes, 11 alpha,
+ * 12-15 A, B, 16 beta, 17-18 C), OZK_ERR_UNSUPPORTED (arg 7) for a count out
+ * of range, OZK_ERR_WORKSPACE (arg 19). */
+ozk_status ozk_gemm_ex(ozk_ctx* ctx, ozk_dtype dtype, ozk_layout layout,
+                       int trans_a, int trans_b, ozk_scheme scheme,
+                       int p_or_s, int64_t M, int64_t N, int64_t K,
+                       const void* alpha, const void* A, int64_t lda,
+                       const void* B, int64_t ldb, const void* beta, void* C,
                        int64_t ldc, void* ws, size_t ws_bytes,
                        hipStream_t stream);
 
@@ -576,8 +623,15 @@ typedef struct ozk_batch_plan ozk_batch_plan;
 /* Plan a batch of `count` uneven problems (descs is a HOST array; the
  * pointers inside are kept and used by every ozk_gemm_batched call).  This
  * is the only step that allocates: a small device table with the problem
- * list, per-step prefix sums of the work units and the order of the GEMM
- * work items (problems by decreasing K, so the longest items start first).
+ * list, per-step prefix sums of the work units and, for each of the two
+ * GEMM tiles, the order of its work items (problems by decreasing K, so the
+ * longest items start first).  Each problem's GEMM items take one of two
+ * tiles: 64 x 64 (several workgroups per CU hide the latency of short
+ * items) or 128 x 128 (fewer LDS bytes per MFMA).  The tile of a problem is
+ * the context table's entry for its size class under op
+ * OZK_OP_DGEMM_BATCHED / OZK_OP_ZGEMM_BATCHED (variant 0 small, 1 large;
+ * written by ozk_tune_batch, ozk_config_set or ozk_config_load), or, for a
+ * class without an entry, the large tile when M and N are both at least 256.
  * *ws_bytes receives the workspace every call needs.  Supported: Scheme II
  * real DGEMM (op OZK_OP_DGEMM) and 3M ZGEMM (op OZK_OP_ZGEMM), 1 <= s <= 20;
  * other combinations return OZK_ERR_UNSUPPORTED.  Not in the paper: its
@@ -595,6 +649,25 @@ ozk_status ozk_gemm_batched(ozk_ctx* ctx, const ozk_batch_plan* plan, void* ws,
                             size_t ws_bytes, hipStream_t stream);
 /* Free a plan (NULL accepted); work using it must have completed. */
 ozk_status ozk_batch_plan_destroy(ozk_batch_plan* plan);
+/* The tile of each problem of a plan: large[i] = 1 for 128 x 128, 0 for
+ * 64 x 64 (HOST array of count = the plan's problem count). */
+ozk_status ozk_batch_plan_tiles(const ozk_batch_plan* plan, int count,
+                                int32_t* large);
+/* Autotune a plan's tiles on its own problems (the paper tunes its kernel
+ * parameters, Sec. V-A; its problems are not batched): run the pre-pass,
+ * then, size class by size class in decreasing INT8 work, time the whole
+ * GEMM step (median of `reps` after one warm-up, HIP events) with the
+ * class's problems on the small and on the large tile, keep the faster
+ * (the classes already decided keep their choice), and store it in the
+ * context table (op OZK_OP_DGEMM_BATCHED / OZK_OP_ZGEMM_BATCHED, variant 0
+ * or 1, the time), where later plans of the context find it.  The plan is
+ * updated in place and the batch is computed with the chosen tiles.  Every
+ * tile computes the same integers, so results do not depend on the choice.
+ * Synchronises the stream (not graph-capturable).  Errors:
+ * OZK_ERR_INVALID_ARG (arg 2 plan, 5 reps outside 1..100),
+ * OZK_ERR_WORKSPACE (arg 3). */
+ozk_status ozk_tune_batch(ozk_ctx* ctx, ozk_batch_plan* plan, void* ws,
+                          size_t ws_bytes, int reps, hipStream_t stream);
 
 /* -------------------------------------------------------- autotuner */
 /* A GEMM configuration.  The paper picks its kernel parameters (M stacking,

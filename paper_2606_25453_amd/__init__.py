@@ -25,6 +25,10 @@ OZK_SCHEME1 = 1
 OZK_SCHEME2 = 2
 OZK_OP_DGEMM = 0
 OZK_OP_ZGEMM = 1
+OZK_OP_DGEMM_BATCHED = 2
+OZK_F64, OZK_F32, OZK_C128, OZK_C64 = 0, 1, 2, 3
+OZK_ROW_MAJOR, OZK_COL_MAJOR = 0, 1
+OZK_OP_ZGEMM_BATCHED = 3
 OZK_ROW_ALIGN = 256
 OZK_K_CHUNK = 32
 OZK_EXP_ZERO = -100000
@@ -57,7 +61,7 @@ class OzkGemmConfig(ctypes.Structure):
 EXPORTS = (
     "ozk_create", "ozk_destroy", "ozk_last_arg", "ozk_status_string", "ozk_version", "ozk_set_k_split",
     "ozk_s1_packed_bytes", "ozk_s2_packed_bytes", "ozk_s1_k_split", "ozk_workspace_size",
-    "ozk_get_flags", "ozk_zgemm", "ozk_cgemm", "ozk_zgemm_auto", "ozk_s2_unfused_workspace_size", "ozk_s2_gemm_unfused",
+    "ozk_gemm_ex", "ozk_get_flags", "ozk_zgemm", "ozk_cgemm", "ozk_zgemm_auto", "ozk_batch_plan_tiles", "ozk_tune_batch", "ozk_s2_unfused_workspace_size", "ozk_s2_gemm_unfused",
     "ozk_dgemm", "ozk_dgemm_noalloc", "ozk_dgemm_t", "ozk_sgemm", "ozk_zgemm_3m", "ozk_cgemm_3m", "ozk_s1_dgemm_unfused", "ozk_s1_unfused_workspace_size", "ozk_s1_split_rows", "ozk_s1_split_cols", "ozk_s1_gemm",
     "ozk_s1_diagonals", "ozk_s2_split_rows", "ozk_s2_split_cols", "ozk_s2_gemm_mod", "ozk_s2_crt",
     "ozk_selector_load", "ozk_select", "ozk_dgemm_auto", "ozk_mlp_forward", "ozk_mlp_grad", "ozk_mlp_adam",
@@ -99,6 +103,9 @@ def _lib() -> ctypes.CDLL:
         "ozk_workspace_size": (I, [P, I, I, I64, I64, I64, I, ctypes.POINTER(SZ)]),
         "ozk_dgemm": (I, [P, I, I, I64, I64, I64, D, P, I64, P, I64, D, P, I64, P, SZ, P]),
         "ozk_get_flags": (I, [P, P, ctypes.POINTER(ctypes.c_uint32)]),
+        "ozk_gemm_ex": (I, [P, I, I, I, I, I, I, I64, I64, I64, P, P, I64, P, I64, P, P, I64, P, SZ, P]),
+        "ozk_batch_plan_tiles": (I, [P, I, P]),
+        "ozk_tune_batch": (I, [P, P, P, SZ, I, P]),
         "ozk_zgemm_auto": (I, [P, D, I64, I64, I64, P, P, I64, P, I64, P, P, I64, P, SZ, P, P]),
         "ozk_zgemm": (I, [P, I, I, I64, I64, I64, P, P, I64, P, I64, P, P, I64, P, SZ, P]),
         "ozk_cgemm": (I, [P, I, I, I64, I64, I64, P, P, I64, P, I64, P, P, I64, P, SZ, P]),
@@ -419,6 +426,58 @@ def ozk_zgemm_3m(ctx: Context, s: int, A, B, C=None, alpha: complex = 1.0, beta:
     return C
 
 
+def _ld_any(t, col: bool) -> int:
+    """Leading dimension of a 2-D view stored row-major (unit column stride)
+    or column-major (unit row stride)."""
+    if not col:
+        return _ld(t)
+    if t.dim() == 2 and t.numel() == 0:
+        return max(t.shape[0], 1)
+    if t.dim() != 2 or (t.shape[0] > 1 and t.stride(0) != 1):
+        raise ValueError("expected a 2-D column-major view with unit row stride")
+    return max(t.stride(1), 1)
+
+
+def ozk_gemm_ex(ctx: Context, scheme: int, p_or_s: int, A, B, C=None, trans_a: bool = False, trans_b: bool = False,
+                alpha=1.0, beta=0.0, ws=None, stream=None):
+    """C = alpha*op(A)*op(B) + beta*C for float64, float32, complex128 or
+    complex64 CUDA tensors; the storage order is that of the tensors (all
+    row-major, e.g. contiguous, or all column-major, e.g. X.T of a
+    contiguous matrix); op(X) = X.T when its flag is set (A, B as stored).
+    Returns C (allocated column-major when the operands are and C is None)."""
+    import torch
+    kinds = {torch.float64: (OZK_F64, ctypes.c_double, False), torch.float32: (OZK_F32, ctypes.c_float, False),
+             torch.complex128: (OZK_C128, ctypes.c_double, True), torch.complex64: (OZK_C64, ctypes.c_float, True)}
+    if not isinstance(A, torch.Tensor) or A.dtype not in kinds:
+        raise ValueError("A must be a float64, float32, complex128 or complex64 tensor")
+    dt, real, cplx = kinds[A.dtype]
+    col = A.dim() == 2 and A.shape[0] > 1 and A.stride(0) == 1 and A.shape[1] > 1 and A.stride(1) != 1
+    _need(A, "A", A.dtype, ctx, dim=2)
+    _need(B, "B", A.dtype, ctx, dim=2)
+    M, K = (A.shape[1], A.shape[0]) if trans_a else A.shape
+    Kb, N = (B.shape[1], B.shape[0]) if trans_b else B.shape
+    if Kb != K:
+        raise ValueError("inner dimensions differ: A gives K = %d, B gives %d" % (K, Kb))
+    if C is None:
+        C = torch.empty((N, M), dtype=A.dtype, device=A.device).T if col else \
+            torch.empty((M, N), dtype=A.dtype, device=A.device)
+    _need(C, "C", A.dtype, ctx, shape=(M, N))
+    _ws(ws, ctx)
+    op = OZK_OP_ZGEMM if cplx else OZK_OP_DGEMM
+    if ws is None:
+        mm, nn = (N, M) if col else (M, N)
+        ws = _workspace(ozk_workspace_size(ctx, op, scheme, mm, nn, K, p_or_s), A.device)
+    vals = (complex(alpha).real, complex(alpha).imag, complex(beta).real, complex(beta).imag)
+    al = (real * 2)(vals[0], vals[1])
+    be = (real * 2)(vals[2], vals[3])
+    st = _lib().ozk_gemm_ex(ctx.handle, dt, OZK_COL_MAJOR if col else OZK_ROW_MAJOR, int(bool(trans_a)),
+                            int(bool(trans_b)), scheme, p_or_s, M, N, K, ctypes.cast(al, ctypes.c_void_p), _ptr(A),
+                            _ld_any(A, col), _ptr(B), _ld_any(B, col), ctypes.cast(be, ctypes.c_void_p), _ptr(C),
+                            _ld_any(C, col), _ptr(ws), ws.numel(), _stream(stream))
+    _check("ozk_gemm_ex", st, ctx)
+    return C
+
+
 def ozk_get_flags(ctx: Context, stream=None) -> int:
     """Wait for `stream`, then take (and clear) the context's condition flags."""
     out = ctypes.c_uint32()
@@ -728,6 +787,21 @@ class BatchPlan:
 
     def run(self, stream=None) -> None:
         ozk_gemm_batched(self.ctx, self.plan, self.ws, stream)
+
+    def tiles(self):
+        """1 for each problem on the 128 x 128 tile, 0 on 64 x 64."""
+        out = (ctypes.c_int32 * max(len(self.keep), 1))()
+        st = _lib().ozk_batch_plan_tiles(self.plan, len(self.keep), ctypes.cast(out, ctypes.c_void_p))
+        if st != OZK_OK:
+            raise OzkError("ozk_batch_plan_tiles", st, 0)
+        return [int(out[i]) for i in range(len(self.keep))]
+
+    def tune(self, reps: int = 3, stream=None) -> None:
+        """ozk_tune_batch: choose each size class's tile on these problems
+        (synchronises) and leave the batch computed."""
+        st = _lib().ozk_tune_batch(self.ctx.handle, self.plan, _ptr(self.ws), self.ws.numel(), int(reps),
+                                   _stream(stream))
+        _check("ozk_tune_batch", st, self.ctx)
 
     def close(self) -> None:
         if self.plan:

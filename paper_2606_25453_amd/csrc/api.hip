@@ -859,6 +859,173 @@ ozk_status ozk_cgemm(ozk_ctx* ctx, ozk_scheme scheme, int p_or_s, int64_t M, int
   return zgemm4m_run<float>(ctx, p_or_s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, ws, ws_bytes, stream, 15);
 }
 
+// ------------------------------------------- general layouts (ozk_gemm_ex)
+
+}  // extern "C"
+
+// Real product with transposed operands in binary32 (the binary64 one is
+// dgemm_run): as ozk_sgemm, with a transposed operand read by the other
+// pre-pass kernel (same packed layout and scales).
+static ozk_status sgemm_run(ozk_ctx* ctx, ozk_scheme scheme, int p_or_s, bool trans_a, bool trans_b, int64_t M,
+                            int64_t N, int64_t K, float alpha, const float* A, int64_t lda, const float* B,
+                            int64_t ldb, float beta, float* C, int64_t ldc, void* ws, size_t ws_bytes,
+                            hipStream_t stream, int ws_arg) {
+  char* w = (char*)ws;
+  if (scheme == OZK_SCHEME2) {
+    const int s = p_or_s;
+    const S2Plan pl = s2_plan(s, false, M, N, K);
+    if (!ws || ws_bytes < pl.total) return fail(ctx, OZK_ERR_WORKSPACE, ws_arg);
+    if (M == 0 || N == 0) return OZK_OK;
+    int32_t* sig = (int32_t*)(w + pl.off_sig);
+    int32_t* tau = (int32_t*)(w + pl.off_tau);
+    int8_t* Ap = (int8_t*)(w + pl.off_a);
+    int8_t* Bp = (int8_t*)(w + pl.off_b);
+    int8_t* res = (int8_t*)(w + pl.off_res);
+    int ta_bits, tb_bits;
+    ozk::s2_targets(s, ta_bits, tb_bits);
+    hipError_t err = trans_a ? ozk::s2_split_cols(s, false, A, lda, K, M, sig, Ap, stream, ta_bits)
+                             : ozk::s2_split_rows(s, false, A, lda, M, K, sig, Ap, stream);
+    if (err == hipSuccess)
+      err = trans_b ? ozk::s2_split_rows(s, false, B, ldb, N, K, tau, Bp, stream, tb_bits)
+                    : ozk::s2_split_cols(s, false, B, ldb, K, N, tau, Bp, stream);
+    if (err == hipSuccess) err = ozk::flag_nonfinite(sig, M, tau, N, ctx->dflags, stream);
+    const ozk_gemm_config cfg = config_for(ctx, OZK_OP_DGEMM, OZK_SCHEME2, s, M, N, K);
+    if (err == hipSuccess)
+      err = ozk::s2_gemm_mod(s, false, M, N, K, Ap, Bp, res, stream, cfg.variant, cfg.raster, cfg.group);
+    const float al[2] = {alpha, 0.0f}, be[2] = {beta, 0.0f};
+    if (err == hipSuccess) err = ozk::s2_crt(s, false, M, N, res, sig, tau, al, be, C, ldc, stream);
+    return hip_status(ctx, err);
+  }
+  const int p = p_or_s;
+  const ozk_gemm_config cfg = config_for(ctx, OZK_OP_DGEMM, OZK_SCHEME1, p, M, N, K);
+  const S1Plan pl = s1_plan(ctx, p, M, N, K, cfg.split);
+  if (!ws || ws_bytes < pl.total) return fail(ctx, OZK_ERR_WORKSPACE, ws_arg);
+  if (M == 0 || N == 0) return OZK_OK;
+  int32_t* e = (int32_t*)(w + pl.off_e);
+  int32_t* f = (int32_t*)(w + pl.off_f);
+  int8_t* Ap = (int8_t*)(w + pl.off_a);
+  int8_t* Bp = (int8_t*)(w + pl.off_b);
+  hipError_t err = trans_a ? ozk::s1_split_cols(p, A, lda, K, M, e, Ap, stream)
+                           : ozk::s1_split_rows(p, A, lda, M, K, e, Ap, stream);
+  if (err == hipSuccess)
+    err = trans_b ? ozk::s1_split_rows(p, B, ldb, N, K, f, Bp, stream) : ozk::s1_split_cols(p, B, ldb, K, N, f, Bp, stream);
+  if (err == hipSuccess) err = ozk::flag_nonfinite(e, M, f, N, ctx->dflags, stream);
+  if (err != hipSuccess) return hip_status(ctx, err);
+  return s1_gemm_common(ctx, p, M, N, K, Ap, e, Bp, f, alpha, beta, nullptr, ldc, w + pl.off_z, pl.total - pl.off_z,
+                        nullptr, stream, cfg, C);
+}
+
+// The 3M complex product with transposed operands (T = double: ZGEMM,
+// float: CGEMM); a transposed operand is read by the other pre-pass kernel.
+template <typename T>
+static ozk_status zgemm3m_run(ozk_ctx* ctx, int s, bool trans_a, bool trans_b, int64_t M, int64_t N, int64_t K,
+                              const T* alpha, const T* A, int64_t lda, const T* B, int64_t ldb, const T* beta, T* C,
+                              int64_t ldc, void* ws, size_t ws_bytes, hipStream_t stream, int ws_arg) {
+  const S2Plan pl = s2_plan(s, true, M, N, K);
+  if (!ws || ws_bytes < pl.total) return fail(ctx, OZK_ERR_WORKSPACE, ws_arg);
+  if (M == 0 || N == 0) return OZK_OK;
+  char* w = (char*)ws;
+  int32_t* sig = (int32_t*)(w + pl.off_sig);
+  int32_t* tau = (int32_t*)(w + pl.off_tau);
+  int8_t* Ap = (int8_t*)(w + pl.off_a);
+  int8_t* Bp = (int8_t*)(w + pl.off_b);
+  int8_t* res = (int8_t*)(w + pl.off_res);
+  int ta_bits, tb_bits;
+  ozk::s2_targets(s, ta_bits, tb_bits);
+  hipError_t err = trans_a ? ozk::s2_split_cols(s, true, A, lda, K, M, sig, Ap, stream, ta_bits)
+                           : ozk::s2_split_rows(s, true, A, lda, M, K, sig, Ap, stream);
+  if (err == hipSuccess)
+    err = trans_b ? ozk::s2_split_rows(s, true, B, ldb, N, K, tau, Bp, stream, tb_bits)
+                  : ozk::s2_split_cols(s, true, B, ldb, K, N, tau, Bp, stream);
+  if (err == hipSuccess) err = ozk::flag_nonfinite(sig, M, tau, N, ctx->dflags, stream);
+  const ozk_gemm_config cfg = config_for(ctx, OZK_OP_ZGEMM, OZK_SCHEME2, s, M, N, K);
+  if (err == hipSuccess)
+    err = ozk::s2_gemm_mod(s, true, M, N, K, Ap, Bp, res, stream, cfg.variant, cfg.raster, cfg.group);
+  if (err == hipSuccess) err = ozk::s2_crt(s, true, M, N, res, sig, tau, alpha, beta, C, ldc, stream);
+  return hip_status(ctx, err);
+}
+
+extern "C" {
+
+ozk_status ozk_gemm_ex(ozk_ctx* ctx, ozk_dtype dtype, ozk_layout layout, int trans_a, int trans_b, ozk_scheme scheme,
+                       int p_or_s, int64_t M, int64_t N, int64_t K, const void* alpha, const void* A, int64_t lda,
+                       const void* B, int64_t ldb, const void* beta, void* C, int64_t ldc, void* ws,
+                       size_t ws_bytes, hipStream_t stream) {
+  if (!ctx) return OZK_ERR_INVALID_ARG;
+  ctx->last_arg = 0;
+  if (dtype != OZK_F64 && dtype != OZK_F32 && dtype != OZK_C128 && dtype != OZK_C64)
+    return fail(ctx, OZK_ERR_INVALID_ARG, 2);
+  if (layout != OZK_ROW_MAJOR && layout != OZK_COL_MAJOR) return fail(ctx, OZK_ERR_INVALID_ARG, 3);
+  if (trans_a != 0 && trans_a != 1) return fail(ctx, OZK_ERR_INVALID_ARG, 4);
+  if (trans_b != 0 && trans_b != 1) return fail(ctx, OZK_ERR_INVALID_ARG, 5);
+  if (scheme != OZK_SCHEME1 && scheme != OZK_SCHEME2) return fail(ctx, OZK_ERR_INVALID_ARG, 6);
+  if (bad_dims(M, N, K)) return fail(ctx, OZK_ERR_INVALID_ARG, M < 0 ? 8 : (N < 0 ? 9 : 10));
+  if (!alpha) return fail(ctx, OZK_ERR_INVALID_ARG, 11);
+  if (!beta) return fail(ctx, OZK_ERR_INVALID_ARG, 16);
+  // Stored shapes: op(A) is M x K, so A holds M x K (no transpose) or K x M;
+  // each leading dimension is at least the length of a stored line (a row
+  // for row-major, a column for column-major).
+  const bool col = layout == OZK_COL_MAJOR;
+  const int64_t a_rows = trans_a ? K : M, a_cols = trans_a ? M : K;
+  const int64_t b_rows = trans_b ? N : K, b_cols = trans_b ? K : N;
+  const int64_t a_line = col ? a_rows : a_cols, b_line = col ? b_rows : b_cols, c_line = col ? M : N;
+  if (!A && a_rows > 0 && a_cols > 0) return fail(ctx, OZK_ERR_INVALID_ARG, 12);
+  if (lda < (a_line > 0 ? a_line : 1)) return fail(ctx, OZK_ERR_INVALID_ARG, 13);
+  if (!B && b_rows > 0 && b_cols > 0) return fail(ctx, OZK_ERR_INVALID_ARG, 14);
+  if (ldb < (b_line > 0 ? b_line : 1)) return fail(ctx, OZK_ERR_INVALID_ARG, 15);
+  if (!C && M > 0 && N > 0) return fail(ctx, OZK_ERR_INVALID_ARG, 17);
+  if (ldc < (c_line > 0 ? c_line : 1)) return fail(ctx, OZK_ERR_INVALID_ARG, 18);
+  const bool cplx = dtype == OZK_C128 || dtype == OZK_C64;
+  const int hi = scheme == OZK_SCHEME1 ? OZK_MAX_P : OZK_MAX_S;
+  if (p_or_s < 1 || p_or_s > hi) return fail(ctx, OZK_ERR_UNSUPPORTED, 7);
+  if (scheme == OZK_SCHEME2 && s2_long_k(K)) return fail(ctx, OZK_ERR_UNSUPPORTED, 10);
+  // Column-major storage of X is row-major storage of X^T, and C = op(A) op(B)
+  // is C^T = op(B)^T op(A)^T: the row-major product of the swapped operands,
+  // each transposed exactly when the other one was.  The scales of a row of
+  // op(A) and a column of op(B) are the same either way, so are the integer
+  // sums, so the results are bit-identical to the row-major call.
+  int64_t m = M, n = N;
+  const void *a = A, *b = B;
+  int64_t la = lda, lb = ldb;
+  bool ta = trans_a != 0, tb = trans_b != 0;
+  if (col) {
+    m = N;
+    n = M;
+    a = B;
+    b = A;
+    la = ldb;
+    lb = lda;
+    ta = trans_b != 0;
+    tb = trans_a != 0;
+  }
+  switch (dtype) {
+    case OZK_F64:
+      return dgemm_run(ctx, scheme, p_or_s, ta, tb, m, n, K, *(const double*)alpha, (const double*)a, la,
+                       (const double*)b, lb, *(const double*)beta, (double*)C, ldc, ws, ws_bytes, stream, 19);
+    case OZK_F32:
+      return sgemm_run(ctx, scheme, p_or_s, ta, tb, m, n, K, *(const float*)alpha, (const float*)a, la,
+                       (const float*)b, lb, *(const float*)beta, (float*)C, ldc, ws, ws_bytes, stream, 19);
+    default:
+      break;
+  }
+  if (scheme == OZK_SCHEME1) {
+    // 4M reads the row operand's stored rows as its real embedding and builds
+    // the column operand's: transposed operands have no such kernels
+    if (ta || tb) return fail(ctx, OZK_ERR_UNSUPPORTED, ta ? (col ? 5 : 4) : (col ? 4 : 5));
+    if (dtype == OZK_C128)
+      return zgemm4m_run<double>(ctx, p_or_s, m, n, K, (const double*)alpha, (const double*)a, la, (const double*)b,
+                                 lb, (const double*)beta, (double*)C, ldc, ws, ws_bytes, stream, 19);
+    return zgemm4m_run<float>(ctx, p_or_s, m, n, K, (const float*)alpha, (const float*)a, la, (const float*)b, lb,
+                              (const float*)beta, (float*)C, ldc, ws, ws_bytes, stream, 19);
+  }
+  (void)cplx;
+  if (dtype == OZK_C128)
+    return zgemm3m_run<double>(ctx, p_or_s, ta, tb, m, n, K, (const double*)alpha, (const double*)a, la,
+                               (const double*)b, lb, (const double*)beta, (double*)C, ldc, ws, ws_bytes, stream, 19);
+  return zgemm3m_run<float>(ctx, p_or_s, ta, tb, m, n, K, (const float*)alpha, (const float*)a, la, (const float*)b,
+                            lb, (const float*)beta, (float*)C, ldc, ws, ws_bytes, stream, 19);
+}
+
 // The unfused Scheme II / 3M baseline: the fused path's pre-pass and CRT
 // around one GEMM per modular product with INT32 planes through HBM.
 static size_t s2_unfused_ws(int s, bool cplx, int64_t M, int64_t N, int64_t K, S2Plan& pl) {
@@ -1073,7 +1240,14 @@ ozk_status ozk_dgemm_auto(ozk_ctx* ctx, double tol, int64_t M, int64_t N, int64_
     g.ldc = ldc;
     g.zpart = p1.nsplit > 1 ? (int64_t*)(w + p1.off_z) : nullptr;
     g.diag = nullptr;
-    err = ozk::s1_gemm_auto(inf, g, stream);
+    int cfg[OZK_MAX_P][3];  // the tuned (or default) tiling of each slice count's size class
+    for (int p = 1; p <= OZK_MAX_P; ++p) {
+      const ozk_gemm_config c = config_for(ctx, OZK_OP_DGEMM, OZK_SCHEME1, p, M, N, K);
+      cfg[p - 1][0] = c.variant;
+      cfg[p - 1][1] = c.raster;
+      cfg[p - 1][2] = c.group;
+    }
+    err = ozk::s1_gemm_auto(inf, g, cfg, stream);
   }
   // Scheme II at the chosen s (every kernel returns when Scheme I was chosen)
   const S2Plan& p2 = ap.s2;
@@ -1175,17 +1349,97 @@ ozk_status ozk_ref_dd(ozk_ctx* ctx, int64_t M, int64_t N, int64_t K, const doubl
 }
 
 struct ozk_batch_plan {
-  int device;
-  ozk_op op;
-  ozk_scheme scheme;
-  int s;
-  int count;
-  void* dev;  // device tables
-  ozk::BatchDev bd;
-  ozk::BatchTotals tot;
-  size_t ws_bytes;
-  int gemm_grid;
+  int device = 0;
+  ozk_op op = OZK_OP_DGEMM;
+  ozk_scheme scheme = OZK_SCHEME2;
+  int s = 0;
+  int count = 0;
+  int ncu = 256;
+  void* dev = nullptr;  // device tables
+  ozk::BatchDev bd{};
+  ozk::BatchTotals tot{};
+  size_t ws_bytes = 0;
+  int grid_small = 1, grid_large = 1;
+  // host state for re-planning the tile of each problem
+  std::vector<ozk::BatchProb> prob;
+  std::vector<uint8_t> large;  // 1: the problem's items take the 128 x 128 tile
+  size_t hint_cap = 0;         // entries of each item hint array on the device
+  int64_t *items_s = nullptr, *items_l = nullptr;
+  int32_t *hint_s = nullptr, *hint_l = nullptr, *order_s = nullptr, *order_l = nullptr;
 };
+
+namespace {
+
+// The batched op code whose table entries hold the batch tile of a size class.
+int batched_op(ozk_op op) { return op == OZK_OP_ZGEMM ? OZK_OP_ZGEMM_BATCHED : OZK_OP_DGEMM_BATCHED; }
+
+// Coarse index of a prefix array: hint[b] = the problem holding unit min(64 b, total - 1).
+std::vector<int32_t> unit_hints(const std::vector<int64_t>& start, int count) {
+  const int64_t tot = start[count];
+  std::vector<int32_t> h((size_t)((tot >> ozk::OZK_BATCH_HINT_SHIFT) + 2), 0);
+  int i = 0;
+  for (size_t b = 0; b < h.size(); ++b) {
+    const int64_t x = std::min<int64_t>((int64_t)b << ozk::OZK_BATCH_HINT_SHIFT, tot > 0 ? tot - 1 : 0);
+    while (i + 1 < count && start[i + 1] <= x) ++i;  // the largest i with start[i] <= x
+    h[b] = i;
+  }
+  return h;
+}
+
+// Item lists of both tiles from pl->large (problems of each tile by
+// decreasing K, the others after them with no items), uploaded into the
+// plan's device regions, and the grids of the two persistent launches.
+hipError_t upload_items(ozk_batch_plan* pl) {
+  const int count = pl->count;
+  const bool cplx = pl->op == OZK_OP_ZGEMM;
+  for (int kind = 0; kind < 2; ++kind) {
+    std::vector<int32_t> order(count);
+    std::iota(order.begin(), order.end(), 0);
+    auto mine = [&](int q) { return pl->large[q] == kind && pl->prob[q].tiles > 0; };
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+      if (mine(a) != mine(b)) return mine(a);
+      return pl->prob[a].Kp > pl->prob[b].Kp;
+    });
+    std::vector<int64_t> items(count + 1, 0);
+    for (int i = 0; i < count; ++i) {
+      const ozk::BatchProb& q = pl->prob[order[i]];
+      items[i + 1] = items[i] + (mine(order[i]) ? ozk::s2_tile_count(cplx, kind == 1, q.M, q.N) : 0);
+    }
+    const std::vector<int32_t> hint = unit_hints(items, count);
+    if (hint.size() > pl->hint_cap) return hipErrorInvalidValue;
+    int64_t* di = kind ? pl->items_l : pl->items_s;
+    int32_t* dh = kind ? pl->hint_l : pl->hint_s;
+    int32_t* dord = kind ? pl->order_l : pl->order_s;
+    hipError_t e = hipMemcpy(di, items.data(), sizeof(int64_t) * (count + 1), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(dh, hint.data(), sizeof(int32_t) * hint.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess && count > 0)
+      e = hipMemcpy(dord, order.data(), sizeof(int32_t) * count, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return e;
+    const int64_t slots = (int64_t)pl->ncu * ozk::s2_batch_gemm_blocks_per_cu(cplx, kind == 1);
+    const int64_t n = items[count];
+    const int grid = (int)(n < slots ? (n > 0 ? n : 1) : slots);
+    if (kind) {
+      pl->tot.items_l = n;
+      pl->grid_large = grid;
+    } else {
+      pl->tot.items = n;
+      pl->grid_small = grid;
+    }
+  }
+  pl->bd.items = {pl->items_s, pl->hint_s};
+  pl->bd.items_l = {pl->items_l, pl->hint_l};
+  pl->bd.order = pl->order_s;
+  pl->bd.order_l = pl->order_l;
+  return hipSuccess;
+}
+
+void free_plan(ozk_batch_plan* pl) {
+  if (!pl) return;
+  if (pl->dev) (void)hipFree(pl->dev);
+  delete pl;
+}
+
+}  // namespace
 
 ozk_status ozk_batch_plan_create(ozk_ctx* ctx, ozk_op op, ozk_scheme scheme, int p_or_s, int count,
                                  const ozk_gemm_desc* descs, ozk_batch_plan** plan, size_t* ws_bytes) {
@@ -1208,18 +1462,27 @@ ozk_status ozk_batch_plan_create(ozk_ctx* ctx, ozk_op op, ozk_scheme scheme, int
       return fail(ctx, OZK_ERR_INVALID_ARG, 6);
     if (s2_long_k(d.K)) return fail(ctx, OZK_ERR_UNSUPPORTED, 6);
   }
-  std::vector<ozk::BatchProb> prob(count);
+  ozk_batch_plan* pl = new (std::nothrow) ozk_batch_plan();
+  if (!pl) return fail(ctx, OZK_ERR_HIP, 0);
+  pl->device = ctx->device;
+  pl->op = op;
+  pl->scheme = scheme;
+  pl->s = s;
+  pl->count = count;
+  pl->prob.resize(count);
+  pl->large.assign(count, 0);
   size_t o = 0;
+  int64_t max_items = 0;
   for (int i = 0; i < count; ++i) {
     const ozk_gemm_desc& d = descs[i];
-    ozk::BatchProb& q = prob[i];
+    ozk::BatchProb& q = pl->prob[i];
     q.M = d.M;
     q.N = d.N;
     q.K = d.K;
     q.Kp = round_up(d.K, OZK_K_CHUNK);
     q.ra = round_up(d.M, ozk::OZK_BATCH_ROW_ALIGN);
     q.rb = round_up(d.N, ozk::OZK_BATCH_ROW_ALIGN);
-    q.tiles = (d.M > 0 && d.N > 0) ? ozk::s2_tile_count(cplx, d.M, d.N) : 0;
+    q.tiles = (d.M > 0 && d.N > 0) ? 1 : 0;  // a live problem
     q.A = d.A;
     q.lda = d.lda;
     q.B = d.B;
@@ -1235,96 +1498,78 @@ ozk_status ozk_batch_plan_create(ozk_ctx* ctx, ozk_op op, ozk_scheme scheme, int
     q.off_a = o; o = align256(o + (size_t)q.ra * q.Kp * s * (cplx ? 3 : 1));
     q.off_b = o; o = align256(o + (size_t)q.rb * q.Kp * s * (cplx ? 3 : 1));
     q.off_res = o; o = align256(o + (size_t)s * (cplx ? 2 : 1) * d.M * d.N);
+    if (q.tiles) {
+      max_items += ozk::s2_tile_count(cplx, false, q.M, q.N);  // the small tile gives the most items
+      // the tile of this size class: the tuned table's choice (variant 1: the
+      // large tile), else the large tile once both sides reach 256
+      auto it = ctx->configs.find(cfg_key(batched_op(op), OZK_SCHEME2, s, d.M, d.N, d.K));
+      pl->large[i] = it != ctx->configs.end() ? (it->second.cfg.variant == 1) : (d.M >= 256 && d.N >= 256);
+    }
   }
-  // GEMM item order: problems by decreasing K (stable), so the longest items go first
-  std::vector<int32_t> order(count);
-  std::iota(order.begin(), order.end(), 0);
-  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return prob[a].Kp > prob[b].Kp; });
-  std::vector<int64_t> rows(count + 1, 0), cols(count + 1, 0), split(count + 1, 0), items(count + 1, 0),
-      crt(count + 1, 0);
+  std::vector<int64_t> rows(count + 1, 0), cols(count + 1, 0), split(count + 1, 0), crt(count + 1, 0);
   for (int i = 0; i < count; ++i) {
-    const ozk::BatchProb& q = prob[i];
-    const bool live = q.M > 0 && q.N > 0;
+    const ozk::BatchProb& q = pl->prob[i];
+    const bool live = q.tiles > 0;
     rows[i + 1] = rows[i] + (live ? ozk::s2_split_rows_blocks(q.ra) : 0);
     cols[i + 1] = cols[i] + (live ? (q.N + 31) / 32 : 0);
     split[i + 1] = split[i] + (live ? ozk::s2_split_cols_blocks(q.rb, q.Kp) : 0);
     crt[i + 1] = crt[i] + (live ? (q.M * q.N + 255) / 256 : 0);
   }
-  for (int i = 0; i < count; ++i) items[i + 1] = items[i] + prob[order[i]].tiles;  // all s moduli per item
-  ozk_batch_plan* pl = (ozk_batch_plan*)calloc(1, sizeof(ozk_batch_plan));
-  if (!pl) return fail(ctx, OZK_ERR_HIP, 0);
-  pl->device = ctx->device;
-  pl->op = op;
-  pl->scheme = scheme;
-  pl->s = s;
-  pl->count = count;
   pl->ws_bytes = o > 0 ? o : 256;
-  pl->tot = {rows[count], cols[count], split[count], items[count], crt[count]};
-  // coarse indexes: hint[b] = the problem holding unit min(64 b, total - 1)
-  auto hints = [&](const std::vector<int64_t>& start) {
-    const int64_t tot = start[count];
-    std::vector<int32_t> h((size_t)((tot >> ozk::OZK_BATCH_HINT_SHIFT) + 2), 0);
-    int i = 0;
-    for (size_t b = 0; b < h.size(); ++b) {
-      const int64_t x = std::min<int64_t>((int64_t)b << ozk::OZK_BATCH_HINT_SHIFT, tot > 0 ? tot - 1 : 0);
-      while (i + 1 < count && start[i + 1] <= x) ++i;  // the largest i with start[i] <= x
-      h[b] = i;
-    }
-    return h;
-  };
-  const std::vector<int32_t> h_rows = hints(rows), h_cols = hints(cols), h_split = hints(split),
-                             h_items = hints(items), h_crt = hints(crt);
-  // device tables: problems, six int64 prefix arrays, the order, five hint arrays
+  pl->tot = {rows[count], cols[count], split[count], 0, 0, crt[count]};
+  const std::vector<int32_t> h_rows = unit_hints(rows, count), h_cols = unit_hints(cols, count),
+                             h_split = unit_hints(split, count), h_crt = unit_hints(crt, count);
+  pl->hint_cap = (size_t)((max_items >> ozk::OZK_BATCH_HINT_SHIFT) + 2);
+  // device tables: problems, four prefix arrays with their hints, and for each
+  // tile an item prefix array, its hints and its order
   const size_t nprob = sizeof(ozk::BatchProb) * (count > 0 ? count : 1);
   const size_t npre = sizeof(int64_t) * (count + 1);
+  const size_t nord = sizeof(int32_t) * (count > 0 ? count : 1);
+  const size_t nhcap = sizeof(int32_t) * pl->hint_cap;
   size_t nhint = 0;
-  for (const auto* h : {&h_rows, &h_cols, &h_split, &h_items, &h_crt}) nhint += align256(sizeof(int32_t) * h->size());
-  const size_t total =
-      align256(nprob) + 6 * align256(npre) + align256(sizeof(int32_t) * (count > 0 ? count : 1)) + nhint;
+  for (const auto* h : {&h_rows, &h_cols, &h_split, &h_crt}) nhint += align256(sizeof(int32_t) * h->size());
+  const size_t total = align256(nprob) + 6 * align256(npre) + nhint + 2 * align256(nhcap) + 2 * align256(nord);
   if (hipMalloc(&pl->dev, total) != hipSuccess) {
-    free(pl);
+    pl->dev = nullptr;
+    free_plan(pl);
     return fail(ctx, OZK_ERR_HIP, 0);
   }
   char* base = (char*)pl->dev;
   size_t off = 0;
-  auto put = [&](const void* src, size_t bytes) -> void* {
+  bool ok = true;
+  auto put = [&](const void* src, size_t bytes, size_t room) -> void* {
     void* dst = base + off;
-    if (bytes && hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice) != hipSuccess) return nullptr;
-    off += align256(bytes > 0 ? bytes : 1);
+    if (bytes && hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice) != hipSuccess) ok = false;
+    off += align256(room > 0 ? room : 1);
     return dst;
   };
-  void* pp = put(prob.data(), sizeof(ozk::BatchProb) * count);
-  if (count == 0) off = align256(nprob);
-  void* r1 = put(rows.data(), npre);
-  void* r2 = put(cols.data(), npre);
-  void* r3 = put(split.data(), npre);
-  void* r4 = put(items.data(), npre);
-  void* r5 = put(crt.data(), npre);
-  off += align256(npre);  // spare
-  void* r6 = put(order.data(), sizeof(int32_t) * count);
-  void* q1 = put(h_rows.data(), sizeof(int32_t) * h_rows.size());
-  void* q2 = put(h_cols.data(), sizeof(int32_t) * h_cols.size());
-  void* q3 = put(h_split.data(), sizeof(int32_t) * h_split.size());
-  void* q4 = put(h_items.data(), sizeof(int32_t) * h_items.size());
-  void* q5 = put(h_crt.data(), sizeof(int32_t) * h_crt.size());
-  if ((count > 0 && (!pp || !r6)) || !r1 || !r2 || !r3 || !r4 || !r5 || !q1 || !q2 || !q3 || !q4 || !q5) {
-    (void)hipFree(pl->dev);
-    free(pl);
-    return fail(ctx, OZK_ERR_HIP, 0);
-  }
+  void* pp = put(pl->prob.data(), sizeof(ozk::BatchProb) * count, nprob);
+  void* r1 = put(rows.data(), npre, npre);
+  void* r2 = put(cols.data(), npre, npre);
+  void* r3 = put(split.data(), npre, npre);
+  void* r5 = put(crt.data(), npre, npre);
+  void* q1 = put(h_rows.data(), sizeof(int32_t) * h_rows.size(), sizeof(int32_t) * h_rows.size());
+  void* q2 = put(h_cols.data(), sizeof(int32_t) * h_cols.size(), sizeof(int32_t) * h_cols.size());
+  void* q3 = put(h_split.data(), sizeof(int32_t) * h_split.size(), sizeof(int32_t) * h_split.size());
+  void* q5 = put(h_crt.data(), sizeof(int32_t) * h_crt.size(), sizeof(int32_t) * h_crt.size());
+  pl->items_s = (int64_t*)put(nullptr, 0, npre);
+  pl->items_l = (int64_t*)put(nullptr, 0, npre);
+  pl->hint_s = (int32_t*)put(nullptr, 0, nhcap);
+  pl->hint_l = (int32_t*)put(nullptr, 0, nhcap);
+  pl->order_s = (int32_t*)put(nullptr, 0, nord);
+  pl->order_l = (int32_t*)put(nullptr, 0, nord);
   pl->bd.prob = (const ozk::BatchProb*)pp;
   pl->bd.rows = {(const int64_t*)r1, (const int32_t*)q1};
   pl->bd.cols = {(const int64_t*)r2, (const int32_t*)q2};
   pl->bd.split = {(const int64_t*)r3, (const int32_t*)q3};
-  pl->bd.items = {(const int64_t*)r4, (const int32_t*)q4};
   pl->bd.crt = {(const int64_t*)r5, (const int32_t*)q5};
-  pl->bd.order = (const int32_t*)r6;
   pl->bd.count = count;
   hipDeviceProp_t prop;
-  int ncu = 256;
-  if (hipGetDeviceProperties(&prop, ctx->device) == hipSuccess) ncu = prop.multiProcessorCount;
-  const int64_t slots = (int64_t)ncu * ozk::s2_batch_gemm_blocks_per_cu(cplx);
-  pl->gemm_grid = (int)(pl->tot.items < slots ? (pl->tot.items > 0 ? pl->tot.items : 1) : slots);
+  if (hipGetDeviceProperties(&prop, ctx->device) == hipSuccess) pl->ncu = prop.multiProcessorCount;
+  if (!ok || upload_items(pl) != hipSuccess) {
+    free_plan(pl);
+    return fail(ctx, OZK_ERR_HIP, 0);
+  }
   *plan = pl;
   if (ws_bytes) *ws_bytes = pl->ws_bytes;
   return OZK_OK;
@@ -1338,22 +1583,82 @@ ozk_status ozk_gemm_batched(ozk_ctx* ctx, const ozk_batch_plan* plan, void* ws, 
   if (!ws || ws_bytes < plan->ws_bytes) return fail(ctx, OZK_ERR_WORKSPACE, 3);
   if (plan->count == 0) return OZK_OK;
   hipError_t err = ozk::s2_batched(plan->s, plan->op == OZK_OP_ZGEMM, plan->bd, plan->tot, (int8_t*)ws,
-                                   plan->gemm_grid, stream);
+                                   plan->grid_small, plan->grid_large, stream);
   if (err == hipSuccess) err = ozk::flag_batch(plan->bd, (const int8_t*)ws, ctx->dflags, stream);
   return hip_status(ctx, err);
 }
 
 ozk_status ozk_batch_plan_destroy(ozk_batch_plan* plan) {
-  if (!plan) return OZK_OK;
-  if (plan->dev) (void)hipFree(plan->dev);
-  free(plan);
+  free_plan(plan);
   return OZK_OK;
+}
+
+ozk_status ozk_batch_plan_tiles(const ozk_batch_plan* plan, int count, int32_t* large) {
+  if (!plan || count != plan->count || (count > 0 && !large)) return OZK_ERR_INVALID_ARG;
+  for (int i = 0; i < count; ++i) large[i] = plan->large[i];
+  return OZK_OK;
+}
+
+ozk_status ozk_tune_batch(ozk_ctx* ctx, ozk_batch_plan* plan, void* ws, size_t ws_bytes, int reps,
+                          hipStream_t stream) {
+  if (!ctx) return OZK_ERR_INVALID_ARG;
+  ctx->last_arg = 0;
+  if (!plan) return fail(ctx, OZK_ERR_INVALID_ARG, 2);
+  if (!ws || ws_bytes < plan->ws_bytes) return fail(ctx, OZK_ERR_WORKSPACE, 3);
+  if (reps < 1 || reps > 100) return fail(ctx, OZK_ERR_INVALID_ARG, 5);
+  if (plan->count == 0) return OZK_OK;
+  const bool cplx = plan->op == OZK_OP_ZGEMM;
+  int8_t* w = (int8_t*)ws;
+  hipError_t err = ozk::s2_batched_prepass(plan->s, cplx, plan->bd, plan->tot, w, stream);
+  // size classes of the live problems, the most INT8 work first
+  std::map<ozk_cfg_key, std::vector<int>> cls;
+  std::map<ozk_cfg_key, double> work;
+  for (int i = 0; i < plan->count; ++i) {
+    const ozk::BatchProb& q = plan->prob[i];
+    if (!q.tiles) continue;
+    const ozk_cfg_key k = cfg_key(batched_op(plan->op), OZK_SCHEME2, plan->s, q.M, q.N, q.K);
+    cls[k].push_back(i);
+    work[k] += (double)q.M * q.N * (q.K > 0 ? q.K : 1);
+  }
+  std::vector<ozk_cfg_key> keys;
+  for (const auto& kv : cls) keys.push_back(kv.first);
+  std::stable_sort(keys.begin(), keys.end(), [&](const ozk_cfg_key& a, const ozk_cfg_key& b) { return work[a] > work[b]; });
+  // greedy over the classes: each takes the tile with the faster GEMM step,
+  // the classes before it keeping their choice
+  for (const ozk_cfg_key& k : keys) {
+    float best_ms = 0.f;
+    int best = 0;
+    for (int kind = 0; kind < 2 && err == hipSuccess; ++kind) {
+      for (int i : cls[k]) plan->large[i] = (uint8_t)kind;
+      err = upload_items(plan);
+      float ms = 0.f;
+      if (err == hipSuccess)
+        err = time_median(stream, reps, [&] {
+          return ozk::s2_batched_gemm(plan->s, cplx, plan->bd, plan->tot, w, plan->grid_small, plan->grid_large,
+                                      stream);
+        }, &ms);
+      if (err == hipSuccess && (kind == 0 || ms < best_ms)) {
+        best_ms = ms;
+        best = kind;
+      }
+    }
+    for (int i : cls[k]) plan->large[i] = (uint8_t)best;
+    ctx->configs[k] = ozk_cfg_entry{ozk_gemm_config{best, 0, 4, 1}, best_ms};
+  }
+  // the chosen tiles, and the batch computed with them
+  if (err == hipSuccess) err = upload_items(plan);
+  if (err == hipSuccess)
+    err = ozk::s2_batched_gemm(plan->s, cplx, plan->bd, plan->tot, w, plan->grid_small, plan->grid_large, stream);
+  if (err == hipSuccess) err = ozk::s2_batched_crt(plan->s, cplx, plan->bd, plan->tot, w, stream);
+  if (err == hipSuccess) err = hipStreamSynchronize(stream);
+  return hip_status(ctx, err);
 }
 
 // ------------------------------------------------------------- autotuner
 
 static ozk_status check_target(ozk_ctx* ctx, int op, int scheme, int p_or_s) {
-  if (op != OZK_OP_DGEMM && op != OZK_OP_ZGEMM) return fail(ctx, OZK_ERR_INVALID_ARG, 2);
+  if (op != OZK_OP_DGEMM && op != OZK_OP_ZGEMM && op != OZK_OP_DGEMM_BATCHED && op != OZK_OP_ZGEMM_BATCHED)
+    return fail(ctx, OZK_ERR_INVALID_ARG, 2);
   if (scheme != OZK_SCHEME1 && scheme != OZK_SCHEME2) return fail(ctx, OZK_ERR_INVALID_ARG, 3);
   if (scheme == OZK_SCHEME1 && op != OZK_OP_DGEMM) return fail(ctx, OZK_ERR_UNSUPPORTED, 3);
   const int hi = scheme == OZK_SCHEME1 ? OZK_MAX_P : OZK_MAX_S;
@@ -1378,6 +1683,8 @@ ozk_status ozk_config_set(ozk_ctx* ctx, ozk_op op, ozk_scheme scheme, int p_or_s
   if (st != OZK_OK) return st;
   if (bad_dims(M, N, K)) return fail(ctx, OZK_ERR_INVALID_ARG, 5);
   if (!cfg || !valid_config(scheme, *cfg)) return fail(ctx, OZK_ERR_INVALID_ARG, 8);
+  if ((op == OZK_OP_DGEMM_BATCHED || op == OZK_OP_ZGEMM_BATCHED) && cfg->variant > 1)
+    return fail(ctx, OZK_ERR_INVALID_ARG, 8);  // batch tiles: 0 small, 1 large
   ozk_gemm_config c = *cfg;
   if (scheme == OZK_SCHEME2) c.split = 1;
   ctx->configs[cfg_key(op, scheme, p_or_s, M, N, K)] = ozk_cfg_entry{c, 0.f};
@@ -1471,7 +1778,9 @@ ozk_status ozk_config_load(ozk_ctx* ctx, const char* path) {
     if (at != std::string::npos) ms = strtod(obj.c_str() + obj.find(':', at) + 1, nullptr);
     const ozk_gemm_config c{(int)v[6], (int)v[7], (int)v[8], (int)v[9]};
     ozk_ctx probe;
+    const bool batched = v[0] == OZK_OP_DGEMM_BATCHED || v[0] == OZK_OP_ZGEMM_BATCHED;
     if (check_target(&probe, (int)v[0], (int)v[1], (int)v[2]) != OZK_OK || !valid_config((int)v[1], c) ||
+        (batched && c.variant > 1) ||
         v[3] < 0 || v[3] > 62 || v[4] < 0 || v[4] > 62 || v[5] < 0 || v[5] > 62)
       return fail(ctx, OZK_ERR_INVALID_ARG, 2);
     add[ozk_cfg_key{(int)v[0], (int)v[1], (int)v[2], (int)v[3], (int)v[4], (int)v[5]}] = ozk_cfg_entry{c, (float)ms};

@@ -62,12 +62,14 @@ hipError_t s1_gemm_unfused(int p, int64_t M, int64_t N, int64_t K, const int8_t*
 hipError_t s1_slice_auto(const int32_t* p_dev, const double* A, int64_t lda, int64_t M, const double* B, int64_t ldb,
                          int64_t N, int64_t K, const int32_t* e, const int32_t* f, int8_t* Ap, int8_t* Bp,
                          hipStream_t st);
-hipError_t s1_gemm_auto(const int32_t* p_dev, const S1GemmArgs& g, hipStream_t st);
+// cfg[p - 1] = {variant, raster, group} of the kernel for slice count p
+hipError_t s1_gemm_auto(const int32_t* p_dev, const S1GemmArgs& g, const int (*cfg)[3], hipStream_t st);
 
-// Packed rows of a batched problem are padded to 64 (the batch GEMM tile, a
-// multiple of the 16-row and 64-column pre-pass blocks), not to
-// OZK_ROW_ALIGN: small problems then carry far fewer padding rows.
-constexpr int OZK_BATCH_ROW_ALIGN = 64;
+// Packed rows of a batched problem are padded to 128 (both batch GEMM tiles,
+// a multiple of the 16-row and 64-column pre-pass blocks), not to
+// OZK_ROW_ALIGN: small problems then carry far fewer padding rows, and the
+// tile of a problem can change without a new layout.
+constexpr int OZK_BATCH_ROW_ALIGN = 128;
 
 // One problem of a batch; workspace parts are byte offsets from the
 // workspace base passed to each launch.
@@ -102,20 +104,28 @@ struct BatchDev {
   BatchUnits rows;   // row blocks of 16 rows (pre-pass of A)
   BatchUnits cols;   // column blocks of 32 (column scales of B)
   BatchUnits split;  // (64-column block, K chunk) pairs (residues of B)
-  BatchUnits items;  // GEMM items (output tiles, all moduli each) in the order below
-  BatchUnits crt;    // output blocks of 256 (CRT)
-  const int32_t* order;  // GEMM item order -> problem index
+  BatchUnits items;    // GEMM items of the small-tile problems (output tiles, all moduli each) in `order`
+  BatchUnits items_l;  // the same for the large-tile problems, in `order_l`
+  BatchUnits crt;      // output blocks of 256 (CRT)
+  const int32_t* order;    // small-tile item order -> problem index (problems without items at the end)
+  const int32_t* order_l;  // large-tile item order -> problem index
   int count;
 };
 
 struct BatchTotals {
-  int64_t rows, cols, split, items, crt;
+  int64_t rows, cols, split, items, items_l, crt;
 };
 
-hipError_t s2_batched(int s, bool cplx, const BatchDev& bd, const BatchTotals& tot, int8_t* ws, int gemm_grid,
-                      hipStream_t st);
-int s2_batch_gemm_blocks_per_cu(bool cplx);
-int64_t s2_tile_count(bool cplx, int64_t M, int64_t N);
+hipError_t s2_batched(int s, bool cplx, const BatchDev& bd, const BatchTotals& tot, int8_t* ws, int grid_small,
+                      int grid_large, hipStream_t st);
+// the steps of s2_batched on their own (the tuner times the GEMM step)
+hipError_t s2_batched_prepass(int s, bool cplx, const BatchDev& bd, const BatchTotals& tot, int8_t* ws,
+                              hipStream_t st);
+hipError_t s2_batched_gemm(int s, bool cplx, const BatchDev& bd, const BatchTotals& tot, int8_t* ws, int grid_small,
+                           int grid_large, hipStream_t st);
+hipError_t s2_batched_crt(int s, bool cplx, const BatchDev& bd, const BatchTotals& tot, int8_t* ws, hipStream_t st);
+int s2_batch_gemm_blocks_per_cu(bool cplx, bool large);
+int64_t s2_tile_count(bool cplx, bool large, int64_t M, int64_t N);
 int64_t s2_split_rows_blocks(int64_t rows_packed);             // workgroups of the row residue pass
 int64_t s2_split_cols_blocks(int64_t cols_packed, int64_t Kp);  // workgroups of the column residue pass
 

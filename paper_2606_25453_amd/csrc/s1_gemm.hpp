@@ -41,6 +41,7 @@ struct S1KArgs {
   float* C32;
   const int32_t* p_dev;  // slice count chosen on the device; the kernel runs only if it equals P (null: always)
   int raster, group;     // workgroup -> tile order
+  int64_t ntiles;        // output tiles; workgroup w takes tiles w, w + G, ... (G = grid size)
 };
 
 // One output tile (workgroup tile index `tile`, K run z): the triangular
@@ -100,7 +101,12 @@ __global__ __launch_bounds__(256, 1) void k_s1_gemm(S1KArgs g) {
   using Cfg = S1Cfg<P, V>;
   extern __shared__ __attribute__((aligned(1024))) int8_t lds[];
   if (g.p_dev && *g.p_dev != P) return;  // another slice count was chosen
-  s1_gemm_tile<P, OUT, Cfg::TM, Cfg::TN, Cfg::NS>(g, blockIdx.x, blockIdx.z, lds);
+  // One tile per workgroup, except on the automatic path, whose grid is
+  // capped so that the kernels of the slice counts not chosen dispatch few
+  // workgroups; a stride that is a multiple of 8 keeps each tile on the XCD
+  // the raster order meant it for.
+  for (int64_t tile = blockIdx.x; tile < g.ntiles; tile += gridDim.x)
+    s1_gemm_tile<P, OUT, Cfg::TM, Cfg::TN, Cfg::NS>(g, tile, blockIdx.z, lds);
 }
 
 // Tiles of the workgroup grid for variant v at p (host side).
@@ -145,7 +151,10 @@ hipError_t s1_launch_pov(const S1GemmArgs& g, const int32_t* p_dev, hipStream_t 
   k.p_dev = p_dev;
   k.raster = g.raster;
   k.group = g.group;
-  const dim3 grid((unsigned)s1_tiles_v<P, V>(g.M, g.N), 1, (unsigned)g.nsplit);
+  k.ntiles = s1_tiles_v<P, V>(g.M, g.N);
+  // the automatic path: at most 512 workgroups (two per CU, a multiple of 8)
+  const int64_t gx = p_dev && k.ntiles > 512 ? 512 : k.ntiles;
+  const dim3 grid((unsigned)gx, 1, (unsigned)g.nsplit);
   hipLaunchKernelGGL(kern, grid, dim3(256), T::LDS_BYTES, st, k);
   return hipGetLastError();
 }

@@ -42,14 +42,8 @@ __device__ __forceinline__ void s1_words(const double (&x)[4], int e, uint32_t (
 
 __device__ __forceinline__ bool live_exponent(int e) { return e != OZK_EXP_ZERO && e != OZK_EXP_NONFINITE; }
 
-// Slices of packed row r whose exponent is e: each lane turns 8 consecutive
-// k into p digits and stores 8 bytes per slice at packed[k/32][t][r][k%32].
-// Rows past `rows`, zero or non-finite rows and k past K are zero.  The
-// branches are per row (wave-uniform) and per 4-k group (only the group that
-// straddles K takes the tail path), so the loads of the main path carry no
-// condition and are issued back to back.
 // 8 consecutive k of packed row r from k0 (a multiple of 8): two 4-entry
-// word groups, stored as one 8-byte piece per slice.
+// word groups, stored as one 8-byte piece per slice at packed[k/32][t][r][k%32].
 template <int P>
 __device__ __forceinline__ void s1_store_row_words(int8_t* __restrict__ packed, int64_t rows_packed, int64_t r,
                                                    int64_t k0, const uint32_t (&lo)[P], const uint32_t (&hi)[P]) {
@@ -59,35 +53,38 @@ __device__ __forceinline__ void s1_store_row_words(int8_t* __restrict__ packed, 
     *reinterpret_cast<uint2*>(packed + ((c * P + t) * rows_packed + r) * OZK_K_CHUNK + kk) = make_uint2(lo[t], hi[t]);
 }
 
-template <int P>
-__device__ __forceinline__ void s1_slice_row(const double* __restrict__ xr, int64_t r, int64_t rows, int64_t K,
-                                             int64_t Kp, int64_t rows_packed, int e, int8_t* __restrict__ packed) {
-  const int lane = threadIdx.x & 63;
-  int64_t k0 = (int64_t)lane * 8;
-  if (r < rows && live_exponent(e)) {
-    for (; k0 + 8 <= K; k0 += 512) {  // main path: 8 loads with no condition between them
-      const double a[4] = {xr[k0], xr[k0 + 1], xr[k0 + 2], xr[k0 + 3]};
-      const double b[4] = {xr[k0 + 4], xr[k0 + 5], xr[k0 + 6], xr[k0 + 7]};
-      uint32_t lo[P], hi[P];
-      s1_words<P>(a, e, lo);
-      s1_words<P>(b, e, hi);
-      s1_store_row_words<P>(packed, rows_packed, r, k0, lo, hi);
-    }
-    for (; k0 < Kp; k0 += 512) {  // the group straddling K, then the zero padding
+// Slices of packed row r (16 lanes per row, lane q taking 8 consecutive k
+// per 128): the digits of a live row, zeros for rows past `rows`, zero and
+// non-finite rows and k past K.  xr points at a row that may be read
+// whatever r (row 0 for rows past the end).
+template <int P, typename T>
+__device__ __forceinline__ void s1_slice_rows4(const T* __restrict__ xr, int64_t r, bool live, int e, int q,
+                                               int64_t K, int64_t Kp, int64_t rows_packed,
+                                               int8_t* __restrict__ packed) {
+  for (int64_t k0 = 8 * q; k0 < Kp; k0 += 128) {
+    uint32_t lo[P], hi[P];
+    if (live) {
       double a[4], b[4];
+      if (k0 + 8 <= K) {
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        a[j] = k0 + j < K ? xr[k0 + j] : 0.0;
-        b[j] = k0 + 4 + j < K ? xr[k0 + 4 + j] : 0.0;
+        for (int j = 0; j < 4; ++j) {
+          a[j] = xr[k0 + j];
+          b[j] = xr[k0 + 4 + j];
+        }
+      } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          a[j] = k0 + j < K ? xr[k0 + j] : 0.0;
+          b[j] = k0 + 4 + j < K ? xr[k0 + 4 + j] : 0.0;
+        }
       }
-      uint32_t lo[P], hi[P];
       s1_words<P>(a, e, lo);
       s1_words<P>(b, e, hi);
-      s1_store_row_words<P>(packed, rows_packed, r, k0, lo, hi);
+    } else {
+#pragma unroll
+      for (int t = 0; t < P; ++t) lo[t] = hi[t] = 0;
     }
-  } else {
-    const uint32_t zero[P] = {};
-    for (; k0 < Kp; k0 += 512) s1_store_row_words<P>(packed, rows_packed, r, k0, zero, zero);
+    if (r < rows_packed) s1_store_row_words<P>(packed, rows_packed, r, k0, lo, hi);
   }
 }
 
@@ -126,54 +123,34 @@ __global__ __launch_bounds__(256) void k_s1_split_rows4(const T* __restrict__ X,
   }
   e = group16_max(in ? e : OZK_EXP_ZERO);
   if (in && q == 0) e_out[r] = e;
-  const bool live = in && live_exponent(e);
-  for (int64_t k0 = 8 * q; k0 < Kp; k0 += 128) {
-    uint32_t lo[P], hi[P];
-    if (live) {
-      double a[4], b[4];
-      if (k0 + 8 <= K) {
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          a[j] = xr[k0 + j];
-          b[j] = xr[k0 + 4 + j];
-        }
-      } else {
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          a[j] = k0 + j < K ? xr[k0 + j] : 0.0;
-          b[j] = k0 + 4 + j < K ? xr[k0 + 4 + j] : 0.0;
-        }
-      }
-      s1_words<P>(a, e, lo);
-      s1_words<P>(b, e, hi);
-    } else {
-#pragma unroll
-      for (int t = 0; t < P; ++t) lo[t] = hi[t] = 0;
-    }
-    if (r < rows_packed) s1_store_row_words<P>(packed, rows_packed, r, k0, lo, hi);
-  }
+  s1_slice_rows4<P>(xr, r, in && live_exponent(e), e, q, K, Kp, rows_packed, packed);
 }
 
-// Slices with p and the row exponents read from device memory (the slice
-// count chosen on the device by the selector).
-__global__ __launch_bounds__(256) void k_s1_slice_rows_auto(const double* __restrict__ X, int64_t ldx, int64_t rows,
-                                                            int64_t K, int64_t Kp, int64_t rows_packed,
-                                                            const int32_t* __restrict__ e_in,
-                                                            const int32_t* __restrict__ p_dev,
-                                                            int8_t* __restrict__ packed) {
-  const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (r >= rows_packed || *p_dev < 1) return;  // p = 0: Scheme II was chosen
-  const int e = r < rows ? e_in[r] : OZK_EXP_ZERO;
-  const double* xr = X + r * ldx;  // read only for r < rows
-  switch (*p_dev) {
-    case 1: s1_slice_row<1>(xr, r, rows, K, Kp, rows_packed, e, packed); break;
-    case 2: s1_slice_row<2>(xr, r, rows, K, Kp, rows_packed, e, packed); break;
-    case 3: s1_slice_row<3>(xr, r, rows, K, Kp, rows_packed, e, packed); break;
-    case 4: s1_slice_row<4>(xr, r, rows, K, Kp, rows_packed, e, packed); break;
-    case 5: s1_slice_row<5>(xr, r, rows, K, Kp, rows_packed, e, packed); break;
-    case 6: s1_slice_row<6>(xr, r, rows, K, Kp, rows_packed, e, packed); break;
-    case 7: s1_slice_row<7>(xr, r, rows, K, Kp, rows_packed, e, packed); break;
-    default: s1_slice_row<8>(xr, r, rows, K, Kp, rows_packed, e, packed); break;
+// The slice kernel of the automatic path: the row exponents come from the
+// statistics pass (which read A once already) and p from device memory, so
+// A is read once more here, four rows per wave as in k_s1_split_rows4.
+__global__ __launch_bounds__(256) void k_s1_slice_rows4_auto(const double* __restrict__ X, int64_t ldx, int64_t rows,
+                                                             int64_t K, int64_t Kp, int64_t rows_packed,
+                                                             const int32_t* __restrict__ e_in,
+                                                             const int32_t* __restrict__ p_dev,
+                                                             int8_t* __restrict__ packed) {
+  const int p = *p_dev;
+  if (p < 1) return;  // p = 0: Scheme II was chosen
+  const int lane = threadIdx.x & 63, q = lane & 15;
+  const int64_t r = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 4 + (lane >> 4);
+  const bool in = r < rows;
+  const double* xr = X + (in ? r : 0) * ldx;
+  const int e = in ? e_in[r] : OZK_EXP_ZERO;
+  const bool live = in && live_exponent(e);
+  switch (p) {
+    case 1: s1_slice_rows4<1>(xr, r, live, e, q, K, Kp, rows_packed, packed); break;
+    case 2: s1_slice_rows4<2>(xr, r, live, e, q, K, Kp, rows_packed, packed); break;
+    case 3: s1_slice_rows4<3>(xr, r, live, e, q, K, Kp, rows_packed, packed); break;
+    case 4: s1_slice_rows4<4>(xr, r, live, e, q, K, Kp, rows_packed, packed); break;
+    case 5: s1_slice_rows4<5>(xr, r, live, e, q, K, Kp, rows_packed, packed); break;
+    case 6: s1_slice_rows4<6>(xr, r, live, e, q, K, Kp, rows_packed, packed); break;
+    case 7: s1_slice_rows4<7>(xr, r, live, e, q, K, Kp, rows_packed, packed); break;
+    default: s1_slice_rows4<8>(xr, r, live, e, q, K, Kp, rows_packed, packed); break;
   }
 }
 
@@ -589,7 +566,7 @@ hipError_t s1_slice_auto(const int32_t* p_dev, const double* A, int64_t lda, int
                          hipStream_t st) {
   const int64_t ra = round_up(M, OZK_ROW_ALIGN), rb = round_up(N, OZK_ROW_ALIGN), kp = round_up(K, OZK_K_CHUNK);
   if (ra > 0 && kp > 0)
-    hipLaunchKernelGGL(k_s1_slice_rows_auto, dim3((unsigned)(ra / 4)), dim3(256), 0, st, A, lda, M, K, kp, ra, e,
+    hipLaunchKernelGGL(k_s1_slice_rows4_auto, dim3((unsigned)(ra / 16)), dim3(256), 0, st, A, lda, M, K, kp, ra, e,
                        p_dev, Ap);
   if (rb > 0 && kp > 0)
     hipLaunchKernelGGL(k_s1_split_cols_auto, dim3((unsigned)(rb / 256), (unsigned)(kp / OZK_K_CHUNK)), dim3(256), 0,
@@ -597,19 +574,26 @@ hipError_t s1_slice_auto(const int32_t* p_dev, const double* A, int64_t lda, int
   return hipGetLastError();
 }
 
-// Every fixed-p kernel is launched; each returns at once unless p_dev holds
-// its slice count, so the chosen p runs with its own tiling and no host
-// round trip.
-static hipError_t launch_gemm_all(int out, const int32_t* p_dev, const S1GemmArgs& g, hipStream_t st) {
+// Every fixed-p kernel is launched, each with the tile variant and raster of
+// its own size class; each returns at once unless p_dev holds its slice
+// count, so the chosen p runs with its own tiling and no host round trip.
+static hipError_t launch_gemm_all(int out, const int32_t* p_dev, const S1GemmArgs& g, const int (*cfg)[3],
+                                  hipStream_t st) {
   hipError_t err = hipSuccess;
-  for (int p = 1; p <= OZK_MAX_P && err == hipSuccess; ++p) err = gemm_launch(p, out, g, p_dev, st);
+  for (int p = 1; p <= OZK_MAX_P && err == hipSuccess; ++p) {
+    S1GemmArgs gp = g;
+    gp.variant = cfg[p - 1][0];
+    gp.raster = cfg[p - 1][1];
+    gp.group = cfg[p - 1][2];
+    err = gemm_launch(p, out, gp, p_dev, st);
+  }
   return err;
 }
 
-hipError_t s1_gemm_auto(const int32_t* p_dev, const S1GemmArgs& g, hipStream_t st) {
+hipError_t s1_gemm_auto(const int32_t* p_dev, const S1GemmArgs& g, const int (*cfg)[3], hipStream_t st) {
   if (g.M == 0 || g.N == 0) return hipSuccess;
-  if (g.nsplit <= 1) return launch_gemm_all(S1_OUT_FINAL, p_dev, g, st);
-  hipError_t err = launch_gemm_all(S1_OUT_PARTIAL, p_dev, g, st);
+  if (g.nsplit <= 1) return launch_gemm_all(S1_OUT_FINAL, p_dev, g, cfg, st);
+  hipError_t err = launch_gemm_all(S1_OUT_PARTIAL, p_dev, g, cfg, st);
   return err == hipSuccess ? launch_fold(OZK_MAX_P, p_dev, g, st) : err;
 }
 

@@ -1298,62 +1298,76 @@ __device__ __forceinline__ bool s2_chosen(const int32_t* __restrict__ info, int&
   return s >= 1 && s <= OZK_MAX_S;
 }
 
+// The grids of these kernels are capped (AUTO_GRID workgroups, a multiple
+// of 8) and each workgroup walks its blocks with the grid as stride: when
+// Scheme I is chosen they dispatch a few workgroups that return at once
+// instead of a full grid.
+constexpr int64_t AUTO_GRID = 2048;
+
+__host__ __device__ constexpr int64_t auto_grid(int64_t blocks) { return blocks < AUTO_GRID ? blocks : AUTO_GRID; }
+
 template <bool CPLX>
 __global__ __launch_bounds__(256) void k_s2_split_rows_auto(const double* __restrict__ X, int64_t ldx, int64_t rows,
-                                                            int64_t K, int64_t Kp, int64_t rows_packed,
+                                                            int64_t K, int64_t Kp, int64_t rows_packed, int64_t nblk,
                                                             const int32_t* __restrict__ info, S2Budgets bud,
                                                             int32_t* __restrict__ sigma_out,
                                                             int8_t* __restrict__ packed) {
   int s;
   if (!s2_chosen(info, s)) return;
-  s2_split_rows_block<CPLX>(X, ldx, rows, K, Kp, rows_packed, S2Args{s, bud.ta[s]}, sigma_out, packed,
-                            blockIdx.x);
+  for (int64_t b = blockIdx.x; b < nblk; b += gridDim.x)
+    s2_split_rows_block<CPLX>(X, ldx, rows, K, Kp, rows_packed, S2Args{s, bud.ta[s]}, sigma_out, packed, b);
 }
 
 template <bool CPLX>
 __global__ __launch_bounds__(256) void k_s2_col_scales_auto(const double* __restrict__ X, int64_t ldx, int64_t K,
-                                                            int64_t cols, const int32_t* __restrict__ info,
-                                                            S2Budgets bud, int32_t* __restrict__ tau) {
+                                                            int64_t cols, int64_t nblk,
+                                                            const int32_t* __restrict__ info, S2Budgets bud,
+                                                            int32_t* __restrict__ tau) {
   int s;
   if (!s2_chosen(info, s)) return;
-  s2_col_scales_block<CPLX>(X, ldx, K, cols, bud.tb[s], tau, blockIdx.x);
+  for (int64_t b = blockIdx.x; b < nblk; b += gridDim.x) s2_col_scales_block<CPLX>(X, ldx, K, cols, bud.tb[s], tau, b);
 }
 
 template <bool CPLX>
 __global__ __launch_bounds__(256) void k_s2_split_cols_auto(const double* __restrict__ X, int64_t ldx, int64_t K,
                                                             int64_t cols, int64_t Kp, int64_t cols_packed,
+                                                            int64_t jblocks, int64_t nblk,
                                                             const int32_t* __restrict__ info,
                                                             const int32_t* __restrict__ tau,
                                                             int8_t* __restrict__ packed) {
   int s;
   if (!s2_chosen(info, s)) return;
-  s2_split_cols_block<CPLX>(X, ldx, K, cols, Kp, cols_packed, s, tau, packed, blockIdx.x, blockIdx.y);
+  for (int64_t b = blockIdx.x; b < nblk; b += gridDim.x)
+    s2_split_cols_block<CPLX>(X, ldx, K, cols, Kp, cols_packed, s, tau, packed, b % jblocks, b / jblocks);
 }
 
-// grid z covers OZK_MAX_S moduli; the planes past the chosen s return
+// Items (tile, modulus), modulus-major as the grid z of the fixed-s kernel;
+// the items of moduli past the chosen s are not visited.
 template <bool CPLX>
 __global__ __launch_bounds__(256, 1) void k_s2_gemm_mod_auto(const int8_t* __restrict__ Ap,
                                                             const int8_t* __restrict__ Bp, int64_t plane_a,
                                                             int64_t plane_b, int64_t rows_a, int64_t rows_b,
-                                                            int64_t nsteps, int M, int N,
+                                                            int64_t nsteps, int M, int N, int64_t tiles,
                                                             const int32_t* __restrict__ info,
                                                             int8_t* __restrict__ out) {
   extern __shared__ __attribute__((aligned(1024))) int8_t lds[];
   int s;
-  if (!s2_chosen(info, s) || (int)blockIdx.z >= s) return;
-  s2_gemm_tile<CPLX, 0>(Ap, Bp, plane_a, plane_b, rows_a, rows_b, nsteps, M, N, out, blockIdx.x, (int)blockIdx.z,
-                        0, 4, lds);
+  if (!s2_chosen(info, s)) return;
+  for (int64_t it = blockIdx.x; it < tiles * s; it += gridDim.x)
+    s2_gemm_tile<CPLX, 0>(Ap, Bp, plane_a, plane_b, rows_a, rows_b, nsteps, M, N, out, it % tiles, (int)(it / tiles),
+                          0, 4, lds);
 }
 
 template <bool CPLX>
-__global__ __launch_bounds__(256) void k_s2_crt_auto(int M, int N, const int8_t* __restrict__ res,
+__global__ __launch_bounds__(256) void k_s2_crt_auto(int M, int N, int64_t nblk, const int8_t* __restrict__ res,
                                                      const int32_t* __restrict__ sigma,
                                                      const int32_t* __restrict__ tau,
                                                      const int32_t* __restrict__ info, double a_re, double a_im,
                                                      double b_re, double b_im, double* __restrict__ C, int64_t ldc) {
   int s;
   if (!s2_chosen(info, s)) return;
-  s2_crt_block<CPLX>(c_crt_all[s - 1], M, N, res, sigma, tau, a_re, a_im, b_re, b_im, C, ldc, blockIdx.x);
+  for (int64_t b = blockIdx.x; b < nblk; b += gridDim.x)
+    s2_crt_block<CPLX>(c_crt_all[s - 1], M, N, res, sigma, tau, a_re, a_im, b_re, b_im, C, ldc, b);
 }
 
 S2Budgets s2_budgets() {
@@ -1374,12 +1388,13 @@ hipError_t s2_split_rows_auto(const int32_t* info, bool cplx, const double* X, i
                               int32_t* sigma, int8_t* packed, hipStream_t st) {
   const int64_t rp = round_up(rows, OZK_ROW_ALIGN), kp = round_up(K, OZK_K_CHUNK);
   if (rp > 0) {
-    const dim3 grid((unsigned)(rp / S2_ROWS_PER_BLOCK));
+    const int64_t nblk = rp / S2_ROWS_PER_BLOCK;
+    const dim3 grid((unsigned)auto_grid(nblk));
     if (cplx)
-      hipLaunchKernelGGL(k_s2_split_rows_auto<true>, grid, dim3(256), 0, st, X, ldx, rows, K, kp, rp, info,
+      hipLaunchKernelGGL(k_s2_split_rows_auto<true>, grid, dim3(256), 0, st, X, ldx, rows, K, kp, rp, nblk, info,
                          s2_budgets(), sigma, packed);
     else
-      hipLaunchKernelGGL(k_s2_split_rows_auto<false>, grid, dim3(256), 0, st, X, ldx, rows, K, kp, rp, info,
+      hipLaunchKernelGGL(k_s2_split_rows_auto<false>, grid, dim3(256), 0, st, X, ldx, rows, K, kp, rp, nblk, info,
                          s2_budgets(), sigma, packed);
   }
   return hipGetLastError();
@@ -1389,21 +1404,24 @@ hipError_t s2_split_cols_auto(const int32_t* info, bool cplx, const double* X, i
                               int32_t* tau, int8_t* packed, hipStream_t st) {
   const int64_t cp = round_up(cols, OZK_ROW_ALIGN), kp = round_up(K, OZK_K_CHUNK);
   if (cols > 0) {
-    const dim3 grid((unsigned)((cols + 31) / 32));
+    const int64_t nblk = (cols + 31) / 32;
+    const dim3 grid((unsigned)auto_grid(nblk));
     if (cplx)
-      hipLaunchKernelGGL(k_s2_col_scales_auto<true>, grid, dim3(256), 0, st, X, ldx, K, cols, info, s2_budgets(), tau);
+      hipLaunchKernelGGL(k_s2_col_scales_auto<true>, grid, dim3(256), 0, st, X, ldx, K, cols, nblk, info,
+                         s2_budgets(), tau);
     else
-      hipLaunchKernelGGL(k_s2_col_scales_auto<false>, grid, dim3(256), 0, st, X, ldx, K, cols, info, s2_budgets(),
-                         tau);
+      hipLaunchKernelGGL(k_s2_col_scales_auto<false>, grid, dim3(256), 0, st, X, ldx, K, cols, nblk, info,
+                         s2_budgets(), tau);
   }
   if (cp > 0 && kp > 0) {
-    const dim3 grid((unsigned)(cp / S2_COL_BLOCK), (unsigned)(kp / OZK_K_CHUNK));
+    const int64_t jblocks = cp / S2_COL_BLOCK, nblk = jblocks * (kp / OZK_K_CHUNK);
+    const dim3 grid((unsigned)auto_grid(nblk));
     if (cplx)
-      hipLaunchKernelGGL(k_s2_split_cols_auto<true>, grid, dim3(256), 0, st, X, ldx, K, cols, kp, cp, info, tau,
-                         packed);
+      hipLaunchKernelGGL(k_s2_split_cols_auto<true>, grid, dim3(256), 0, st, X, ldx, K, cols, kp, cp, jblocks, nblk,
+                         info, tau, packed);
     else
-      hipLaunchKernelGGL(k_s2_split_cols_auto<false>, grid, dim3(256), 0, st, X, ldx, K, cols, kp, cp, info, tau,
-                         packed);
+      hipLaunchKernelGGL(k_s2_split_cols_auto<false>, grid, dim3(256), 0, st, X, ldx, K, cols, kp, cp, jblocks, nblk,
+                         info, tau, packed);
   }
   return hipGetLastError();
 }
@@ -1423,9 +1441,9 @@ static hipError_t launch_gemm_mod_auto(const int32_t* info, int64_t M, int64_t N
   const int64_t kp = round_up(K, OZK_K_CHUNK);
   const int64_t ra = round_up(M, OZK_ROW_ALIGN), rb = round_up(N, OZK_ROW_ALIGN);
   const int64_t tiles = ((M + T::BM - 1) / T::BM) * ((N + T::BN - 1) / T::BN);
-  const dim3 grid((unsigned)tiles, 1, (unsigned)OZK_MAX_S);
+  const dim3 grid((unsigned)auto_grid(tiles * OZK_MAX_S));
   hipLaunchKernelGGL(k_s2_gemm_mod_auto<CPLX>, grid, dim3(256), Cfg::LDS_BYTES, st, Ap, Bp, ra * kp * Cfg::P,
-                     rb * kp * Cfg::P, ra, rb, kp / OZK_K_CHUNK, (int)M, (int)N, info, out);
+                     rb * kp * Cfg::P, ra, rb, kp / OZK_K_CHUNK, (int)M, (int)N, tiles, info, out);
   return hipGetLastError();
 }
 
@@ -1441,13 +1459,14 @@ hipError_t s2_crt_auto(const int32_t* info, bool cplx, int64_t M, int64_t N, con
                        hipStream_t st) {
   const int64_t n = M * N;
   if (n <= 0) return hipSuccess;
-  const dim3 grid((unsigned)((n + 255) / 256));
+  const int64_t nblk = (n + 255) / 256;
+  const dim3 grid((unsigned)auto_grid(nblk));
   if (cplx)
-    hipLaunchKernelGGL(k_s2_crt_auto<true>, grid, dim3(256), 0, st, (int)M, (int)N, res, sigma, tau, info, alpha[0],
-                       alpha[1], beta[0], beta[1], C, ldc);
+    hipLaunchKernelGGL(k_s2_crt_auto<true>, grid, dim3(256), 0, st, (int)M, (int)N, nblk, res, sigma, tau, info,
+                       alpha[0], alpha[1], beta[0], beta[1], C, ldc);
   else
-    hipLaunchKernelGGL(k_s2_crt_auto<false>, grid, dim3(256), 0, st, (int)M, (int)N, res, sigma, tau, info, alpha[0],
-                       0.0, beta[0], 0.0, C, ldc);
+    hipLaunchKernelGGL(k_s2_crt_auto<false>, grid, dim3(256), 0, st, (int)M, (int)N, nblk, res, sigma, tau, info,
+                       alpha[0], 0.0, beta[0], 0.0, C, ldc);
   return hipGetLastError();
 }
 
@@ -1502,26 +1521,47 @@ __global__ __launch_bounds__(256) void k_b_split_cols(BatchDev bd, int8_t* __res
                             ws + q.off_b, local % jblocks, local / jblocks);
 }
 
-// The batch GEMM takes the small tile (variant 4): its problems are small
-// and short in K, so each item is mostly prologue and epilogue latency, which
-// several resident workgroups per CU overlap.
+// Two batch GEMM tiles, chosen per problem by the plan (from the tuned
+// table, see ozk_batch_plan_create): the small tile (variant 4, 64 x 64,
+// several resident workgroups per CU overlapping the prologue and epilogue
+// latency of short items) and the large one (128 x 128: variant 1 for real
+// products, 2 for 3M), which reads half (real) or a quarter (3M) of the LDS
+// bytes per MFMA and pays off on the larger problems.
 constexpr int S2_BATCH_V = 4;
-static_assert(OZK_BATCH_ROW_ALIGN % GemmTile<1, S2Cfg<false, S2_BATCH_V>::TM, S2Cfg<false, S2_BATCH_V>::TN, 4>::BM == 0 &&
-                  OZK_BATCH_ROW_ALIGN % GemmTile<1, S2Cfg<true, S2_BATCH_V>::TM, S2Cfg<true, S2_BATCH_V>::TN, 4>::BN == 0 &&
+template <bool CPLX>
+struct S2BatchLarge {
+  static constexpr int V = CPLX ? 2 : 1;
+};
+template <bool CPLX, int V>
+constexpr int batch_rows() {
+  return GemmTile<S2Cfg<CPLX, V>::P, S2Cfg<CPLX, V>::TM, S2Cfg<CPLX, V>::TN, S2Cfg<CPLX, V>::NS>::BM;
+}
+template <bool CPLX, int V>
+constexpr int batch_cols() {
+  return GemmTile<S2Cfg<CPLX, V>::P, S2Cfg<CPLX, V>::TM, S2Cfg<CPLX, V>::TN, S2Cfg<CPLX, V>::NS>::BN;
+}
+static_assert(OZK_BATCH_ROW_ALIGN % batch_rows<false, S2_BATCH_V>() == 0 &&
+                  OZK_BATCH_ROW_ALIGN % batch_cols<false, S2_BATCH_V>() == 0 &&
+                  OZK_BATCH_ROW_ALIGN % batch_rows<true, S2_BATCH_V>() == 0 &&
+                  OZK_BATCH_ROW_ALIGN % batch_cols<true, S2_BATCH_V>() == 0 &&
+                  OZK_BATCH_ROW_ALIGN % batch_rows<false, S2BatchLarge<false>::V>() == 0 &&
+                  OZK_BATCH_ROW_ALIGN % batch_cols<false, S2BatchLarge<false>::V>() == 0 &&
+                  OZK_BATCH_ROW_ALIGN % batch_rows<true, S2BatchLarge<true>::V>() == 0 &&
+                  OZK_BATCH_ROW_ALIGN % batch_cols<true, S2BatchLarge<true>::V>() == 0 &&
                   OZK_BATCH_ROW_ALIGN % S2_ROWS_PER_BLOCK == 0 && OZK_BATCH_ROW_ALIGN % S2_COL_BLOCK == 0,
-              "batched packed rows cover whole tiles and pre-pass blocks");
+              "batched packed rows cover whole tiles of both sizes and whole pre-pass blocks");
 
 // One output tile of a batched problem for all s moduli.  The residue planes
 // of consecutive moduli are consecutive K chunks of the packed operands, so
 // the s GEMMs run as one K loop of s nsteps chunks whose load pipeline never
 // drains between moduli; the step hook stores a modulus's residues once its
 // last chunk is in (and reduces the sums at run ends, as above).
-template <bool CPLX>
+template <bool CPLX, int V>
 __device__ __forceinline__ void s2_gemm_tile_moduli(const int8_t* __restrict__ Ap, const int8_t* __restrict__ Bp,
                                                     int64_t rows_a, int64_t rows_b, int64_t nsteps, int64_t M,
                                                     int64_t N, int8_t* __restrict__ out, int64_t tile, int s,
                                                     int8_t* lds) {
-  using Cfg = S2Cfg<CPLX, S2_BATCH_V>;
+  using Cfg = S2Cfg<CPLX, V>;
   static_assert(Cfg::G == 1, "one K chunk per stage");
   constexpr int P = Cfg::P, TM = Cfg::TM, TN = Cfg::TN, NS = Cfg::NS;
   using T = GemmTile<P, TM, TN, NS>;
@@ -1556,15 +1596,19 @@ __device__ __forceinline__ void s2_gemm_tile_moduli(const int8_t* __restrict__ A
                                                    hook);
 }
 
-template <bool CPLX>
-__global__ __launch_bounds__(256, 3) void k_b_gemm_mod(BatchDev bd, int8_t* __restrict__ ws, int s) {
+// Persistent over the items of one tile size: workgroup w takes items w,
+// w + G, ... of `items` (problems in the order `order`).
+template <bool CPLX, int V>
+__global__ __launch_bounds__(256, V == S2_BATCH_V ? 3 : 1) void k_b_gemm_mod(BatchDev bd, BatchUnits items,
+                                                                            const int32_t* __restrict__ order,
+                                                                            int8_t* __restrict__ ws, int s) {
   extern __shared__ __attribute__((aligned(1024))) int8_t lds[];
-  const int64_t total = bd.items.start[bd.count];
+  const int64_t total = items.start[bd.count];
   for (int64_t it = blockIdx.x; it < total; it += gridDim.x) {
-    const int i = find_problem(bd.items, it);
-    const BatchProb& q = bd.prob[bd.order[i]];
-    s2_gemm_tile_moduli<CPLX>(ws + q.off_a, ws + q.off_b, q.ra, q.rb, q.Kp / OZK_K_CHUNK, q.M, q.N, ws + q.off_res,
-                              it - bd.items.start[i], s, lds);
+    const int i = find_problem(items, it);
+    const BatchProb& q = bd.prob[order[i]];
+    s2_gemm_tile_moduli<CPLX, V>(ws + q.off_a, ws + q.off_b, q.ra, q.rb, q.Kp / OZK_K_CHUNK, q.M, q.N,
+                                 ws + q.off_res, it - items.start[i], s, lds);
   }
 }
 
@@ -1577,44 +1621,82 @@ __global__ __launch_bounds__(256) void k_b_crt(CrtArgs ca, BatchDev bd, int8_t* 
                      blockIdx.x - bd.crt.start[p]);
 }
 
-int64_t s2_tile_count(bool cplx, int64_t M, int64_t N) {
-  using TC = GemmTile<3, S2Cfg<true, S2_BATCH_V>::TM, S2Cfg<true, S2_BATCH_V>::TN, S2Cfg<true, S2_BATCH_V>::NS>;
-  using TR = GemmTile<1, S2Cfg<false, S2_BATCH_V>::TM, S2Cfg<false, S2_BATCH_V>::TN, S2Cfg<false, S2_BATCH_V>::NS>;
-  const int bm = cplx ? TC::BM : TR::BM;
-  const int bn = cplx ? TC::BN : TR::BN;
+int64_t s2_tile_count(bool cplx, bool large, int64_t M, int64_t N) {
+  int bm, bn;
+  if (large) {
+    bm = cplx ? batch_rows<true, S2BatchLarge<true>::V>() : batch_rows<false, S2BatchLarge<false>::V>();
+    bn = cplx ? batch_cols<true, S2BatchLarge<true>::V>() : batch_cols<false, S2BatchLarge<false>::V>();
+  } else {
+    bm = cplx ? batch_rows<true, S2_BATCH_V>() : batch_rows<false, S2_BATCH_V>();
+    bn = cplx ? batch_cols<true, S2_BATCH_V>() : batch_cols<false, S2_BATCH_V>();
+  }
   return ((M + bm - 1) / bm) * ((N + bn - 1) / bn);
 }
 
-int s2_batch_gemm_blocks_per_cu(bool cplx) {
+template <bool CPLX, int V>
+static int batch_blocks_per_cu() {
   int n = 0;
-  const int lds = cplx ? S2Cfg<true, S2_BATCH_V>::LDS_BYTES : S2Cfg<false, S2_BATCH_V>::LDS_BYTES;
-  hipError_t e = cplx ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_b_gemm_mod<true>, 256, lds)
-                      : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_b_gemm_mod<false>, 256, lds);
+  const hipError_t e =
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_b_gemm_mod<CPLX, V>, 256, S2Cfg<CPLX, V>::LDS_BYTES);
   return (e == hipSuccess && n > 0) ? n : 1;
 }
 
-hipError_t s2_batched(int s, bool cplx, const BatchDev& bd, const BatchTotals& tot, int8_t* ws, int gemm_grid,
-                      hipStream_t st) {
+int s2_batch_gemm_blocks_per_cu(bool cplx, bool large) {
+  if (large) return cplx ? batch_blocks_per_cu<true, 2>() : batch_blocks_per_cu<false, 1>();
+  return cplx ? batch_blocks_per_cu<true, S2_BATCH_V>() : batch_blocks_per_cu<false, S2_BATCH_V>();
+}
+
+template <bool CPLX, int V>
+static hipError_t launch_batch_gemm(const BatchDev& bd, const BatchUnits& items, const int32_t* order, int64_t n,
+                                    int grid, int8_t* ws, int s, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  constexpr int lds = S2Cfg<CPLX, V>::LDS_BYTES;
+  static bool attr = false;
+  if (!attr) {
+    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_b_gemm_mod<CPLX, V>),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  hipLaunchKernelGGL((k_b_gemm_mod<CPLX, V>), dim3((unsigned)grid), dim3(256), lds, st, bd, items, order, ws, s);
+  return hipGetLastError();
+}
+
+// The GEMM step of a batch: the large-tile items, then the small-tile ones.
+hipError_t s2_batched_gemm(int s, bool cplx, const BatchDev& bd, const BatchTotals& tot, int8_t* ws, int grid_small,
+                           int grid_large, hipStream_t st) {
+  hipError_t e = cplx ? launch_batch_gemm<true, 2>(bd, bd.items_l, bd.order_l, tot.items_l, grid_large, ws, s, st)
+                      : launch_batch_gemm<false, 1>(bd, bd.items_l, bd.order_l, tot.items_l, grid_large, ws, s, st);
+  if (e != hipSuccess) return e;
+  return cplx ? launch_batch_gemm<true, S2_BATCH_V>(bd, bd.items, bd.order, tot.items, grid_small, ws, s, st)
+              : launch_batch_gemm<false, S2_BATCH_V>(bd, bd.items, bd.order, tot.items, grid_small, ws, s, st);
+}
+
+hipError_t s2_batched_prepass(int s, bool cplx, const BatchDev& bd, const BatchTotals& tot, int8_t* ws,
+                              hipStream_t st) {
   int ta, tb;
   CrtArgs ca;
   crt_args(s, ca, ta, tb);
-  if (tot.rows == 0 || tot.crt == 0) return hipSuccess;
+  if (tot.rows == 0) return hipSuccess;
   S2Args sa{s, ta};
-  const int lds = cplx ? S2Cfg<true, S2_BATCH_V>::LDS_BYTES : S2Cfg<false, S2_BATCH_V>::LDS_BYTES;
-  static bool attr[2] = {false, false};
-  if (!attr[cplx]) {
-    hipError_t e = cplx ? hipFuncSetAttribute(reinterpret_cast<const void*>(k_b_gemm_mod<true>),
-                                              hipFuncAttributeMaxDynamicSharedMemorySize, lds)
-                        : hipFuncSetAttribute(reinterpret_cast<const void*>(k_b_gemm_mod<false>),
-                                              hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    if (e != hipSuccess) return e;
-    attr[cplx] = true;
-  }
   if (cplx) {
     hipLaunchKernelGGL(k_b_split_rows<true>, dim3((unsigned)tot.rows), dim3(256), 0, st, bd, ws, sa);
     hipLaunchKernelGGL(k_b_col_scales<true>, dim3((unsigned)tot.cols), dim3(256), 0, st, bd, ws, tb);
     if (tot.split) hipLaunchKernelGGL(k_b_split_cols<true>, dim3((unsigned)tot.split), dim3(256), 0, st, bd, ws, s);
-    if (tot.items) hipLaunchKernelGGL(k_b_gemm_mod<true>, dim3((unsigned)gemm_grid), dim3(256), lds, st, bd, ws, s);
+  } else {
+    hipLaunchKernelGGL(k_b_split_rows<false>, dim3((unsigned)tot.rows), dim3(256), 0, st, bd, ws, sa);
+    hipLaunchKernelGGL(k_b_col_scales<false>, dim3((unsigned)tot.cols), dim3(256), 0, st, bd, ws, tb);
+    if (tot.split) hipLaunchKernelGGL(k_b_split_cols<false>, dim3((unsigned)tot.split), dim3(256), 0, st, bd, ws, s);
+  }
+  return hipGetLastError();
+}
+
+hipError_t s2_batched_crt(int s, bool cplx, const BatchDev& bd, const BatchTotals& tot, int8_t* ws, hipStream_t st) {
+  int ta, tb;
+  CrtArgs ca;
+  crt_args(s, ca, ta, tb);
+  if (tot.crt == 0) return hipSuccess;
+  if (cplx) {
     switch (crt_limbs(ca)) {
       case 1: case 2: case 3: case 4:
         hipLaunchKernelGGL((k_b_crt<true, 4>), dim3((unsigned)tot.crt), dim3(256), 0, st, ca, bd, ws); break;
@@ -1622,11 +1704,6 @@ hipError_t s2_batched(int s, bool cplx, const BatchDev& bd, const BatchTotals& t
       default: hipLaunchKernelGGL((k_b_crt<true, NL>), dim3((unsigned)tot.crt), dim3(256), 0, st, ca, bd, ws);
     }
   } else {
-    hipLaunchKernelGGL(k_b_split_rows<false>, dim3((unsigned)tot.rows), dim3(256), 0, st, bd, ws, sa);
-    hipLaunchKernelGGL(k_b_col_scales<false>, dim3((unsigned)tot.cols), dim3(256), 0, st, bd, ws, tb);
-    if (tot.split) hipLaunchKernelGGL(k_b_split_cols<false>, dim3((unsigned)tot.split), dim3(256), 0, st, bd, ws, s);
-    if (tot.items)
-      hipLaunchKernelGGL(k_b_gemm_mod<false>, dim3((unsigned)gemm_grid), dim3(256), lds, st, bd, ws, s);
     switch (crt_limbs(ca)) {
       case 1: case 2: case 3: case 4:
         hipLaunchKernelGGL((k_b_crt<false, 4>), dim3((unsigned)tot.crt), dim3(256), 0, st, ca, bd, ws); break;
@@ -1635,6 +1712,15 @@ hipError_t s2_batched(int s, bool cplx, const BatchDev& bd, const BatchTotals& t
     }
   }
   return hipGetLastError();
+}
+
+hipError_t s2_batched(int s, bool cplx, const BatchDev& bd, const BatchTotals& tot, int8_t* ws, int grid_small,
+                      int grid_large, hipStream_t st) {
+  if (tot.rows == 0 || tot.crt == 0) return hipSuccess;
+  hipError_t e = s2_batched_prepass(s, cplx, bd, tot, ws, st);
+  if (e == hipSuccess) e = s2_batched_gemm(s, cplx, bd, tot, ws, grid_small, grid_large, st);
+  if (e == hipSuccess) e = s2_batched_crt(s, cplx, bd, tot, ws, st);
+  return e;
 }
 
 }  // namespace ozk

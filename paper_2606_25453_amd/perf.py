@@ -304,6 +304,10 @@ def batch(torch, ctx, count, s, reps):
         flops += 8.0 * M * N * K
         ops += 6 * s * M * N * K
     plan = ozk.BatchPlan(ctx, ozk.OZK_OP_ZGEMM, ozk.OZK_SCHEME2, s, list(zip(dA, dB, dC)))
+    default_tiles = plan.tiles()
+    ms_default = time_call(torch, plan.run, reps)
+    plan.tune(reps=3)  # the tile of each size class, on these problems
+    tiles = plan.tiles()
     side = torch.cuda.Stream()
     side.wait_stream(torch.cuda.current_stream())
     graph = torch.cuda.CUDAGraph()
@@ -318,7 +322,9 @@ def batch(torch, ctx, count, s, reps):
     plan.close()
     return {"path": "batch_zgemm_3m", "count": count, "s": s, "ms_graph": round(ms_graph, 4),
             "ms_eager": round(ms_eager, 4), "tflops": round(flops / ms_graph / 1e9, 3), "int8_ops": ops,
-            "end_to_end_frac_int8_peak": round(ops / ms_graph / 1e9 / INT8_PEAK_TOPS, 4)}
+            "end_to_end_frac_int8_peak": round(ops / ms_graph / 1e9 / INT8_PEAK_TOPS, 4),
+            "large_tile_problems": sum(tiles), "ms_eager_untuned": round(ms_default, 4),
+            "large_tile_problems_untuned": sum(default_tiles)}
 
 
 def auto(torch, ctx, n, tol, reps):

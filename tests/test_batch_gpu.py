@@ -138,6 +138,80 @@ def test_batch_config_256_uneven_zgemm(ctx):
     plan = ozk.BatchPlan(ctx, ozk.OZK_OP_ZGEMM, ozk.OZK_SCHEME2, s, list(zip(dA, dB, dC)))
     plan.run()
     torch.cuda.synchronize()
-    for i in (0, 17, 101, 255):
+    tiles = plan.tiles()
+    assert 0 < sum(tiles) < count  # both tiles in use
+    for i in range(count):
         assert torch.equal(dC[i], ozk.ozk_zgemm_3m(ctx, s, dA[i], dB[i])), i
     plan.close()
+
+
+def _device_batch(probs):
+    dA = [dev(A) for A, _ in probs]
+    dB = [dev(B) for _, B in probs]
+    dtype = dA[0].dtype
+    dC = [torch.full((A.shape[0], B.shape[1]), float("nan"), dtype=dtype, device="cuda:0") for A, B in probs]
+    return dA, dB, dC
+
+
+@pytest.mark.parametrize("cplx", [False, True])
+def test_batch_tiles_from_the_table_are_bit_identical(cplx):
+    """Every problem on the small tile, every problem on the large tile (the
+    table entries of the batched op code decide), and the default choice:
+    the same results as the single calls."""
+    s = 10
+    probs = make_batch(14, 30, 420, 900 + int(cplx), cplx)
+    dA, dB, dC = _device_batch(probs)
+    op = ozk.OZK_OP_ZGEMM if cplx else ozk.OZK_OP_DGEMM
+    bop = ozk.OZK_OP_ZGEMM_BATCHED if cplx else ozk.OZK_OP_DGEMM_BATCHED
+    singles = []
+    ctx = ozk.Context(0)
+    try:
+        for i in range(len(probs)):
+            singles.append(host(ozk.ozk_zgemm_3m(ctx, s, dA[i], dB[i]) if cplx else
+                                ozk.ozk_dgemm(ctx, ozk.OZK_SCHEME2, s, dA[i], dB[i])))
+        default = ozk.BatchPlan(ctx, op, ozk.OZK_SCHEME2, s, list(zip(dA, dB, dC)))
+        expect = [int(A.shape[0] >= 256 and B.shape[1] >= 256) for A, B in probs]
+        assert default.tiles() == expect
+        default.close()
+        for kind in (0, 1):
+            for A, B in probs:
+                ozk.ozk_config_set(ctx, bop, ozk.OZK_SCHEME2, s, A.shape[0], B.shape[1], A.shape[1], (kind, 0, 4, 1))
+            plan = ozk.BatchPlan(ctx, op, ozk.OZK_SCHEME2, s, list(zip(dA, dB, dC)))
+            assert plan.tiles() == [kind] * len(probs)
+            for c in dC:
+                c.fill_(float("nan"))
+            plan.run()
+            for i in range(len(probs)):
+                assert np.array_equal(host(dC[i]), singles[i]), (kind, i)
+            plan.close()
+        with pytest.raises(ozk.OzkError):  # batch tiles are 0 or 1
+            ozk.ozk_config_set(ctx, bop, ozk.OZK_SCHEME2, s, 64, 64, 64, (2, 0, 4, 1))
+    finally:
+        ctx.close()
+
+
+def test_tune_batch_picks_tiles_and_stores_them():
+    s = 16
+    probs = make_batch(24, 40, 700, 950, True)
+    dA, dB, dC = _device_batch(probs)
+    ctx = ozk.Context(0)
+    try:
+        plan = ozk.BatchPlan(ctx, ozk.OZK_OP_ZGEMM, ozk.OZK_SCHEME2, s, list(zip(dA, dB, dC)))
+        plan.tune(reps=2)
+        tiles = plan.tiles()
+        for i, (A, B) in enumerate(probs):
+            assert np.array_equal(host(dC[i]), host(ozk.ozk_zgemm_3m(ctx, s, dA[i], dB[i]))), i
+            cfg, found, ms = ozk.ozk_config_get(ctx, ozk.OZK_OP_ZGEMM_BATCHED, ozk.OZK_SCHEME2, s, A.shape[0],
+                                                B.shape[1], A.shape[1])
+            assert found and cfg[0] == tiles[i] and ms > 0, (i, cfg, tiles[i])
+        again = ozk.BatchPlan(ctx, ozk.OZK_OP_ZGEMM, ozk.OZK_SCHEME2, s, list(zip(dA, dB, dC)))
+        assert again.tiles() == tiles  # a new plan of the context takes the tuned tiles
+        for c in dC:
+            c.fill_(float("nan"))
+        again.run()
+        for i in range(len(probs)):
+            assert np.array_equal(host(dC[i]), host(ozk.ozk_zgemm_3m(ctx, s, dA[i], dB[i]))), i
+        again.close()
+        plan.close()
+    finally:
+        ctx.close()

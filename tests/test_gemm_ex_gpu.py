@@ -1,0 +1,98 @@
+"""ozk_gemm_ex: every element type, row- and column-major storage and
+transposed operands give results bit-identical to the row-major calls on the
+explicit operands (and hence to the oracle those calls are checked against)."""
+import ctypes
+import itertools
+
+import numpy as np
+import pytest
+
+import paper_2606_25453_amd as ozk
+import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = ozk.Context(0)
+    yield c
+    c.close()
+
+
+def stored(X, trans: bool, col: bool, dtype):
+    """A CUDA tensor holding X (trans: X.T) in the given storage order."""
+    Y = np.ascontiguousarray(X.T if trans else X)
+    t = torch.from_numpy(np.ascontiguousarray(Y.T)).to(dtype).cuda().T if col else \
+        torch.from_numpy(Y).to(dtype).cuda()
+    return t
+
+
+def reference(ctx, dtype, scheme, count, A, B, C0, alpha, beta):
+    a = torch.from_numpy(A).to(dtype).cuda()
+    b = torch.from_numpy(B).to(dtype).cuda()
+    c = torch.from_numpy(C0).to(dtype).cuda()
+    if dtype == torch.float64:
+        return ozk.ozk_dgemm(ctx, scheme, count, a, b, C=c, alpha=alpha.real, beta=beta.real)
+    if dtype == torch.float32:
+        return ozk.ozk_sgemm(ctx, scheme, count, a, b, C=c, alpha=alpha.real, beta=beta.real)
+    if dtype == torch.complex128:
+        return ozk.ozk_zgemm(ctx, scheme, count, a, b, C=c, alpha=alpha, beta=beta)
+    return ozk.ozk_cgemm(ctx, scheme, count, a, b, C=c, alpha=alpha, beta=beta)
+
+
+CASES = [(torch.float64, 1, 6), (torch.float64, 2, 12), (torch.float32, 1, 3), (torch.float32, 2, 9),
+         (torch.complex128, 1, 5), (torch.complex128, 2, 14), (torch.complex64, 1, 2), (torch.complex64, 2, 8)]
+
+
+@pytest.mark.parametrize("dtype,scheme,count", CASES)
+def test_layouts_and_transposes(ctx, dtype, scheme, count):
+    M, N, K = 75, 130, 97
+    cplx = dtype.is_complex
+    if cplx:
+        A = synth.complex_phi_matrix(M, K, 1.0, 5100, 5101)
+        B = synth.complex_phi_matrix(K, N, 1.0, 5102, 5103)
+        C0 = synth.complex_phi_matrix(M, N, 1.0, 5104, 5105)
+        alpha, beta = 0.75 - 0.5j, -1.25 + 0.25j
+    else:
+        A = synth.phi_matrix(M, K, 1.0, 5100)
+        B = synth.phi_matrix(K, N, 1.0, 5102)
+        C0 = synth.phi_matrix(M, N, 1.0, 5104)
+        alpha, beta = 0.75 + 0j, -1.25 + 0j
+    want = reference(ctx, dtype, scheme, count, A, B, C0, alpha, beta)
+    torch.cuda.synchronize()
+    for col, ta, tb in itertools.product((False, True), (False, True), (False, True)):
+        a, b = stored(A, ta, col, dtype), stored(B, tb, col, dtype)
+        c = stored(C0, False, col, dtype)
+        if scheme == 1 and cplx and (ta or tb):
+            with pytest.raises(ozk.OzkError) as ei:
+                ozk.ozk_gemm_ex(ctx, scheme, count, a, b, C=c, trans_a=ta, trans_b=tb, alpha=alpha, beta=beta)
+            assert ei.value.status == ozk.OZK_ERR_UNSUPPORTED
+            continue
+        got = ozk.ozk_gemm_ex(ctx, scheme, count, a, b, C=c, trans_a=ta, trans_b=tb, alpha=alpha, beta=beta)
+        torch.cuda.synchronize()
+        assert torch.equal(got.contiguous(), want), (col, ta, tb)
+
+
+def test_gemm_ex_argument_errors(ctx):
+    lib = ozk.library()
+    A = torch.ones((4, 4), dtype=torch.float64, device="cuda:0")
+    one = (ctypes.c_double * 2)(1.0, 0.0)
+    p = ctypes.cast(one, ctypes.c_void_p)
+    ws = torch.empty(1 << 20, dtype=torch.uint8, device="cuda:0")
+    st = lib.ozk_gemm_ex(ctx.handle, 7, 0, 0, 0, 1, 4, 4, 4, 4, p, A.data_ptr(), 4, A.data_ptr(), 4, p, A.data_ptr(), 4,
+                         ws.data_ptr(), ws.numel(), None)
+    assert st == ozk.OZK_ERR_INVALID_ARG and lib.ozk_last_arg(ctx.handle) == 2
+    st = lib.ozk_gemm_ex(ctx.handle, 0, 2, 0, 0, 1, 4, 4, 4, 4, p, A.data_ptr(), 4, A.data_ptr(), 4, p, A.data_ptr(), 4,
+                         ws.data_ptr(), ws.numel(), None)
+    assert st == ozk.OZK_ERR_INVALID_ARG and lib.ozk_last_arg(ctx.handle) == 3
+    # column-major: lda must cover a stored column (M rows of A when not transposed)
+    st = lib.ozk_gemm_ex(ctx.handle, 0, 1, 0, 0, 1, 4, 6, 4, 4, p, A.data_ptr(), 5, A.data_ptr(), 4, p, A.data_ptr(), 6,
+                         ws.data_ptr(), ws.numel(), None)
+    assert st == ozk.OZK_ERR_INVALID_ARG and lib.ozk_last_arg(ctx.handle) == 13  # M = 6 rows, lda = 5
+    st = lib.ozk_gemm_ex(ctx.handle, 0, 0, 0, 0, 1, 9, 4, 4, 4, p, A.data_ptr(), 4, A.data_ptr(), 4, p, A.data_ptr(), 4,
+                         ws.data_ptr(), ws.numel(), None)
+    assert st == ozk.OZK_ERR_UNSUPPORTED and lib.ozk_last_arg(ctx.handle) == 7
