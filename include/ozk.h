@@ -88,7 +88,7 @@ extern "C" {
 #define OZK_MAX_ROWS 16777216       /* 2^24: largest M, N (32-bit packed offsets) */
 #define OZK_S2_MAX_K 4194304        /* 2^22: longest K of a Scheme II product (see below) */
 #define OZK_S1_VARIANTS 4           /* Scheme I GEMM tile variants */
-#define OZK_S2_VARIANTS 5           /* Scheme II GEMM variants (the last: fused CRT) */
+#define OZK_S2_VARIANTS 7           /* Scheme II GEMM variants (4: fused CRT) */
 #define OZK_S2_FUSED_CRT 4          /* Scheme II variant with the CRT fused into the GEMM (real only) */
 #define OZK_NOALLOC_SCRATCH_BYTES 67108864  /* 64 MiB: the fixed buffer of ozk_dgemm_noalloc */
 #define OZK_SELECTOR_PARAMS 8220   /* float32 parameters of the selector MLP */
@@ -686,7 +686,10 @@ ozk_status ozk_tune_batch(ozk_ctx* ctx, ozk_batch_plan* plan, void* ws,
  *            128x128 / 128x64, taken only while K <= 131040 and replaced by
  *            the base tile beyond; bit 0: the other LDS staging depth: K
  *            chunks per stage and stages 2 x 4 (variant 0), 1 x 4 (1),
- *            2 x 4 or 3M 1 x 4 (2), 2 x 3 (3)); variant OZK_S2_FUSED_CRT (4)
+ *            2 x 4 or 3M 1 x 4 (2), 2 x 3 (3)); variants 5 and 6: the large
+ *            tiles with other stagings (real 256x128 with 4 x 2, 256x256 with
+ *            3 x 2; 3M 128x128 with 2 x 3, 1 x 6), replaced by variants 1 and
+ *            0 beyond K = 131040; variant OZK_S2_FUSED_CRT (4)
  *            fuses the CRT into the GEMM of a real product (64x64 tiles
  *            running all s moduli, the CRT sums in registers, C written
  *            directly, no residue planes; the paper keeps the CRT in a

@@ -40,7 +40,7 @@ OZK_SELECTOR_INFO = 8
 OZK_MAX_ROWS = 1 << 24
 OZK_S2_MAX_K = 1 << 22
 OZK_S1_VARIANTS = 4
-OZK_S2_VARIANTS = 5
+OZK_S2_VARIANTS = 7
 OZK_S2_FUSED_CRT = 4
 OZK_NOALLOC_SCRATCH_BYTES = 64 << 20
 OZK_FLAG_NONFINITE = 1

@@ -476,15 +476,21 @@ constexpr int64_t S2_RUN_STEPS = 4095;
 // tile per wave, one chunk per stage, two stages; it needs few registers and
 // little LDS, so four workgroups share a CU and hide each other's per-item
 // latency.
+// Variants 5 and 6: the large tiles with other stagings (real: 256 x 128
+// with G = 4 over 2 stages, 256 x 256 with G = 3 over 2 stages -- one barrier
+// per more MFMAs; 3M: 128 x 128 with G = 2 over 3 stages, G = 1 over 6
+// stages -- more chunks in flight), within the registers that two sets of
+// step fragments and the accumulators leave.
 template <bool CPLX, int V = 0>
 struct S2Cfg {
   static constexpr int P = CPLX ? 3 : 1;
-  static constexpr bool LARGE = V == 2 || V == 3;
+  static constexpr bool LARGE = V == 2 || V == 3 || V == 5 || V == 6;
   static constexpr bool SMALL = V == 4;
   static constexpr int TM = SMALL ? 1 : LARGE && !CPLX ? 4 : 2;
-  static constexpr int TN = SMALL ? 1 : (V == 3 && !CPLX) ? 4 : CPLX && !LARGE ? 1 : 2;
-  static constexpr int NS = V == 3 ? 3 : V == 4 ? 2 : 4;
-  static constexpr int G = V == 0 ? 2 : V == 1 || V == 4 ? 1 : V == 2 ? (CPLX ? 1 : 2) : 2;
+  static constexpr int TN = SMALL ? 1 : ((V == 3 || V == 6) && !CPLX) ? 4 : CPLX && !LARGE ? 1 : 2;
+  static constexpr int NS = V == 3 ? 3 : V == 4 ? 2 : V == 5 ? (CPLX ? 3 : 2) : V == 6 ? (CPLX ? 6 : 2) : 4;
+  static constexpr int G = V == 0 ? 2 : V == 1 || V == 4 ? 1 : V == 2 ? (CPLX ? 1 : 2) : V == 5 ? (CPLX ? 2 : 4)
+                                       : V == 6 ? (CPLX ? 1 : 3) : 2;
   static constexpr int LDS_BYTES = GemmTile<G * P, TM, TN, NS>::LDS_BYTES;
   static_assert(LDS_BYTES <= 160 * 1024, "LDS budget");
 };
@@ -1030,7 +1036,7 @@ static hipError_t launch_gemm_mod(int s, int64_t M, int64_t N, int64_t K, const 
 hipError_t s2_gemm_mod(int s, bool cplx, int64_t M, int64_t N, int64_t K, const int8_t* Ap, const int8_t* Bp,
                        int8_t* out, hipStream_t st, int variant, int raster, int group) {
   if (M == 0 || N == 0) return hipSuccess;
-  static_assert(OZK_S2_VARIANTS == 5 && OZK_S2_FUSED_CRT == 4, "the variant switch below covers four tile variants");
+  static_assert(OZK_S2_VARIANTS == 7 && OZK_S2_FUSED_CRT == 4, "the variant switch below covers six tile variants");
   if (variant == OZK_S2_FUSED_CRT) variant = 0;  // residue planes wanted: the separate-kernel form
   if (variant >= 2 && round_up(K, OZK_K_CHUNK) / OZK_K_CHUNK > S2_RUN_STEPS) variant &= 1;  // large tiles: one run
   switch (variant) {
@@ -1043,6 +1049,12 @@ hipError_t s2_gemm_mod(int s, bool cplx, int64_t M, int64_t N, int64_t K, const 
     case 3:
       return cplx ? launch_gemm_mod<true, 3>(s, M, N, K, Ap, Bp, out, raster, group, st)
                   : launch_gemm_mod<false, 3>(s, M, N, K, Ap, Bp, out, raster, group, st);
+    case 5:
+      return cplx ? launch_gemm_mod<true, 5>(s, M, N, K, Ap, Bp, out, raster, group, st)
+                  : launch_gemm_mod<false, 5>(s, M, N, K, Ap, Bp, out, raster, group, st);
+    case 6:
+      return cplx ? launch_gemm_mod<true, 6>(s, M, N, K, Ap, Bp, out, raster, group, st)
+                  : launch_gemm_mod<false, 6>(s, M, N, K, Ap, Bp, out, raster, group, st);
   }
   return cplx ? launch_gemm_mod<true, 0>(s, M, N, K, Ap, Bp, out, raster, group, st)
               : launch_gemm_mod<false, 0>(s, M, N, K, Ap, Bp, out, raster, group, st);

@@ -128,7 +128,7 @@ def test_cgemm_4m_bit_exact(ctx, p, shape):
     assert np.array_equal(got2, s2.z3m_cgemm(A, B, 8))
 
 
-@pytest.mark.parametrize("n,p", [(2048, 7), (4096, 7)])
+@pytest.mark.parametrize("n,p", [(2048, 7), (4096, 7), (8192, 7)])
 def test_zgemm_4m_large_sampled(ctx, n, p):
     """Full-size 4M ZGEMM: sampled rows and columns against the oracle (the
     exponents of a row of A and a column of B depend on nothing else), and

@@ -66,3 +66,28 @@ def test_unfused_scheme2_limits(ctx):
     got = host(ozk.ozk_s2_gemm_unfused(ctx, 20, A, B))
     assert np.array_equal(got, host(ozk.ozk_dgemm(ctx, ozk.OZK_SCHEME2, 20, A, B)))
     assert np.array_equal(got, np.full((2, 3), -float(K)))
+
+
+@pytest.mark.parametrize("cplx,s", [(False, 14), (True, 16)])
+def test_unfused_at_the_measured_size(ctx, cplx, s):
+    """4096^3, the size the ablation is measured at: the unfused result is the
+    fused one everywhere and the oracle's on sampled rows and columns."""
+    n = 4096
+    if cplx:
+        A = torch.complex(synth.phi_matrix_device(n, n, 1.0, 5300), synth.phi_matrix_device(n, n, 1.0, 5302))
+        B = torch.complex(synth.phi_matrix_device(n, n, 1.0, 5301), synth.phi_matrix_device(n, n, 1.0, 5303))
+        fused = ozk.ozk_zgemm_3m(ctx, s, A, B)
+    else:
+        A = synth.phi_matrix_device(n, n, 1.0, 5300)
+        B = synth.phi_matrix_device(n, n, 1.0, 5301)
+        fused = ozk.ozk_dgemm(ctx, ozk.OZK_SCHEME2, s, A, B)
+    got = ozk.ozk_s2_gemm_unfused(ctx, s, A, B)
+    torch.cuda.synchronize()
+    assert torch.equal(got, fused)
+    rng = np.random.default_rng(s)
+    rows = np.unique(rng.integers(0, n, 10))
+    cols = np.unique(rng.integers(0, n, 10))
+    r, c = torch.from_numpy(rows).cuda(), torch.from_numpy(cols).cuda()
+    As, Bs = A.index_select(0, r).cpu().numpy(), B.index_select(1, c).cpu().numpy()
+    sub = got.index_select(0, r).index_select(1, c).cpu().numpy()
+    assert np.array_equal(sub, s2.z3m_gemm(As, Bs, s) if cplx else s2.s2_dgemm(As, Bs, s))
