@@ -272,10 +272,16 @@ ozk_status ozk_dgemm_t(ozk_ctx* ctx, ozk_scheme scheme, int p_or_s, int trans_a,
  * op(A)^T of the same memory (the operands swap, each transposed exactly
  * when the other one was), and a transposed operand is read by the other
  * pre-pass kernel: each row of op(A) and each column of op(B) keeps its
- * scale, the integer sums are the same, so results are bit-identical to
- * ozk_dgemm / ozk_sgemm / ozk_zgemm / ozk_cgemm on the explicit row-major
- * operands.  Schemes and counts as those calls; Scheme I complex (4M) takes
- * no transposed operand (OZK_ERR_UNSUPPORTED, arg 4 or 5: its embedding is
+ * scale (and, Scheme II, its bit budget), the integer sums are the same, so
+ * results are bit-identical to ozk_dgemm / ozk_sgemm / ozk_zgemm /
+ * ozk_cgemm on the explicit row-major operands.  One exception: the Scheme
+ * I complex product of column-major operands is the 4M product of the
+ * transposed problem, B^T A^T, whose embedding negates the imaginary parts
+ * of A instead of B; Scheme I drops slice pairs of the balanced digits,
+ * whose expansion of -x is not the negated expansion of x, so its last bits
+ * differ from the row-major call while the error bound is the same.
+ * Schemes and counts as those calls; Scheme I complex (4M) takes no
+ * transposed operand (OZK_ERR_UNSUPPORTED, arg 4 or 5: its embedding is
  * built from stored rows of op(A) and columns of op(B)).  Workspace:
  * ozk_workspace_size(ctx, F64/F32 -> OZK_OP_DGEMM, C128/C64 -> OZK_OP_ZGEMM,
  * scheme, M', N', K, p_or_s) with (M', N') = (M, N) for row-major and

@@ -468,10 +468,14 @@ ozk_status ozk_s1_diagonals(ozk_ctx* ctx, int p, int64_t M, int64_t N, int64_t K
 
 // The DGEMM pipeline after argument checks; trans_a / trans_b: the operand
 // is stored transposed (A as K x M, B as N x K, row-major).
+// swap_budgets: the row operand takes Scheme II's column budget T_B and the
+// column operand T_A (a column-major problem run as its row-major transpose
+// keeps each operand's own budget; T_A and T_B differ by one bit when
+// ceil(log2 P) is odd).
 static ozk_status dgemm_run(ozk_ctx* ctx, ozk_scheme scheme, int p_or_s, bool trans_a, bool trans_b, int64_t M,
                             int64_t N, int64_t K, double alpha, const double* A, int64_t lda, const double* B,
                             int64_t ldb, double beta, double* C, int64_t ldc, void* ws, size_t ws_bytes,
-                            hipStream_t stream, int ws_arg) {
+                            hipStream_t stream, int ws_arg, bool swap_budgets = false) {
   if (scheme == OZK_SCHEME2) {
     const int s = p_or_s;
     if (s < 1 || s > OZK_MAX_S) return fail(ctx, OZK_ERR_UNSUPPORTED, 3);
@@ -488,12 +492,13 @@ static ozk_status dgemm_run(ozk_ctx* ctx, ozk_scheme scheme, int p_or_s, bool tr
     int8_t* res = (int8_t*)(w + pl.off_res);
     int ta_bits, tb_bits;
     ozk::s2_targets(s, ta_bits, tb_bits);
+    if (swap_budgets) std::swap(ta_bits, tb_bits);
     // a transposed operand is read by the other pass, with its own bit budget
     hipError_t err = trans_a ? ozk::s2_split_cols(s, false, A, lda, K, M, sig, Ap, stream, ta_bits)
-                             : ozk::s2_split_rows(s, false, A, lda, M, K, sig, Ap, stream);
+                             : ozk::s2_split_rows(s, false, A, lda, M, K, sig, Ap, stream, ta_bits);
     if (err == hipSuccess)
       err = trans_b ? ozk::s2_split_rows(s, false, B, ldb, N, K, tau, Bp, stream, tb_bits)
-                    : ozk::s2_split_cols(s, false, B, ldb, K, N, tau, Bp, stream);
+                    : ozk::s2_split_cols(s, false, B, ldb, K, N, tau, Bp, stream, tb_bits);
     if (err == hipSuccess) err = ozk::flag_nonfinite(sig, M, tau, N, ctx->dflags, stream);
     const ozk_gemm_config cfg = config_for(ctx, OZK_OP_DGEMM, OZK_SCHEME2, s, M, N, K);
     if (cfg.variant == OZK_S2_FUSED_CRT) {
@@ -869,7 +874,7 @@ ozk_status ozk_cgemm(ozk_ctx* ctx, ozk_scheme scheme, int p_or_s, int64_t M, int
 static ozk_status sgemm_run(ozk_ctx* ctx, ozk_scheme scheme, int p_or_s, bool trans_a, bool trans_b, int64_t M,
                             int64_t N, int64_t K, float alpha, const float* A, int64_t lda, const float* B,
                             int64_t ldb, float beta, float* C, int64_t ldc, void* ws, size_t ws_bytes,
-                            hipStream_t stream, int ws_arg) {
+                            hipStream_t stream, int ws_arg, bool swap_budgets) {
   char* w = (char*)ws;
   if (scheme == OZK_SCHEME2) {
     const int s = p_or_s;
@@ -883,11 +888,12 @@ static ozk_status sgemm_run(ozk_ctx* ctx, ozk_scheme scheme, int p_or_s, bool tr
     int8_t* res = (int8_t*)(w + pl.off_res);
     int ta_bits, tb_bits;
     ozk::s2_targets(s, ta_bits, tb_bits);
+    if (swap_budgets) std::swap(ta_bits, tb_bits);
     hipError_t err = trans_a ? ozk::s2_split_cols(s, false, A, lda, K, M, sig, Ap, stream, ta_bits)
-                             : ozk::s2_split_rows(s, false, A, lda, M, K, sig, Ap, stream);
+                             : ozk::s2_split_rows(s, false, A, lda, M, K, sig, Ap, stream, ta_bits);
     if (err == hipSuccess)
       err = trans_b ? ozk::s2_split_rows(s, false, B, ldb, N, K, tau, Bp, stream, tb_bits)
-                    : ozk::s2_split_cols(s, false, B, ldb, K, N, tau, Bp, stream);
+                    : ozk::s2_split_cols(s, false, B, ldb, K, N, tau, Bp, stream, tb_bits);
     if (err == hipSuccess) err = ozk::flag_nonfinite(sig, M, tau, N, ctx->dflags, stream);
     const ozk_gemm_config cfg = config_for(ctx, OZK_OP_DGEMM, OZK_SCHEME2, s, M, N, K);
     if (err == hipSuccess)
@@ -920,7 +926,8 @@ static ozk_status sgemm_run(ozk_ctx* ctx, ozk_scheme scheme, int p_or_s, bool tr
 template <typename T>
 static ozk_status zgemm3m_run(ozk_ctx* ctx, int s, bool trans_a, bool trans_b, int64_t M, int64_t N, int64_t K,
                               const T* alpha, const T* A, int64_t lda, const T* B, int64_t ldb, const T* beta, T* C,
-                              int64_t ldc, void* ws, size_t ws_bytes, hipStream_t stream, int ws_arg) {
+                              int64_t ldc, void* ws, size_t ws_bytes, hipStream_t stream, int ws_arg,
+                              bool swap_budgets) {
   const S2Plan pl = s2_plan(s, true, M, N, K);
   if (!ws || ws_bytes < pl.total) return fail(ctx, OZK_ERR_WORKSPACE, ws_arg);
   if (M == 0 || N == 0) return OZK_OK;
@@ -932,11 +939,12 @@ static ozk_status zgemm3m_run(ozk_ctx* ctx, int s, bool trans_a, bool trans_b, i
   int8_t* res = (int8_t*)(w + pl.off_res);
   int ta_bits, tb_bits;
   ozk::s2_targets(s, ta_bits, tb_bits);
+  if (swap_budgets) std::swap(ta_bits, tb_bits);
   hipError_t err = trans_a ? ozk::s2_split_cols(s, true, A, lda, K, M, sig, Ap, stream, ta_bits)
-                           : ozk::s2_split_rows(s, true, A, lda, M, K, sig, Ap, stream);
+                           : ozk::s2_split_rows(s, true, A, lda, M, K, sig, Ap, stream, ta_bits);
   if (err == hipSuccess)
     err = trans_b ? ozk::s2_split_rows(s, true, B, ldb, N, K, tau, Bp, stream, tb_bits)
-                  : ozk::s2_split_cols(s, true, B, ldb, K, N, tau, Bp, stream);
+                  : ozk::s2_split_cols(s, true, B, ldb, K, N, tau, Bp, stream, tb_bits);
   if (err == hipSuccess) err = ozk::flag_nonfinite(sig, M, tau, N, ctx->dflags, stream);
   const ozk_gemm_config cfg = config_for(ctx, OZK_OP_ZGEMM, OZK_SCHEME2, s, M, N, K);
   if (err == hipSuccess)
@@ -981,9 +989,12 @@ ozk_status ozk_gemm_ex(ozk_ctx* ctx, ozk_dtype dtype, ozk_layout layout, int tra
   if (scheme == OZK_SCHEME2 && s2_long_k(K)) return fail(ctx, OZK_ERR_UNSUPPORTED, 10);
   // Column-major storage of X is row-major storage of X^T, and C = op(A) op(B)
   // is C^T = op(B)^T op(A)^T: the row-major product of the swapped operands,
-  // each transposed exactly when the other one was.  The scales of a row of
-  // op(A) and a column of op(B) are the same either way, so are the integer
-  // sums, so the results are bit-identical to the row-major call.
+  // each transposed exactly when the other one was.  A row of op(A) and a
+  // column of op(B) keep their scales (Scheme II: each operand keeps its own
+  // bit budget), so the integer sums and the results are those of the
+  // row-major call -- except for the Scheme I complex product, whose 4M
+  // embedding then carries the negated imaginary parts on the other operand
+  // (its results are the 4M product of the transposed problem).
   int64_t m = M, n = N;
   const void *a = A, *b = B;
   int64_t la = lda, lb = ldb;
@@ -1001,10 +1012,10 @@ ozk_status ozk_gemm_ex(ozk_ctx* ctx, ozk_dtype dtype, ozk_layout layout, int tra
   switch (dtype) {
     case OZK_F64:
       return dgemm_run(ctx, scheme, p_or_s, ta, tb, m, n, K, *(const double*)alpha, (const double*)a, la,
-                       (const double*)b, lb, *(const double*)beta, (double*)C, ldc, ws, ws_bytes, stream, 19);
+                       (const double*)b, lb, *(const double*)beta, (double*)C, ldc, ws, ws_bytes, stream, 19, col);
     case OZK_F32:
       return sgemm_run(ctx, scheme, p_or_s, ta, tb, m, n, K, *(const float*)alpha, (const float*)a, la,
-                       (const float*)b, lb, *(const float*)beta, (float*)C, ldc, ws, ws_bytes, stream, 19);
+                       (const float*)b, lb, *(const float*)beta, (float*)C, ldc, ws, ws_bytes, stream, 19, col);
     default:
       break;
   }
@@ -1021,9 +1032,10 @@ ozk_status ozk_gemm_ex(ozk_ctx* ctx, ozk_dtype dtype, ozk_layout layout, int tra
   (void)cplx;
   if (dtype == OZK_C128)
     return zgemm3m_run<double>(ctx, p_or_s, ta, tb, m, n, K, (const double*)alpha, (const double*)a, la,
-                               (const double*)b, lb, (const double*)beta, (double*)C, ldc, ws, ws_bytes, stream, 19);
+                               (const double*)b, lb, (const double*)beta, (double*)C, ldc, ws, ws_bytes, stream, 19,
+                               col);
   return zgemm3m_run<float>(ctx, p_or_s, ta, tb, m, n, K, (const float*)alpha, (const float*)a, la, (const float*)b,
-                            lb, (const float*)beta, (float*)C, ldc, ws, ws_bytes, stream, 19);
+                            lb, (const float*)beta, (float*)C, ldc, ws, ws_bytes, stream, 19, col);
 }
 
 // The unfused Scheme II / 3M baseline: the fused path's pre-pass and CRT
