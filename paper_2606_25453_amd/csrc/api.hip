@@ -1635,28 +1635,48 @@ ozk_status ozk_tune_batch(ozk_ctx* ctx, ozk_batch_plan* plan, void* ws, size_t w
   std::vector<ozk_cfg_key> keys;
   for (const auto& kv : cls) keys.push_back(kv.first);
   std::stable_sort(keys.begin(), keys.end(), [&](const ozk_cfg_key& a, const ozk_cfg_key& b) { return work[a] > work[b]; });
-  // greedy over the classes: each takes the tile with the faster GEMM step,
-  // the classes before it keeping their choice
-  for (const ozk_cfg_key& k : keys) {
-    float best_ms = 0.f;
-    int best = 0;
-    for (int kind = 0; kind < 2 && err == hipSuccess; ++kind) {
-      for (int i : cls[k]) plan->large[i] = (uint8_t)kind;
-      err = upload_items(plan);
-      float ms = 0.f;
-      if (err == hipSuccess)
-        err = time_median(stream, reps, [&] {
-          return ozk::s2_batched_gemm(plan->s, cplx, plan->bd, plan->tot, w, plan->grid_small, plan->grid_large,
-                                      stream);
-        }, &ms);
-      if (err == hipSuccess && (kind == 0 || ms < best_ms)) {
-        best_ms = ms;
-        best = kind;
-      }
+  // the GEMM step of the batch with the tiles `t`
+  auto time_tiles = [&](const std::vector<uint8_t>& t, float* ms) {
+    plan->large = t;
+    hipError_t e = upload_items(plan);
+    if (e == hipSuccess)
+      e = time_median(stream, reps, [&] {
+        return ozk::s2_batched_gemm(plan->s, cplx, plan->bd, plan->tot, w, plan->grid_small, plan->grid_large,
+                                    stream);
+      }, ms);
+    return e;
+  };
+  // start from the fastest of the plan's tiles, all small and all large (the
+  // two tiles run as two launches one after the other, so a class's best
+  // tile depends on what the others use)
+  std::vector<uint8_t> cur = plan->large;
+  float cur_ms = 0.f;
+  if (err == hipSuccess) err = time_tiles(cur, &cur_ms);
+  for (uint8_t kind = 0; kind < 2 && err == hipSuccess; ++kind) {
+    std::vector<uint8_t> t(plan->count, kind);
+    float ms = 0.f;
+    err = time_tiles(t, &ms);
+    if (err == hipSuccess && ms < cur_ms) {
+      cur = t;
+      cur_ms = ms;
     }
-    for (int i : cls[k]) plan->large[i] = (uint8_t)best;
-    ctx->configs[k] = ozk_cfg_entry{ozk_gemm_config{best, 0, 4, 1}, best_ms};
   }
+  // then greedy over the classes: each takes the tile with the faster GEMM
+  // step, the others keeping their current choice
+  for (const ozk_cfg_key& k : keys) {
+    if (err != hipSuccess) break;
+    const uint8_t had = cur[cls[k].front()];
+    std::vector<uint8_t> t = cur;
+    for (int i : cls[k]) t[i] = (uint8_t)(1 - had);
+    float ms = 0.f;
+    err = time_tiles(t, &ms);
+    if (err == hipSuccess && ms < cur_ms) {
+      cur = t;
+      cur_ms = ms;
+    }
+  }
+  plan->large = cur;
+  for (const ozk_cfg_key& k : keys) ctx->configs[k] = ozk_cfg_entry{ozk_gemm_config{cur[cls[k].front()], 0, 4, 1}, cur_ms};
   // the chosen tiles, and the batch computed with them
   if (err == hipSuccess) err = upload_items(plan);
   if (err == hipSuccess)

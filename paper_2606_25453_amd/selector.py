@@ -10,19 +10,21 @@ Everything numeric runs on the GPU through the library's C ABI:
   Scheme I with p = 1..8 and Scheme II with s = 1..20, and for each of four
   tolerances drawn log-uniformly in [1e-16, 1e-5] the smallest p (9 if none)
   and the smallest s (21 if none) whose error is at most half the
-  tolerance.  The error is measured on up to 512 x 512 outputs (rows and
-  columns drawn at random; all of them for smaller products): the row
-  (column) scales of both schemes depend only on that row of A (column of
-  B), so the emulation of the sampled rows times the sampled columns gives
-  exactly the full product's values there, and the factor of two covers the
+  tolerance (the training targets), and the smallest counts whose error is
+  at most the tolerance itself (the calibration targets).  The error is
+  measured on up to 512 x 512 outputs (rows and columns drawn at random; all
+  of them for smaller products): the row (column) scales of both schemes
+  depend only on that row of A (column of B), so the emulation of the
+  sampled rows times the sampled columns gives exactly the full product's
+  values there, and the factor of two of the training targets covers the
   outputs not sampled;
 * features: the selector's own exponent-statistics kernels on the full A, B;
 * training: the library's MLP forward / gradient / Adam kernels on the
   ordinal binary cross-entropy of the 28 heads;
 * calibration on held-out problems: per head the largest threshold below
-  which no held-out sample that needs the head on falls (so no held-out
-  sample is given fewer slices or moduli than it needs), lowered by one
-  logit for the problems not seen.
+  which no held-out sample whose error at that count exceeds the tolerance
+  falls (so no held-out sample gets a result outside its tolerance), lowered
+  by half a logit for the problems not seen.
 PyTorch only allocates and fills device memory and does the small
 element-wise bookkeeping around those calls.
 
@@ -148,11 +150,12 @@ def _log_uniform(u: float, lo: int, hi: int) -> int:
 def build_dataset(ctx, count: int, seed: int, mn=(256, 4096), k_range=(256, 16384), tols_per_problem: int = 4,
                   device="cuda:0"):
     """Features (n x 34), Scheme I labels p (n), Scheme II labels s (n), the
-    a-priori bounds' decisions (n x 2) and the per-problem error curves."""
+    a-priori bounds' decisions (n x 2), the per-problem error curves and the
+    labels at the full tolerance (n x 2: p, s)."""
     torch = _torch()
     host_gen = torch.Generator().manual_seed(seed)
     gen = torch.Generator(device=device).manual_seed(seed)
-    X, lp, ls, bounds, curves = [], [], [], [], []
+    X, lp, ls, bounds, curves, full = [], [], [], [], [], []
     for i in range(count):
         if i % 500 == 0:
             print("dataset seed %d: problem %d of %d" % (seed, i, count), flush=True)
@@ -170,10 +173,11 @@ def build_dataset(ctx, count: int, seed: int, mn=(256, 4096), k_range=(256, 1638
             X.append(feat.clone())
             lp.append(label_from_curve(cp, tol))
             ls.append(label_from_curve(cs, tol))
+            full.append((label_from_curve(cp, tol, 1.0), label_from_curve(cs, tol, 1.0)))
             bounds.append(info[[2, 6]].clone())
         del A, B
     return (torch.stack(X), torch.tensor(lp, dtype=torch.int64), torch.tensor(ls, dtype=torch.int64),
-            torch.stack(bounds).cpu(), curves)
+            torch.stack(bounds).cpu(), curves, torch.tensor(full, dtype=torch.int64))
 
 
 def ordinal_targets(lp, ls):
@@ -249,10 +253,12 @@ def counts(logits, thresholds, margin: int = 0):
     return p, s
 
 
-def calibrate(ctx, w, X, Y, slack: float = 1.0):
+def calibrate(ctx, w, X, Y, slack: float = 0.5):
     """Per-head thresholds: sigmoid(min logit over the held-out samples that
     need the head on - slack), so that every such sample turns it on with
-    room to spare; 0.5 for a head no held-out sample needs."""
+    room to spare; 0.5 for a head no held-out sample needs.  Y holds the
+    targets at the full tolerance: a sample needs head t when its error at
+    count t exceeds the tolerance."""
     torch = _torch()
     logits = forward(ctx, w, X)
     thr = torch.full((N_HEADS,), 0.5, dtype=torch.float32)
@@ -312,21 +318,22 @@ def main():
     a = ap.parse_args()
     ctx = ozk.Context(0)
     t0 = time.time()
-    Xtr, ptr, str_, btr, ctr = build_dataset(ctx, a.train, seed=1)
-    Xva, pva, sva, bva, cva = build_dataset(ctx, a.val, seed=2)
+    Xtr, ptr, str_, btr, ctr, ftr = build_dataset(ctx, a.train, seed=1)
+    Xva, pva, sva, bva, cva, fva = build_dataset(ctx, a.val, seed=2)
     t_data = time.time() - t0
     print("datasets %.1fs: train %d val %d samples" % (t_data, len(ptr), len(pva)), flush=True)
     if a.data:
-        torch.save({"Xtr": Xtr.cpu(), "ptr": ptr, "str": str_, "btr": btr, "Xva": Xva.cpu(), "pva": pva,
-                    "sva": sva, "bva": bva}, a.data)
+        torch.save({"Xtr": Xtr.cpu(), "ptr": ptr, "str": str_, "btr": btr, "ftr": ftr, "Xva": Xva.cpu(), "pva": pva,
+                    "sva": sva, "bva": bva, "fva": fva}, a.data)
     dev = Xtr.device
     Ytr = ordinal_targets(ptr.to(dev), str_.to(dev))
     Yva = ordinal_targets(pva.to(dev), sva.to(dev))
     w, hist = train(ctx, Xtr, Ytr, steps=a.steps)
-    thr = calibrate(ctx, w, Xva, Yva)
+    thr = calibrate(ctx, w, Xva, ordinal_targets(fva[:, 0].to(dev), fva[:, 1].to(dev)))
     p_net, s_net = counts(forward(ctx, w, Xva), thr)
     p_use, s_use = decisions(p_net, s_net, bva)
     pva_d, sva_d = pva.to(dev), sva.to(dev)
+    pf, sf = fva[:, 0].to(dev), fva[:, 1].to(dev)
     pb, sb = bva[:, 0].to(dev), bva[:, 1].to(dev)
     to2 = p_use > 8
     meta = {"train_problems": a.train, "val_problems": a.val, "samples_per_problem": 4, "steps": a.steps,
@@ -335,15 +342,18 @@ def main():
             "sizes": "M, N log-uniform in [256, 4096], K log-uniform in [256, 16384]",
             "phi": "U(0,4) for A and for B",
             "labels": "smallest p (s) with E_cw <= tol / 2 on up to 512 x 512 sampled outputs",
+            "calibration": "per head, 0.5 logit below the lowest held-out logit whose E_cw at that count > tol",
             "heads": "8 for p > t (t = 1..8), 20 for s > t (t = 1..20)", "margin": 0,
             "val_mean_p_selector": float(p_use.double().mean()), "val_mean_p_bound": float(pb.double().mean()),
             "val_to_scheme2_selector": int(to2.sum()), "val_to_scheme2_bound": int((pb > 8).sum()),
             "val_scheme2_needed": int((pva_d > 8).sum()), "val_mean_p_needed": float(pva_d.double().mean()),
-            "val_under_p": int(((p_use < pva_d) & ~to2).sum()),
+            "val_under_p": int(((p_use < pf) & ~to2).sum()),
+            "val_under_p_half_tol": int(((p_use < pva_d) & ~to2).sum()),
             "val_mean_s_selector": float(s_use[to2].double().mean()) if bool(to2.any()) else 0.0,
             "val_mean_s_bound": float(torch.clamp(sb[to2], max=20).double().mean()) if bool(to2.any()) else 0.0,
             "val_mean_s_needed": float(sva_d[to2].double().mean()) if bool(to2.any()) else 0.0,
-            "val_under_s": int(((s_use < sva_d) & to2 & (sva_d <= 20)).sum())}
+            "val_under_s": int(((s_use < sf) & to2 & (sf <= 20)).sum()),
+            "val_under_s_half_tol": int(((s_use < sva_d) & to2 & (sva_d <= 20)).sum())}
     save(a.out, w, thr, 0, meta)
     print(json.dumps(meta), flush=True)
     ctx.close()

@@ -457,3 +457,34 @@ def test_trained_selector_never_misses_the_tolerance(ctx):
                  np.mean(bound_s) if bound_s else 0, len(used_s)), flush=True)
     finally:
         ctx2.close()
+
+
+def test_trained_selector_at_the_headline_size(ctx):
+    """8192^3, phi = 1 for both operands, at 1e-13 and 1e-10: the automatic
+    call meets the tolerance on sampled outputs judged by the CPU oracle's
+    double-double product, and picks a Scheme I slice count (the fixed-p
+    calls show p = 7 meets 1e-13 there with room to spare)."""
+    from oracle import metrics
+    from paper_2606_25453_amd import selector as train
+    n = 8192
+    ctx2 = ozk.Context(0)
+    try:
+        train.install(ctx2)
+        A = synth.phi_matrix_device(n, n, 1.0, 424242)
+        B = synth.phi_matrix_device(n, n, 1.0, 434343)
+        rng = np.random.default_rng(99)
+        rows = np.unique(np.concatenate([rng.integers(0, n, 14), [0, n - 1]]))
+        cols = np.unique(np.concatenate([rng.integers(0, n, 14), [0, n - 1]]))
+        r, c = torch.from_numpy(rows).cuda(), torch.from_numpy(cols).cuda()
+        As, Bs = A.index_select(0, r).cpu().numpy(), B.index_select(1, c).cpu().numpy()
+        hi, lo = oracle.gemm_dd(As, Bs)
+        for tol in (1e-13, 1e-10):
+            C, info = dgemm_auto(ctx2, tol, A, B)
+            got = C.index_select(0, r).index_select(1, c).cpu().numpy()
+            err = metrics.e_cw(got, hi, lo, As, Bs)
+            print("tol %g: scheme %d p %d (bound %d), E_cw %.3g" % (tol, info[4], info[0], info[2], err), flush=True)
+            assert info[3] == 0 and info[4] == 1 and info[0] <= 8, info.tolist()
+            assert err <= tol, (tol, info.tolist(), err)
+            del C
+    finally:
+        ctx2.close()
