@@ -515,8 +515,22 @@ __device__ __forceinline__ void s2_reduce_acc(v16i (&acc)[P][TM][TN], int l) {
         }
 }
 
+// A lane's four residues of rows r0..r0+3 of its column, one byte each
+// (byte k: row r0 + k), transposed across its quad of lanes (columns c0..c0+3):
+// afterwards lane q holds row r0 + q, byte j being column c0 + j.  Two
+// exchanges with the quad neighbours (DPP quad permutations lane ^ 1, lane ^ 2).
+__device__ __forceinline__ uint32_t quad_transpose4(uint32_t w, int q) {
+  uint32_t p = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)w, 0xB1, 0xF, 0xF, false);
+  w = (q & 1) ? ((w & 0xFF00FF00u) | ((p >> 8) & 0x00FF00FFu)) : ((w & 0x00FF00FFu) | ((p << 8) & 0xFF00FF00u));
+  p = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)w, 0x4E, 0xF, 0xF, false);
+  return (q & 2) ? ((p >> 16) | (w & 0xFFFF0000u)) : ((w & 0xFFFFu) | (p << 16));
+}
+
 // The residues mod m_l of a finished tile (Eq. 7); for 3M the real and
-// imaginary parts from the three products (Eq. 16).
+// imaginary parts from the three products (Eq. 16).  When N is a multiple of
+// 4 (and `out` 4-byte aligned) each group of four rows of a lane is
+// transposed across its quad so that every lane writes 4 bytes of one row:
+// a quarter of the store instructions.
 // The output positions are derived from a lane index the compiler cannot see
 // through: inside a K loop (the batched tiles store every modulus there) it
 // would otherwise keep all of them live across the loop.
@@ -528,6 +542,48 @@ __device__ __forceinline__ void s2_store_tile(const v16i (&acc)[P][TM][TN], int6
   asm volatile("" : "+v"(tid));
   const int lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
+  // residue byte(s) of value v of MFMA tile (a, b): real -> r[0]; 3M -> re, im
+  auto residues = [&](int a, int b, int v, int (&r)[2]) {
+    if (!CPLX) {
+      r[0] = smod_i32(acc[0][a][b][v], l);
+      r[1] = 0;
+    } else {
+      // T1 - T2 and T3 - T1 - T2 are exact in binary64 (|T| < 2^31): two
+      // reductions instead of three and the residue sums
+      const double t1 = (double)acc[0][a][b][v], t2 = (double)acc[CPLX ? 1 : 0][a][b][v],
+                   t3 = (double)acc[CPLX ? 2 : 0][a][b][v];
+      r[0] = smod_exact(t1 - t2, l);
+      r[1] = smod_exact(t3 - t1 - t2, l);
+    }
+  };
+  constexpr int NPL = CPLX ? 2 : 1;  // output planes per modulus
+  if ((N & 3) == 0 && ((uintptr_t)out & 3) == 0) {
+    const int q = lane & 3;
+#pragma unroll
+    for (int a = 0; a < TM; ++a)
+#pragma unroll
+      for (int b = 0; b < TN; ++b)
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+          uint32_t w[2] = {0u, 0u};
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            int r[2];
+            residues(a, b, 4 * g + k, r);
+#pragma unroll
+            for (int pl = 0; pl < NPL; ++pl) w[pl] |= (uint32_t)(uint8_t)r[pl] << (8 * k);
+          }
+          const int64_t row = m0 + wm * 32 * TM + a * 32 + 8 * g + 4 * (lane >> 5) + q;
+          const int64_t c0 = n0 + wn * 32 * TN + b * 32 + ((lane & 31) & ~3);
+#pragma unroll
+          for (int pl = 0; pl < NPL; ++pl) {
+            const uint32_t t = quad_transpose4(w[pl], q);
+            if (row < M && c0 < N)
+              *reinterpret_cast<uint32_t*>(out + (NPL * l + pl) * mn + row * N + c0) = t;
+          }
+        }
+    return;
+  }
 #pragma unroll
   for (int a = 0; a < TM; ++a)
 #pragma unroll
@@ -538,14 +594,10 @@ __device__ __forceinline__ void s2_store_tile(const v16i (&acc)[P][TM][TN], int6
         const int64_t row = m0 + wm * 32 * TM + a * 32 + 8 * (v / 4) + 4 * (lane >> 5) + (v % 4);
         const int64_t col = n0 + wn * 32 * TN + b * 32 + (lane & 31);
         if (row >= M || col >= N) continue;
-        if (!CPLX) {
-          out[l * mn + row * N + col] = (int8_t)smod_i32(acc[0][a][b][v], l);
-        } else {
-          const int t1 = smod_i32(acc[0][a][b][v], l), t2 = smod_i32(acc[CPLX ? 1 : 0][a][b][v], l),
-                    t3 = smod_i32(acc[CPLX ? 2 : 0][a][b][v], l);
-          out[(2 * l) * mn + row * N + col] = (int8_t)smod_sum(t1, -t2, l);
-          out[(2 * l + 1) * mn + row * N + col] = (int8_t)smod_sum(smod_sum(t3, -t1, l), -t2, l);
-        }
+        int r[2];
+        residues(a, b, v, r);
+#pragma unroll
+        for (int pl = 0; pl < NPL; ++pl) out[(NPL * l + pl) * mn + row * N + col] = (int8_t)r[pl];
       }
 }
 
