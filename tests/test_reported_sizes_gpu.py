@@ -131,7 +131,8 @@ def test_unfused_ablation_8192(ctx):
     assert torch.equal(C, ozk.ozk_dgemm(ctx, ozk.OZK_SCHEME1, p, A, B))
 
 
-@pytest.mark.parametrize("M,N,K,s", [(16384, 16384, 16384, 15), (8192, 8192, 2048, 14), (8192, 8192, 2048, 16)])
+@pytest.mark.parametrize("M,N,K,s", [(16384, 16384, 16384, 15), (8192, 8192, 2048, 14), (8192, 8192, 2048, 16),
+                                     (4096, 4096, 4096, 14), (4096, 4096, 4096, 16)])
 def test_scheme2_reported(ctx, M, N, K, s):
     print("case Scheme II %dx%dx%d s=%d" % (M, N, K, s), flush=True)
     A, B = real_pair(M, N, K, 9000 + s)
@@ -157,9 +158,9 @@ def test_zgemm_3m_reported(ctx, n, s):
     report("3M ZGEMM %d^3 s=%d" % (n, s), got, nat, As, Bs)
 
 
+@pytest.mark.parametrize("n", [8192, 16384])
 @pytest.mark.parametrize("p", [2, 4])
-def test_sgemm_16384(ctx, p):
-    n = 16384
+def test_sgemm_reported(ctx, p, n):
     print("case SGEMM %d^3 p=%d" % (n, p), flush=True)
     A, B = real_pair(n, n, n, 9800 + p, dtype=torch.float32)
     C = ozk.ozk_sgemm(ctx, ozk.OZK_SCHEME1, p, A, B)
