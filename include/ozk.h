@@ -661,12 +661,14 @@ ozk_status ozk_batch_plan_tiles(const ozk_batch_plan* plan, int count,
                                 int32_t* large);
 /* Autotune a plan's tiles on its own problems (the paper tunes its kernel
  * parameters, Sec. V-A; its problems are not batched): run the pre-pass,
- * then, size class by size class in decreasing INT8 work, time the whole
- * GEMM step (median of `reps` after one warm-up, HIP events) with the
- * class's problems on the small and on the large tile, keep the faster
- * (the classes already decided keep their choice), and store it in the
- * context table (op OZK_OP_DGEMM_BATCHED / OZK_OP_ZGEMM_BATCHED, variant 0
- * or 1, the time), where later plans of the context find it.  The plan is
+ * time the whole GEMM step (median of `reps` after one warm-up, HIP events)
+ * with the plan's tiles, with every problem on the small tile and with
+ * every problem on the large one, start from the fastest, then, size class
+ * by size class in decreasing INT8 work, move the class's problems to the
+ * other tile when that makes the whole step faster, and store each class's
+ * tile in the context table (op OZK_OP_DGEMM_BATCHED /
+ * OZK_OP_ZGEMM_BATCHED, variant 0 or 1, with the step time), where later
+ * plans of the context find it.  The plan is
  * updated in place and the batch is computed with the chosen tiles.  Every
  * tile computes the same integers, so results do not depend on the choice.
  * Synchronises the stream (not graph-capturable).  Errors:

@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <atomic>
+
 #include "ozk.h"
 
 namespace ozk {
@@ -212,5 +214,20 @@ hipError_t flag_nonfinite(const int32_t* a, int64_t na, const int32_t* b, int64_
 hipError_t flag_batch(const BatchDev& bd, const int8_t* ws, uint32_t* flags, hipStream_t st);
 hipError_t flag_decision(const int32_t* info, uint32_t* flags, hipStream_t st);
 hipError_t flag_take(uint32_t* flags, uint32_t* out, hipStream_t st);
+
+// Raise the dynamic LDS limit of kernel `fn` to `bytes` on the current
+// device, once per device (`done` holds one bit per device ordinal < 64 and
+// is safe to share between host threads; devices beyond 64 set it on every
+// launch).
+inline hipError_t lds_limit(const void* fn, int bytes, std::atomic<uint64_t>& done) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  const uint64_t bit = dev >= 0 && dev < 64 ? (uint64_t)1 << dev : 0;
+  if (bit && (done.load(std::memory_order_acquire) & bit)) return hipSuccess;
+  e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (e == hipSuccess && bit) done.fetch_or(bit, std::memory_order_acq_rel);
+  return e;
+}
 
 }  // namespace ozk

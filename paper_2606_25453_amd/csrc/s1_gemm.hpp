@@ -123,13 +123,9 @@ hipError_t s1_launch_pov(const S1GemmArgs& g, const int32_t* p_dev, hipStream_t 
   using T = GemmTile<P, Cfg::TM, Cfg::TN, Cfg::NS>;
   static_assert(T::LDS_BYTES <= 160 * 1024, "LDS budget");
   auto kern = k_s1_gemm<P, OUT, V>;
-  static bool attr_set = false;
-  if (!attr_set) {
-    hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
-                                         hipFuncAttributeMaxDynamicSharedMemorySize, T::LDS_BYTES);
-    if (err != hipSuccess) return err;
-    attr_set = true;
-  }
+  static std::atomic<uint64_t> lds_done{0};
+  const hipError_t e_lds = lds_limit(reinterpret_cast<const void*>(kern), T::LDS_BYTES, lds_done);
+  if (e_lds != hipSuccess) return e_lds;
   S1KArgs k;
   k.Ap = g.Ap;
   k.Bp = g.Bp;

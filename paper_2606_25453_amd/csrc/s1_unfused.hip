@@ -77,13 +77,9 @@ hipError_t s1_gemm_unfused(int p, int64_t M, int64_t N, int64_t K, const int8_t*
       pa.t[n] = t;
       pa.u[n] = d - t;
     }
-  static bool attr = false;
-  if (!attr) {
-    hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void*>(k_s1_pair_gemm),
-                                         hipFuncAttributeMaxDynamicSharedMemorySize, PairTile::LDS_BYTES);
-    if (err != hipSuccess) return err;
-    attr = true;
-  }
+  static std::atomic<uint64_t> lds_done{0};
+  const hipError_t e_lds = lds_limit(reinterpret_cast<const void*>(k_s1_pair_gemm), PairTile::LDS_BYTES, lds_done);
+  if (e_lds != hipSuccess) return e_lds;
   const int64_t ra = round_up(M, OZK_ROW_ALIGN), rb = round_up(N, OZK_ROW_ALIGN);
   const int64_t nchunk = round_up(K, OZK_K_CHUNK) / OZK_K_CHUNK;
   const int64_t tiles = ((M + PairTile::BM - 1) / PairTile::BM) * ((N + PairTile::BN - 1) / PairTile::BN);

@@ -1068,13 +1068,9 @@ static hipError_t launch_gemm_mod(int s, int64_t M, int64_t N, int64_t K, const 
   constexpr int P = Cfg::P;
   using T = GemmTile<P, Cfg::TM, Cfg::TN, Cfg::NS>;
   auto kern = k_s2_gemm_mod<CPLX, V>;
-  static bool attr = false;
-  if (!attr) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, Cfg::LDS_BYTES);
-    if (e != hipSuccess) return e;
-    attr = true;
-  }
+  static std::atomic<uint64_t> lds_done{0};
+  const hipError_t e_lds = lds_limit(reinterpret_cast<const void*>(kern), Cfg::LDS_BYTES, lds_done);
+  if (e_lds != hipSuccess) return e_lds;
   const int64_t kp = round_up(K, OZK_K_CHUNK);
   const int64_t ra = round_up(M, OZK_ROW_ALIGN), rb = round_up(N, OZK_ROW_ALIGN);
   const int64_t plane_a = ra * kp * P, plane_b = rb * kp * P;
@@ -1176,13 +1172,9 @@ int64_t s2_unfused_planes_bytes(int s, bool cplx, int64_t M, int64_t N) { return
 hipError_t s2_gemm_mod_unfused(int s, bool cplx, int64_t M, int64_t N, int64_t K, const int8_t* Ap, const int8_t* Bp,
                                int32_t* planes, int8_t* out, hipStream_t st) {
   if (M == 0 || N == 0) return hipSuccess;
-  static bool attr = false;
-  if (!attr) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_s2_plane_gemm),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, NaiveTile::LDS_BYTES);
-    if (e != hipSuccess) return e;
-    attr = true;
-  }
+  static std::atomic<uint64_t> lds_done{0};
+  const hipError_t e_lds = lds_limit(reinterpret_cast<const void*>(k_s2_plane_gemm), NaiveTile::LDS_BYTES, lds_done);
+  if (e_lds != hipSuccess) return e_lds;
   const int Q = cplx ? 3 : 1;
   const int64_t ra = round_up(M, OZK_ROW_ALIGN), rb = round_up(N, OZK_ROW_ALIGN);
   const int64_t nchunk = round_up(K, OZK_K_CHUNK) / OZK_K_CHUNK;
@@ -1495,13 +1487,9 @@ static hipError_t launch_gemm_mod_auto(const int32_t* info, int64_t M, int64_t N
                                        const int8_t* Bp, int8_t* out, hipStream_t st) {
   using Cfg = S2Cfg<CPLX, 0>;
   using T = GemmTile<Cfg::P, Cfg::TM, Cfg::TN, Cfg::NS>;
-  static bool attr = false;
-  if (!attr) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_s2_gemm_mod_auto<CPLX>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, Cfg::LDS_BYTES);
-    if (e != hipSuccess) return e;
-    attr = true;
-  }
+  static std::atomic<uint64_t> lds_done{0};
+  const hipError_t e_lds = lds_limit(reinterpret_cast<const void*>(k_s2_gemm_mod_auto<CPLX>), Cfg::LDS_BYTES, lds_done);
+  if (e_lds != hipSuccess) return e_lds;
   const int64_t kp = round_up(K, OZK_K_CHUNK);
   const int64_t ra = round_up(M, OZK_ROW_ALIGN), rb = round_up(N, OZK_ROW_ALIGN);
   const int64_t tiles = ((M + T::BM - 1) / T::BM) * ((N + T::BN - 1) / T::BN);
@@ -1715,13 +1703,9 @@ static hipError_t launch_batch_gemm(const BatchDev& bd, const BatchUnits& items,
                                     int grid, int8_t* ws, int s, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   constexpr int lds = S2Cfg<CPLX, V>::LDS_BYTES;
-  static bool attr = false;
-  if (!attr) {
-    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_b_gemm_mod<CPLX, V>),
-                                             hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    if (e != hipSuccess) return e;
-    attr = true;
-  }
+  static std::atomic<uint64_t> lds_done{0};
+  const hipError_t e_lds = lds_limit(reinterpret_cast<const void*>(k_b_gemm_mod<CPLX, V>), lds, lds_done);
+  if (e_lds != hipSuccess) return e_lds;
   hipLaunchKernelGGL((k_b_gemm_mod<CPLX, V>), dim3((unsigned)grid), dim3(256), lds, st, bd, items, order, ws, s);
   return hipGetLastError();
 }
