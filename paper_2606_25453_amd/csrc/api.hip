@@ -1509,7 +1509,8 @@ ozk_status ozk_batch_plan_create(ozk_ctx* ctx, ozk_op op, ozk_scheme scheme, int
     q.off_tau = o; o = align256(o + 4 * (size_t)(d.N > 0 ? d.N : 1));
     q.off_a = o; o = align256(o + (size_t)q.ra * q.Kp * s * (cplx ? 3 : 1));
     q.off_b = o; o = align256(o + (size_t)q.rb * q.Kp * s * (cplx ? 3 : 1));
-    q.off_res = o; o = align256(o + (size_t)s * (cplx ? 2 : 1) * d.M * d.N);
+    q.ldr = round_up(d.N, 4);  // whole 4-byte residue words per row
+    q.off_res = o; o = align256(o + (size_t)s * (cplx ? 2 : 1) * d.M * q.ldr);
     if (q.tiles) {
       max_items += ozk::s2_tile_count(cplx, false, q.M, q.N);  // the small tile gives the most items
       // the tile of this size class: the tuned table's choice (variant 1: the

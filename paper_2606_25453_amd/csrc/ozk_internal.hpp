@@ -77,6 +77,7 @@ constexpr int OZK_BATCH_ROW_ALIGN = 128;
 // workspace base passed to each launch.
 struct BatchProb {
   int64_t M, N, K, Kp, ra, rb, tiles;
+  int64_t ldr;  // row stride of the problem's residue planes: N rounded up to 4
   const double* A;
   int64_t lda;
   const double* B;

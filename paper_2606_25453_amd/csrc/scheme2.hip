@@ -527,8 +527,9 @@ __device__ __forceinline__ uint32_t quad_transpose4(uint32_t w, int q) {
 }
 
 // The residues mod m_l of a finished tile (Eq. 7); for 3M the real and
-// imaginary parts from the three products (Eq. 16).  When N is a multiple of
-// 4 (and `out` 4-byte aligned) each group of four rows of a lane is
+// imaginary parts from the three products (Eq. 16), into planes of M rows
+// of ldr >= N bytes.  When ldr is a multiple of 4 (and `out` 4-byte
+// aligned) each group of four rows of a lane is
 // transposed across its quad so that every lane writes 4 bytes of one row:
 // a quarter of the store instructions.
 // The output positions are derived from a lane index the compiler cannot see
@@ -536,8 +537,8 @@ __device__ __forceinline__ uint32_t quad_transpose4(uint32_t w, int q) {
 // would otherwise keep all of them live across the loop.
 template <bool CPLX, int P, int TM, int TN>
 __device__ __forceinline__ void s2_store_tile(const v16i (&acc)[P][TM][TN], int64_t m0, int64_t n0, int64_t M,
-                                              int64_t N, int8_t* __restrict__ out, int l) {
-  const int64_t mn = (int64_t)M * N;
+                                              int64_t N, int8_t* __restrict__ out, int l, int64_t ldr) {
+  const int64_t mn = (int64_t)M * ldr;  // a plane: M rows of ldr >= N bytes
   int tid = (int)threadIdx.x;
   asm volatile("" : "+v"(tid));
   const int lane = tid & 63, wave = tid >> 6;
@@ -557,7 +558,7 @@ __device__ __forceinline__ void s2_store_tile(const v16i (&acc)[P][TM][TN], int6
     }
   };
   constexpr int NPL = CPLX ? 2 : 1;  // output planes per modulus
-  if ((N & 3) == 0 && ((uintptr_t)out & 3) == 0) {
+  if ((ldr & 3) == 0 && ((uintptr_t)out & 3) == 0) {
     const int q = lane & 3;
 #pragma unroll
     for (int a = 0; a < TM; ++a)
@@ -578,8 +579,8 @@ __device__ __forceinline__ void s2_store_tile(const v16i (&acc)[P][TM][TN], int6
 #pragma unroll
           for (int pl = 0; pl < NPL; ++pl) {
             const uint32_t t = quad_transpose4(w[pl], q);
-            if (row < M && c0 < N)
-              *reinterpret_cast<uint32_t*>(out + (NPL * l + pl) * mn + row * N + c0) = t;
+            if (row < M && c0 < N)  // columns c0 + 3 < ldr: past N only the plane's padding
+              *reinterpret_cast<uint32_t*>(out + (NPL * l + pl) * mn + row * ldr + c0) = t;
           }
         }
     return;
@@ -597,7 +598,7 @@ __device__ __forceinline__ void s2_store_tile(const v16i (&acc)[P][TM][TN], int6
         int r[2];
         residues(a, b, v, r);
 #pragma unroll
-        for (int pl = 0; pl < NPL; ++pl) out[(NPL * l + pl) * mn + row * N + col] = (int8_t)r[pl];
+        for (int pl = 0; pl < NPL; ++pl) out[(NPL * l + pl) * mn + row * ldr + col] = (int8_t)r[pl];
       }
 }
 
@@ -632,7 +633,7 @@ __device__ __forceinline__ void s2_gemm_tile(const int8_t* __restrict__ Ap, cons
     if (c0 + run >= nsteps) break;
     s2_reduce_acc<P, TM, TN>(acc, l);
   }
-  s2_store_tile<CPLX, P, TM, TN>(acc, m0, n0, M, N, out, l);
+  s2_store_tile<CPLX, P, TM, TN>(acc, m0, n0, M, N, out, l, N);
 }
 
 template <bool CPLX, int V>
@@ -854,15 +855,17 @@ __device__ __forceinline__ void s2_store_c(const TO (&h)[2], int64_t row, int64_
   }
 }
 
+// Residue planes of M rows of ldr >= N bytes (ldr < 0: N).
 template <bool CPLX, typename TO = double, int U = NL>
 __device__ __forceinline__ void s2_crt_block(const CrtArgs& ca, int64_t M, int64_t N, const int8_t* __restrict__ res,
                                              const int32_t* __restrict__ sigma, const int32_t* __restrict__ tau,
                                              TO a_re, TO a_im, TO b_re, TO b_im, TO* __restrict__ C, int64_t ldc,
-                                             int64_t blk) {
+                                             int64_t blk, int64_t ldr = -1) {
   const int64_t idx = blk * 256 + threadIdx.x;
-  const int64_t mn = (int64_t)M * N;
-  if (idx >= mn) return;
+  if (idx >= (int64_t)M * N) return;
   const int64_t row = idx / N, col = idx % N;
+  if (ldr < 0) ldr = N;
+  const int64_t mn = (int64_t)M * ldr, at = row * ldr + col;
   const int si = sigma[row], tj = tau[col];
   const bool bad = si == OZK_EXP_NONFINITE || tj == OZK_EXP_NONFINITE;
   const int E = -si - tj;
@@ -875,7 +878,7 @@ __device__ __forceinline__ void s2_crt_block(const CrtArgs& ca, int64_t M, int64
     }
     uint32_t mag[NL];
     bool neg;
-    crt_combine<U>(ca, res + (CPLX ? q * mn : 0) + idx, CPLX ? 2 * mn : mn, mag, neg);
+    crt_combine<U>(ca, res + (CPLX ? q * mn : 0) + at, CPLX ? 2 * mn : mn, mag, neg);
     h[q] = round_limbs<TO>(mag, neg, E);
   }
   s2_store_c<CPLX, TO>(h, row, col, a_re, a_im, b_re, b_im, C, ldc);
@@ -1611,8 +1614,8 @@ static_assert(OZK_BATCH_ROW_ALIGN % batch_rows<false, S2_BATCH_V>() == 0 &&
 template <bool CPLX, int V>
 __device__ __forceinline__ void s2_gemm_tile_moduli(const int8_t* __restrict__ Ap, const int8_t* __restrict__ Bp,
                                                     int64_t rows_a, int64_t rows_b, int64_t nsteps, int64_t M,
-                                                    int64_t N, int8_t* __restrict__ out, int64_t tile, int s,
-                                                    int8_t* lds) {
+                                                    int64_t N, int8_t* __restrict__ out, int64_t ldr, int64_t tile,
+                                                    int s, int8_t* lds) {
   using Cfg = S2Cfg<CPLX, V>;
   static_assert(Cfg::G == 1, "one K chunk per stage");
   constexpr int P = Cfg::P, TM = Cfg::TM, TN = Cfg::TN, NS = Cfg::NS;
@@ -1624,7 +1627,7 @@ __device__ __forceinline__ void s2_gemm_tile_moduli(const int8_t* __restrict__ A
   v16i acc[P][TM][TN];
   zero_acc<P, TM, TN>(acc);
   if (nsteps == 0) {  // K = 0: every residue is 0
-    for (int l = 0; l < s; ++l) s2_store_tile<CPLX, P, TM, TN>(acc, m0, n0, M, N, out, l);
+    for (int l = 0; l < s; ++l) s2_store_tile<CPLX, P, TM, TN>(acc, m0, n0, M, N, out, l, ldr);
     return;
   }
   int l = 0;
@@ -1634,7 +1637,7 @@ __device__ __forceinline__ void s2_gemm_tile_moduli(const int8_t* __restrict__ A
     ++in_mod;
     ++in_run;
     if (in_mod == nsteps) {
-      s2_store_tile<CPLX, P, TM, TN>(acc, m0, n0, M, N, out, l);
+      s2_store_tile<CPLX, P, TM, TN>(acc, m0, n0, M, N, out, l, ldr);
       zero_acc<P, TM, TN>(acc);
       ++l;
       in_mod = 0;
@@ -1660,7 +1663,7 @@ __global__ __launch_bounds__(256, V == S2_BATCH_V ? 3 : 1) void k_b_gemm_mod(Bat
     const int i = find_problem(items, it);
     const BatchProb& q = bd.prob[order[i]];
     s2_gemm_tile_moduli<CPLX, V>(ws + q.off_a, ws + q.off_b, q.ra, q.rb, q.Kp / OZK_K_CHUNK, q.M, q.N,
-                                 ws + q.off_res, it - items.start[i], s, lds);
+                                 ws + q.off_res, q.ldr, it - items.start[i], s, lds);
   }
 }
 
@@ -1669,8 +1672,8 @@ __global__ __launch_bounds__(256) void k_b_crt(CrtArgs ca, BatchDev bd, int8_t* 
   const int p = find_problem(bd.crt, blockIdx.x);
   const BatchProb& q = bd.prob[p];
   s2_crt_block<CPLX, double, U>(ca, q.M, q.N, ws + q.off_res, reinterpret_cast<const int32_t*>(ws + q.off_sig),
-                     reinterpret_cast<const int32_t*>(ws + q.off_tau), q.a_re, q.a_im, q.b_re, q.b_im, q.C, q.ldc,
-                     blockIdx.x - bd.crt.start[p]);
+                                reinterpret_cast<const int32_t*>(ws + q.off_tau), q.a_re, q.a_im, q.b_re, q.b_im,
+                                q.C, q.ldc, blockIdx.x - bd.crt.start[p], q.ldr);
 }
 
 int64_t s2_tile_count(bool cplx, bool large, int64_t M, int64_t N) {
