@@ -114,8 +114,10 @@ def test_split_complex(ctx, s, K):
 
 
 @pytest.mark.parametrize("s", [3, 16])
-@pytest.mark.parametrize("shape", [(63, 65, 127), (129, 257, 95)])
+@pytest.mark.parametrize("shape", [(63, 65, 127), (129, 257, 95), (61, 44, 90)])
 def test_gemm_mod_residues_bit_exact(ctx, s, shape):
+    # (61, 44, 90): N a multiple of 4, so the residues leave the GEMM as 4-byte
+    # words transposed across lane quads; M leaves a partial group of rows
     M, N, K = shape
     A = synth.phi_matrix(M, K, 1.0, 800 + s)
     B = synth.phi_matrix(K, N, 1.0, 810 + s)
@@ -127,8 +129,10 @@ def test_gemm_mod_residues_bit_exact(ctx, s, shape):
         assert np.array_equal(Cres[l], s2.modular_product(st["RA"][l], st["RB"][l], m)), l
 
 
-def test_gemm_mod_3m_residues_bit_exact(ctx):
-    s, M, N, K = 9, 70, 90, 110
+@pytest.mark.parametrize("M,N", [(70, 90), (61, 44)])
+def test_gemm_mod_3m_residues_bit_exact(ctx, M, N):
+    # (61, 44): the 4-byte transposed residue stores (N a multiple of 4)
+    s, K = 9, 110
     A = synth.complex_phi_matrix(M, K, 1.0, 900, 901)
     B = synth.complex_phi_matrix(K, N, 1.0, 902, 903)
     _, pa = ozk.ozk_s2_split_rows(ctx, s, dev(A), complex_planes=1)
