@@ -69,6 +69,21 @@ __device__ __forceinline__ int smod_exact(double t, int l) {
 // smod of an INT32 accumulator.
 __device__ __forceinline__ int smod_i32(int x, int l) { return smod_exact((double)x, l); }
 
+// smod(x, m_l) for |x| < 2^30 in two binary64 operations and a 24-bit
+// multiply: fma(x, 1/m, 1.5 * 2^52) rounds x / m to the nearest integer q,
+// which the low 32 bits of that double hold (its unit in the last place is 1
+// and 2^51 + q is its fraction); the product's error is below 2^-29 while an
+// odd m keeps x / m at least 1/(2m) from a half-integer, so q is exact, and
+// x - q m (|q| < 2^23) is the symmetric residue.  m = 256 (the only even
+// modulus) is the sign-extended low byte.
+__device__ __forceinline__ int smod_small(int x, int l) {
+  const int m = c_s2.m[l];
+  const double y = __fma_rn((double)x, c_s2.inv_m[l], 6755399441055744.0);
+  const int q = (int)(uint32_t)(uint64_t)__double_as_longlong(y);
+  const int r = x - __mul24(q, m);
+  return m == 256 ? (int)(int8_t)x : r;  // a select, no branch: the values interleave
+}
+
 // smod(a + b, m_l) for a, b already symmetric residues of m_l.
 __device__ __forceinline__ int smod_sum(int a, int b, int l) {
   const int m = c_s2.m[l];
@@ -459,6 +474,9 @@ __global__ __launch_bounds__(256) void k_s2_split_cols(const T* __restrict__ X, 
 // so the accumulators are reduced mod m every 4095 steps (K = 131040); the
 // reduction is exact because only the residue is kept.
 constexpr int64_t S2_RUN_STEPS = 4095;
+// K chunks up to which a tile's sums stay within 2^28 (|T| <= 32 * 128^2 per
+// chunk), so that the epilogue can use the short reduction.
+constexpr int64_t S2_SMALL_STEPS = 512;
 
 // Tiling of the per-modulus GEMM.  Base tile: real 128 x 128, 3M 128 x 64;
 // large tile: real 256 x 128 (4 x 2 MFMA tiles per wave; variant 3: 256 x 256,
@@ -528,16 +546,18 @@ __device__ __forceinline__ uint32_t quad_transpose4(uint32_t w, int q) {
 
 // The residues mod m_l of a finished tile (Eq. 7); for 3M the real and
 // imaginary parts from the three products (Eq. 16), into planes of M rows
-// of ldr >= N bytes.  When ldr is a multiple of 4 (and `out` 4-byte
+// of ldr >= N bytes.  `small`: the tile summed at most 512 K chunks in this
+// run (|T| <= 512 * 32 * 128^2 = 2^28, so the 3M combinations stay below
+// 2^30 in INT32), and the short reduction applies.  When ldr is a multiple of 4 (and `out` 4-byte
 // aligned) each group of four rows of a lane is
 // transposed across its quad so that every lane writes 4 bytes of one row:
 // a quarter of the store instructions.
 // The output positions are derived from a lane index the compiler cannot see
 // through: inside a K loop (the batched tiles store every modulus there) it
 // would otherwise keep all of them live across the loop.
-template <bool CPLX, int P, int TM, int TN>
-__device__ __forceinline__ void s2_store_tile(const v16i (&acc)[P][TM][TN], int64_t m0, int64_t n0, int64_t M,
-                                              int64_t N, int8_t* __restrict__ out, int l, int64_t ldr) {
+template <bool CPLX, int P, int TM, int TN, bool SMALL>
+__device__ __forceinline__ void s2_store_tile_as(const v16i (&acc)[P][TM][TN], int64_t m0, int64_t n0, int64_t M,
+                                                 int64_t N, int8_t* __restrict__ out, int l, int64_t ldr) {
   const int64_t mn = (int64_t)M * ldr;  // a plane: M rows of ldr >= N bytes
   int tid = (int)threadIdx.x;
   asm volatile("" : "+v"(tid));
@@ -545,7 +565,16 @@ __device__ __forceinline__ void s2_store_tile(const v16i (&acc)[P][TM][TN], int6
   const int wm = wave >> 1, wn = wave & 1;
   // residue byte(s) of value v of MFMA tile (a, b): real -> r[0]; 3M -> re, im
   auto residues = [&](int a, int b, int v, int (&r)[2]) {
-    if (!CPLX) {
+    if constexpr (SMALL) {  // |T| <= 2^28: the differences in INT32, the short reduction
+      if (!CPLX) {
+        r[0] = smod_small(acc[0][a][b][v], l);
+        r[1] = 0;
+      } else {
+        const int t1 = acc[0][a][b][v], t2 = acc[CPLX ? 1 : 0][a][b][v], t3 = acc[CPLX ? 2 : 0][a][b][v];
+        r[0] = smod_small(t1 - t2, l);
+        r[1] = smod_small(t3 - t1 - t2, l);
+      }
+    } else if (!CPLX) {
       r[0] = smod_i32(acc[0][a][b][v], l);
       r[1] = 0;
     } else {
@@ -602,6 +631,17 @@ __device__ __forceinline__ void s2_store_tile(const v16i (&acc)[P][TM][TN], int6
       }
 }
 
+// The epilogue form chosen once per tile (each form keeps its values in
+// straight-line code that the compiler interleaves).
+template <bool CPLX, int P, int TM, int TN>
+__device__ __forceinline__ void s2_store_tile(const v16i (&acc)[P][TM][TN], int64_t m0, int64_t n0, int64_t M,
+                                              int64_t N, int8_t* __restrict__ out, int l, int64_t ldr, bool small) {
+  if (small)
+    s2_store_tile_as<CPLX, P, TM, TN, true>(acc, m0, n0, M, N, out, l, ldr);
+  else
+    s2_store_tile_as<CPLX, P, TM, TN, false>(acc, m0, n0, M, N, out, l, ldr);
+}
+
 template <bool CPLX, int V>
 __device__ __forceinline__ void s2_gemm_tile(const int8_t* __restrict__ Ap, const int8_t* __restrict__ Bp,
                                              int64_t plane_a, int64_t plane_b, int64_t rows_a, int64_t rows_b,
@@ -633,7 +673,7 @@ __device__ __forceinline__ void s2_gemm_tile(const int8_t* __restrict__ Ap, cons
     if (c0 + run >= nsteps) break;
     s2_reduce_acc<P, TM, TN>(acc, l);
   }
-  s2_store_tile<CPLX, P, TM, TN>(acc, m0, n0, M, N, out, l, N);
+  s2_store_tile<CPLX, P, TM, TN>(acc, m0, n0, M, N, out, l, N, nsteps <= S2_SMALL_STEPS);
 }
 
 template <bool CPLX, int V>
@@ -1283,6 +1323,9 @@ __global__ __launch_bounds__(256, 1) void k_s2_gemm_crt(CrtArgs ca, const int8_t
     for (int i = 0; i < NZ; ++i) z[v][i] = 0;
   int l = 0;
   int64_t in_mod = 0, in_run = 0;  // chunks of modulus l, of its current run
+  // the short reduction in the small tile only: the large one keeps its
+  // accumulators in registers around these stores only with one epilogue form
+  const bool small = !Cfg::LARGE && Cfg::SMALL && nsteps <= S2_SMALL_STEPS;
   auto hook = [&](int64_t r) {
     if (r < 0) return;
     ++in_mod;
@@ -1627,17 +1670,20 @@ __device__ __forceinline__ void s2_gemm_tile_moduli(const int8_t* __restrict__ A
   v16i acc[P][TM][TN];
   zero_acc<P, TM, TN>(acc);
   if (nsteps == 0) {  // K = 0: every residue is 0
-    for (int l = 0; l < s; ++l) s2_store_tile<CPLX, P, TM, TN>(acc, m0, n0, M, N, out, l, ldr);
+    for (int l = 0; l < s; ++l) s2_store_tile<CPLX, P, TM, TN>(acc, m0, n0, M, N, out, l, ldr, false);
     return;
   }
   int l = 0;
   int64_t in_mod = 0, in_run = 0;  // chunks of modulus l, of its current run
+  // the short reduction in the small tile only: the large one keeps its
+  // accumulators in registers around these stores only with one epilogue form
+  const bool small = !Cfg::LARGE && Cfg::SMALL && nsteps <= S2_SMALL_STEPS;
   auto hook = [&](int64_t r) {
     if (r < 0) return;
     ++in_mod;
     ++in_run;
     if (in_mod == nsteps) {
-      s2_store_tile<CPLX, P, TM, TN>(acc, m0, n0, M, N, out, l, ldr);
+      s2_store_tile<CPLX, P, TM, TN>(acc, m0, n0, M, N, out, l, ldr, small);
       zero_acc<P, TM, TN>(acc);
       ++l;
       in_mod = 0;
