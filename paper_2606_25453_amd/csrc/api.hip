@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
 #include <map>
 #include <mutex>
 #include <new>
@@ -1376,8 +1377,13 @@ struct ozk_batch_plan {
   std::vector<ozk::BatchProb> prob;
   std::vector<uint8_t> large;  // 1: the problem's items take the 128 x 128 tile
   size_t hint_cap = 0;         // entries of each item hint array on the device
-  int64_t *items_s = nullptr, *items_l = nullptr;
-  int32_t *hint_s = nullptr, *hint_l = nullptr, *order_s = nullptr, *order_l = nullptr;
+  struct ItemTables {          // device regions of one tile's item chunks (ozk::BatchItems)
+    int64_t* start = nullptr;
+    int32_t* hint = nullptr;
+    int32_t* prob = nullptr;
+    int64_t* tile0 = nullptr;
+    int64_t* queue = nullptr;
+  } tab[2];                    // [0] small tile, [1] large tile
 };
 
 namespace {
@@ -1398,50 +1404,93 @@ std::vector<int32_t> unit_hints(const std::vector<int64_t>& start, int count) {
   return h;
 }
 
-// Item lists of both tiles from pl->large (problems of each tile by
-// decreasing K, the others after them with no items), uploaded into the
-// plan's device regions, and the grids of the two persistent launches.
+// The item chunks and queues of both tiles (ozk::BatchItems) from pl->large,
+// uploaded into the plan's device regions, and the grids of the two
+// persistent launches.  A problem whose items carry more than a quarter of
+// one queue's share of the tile's INT8 work is cut into up to
+// OZK_BATCH_QUEUES chunks of consecutive tiles; the chunks, the most work
+// first, each go to the queue with the least work so far (longest processing
+// time first); a queue then runs its chunks by decreasing K, so that its
+// longest items start first.
 hipError_t upload_items(ozk_batch_plan* pl) {
+  constexpr int Q = ozk::OZK_BATCH_QUEUES;
   const int count = pl->count;
   const bool cplx = pl->op == OZK_OP_ZGEMM;
+  struct Chunk {
+    int prob;
+    int64_t tile0, n, kp;
+  };
   for (int kind = 0; kind < 2; ++kind) {
-    std::vector<int32_t> order(count);
-    std::iota(order.begin(), order.end(), 0);
-    auto mine = [&](int q) { return pl->large[q] == kind && pl->prob[q].tiles > 0; };
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-      if (mine(a) != mine(b)) return mine(a);
-      return pl->prob[a].Kp > pl->prob[b].Kp;
-    });
-    std::vector<int64_t> items(count + 1, 0);
+    auto tiles = [&](int i) {
+      const ozk::BatchProb& q = pl->prob[i];
+      return (pl->large[i] == kind && q.tiles > 0) ? ozk::s2_tile_count(cplx, kind == 1, q.M, q.N) : (int64_t)0;
+    };
+    auto kp = [&](int i) { return pl->prob[i].Kp > 0 ? pl->prob[i].Kp : (int64_t)1; };  // K = 0 items still store
+    double total = 0.0;
+    for (int i = 0; i < count; ++i) total += (double)tiles(i) * (double)kp(i);
+    std::vector<Chunk> chunks;
     for (int i = 0; i < count; ++i) {
-      const ozk::BatchProb& q = pl->prob[order[i]];
-      items[i + 1] = items[i] + (mine(order[i]) ? ozk::s2_tile_count(cplx, kind == 1, q.M, q.N) : 0);
+      const int64_t t = tiles(i);
+      if (t == 0) continue;
+      const double w = (double)t * (double)kp(i);
+      int64_t c = (int64_t)std::ceil(w * 4.0 * Q / total);
+      c = std::max<int64_t>(1, std::min<int64_t>(c, std::min<int64_t>(t, Q)));
+      for (int64_t j = 0; j < c; ++j) chunks.push_back({i, t * j / c, t * (j + 1) / c - t * j / c, kp(i)});
     }
-    const std::vector<int32_t> hint = unit_hints(items, count);
+    std::vector<int> by_work(chunks.size());
+    std::iota(by_work.begin(), by_work.end(), 0);
+    std::stable_sort(by_work.begin(), by_work.end(), [&](int a, int b) {
+      return chunks[a].n * chunks[a].kp > chunks[b].n * chunks[b].kp;
+    });
+    std::vector<std::vector<int>> queue(Q);
+    std::vector<double> load(Q, 0.0);
+    for (int c : by_work) {
+      const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+      queue[x].push_back(c);
+      load[x] += (double)chunks[c].n * (double)chunks[c].kp;
+    }
+    std::vector<int64_t> start(1, 0), tile0, qoff(Q + 1, 0);
+    std::vector<int32_t> prob;
+    int64_t qmax = 0;
+    for (int x = 0; x < Q; ++x) {
+      std::stable_sort(queue[x].begin(), queue[x].end(), [&](int a, int b) { return chunks[a].kp > chunks[b].kp; });
+      qoff[x] = start.back();
+      for (int c : queue[x]) {
+        prob.push_back(chunks[c].prob);
+        tile0.push_back(chunks[c].tile0);
+        start.push_back(start.back() + chunks[c].n);
+      }
+      qmax = std::max<int64_t>(qmax, start.back() - qoff[x]);
+    }
+    qoff[Q] = start.back();
+    const int nchunk = (int)prob.size();
+    if (nchunk > Q * (count > 0 ? count : 1)) return hipErrorInvalidValue;
+    const std::vector<int32_t> hint = unit_hints(start, nchunk);
     if (hint.size() > pl->hint_cap) return hipErrorInvalidValue;
-    int64_t* di = kind ? pl->items_l : pl->items_s;
-    int32_t* dh = kind ? pl->hint_l : pl->hint_s;
-    int32_t* dord = kind ? pl->order_l : pl->order_s;
-    hipError_t e = hipMemcpy(di, items.data(), sizeof(int64_t) * (count + 1), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(dh, hint.data(), sizeof(int32_t) * hint.size(), hipMemcpyHostToDevice);
-    if (e == hipSuccess && count > 0)
-      e = hipMemcpy(dord, order.data(), sizeof(int32_t) * count, hipMemcpyHostToDevice);
+    const ozk_batch_plan::ItemTables& d = pl->tab[kind];
+    hipError_t e = hipMemcpy(d.start, start.data(), sizeof(int64_t) * start.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(d.hint, hint.data(), sizeof(int32_t) * hint.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess && nchunk > 0)
+      e = hipMemcpy(d.prob, prob.data(), sizeof(int32_t) * nchunk, hipMemcpyHostToDevice);
+    if (e == hipSuccess && nchunk > 0)
+      e = hipMemcpy(d.tile0, tile0.data(), sizeof(int64_t) * nchunk, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(d.queue, qoff.data(), sizeof(int64_t) * (Q + 1), hipMemcpyHostToDevice);
     if (e != hipSuccess) return e;
+    // resident workgroups, a multiple of Q, and no more than the longest queue needs
     const int64_t slots = (int64_t)pl->ncu * ozk::s2_batch_gemm_blocks_per_cu(cplx, kind == 1);
-    const int64_t n = items[count];
-    const int grid = (int)(n < slots ? (n > 0 ? n : 1) : slots);
+    const int64_t n = start.back();
+    const int grid = (int)std::max<int64_t>(Q, std::min<int64_t>(slots / Q, qmax) * Q);
+    const ozk::BatchItems items{{d.start, d.hint}, d.prob, d.tile0, d.queue};
     if (kind) {
       pl->tot.items_l = n;
       pl->grid_large = grid;
+      pl->bd.items_l = items;
     } else {
       pl->tot.items = n;
       pl->grid_small = grid;
+      pl->bd.items = items;
     }
   }
-  pl->bd.items = {pl->items_s, pl->hint_s};
-  pl->bd.items_l = {pl->items_l, pl->hint_l};
-  pl->bd.order = pl->order_s;
-  pl->bd.order_l = pl->order_l;
   return hipSuccess;
 }
 
@@ -1534,14 +1583,17 @@ ozk_status ozk_batch_plan_create(ozk_ctx* ctx, ozk_op op, ozk_scheme scheme, int
                              h_split = unit_hints(split, count), h_crt = unit_hints(crt, count);
   pl->hint_cap = (size_t)((max_items >> ozk::OZK_BATCH_HINT_SHIFT) + 2);
   // device tables: problems, four prefix arrays with their hints, and for each
-  // tile an item prefix array, its hints and its order
+  // tile the item chunks (prefix array, hints, problem, first tile) and queues
   const size_t nprob = sizeof(ozk::BatchProb) * (count > 0 ? count : 1);
   const size_t npre = sizeof(int64_t) * (count + 1);
-  const size_t nord = sizeof(int32_t) * (count > 0 ? count : 1);
+  const size_t nchk = (size_t)ozk::OZK_BATCH_QUEUES * (count > 0 ? count : 1);  // chunks per tile at most
   const size_t nhcap = sizeof(int32_t) * pl->hint_cap;
+  const size_t nqueue = sizeof(int64_t) * (ozk::OZK_BATCH_QUEUES + 1);
   size_t nhint = 0;
   for (const auto* h : {&h_rows, &h_cols, &h_split, &h_crt}) nhint += align256(sizeof(int32_t) * h->size());
-  const size_t total = align256(nprob) + 6 * align256(npre) + nhint + 2 * align256(nhcap) + 2 * align256(nord);
+  const size_t per_tile = align256(sizeof(int64_t) * (nchk + 1)) + align256(nhcap) + align256(sizeof(int32_t) * nchk) +
+                          align256(sizeof(int64_t) * nchk) + align256(nqueue);
+  const size_t total = align256(nprob) + 4 * align256(npre) + nhint + 2 * per_tile;
   if (hipMalloc(&pl->dev, total) != hipSuccess) {
     pl->dev = nullptr;
     free_plan(pl);
@@ -1565,12 +1617,13 @@ ozk_status ozk_batch_plan_create(ozk_ctx* ctx, ozk_op op, ozk_scheme scheme, int
   void* q2 = put(h_cols.data(), sizeof(int32_t) * h_cols.size(), sizeof(int32_t) * h_cols.size());
   void* q3 = put(h_split.data(), sizeof(int32_t) * h_split.size(), sizeof(int32_t) * h_split.size());
   void* q5 = put(h_crt.data(), sizeof(int32_t) * h_crt.size(), sizeof(int32_t) * h_crt.size());
-  pl->items_s = (int64_t*)put(nullptr, 0, npre);
-  pl->items_l = (int64_t*)put(nullptr, 0, npre);
-  pl->hint_s = (int32_t*)put(nullptr, 0, nhcap);
-  pl->hint_l = (int32_t*)put(nullptr, 0, nhcap);
-  pl->order_s = (int32_t*)put(nullptr, 0, nord);
-  pl->order_l = (int32_t*)put(nullptr, 0, nord);
+  for (ozk_batch_plan::ItemTables& t : pl->tab) {
+    t.start = (int64_t*)put(nullptr, 0, sizeof(int64_t) * (nchk + 1));
+    t.hint = (int32_t*)put(nullptr, 0, nhcap);
+    t.prob = (int32_t*)put(nullptr, 0, sizeof(int32_t) * nchk);
+    t.tile0 = (int64_t*)put(nullptr, 0, sizeof(int64_t) * nchk);
+    t.queue = (int64_t*)put(nullptr, 0, nqueue);
+  }
   pl->bd.prob = (const ozk::BatchProb*)pp;
   pl->bd.rows = {(const int64_t*)r1, (const int32_t*)q1};
   pl->bd.cols = {(const int64_t*)r2, (const int32_t*)q2};

@@ -100,18 +100,32 @@ struct BatchUnits {
   const int32_t* hint;
 };
 
+// GEMM items (output tiles of a problem, all moduli each) of one batch tile,
+// in the order of the persistent launch.  Items come in chunks, runs of
+// consecutive output tiles of one problem, and the chunks in
+// OZK_BATCH_QUEUES queues of about equal INT8 work: queue x holds the items
+// [queue[x], queue[x + 1]) and is run by the workgroups w with
+// w % OZK_BATCH_QUEUES == x.  Workgroups are dispatched to the eight XCDs in
+// turn, so a queue is one XCD's and the tiles of a chunk share its L2.
+constexpr int OZK_BATCH_QUEUES = 8;
+
+struct BatchItems {
+  BatchUnits chunks;     // item prefix sums over the chunks, queue by queue
+  const int32_t* prob;   // chunk -> problem
+  const int64_t* tile0;  // chunk -> its first output tile within the problem
+  const int64_t* queue;  // OZK_BATCH_QUEUES + 1 item offsets
+};
+
 // Device view of a batch plan: the problem table and the work units of each
 // step.
 struct BatchDev {
   const BatchProb* prob;
-  BatchUnits rows;   // row blocks of 16 rows (pre-pass of A)
-  BatchUnits cols;   // column blocks of 32 (column scales of B)
-  BatchUnits split;  // (64-column block, K chunk) pairs (residues of B)
-  BatchUnits items;    // GEMM items of the small-tile problems (output tiles, all moduli each) in `order`
-  BatchUnits items_l;  // the same for the large-tile problems, in `order_l`
+  BatchUnits rows;     // row blocks of 16 rows (pre-pass of A)
+  BatchUnits cols;     // column blocks of 32 (column scales of B)
+  BatchUnits split;    // (64-column block, K chunk) pairs (residues of B)
+  BatchItems items;    // GEMM items of the small-tile problems
+  BatchItems items_l;  // the same for the large-tile problems
   BatchUnits crt;      // output blocks of 256 (CRT)
-  const int32_t* order;    // small-tile item order -> problem index (problems without items at the end)
-  const int32_t* order_l;  // large-tile item order -> problem index
   int count;
 };
 

@@ -1573,10 +1573,12 @@ hipError_t s2_crt_auto(const int32_t* info, bool cplx, int64_t M, int64_t N, con
 // Many uneven problems in one launch per step.  The plan uploads a problem
 // table and, per step, the prefix sums of the work units of each problem;
 // a workgroup finds its problem by binary search.  The GEMM step is one
-// persistent launch: the (problem, output tile) items, each running all s
-// moduli in one K loop, are enumerated with the problems in decreasing K
-// (longest items first) and workgroup w takes items w, w + G, w + 2G, ... so
-// that the load is balanced without atomics.
+// persistent launch per tile size over (problem, output tile) items, each
+// running all s moduli in one K loop: the plan deals the items out to one
+// queue per XCD in chunks of consecutive tiles of one problem (so that the
+// operand panels a problem's tiles share are fetched into one L2, not eight),
+// balancing the queues' INT8 work, longest items first within a queue, and
+// the workgroups of an XCD walk its queue with a fixed stride, without atomics.
 
 namespace {
 
@@ -1651,9 +1653,10 @@ static_assert(OZK_BATCH_ROW_ALIGN % batch_rows<false, S2_BATCH_V>() == 0 &&
 
 // One output tile of a batched problem for all s moduli.  The residue planes
 // of consecutive moduli are consecutive K chunks of the packed operands, so
-// the s GEMMs run as one K loop of s nsteps chunks whose load pipeline never
-// drains between moduli; the step hook stores a modulus's residues once its
-// last chunk is in (and reduces the sums at run ends, as above).
+// when a modulus's sums fit one INT32 run (nsteps <= S2_RUN_STEPS) the s GEMMs
+// run as one K loop of s nsteps chunks whose load pipeline never drains
+// between moduli; the step hook stores a modulus's residues once its last
+// chunk is in.  Longer K takes each modulus as its own sequence of runs.
 template <bool CPLX, int V>
 __device__ __forceinline__ void s2_gemm_tile_moduli(const int8_t* __restrict__ Ap, const int8_t* __restrict__ Bp,
                                                     int64_t rows_a, int64_t rows_b, int64_t nsteps, int64_t M,
@@ -1665,7 +1668,7 @@ __device__ __forceinline__ void s2_gemm_tile_moduli(const int8_t* __restrict__ A
   using T = GemmTile<P, TM, TN, NS>;
   const int64_t tiles_m = (M + T::BM - 1) / T::BM, tiles_n = (N + T::BN - 1) / T::BN;
   int64_t tm, tn;
-  tile_of(tile, tiles_m, tiles_n, 0, 4, tm, tn);
+  tile_of(tile, tiles_m, tiles_n, 1, 4, tm, tn);  // a chunk's tiles run on one XCD: groups of 4 tile rows
   const int64_t m0 = tm * T::BM, n0 = tn * T::BN;
   v16i acc[P][TM][TN];
   zero_acc<P, TM, TN>(acc);
@@ -1673,43 +1676,53 @@ __device__ __forceinline__ void s2_gemm_tile_moduli(const int8_t* __restrict__ A
     for (int l = 0; l < s; ++l) s2_store_tile<CPLX, P, TM, TN>(acc, m0, n0, M, N, out, l, ldr, false);
     return;
   }
+  if (nsteps > S2_RUN_STEPS) {
+    for (int l = 0; l < s; ++l) {
+      for (int64_t c0 = 0; c0 < nsteps; c0 += S2_RUN_STEPS) {
+        const int64_t n = nsteps - c0 < S2_RUN_STEPS ? nsteps - c0 : S2_RUN_STEPS;
+        gemm_tile_accumulate<P, TM, TN, NS, DIAGONAL, P>(Ap, Bp, rows_a, rows_b, m0, n0, l * nsteps + c0, n, lds,
+                                                         acc);
+        if (c0 + n < nsteps) s2_reduce_acc<P, TM, TN>(acc, l);
+      }
+      s2_store_tile<CPLX, P, TM, TN>(acc, m0, n0, M, N, out, l, ldr, false);
+      zero_acc<P, TM, TN>(acc);
+    }
+    return;
+  }
   int l = 0;
-  int64_t in_mod = 0, in_run = 0;  // chunks of modulus l, of its current run
+  int64_t in_mod = 0;  // chunks of modulus l done
   // the short reduction in the small tile only: the large one keeps its
   // accumulators in registers around these stores only with one epilogue form
   const bool small = !Cfg::LARGE && Cfg::SMALL && nsteps <= S2_SMALL_STEPS;
+  // one rare branch that rewrites the accumulators in place (a second one,
+  // for run reductions, made the compiler copy them on every step)
   auto hook = [&](int64_t r) {
     if (r < 0) return;
-    ++in_mod;
-    ++in_run;
-    if (in_mod == nsteps) {
+    if (++in_mod == nsteps) {
       s2_store_tile<CPLX, P, TM, TN>(acc, m0, n0, M, N, out, l, ldr, small);
       zero_acc<P, TM, TN>(acc);
       ++l;
       in_mod = 0;
-      in_run = 0;
-    } else if (in_run == S2_RUN_STEPS) {
-      s2_reduce_acc<P, TM, TN>(acc, l);
-      in_run = 0;
     }
   };
   gemm_tile_accumulate<P, TM, TN, NS, DIAGONAL, P>(Ap, Bp, rows_a, rows_b, m0, n0, 0, (int64_t)s * nsteps, lds, acc,
                                                    hook);
 }
 
-// Persistent over the items of one tile size: workgroup w takes items w,
-// w + G, ... of `items` (problems in the order `order`).
+// Persistent over the items of one tile size: with Q = OZK_BATCH_QUEUES
+// (the grid a multiple of Q), workgroup w runs queue w % Q, taking its items
+// w / Q, w / Q + G / Q, ...
 template <bool CPLX, int V>
-__global__ __launch_bounds__(256, V == S2_BATCH_V ? 3 : 1) void k_b_gemm_mod(BatchDev bd, BatchUnits items,
-                                                                            const int32_t* __restrict__ order,
+__global__ __launch_bounds__(256, V == S2_BATCH_V ? 3 : 1) void k_b_gemm_mod(BatchDev bd, BatchItems items,
                                                                             int8_t* __restrict__ ws, int s) {
   extern __shared__ __attribute__((aligned(1024))) int8_t lds[];
-  const int64_t total = items.start[bd.count];
-  for (int64_t it = blockIdx.x; it < total; it += gridDim.x) {
-    const int i = find_problem(items, it);
-    const BatchProb& q = bd.prob[order[i]];
+  const int x = blockIdx.x % OZK_BATCH_QUEUES;
+  const int64_t stride = gridDim.x / OZK_BATCH_QUEUES, end = items.queue[x + 1];
+  for (int64_t it = items.queue[x] + blockIdx.x / OZK_BATCH_QUEUES; it < end; it += stride) {
+    const int c = find_problem(items.chunks, it);
+    const BatchProb& q = bd.prob[items.prob[c]];
     s2_gemm_tile_moduli<CPLX, V>(ws + q.off_a, ws + q.off_b, q.ra, q.rb, q.Kp / OZK_K_CHUNK, q.M, q.N,
-                                 ws + q.off_res, q.ldr, it - items.start[i], s, lds);
+                                 ws + q.off_res, q.ldr, items.tile0[c] + (it - items.chunks.start[c]), s, lds);
   }
 }
 
@@ -1748,25 +1761,26 @@ int s2_batch_gemm_blocks_per_cu(bool cplx, bool large) {
 }
 
 template <bool CPLX, int V>
-static hipError_t launch_batch_gemm(const BatchDev& bd, const BatchUnits& items, const int32_t* order, int64_t n,
-                                    int grid, int8_t* ws, int s, hipStream_t st) {
+static hipError_t launch_batch_gemm(const BatchDev& bd, const BatchItems& items, int64_t n, int grid, int8_t* ws,
+                                    int s, hipStream_t st) {
   if (n <= 0) return hipSuccess;
+  if (grid < OZK_BATCH_QUEUES || grid % OZK_BATCH_QUEUES != 0) return hipErrorInvalidConfiguration;
   constexpr int lds = S2Cfg<CPLX, V>::LDS_BYTES;
   static std::atomic<uint64_t> lds_done{0};
   const hipError_t e_lds = lds_limit(reinterpret_cast<const void*>(k_b_gemm_mod<CPLX, V>), lds, lds_done);
   if (e_lds != hipSuccess) return e_lds;
-  hipLaunchKernelGGL((k_b_gemm_mod<CPLX, V>), dim3((unsigned)grid), dim3(256), lds, st, bd, items, order, ws, s);
+  hipLaunchKernelGGL((k_b_gemm_mod<CPLX, V>), dim3((unsigned)grid), dim3(256), lds, st, bd, items, ws, s);
   return hipGetLastError();
 }
 
 // The GEMM step of a batch: the large-tile items, then the small-tile ones.
 hipError_t s2_batched_gemm(int s, bool cplx, const BatchDev& bd, const BatchTotals& tot, int8_t* ws, int grid_small,
                            int grid_large, hipStream_t st) {
-  hipError_t e = cplx ? launch_batch_gemm<true, 2>(bd, bd.items_l, bd.order_l, tot.items_l, grid_large, ws, s, st)
-                      : launch_batch_gemm<false, 1>(bd, bd.items_l, bd.order_l, tot.items_l, grid_large, ws, s, st);
+  hipError_t e = cplx ? launch_batch_gemm<true, 2>(bd, bd.items_l, tot.items_l, grid_large, ws, s, st)
+                      : launch_batch_gemm<false, 1>(bd, bd.items_l, tot.items_l, grid_large, ws, s, st);
   if (e != hipSuccess) return e;
-  return cplx ? launch_batch_gemm<true, S2_BATCH_V>(bd, bd.items, bd.order, tot.items, grid_small, ws, s, st)
-              : launch_batch_gemm<false, S2_BATCH_V>(bd, bd.items, bd.order, tot.items, grid_small, ws, s, st);
+  return cplx ? launch_batch_gemm<true, S2_BATCH_V>(bd, bd.items, tot.items, grid_small, ws, s, st)
+              : launch_batch_gemm<false, S2_BATCH_V>(bd, bd.items, tot.items, grid_small, ws, s, st);
 }
 
 hipError_t s2_batched_prepass(int s, bool cplx, const BatchDev& bd, const BatchTotals& tot, int8_t* ws,
