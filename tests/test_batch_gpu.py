@@ -86,6 +86,49 @@ def test_batch_alpha_beta(ctx):
     plan.close()
 
 
+
+@pytest.mark.parametrize("cplx", [False, True])
+def test_batch_long_k_and_split_problems(ctx, cplx):
+    """The two item schedules the plan can give a problem: K beyond one INT32
+    run (more than 4095 chunks of 32 per modulus: the item walks each
+    modulus as its own runs) next to a short-K problem, and a batch of one
+    problem whose output tiles are cut into chunks for all eight XCD queues;
+    both equal the single calls and the oracle on sampled rows and columns."""
+    s = 3
+    rng = np.random.default_rng(11)
+    if cplx:
+        A0 = synth.complex_phi_matrix(20, 131104, 1.0, 61, 62)
+        B0 = synth.complex_phi_matrix(131104, 12, 1.0, 63, 64)
+        A1 = synth.complex_phi_matrix(70, 96, 1.0, 65, 66)
+        B1 = synth.complex_phi_matrix(96, 50, 1.0, 67, 68)
+        A2 = synth.complex_phi_matrix(512, 64, 1.0, 69, 70)
+        B2 = synth.complex_phi_matrix(64, 520, 1.0, 71, 72)
+    else:
+        A0 = synth.phi_matrix(20, 131104, 1.0, 61)
+        B0 = synth.phi_matrix(131104, 12, 1.0, 63)
+        A1 = synth.phi_matrix(70, 96, 1.0, 65)
+        B1 = synth.phi_matrix(96, 50, 1.0, 67)
+        A2 = synth.phi_matrix(512, 64, 1.0, 69)
+        B2 = synth.phi_matrix(64, 520, 1.0, 71)
+    op = ozk.OZK_OP_ZGEMM if cplx else ozk.OZK_OP_DGEMM
+    for probs in ([(A0, B0), (A1, B1)], [(A2, B2)]):
+        dA, dB, dC = _device_batch(probs)
+        plan = ozk.BatchPlan(ctx, op, ozk.OZK_SCHEME2, s, list(zip(dA, dB, dC)))
+        plan.run()
+        for i, (A, B) in enumerate(probs):
+            got = host(dC[i])
+            single = host(ozk.ozk_zgemm_3m(ctx, s, dA[i], dB[i]) if cplx
+                          else ozk.ozk_dgemm(ctx, ozk.OZK_SCHEME2, s, dA[i], dB[i]))
+            assert np.array_equal(got, single), i
+            rows = np.sort(rng.choice(A.shape[0], size=min(6, A.shape[0]), replace=False))
+            cols = np.sort(rng.choice(B.shape[1], size=min(5, B.shape[1]), replace=False))
+            # the row and column scales depend only on their own row or column,
+            # so the product of the sampled rows and columns is the full
+            # product's values there
+            ref = (s2.z3m_gemm(A[rows], B[:, cols], s) if cplx else s2.s2_dgemm(A[rows], B[:, cols], s))
+            assert np.array_equal(got[np.ix_(rows, cols)], ref), i
+        plan.close()
+
 def test_batch_graph_replay_is_bit_identical(ctx):
     s = 16
     probs = make_batch(40, 16, 256, 123, True)
