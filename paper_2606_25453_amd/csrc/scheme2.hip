@@ -69,19 +69,21 @@ __device__ __forceinline__ int smod_exact(double t, int l) {
 // smod of an INT32 accumulator.
 __device__ __forceinline__ int smod_i32(int x, int l) { return smod_exact((double)x, l); }
 
-// smod(x, m_l) for |x| < 2^30 in two binary64 operations and a 24-bit
-// multiply: fma(x, 1/m, 1.5 * 2^52) rounds x / m to the nearest integer q,
-// which the low 32 bits of that double hold (its unit in the last place is 1
-// and 2^51 + q is its fraction); the product's error is below 2^-29 while an
-// odd m keeps x / m at least 1/(2m) from a half-integer, so q is exact, and
-// x - q m (|q| < 2^23) is the symmetric residue.  m = 256 (the only even
-// modulus) is the sign-extended low byte.
-__device__ __forceinline__ int smod_small(int x, int l) {
-  const int m = c_s2.m[l];
+// The low byte of smod(x, m_l) for |x| < 2^30, in two binary64 operations
+// and a 24-bit multiply: fma(x, 1/m, 1.5 * 2^52) rounds x / m to the nearest
+// integer q, which the low 32 bits of that double hold (its unit in the last
+// place is 1 and 2^51 + q is its fraction); the product's error is below
+// 2^-29 while an odd m keeps x / m at least 1/(2m) from a half-integer, so q
+// is exact and x - q m is the symmetric residue.  Only its byte is kept, which
+// needs q m mod 256 alone (from the low byte of q), and for m = 256 (the only
+// even modulus) any integer q leaves the low byte of x, the byte of the
+// symmetric residue.  The upper bytes of the result are not defined.
+__device__ __forceinline__ uint32_t smod_small_byte(int x, int l) {
   const double y = __fma_rn((double)x, c_s2.inv_m[l], 6755399441055744.0);
-  const int q = (int)(uint32_t)(uint64_t)__double_as_longlong(y);
-  const int r = x - __mul24(q, m);
-  return m == 256 ? (int)(int8_t)x : r;  // a select, no branch: the values interleave
+  const uint32_t q = (uint32_t)(uint64_t)__double_as_longlong(y);
+  // both factors visibly below 2^24 (m <= 256), so that the product is one
+  // 24-bit multiply
+  return (uint32_t)x - (q & 0xFFu) * ((uint32_t)c_s2.m[l] & 0x1FFu);
 }
 
 // smod(a + b, m_l) for a, b already symmetric residues of m_l.
@@ -533,23 +535,47 @@ __device__ __forceinline__ void s2_reduce_acc(v16i (&acc)[P][TM][TN], int l) {
         }
 }
 
+// Bytes of two words by a selector (v_perm_b32): selector byte i picks byte
+// i of the result, 0-3 from lo, 4-7 from hi, 12 a zero byte.
+__device__ __forceinline__ uint32_t perm_bytes(uint32_t hi, uint32_t lo, uint32_t sel) {
+  return __builtin_amdgcn_perm(hi, lo, sel);
+}
+
+// Byte 0 of four values as one word (byte k from r[k]).
+__device__ __forceinline__ uint32_t pack_bytes(const uint32_t (&r)[4]) {
+  const uint32_t lo = perm_bytes(r[1], r[0], 0x0C0C0400u), hi = perm_bytes(r[3], r[2], 0x0C0C0400u);
+  return lo | (hi << 16);
+}
+
 // A lane's four residues of rows r0..r0+3 of its column, one byte each
 // (byte k: row r0 + k), transposed across its quad of lanes (columns c0..c0+3):
 // afterwards lane q holds row r0 + q, byte j being column c0 + j.  Two
-// exchanges with the quad neighbours (DPP quad permutations lane ^ 1, lane ^ 2).
-__device__ __forceinline__ uint32_t quad_transpose4(uint32_t w, int q) {
-  uint32_t p = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)w, 0xB1, 0xF, 0xF, false);
-  w = (q & 1) ? ((w & 0xFF00FF00u) | ((p >> 8) & 0x00FF00FFu)) : ((w & 0x00FF00FFu) | ((p << 8) & 0xFF00FF00u));
-  p = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)w, 0x4E, 0xF, 0xF, false);
-  return (q & 2) ? ((p >> 16) | (w & 0xFFFF0000u)) : ((w & 0xFFFFu) | (p << 16));
+// exchanges with the quad neighbours (DPP quad permutations lane ^ 1, lane ^ 2),
+// each followed by one byte selection whose selector depends on the lane:
+// sel1 / sel2 from quad_selectors.
+__device__ __forceinline__ void quad_selectors(int q, uint32_t& sel1, uint32_t& sel2) {
+  // exchange with lane ^ 1: even lanes keep bytes 0, 2 and take the
+  // neighbour's 0, 2 into 1, 3; odd lanes keep 1, 3 and take its 1, 3 into 0, 2
+  sel1 = (q & 1) ? 0x03070105u : 0x06020400u;
+  // exchange with lane ^ 2: lanes 0, 1 keep bytes 0, 1 and take the
+  // neighbour's 0, 1 into 2, 3; lanes 2, 3 keep 2, 3 and take its 2, 3 into 0, 1
+  sel2 = (q & 2) ? 0x03020706u : 0x05040100u;
+}
+
+__device__ __forceinline__ uint32_t quad_transpose4(uint32_t w, uint32_t sel1, uint32_t sel2) {
+  // every lane of a quad permutation has a source lane
+  uint32_t p = (uint32_t)__builtin_amdgcn_mov_dpp((int)w, 0xB1, 0xF, 0xF, true);
+  w = perm_bytes(p, w, sel1);
+  p = (uint32_t)__builtin_amdgcn_mov_dpp((int)w, 0x4E, 0xF, 0xF, true);
+  return perm_bytes(p, w, sel2);
 }
 
 // The residues mod m_l of a finished tile (Eq. 7); for 3M the real and
 // imaginary parts from the three products (Eq. 16), into planes of M rows
 // of ldr >= N bytes.  `small`: the tile summed at most 512 K chunks in this
 // run (|T| <= 512 * 32 * 128^2 = 2^28, so the 3M combinations stay below
-// 2^30 in INT32), and the short reduction applies.  When ldr is a multiple of 4 (and `out` 4-byte
-// aligned) each group of four rows of a lane is
+// 2^30 in INT32), and the short reduction applies.  When ldr is a multiple of
+// 4 (and `out` 4-byte aligned) each group of four rows of a lane is
 // transposed across its quad so that every lane writes 4 bytes of one row:
 // a quarter of the store instructions.
 // The output positions are derived from a lane index the compiler cannot see
@@ -563,53 +589,66 @@ __device__ __forceinline__ void s2_store_tile_as(const v16i (&acc)[P][TM][TN], i
   asm volatile("" : "+v"(tid));
   const int lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
-  // residue byte(s) of value v of MFMA tile (a, b): real -> r[0]; 3M -> re, im
-  auto residues = [&](int a, int b, int v, int (&r)[2]) {
+  // residue byte(s) of value v of MFMA tile (a, b) (byte 0; the upper bytes
+  // are not defined): real -> r[0]; 3M -> re, im
+  auto residues = [&](int a, int b, int v, uint32_t (&r)[2]) {
     if constexpr (SMALL) {  // |T| <= 2^28: the differences in INT32, the short reduction
       if (!CPLX) {
-        r[0] = smod_small(acc[0][a][b][v], l);
+        r[0] = smod_small_byte(acc[0][a][b][v], l);
         r[1] = 0;
       } else {
         const int t1 = acc[0][a][b][v], t2 = acc[CPLX ? 1 : 0][a][b][v], t3 = acc[CPLX ? 2 : 0][a][b][v];
-        r[0] = smod_small(t1 - t2, l);
-        r[1] = smod_small(t3 - t1 - t2, l);
+        r[0] = smod_small_byte(t1 - t2, l);
+        r[1] = smod_small_byte(t3 - t1 - t2, l);
       }
     } else if (!CPLX) {
-      r[0] = smod_i32(acc[0][a][b][v], l);
+      r[0] = (uint32_t)smod_i32(acc[0][a][b][v], l);
       r[1] = 0;
     } else {
       // T1 - T2 and T3 - T1 - T2 are exact in binary64 (|T| < 2^31): two
       // reductions instead of three and the residue sums
       const double t1 = (double)acc[0][a][b][v], t2 = (double)acc[CPLX ? 1 : 0][a][b][v],
                    t3 = (double)acc[CPLX ? 2 : 0][a][b][v];
-      r[0] = smod_exact(t1 - t2, l);
-      r[1] = smod_exact(t3 - t1 - t2, l);
+      r[0] = (uint32_t)smod_exact(t1 - t2, l);
+      r[1] = (uint32_t)smod_exact(t3 - t1 - t2, l);
     }
   };
   constexpr int NPL = CPLX ? 2 : 1;  // output planes per modulus
   if ((ldr & 3) == 0 && ((uintptr_t)out & 3) == 0) {
     const int q = lane & 3;
+    uint32_t sel1, sel2;
+    quad_selectors(q, sel1, sel2);
+    // the lane's row and first column for a = b = g = 0; the others are
+    // uniform offsets from there
+    const int64_t row0 = m0 + wm * 32 * TM + 4 * (lane >> 5) + q;
+    const int64_t col0 = n0 + wn * 32 * TN + ((lane & 31) & ~3);
+    int8_t* const base = out + (int64_t)(NPL * l) * mn + row0 * ldr + col0;
+    // rows and columns left from there (the whole workgroup tile inside the
+    // output: no bound), so that each store's test is two 32-bit compares
+    const bool full = m0 + 64 * TM <= M && n0 + 64 * TN <= N;
+    const int64_t rl = M - row0, cl = N - col0;
+    const int rlim = full || rl > 1024 ? 1024 : (int)rl, clim = full || cl > 1024 ? 1024 : (int)cl;
 #pragma unroll
     for (int a = 0; a < TM; ++a)
 #pragma unroll
       for (int b = 0; b < TN; ++b)
 #pragma unroll
         for (int g = 0; g < 4; ++g) {
-          uint32_t w[2] = {0u, 0u};
+          uint32_t r4[2][4];
 #pragma unroll
           for (int k = 0; k < 4; ++k) {
-            int r[2];
+            uint32_t r[2];
             residues(a, b, 4 * g + k, r);
 #pragma unroll
-            for (int pl = 0; pl < NPL; ++pl) w[pl] |= (uint32_t)(uint8_t)r[pl] << (8 * k);
+            for (int pl = 0; pl < NPL; ++pl) r4[pl][k] = r[pl];
           }
-          const int64_t row = m0 + wm * 32 * TM + a * 32 + 8 * g + 4 * (lane >> 5) + q;
-          const int64_t c0 = n0 + wn * 32 * TN + b * 32 + ((lane & 31) & ~3);
+          // columns col0 + 3 < ldr: past N only the plane's padding
+          const bool in = a * 32 + 8 * g < rlim && b * 32 < clim;
 #pragma unroll
           for (int pl = 0; pl < NPL; ++pl) {
-            const uint32_t t = quad_transpose4(w[pl], q);
-            if (row < M && c0 < N)  // columns c0 + 3 < ldr: past N only the plane's padding
-              *reinterpret_cast<uint32_t*>(out + (NPL * l + pl) * mn + row * ldr + c0) = t;
+            const uint32_t t = quad_transpose4(pack_bytes(r4[pl]), sel1, sel2);
+            if (in)
+              *reinterpret_cast<uint32_t*>(base + pl * mn + (int64_t)(a * 32 + 8 * g) * ldr + b * 32) = t;
           }
         }
     return;
@@ -624,7 +663,7 @@ __device__ __forceinline__ void s2_store_tile_as(const v16i (&acc)[P][TM][TN], i
         const int64_t row = m0 + wm * 32 * TM + a * 32 + 8 * (v / 4) + 4 * (lane >> 5) + (v % 4);
         const int64_t col = n0 + wn * 32 * TN + b * 32 + (lane & 31);
         if (row >= M || col >= N) continue;
-        int r[2];
+        uint32_t r[2];
         residues(a, b, v, r);
 #pragma unroll
         for (int pl = 0; pl < NPL; ++pl) out[(NPL * l + pl) * mn + row * ldr + col] = (int8_t)r[pl];
