@@ -735,111 +735,122 @@ struct CrtArgs {
   uint32_t W[OZK_MAX_S][NL];  // (P/m_l) q_l
   uint32_t P[NL];
   double Pf;
+  double Pinv;  // 1 / Pf rounded
 };
 
 // Z = smod(V, P) as a sign and magnitude limbs, for V = sum_l W_l c_l >= 0
-// given as NL + 1 32-bit limbs.
+// given as NL + 1 32-bit limbs; Z in [-P/2, P/2).
 template <int U = NL>
 __device__ __forceinline__ void crt_reduce(const CrtArgs& ca, const uint32_t (&v)[NL + 1], uint32_t (&mag)[NL],
                                            bool& neg) {
   static_assert(U >= 1 && U <= NL, "limbs used");
-  // quotient estimate by floating point, then exact correction
+  // quotient estimate: V / P < s 2^8 <= 2^13 (W_l < P, c_l < 2^8) and the
+  // estimate's relative error is below 2^-49 (U + 1 roundings of V, two of
+  // 1 / P, one of the product), so its floor is floor(V / P) or one off
   double vf = 0.0;
 #pragma unroll
   for (int i = U; i >= 0; --i) vf = vf * 4294967296.0 + (double)v[i];
-  int64_t q = (int64_t)floor(vf / ca.Pf);
-  if (q < 0) q = 0;
-  // r = v - q P (signed, U+1 limbs, two's complement)
-  int64_t borrow = 0;
+  const double qd = floor(vf * ca.Pinv);
+  const uint32_t q = qd > 0.0 ? (uint32_t)qd : 0u;
+  // r = V - q P (U + 1 limbs, two's complement)
   uint32_t r[NL + 1];
-  uint64_t mc = 0;
+  {
+    uint64_t mc = 0;
+    int64_t borrow = 0;
 #pragma unroll
-  for (int i = 0; i <= U; ++i) {
-    const uint64_t pi = i < U ? ca.P[i] : 0;
-    const uint64_t prod = pi * (uint64_t)q + mc;
-    mc = prod >> 32;
-    const int64_t d = (int64_t)v[i] - (int64_t)(uint32_t)prod + borrow;
-    r[i] = (uint32_t)d;
-    borrow = d >> 32;  // 0 or -1
+    for (int i = 0; i <= U; ++i) {
+      const uint64_t prod = (uint64_t)(i < U ? ca.P[i] : 0u) * q + mc;
+      mc = prod >> 32;
+      const int64_t d = (int64_t)v[i] - (int64_t)(uint32_t)prod + borrow;
+      r[i] = (uint32_t)d;
+      borrow = d >> 32;  // 0 or -1
+    }
   }
-  auto negative = [&]() { return (int32_t)r[U] < 0; };
-  auto add_p = [&](int sign) {  // r += sign * P
+  // one step into [0, P): + P after an estimate one too high (rare), - P
+  // after one too low
+  if ((int32_t)r[U] < 0) {
     int64_t cy = 0;
 #pragma unroll
     for (int i = 0; i <= U; ++i) {
-      const int64_t pi = i < U ? (int64_t)ca.P[i] : 0;
-      const int64_t d = (int64_t)r[i] + sign * pi + cy;
+      const int64_t d = (int64_t)r[i] + (int64_t)(i < U ? ca.P[i] : 0u) + cy;
       r[i] = (uint32_t)d;
       cy = d >> 32;
     }
-  };
-  auto ge_p = [&]() {  // r >= P (r non-negative)
-    if (r[U]) return true;
-    for (int i = U - 1; i >= 0; --i) {
-      if (r[i] != ca.P[i]) return r[i] > ca.P[i];
-    }
-    return true;
-  };
-  while (negative()) add_p(1);
-  while (ge_p()) add_p(-1);
-  // symmetric lift: r >= P/2  <=>  2r >= P
-  uint32_t tw[NL + 1];
-  uint32_t cy2 = 0;
-#pragma unroll
-  for (int i = 0; i <= U; ++i) {
-    tw[i] = (r[i] << 1) | cy2;
-    cy2 = r[i] >> 31;
   }
-  bool ge = false;
   {
-    bool decided = false;
-    if (tw[U]) {
-      ge = true;
-      decided = true;
-    }
-    for (int i = U - 1; i >= 0 && !decided; --i) {
-      if (tw[i] != ca.P[i]) {
-        ge = tw[i] > ca.P[i];
-        decided = true;
-      }
-    }
-    if (!decided) ge = true;
-  }
-  if (ge) {
-    // magnitude = P - r
+    uint32_t d[NL + 1];
     int64_t b = 0;
 #pragma unroll
-    for (int i = 0; i < U; ++i) {
-      const int64_t d = (int64_t)ca.P[i] - (int64_t)r[i] + b;
-      mag[i] = (uint32_t)d;
-      b = d >> 32;
+    for (int i = 0; i <= U; ++i) {
+      const int64_t t = (int64_t)r[i] - (int64_t)(i < U ? ca.P[i] : 0u) + b;
+      d[i] = (uint32_t)t;
+      b = t >> 32;
     }
-    neg = true;
-  } else {
+    const bool ge = b == 0;  // r >= P
 #pragma unroll
-    for (int i = 0; i < U; ++i) mag[i] = r[i];
-    neg = false;
+    for (int i = 0; i <= U; ++i) r[i] = ge ? d[i] : r[i];
   }
+  // symmetric lift: Z = r - P when 2r >= P, i.e. r >= P - r
+  uint32_t m2[NL];
+  int64_t b = 0, b2 = 0;
+#pragma unroll
+  for (int i = 0; i < U; ++i) {
+    const int64_t t = (int64_t)ca.P[i] - (int64_t)r[i] + b;
+    m2[i] = (uint32_t)t;
+    b = t >> 32;
+  }
+#pragma unroll
+  for (int i = 0; i < U; ++i) b2 = ((int64_t)r[i] - (int64_t)m2[i] + b2) >> 32;
+  neg = b2 == 0;
+#pragma unroll
+  for (int i = 0; i < U; ++i) mag[i] = neg ? m2[i] : r[i];
 #pragma unroll
   for (int i = U; i < NL; ++i) mag[i] = 0;
 }
 
-// Z = smod(sum_l W_l c_l, P) from the s residue planes at res (stride apart).
-template <int U = NL>
-__device__ __forceinline__ void crt_combine(const CrtArgs& ca, const int8_t* res, int64_t stride, uint32_t (&mag)[NL],
-                                            bool& neg) {
-  // all residues first (independent loads in flight together), then the sum
-  int cv[OZK_MAX_S];
+// 32-bit limbs the CRT sums of the first s moduli need: sum_l W_l c_l <
+// s 2^8 P < 2^(bits(P) + 13) for s <= 20 (the same count as the host's).
+constexpr int crt_limbs_of(int s) {
+  uint32_t p[NL + 1] = {1};
+  for (int l = 0; l < s; ++l) {
+    uint64_t c = 0;
+    for (int i = 0; i <= NL; ++i) {
+      const uint64_t t = (uint64_t)p[i] * (uint32_t)kS2.m[l] + c;
+      p[i] = (uint32_t)t;
+      c = t >> 32;
+    }
+  }
+  int bits = 0;
+  for (int i = NL; i >= 0 && bits == 0; --i)
+    if (p[i]) {
+      int b = 32;
+      while (!((p[i] >> (b - 1)) & 1u)) --b;
+      bits = 32 * i + b;
+    }
+  return (bits + 13 + 31) / 32;
+}
+
+// Z = smod(sum_l W_l c_l, P) from the S residue planes at res (stride apart),
+// S known at compile time: straight-line code (a loop over a runtime count
+// kept the residues in indexed registers and branched per modulus).
+template <int S>
+__device__ __forceinline__ void crt_combine_s(const CrtArgs& ca, const int8_t* res, int64_t stride,
+                                              uint32_t (&mag)[NL], bool& neg) {
+  constexpr int U = crt_limbs_of(S);
+  static_assert(U >= 1 && U <= NL, "limbs");
+  // all residues first (independent loads in flight together)
+  int cv[S];
 #pragma unroll
-  for (int l = 0; l < OZK_MAX_S; ++l) cv[l] = l < ca.s ? (int)res[l * stride] : 0;
+  for (int l = 0; l < S; ++l) cv[l] = (int)res[l * stride];
+  // V = sum_l W_l u_l with the residues u_l in [0, m_l): 32 x 32-bit products
+  // summed in 64 bits per limb of W (V < S 2^8 P fits U limbs)
   uint64_t acc[U] = {};
 #pragma unroll
-  for (int l = 0; l < OZK_MAX_S; ++l) {
-    if (l >= ca.s) break;
-    int c = cv[l];
-    if (c < 0) c += c_s2.m[l];
+  for (int l = 0; l < S; ++l) {
+    const int c = cv[l];
+    const uint32_t u = (uint32_t)(c + (c < 0 ? kS2.m[l] : 0));
 #pragma unroll
-    for (int i = 0; i < U; ++i) acc[i] += (uint64_t)ca.W[l][i] * (uint32_t)c;
+    for (int i = 0; i < U; ++i) acc[i] += (uint64_t)ca.W[l][i] * u;
   }
   uint32_t v[NL + 1] = {};
   uint64_t carry = 0;
@@ -851,6 +862,29 @@ __device__ __forceinline__ void crt_combine(const CrtArgs& ca, const int8_t* res
   }
   v[U] = (uint32_t)carry;
   crt_reduce<U>(ca, v, mag, neg);
+}
+
+// Z = smod(sum_l W_l c_l, P) for the runtime s = ca.s, dispatched (a uniform
+// branch) to the straight-line body of that s: among the s whose sums need
+// U limbs, or every s when U = CRT_ANY_S.
+constexpr int CRT_ANY_S = 0;
+
+template <int U, int S = 1>
+__device__ __forceinline__ void crt_combine(const CrtArgs& ca, const int8_t* res, int64_t stride, uint32_t (&mag)[NL],
+                                            bool& neg) {
+  if constexpr (S <= OZK_MAX_S) {
+    if constexpr (U == CRT_ANY_S || crt_limbs_of(S) == U) {
+      if (ca.s == S) {
+        crt_combine_s<S>(ca, res, stride, mag, neg);
+        return;
+      }
+    }
+    crt_combine<U, S + 1>(ca, res, stride, mag, neg);
+  } else {  // no such s (never launched so)
+#pragma unroll
+    for (int i = 0; i < NL; ++i) mag[i] = 0;
+    neg = false;
+  }
 }
 
 // The CRT sum of one output kept in registers while the moduli stream by
@@ -940,9 +974,24 @@ __device__ __forceinline__ void s2_crt_block(const CrtArgs& ca, int64_t M, int64
                                              const int32_t* __restrict__ sigma, const int32_t* __restrict__ tau,
                                              TO a_re, TO a_im, TO b_re, TO b_im, TO* __restrict__ C, int64_t ldc,
                                              int64_t blk, int64_t ldr = -1) {
-  const int64_t idx = blk * 256 + threadIdx.x;
-  if (idx >= (int64_t)M * N) return;
-  const int64_t row = idx / N, col = idx % N;
+  // output blk * 256 + thread: the block's first row and column by one
+  // uniform division, the thread's by a binary32 quotient estimate of the
+  // few rows it lies past them (t / N < 256 / N + 2, estimate off by at most
+  // one) and one correction
+  if (N <= 0) return;
+  const int64_t idx0 = blk * 256, row0 = idx0 / N, col0 = idx0 - row0 * N;
+  const uint32_t t = (uint32_t)(col0 + (int64_t)threadIdx.x);  // < N + 256
+  int64_t dq = (int64_t)(uint32_t)((float)t * __builtin_amdgcn_rcpf((float)N));
+  int64_t col = (int64_t)t - dq * N;
+  if (col < 0) {
+    --dq;
+    col += N;
+  } else if (col >= N) {
+    ++dq;
+    col -= N;
+  }
+  const int64_t row = row0 + dq;
+  if (row >= M) return;
   if (ldr < 0) ldr = N;
   const int64_t mn = (int64_t)M * ldr, at = row * ldr + col;
   const int si = sigma[row], tj = tau[col];
@@ -963,7 +1012,7 @@ __device__ __forceinline__ void s2_crt_block(const CrtArgs& ca, int64_t M, int64
   s2_store_c<CPLX, TO>(h, row, col, a_re, a_im, b_re, b_im, C, ldc);
 }
 
-// U: 32-bit limbs in use (P and the sums of s W_l c_l < s 2^8 P fit U limbs).
+// U: the 32-bit limbs the sums of this call's s need (crt_limbs_of), or CRT_ANY_S.
 template <bool CPLX, typename TO = double, int U = NL>
 __global__ __launch_bounds__(256) void k_s2_crt(CrtArgs ca, int M, int N, const int8_t* __restrict__ res,
                                                 const int32_t* __restrict__ sigma, const int32_t* __restrict__ tau,
@@ -1011,6 +1060,7 @@ static void crt_args(int s, CrtArgs& ca, int& ta, int& tb) {
   double pf = 0.0;
   for (int i = NL - 1; i >= 0; --i) pf = pf * 4294967296.0 + (double)P[i];
   ca.Pf = pf;
+  ca.Pinv = 1.0 / pf;
   for (int l = 0; l < OZK_MAX_S; ++l)
     for (int i = 0; i < NL; ++i) ca.W[l][i] = 0;
   for (int l = 0; l < s; ++l) {
@@ -1024,6 +1074,7 @@ static void crt_args(int s, CrtArgs& ca, int& ta, int& tb) {
     big_mul_small(Q, NL, (uint32_t)q);
     for (int i = 0; i < NL; ++i) ca.W[l][i] = Q[i];
   }
+
   // ceil(log2 P) = bit length of P - 1
   uint32_t Pm1[NL];
   for (int i = 0; i < NL; ++i) Pm1[i] = P[i];
@@ -1508,7 +1559,7 @@ __global__ __launch_bounds__(256) void k_s2_crt_auto(int M, int N, int64_t nblk,
   int s;
   if (!s2_chosen(info, s)) return;
   for (int64_t b = blockIdx.x; b < nblk; b += gridDim.x)
-    s2_crt_block<CPLX>(c_crt_all[s - 1], M, N, res, sigma, tau, a_re, a_im, b_re, b_im, C, ldc, b);
+    s2_crt_block<CPLX, double, CRT_ANY_S>(c_crt_all[s - 1], M, N, res, sigma, tau, a_re, a_im, b_re, b_im, C, ldc, b);
 }
 
 S2Budgets s2_budgets() {
@@ -1846,22 +1897,23 @@ hipError_t s2_batched_crt(int s, bool cplx, const BatchDev& bd, const BatchTotal
   CrtArgs ca;
   crt_args(s, ca, ta, tb);
   if (tot.crt == 0) return hipSuccess;
-  if (cplx) {
-    switch (crt_limbs(ca)) {
-      case 1: case 2: case 3: case 4:
-        hipLaunchKernelGGL((k_b_crt<true, 4>), dim3((unsigned)tot.crt), dim3(256), 0, st, ca, bd, ws); break;
-      case 5: hipLaunchKernelGGL((k_b_crt<true, 5>), dim3((unsigned)tot.crt), dim3(256), 0, st, ca, bd, ws); break;
-      default: hipLaunchKernelGGL((k_b_crt<true, NL>), dim3((unsigned)tot.crt), dim3(256), 0, st, ca, bd, ws);
+  const dim3 grid((unsigned)tot.crt);
+  auto launch = [&](auto kern) {
+    hipLaunchKernelGGL(kern, grid, dim3(256), 0, st, ca, bd, ws);
+    return hipGetLastError();
+  };
+  auto pick = [&](auto cplx_c) {
+    constexpr bool CP = decltype(cplx_c)::value;
+    switch (crt_limbs(ca)) {  // the kernel holding this s
+      case 1: return launch(k_b_crt<CP, 1>);
+      case 2: return launch(k_b_crt<CP, 2>);
+      case 3: return launch(k_b_crt<CP, 3>);
+      case 4: return launch(k_b_crt<CP, 4>);
+      case 5: return launch(k_b_crt<CP, 5>);
     }
-  } else {
-    switch (crt_limbs(ca)) {
-      case 1: case 2: case 3: case 4:
-        hipLaunchKernelGGL((k_b_crt<false, 4>), dim3((unsigned)tot.crt), dim3(256), 0, st, ca, bd, ws); break;
-      case 5: hipLaunchKernelGGL((k_b_crt<false, 5>), dim3((unsigned)tot.crt), dim3(256), 0, st, ca, bd, ws); break;
-      default: hipLaunchKernelGGL((k_b_crt<false, NL>), dim3((unsigned)tot.crt), dim3(256), 0, st, ca, bd, ws);
-    }
-  }
-  return hipGetLastError();
+    return launch(k_b_crt<CP, NL>);
+  };
+  return cplx ? pick(std::true_type{}) : pick(std::false_type{});
 }
 
 hipError_t s2_batched(int s, bool cplx, const BatchDev& bd, const BatchTotals& tot, int8_t* ws, int grid_small,
