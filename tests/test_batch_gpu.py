@@ -46,7 +46,7 @@ def make_batch(count, lo, hi, seed, cplx):
     return probs
 
 
-@pytest.mark.parametrize("cplx,s", [(True, 16), (True, 7), (False, 14)])
+@pytest.mark.parametrize("cplx,s", [(True, 16), (True, 7), (False, 14), (False, 1), (True, 20)])
 def test_batch_matches_single_calls_and_oracle(ctx, cplx, s):
     probs = make_batch(12, 1, 300, 77 + s, cplx)
     probs.append((np.zeros((0, 5), probs[0][0].dtype), np.zeros((5, 3), probs[0][0].dtype)))  # empty M

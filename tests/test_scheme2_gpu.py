@@ -154,6 +154,25 @@ def test_dgemm_scheme2_bit_exact(ctx, s, shape):
     assert np.array_equal(C, s2.s2_dgemm(A, B, s))
 
 
+
+@pytest.mark.parametrize("s", list(range(1, 21)))
+@pytest.mark.parametrize("cplx", [False, True])
+def test_crt_every_modulus_count(ctx, s, cplx):
+    """The CRT has one straight-line body per modulus count (chosen by a
+    uniform branch inside the kernel of the count's limb count): every count
+    1..20, real and 3M, against the oracle on a ragged shape."""
+    M, N, K = 37, 45, 70
+    if cplx:
+        A = synth.complex_phi_matrix(M, K, 1.0, 2000 + s, 2100 + s)
+        B = synth.complex_phi_matrix(K, N, 1.0, 2200 + s, 2300 + s)
+        C = host(ozk.ozk_zgemm_3m(ctx, s, dev(A), dev(B)))
+        assert np.array_equal(C, s2.z3m_gemm(A, B, s))
+    else:
+        A = synth.phi_matrix(M, K, 1.0, 2400 + s)
+        B = synth.phi_matrix(K, N, 1.0, 2500 + s)
+        C = host(ozk.ozk_dgemm(ctx, ozk.OZK_SCHEME2, s, dev(A), dev(B)))
+        assert np.array_equal(C, s2.s2_dgemm(A, B, s))
+
 def test_scheme2_alpha_beta_edges(ctx):
     s, M, N, K = 14, 40, 30, 50
     A = synth.phi_matrix(M, K, 1.0, 1)
