@@ -485,9 +485,10 @@ constexpr int64_t S2_SMALL_STEPS = 512;
 // 4 x 4, all 256 matrix registers), 3M 128 x 128.  An LDS stage holds G
 // consecutive K chunks (a stage of G P planes; one barrier per G chunks):
 //   V0 base,  G = 2, 4 stages     V1 base,  G = 1, 4 stages
-//   V2 large, G = 2 (3M 1), 4 stages     V3 large, G = 2, 3 stages
-// The real base tile runs two workgroups per CU (its registers and its
-// 64 KB of LDS allow it), the others one.  The large tile reuses each operand
+//   V2 large, G = 1, 4 stages     V3 large, G = 2, 3 stages
+// The real base tile and the real V2 (192 registers, 48 KB of LDS) run two
+// workgroups per CU, so that one's tile epilogue and pipeline ramp overlap the
+// other's MFMAs (V2 pays off at short K); the others run one.  The large tile reuses each operand
 // fragment read from LDS over more MFMAs; it holds one INT32-safe run only
 // (no mid-run reduction, which would push its accumulators out of the matrix
 // registers), so the launcher takes the base tile (variant - 2) when K is
@@ -509,10 +510,11 @@ struct S2Cfg {
   static constexpr int TM = SMALL ? 1 : LARGE && !CPLX ? 4 : 2;
   static constexpr int TN = SMALL ? 1 : ((V == 3 || V == 6) && !CPLX) ? 4 : CPLX && !LARGE ? 1 : 2;
   static constexpr int NS = V == 3 ? 3 : V == 4 ? 2 : V == 5 ? (CPLX ? 3 : 2) : V == 6 ? (CPLX ? 6 : 2) : 4;
-  static constexpr int G = V == 0 ? 2 : V == 1 || V == 4 ? 1 : V == 2 ? (CPLX ? 1 : 2) : V == 5 ? (CPLX ? 2 : 4)
+  static constexpr int G = V == 0 ? 2 : V == 1 || V == 4 ? 1 : V == 2 ? 1 : V == 5 ? (CPLX ? 2 : 4)
                                        : V == 6 ? (CPLX ? 1 : 3) : 2;
   static constexpr int LDS_BYTES = GemmTile<G * P, TM, TN, NS>::LDS_BYTES;
   static_assert(LDS_BYTES <= 160 * 1024, "LDS budget");
+  static constexpr int MINB = V == 2 && !CPLX ? 2 : 1;  // workgroups per CU the registers must allow
 };
 
 // One output tile of one modulus: the per-modulus products, then smod (3M:
@@ -716,7 +718,7 @@ __device__ __forceinline__ void s2_gemm_tile(const int8_t* __restrict__ Ap, cons
 }
 
 template <bool CPLX, int V>
-__global__ __launch_bounds__(256, 1) void k_s2_gemm_mod(const int8_t* __restrict__ Ap,
+__global__ __launch_bounds__(256, (S2Cfg<CPLX, V>::MINB)) void k_s2_gemm_mod(const int8_t* __restrict__ Ap,
                                                        const int8_t* __restrict__ Bp, int64_t plane_a,
                                                        int64_t plane_b, int64_t rows_a, int64_t rows_b,
                                                        int64_t nsteps, int M, int N, int raster, int group,
