@@ -195,42 +195,82 @@ __device__ __forceinline__ void s2_store_residues(const double (&re)[4], const d
 // layout, so every store instruction writes whole 128-byte lines.  Every
 // modulus plane is a packed operand of the shared GEMM core: real
 // packed[l][c][r][32], complex packed[l][c][q][r][32] (q = re, im, sum).
-// Padding rows, non-finite rows and k past K get zero residues; the main
-// loop has no condition between its loads (only the 4-k group straddling K
-// takes the guarded path).  Rows past `rows` load row 0 and discard it, so
-// that every lane takes part in the reductions.
+// Non-finite rows and k past K get zero residues, and so do the padding rows
+// when zero_pad is set (an operand whose padding rows feed only outputs that
+// are never stored may leave them as they are); the main loop has no
+// condition between its loads (only the 4-k group straddling K takes the
+// guarded path).  Rows past `rows` load row 0 and discard it, so that every
+// lane takes part in the reductions.
 constexpr int S2_ROWS_PER_BLOCK = 16;
+
+// The entry exponents of a row block kept in LDS between the maximum and the
+// norm-bound pass (one read of the operand instead of two): int16 per entry,
+// rows (K + 2) entries apart (a row per bank offset), zero entries as
+// INT16_MIN.  The batched pre-pass caches rows up to this K.
+constexpr int S2_ECACHE_BATCH_K = 512;
+// The row-scale launch caches rows up to this K (128 KB of LDS).
+constexpr int S2_ECACHE_MAX_K = 4096;
+
+__host__ __device__ constexpr int s2_ecache_bytes(int64_t kc) {
+  return kc > 0 ? (int)(S2_ROWS_PER_BLOCK * (kc + 2) * 2) : 0;
+}
 
 template <bool CPLX, typename T = double>
 // kb0, kb1 (multiples of 64): the K range whose residues this block writes
 // (kb1 < 0: to Kp); sigma_in: the row scales already computed (the residue
-// pass split over K), else this block computes and stores them.
+// pass split over K), else this block computes and stores them; ecache: LDS
+// for the exponents of rows with K <= kc (null: read the row twice).
 __device__ __forceinline__ void s2_split_rows_block(const T* __restrict__ X, int64_t ldx, int64_t rows,
                                                     int64_t K, int64_t Kp, int64_t rows_packed, S2Args sa,
                                                     int32_t* __restrict__ sigma_out, int8_t* __restrict__ packed,
                                                     int64_t blk, int64_t kb0 = 0, int64_t kb1 = -1,
-                                                    const int32_t* __restrict__ sigma_in = nullptr) {
+                                                    const int32_t* __restrict__ sigma_in = nullptr,
+                                                    bool zero_pad = true, int16_t* ecache = nullptr,
+                                                    int64_t kc = 0) {
   constexpr int W = CPLX ? 2 : 1, NP = CPLX ? 3 : 1;
   const int lane = threadIdx.x & 63, q = lane & 15;
   const int64_t r = (blk * 4 + (threadIdx.x >> 6)) * 4 + (lane >> 4);
   if (r >= rows_packed) return;  // whole waves only (rows_packed is a multiple of 16)
   const bool in = r < rows;
+  if (!in && !zero_pad) return;  // a whole row's 16 lanes: the reductions stay within rows
   const T* xr = X + (in ? r : 0) * ldx * W;
   int sigma = 0;
   if (sigma_in) {
     sigma = in ? sigma_in[r] : 0;
   } else {
+    const bool cached = ecache != nullptr && K <= kc;  // uniform
+    int16_t* er = cached ? ecache + (threadIdx.x >> 4) * (kc + 2) : nullptr;
     int e = OZK_EXP_ZERO;
+    if (cached) {
 #pragma unroll 8
-    for (int64_t k = q; k < K; k += 16) {
-      const int ek = entry_expo<CPLX>(xr + k * W);
-      e = ek > e ? ek : e;
+      for (int64_t k = q; k < K; k += 16) {
+        const int ek = entry_expo<CPLX>(xr + k * W);
+        // finite exponents lie in [-1074, 1025]; a non-finite entry makes the
+        // row's scale non-finite, so its cached value is never read
+        er[k] = (int16_t)(ek == OZK_EXP_ZERO ? -32768 : ek > 32767 ? 32767 : ek);
+        e = ek > e ? ek : e;
+      }
+    } else {
+#pragma unroll 8
+      for (int64_t k = q; k < K; k += 16) {
+        const int ek = entry_expo<CPLX>(xr + k * W);
+        e = ek > e ? ek : e;
+      }
     }
     e = group16_max(in ? e : OZK_EXP_ZERO);
     int64_t S = 0;
-    if (e != OZK_EXP_NONFINITE && e != OZK_EXP_ZERO)
+    if (e != OZK_EXP_NONFINITE && e != OZK_EXP_ZERO) {
+      if (cached) {  // each lane reads back the entries it wrote
 #pragma unroll 8
-      for (int64_t k = q; k < K; k += 16) S += norm_term(entry_expo<CPLX>(xr + k * W), e);
+        for (int64_t k = q; k < K; k += 16) {
+          const int c = er[k];
+          S += norm_term(c == -32768 ? OZK_EXP_ZERO : c, e);
+        }
+      } else {
+#pragma unroll 8
+        for (int64_t k = q; k < K; k += 16) S += norm_term(entry_expo<CPLX>(xr + k * W), e);
+      }
+    }
     S = group16_sum64(S);
     sigma = in ? scale_from(e, S, sa.T) : 0;
     if (in && q == 0) sigma_out[r] = sigma;
@@ -269,12 +309,15 @@ __device__ __forceinline__ void s2_split_rows_block(const T* __restrict__ X, int
   }
 }
 
+// kc > 0: the exponents cached in s2_ecache_bytes(kc) bytes of dynamic LDS.
 template <bool CPLX, typename T = double>
 __global__ __launch_bounds__(256) void k_s2_split_rows(const T* __restrict__ X, int64_t ldx, int64_t rows,
                                                        int64_t K, int64_t Kp, int64_t rows_packed, S2Args sa,
                                                        int32_t* __restrict__ sigma_out,
-                                                       int8_t* __restrict__ packed) {
-  s2_split_rows_block<CPLX, T>(X, ldx, rows, K, Kp, rows_packed, sa, sigma_out, packed, blockIdx.x);
+                                                       int8_t* __restrict__ packed, int64_t kc) {
+  extern __shared__ int16_t ecache[];
+  s2_split_rows_block<CPLX, T>(X, ldx, rows, K, Kp, rows_packed, sa, sigma_out, packed, blockIdx.x, 0, -1, nullptr,
+                               true, kc > 0 ? ecache : nullptr, kc);
 }
 
 // The residues of a row block over one K range per grid y (the row scales
@@ -397,7 +440,8 @@ __global__ __launch_bounds__(256) void k_s2_col_finish(int64_t cols, int T, cons
 // takes the 8 k of quarter q of the chunk in column j and writes one 8-byte
 // piece per plane: the four quarters of 16 consecutive columns are 512
 // contiguous bytes of a plane (16 packed rows of 32 bytes), and every load
-// reads 16 consecutive columns in 4 rows of B.
+// reads 16 consecutive columns in 4 rows of B.  Padding columns get zero
+// residues when zero_pad is set, else they are left as they are.
 constexpr int S2_COL_BLOCK = 64;
 constexpr int S2_COL_K = OZK_K_CHUNK / 4;
 
@@ -411,11 +455,12 @@ template <bool CPLX, typename T = double>
 __device__ __forceinline__ void s2_split_cols_block(const T* __restrict__ X, int64_t ldx, int64_t K,
                                                     int64_t cols, int64_t Kp, int64_t cols_packed, int s,
                                                     const int32_t* __restrict__ tau, int8_t* __restrict__ packed,
-                                                    int64_t jb, int64_t c) {
+                                                    int64_t jb, int64_t c, bool zero_pad = true) {
   constexpr int W = CPLX ? 2 : 1, NP = CPLX ? 3 : 1;
   const int lane = threadIdx.x & 63, qk = lane & 3;
   const int64_t j = jb * S2_COL_BLOCK + (threadIdx.x >> 6) * 16 + (lane >> 2);
   const int64_t k0 = c * OZK_K_CHUNK + qk * S2_COL_K;
+  if (j >= cols && !zero_pad) return;  // no cross-lane work below
   const int t = j < cols ? tau[j] : 0;
   const bool live = j < cols && t != OZK_EXP_NONFINITE;
   double re[S2_COL_K], im[S2_COL_K];
@@ -1113,14 +1158,27 @@ static hipError_t split_rows_t(int s, bool cplx, const T* X, int64_t ldx, int64_
     // few long rows: the scales first (a launch that writes no residues),
     // then the residues over (row block, K range)
     const dim3 g2((unsigned)blocks, (unsigned)((kp + S2_ROW_KR - 1) / S2_ROW_KR));
+    // the exponents cached in LDS when every block of the launch still fits
+    // the GPU at once with them (the cache then costs no occupancy)
+    int64_t kc = round_up(K, 16);
+    const int bytes = s2_ecache_bytes(kc);
+    if (K > S2_ECACHE_MAX_K || blocks > 256 * (int64_t)(160 * 1024 / bytes)) kc = 0;
+    const int dyn = s2_ecache_bytes(kc);
+    static std::atomic<uint64_t> lds_c{0}, lds_r{0};
+    const hipError_t e_lds =
+        kc ? lds_limit(cplx ? reinterpret_cast<const void*>(k_s2_split_rows<true, T>)
+                            : reinterpret_cast<const void*>(k_s2_split_rows<false, T>),
+                       s2_ecache_bytes(S2_ECACHE_MAX_K), cplx ? lds_c : lds_r)
+           : hipSuccess;
+    if (e_lds != hipSuccess) return e_lds;
     if (cplx) {
-      hipLaunchKernelGGL((k_s2_split_rows<true, T>), dim3((unsigned)blocks), dim3(256), 0, st, X, ldx, rows, K, 0, rp,
-                         sa, sigma, packed);
+      hipLaunchKernelGGL((k_s2_split_rows<true, T>), dim3((unsigned)blocks), dim3(256), dyn, st, X, ldx, rows, K, 0,
+                         rp, sa, sigma, packed, kc);
       hipLaunchKernelGGL((k_s2_row_residues<true, T>), g2, dim3(256), 0, st, X, ldx, rows, K, kp, rp, sa, sigma,
                          packed);
     } else {
-      hipLaunchKernelGGL((k_s2_split_rows<false, T>), dim3((unsigned)blocks), dim3(256), 0, st, X, ldx, rows, K, 0, rp,
-                         sa, sigma, packed);
+      hipLaunchKernelGGL((k_s2_split_rows<false, T>), dim3((unsigned)blocks), dim3(256), dyn, st, X, ldx, rows, K, 0,
+                         rp, sa, sigma, packed, kc);
       hipLaunchKernelGGL((k_s2_row_residues<false, T>), g2, dim3(256), 0, st, X, ldx, rows, K, kp, rp, sa, sigma,
                          packed);
     }
@@ -1128,10 +1186,10 @@ static hipError_t split_rows_t(int s, bool cplx, const T* X, int64_t ldx, int64_
   }
   if (cplx)
     hipLaunchKernelGGL((k_s2_split_rows<true, T>), dim3((unsigned)blocks), dim3(256), 0, st, X, ldx, rows, K, kp, rp,
-                       sa, sigma, packed);
+                       sa, sigma, packed, (int64_t)0);
   else
     hipLaunchKernelGGL((k_s2_split_rows<false, T>), dim3((unsigned)blocks), dim3(256), 0, st, X, ldx, rows, K, kp,
-                       rp, sa, sigma, packed);
+                       rp, sa, sigma, packed, (int64_t)0);
   return hipGetLastError();
 }
 
@@ -1687,12 +1745,17 @@ __device__ __forceinline__ int find_problem(const BatchUnits& u, int64_t x) {
 
 }  // namespace
 
+// The batched pre-pass leaves the padding rows and columns of the packed
+// operands as they are: they feed only outputs past M and N, which no later
+// step reads.
 template <bool CPLX>
 __global__ __launch_bounds__(256) void k_b_split_rows(BatchDev bd, int8_t* __restrict__ ws, S2Args sa) {
+  __shared__ int16_t ecache[s2_ecache_bytes(S2_ECACHE_BATCH_K) / 2];
   const int p = find_problem(bd.rows, blockIdx.x);
   const BatchProb& q = bd.prob[p];
   s2_split_rows_block<CPLX>(q.A, q.lda, q.M, q.K, q.Kp, q.ra, sa, reinterpret_cast<int32_t*>(ws + q.off_sig),
-                            ws + q.off_a, blockIdx.x - bd.rows.start[p]);
+                            ws + q.off_a, blockIdx.x - bd.rows.start[p], 0, -1, nullptr, false, ecache,
+                            S2_ECACHE_BATCH_K);
 }
 
 template <bool CPLX>
@@ -1710,7 +1773,7 @@ __global__ __launch_bounds__(256) void k_b_split_cols(BatchDev bd, int8_t* __res
   const int64_t local = blockIdx.x - bd.split.start[p];
   const int64_t jblocks = q.rb / S2_COL_BLOCK;
   s2_split_cols_block<CPLX>(q.B, q.ldb, q.K, q.N, q.Kp, q.rb, s, reinterpret_cast<const int32_t*>(ws + q.off_tau),
-                            ws + q.off_b, local % jblocks, local / jblocks);
+                            ws + q.off_b, local % jblocks, local / jblocks, false);
 }
 
 // Two batch GEMM tiles, chosen per problem by the plan (from the tuned
