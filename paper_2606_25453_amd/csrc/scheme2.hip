@@ -797,6 +797,40 @@ __device__ __forceinline__ void crt_reduce(const CrtArgs& ca, const uint32_t (&v
   double vf = 0.0;
 #pragma unroll
   for (int i = U; i >= 0; --i) vf = vf * 4294967296.0 + (double)v[i];
+  // Nearly always V / P + 1/2 lies well inside (q, q + 1) for an integer q:
+  // the estimate, within 2^-35 of V / P + 1/2 (V / P < 2^13), then fixes
+  // q = floor(V / P + 1/2) and Z = V - q P is the symmetric residue at once.
+  // Otherwise (V near a half-multiple of P) the exact steps below decide.
+  {
+    const double h = __fma_rn(vf, ca.Pinv, 0.5);
+    const double qh = floor(h), fr = h - qh;  // fr exact
+    if (fr > 0x1p-30 && fr < 1.0 - 0x1p-30) {
+      const uint32_t q = (uint32_t)qh;
+      uint32_t r[NL + 1];
+      uint64_t mc = 0;
+      int64_t borrow = 0;
+#pragma unroll
+      for (int i = 0; i <= U; ++i) {
+        const uint64_t prod = (uint64_t)(i < U ? ca.P[i] : 0u) * q + mc;
+        mc = prod >> 32;
+        const int64_t d = (int64_t)v[i] - (int64_t)(uint32_t)prod + borrow;
+        r[i] = (uint32_t)d;
+        borrow = d >> 32;
+      }
+      // |Z| <= P/2 < 2^(32U - 1): limb U is the sign extension
+      neg = (int32_t)r[U] < 0;
+      uint64_t c = neg ? 1u : 0u;
+#pragma unroll
+      for (int i = 0; i < U; ++i) {
+        const uint64_t t = (uint64_t)(neg ? ~r[i] : r[i]) + c;
+        mag[i] = (uint32_t)t;
+        c = t >> 32;
+      }
+#pragma unroll
+      for (int i = U; i < NL; ++i) mag[i] = 0;
+      return;
+    }
+  }
   const double qd = floor(vf * ca.Pinv);
   const uint32_t q = qd > 0.0 ? (uint32_t)qd : 0u;
   // r = V - q P (U + 1 limbs, two's complement)
