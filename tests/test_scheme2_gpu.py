@@ -173,6 +173,50 @@ def test_crt_every_modulus_count(ctx, s, cplx):
         C = host(ozk.ozk_dgemm(ctx, ozk.OZK_SCHEME2, s, dev(A), dev(B)))
         assert np.array_equal(C, s2.s2_dgemm(A, B, s))
 
+@pytest.mark.parametrize("s", [1, 2, 7, 11, 14, 15, 16, 20])
+@pytest.mark.parametrize("cplx", [False, True])
+def test_crt_near_half_multiples_of_p(ctx, s, cplx):
+    """Residue sets whose CRT value Z lies at and next to -P/2 and P/2 - 1
+    (the ends of the symmetric range, where the sum V is at or next to a
+    half-multiple of P: the binary64 quotient estimate cannot settle q there
+    and the exact steps decide), at 0 and +-1, and random ones, through the
+    CRT entry point: Z rebuilt by the oracle's CRT (Eq. 8) must equal the
+    chosen values, and the outputs its rounding (sigma, tau in [30, 60])."""
+    ms = s2.moduli(s)
+    P = 1
+    for m in ms:
+        P *= m
+    half = P // 2
+    rng = np.random.default_rng(s)
+    M, N = 6, 7
+    def targets(flip):
+        t = [-half, -half + 1, -half + 2, half - 1, half - 2, half - 3, 0, 1, -1, half // 3, -(half // 7)]
+        t = [max(-half, min(half - 1, v)) for v in t]
+        t += [int(rng.integers(-2 ** 62, 2 ** 62)) * (half // 2 ** 62 + 1) % P - half for _ in range(M * N - len(t))]
+        z = np.array(t, dtype=object).reshape(M, N)
+        return -z - 1 if flip else z  # -z - 1 keeps [-P/2, P/2)
+    Zt = [targets(False)] + ([targets(True)] if cplx else [])
+    planes = []
+    for l, m in enumerate(ms):
+        for z in Zt:
+            planes.append(np.array([[s2.smod(int(v) % m, m) for v in row] for row in z], np.int8))
+    res = np.stack(planes)  # [l][re, im][M][N]
+    sig = rng.integers(30, 61, M).astype(np.int32)
+    tau = rng.integers(30, 61, N).astype(np.int32)
+    want = []
+    for q, z in enumerate(Zt):
+        Z = s2.crt([res[len(Zt) * l + q] for l in range(s)], s)
+        assert np.array_equal(Z, z)  # the construction itself
+        want.append(np.array([[s2.scaled_round(int(Z[i, j]), -int(sig[i]) - int(tau[j])) for j in range(N)]
+                              for i in range(M)]))
+    C = torch.empty((M, N), dtype=torch.complex128 if cplx else torch.float64, device="cuda:0")
+    got = host(ozk.ozk_s2_crt(ctx, s, M, N, dev(res), dev(sig), dev(tau), C, complex_planes=int(cplx)))
+    if cplx:
+        assert np.array_equal(got.real, want[0]) and np.array_equal(got.imag, want[1])
+    else:
+        assert np.array_equal(got, want[0])
+
+
 def test_scheme2_alpha_beta_edges(ctx):
     s, M, N, K = 14, 40, 30, 50
     A = synth.phi_matrix(M, K, 1.0, 1)
