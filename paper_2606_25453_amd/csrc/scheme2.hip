@@ -380,6 +380,64 @@ __global__ __launch_bounds__(256) void k_s2_col_scales(const TX* __restrict__ X,
   s2_col_scales_block<CPLX, TX>(X, ldx, K, cols, T, tau, blockIdx.x);
 }
 
+// Column scales with one read of the operand: a block covers CC columns
+// (16 real, 8 complex: 128 bytes of a row) over all of K in 256 / CC k-groups
+// of CC lanes, keeping each entry's exponent in LDS (int16, k-major, zero
+// entries as INT16_MIN) for the norm-bound pass; the maximum and the sum are
+// reduced through LDS, in a fixed order.  Used when the cache of every block
+// of the launch fits the GPU at once (K <= S2_ECACHE_MAX_K).
+template <bool CPLX>
+struct S2CCols {
+  static constexpr int CC = CPLX ? 8 : 16;  // columns per block
+  static constexpr int G = 256 / CC;        // k-groups
+};
+
+__host__ __device__ constexpr int s2_ccache_bytes(bool cplx, int64_t K) {
+  return (int)((cplx ? S2CCols<true>::CC : S2CCols<false>::CC) * 2 * K);
+}
+
+template <bool CPLX, typename TX = double>
+__global__ __launch_bounds__(256) void k_s2_col_scales_cached(const TX* __restrict__ X, int64_t ldx, int64_t K,
+                                                              int64_t cols, int T, int32_t* __restrict__ tau) {
+  constexpr int W = CPLX ? 2 : 1, CC = S2CCols<CPLX>::CC, G = S2CCols<CPLX>::G;
+  extern __shared__ int16_t ecache[];
+  __shared__ int red_e[G][CC];
+  __shared__ int64_t red_s[G][CC];
+  const int cl = threadIdx.x & (CC - 1), g = threadIdx.x / CC;
+  const int64_t j = (int64_t)blockIdx.x * CC + cl;
+  const bool in = j < cols;
+  const TX* xc = X + (in ? j : 0) * W;
+  int e = OZK_EXP_ZERO;
+#pragma unroll 8
+  for (int64_t k = g; k < K; k += G) {
+    const int ek = entry_expo<CPLX>(xc + k * ldx * W);
+    // finite exponents lie in [-1074, 1025]; a non-finite entry makes the
+    // column's scale non-finite, so its cached value is never read
+    ecache[k * CC + cl] = (int16_t)(ek == OZK_EXP_ZERO ? -32768 : ek > 32767 ? 32767 : ek);
+    e = ek > e ? ek : e;
+  }
+  red_e[g][cl] = in ? e : OZK_EXP_ZERO;
+  __syncthreads();
+  int emax = red_e[0][cl];
+#pragma unroll
+  for (int i = 1; i < G; ++i) emax = red_e[i][cl] > emax ? red_e[i][cl] : emax;
+  int64_t S = 0;
+  if (in && emax != OZK_EXP_ZERO && emax != OZK_EXP_NONFINITE)
+#pragma unroll 8
+    for (int64_t k = g; k < K; k += G) {
+      const int c = ecache[k * CC + cl];
+      S += norm_term(c == -32768 ? OZK_EXP_ZERO : c, emax);
+    }
+  red_s[g][cl] = S;
+  __syncthreads();
+  if (g == 0 && in) {
+    int64_t tot = 0;
+#pragma unroll
+    for (int i = 0; i < G; ++i) tot += red_s[i][cl];
+    tau[j] = scale_from(emax, tot, T);
+  }
+}
+
 // Column scales for long K, split over K so that every CU has work: pass 1
 // the exponent maximum per column (integer atomic max), pass 2 the
 // norm-bound sum relative to it (integer atomic add), then the scale.  Both
@@ -1234,7 +1292,24 @@ static hipError_t split_cols_t(int s, bool cplx, const T* X, int64_t ldx, int64_
   s2_targets(s, ta, tb);
   if (budget >= 0) tb = budget;
   const int64_t cp = round_up(cols, OZK_ROW_ALIGN), kp = round_up(K, OZK_K_CHUNK);
-  if (cols > 0 && cp > 0 && kp >= 4 * S2_COLS_KB) {
+  const int cc = cplx ? S2CCols<true>::CC : S2CCols<false>::CC;
+  const int64_t cblocks = (cols + cc - 1) / cc;
+  const int cbytes = s2_ccache_bytes(cplx, K);
+  if (cols > 0 && K > 0 && K <= S2_ECACHE_MAX_K && cblocks <= 256 * (int64_t)(160 * 1024 / (cbytes + 3072))) {
+    // one read of B: every block's exponent cache resident at once
+    static std::atomic<uint64_t> lds_c{0}, lds_r{0};
+    const hipError_t e_lds =
+        lds_limit(cplx ? reinterpret_cast<const void*>(k_s2_col_scales_cached<true, T>)
+                       : reinterpret_cast<const void*>(k_s2_col_scales_cached<false, T>),
+                  s2_ccache_bytes(cplx, S2_ECACHE_MAX_K), cplx ? lds_c : lds_r);
+    if (e_lds != hipSuccess) return e_lds;
+    if (cplx)
+      hipLaunchKernelGGL((k_s2_col_scales_cached<true, T>), dim3((unsigned)cblocks), dim3(256), cbytes, st, X, ldx, K,
+                         cols, tb, tau);
+    else
+      hipLaunchKernelGGL((k_s2_col_scales_cached<false, T>), dim3((unsigned)cblocks), dim3(256), cbytes, st, X, ldx,
+                         K, cols, tb, tau);
+  } else if (cols > 0 && cp > 0 && kp >= 4 * S2_COLS_KB) {
     // long K: split over K; the statistics live at the start of `packed`
     // until the residues overwrite them (s Kp cp >= 12 cols bytes here)
     unsigned long long* S = reinterpret_cast<unsigned long long*>(packed);
