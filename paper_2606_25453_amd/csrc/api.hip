@@ -1573,7 +1573,7 @@ ozk_status ozk_batch_plan_create(ozk_ctx* ctx, ozk_op op, ozk_scheme scheme, int
     const ozk::BatchProb& q = pl->prob[i];
     const bool live = q.tiles > 0;
     rows[i + 1] = rows[i] + (live ? ozk::s2_split_rows_blocks(q.ra) : 0);
-    cols[i + 1] = cols[i] + (live ? (q.N + 31) / 32 : 0);
+    cols[i + 1] = cols[i] + (live ? ozk::s2_batch_col_blocks(cplx, q.K, q.N) : 0);
     split[i + 1] = split[i] + (live ? ozk::s2_split_cols_blocks(q.rb, q.Kp) : 0);
     crt[i + 1] = crt[i] + (live ? (q.M * q.N + 255) / 256 : 0);
   }

@@ -145,6 +145,7 @@ int s2_batch_gemm_blocks_per_cu(bool cplx, bool large);
 int64_t s2_tile_count(bool cplx, bool large, int64_t M, int64_t N);
 int64_t s2_split_rows_blocks(int64_t rows_packed);             // workgroups of the row residue pass
 int64_t s2_split_cols_blocks(int64_t cols_packed, int64_t Kp);  // workgroups of the column residue pass
+int64_t s2_batch_col_blocks(bool cplx, int64_t K, int64_t cols);  // workgroups of the batched column-scale pass
 
 void s2_targets(int s, int& ta, int& tb);
 

@@ -397,14 +397,14 @@ __host__ __device__ constexpr int s2_ccache_bytes(bool cplx, int64_t K) {
 }
 
 template <bool CPLX, typename TX = double>
-__global__ __launch_bounds__(256) void k_s2_col_scales_cached(const TX* __restrict__ X, int64_t ldx, int64_t K,
-                                                              int64_t cols, int T, int32_t* __restrict__ tau) {
+__device__ __forceinline__ void s2_col_scales_cached_block(const TX* __restrict__ X, int64_t ldx, int64_t K,
+                                                           int64_t cols, int T, int32_t* __restrict__ tau,
+                                                           int64_t blk, int16_t* ecache) {
   constexpr int W = CPLX ? 2 : 1, CC = S2CCols<CPLX>::CC, G = S2CCols<CPLX>::G;
-  extern __shared__ int16_t ecache[];
   __shared__ int red_e[G][CC];
   __shared__ int64_t red_s[G][CC];
   const int cl = threadIdx.x & (CC - 1), g = threadIdx.x / CC;
-  const int64_t j = (int64_t)blockIdx.x * CC + cl;
+  const int64_t j = blk * CC + cl;
   const bool in = j < cols;
   const TX* xc = X + (in ? j : 0) * W;
   int e = OZK_EXP_ZERO;
@@ -436,6 +436,26 @@ __global__ __launch_bounds__(256) void k_s2_col_scales_cached(const TX* __restri
     for (int i = 0; i < G; ++i) tot += red_s[i][cl];
     tau[j] = scale_from(emax, tot, T);
   }
+}
+
+template <bool CPLX, typename TX = double>
+__global__ __launch_bounds__(256) void k_s2_col_scales_cached(const TX* __restrict__ X, int64_t ldx, int64_t K,
+                                                              int64_t cols, int T, int32_t* __restrict__ tau) {
+  extern __shared__ int16_t ecache[];
+  s2_col_scales_cached_block<CPLX, TX>(X, ldx, K, cols, T, tau, blockIdx.x, ecache);
+}
+
+// The batched column-scale pass caches the exponents of problems up to this K
+// (16 KB of LDS per block: eight blocks still share a CU).
+template <bool CPLX>
+constexpr int64_t s2_batch_ccache_k() {
+  return 8192 / S2CCols<CPLX>::CC;
+}
+
+int64_t s2_batch_col_blocks(bool cplx, int64_t K, int64_t cols) {
+  const int64_t kc = cplx ? s2_batch_ccache_k<true>() : s2_batch_ccache_k<false>();
+  const int cc = cplx ? S2CCols<true>::CC : S2CCols<false>::CC;
+  return K <= kc ? (cols + cc - 1) / cc : (cols + 31) / 32;
 }
 
 // Column scales for long K, split over K so that every CU has work: pass 1
@@ -1869,10 +1889,15 @@ __global__ __launch_bounds__(256) void k_b_split_rows(BatchDev bd, int8_t* __res
 
 template <bool CPLX>
 __global__ __launch_bounds__(256) void k_b_col_scales(BatchDev bd, int8_t* __restrict__ ws, int T) {
+  __shared__ int16_t ecache[S2CCols<CPLX>::CC * s2_batch_ccache_k<CPLX>()];
   const int p = find_problem(bd.cols, blockIdx.x);
   const BatchProb& q = bd.prob[p];
-  s2_col_scales_block<CPLX>(q.B, q.ldb, q.K, q.N, T, reinterpret_cast<int32_t*>(ws + q.off_tau),
-                            blockIdx.x - bd.cols.start[p]);
+  const int64_t blk = blockIdx.x - bd.cols.start[p];
+  int32_t* tau = reinterpret_cast<int32_t*>(ws + q.off_tau);
+  if (q.K <= s2_batch_ccache_k<CPLX>())  // uniform: the block count follows s2_batch_col_blocks
+    s2_col_scales_cached_block<CPLX>(q.B, q.ldb, q.K, q.N, T, tau, blk, ecache);
+  else
+    s2_col_scales_block<CPLX>(q.B, q.ldb, q.K, q.N, T, tau, blk);
 }
 
 template <bool CPLX>
