@@ -207,7 +207,7 @@ constexpr int S2_ROWS_PER_BLOCK = 16;
 // norm-bound pass (one read of the operand instead of two): int16 per entry,
 // rows (K + 2) entries apart (a row per bank offset), zero entries as
 // INT16_MIN.  The batched pre-pass caches rows up to this K.
-constexpr int S2_ECACHE_BATCH_K = 512;
+constexpr int S2_ECACHE_BATCH_K = 1024;
 // The row-scale launch caches rows up to this K (128 KB of LDS).
 constexpr int S2_ECACHE_MAX_K = 4096;
 
