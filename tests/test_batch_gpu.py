@@ -129,6 +129,45 @@ def test_batch_long_k_and_split_problems(ctx, cplx):
             assert np.array_equal(got[np.ix_(rows, cols)], ref), i
         plan.close()
 
+@pytest.mark.parametrize("cplx", [False, True])
+def test_batch_exponent_cache_boundaries(ctx, cplx):
+    """The batched row and column scale passes keep the entry exponents in
+    LDS for short K (rows up to K = 1024; columns up to 512 real, 1024
+    complex) and read the operand again beyond: problems on both sides of
+    each boundary, with zero and tiny entries, equal the single calls and the
+    oracle on sampled rows and columns."""
+    s = 5
+    rng = np.random.default_rng(23)
+    probs = []
+    for i, K in enumerate((511, 512, 513, 1023, 1024, 1025)):
+        M, N = 33 + 7 * i, 41 + 5 * i
+        if cplx:
+            A = synth.complex_phi_matrix(M, K, 1.0, 300 + i, 310 + i)
+            B = synth.complex_phi_matrix(K, N, 1.0, 320 + i, 330 + i)
+        else:
+            A = synth.phi_matrix(M, K, 1.0, 300 + i)
+            B = synth.phi_matrix(K, N, 1.0, 320 + i)
+        A[1, ::3] = 0
+        A[2, 5] *= 1e-200
+        B[::4, 3] = 0
+        B[7, 4] *= 1e-200
+        probs.append((A, B))
+    dA, dB, dC = _device_batch(probs)
+    op = ozk.OZK_OP_ZGEMM if cplx else ozk.OZK_OP_DGEMM
+    plan = ozk.BatchPlan(ctx, op, ozk.OZK_SCHEME2, s, list(zip(dA, dB, dC)))
+    plan.run()
+    for i, (A, B) in enumerate(probs):
+        got = host(dC[i])
+        single = host(ozk.ozk_zgemm_3m(ctx, s, dA[i], dB[i]) if cplx
+                      else ozk.ozk_dgemm(ctx, ozk.OZK_SCHEME2, s, dA[i], dB[i]))
+        assert np.array_equal(got, single), i
+        rows = np.unique(np.concatenate([[1, 2], rng.choice(A.shape[0], size=4, replace=False)]))
+        cols = np.unique(np.concatenate([[3, 4], rng.choice(B.shape[1], size=4, replace=False)]))
+        ref = (s2.z3m_gemm(A[rows], B[:, cols], s) if cplx else s2.s2_dgemm(A[rows], B[:, cols], s))
+        assert np.array_equal(got[np.ix_(rows, cols)], ref), i
+    plan.close()
+
+
 def test_batch_graph_replay_is_bit_identical(ctx):
     s = 16
     probs = make_batch(40, 16, 256, 123, True)
