@@ -217,6 +217,35 @@ def test_crt_near_half_multiples_of_p(ctx, s, cplx):
         assert np.array_equal(got, want[0])
 
 
+@pytest.mark.parametrize("cplx", [False, True])
+def test_column_scales_wide_short_k(ctx, cplx):
+    """Very many columns with short K: more column blocks than can hold their
+    exponent caches on the GPU at once, so the scales take the two-pass
+    column kernel; sampled columns (a column's scale depends on that column
+    alone) against the oracle, and the single-read path on a narrow slice of
+    the same B against the oracle too."""
+    s, M, K, N = 4, 20, 256, 65536
+    rng = np.random.default_rng(5)
+    if cplx:
+        A = synth.complex_phi_matrix(M, K, 1.0, 401, 402)
+        B = synth.complex_phi_matrix(K, N, 1.0, 403, 404)
+    else:
+        A = synth.phi_matrix(M, K, 1.0, 401)
+        B = synth.phi_matrix(K, N, 1.0, 403)
+    B[::5, 7] = 0
+    rows = np.sort(rng.choice(M, size=5, replace=False))
+    cols = np.unique(np.concatenate([[7, N - 1], rng.choice(N, size=8, replace=False)]))
+    call = (lambda a, b: ozk.ozk_zgemm_3m(ctx, s, a, b)) if cplx else \
+        (lambda a, b: ozk.ozk_dgemm(ctx, ozk.OZK_SCHEME2, s, a, b))
+    ref_of = (lambda a, b: s2.z3m_gemm(a, b, s)) if cplx else (lambda a, b: s2.s2_dgemm(a, b, s))
+    got = host(call(dev(A), dev(B)))
+    assert np.array_equal(got[np.ix_(rows, cols)], ref_of(A[rows], B[:, cols]))
+    narrow = np.ascontiguousarray(B[:, :300])
+    got_n = host(call(dev(A), dev(narrow)))
+    assert np.array_equal(got_n, got[:, :300])
+    assert np.array_equal(got_n[rows], ref_of(A[rows], narrow))
+
+
 def test_scheme2_alpha_beta_edges(ctx):
     s, M, N, K = 14, 40, 30, 50
     A = synth.phi_matrix(M, K, 1.0, 1)
