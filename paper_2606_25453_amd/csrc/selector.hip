@@ -84,9 +84,12 @@ __device__ __forceinline__ void flush_bins(const int (&c)[SEL_BINS], int dmax, i
 
 // One wave per row: the row exponent (written to e_out), then the deficit
 // histogram of the row's nonzero entries.
+// kc > 0: each wave keeps its row's entry exponents in kc int16 of dynamic
+// LDS (K <= kc), so that the histogram pass reads them instead of the row.
 __global__ __launch_bounds__(256) void k_sel_rows(const double* __restrict__ X, int64_t ldx, int64_t rows,
                                                   int64_t K, int32_t* __restrict__ e_out,
-                                                  int32_t* __restrict__ cnt) {
+                                                  int32_t* __restrict__ cnt, int64_t kc) {
+  extern __shared__ int16_t ecache[];
   __shared__ int h[SEL_BINS];
   __shared__ int md;
   if (threadIdx.x < SEL_BINS) h[threadIdx.x] = 0;
@@ -98,11 +101,24 @@ __global__ __launch_bounds__(256) void k_sel_rows(const double* __restrict__ X, 
   int dmax = 0;
   if (r < rows) {  // wave-uniform
     const double* xr = X + r * ldx;
+    const bool cached = kc > 0 && K <= kc;  // uniform
+    int16_t* er = ecache + (cached ? (threadIdx.x >> 6) * kc : 0);
     int e = OZK_EXP_ZERO;
+    if (cached) {
 #pragma unroll 8
-    for (int64_t k = lane; k < K; k += 64) {
-      const int ek = expo_of(xr[k]);
-      e = ek > e ? ek : e;
+      for (int64_t k = lane; k < K; k += 64) {
+        const int ek = expo_of(xr[k]);
+        // finite exponents lie in [-1074, 1024]; a non-finite entry makes the
+        // row's exponent non-finite, so its cached value is never read
+        er[k] = (int16_t)(ek == OZK_EXP_ZERO ? -32768 : ek > 32767 ? 32767 : ek);
+        e = ek > e ? ek : e;
+      }
+    } else {
+#pragma unroll 8
+      for (int64_t k = lane; k < K; k += 64) {
+        const int ek = expo_of(xr[k]);
+        e = ek > e ? ek : e;
+      }
     }
     e = wave_max(e);
     if (lane == 0) e_out[r] = e;
@@ -112,7 +128,12 @@ __global__ __launch_bounds__(256) void k_sel_rows(const double* __restrict__ X, 
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           const int64_t k = k0 + 64 * u + lane;
-          ek[u] = k < K ? expo_of(xr[k < K ? k : 0]) : OZK_EXP_ZERO;
+          if (cached) {  // each lane reads back the entries it wrote
+            const int c = k < K ? er[k] : -32768;
+            ek[u] = c == -32768 ? OZK_EXP_ZERO : c;
+          } else {
+            ek[u] = k < K ? expo_of(xr[k < K ? k : 0]) : OZK_EXP_ZERO;
+          }
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
@@ -528,7 +549,17 @@ __global__ __launch_bounds__(256) void k_ref_dd(int64_t M, int64_t N, int64_t K,
 hipError_t sel_features(const double* A, int64_t lda, int64_t M, const double* B, int64_t ldb, int64_t N, int64_t K,
                         int32_t* e, int32_t* f, int32_t* cnt, hipStream_t st) {
   hipLaunchKernelGGL(k_sel_zero, dim3(1), dim3(64), 0, st, cnt);
-  if (M > 0) hipLaunchKernelGGL(k_sel_rows, dim3((unsigned)((M + 3) / 4)), dim3(256), 0, st, A, lda, M, K, e, cnt);
+  if (M > 0) {
+    // the row exponents cached in LDS for K <= 4096 (32 KB per block of four rows)
+    const int64_t kc = K > 0 && K <= 4096 ? K : 0;
+    static std::atomic<uint64_t> lds_done{0};
+    if (kc) {
+      const hipError_t e_lds = lds_limit(reinterpret_cast<const void*>(k_sel_rows), 4 * 4096 * 2, lds_done);
+      if (e_lds != hipSuccess) return e_lds;
+    }
+    hipLaunchKernelGGL(k_sel_rows, dim3((unsigned)((M + 3) / 4)), dim3(256), (unsigned)(4 * kc * 2), st, A, lda, M,
+                       K, e, cnt, kc);
+  }
   if (N > 0) {
     hipLaunchKernelGGL(k_sel_fill, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st, f, N, (int32_t)OZK_EXP_ZERO);
     if (K > 0) {
